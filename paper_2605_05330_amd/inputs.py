@@ -1,0 +1,236 @@
+"""Seeded synthetic inputs: graphs (CSR) and vertex weights.
+
+This module is shared by the HIP path's tests and benchmark and by the oracle's
+tests.  It builds problem data only -- simple undirected graphs and positive
+vertex weights, the input ``G = (A, w)`` of the MWIS problem (Section 2 and the
+WRGN definition: ``A`` symmetric with zero diagonal, ``w`` strictly positive) --
+and contains none of the method's arithmetic.
+
+Every generator is a pure function of its arguments: the random streams are
+numpy ``PCG64`` generators seeded with ``SeedSequence([seed, stream])``.
+
+Graph families (stand-ins for the paper's AVR / MSCD conflict graphs, which are
+not available):
+
+* Erdos-Renyi ``G(n, p)``: each unordered pair independently with probability p.
+* Barabasi-Albert: seed clique ``K_{m+1}``, every later vertex attaches to ``m``
+  distinct earlier vertices chosen with probability proportional to degree.
+* 2-D unit-disk: ``n`` points uniform in the unit square, an edge when the
+  Euclidean distance is at most ``r``.
+* Rook graph of an ``N x N`` board: the line graph of ``K_{N,N}`` used for the
+  assignment problem; cell ``(i, j)`` has index ``N*i + j`` and conflicts with
+  every other cell of its row and of its column.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Graph", "rng_for", "csr_from_edges", "erdos_renyi", "barabasi_albert",
+    "unit_disk", "rook", "weights_uniform01", "weights_uniform", "rook_weights",
+    "concat_graphs", "batch_sizes_loguniform", "edges_of",
+]
+
+
+@dataclass
+class Graph:
+    """Simple undirected graph in CSR form (int32), columns sorted per row."""
+    n: int
+    row_ptr: np.ndarray  # int32 [n+1]
+    col_idx: np.ndarray  # int32 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def n_edges(self) -> int:
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr).astype(np.int64)
+
+
+def rng_for(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream)])))
+
+
+def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray) -> Graph:
+    """Symmetric CSR from undirected edges ``src[k] -- dst[k]`` (no loops, no duplicates)."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    rows = np.concatenate([src, dst])
+    cols = np.concatenate([dst, src])
+    order = np.lexsort((cols, rows))
+    rows = rows[order]
+    cols = cols[order]
+    counts = np.bincount(rows, minlength=n) if n > 0 else np.zeros(0, np.int64)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] > np.iinfo(np.int32).max:
+        raise ValueError("graph too large for int32 CSR")
+    return Graph(n, row_ptr.astype(np.int32), cols.astype(np.int32))
+
+
+def edges_of(g: Graph) -> tuple[np.ndarray, np.ndarray]:
+    """Undirected edge list (i < j) of a CSR graph."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    cols = g.col_idx.astype(np.int64)
+    keep = rows < cols
+    return rows[keep], cols[keep]
+
+
+def _pair_from_linear(idx: np.ndarray, n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Map a linear index over the pairs i<j (row-major) to (i, j)."""
+    # number of pairs before row i: i*n - i*(i+1)/2
+    idx = idx.astype(np.int64)
+    nf = float(n)
+    i = np.floor((2 * nf - 1 - np.sqrt((2 * nf - 1) ** 2 - 8.0 * idx)) / 2).astype(np.int64)
+    i = np.clip(i, 0, n - 2)
+    before = i * n - i * (i + 1) // 2
+    # fix float rounding at row boundaries
+    for _ in range(2):
+        hi = idx >= before + (n - 1 - i)
+        i = np.where(hi, i + 1, i)
+        before = i * n - i * (i + 1) // 2
+        lo = idx < before
+        i = np.where(lo, i - 1, i)
+        before = i * n - i * (i + 1) // 2
+    j = idx - before + i + 1
+    return i, j
+
+
+def erdos_renyi(n: int, p: float, seed: int, stream: int = 0) -> Graph:
+    """``G(n, p)``: the number of edges is Binomial(n(n-1)/2, p) and the edge set is a
+    uniform subset of that size, which is the same distribution as independent pairs."""
+    rng = rng_for(seed, stream)
+    npairs = n * (n - 1) // 2
+    if npairs == 0 or p <= 0.0:
+        return csr_from_edges(n, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    m = int(rng.binomial(npairs, min(p, 1.0)))
+    lin = rng.choice(npairs, size=m, replace=False)
+    i, j = _pair_from_linear(np.sort(lin), n)
+    return csr_from_edges(n, i, j)
+
+
+def barabasi_albert(n: int, m: int, seed: int, stream: int = 0) -> Graph:
+    """Preferential attachment with a ``K_{m+1}`` seed; each new vertex takes ``m``
+    distinct targets drawn proportionally to current degree."""
+    if n <= m + 1:
+        iu = np.triu_indices(n, 1)
+        return csr_from_edges(n, iu[0], iu[1])
+    rng = rng_for(seed, stream)
+    n_edges = (m + 1) * m // 2 + (n - m - 1) * m
+    src = np.empty(n_edges, dtype=np.int64)
+    dst = np.empty(n_edges, dtype=np.int64)
+    ends = np.empty(2 * n_edges, dtype=np.int64)   # every edge endpoint, degree-proportional pool
+    iu = np.triu_indices(m + 1, 1)
+    e0 = len(iu[0])
+    src[:e0] = iu[0]
+    dst[:e0] = iu[1]
+    ends[0:2 * e0:2] = iu[0]
+    ends[1:2 * e0:2] = iu[1]
+    e = e0
+    pool = 2 * e0
+    draws = rng.random(size=(n - m - 1, 4 * m))
+    for t in range(m + 1, n):
+        row = draws[t - m - 1]
+        chosen: list[int] = []
+        k = 0
+        while len(chosen) < m:
+            if k < row.shape[0]:
+                u = row[k]
+            else:
+                u = rng.random()
+            k += 1
+            c = int(ends[int(u * pool)])
+            if c not in chosen:
+                chosen.append(c)
+        for c in chosen:
+            src[e] = c
+            dst[e] = t
+            ends[pool] = c
+            ends[pool + 1] = t
+            e += 1
+            pool += 2
+    return csr_from_edges(n, src, dst)
+
+
+def unit_disk(n: int, avg_degree: float, seed: int, stream: int = 0) -> Graph:
+    """Points uniform in [0,1)^2, radius ``r = sqrt(avg_degree / (pi (n-1)))`` (boundary
+    effects make the realised mean degree slightly lower)."""
+    from scipy.spatial import cKDTree
+    rng = rng_for(seed, stream)
+    pts = rng.random(size=(n, 2))
+    if n < 2:
+        return csr_from_edges(n, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    r = math.sqrt(avg_degree / (math.pi * (n - 1)))
+    pairs = cKDTree(pts).query_pairs(r, output_type="ndarray")
+    if pairs.size == 0:
+        return csr_from_edges(n, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    return csr_from_edges(n, pairs[:, 0], pairs[:, 1])
+
+
+def rook(N: int) -> Graph:
+    """Rook graph of an N x N board, built directly in sorted CSR order."""
+    n = N * N
+    deg = 2 * (N - 1)
+    row_ptr = (np.arange(n + 1, dtype=np.int64) * deg)
+    if row_ptr[-1] > np.iinfo(np.int32).max:
+        raise ValueError("board too large for int32 CSR")
+    i = np.arange(N, dtype=np.int64)[:, None]
+    j = np.arange(N, dtype=np.int64)[None, :]
+    cols = np.empty((N, N, deg), dtype=np.int32)
+    k = np.arange(N, dtype=np.int64)
+    # column mates above (k < i), row mates (k != j), column mates below (k > i)
+    for a in range(N):
+        for_col = k * N  # cells (k, b) have index k*N + b
+        above = for_col[:a]
+        below = for_col[a + 1:]
+        rowmates = a * N + k
+        for b in range(N):
+            seg = np.concatenate([above + b, np.delete(rowmates, b), below + b])
+            cols[a, b, :] = seg
+    del i, j
+    return Graph(n, row_ptr.astype(np.int32), cols.reshape(-1))
+
+
+def weights_uniform01(n: int, seed: int, stream: int = 1) -> np.ndarray:
+    """w = 1 - u with u uniform on [0, 1) in fp32: values in (0, 1], exact in fp32."""
+    u = rng_for(seed, stream).random(size=n, dtype=np.float32)
+    return (np.float32(1.0) - u).astype(np.float32)
+
+
+def weights_uniform(n: int, lo: float, hi: float, seed: int, stream: int = 1) -> np.ndarray:
+    """w uniform on (lo, hi]: ``hi - (hi - lo) * u`` rounded to fp32."""
+    u = rng_for(seed, stream).random(size=n)
+    return (hi - (hi - lo) * u).astype(np.float32)
+
+
+def rook_weights(N: int, seed: int, temperature: float = 0.1, stream: int = 1) -> tuple[np.ndarray, np.ndarray]:
+    """Assignment weights ``w = exp(-C / T)`` with C uniform [0, 1) (fp32), w rounded to
+    fp32.  Returns (w as an N*N vector in cell order, C as an N x N matrix)."""
+    C = rng_for(seed, stream).random(size=(N, N), dtype=np.float32)
+    w = np.exp(-C.astype(np.float64) / temperature).astype(np.float32)
+    return w.reshape(-1), C
+
+
+def batch_sizes_loguniform(count: int, lo: int, hi: int, seed: int, stream: int = 7) -> np.ndarray:
+    """n_g = floor(exp(U(ln lo, ln hi)))."""
+    u = rng_for(seed, stream).random(size=count)
+    return np.floor(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+
+
+def concat_graphs(graphs: list[Graph]) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """Concatenate graphs into per-graph sizes and *local* CSR arrays back to back.
+
+    Returns (n[count] int32, nnz[count] int64, row_ptr_cat int32 (sum(n)+count entries:
+    each graph's own row_ptr, starting at 0), col_idx_cat int32 (local column ids))."""
+    ns = np.array([g.n for g in graphs], dtype=np.int32)
+    nnzs = np.array([g.nnz for g in graphs], dtype=np.int64)
+    rp = np.concatenate([g.row_ptr for g in graphs]).astype(np.int32) if graphs else np.zeros(0, np.int32)
+    ci = np.concatenate([g.col_idx for g in graphs]).astype(np.int32) if graphs else np.zeros(0, np.int32)
+    return ns, nnzs, rp, ci
