@@ -30,6 +30,13 @@
  * a closed-neighbourhood sum at or below 1e-9 resets the node to 1/2. */
 static const double ORC_SAFE_DIV = 1e-9;
 static const double ORC_FALLBACK_X = 0.5;
+/* Support invariance (Section 2, property ii) in finite precision: a positive
+ * state never becomes an exact zero.  Without this bound a decaying value
+ * underflows to 0 and is then frozen forever (0 is a fixed point), so a vertex
+ * that later should regrow (its neighbourhood lost the set) cannot, and the
+ * iteration can stop on a set that is not gamma-stable.  2^-100 is exact in
+ * fp32 and fp64 and far below every threshold of the method. */
+static const double ORC_X_MIN = 7.888609052210118e-31; /* 2^-100 */
 
 /* ---------------------------------------------------------------------------
  * Problem statement checks (Section 2): A is the adjacency matrix of a simple
@@ -79,7 +86,8 @@ double orc_gamma(double gamma0, double gamma1, int32_t ramp, int64_t k) {
 /* One WRGN step (Definition WRGN; y-space form of the energy-descent proof;
  * safe division of the code appendix):
  *     y_i = v_i x_i,  s_i = y_i + gamma * sum_{j in N(i)} y_j,
- *     x'_i = y_i / s_i   if s_i > 1e-9,   x'_i = 1/2 otherwise.
+ *     x'_i = y_i / s_i   if s_i > 1e-9,   x'_i = 1/2 otherwise,
+ * and a positive x'_i is kept >= 2^-100 (support invariance, see ORC_X_MIN).
  * Returns how many nodes took the 1/2 fallback.  x and x_out may alias. */
 int64_t orc_step(int32_t n, const int32_t* rp, const int32_t* ci, const double* v,
                  double gamma, const double* x, double* x_out) {
@@ -91,7 +99,9 @@ int64_t orc_step(int32_t n, const int32_t* rp, const int32_t* ci, const double* 
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) nb += y[ci[e]];
         double s = gamma * nb + y[i];
         if (s > ORC_SAFE_DIV) {
-            x_out[i] = y[i] / s;
+            double xn = y[i] / s;
+            if (y[i] > 0.0 && xn < ORC_X_MIN) xn = ORC_X_MIN;
+            x_out[i] = xn;
         } else {
             x_out[i] = ORC_FALLBACK_X;
             ++fallback;
@@ -305,7 +315,7 @@ int64_t orc_unrolled_forward(int32_t n, const int32_t* rp, const int32_t* ci, co
  *   dL/dy = gbar (/) s - (I + gamma A) t,   t = gbar (.) y (/) s^2
  * (I + gamma A is symmetric), dL/dx = v (.) dL/dy, dL/dv += x (.) dL/dy, and
  * dL/dw = dL/dv (/) (2 v) since v = sqrt(w).  Rows that took the 1/2 fallback
- * are constant and pass no gradient.  gxT = dL/dx^T on input; outputs the
+ * or sit at the 2^-100 bound are constant and pass no gradient.  gxT = dL/dx^T on input; outputs the
  * gradient through the dynamics only (gw, gx0). */
 void orc_unrolled_vjp(int32_t n, const int32_t* rp, const int32_t* ci, const double* w,
                       const double* gammas, int32_t T, const double* x0, const double* gxT,
@@ -330,7 +340,7 @@ void orc_unrolled_vjp(int32_t n, const int32_t* rp, const int32_t* ci, const dou
             double nb = 0.0;
             for (int64_t e = rp[i]; e < rp[i + 1]; ++e) nb += y[ci[e]];
             s[i] = g * nb + y[i];
-            if (s[i] > ORC_SAFE_DIV) {
+            if (s[i] > ORC_SAFE_DIV && !(y[i] > 0.0 && y[i] / s[i] < ORC_X_MIN)) {
                 a[i] = gbar[i] / s[i];
                 t[i] = gbar[i] * y[i] / (s[i] * s[i]);
             } else {

@@ -443,3 +443,40 @@ def test_batched_reference_is_per_graph():
     U = csr_from_edges(off, np.concatenate(src), np.concatenate(dst))
     xs = O.unrolled_forward(U.n, U.row_ptr, U.col_idx, w, np.full(3000, 1.4), x0)[-1]
     np.testing.assert_array_equal(np.concatenate([p.x for p in per]), xs)
+
+
+def test_support_invariance_over_long_runs():
+    """Section 2 property ii: supp(N(x)) = supp(x).  In finite precision positive states
+    are held at >= 2^-100 instead of underflowing to 0; exact zeros stay 0."""
+    g = I.erdos_renyi(300, 8 / 299, 21)
+    w = I.weights_uniform01(300, 21).astype(np.float64)
+    x = I.rng_for(21, 1).random(300) * 0.9 + 0.05
+    deg = g.degrees()
+    zeros = [i for i in range(300) if deg[i] > 0][:20:2]   # spaced out: each keeps positive neighbours
+    x[zeros] = 0.0
+    assert O.is_normalizable(300, g.row_ptr, g.col_idx, x) == O.OK
+    xs = O.unrolled_forward(300, g.row_ptr, g.col_idx, w, np.full(3000, 1.5), x)
+    pos = np.setdiff1d(np.arange(300), zeros)
+    assert np.all(xs[:, pos] >= 2.0 ** -100)      # positives never underflow to 0
+    # zeros stay 0 as long as their closed-neighbourhood sum is above the 1e-9 reset
+    v = np.sqrt(w)
+    A = _sparse(g)
+    for k in range(3000):
+        s_k = 1.5 * (A @ (v * xs[k]))
+        live = [z for z in zeros if s_k[z] > 1e-9]
+        assert np.all(xs[k + 1, live] == 0.0)
+
+
+def test_frozen_vertex_regrows_to_stable_set():
+    """Theorem 4 convergence needs support invariance: on this graph a light vertex
+    decays below 1e-70 while its neighbour is selected and must later regrow to
+    replace it; the solve ends on a gamma-stable set that a long continuation keeps."""
+    g = I.erdos_renyi(1500, 6 / 1499, 109)
+    w = I.weights_uniform01(1500, 109).astype(np.float64)
+    r = O.solve(1500, g.row_ptr, g.col_idx, w, np.full(1500, 0.5), gamma0=0.9, gamma1=1.5, ramp_steps=1000,
+                max_steps=3000)
+    assert r.binarised and r.sel[775] and not r.sel[276]
+    assert r.growing == 0 and r.stab > 1.0 - 1e-3
+    r2 = O.solve(1500, g.row_ptr, g.col_idx, w, r.x, gamma0=1.5, gamma1=1.5, ramp_steps=1, max_steps=2000,
+                 tau=0.0)
+    assert np.array_equal(r2.sel, r.sel)
