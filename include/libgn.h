@@ -1,0 +1,213 @@
+/*
+ * libgn -- Weighted Regularized Graph Normalization (WRGN) for Maximum Weight
+ * Independent Set on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2 and the WRGN definition): G = (A, w) is a simple
+ * undirected graph on n vertices (A symmetric, A_ii = 0) with strictly positive
+ * vertex weights w.  With v = sqrt(w) and a regularization gamma > 0, one WRGN
+ * step maps a state x in [0,1]^n to
+ *
+ *     x'_i = x_i / (x_i + gamma * sum_{j in N(i)} (v_j / v_i) x_j),
+ *
+ * computed in weighted state space y = v (.) x as x'_i = y_i / s_i with
+ * s = (I + gamma A) y, and with the safe division of the paper's PyTorch module
+ * (code appendix): x'_i = 1/2 wherever s_i <= 1e-9.  Iterated with gamma > 1 it
+ * converges to the indicator of a gamma-stable maximal independent set
+ * (Theorem "Binary Regularization").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All vertex-indexed arrays passed to or returned from the library are in the
+ *    caller's vertex order ("user order"), length n, contiguous.
+ *  - "device" pointers are HIP device memory of the current device owned by the
+ *    caller; the library never frees them.  "host" pointers are ordinary host
+ *    memory.
+ *  - Every call returns a gn_status.  Negative values are errors; nothing is
+ *    thrown and nothing aborts.  Argument and input-validation errors are
+ *    detected on the host before any work is queued.  A fault inside a kernel
+ *    surfaces as GN_E_HIP at the next call that synchronises.
+ *  - Calls marked ASYNC only enqueue work on `stream`; calls marked SYNC wait for
+ *    `stream` before returning because they fill host outputs.
+ *  - A handle's device work buffers are shared by all calls on that handle:
+ *    calls on one handle must not overlap in time (on one stream they never do).
+ *  - Floating-point state is fp32; reductions of objectives use fp64.
+ */
+#ifndef LIBGN_H
+#define LIBGN_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gn_graph gn_graph; /* one graph: CSR, weights, degree bins, work buffers */
+typedef struct gn_batch gn_batch; /* many independent graphs solved in one launch        */
+
+typedef enum {
+    GN_OK = 0,
+    GN_NOT_CONVERGED = 1,        /* outputs written, stopping test not met by max_steps  */
+    GN_E_ARG = -1,               /* bad argument (null pointer, negative size, NaN, ...)  */
+    GN_E_CSR = -2,               /* row_ptr not monotone / bad bounds, column out of range,
+                                    columns of a row not strictly increasing             */
+    GN_E_SELF_LOOP = -3,         /* A_ii != 0                                             */
+    GN_E_ASYMMETRIC = -4,        /* A != A^T                                              */
+    GN_E_WEIGHT = -5,            /* some w_i not finite or not > 0                        */
+    GN_E_NOT_NORMALIZABLE = -6,  /* x0 has a closed neighbourhood of zero mass            */
+    GN_E_NUMERIC = -7,           /* non-finite value produced                             */
+    GN_E_HIP = -8,               /* a HIP runtime call failed                             */
+    GN_E_NOMEM = -9              /* device or host allocation failed                      */
+} gn_status;
+
+/* flags of gn_graph_create / gn_batch_create */
+#define GN_INPUT_HOST   0u  /* row_ptr, col_idx, w are host pointers                      */
+#define GN_INPUT_DEVICE 1u  /* row_ptr, col_idx, w are device pointers                    */
+#define GN_NO_VALIDATE  2u  /* skip the O(nnz) symmetry / ordering checks (trusted input) */
+
+/* Iteration schedule (Section 6, gamma-pursuit): gamma_k = p*gamma1 + (1-p)*gamma0
+ * with p = min(k, ramp_steps-1)/(ramp_steps-1); ramp_steps <= 1 means constant
+ * gamma1.  The paper runs 1000 steps with gamma 0.9 -> 1.5 (ramp_steps = 1000).
+ * Stopping rule of this library (the paper has none): at steps k >= 1 with
+ * k % check_every == 0, and at k = max_steps, the state x^k passes when
+ *   (1) max_i min(x_i, 1 - x_i) <= tau,
+ *   (2) every vertex with x_i <= 1/2 has a neighbour with x_j > 1/2, and
+ *   (3) every vertex with 0 < x_i <= 1/2 satisfies s_i > v_i under gamma_k, i.e.
+ *       the next step shrinks it (the finite-state form of stab > 1).        */
+typedef struct {
+    float gamma0, gamma1;
+    int32_t ramp_steps;
+    int32_t max_steps;
+    float tau;
+    int32_t check_every;
+} gn_schedule;
+
+/* Result of a solve.  The selected set is S = {i : x_i > 1/2}. */
+typedef struct {
+    int32_t steps;              /* WRGN steps applied                                   */
+    int32_t binarised;          /* 1 when the stopping test passed                      */
+    int64_t fallback_count;     /* 1/2-resets taken by the safe division, all steps     */
+    double relaxed_objective;   /* sum_i w_i x_i   (fp64)                               */
+    double set_objective;       /* W(S) = sum_{i in S} w_i   (fp64)                     */
+    int64_t set_size;           /* |S|                                                  */
+    int64_t conflicts;          /* undirected edges with both ends in S                 */
+    int64_t uncovered;          /* vertices outside S with no neighbour in S            */
+    float stab;                 /* gamma_k * min_{i not in S} sum_{j in N(i) cap S}
+                                   sqrt(w_j / w_i)  (stability equation of Theorem
+                                   "Binary Regularization"), gamma_k of the final step;
+                                   +inf when S = V                                      */
+} gn_result;
+
+/* Number of degree bins a graph is split into (see gn_graph_info). */
+#define GN_NUM_BINS 7
+
+/* Create a graph from CSR + weights.  n >= 0 vertices, nnz = row_ptr[n] stored
+ * entries (2|E|).  row_ptr: int32[n+1], col_idx: int32[nnz], w: float[n], all
+ * host or all device per `flags`.  The CSR must be symmetric with no diagonal
+ * entries and strictly increasing columns in every row; w must be finite and
+ * > 0 (Section 2).  The library copies everything into memory it owns, so the
+ * caller may free its arrays on return.  Precomputes v = sqrt(w) (fp32, rounded
+ * from the double square root) and the degree bins.  SYNC.
+ * Errors: GN_E_ARG, GN_E_CSR, GN_E_SELF_LOOP, GN_E_ASYMMETRIC, GN_E_WEIGHT,
+ * GN_E_NOMEM, GN_E_HIP.  On error *out is set to NULL. */
+gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                          const float* w, uint32_t flags, hipStream_t stream, gn_graph** out);
+
+/* Free a graph and everything it owns (NULL is allowed).  Waits for the device. */
+void gn_graph_destroy(gn_graph* g);
+
+/* Diagnostics: n, nnz, max degree and the number of rows in each degree bin
+ * (bin_rows may be NULL; else GN_NUM_BINS entries, lightest first: one thread
+ * per row (deg <= 16), one thread per row (deg <= 32), 8 threads per row
+ * (deg <= 128), one wavefront per row (deg <= 512), one workgroup per row with
+ * LDS staging (deg > 512), then unused zeros).  Host only. */
+gn_status gn_graph_info(const gn_graph* g, int32_t* n, int64_t* nnz, int32_t* max_degree,
+                        int32_t* bin_rows);
+
+/* One WRGN step (definition above, with the safe division) at a given gamma:
+ * x_out = N(x_in).  x_in, x_out: device float[n], user order; they must not
+ * alias (GN_E_ARG).  x_in must be finite and >= 0; vertices whose closed
+ * neighbourhood sum is <= 1e-9 take x = 1/2.  ASYNC. */
+gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, float* x_out, hipStream_t stream);
+
+/* Iterate WRGN from x to binarisation under `sch`.  x: device float[n], x^0 on
+ * entry and the final state on exit (clamped to [0,1]); sel: device uint8[n],
+ * sel_i = (x_i > 1/2); res: host.  x^0 must be finite, >= 0 and normalizable
+ * ((A+I) x^0 > 0 componentwise, Section 2), else GN_E_ARG / GN_E_NOT_NORMALIZABLE
+ * and x, sel are left unchanged.  Returns GN_OK when binarised, GN_NOT_CONVERGED
+ * when max_steps ran out (outputs still valid).  SYNC. */
+gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                   hipStream_t stream);
+
+/* Relaxed MWIS objective sum_i w_i x_i (Theorem "Weighted Mass Growth"), fp64
+ * accumulation in a fixed order.  x: device float[n]; out: host.  SYNC. */
+gn_status gn_objective(const gn_graph* g, const float* x, double* out, hipStream_t stream);
+
+/* Independence and maximality of a vertex set (Section 2): conflicts = number
+ * of undirected edges with both ends selected (1_S^T A 1_S / 2), uncovered =
+ * number of unselected vertices with no selected neighbour.  sel: device
+ * uint8[n], nonzero = selected.  conflicts: host, required; uncovered: host,
+ * may be NULL.  SYNC. */
+gn_status gn_check_independent(const gn_graph* g, const uint8_t* sel, int64_t* conflicts,
+                               int64_t* uncovered, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched solve: many independent graphs in one persistent launch.
+ *
+ * Connected components do not interact (Section 2, property iii), so a batch
+ * is solved graph by graph: every graph keeps its own step counter, its own
+ * gamma_k and its own stopping test, and each graph's result is bit-identical
+ * to gn_solve on that graph alone (same arithmetic in the same order).
+ * ------------------------------------------------------------------------- */
+
+/* Launch shape of the batched kernel, chosen by gn_batch_autotune.  It changes
+ * speed only, never results. */
+typedef struct {
+    int32_t block_threads;   /* threads per workgroup: 128, 256 or 512                      */
+    int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1 .. 4               */
+    int32_t lds_vertices;    /* graphs with n <= lds_vertices keep y and v in LDS            */
+    int32_t reserved;
+} gn_tuning;
+
+/* Create a batch.  count >= 1 graphs; n[g], nnz[g] host arrays; row_ptr_cat:
+ * the graphs' own row_ptr arrays (each starting at 0) back to back, sum(n[g]+1)
+ * int32; col_idx_cat: the graphs' column arrays back to back, local vertex ids,
+ * sum(nnz[g]) int32; w_cat: weights back to back, sum(n[g]) float.  The three
+ * concatenated arrays are host or device per `flags`.  Each graph must satisfy
+ * the conditions of gn_graph_create.  Copies everything.  SYNC.
+ * Errors as gn_graph_create. */
+gn_status gn_batch_create(int32_t count, const int32_t* n, const int64_t* nnz, const int32_t* row_ptr_cat,
+                          const int32_t* col_idx_cat, const float* w_cat, uint32_t flags, hipStream_t stream,
+                          gn_batch** out);
+
+/* Free a batch (NULL is allowed).  Waits for the device. */
+void gn_batch_destroy(gn_batch* b);
+
+/* Solve every graph of the batch to binarisation under one schedule.  x_cat:
+ * device float[sum n], x^0 on entry (user order within each graph), final
+ * states on exit; sel_cat: device uint8[sum n]; res: host gn_result[count].
+ * tuning may be NULL (then the cached or default shape is used).  If any
+ * graph's x^0 is negative, non-finite or not normalizable the call returns
+ * GN_E_ARG / GN_E_NOT_NORMALIZABLE and leaves x_cat, sel_cat unchanged.
+ * Returns GN_OK when every graph binarised, GN_NOT_CONVERGED otherwise.  SYNC. */
+gn_status gn_batch_solve(gn_batch* b, const gn_schedule* sch, const gn_tuning* tuning, float* x_cat,
+                         uint8_t* sel_cat, gn_result* res, hipStream_t stream);
+
+/* Time candidate launch shapes on this batch (a bounded number of steps from
+ * x0 = 1/2) and return the fastest; the choice is cached in the batch handle
+ * and used by later gn_batch_solve calls with tuning == NULL.  SYNC. */
+gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_tuning* out, hipStream_t stream);
+
+/* The batch as one block-diagonal graph (vertex ids offset graph by graph),
+ * owned by the batch: valid until gn_batch_destroy.  Used by the unrolled
+ * (differentiable) calls and by single-graph diagnostics. */
+const gn_graph* gn_batch_graph(const gn_batch* b);
+
+/* Human-readable name of a status code (static string). */
+const char* gn_status_str(gn_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBGN_H */

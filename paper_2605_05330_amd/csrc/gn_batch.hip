@@ -1,0 +1,747 @@
+// Batched WRGN: many independent graphs in one persistent launch.
+//
+// Components do not interact (Section 2, property iii), so every graph is
+// iterated to its own binarisation by one workgroup: the workgroup pulls a
+// graph from a device work queue (largest graphs first), keeps the graph's
+// weighted state y (ping-pong) and v = sqrt(w) in LDS, and runs the fused WRGN
+// step with a workgroup barrier between steps instead of a grid-wide one.  Each
+// graph has its own step counter, gamma_k and stopping test; a finished graph
+// frees its workgroup for the next one.  Row sums use the library's canonical
+// order (gn_rowsum.h), so every graph's states, steps and selected set are
+// bit-identical to gn_solve on that graph alone.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <vector>
+
+#include "gn_internal.h"
+#include "gn_rowsum.h"
+
+using gnk::sign_of;
+
+namespace {
+
+constexpr int kLightMaxDeg = 32;  // rows up to this degree run one per thread
+constexpr int kLdsBudget = 160 * 1024 - 2048;  // dynamic LDS per CU (static LDS of the kernel set aside)
+
+struct BatchDesc {
+    int32_t n;        // vertices
+    int32_t n_light;  // internal rows [0, n_light) have degree <= kLightMaxDeg
+    int64_t v_off;    // offset of the graph's vertices in the vertex arrays
+    int64_t rp_off;   // offset of its row_ptr (n + 1 entries)
+    int64_t e_off;    // offset of its columns
+};
+
+struct BatchRes {
+    int32_t steps, binarised;
+    long long fallback;
+    double relaxed, set_w;
+    long long size, conflicts, uncovered;
+    float stab;
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const BatchDesc* desc;
+    const int32_t* order;    // processing order (graph ids, most entries first)
+    int32_t count;
+    const int32_t* row_ptr;  // internal, per graph
+    const int32_t* col;      // internal local ids
+    const float* v;          // internal order
+    const float* w;          // internal order
+    const int32_t* perm;     // internal row -> user local id, per graph
+    const float* gamma;      // gamma table, >= max_steps + 1 entries
+    int32_t max_steps, check_every;
+    float tau;
+    int32_t lds_vertices;
+    float* x_cat;            // user order; x0 in, final x out
+    uint8_t* sel_cat;
+    float* yg0;              // global ping-pong state for graphs above lds_vertices
+    float* yg1;
+    int32_t* queue;          // [0]: next queue slot, [1]: error bits
+    BatchRes* res;
+};
+
+__device__ __forceinline__ bool step_row(float yraw, float vi, float sigma, bool nbr_sel, float g, bool do_test,
+                                         bool do_write, float tau, float* y_out, int i, int& fb) {
+    const float yi = fabsf(yraw);
+    const float s = __fmaf_rn(g, sigma, yi);
+    const bool fallback = !(s > 1e-9f);
+    const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
+    if (do_write) {
+        const float yn = vi * xn;
+        y_out[i] = xn > 0.5f ? -yn : yn;
+        fb += fallback ? 1 : 0;
+    }
+    if (!do_test) return false;
+    const bool in_s = sign_of(yraw) != 0u;
+    const float tv = tau * vi;
+    const bool far = (yi > tv) && ((vi - yi) > tv);
+    const bool uncovered = !in_s && !nbr_sel;
+    const bool growing = !in_s && (yi > 0.0f) && !(s > vi);
+    return far || uncovered || growing;
+}
+
+template <int BT>
+__device__ double block_sum_d(double x, double* sm) {
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[wave] = x;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < BT / 64; ++w) r += sm[w];
+    return r;
+}
+
+template <int BT>
+__device__ long long block_sum_ll(long long x, long long* sm) {
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[wave] = x;
+    __syncthreads();
+    long long r = 0;
+    for (int w = 0; w < BT / 64; ++w) r += sm[w];
+    return r;
+}
+
+template <int BT>
+__device__ float block_min_f(float x, float* sm) {
+    for (int off = 32; off >= 1; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[wave] = x;
+    __syncthreads();
+    float r = INFINITY;
+    for (int w = 0; w < BT / 64; ++w) r = fminf(r, sm[w]);
+    return r;
+}
+
+template <int BT, bool LDS>
+__device__ void solve_graph(const BatchArgs& a, int gi, float* lds) {
+    __shared__ double sm_d[BT / 64];
+    __shared__ long long sm_l[BT / 64];
+    __shared__ float sm_f[BT / 64];
+    const BatchDesc d = a.desc[gi];
+    const int n = d.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (n == 0) return;  // result filled on the host
+    const int32_t* __restrict__ rp = a.row_ptr + d.rp_off;
+    const int32_t* __restrict__ col = a.col + d.e_off;
+    const int32_t* __restrict__ perm = a.perm + d.v_off;
+    const int L = a.lds_vertices;
+    float* ya = LDS ? lds : a.yg0 + d.v_off;
+    float* yb = LDS ? lds + L : a.yg1 + d.v_off;
+    float* vv = LDS ? lds + 2 * L : const_cast<float*>(a.v) + d.v_off;
+    float* xg = a.x_cat + d.v_off;
+
+    for (int i = tid; i < n; i += BT) {
+        const float vi = a.v[d.v_off + i];
+        const float x = xg[perm[i]];
+        const float yy = vi * x;
+        ya[i] = x > 0.5f ? -yy : yy;
+        if (LDS) vv[i] = vi;
+    }
+    __syncthreads();
+
+    float* yin = ya;
+    float* yout = yb;
+    int fb = 0;
+    int steps = 0;
+    bool binarised = false;
+    for (int k = 0;; ++k) {
+        const bool do_test = k >= 1 && (k % a.check_every == 0 || k == a.max_steps);
+        const bool do_write = k < a.max_steps;
+        const float g = a.gamma[k];
+        bool viol = false;
+        for (int i = tid; i < d.n_light; i += BT) {
+            const int s0 = gnk::ld_stream(rp + i);
+            const int dd = gnk::ld_stream(rp + i + 1) - s0;
+            unsigned sel = 0u;
+            const float sigma = gnk::row_sum<1, kLightMaxDeg>(col + s0, dd, yin, 0, sel);
+            viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
+        }
+        for (int i = d.n_light + wave; i < n; i += BT / 64) {
+            const int s0 = gnk::ld_stream(rp + i);
+            const int dd = gnk::ld_stream(rp + i + 1) - s0;
+            unsigned sel = 0u;
+            const float sigma = gnk::row_sum_wave<8>(col + s0, dd, yin, lane, sel);
+            const bool any_sel = __any(sel != 0u);
+            if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+        }
+        const int any = __syncthreads_or(viol ? 1 : 0);
+        if (do_test && !any) {
+            binarised = true;
+            steps = k;
+            break;
+        }
+        if (!do_write) {
+            steps = k;
+            break;
+        }
+        float* t = yin;
+        yin = yout;
+        yout = t;
+    }
+
+    // final state, rounded set, and the statistics of the set (one more pass)
+    for (int i = tid; i < n; i += BT) {
+        float x = fabsf(yin[i]) / vv[i];
+        x = fminf(fmaxf(x, 0.0f), 1.0f);
+        const uint8_t s = x > 0.5f ? 1 : 0;
+        xg[perm[i]] = x;
+        a.sel_cat[d.v_off + perm[i]] = s;
+        yout[i] = s ? 1.0f : 0.0f;  // selection flags for the pass below
+    }
+    __syncthreads();
+    double relaxed = 0.0, set_w = 0.0;
+    long long size = 0, conf = 0, unc = 0;
+    float stab = INFINITY;
+    for (int i = tid; i < n; i += BT) {
+        const bool in_s = yout[i] != 0.0f;
+        float x = fabsf(yin[i]) / vv[i];
+        x = fminf(fmaxf(x, 0.0f), 1.0f);
+        const float wi = a.w[d.v_off + i];
+        relaxed += (double)wi * (double)x;
+        bool any = false;
+        float vsum = 0.0f;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = col[e];
+            if (yout[j] != 0.0f) {
+                any = true;
+                if (in_s && j > i) conf += 1;
+                if (!in_s) vsum += vv[j];
+            }
+        }
+        if (in_s) {
+            set_w += (double)wi;
+            size += 1;
+        } else {
+            if (!any) unc += 1;
+            stab = fminf(stab, vsum / vv[i]);
+        }
+    }
+    long long fbl = fb;
+    relaxed = block_sum_d<BT>(relaxed, sm_d);
+    set_w = block_sum_d<BT>(set_w, sm_d);
+    size = block_sum_ll<BT>(size, sm_l);
+    conf = block_sum_ll<BT>(conf, sm_l);
+    unc = block_sum_ll<BT>(unc, sm_l);
+    fbl = block_sum_ll<BT>(fbl, sm_l);
+    stab = block_min_f<BT>(stab, sm_f);
+    if (tid == 0) {
+        BatchRes r;
+        r.steps = steps;
+        r.binarised = binarised ? 1 : 0;
+        r.fallback = fbl;
+        r.relaxed = relaxed;
+        r.set_w = set_w;
+        r.size = size;
+        r.conflicts = conf;
+        r.uncovered = unc;
+        r.stab = isinf(stab) ? INFINITY : a.gamma[steps] * stab;
+        r.pad = 0;
+        a.res[gi] = r;
+    }
+    __syncthreads();
+}
+
+template <int BT>
+__global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
+    extern __shared__ float lds[];
+    __shared__ int s_g;
+    if (a.queue[1] != 0) return;  // x0 rejected: leave every output untouched
+    for (;;) {
+        if (threadIdx.x == 0) s_g = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int q = s_g;
+        __syncthreads();
+        if (q >= a.count) break;
+        const int gi = a.order[q];
+        if (a.desc[gi].n <= a.lds_vertices)
+            solve_graph<BT, true>(a, gi, lds);
+        else
+            solve_graph<BT, false>(a, gi, lds);
+    }
+}
+
+// Reset queue / error bits and fill the gamma table (Section 6 gamma-pursuit).
+__global__ void batch_init_kernel(int32_t* queue, float* gamma, int32_t max_steps, float g0, float g1, int32_t ramp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        queue[0] = 0;
+        queue[1] = 0;
+    }
+    for (int k = t; k <= max_steps; k += gridDim.x * blockDim.x) {
+        double gk;
+        if (ramp <= 1) {
+            gk = (double)g1;
+        } else {
+            const int kk = k < ramp - 1 ? k : ramp - 1;
+            const double p = (double)kk / (double)(ramp - 1);
+            gk = p * (double)g1 + (1.0 - p) * (double)g0;
+        }
+        gamma[k] = (float)gk;
+    }
+}
+
+// x0 checks for every graph: finite and >= 0 (error bit 1), normalizable: each
+// vertex or one of its neighbours positive (error bit 2).  One thread per
+// vertex of the concatenated batch.
+__global__ void batch_check_x0_kernel(int64_t total, const int32_t* __restrict__ vgraph, const BatchDesc* __restrict__ desc,
+                                      const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                      const int32_t* __restrict__ perm, const float* __restrict__ x_cat,
+                                      int32_t* queue) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int gi = vgraph[t];
+    const BatchDesc d = desc[gi];
+    const int i = (int)(t - d.v_off);
+    const float* xg = x_cat + d.v_off;
+    const int32_t* pm = perm + d.v_off;
+    const float x = xg[pm[i]];
+    if (!(x >= 0.0f) || !isfinite(x)) {
+        atomicOr(queue + 1, 1);
+        return;
+    }
+    if (x > 0.0f) return;
+    const int32_t* rp = row_ptr + d.rp_off;
+    const int32_t* cl = col + d.e_off;
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (xg[pm[cl[e]]] > 0.0f) return;
+    atomicOr(queue + 1, 2);
+}
+
+template <int BT>
+hipError_t launch_batch(dim3 grid, size_t lds_bytes, hipStream_t s, const BatchArgs& a) {
+    hipLaunchKernelGGL(batch_solve_kernel<BT>, grid, dim3(BT), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+template <int BT>
+const void* batch_kernel_ptr() {
+    return (const void*)batch_solve_kernel<BT>;
+}
+
+}  // namespace
+
+struct gn_batch {
+    int32_t count = 0;
+    int64_t total_n = 0, total_nnz = 0;
+    int32_t max_n = 0;
+    int device = 0;
+    int32_t cus = 0;
+    BatchDesc* desc = nullptr;
+    int32_t* order = nullptr;
+    int32_t* vgraph = nullptr;
+    int32_t* row_ptr = nullptr;
+    int32_t* col = nullptr;
+    float* v = nullptr;
+    float* w = nullptr;
+    int32_t* perm = nullptr;
+    float* yg0 = nullptr;
+    float* yg1 = nullptr;
+    int32_t* queue = nullptr;
+    float* gamma = nullptr;
+    int32_t gamma_cap = 0;
+    BatchRes* res = nullptr;
+    BatchRes* res_host = nullptr;  // pinned
+    bool tuned = false;
+    gn_tuning tuning{};
+    // host copies of the caller's CSR for the block-diagonal union graph
+    std::vector<int32_t> h_n;
+    std::vector<int64_t> h_nnz;
+    std::vector<int32_t> h_rp, h_ci;
+    std::vector<float> h_w;
+    gn_graph* uni = nullptr;
+};
+
+static void batch_free(gn_batch* b) {
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(b->desc); f(b->order); f(b->vgraph); f(b->row_ptr); f(b->col); f(b->v); f(b->w); f(b->perm);
+    f(b->yg0); f(b->yg1); f(b->queue); f(b->gamma); f(b->res);
+    if (b->res_host) (void)hipHostFree(b->res_host);
+    if (b->uni) gn_graph_destroy(b->uni);
+}
+
+extern "C" void gn_batch_destroy(gn_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+    delete b;
+}
+
+template <typename T>
+static bool dalloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    return true;
+}
+
+extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int64_t* nnz, const int32_t* row_ptr_cat,
+                                     const int32_t* col_idx_cat, const float* w_cat, uint32_t flags, hipStream_t stream,
+                                     gn_batch** out) {
+    if (!out) return GN_E_ARG;
+    *out = nullptr;
+    if (count < 1 || !n || !nnz || !row_ptr_cat || (flags & ~3u)) return GN_E_ARG;
+    int64_t tn = 0, tnnz = 0, trp = 0;
+    int32_t maxn = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        if (n[g] < 0 || nnz[g] < 0 || nnz[g] > INT32_MAX) return GN_E_ARG;
+        tn += n[g];
+        tnnz += nnz[g];
+        trp += (int64_t)n[g] + 1;
+        maxn = std::max(maxn, n[g]);
+    }
+    if (tn > INT32_MAX || (tn > 0 && !w_cat) || (tnnz > 0 && !col_idx_cat)) return GN_E_ARG;
+
+    gn_batch* b = new (std::nothrow) gn_batch();
+    if (!b) return GN_E_NOMEM;
+    b->h_n.assign(n, n + count);
+    b->h_nnz.assign(nnz, nnz + count);
+    b->h_rp.resize((size_t)trp);
+    b->h_ci.resize((size_t)std::max<int64_t>(tnnz, 1));
+    b->h_w.resize((size_t)std::max<int64_t>(tn, 1));
+    if (flags & GN_INPUT_DEVICE) {
+        bool ok = hipMemcpyAsync(b->h_rp.data(), row_ptr_cat, sizeof(int32_t) * trp, hipMemcpyDeviceToHost, stream) ==
+                  hipSuccess;
+        if (ok && tnnz)
+            ok = hipMemcpyAsync(b->h_ci.data(), col_idx_cat, sizeof(int32_t) * tnnz, hipMemcpyDeviceToHost, stream) ==
+                 hipSuccess;
+        if (ok && tn)
+            ok = hipMemcpyAsync(b->h_w.data(), w_cat, sizeof(float) * tn, hipMemcpyDeviceToHost, stream) == hipSuccess;
+        if (ok) ok = hipStreamSynchronize(stream) == hipSuccess;
+        if (!ok) {
+            delete b;
+            return GN_E_HIP;
+        }
+    } else {
+        std::memcpy(b->h_rp.data(), row_ptr_cat, sizeof(int32_t) * trp);
+        if (tnnz) std::memcpy(b->h_ci.data(), col_idx_cat, sizeof(int32_t) * tnnz);
+        if (tn) std::memcpy(b->h_w.data(), w_cat, sizeof(float) * tn);
+    }
+
+    // validate each graph (same conditions as gn_graph_create) and relabel it:
+    // rows of degree <= kLightMaxDeg first, the rest after, each group in order
+    std::vector<BatchDesc> desc((size_t)count);
+    std::vector<int32_t> rp_int((size_t)trp), col_int((size_t)std::max<int64_t>(tnnz, 1)), perm((size_t)std::max<int64_t>(tn, 1));
+    std::vector<int32_t> vgraph((size_t)std::max<int64_t>(tn, 1));
+    std::vector<float> v_int((size_t)std::max<int64_t>(tn, 1)), w_int((size_t)std::max<int64_t>(tn, 1));
+    int64_t vo = 0, ro = 0, eo = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const int32_t ng = n[g];
+        const int32_t* rp = b->h_rp.data() + ro;
+        const int32_t* ci = b->h_ci.data() + eo;
+        const float* wg = b->h_w.data() + vo;
+        if (rp[0] != 0 || (int64_t)rp[ng] != nnz[g]) { delete b; return GN_E_CSR; }
+        for (int32_t i = 0; i < ng; ++i)
+            if (rp[i + 1] < rp[i]) { delete b; return GN_E_CSR; }
+        for (int64_t e = 0; e < nnz[g]; ++e)
+            if (ci[e] < 0 || ci[e] >= ng) { delete b; return GN_E_CSR; }
+        if (!(flags & GN_NO_VALIDATE)) {
+            for (int32_t i = 0; i < ng; ++i)
+                for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+                    if (ci[e] == i) { delete b; return GN_E_SELF_LOOP; }
+                    if (e > rp[i] && ci[e] <= ci[e - 1]) { delete b; return GN_E_CSR; }
+                }
+            // symmetry via a counting transpose, as in gn_graph_create
+            std::vector<int32_t> tptr((size_t)ng + 1, 0);
+            for (int64_t e = 0; e < nnz[g]; ++e) tptr[(size_t)ci[e] + 1]++;
+            for (int32_t i = 0; i < ng; ++i) tptr[(size_t)i + 1] += tptr[i];
+            for (int32_t i = 0; i <= ng; ++i)
+                if (tptr[i] != rp[i]) { delete b; return GN_E_ASYMMETRIC; }
+            std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1), tcol((size_t)std::max<int64_t>(nnz[g], 1));
+            for (int32_t i = 0; i < ng; ++i)
+                for (int32_t e = rp[i]; e < rp[i + 1]; ++e) tcol[(size_t)fill[ci[e]]++] = i;
+            for (int64_t e = 0; e < nnz[g]; ++e)
+                if (tcol[(size_t)e] != ci[e]) { delete b; return GN_E_ASYMMETRIC; }
+        }
+        for (int32_t i = 0; i < ng; ++i)
+            if (!(wg[i] > 0.0f) || !std::isfinite(wg[i])) { delete b; return GN_E_WEIGHT; }
+        std::vector<int32_t> p((size_t)ng), q((size_t)ng);
+        std::iota(p.begin(), p.end(), 0);
+        std::stable_partition(p.begin(), p.end(), [&](int32_t i) { return rp[i + 1] - rp[i] <= kLightMaxDeg; });
+        int32_t nl = 0;
+        for (int32_t i = 0; i < ng; ++i) nl += (rp[i + 1] - rp[i] <= kLightMaxDeg) ? 1 : 0;
+        for (int32_t r = 0; r < ng; ++r) q[p[r]] = r;
+        int32_t* rpi = rp_int.data() + ro;
+        rpi[0] = 0;
+        for (int32_t r = 0; r < ng; ++r) {
+            const int32_t i = p[r];
+            const int32_t dg = rp[i + 1] - rp[i];
+            for (int32_t e = 0; e < dg; ++e) col_int[(size_t)(eo + rpi[r] + e)] = q[ci[rp[i] + e]];
+            rpi[r + 1] = rpi[r] + dg;
+            perm[(size_t)(vo + r)] = i;
+            v_int[(size_t)(vo + r)] = (float)std::sqrt((double)wg[i]);
+            w_int[(size_t)(vo + r)] = wg[i];
+            vgraph[(size_t)(vo + r)] = g;
+        }
+        desc[g] = BatchDesc{ng, nl, vo, ro, eo};
+        vo += ng;
+        ro += (int64_t)ng + 1;
+        eo += nnz[g];
+    }
+    std::vector<int32_t> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        return (int64_t)nnz[a] + n[a] > (int64_t)nnz[c] + n[c];
+    });
+
+    b->count = count;
+    b->total_n = tn;
+    b->total_nnz = tnnz;
+    b->max_n = maxn;
+    (void)hipGetDevice(&b->device);
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    b->cus = cus > 0 ? cus : 256;
+    bool ok = dalloc(&b->desc, count) && dalloc(&b->order, count) && dalloc(&b->vgraph, tn) &&
+              dalloc(&b->row_ptr, trp) && dalloc(&b->col, tnnz) && dalloc(&b->v, tn) && dalloc(&b->w, tn) &&
+              dalloc(&b->perm, tn) && dalloc(&b->yg0, tn) && dalloc(&b->yg1, tn) && dalloc(&b->queue, 2) &&
+              dalloc(&b->res, count);
+    if (ok && hipHostMalloc((void**)&b->res_host, sizeof(BatchRes) * count, hipHostMallocDefault) != hipSuccess) {
+        b->res_host = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        batch_free(b);
+        delete b;
+        return GN_E_NOMEM;
+    }
+    hipError_t e = hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    up(b->desc, desc.data(), sizeof(BatchDesc) * count);
+    up(b->order, order.data(), sizeof(int32_t) * count);
+    up(b->vgraph, vgraph.data(), sizeof(int32_t) * tn);
+    up(b->row_ptr, rp_int.data(), sizeof(int32_t) * trp);
+    up(b->col, col_int.data(), sizeof(int32_t) * tnnz);
+    up(b->v, v_int.data(), sizeof(float) * tn);
+    up(b->w, w_int.data(), sizeof(float) * tn);
+    up(b->perm, perm.data(), sizeof(int32_t) * tn);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        batch_free(b);
+        delete b;
+        return GN_E_HIP;
+    }
+    *out = b;
+    return GN_OK;
+}
+
+static bool tuning_valid(const gn_tuning& t) {
+    return (t.block_threads == 128 || t.block_threads == 256 || t.block_threads == 512) && t.blocks_per_cu >= 1 &&
+           t.blocks_per_cu <= 4 && t.lds_vertices >= 0 && (size_t)t.lds_vertices * 12 * t.blocks_per_cu <= kLdsBudget;
+}
+
+static gn_tuning default_tuning(const gn_batch* b) {
+    gn_tuning t{};
+    t.block_threads = 256;
+    t.blocks_per_cu = 2;
+    t.lds_vertices = std::min<int32_t>(b->max_n, kLdsBudget / (12 * 2));
+    t.reserved = 0;
+    return t;
+}
+
+static gn_status ensure_gamma(gn_batch* b, int32_t entries) {
+    if (entries <= b->gamma_cap) return GN_OK;
+    if (b->gamma) (void)hipFree(b->gamma);
+    b->gamma = nullptr;
+    b->gamma_cap = 0;
+    if (!dalloc(&b->gamma, (size_t)entries)) return GN_E_NOMEM;
+    b->gamma_cap = entries;
+    return GN_OK;
+}
+
+// Enqueue the whole batched solve (init, x0 checks, persistent kernel).
+static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, float* x_cat, uint8_t* sel_cat,
+                               hipStream_t s) {
+    gn_status st = ensure_gamma(b, sch->max_steps + 1);
+    if (st != GN_OK) return st;
+    hipLaunchKernelGGL(batch_init_kernel, dim3(std::min((sch->max_steps + 1 + 255) / 256, 1024)), dim3(256), 0, s,
+                       b->queue, b->gamma, sch->max_steps, sch->gamma0, sch->gamma1, sch->ramp_steps);
+    GN_HIP_TRY(hipGetLastError());
+    if (b->total_n > 0) {
+        hipLaunchKernelGGL(batch_check_x0_kernel, dim3((unsigned)((b->total_n + 255) / 256)), dim3(256), 0, s,
+                           b->total_n, b->vgraph, b->desc, b->row_ptr, b->col, b->perm, x_cat, b->queue);
+        GN_HIP_TRY(hipGetLastError());
+    }
+    BatchArgs a{};
+    a.desc = b->desc;
+    a.order = b->order;
+    a.count = b->count;
+    a.row_ptr = b->row_ptr;
+    a.col = b->col;
+    a.v = b->v;
+    a.w = b->w;
+    a.perm = b->perm;
+    a.gamma = b->gamma;
+    a.max_steps = sch->max_steps;
+    a.check_every = sch->check_every;
+    a.tau = sch->tau;
+    a.lds_vertices = t.lds_vertices;
+    a.x_cat = x_cat;
+    a.sel_cat = sel_cat;
+    a.yg0 = b->yg0;
+    a.yg1 = b->yg1;
+    a.queue = b->queue;
+    a.res = b->res;
+    const int blocks = std::min<int64_t>((int64_t)b->cus * t.blocks_per_cu, b->count);
+    const size_t lds = (size_t)t.lds_vertices * 3 * sizeof(float);
+    hipError_t e;
+    if (t.block_threads == 128)
+        e = launch_batch<128>(dim3(blocks), lds, s, a);
+    else if (t.block_threads == 512)
+        e = launch_batch<512>(dim3(blocks), lds, s, a);
+    else
+        e = launch_batch<256>(dim3(blocks), lds, s, a);
+    return e == hipSuccess ? GN_OK : GN_E_HIP;
+}
+
+static void allow_lds(int bt, size_t bytes) {
+    const void* f = bt == 128 ? batch_kernel_ptr<128>() : bt == 512 ? batch_kernel_ptr<512>() : batch_kernel_ptr<256>();
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static gn_status check_schedule(const gn_schedule* sch) {
+    if (!sch || sch->max_steps < 0 || sch->check_every < 1 || !(sch->tau >= 0.0f) || !std::isfinite(sch->tau) ||
+        !std::isfinite(sch->gamma0) || !std::isfinite(sch->gamma1) || sch->gamma0 < 0.0f || sch->gamma1 < 0.0f ||
+        sch->max_steps > (1 << 28))
+        return GN_E_ARG;
+    return GN_OK;
+}
+
+extern "C" gn_status gn_batch_solve(gn_batch* b, const gn_schedule* sch, const gn_tuning* tuning, float* x_cat,
+                                    uint8_t* sel_cat, gn_result* res, hipStream_t stream) {
+    if (!b || !res) return GN_E_ARG;
+    gn_status st = check_schedule(sch);
+    if (st != GN_OK) return st;
+    if (b->total_n > 0 && (!x_cat || !sel_cat)) return GN_E_ARG;
+    gn_tuning t = tuning ? *tuning : (b->tuned ? b->tuning : default_tuning(b));
+    if (!tuning_valid(t)) return GN_E_ARG;
+    allow_lds(t.block_threads, (size_t)t.lds_vertices * 12);
+    st = enqueue_batch(b, sch, t, x_cat, sel_cat, stream);
+    if (st != GN_OK) return st;
+    int32_t qh[2];
+    GN_HIP_TRY(hipMemcpyAsync(b->res_host, b->res, sizeof(BatchRes) * b->count, hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipMemcpyAsync(qh, b->queue, sizeof(qh), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    if (qh[1] & 1) return GN_E_ARG;
+    if (qh[1] & 2) return GN_E_NOT_NORMALIZABLE;
+    bool all = true;
+    for (int32_t g = 0; g < b->count; ++g) {
+        const BatchRes& r = b->res_host[g];
+        gn_result& o = res[g];
+        if (b->h_n[g] == 0) {
+            std::memset(&o, 0, sizeof(o));
+            o.binarised = 1;
+            o.stab = INFINITY;
+            continue;
+        }
+        o.steps = r.steps;
+        o.binarised = r.binarised;
+        o.fallback_count = r.fallback;
+        o.relaxed_objective = r.relaxed;
+        o.set_objective = r.set_w;
+        o.set_size = r.size;
+        o.conflicts = r.conflicts;
+        o.uncovered = r.uncovered;
+        o.stab = r.stab;
+        all = all && r.binarised;
+    }
+    return all ? GN_OK : GN_NOT_CONVERGED;
+}
+
+extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_tuning* out, hipStream_t stream) {
+    if (!b || !out) return GN_E_ARG;
+    gn_status st = check_schedule(sch);
+    if (st != GN_OK) return st;
+    // bounded timing runs: at most 64 steps, from x0 = 1/2
+    gn_schedule ts = *sch;
+    ts.max_steps = std::min<int32_t>(sch->max_steps, 64);
+    float* x = nullptr;
+    uint8_t* sel = nullptr;
+    if (!dalloc(&x, (size_t)b->total_n) || !dalloc(&sel, (size_t)b->total_n)) {
+        if (x) (void)hipFree(x);
+        return GN_E_NOMEM;
+    }
+    std::vector<float> half((size_t)std::max<int64_t>(b->total_n, 1), 0.5f);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    gn_tuning best = default_tuning(b);
+    float best_ms = INFINITY;
+    st = GN_OK;
+    for (int bt : {128, 256, 512}) {
+        for (int bpc : {1, 2, 4}) {
+            gn_tuning t{};
+            t.block_threads = bt;
+            t.blocks_per_cu = bpc;
+            t.lds_vertices = std::min<int32_t>(b->max_n, kLdsBudget / (12 * bpc));
+            if (!tuning_valid(t)) continue;
+            allow_lds(bt, (size_t)t.lds_vertices * 12);
+            float ms_sum = 0.0f;
+            for (int rep = 0; rep < 2 && st == GN_OK; ++rep) {
+                if (hipMemcpyAsync(x, half.data(), sizeof(float) * b->total_n, hipMemcpyHostToDevice, stream) !=
+                    hipSuccess) {
+                    st = GN_E_HIP;
+                    break;
+                }
+                (void)hipEventRecord(e0, stream);
+                st = enqueue_batch(b, &ts, t, x, sel, stream);
+                (void)hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess) st = GN_E_HIP;
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep == 1) ms_sum += ms;
+            }
+            if (st != GN_OK) break;
+            if (ms_sum < best_ms) {
+                best_ms = ms_sum;
+                best = t;
+            }
+        }
+        if (st != GN_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(sel);
+    if (st != GN_OK) return st;
+    b->tuning = best;
+    b->tuned = true;
+    *out = best;
+    return GN_OK;
+}
+
+extern "C" const gn_graph* gn_batch_graph(const gn_batch* bc) {
+    if (!bc) return nullptr;
+    gn_batch* b = const_cast<gn_batch*>(bc);
+    if (b->uni) return b->uni;
+    // block-diagonal union with global vertex ids
+    std::vector<int32_t> rp((size_t)b->total_n + 1), ci((size_t)std::max<int64_t>(b->total_nnz, 1));
+    int64_t vo = 0, ro = 0, eo = 0;
+    rp[0] = 0;
+    for (int32_t g = 0; g < b->count; ++g) {
+        const int32_t ng = b->h_n[g];
+        for (int32_t i = 0; i < ng; ++i) rp[(size_t)(vo + i + 1)] = (int32_t)(eo + b->h_rp[(size_t)(ro + i + 1)]);
+        for (int64_t e = 0; e < b->h_nnz[g]; ++e) ci[(size_t)(eo + e)] = (int32_t)(vo + b->h_ci[(size_t)(eo + e)]);
+        vo += ng;
+        ro += (int64_t)ng + 1;
+        eo += b->h_nnz[g];
+    }
+    gn_graph* u = nullptr;
+    if (gn_graph_create((int32_t)b->total_n, b->total_nnz, rp.data(), ci.data(), b->h_w.data(),
+                        GN_INPUT_HOST | GN_NO_VALIDATE, nullptr, &u) != GN_OK)
+        return nullptr;
+    b->uni = u;
+    return u;
+}

@@ -1,0 +1,443 @@
+// The fused WRGN step kernel and the solve driver.
+//
+// One step (WRGN definition; y-space form of the energy-descent appendix; safe
+// division of the code appendix), for every row i:
+//     s_i  = |y_i| + gamma * sum_{j in N(i)} |y_j|
+//     x'_i = |y_i| / s_i  if s_i > 1e-9,  else 1/2
+//     y'_i = v_i x'_i, stored with its sign bit set when x'_i > 1/2
+// The sign bit carries the rounded set S to the next step, so the stopping test
+// on the input state (cover of S, decay of the non-selected rows, distance to
+// binary) is computed inside the same pass at no extra memory traffic.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "gn_internal.h"
+#include "gn_rowsum.h"
+
+using gnk::sign_of;
+
+namespace {
+
+// Row epilogue; returns true when the input state fails the stopping test at row i.
+__device__ __forceinline__ bool row_update(const StepArgs& a, int i, float yraw, float vi, float sigma, bool nbr_sel,
+                                           float g, bool do_test, bool do_write, float tau, int& fb) {
+    const float yi = fabsf(yraw);
+    const float s = __fmaf_rn(g, sigma, yi);
+    const bool fallback = !(s > 1e-9f);
+    const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
+    if (do_write) {
+        if (a.y_out) {
+            const float yn = vi * xn;
+            a.y_out[i] = xn > 0.5f ? -yn : yn;
+        }
+        if (a.x_out_user) a.x_out_user[a.perm[i]] = xn;
+        fb += fallback ? 1 : 0;
+    }
+    if (!do_test) return false;
+    const bool in_s = sign_of(yraw) != 0u;
+    const float tv = tau * vi;
+    const bool far = (yi > tv) && ((vi - yi) > tv);   // min(x, 1-x) > tau with x = y/v
+    const bool uncovered = !in_s && !nbr_sel;
+    const bool growing = !in_s && (yi > 0.0f) && !(s > vi);
+    return far || uncovered || growing;
+}
+
+// Rows of one bin handled by groups of G threads, MAXD = the bin's degree bound.
+template <int G, int MAXD>
+__device__ __forceinline__ bool group_rows(const StepArgs& a, int rb, int re, int lb, float g, bool do_test,
+                                           bool do_write, float tau, int& fb) {
+    constexpr int per_block = kBlock / G;
+    const int t = threadIdx.x & (G - 1);
+    const int i = rb + lb * per_block + threadIdx.x / G;
+    const bool valid = i < re;
+    const float* __restrict__ y = a.y_in;
+    float yraw = 0.0f, vi = 1.0f;
+    int start = 0, d = 0;
+    if (valid) {
+        start = gnk::ld_stream(a.row_ptr + i);
+        d = gnk::ld_stream(a.row_ptr + i + 1) - start;
+        yraw = y[i];
+        vi = gnk::ld_stream(a.v + i);
+    }
+    unsigned sel = 0u;
+    const float sigma = gnk::row_sum<G, MAXD>(a.col + start, d, y, t, sel);
+    const bool any_sel = gnk::group_any<G>(sel != 0u);
+    if (valid && t == 0) return row_update(a, i, yraw, vi, sigma, any_sel, g, do_test, do_write, tau, fb);
+    return false;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
+    __shared__ float stage[kStage];
+    __shared__ int s_flag;
+    __shared__ int s_fb;
+
+    float g;
+    float tau = 0.0f;
+    bool do_test = false, do_write = true;
+    if (a.solve) {
+        // every value is loaded up front (independent loads); the gamma and flag
+        // tables cover every step index a captured chain can reach
+        const SolveState* st = a.st;
+        const int done = st->done_step, err = st->err, ms = st->max_steps, ce = st->check_every;
+        const float tau_s = st->tau;
+        const int km = a.k >= 1 ? a.k - 1 : 0;
+        const int nc_prev = a.notconv[km];
+        const float gk = a.gamma[a.k];
+        if (a.k > ms || done >= 0 || err) return;
+        if (a.k >= 2 && (km % ce == 0 || km == ms) && nc_prev == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.st->done_step = km;
+            return;
+        }
+        do_test = a.k >= 1 && (a.k % ce == 0 || a.k == ms);
+        do_write = a.k < ms;
+        tau = tau_s;
+        g = gk;
+    } else {
+        g = a.gamma_scalar;
+    }
+    if (threadIdx.x == 0) {
+        s_flag = 0;
+        s_fb = 0;
+    }
+    __syncthreads();
+
+    const int blk = blockIdx.x;
+    int b = 0;
+    while (b < BIN_COUNT - 1 && blk >= a.bins.blk_begin[b + 1]) ++b;
+    const int lb = blk - a.bins.blk_begin[b];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rb = a.bins.row_begin[b], re = a.bins.row_begin[b + 1];
+    bool viol = false;
+    int fb = 0;
+
+    if (b == BIN_BLOCK) {
+        // one workgroup per row: all waves gather neighbour values into LDS,
+        // wave 0 runs the 64 canonical chains over them
+        const int i = rb + lb;
+        const int start = gnk::ld_stream(a.row_ptr + i);
+        const int d = gnk::ld_stream(a.row_ptr + i + 1) - start;
+        const float yraw = a.y_in[i];
+        const float vi = a.v[i];
+        constexpr int PT = kStage / kBlock;  // entries per thread per chunk
+        float acc = 0.0f;
+        unsigned sel = 0u;
+        for (int c0 = 0; c0 < d; c0 += kStage) {
+            const int cn = min(kStage, d - c0);
+            int cidx[PT];
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                const int p = threadIdx.x + kBlock * u;
+                cidx[u] = p < cn ? a.col[start + c0 + p] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < PT; ++u)
+                if (cidx[u] >= 0) stage[threadIdx.x + kBlock * u] = a.y_in[cidx[u]];
+            __syncthreads();
+            if (wave == 0) {
+                for (int q = lane; q < cn; q += 64) {
+                    const float yv = stage[q];
+                    acc += fabsf(yv);
+                    sel |= sign_of(yv);
+                }
+            }
+            __syncthreads();
+        }
+        if (wave == 0) {
+            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            const bool any_sel = __any(sel != 0u);
+            if (lane == 0) viol = row_update(a, i, yraw, vi, acc, any_sel, g, do_test, do_write, tau, fb);
+        }
+    } else if (b == BIN_WAVE) {
+        // two rows per wavefront, all their loads in flight together
+        const int ia = rb + (lb * kWaves + wave) * 2;
+        const int ib = ia + 1;
+        if (ia < re) {
+            const bool hb = ib < re;
+            const int sa = gnk::ld_stream(a.row_ptr + ia), ea = gnk::ld_stream(a.row_ptr + ia + 1);
+            const int sb = hb ? ea : 0, eb = hb ? gnk::ld_stream(a.row_ptr + ib + 1) : 0;
+            const float ya = a.y_in[ia], va = a.v[ia];
+            const float yb = hb ? a.y_in[ib] : 0.0f, vb = hb ? a.v[ib] : 1.0f;
+            unsigned sela = 0u, selb = 0u;
+            float acca, accb;
+            gnk::row_sum_wave2<kWaveMaxDeg / 64>(a.col + sa, ea - sa, a.col + sb, eb - sb, a.y_in, lane, acca, accb,
+                                                 sela, selb);
+            const bool anya = __any(sela != 0u);
+            const bool anyb = __any(selb != 0u);
+            if (lane == 0) viol = row_update(a, ia, ya, va, acca, anya, g, do_test, do_write, tau, fb);
+            if (lane == 1 && hb) viol = row_update(a, ib, yb, vb, accb, anyb, g, do_test, do_write, tau, fb);
+        }
+    } else if (b == BIN_G8) {
+        viol = group_rows<8, 128>(a, rb, re, lb, g, do_test, do_write, tau, fb);
+    } else if (b == BIN_LANE32) {
+        viol = group_rows<2, 32>(a, rb, re, lb, g, do_test, do_write, tau, fb);
+    } else {
+        viol = group_rows<1, 16>(a, rb, re, lb, g, do_test, do_write, tau, fb);
+    }
+
+    if (a.solve) {
+        if (viol) s_flag = 1;
+        if (fb) atomicAdd(&s_fb, fb);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_flag) a.notconv[a.k] = 1;
+            if (s_fb) atomicAdd(&a.st->fallback, (unsigned long long)s_fb);
+        }
+    }
+}
+
+// x (user order) -> signed weighted state y (internal order); flags x < 0 or
+// non-finite (err bit 1).
+__global__ void prep_state_kernel(int32_t n, const float* __restrict__ x_user, const int32_t* __restrict__ perm,
+                                  const float* __restrict__ v, float* __restrict__ y, SolveState* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x = x_user[perm[i]];
+    if (!(x >= 0.0f) || !isfinite(x)) {
+        if (st) atomicOr(&st->err, 1);
+        x = 0.0f;
+    }
+    const float yy = v[i] * x;
+    y[i] = x > 0.5f ? -yy : yy;
+}
+
+// Normalizable (Section 2): (A + I) x > 0, i.e. x_i > 0 or some neighbour
+// x_j > 0.  Flags err bit 2 otherwise.
+__global__ void normalizable_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                    const float* __restrict__ x_user, const int32_t* __restrict__ perm,
+                                    SolveState* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (x_user[perm[i]] > 0.0f) return;
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+        if (x_user[perm[col[e]]] > 0.0f) return;
+    atomicOr(&st->err, 2);
+}
+
+// Reset the solve state and fill the gamma table (Section 6 gamma-pursuit,
+// evaluated in double and rounded once to fp32).
+__global__ void init_solve_kernel(SolveState* st, int32_t* notconv, float* gamma, int32_t max_steps,
+                                  int32_t check_every, float tau, float g0, float g1, int32_t ramp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        st->done_step = -1;
+        st->err = 0;
+        st->max_steps = max_steps;
+        st->check_every = check_every;
+        st->tau = tau;
+        st->pad = 0;
+        st->fallback = 0ull;
+    }
+    for (int k = t; k <= max_steps; k += gridDim.x * blockDim.x) {
+        notconv[k] = 0;
+        double gk;
+        if (ramp <= 1) {
+            gk = (double)g1;
+        } else {
+            const int kk = k < ramp - 1 ? k : ramp - 1;
+            const double p = (double)kk / (double)(ramp - 1);
+            gk = p * (double)g1 + (1.0 - p) * (double)g0;
+        }
+        gamma[k] = (float)gk;
+    }
+}
+
+static float host_gamma(const gn_schedule* s, int32_t k) {
+    if (s->ramp_steps <= 1) return s->gamma1;
+    const int32_t kk = k < s->ramp_steps - 1 ? k : s->ramp_steps - 1;
+    const double p = (double)kk / (double)(s->ramp_steps - 1);
+    return (float)(p * (double)s->gamma1 + (1.0 - p) * (double)s->gamma0);
+}
+
+gn_status gn_internal_launch_step(const gn_graph* g, const StepArgs& a, hipStream_t s) {
+    const int nblk = gn_internal_grid_blocks(g->bins);
+    if (nblk == 0) return GN_OK;
+    hipLaunchKernelGGL(wrgn_step_kernel, dim3(nblk), dim3(kBlock), 0, s, a);
+    GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
+}
+
+static StepArgs base_args(const gn_graph* g) {
+    StepArgs a{};
+    a.row_ptr = g->row_ptr;
+    a.col = g->col;
+    a.v = g->v;
+    a.perm = g->perm;
+    a.bins = g->bins;
+    return a;
+}
+
+extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, float* x_out,
+                             hipStream_t stream) {
+    if (!g) return GN_E_ARG;
+    if (!std::isfinite(gamma) || gamma < 0.0f) return GN_E_ARG;
+    if (g->n == 0) return GN_OK;
+    if (!x_in || !x_out || x_in == x_out) return GN_E_ARG;
+    gn_graph* gm = const_cast<gn_graph*>(g);
+    gn_status st = gn_internal_ensure_ws(gm, 1);
+    if (st != GN_OK) return st;
+    const int n = g->n;
+    hipLaunchKernelGGL(prep_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, x_in, g->perm, g->v,
+                       g->ws.y[0], (SolveState*)nullptr);
+    GN_HIP_TRY(hipGetLastError());
+    StepArgs a = base_args(g);
+    a.y_in = g->ws.y[0];
+    a.y_out = nullptr;
+    a.gamma = nullptr;
+    a.gamma_scalar = gamma;
+    a.solve = 0;
+    a.x_out_user = x_out;
+    return gn_internal_launch_step(g, a, stream);
+}
+
+// Captured chain of `len` step launches for steps [c*len, (c+1)*len).
+static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t* out) {
+    GraphWorkspace& ws = g->ws;
+    hipGraph_t graph;
+    GN_HIP_TRY(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    const int nblk = gn_internal_grid_blocks(g->bins);
+    for (int32_t j = 0; j < len; ++j) {
+        StepArgs a = base_args(g);
+        a.k = c * len + j;
+        a.y_in = ws.y[a.k & 1];
+        a.y_out = ws.y[(a.k + 1) & 1];
+        a.gamma = ws.gamma;
+        a.solve = 1;
+        a.st = ws.state;
+        a.notconv = ws.notconv;
+        a.x_out_user = nullptr;
+        void* args[] = {&a};
+        hipKernelNodeParams p{};
+        p.func = (void*)wrgn_step_kernel;
+        p.gridDim = dim3(nblk);
+        p.blockDim = dim3(kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return GN_E_HIP;
+        }
+        prev = node;
+    }
+    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e == hipSuccess ? GN_OK : GN_E_HIP;
+}
+
+static int32_t g_chunk_len = 32;
+
+extern "C" gn_status gn_set_chunk_len(int32_t len);
+gn_status gn_set_chunk_len(int32_t len) {
+    if (len < 1 || len > 4096) return GN_E_ARG;
+    g_chunk_len = len;
+    return GN_OK;
+}
+
+extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                              hipStream_t stream) {
+    if (!g || !sch || !res) return GN_E_ARG;
+    if (sch->max_steps < 0 || sch->check_every < 1 || !(sch->tau >= 0.0f) || !std::isfinite(sch->tau) ||
+        !std::isfinite(sch->gamma0) || !std::isfinite(sch->gamma1) || sch->gamma0 < 0.0f || sch->gamma1 < 0.0f ||
+        sch->max_steps > (1 << 28))
+        return GN_E_ARG;
+    std::memset(res, 0, sizeof(*res));
+    if (g->n == 0) {
+        res->binarised = 1;
+        res->stab = INFINITY;
+        return GN_OK;
+    }
+    if (!x || !sel) return GN_E_ARG;
+    const int32_t ms = sch->max_steps;
+    const int32_t C = g_chunk_len;
+    const int32_t nchunks = (ms + 1 + C - 1) / C;
+    gn_status st = gn_internal_ensure_ws(g, nchunks * C);
+    if (st != GN_OK) return st;
+    GraphWorkspace& ws = g->ws;
+    const int n = g->n;
+
+    hipLaunchKernelGGL(init_solve_kernel, dim3(std::min((ms + 1 + 255) / 256, 1024)), dim3(256), 0, stream, ws.state,
+                       ws.notconv, ws.gamma, ms, sch->check_every, sch->tau, sch->gamma0, sch->gamma1,
+                       sch->ramp_steps);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(prep_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, (const float*)x, g->perm,
+                       g->v, ws.y[0], ws.state);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(normalizable_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, g->row_ptr, g->col,
+                       (const float*)x, g->perm, ws.state);
+    GN_HIP_TRY(hipGetLastError());
+
+    if (ws.chunk_len != C) {
+        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        ws.chunks.clear();
+        ws.chunk_len = C;
+    }
+    if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
+    volatile int32_t* pin = (volatile int32_t*)ws.host_pinned;  // [slot][done_step, err]
+    hipEvent_t ev[2];
+    GN_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return GN_E_HIP;
+    }
+    gn_status rs = GN_OK;
+    for (int32_t c = 0; c < nchunks && rs == GN_OK; ++c) {
+        if (!ws.chunks[c]) {
+            rs = build_chunk(g, c, C, &ws.chunks[c]);
+            if (rs != GN_OK) break;
+        }
+        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess ||
+            hipMemcpyAsync((void*)(pin + 2 * (c & 1)), ws.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess ||
+            hipEventRecord(ev[c & 1], stream) != hipSuccess) {
+            rs = GN_E_HIP;
+            break;
+        }
+        if (c >= 1) {
+            const int p = (c - 1) & 1;
+            if (hipEventSynchronize(ev[p]) != hipSuccess) {
+                rs = GN_E_HIP;
+                break;
+            }
+            if (pin[2 * p] >= 0 || pin[2 * p + 1] != 0) break;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rs != GN_OK) return rs;
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    SolveState hs;
+    int32_t nc_last = 1;
+    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    GN_HIP_TRY(hipMemcpy(&nc_last, ws.notconv + ms, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (hs.err & 1) return GN_E_ARG;
+    if (hs.err & 2) return GN_E_NOT_NORMALIZABLE;
+    int32_t steps;
+    bool binarised;
+    if (hs.done_step >= 0) {
+        steps = hs.done_step;
+        binarised = true;
+    } else {
+        steps = ms;
+        binarised = ms >= 1 && nc_last == 0;
+    }
+    FinalStats fs{};
+    st = gn_internal_final_stats(g, ws.y[steps & 1], host_gamma(sch, steps), x, sel, &fs, stream);
+    if (st != GN_OK) return st;
+    res->steps = steps;
+    res->binarised = binarised ? 1 : 0;
+    res->fallback_count = (int64_t)hs.fallback;
+    res->relaxed_objective = fs.relaxed_objective;
+    res->set_objective = fs.set_objective;
+    res->set_size = fs.set_size;
+    res->conflicts = fs.conflicts;
+    res->uncovered = fs.uncovered;
+    res->stab = fs.stab;
+    return binarised ? GN_OK : GN_NOT_CONVERGED;
+}

@@ -58,10 +58,16 @@ def rng_for(seed: int, stream: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream)])))
 
 
-def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray) -> Graph:
-    """Symmetric CSR from undirected edges ``src[k] -- dst[k]`` (no loops, no duplicates)."""
+def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray, dedup: bool = False) -> Graph:
+    """Symmetric CSR from undirected edges ``src[k] -- dst[k]`` (no loops; duplicates
+    must be absent unless ``dedup``, which drops repeated pairs and loops)."""
     src = np.asarray(src, dtype=np.int64)
     dst = np.asarray(dst, dtype=np.int64)
+    if dedup and src.size:
+        a, b = np.minimum(src, dst), np.maximum(src, dst)
+        keep = a != b
+        pairs = np.unique(np.stack([a[keep], b[keep]], axis=1), axis=0)
+        src, dst = pairs[:, 0], pairs[:, 1]
     rows = np.concatenate([src, dst])
     cols = np.concatenate([dst, src])
     order = np.lexsort((cols, rows))
@@ -198,6 +204,23 @@ def rook(N: int) -> Graph:
     return Graph(n, row_ptr.astype(np.int32), cols.reshape(-1))
 
 
+def hub_graph(n: int, hub_degrees, background_degree: float, seed: int, stream: int = 0) -> Graph:
+    """Sparse ER background of the given mean degree plus one hub per entry of
+    ``hub_degrees``, each joined to that many distinct random vertices: a
+    ragged degree mix from 0 to the largest hub degree."""
+    rng = rng_for(seed, stream)
+    bg = erdos_renyi(n, background_degree / max(n - 1, 1), seed, stream + 100)
+    s0, d0 = edges_of(bg)
+    srcs, dsts = [s0], [d0]
+    hubs = rng.choice(n, size=len(hub_degrees), replace=False)
+    for h, d in zip(hubs, hub_degrees):
+        others = rng.choice(n - 1, size=int(d), replace=False)
+        others = others + (others >= h)
+        srcs.append(np.full(int(d), h, dtype=np.int64))
+        dsts.append(others.astype(np.int64))
+    return csr_from_edges(n, np.concatenate(srcs), np.concatenate(dsts), dedup=True)
+
+
 def weights_uniform01(n: int, seed: int, stream: int = 1) -> np.ndarray:
     """w = 1 - u with u uniform on [0, 1) in fp32: values in (0, 1], exact in fp32."""
     u = rng_for(seed, stream).random(size=n, dtype=np.float32)
@@ -234,3 +257,23 @@ def concat_graphs(graphs: list[Graph]) -> tuple[np.ndarray, np.ndarray, np.ndarr
     rp = np.concatenate([g.row_ptr for g in graphs]).astype(np.int32) if graphs else np.zeros(0, np.int32)
     ci = np.concatenate([g.col_idx for g in graphs]).astype(np.int32) if graphs else np.zeros(0, np.int32)
     return ns, nnzs, rp, ci
+
+
+def batch_workload(count: int = 4096, seed: int = 0, n_lo: int = 50, n_hi: int = 5000):
+    """Many independent graphs of uneven sizes: n_g = floor(exp(U(ln n_lo, ln n_hi))),
+    the first half Erdos-Renyi with mean degree 6, the second half unit-disk with
+    radius set for mean degree 10; weights uniform (0, 1].  Graph g uses seed
+    (seed, g).  Returns (graphs, weights)."""
+    ns = batch_sizes_loguniform(count, n_lo, n_hi, seed)
+    graphs, weights = [], []
+    half = count // 2
+    for g in range(count):
+        n = int(ns[g])
+        gseed = seed * 1_000_003 + g
+        if g < half:
+            gr = erdos_renyi(n, 6.0 / max(n - 1, 1), gseed)
+        else:
+            gr = unit_disk(n, 10.0, gseed)
+        graphs.append(gr)
+        weights.append(weights_uniform01(n, gseed))
+    return graphs, weights

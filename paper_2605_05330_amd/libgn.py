@@ -1,0 +1,356 @@
+"""Thin ctypes binding of libgn (include/libgn.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory (``tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if
+``libgn.so`` is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libgn.so")
+
+GN_OK, GN_NOT_CONVERGED = 0, 1
+GN_E_ARG, GN_E_CSR, GN_E_SELF_LOOP, GN_E_ASYMMETRIC, GN_E_WEIGHT = -1, -2, -3, -4, -5
+GN_E_NOT_NORMALIZABLE, GN_E_NUMERIC, GN_E_HIP, GN_E_NOMEM = -6, -7, -8, -9
+GN_INPUT_HOST, GN_INPUT_DEVICE, GN_NO_VALIDATE = 0, 1, 2
+GN_NUM_BINS = 7
+
+
+class GNError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {gn_status_str(status)} ({status})")
+
+
+class gn_schedule(ctypes.Structure):
+    _fields_ = [("gamma0", ctypes.c_float), ("gamma1", ctypes.c_float), ("ramp_steps", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("tau", ctypes.c_float), ("check_every", ctypes.c_int32)]
+
+
+class gn_result(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("binarised", ctypes.c_int32), ("fallback_count", ctypes.c_int64),
+                ("relaxed_objective", ctypes.c_double), ("set_objective", ctypes.c_double),
+                ("set_size", ctypes.c_int64), ("conflicts", ctypes.c_int64), ("uncovered", ctypes.c_int64),
+                ("stab", ctypes.c_float)]
+
+
+class gn_tuning(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lds_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libgn.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libgn.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "gn_graph_create": ([ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_uint32, _vp,
+                                 ctypes.POINTER(_vp)], ctypes.c_int),
+            "gn_graph_destroy": ([_vp], None),
+            "gn_graph_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "gn_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
+            "gn_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
+                         ctypes.c_int),
+            "gn_objective": ([_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp], ctypes.c_int),
+            "gn_check_independent": ([_vp, _vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      _vp], ctypes.c_int),
+            "gn_status_str": ([ctypes.c_int], ctypes.c_char_p),
+            "gn_set_chunk_len": ([ctypes.c_int32], ctypes.c_int),
+            "gn_batch_create": ([ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
+                                ctypes.c_int),
+            "gn_batch_destroy": ([_vp], None),
+            "gn_batch_solve": ([_vp, ctypes.POINTER(gn_schedule), ctypes.POINTER(gn_tuning), _vp, _vp,
+                                ctypes.POINTER(gn_result), _vp], ctypes.c_int),
+            "gn_batch_autotune": ([_vp, ctypes.POINTER(gn_schedule), ctypes.POINTER(gn_tuning), _vp], ctypes.c_int),
+            "gn_batch_graph": ([_vp], _vp),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def gn_status_str(s: int) -> str:
+    try:
+        return lib().gn_status_str(int(s)).decode()
+    except Exception:
+        return f"status {s}"
+
+
+def _check(st: int, where: str, allow=(GN_OK,)) -> int:
+    if st not in allow:
+        raise GNError(st, where)
+    return st
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, dtype=None, what="tensor"):
+    """Device pointer of a contiguous CUDA tensor (checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, ctypes.c_void_p(a.ctypes.data if a.size else 0)
+
+
+def gn_graph_create(n, row_ptr, col_idx, w, flags=None, validate=True, stream=None):
+    """Create a graph handle.  Host numpy arrays or CUDA tensors (int32, int32, float32)."""
+    import torch
+    dev = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
+    keep = []
+    if dev:
+        nnz = int(col_idx.numel())
+        p_rp = _dptr(row_ptr, torch.int32, "row_ptr")
+        p_ci = _dptr(col_idx, torch.int32, "col_idx") if nnz else ctypes.c_void_p(0)
+        p_w = _dptr(w, torch.float32, "w") if n else ctypes.c_void_p(0)
+        fl = GN_INPUT_DEVICE
+    else:
+        rp, p_rp = _hptr(row_ptr, np.int32)
+        ci, p_ci = _hptr(col_idx, np.int32)
+        ww, p_w = _hptr(w, np.float32)
+        keep += [rp, ci, ww]
+        nnz = int(ci.size)
+        fl = GN_INPUT_HOST
+    if flags is not None:
+        fl = flags
+    elif not validate:
+        fl |= GN_NO_VALIDATE
+    h = ctypes.c_void_p()
+    _check(lib().gn_graph_create(int(n), nnz, p_rp, p_ci, p_w, fl, _stream(stream), ctypes.byref(h)),
+           "gn_graph_create")
+    return h
+
+
+def gn_graph_destroy(h):
+    if h:
+        lib().gn_graph_destroy(h)
+
+
+def gn_graph_info(h) -> dict:
+    n = ctypes.c_int32()
+    nnz = ctypes.c_int64()
+    md = ctypes.c_int32()
+    bins = (ctypes.c_int32 * GN_NUM_BINS)()
+    _check(lib().gn_graph_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(md), bins), "gn_graph_info")
+    names = ["lane16", "lane32", "g8", "wave", "block", "unused5", "unused6"]
+    return {"n": n.value, "nnz": nnz.value, "max_degree": md.value,
+            "bins": {k: bins[i] for i, k in enumerate(names)}}
+
+
+def gn_step(h, gamma, x_in, x_out, stream=None):
+    import torch
+    _check(lib().gn_step(h, float(gamma), _dptr(x_in, torch.float32, "x_in"), _dptr(x_out, torch.float32, "x_out"),
+                         _stream(stream)), "gn_step")
+
+
+def make_schedule(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4, check_every=1) -> gn_schedule:
+    return gn_schedule(float(gamma0), float(gamma1), int(ramp_steps), int(max_steps), float(tau), int(check_every))
+
+
+@dataclass
+class Result:
+    status: int
+    steps: int
+    binarised: bool
+    fallback_count: int
+    relaxed_objective: float
+    set_objective: float
+    set_size: int
+    conflicts: int
+    uncovered: int
+    stab: float
+
+
+def gn_solve(h, schedule: gn_schedule, x, sel, stream=None) -> Result:
+    import torch
+    r = gn_result()
+    st = lib().gn_solve(h, ctypes.byref(schedule), _dptr(x, torch.float32, "x"), _dptr(sel, torch.uint8, "sel"),
+                        ctypes.byref(r), _stream(stream))
+    _check(st, "gn_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return Result(st, r.steps, bool(r.binarised), r.fallback_count, r.relaxed_objective, r.set_objective,
+                  r.set_size, r.conflicts, r.uncovered, float(r.stab))
+
+
+def gn_objective(h, x, stream=None) -> float:
+    import torch
+    out = ctypes.c_double()
+    _check(lib().gn_objective(h, _dptr(x, torch.float32, "x"), ctypes.byref(out), _stream(stream)), "gn_objective")
+    return out.value
+
+
+def gn_check_independent(h, sel, stream=None) -> tuple[int, int]:
+    import torch
+    c = ctypes.c_int64()
+    u = ctypes.c_int64()
+    _check(lib().gn_check_independent(h, _dptr(sel, torch.uint8, "sel"), ctypes.byref(c), ctypes.byref(u),
+                                      _stream(stream)), "gn_check_independent")
+    return c.value, u.value
+
+
+def gn_set_chunk_len(length: int):
+    _check(lib().gn_set_chunk_len(int(length)), "gn_set_chunk_len")
+
+
+class Graph:
+    """Owning wrapper of a gn_graph handle."""
+
+    def __init__(self, n, row_ptr, col_idx, w, validate=True, stream=None):
+        self.n = int(n)
+        self.handle = gn_graph_create(n, row_ptr, col_idx, w, validate=validate, stream=stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            gn_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return gn_graph_info(self.handle)
+
+    def step(self, gamma, x_in, x_out, stream=None):
+        gn_step(self.handle, gamma, x_in, x_out, stream)
+
+    def solve(self, x, sel, stream=None, **sched) -> Result:
+        return gn_solve(self.handle, make_schedule(**sched), x, sel, stream)
+
+    def objective(self, x, stream=None) -> float:
+        return gn_objective(self.handle, x, stream)
+
+    def check(self, sel, stream=None):
+        return gn_check_independent(self.handle, sel, stream)
+
+
+def _result(r: gn_result, st: int) -> Result:
+    return Result(st, r.steps, bool(r.binarised), r.fallback_count, r.relaxed_objective, r.set_objective,
+                  r.set_size, r.conflicts, r.uncovered, float(r.stab))
+
+
+def gn_batch_create(n, nnz, row_ptr_cat, col_idx_cat, w_cat, validate=True, stream=None):
+    """Batch handle from per-graph sizes (host) and concatenated local CSR + weights
+    (host numpy arrays or CUDA tensors)."""
+    import torch
+    ns, p_n = _hptr(n, np.int32)
+    nz, p_nz = _hptr(nnz, np.int64)
+    keep = [ns, nz]
+    if isinstance(row_ptr_cat, torch.Tensor) and row_ptr_cat.is_cuda:
+        p_rp = _dptr(row_ptr_cat, torch.int32, "row_ptr_cat")
+        p_ci = _dptr(col_idx_cat, torch.int32, "col_idx_cat") if col_idx_cat.numel() else ctypes.c_void_p(0)
+        p_w = _dptr(w_cat, torch.float32, "w_cat") if w_cat.numel() else ctypes.c_void_p(0)
+        fl = GN_INPUT_DEVICE
+    else:
+        rp, p_rp = _hptr(row_ptr_cat, np.int32)
+        ci, p_ci = _hptr(col_idx_cat, np.int32)
+        ww, p_w = _hptr(w_cat, np.float32)
+        keep += [rp, ci, ww]
+        fl = GN_INPUT_HOST
+    if not validate:
+        fl |= GN_NO_VALIDATE
+    h = ctypes.c_void_p()
+    _check(lib().gn_batch_create(len(ns), p_n, p_nz, p_rp, p_ci, p_w, fl, _stream(stream), ctypes.byref(h)),
+           "gn_batch_create")
+    return h
+
+
+def gn_batch_destroy(h):
+    if h:
+        lib().gn_batch_destroy(h)
+
+
+def gn_batch_solve(h, count, schedule: gn_schedule, x_cat, sel_cat, tuning: gn_tuning | None = None,
+                   stream=None) -> tuple[int, list[Result]]:
+    import torch
+    res = (gn_result * count)()
+    st = lib().gn_batch_solve(h, ctypes.byref(schedule), ctypes.byref(tuning) if tuning is not None else None,
+                              _dptr(x_cat, torch.float32, "x_cat"), _dptr(sel_cat, torch.uint8, "sel_cat"), res,
+                              _stream(stream))
+    _check(st, "gn_batch_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return st, [_result(res[g], st) for g in range(count)]
+
+
+def gn_batch_autotune(h, schedule: gn_schedule, stream=None) -> gn_tuning:
+    t = gn_tuning()
+    _check(lib().gn_batch_autotune(h, ctypes.byref(schedule), ctypes.byref(t), _stream(stream)), "gn_batch_autotune")
+    return t
+
+
+def gn_batch_graph(h):
+    g = lib().gn_batch_graph(h)
+    if not g:
+        raise GNError(GN_E_HIP, "gn_batch_graph")
+    return ctypes.c_void_p(g)
+
+
+class Batch:
+    """Owning wrapper of a gn_batch handle."""
+
+    def __init__(self, n, nnz, row_ptr_cat, col_idx_cat, w_cat, validate=True, stream=None):
+        self.n = np.asarray(n, dtype=np.int64)
+        self.count = len(self.n)
+        self.total_n = int(self.n.sum())
+        self.handle = gn_batch_create(n, nnz, row_ptr_cat, col_idx_cat, w_cat, validate, stream)
+
+    @classmethod
+    def from_graphs(cls, graphs, weights, **kw):
+        ns = [g.n for g in graphs]
+        nnz = [g.nnz for g in graphs]
+        rp = np.concatenate([g.row_ptr for g in graphs]).astype(np.int32)
+        ci = np.concatenate([g.col_idx for g in graphs]).astype(np.int32)
+        w = np.concatenate([np.asarray(x, np.float32) for x in weights])
+        return cls(ns, nnz, rp, ci, w, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            gn_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, x_cat, sel_cat, tuning=None, stream=None, **sched):
+        return gn_batch_solve(self.handle, self.count, make_schedule(**sched), x_cat, sel_cat, tuning, stream)
+
+    def autotune(self, stream=None, **sched) -> gn_tuning:
+        return gn_batch_autotune(self.handle, make_schedule(**sched), stream)
+
+    def graph_handle(self):
+        return gn_batch_graph(self.handle)

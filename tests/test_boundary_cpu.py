@@ -1,0 +1,119 @@
+"""Host-side checks of the C-ABI library that need no GPU: the library loads,
+exports every entry point declared in include/*.h, and rejects malformed input
+on the host (before any device work) with the documented status codes."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_05330_amd import libgn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(gn_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    syms = _declared_symbols()
+    for s in ["gn_graph_create", "gn_graph_destroy", "gn_step", "gn_solve", "gn_objective",
+              "gn_check_independent", "gn_status_str"]:
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = libgn.lib()
+    missing = [s for s in _declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for code in range(-9, 2):
+        assert libgn.gn_status_str(code).startswith("GN_")
+
+
+def _create(n, rp, ci, w, flags=libgn.GN_INPUT_HOST):
+    L = libgn.lib()
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    w = np.ascontiguousarray(w, np.float32)
+    h = ctypes.c_void_p(123)
+    st = L.gn_graph_create(n, int(ci.size), rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                           w.ctypes.data if w.size else None, flags, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("asym", libgn.GN_E_ASYMMETRIC),
+    ("self", libgn.GN_E_SELF_LOOP),
+    ("dup", libgn.GN_E_CSR),
+    ("range", libgn.GN_E_CSR),
+    ("monotone", libgn.GN_E_CSR),
+    ("rowptr_end", libgn.GN_E_CSR),
+    ("w_zero", libgn.GN_E_WEIGHT),
+    ("w_nan", libgn.GN_E_WEIGHT),
+    ("w_inf", libgn.GN_E_WEIGHT),
+    ("n_neg", libgn.GN_E_ARG),
+])
+def test_create_rejects_malformed_input_on_host(case, expect):
+    w = np.ones(3, np.float32)
+    rp, ci, n = [0, 1, 2, 2], [1, 0], 3
+    if case == "asym":
+        rp, ci = [0, 1, 1, 1], [1]
+    elif case == "self":
+        rp, ci = [0, 1, 2, 2], [0, 1]
+    elif case == "dup":
+        rp, ci = [0, 2, 3, 3], [1, 1, 0]
+    elif case == "range":
+        rp, ci = [0, 1, 2, 2], [7, 0]
+    elif case == "monotone":
+        rp, ci = [0, 2, 1, 2], [1, 0]
+    elif case == "rowptr_end":
+        rp, ci = [0, 1, 2, 3], [1, 0]
+    elif case == "w_zero":
+        w = np.array([1, 0, 1], np.float32)
+    elif case == "w_nan":
+        w = np.array([1, np.nan, 1], np.float32)
+    elif case == "w_inf":
+        w = np.array([1, np.inf, 1], np.float32)
+    elif case == "n_neg":
+        n = -1
+    st, h = _create(n, rp, ci, w)
+    assert st == expect
+    assert h.value is None  # *out is cleared on error
+
+
+def test_no_validate_still_checks_bounds():
+    # an out-of-range column must never reach a kernel, even when validation is skipped
+    st, _ = _create(3, [0, 1, 2, 2], [9, 0], np.ones(3), flags=libgn.GN_INPUT_HOST | libgn.GN_NO_VALIDATE)
+    assert st == libgn.GN_E_CSR
+
+
+def test_null_arguments():
+    L = libgn.lib()
+    assert L.gn_graph_create(3, 0, None, None, None, 0, None, None) == libgn.GN_E_ARG
+    assert L.gn_step(None, ctypes.c_float(1.0), None, None, None) == libgn.GN_E_ARG
+    assert L.gn_solve(None, None, None, None, None, None) == libgn.GN_E_ARG
+    assert L.gn_objective(None, None, None, None) == libgn.GN_E_ARG
+    assert L.gn_check_independent(None, None, None, None, None) == libgn.GN_E_ARG
+    L.gn_graph_destroy(None)  # allowed
+
+
+def test_product_path_does_not_import_oracle():
+    """The package must never reach the oracle (test infrastructure only)."""
+    pkg = os.path.join(ROOT, "paper_2605_05330_amd")
+    for path in glob.glob(os.path.join(pkg, "**", "*.py"), recursive=True):
+        src = open(path).read()
+        assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), path
+    for path in glob.glob(os.path.join(pkg, "csrc", "*")):
+        assert "gn_oracle" not in open(path).read(), path

@@ -1,0 +1,167 @@
+"""Batched solve (many graphs, one persistent launch) through the C-ABI.
+
+Every graph's result must be bit-identical to gn_solve on that graph alone:
+components do not interact (Section 2, property iii) and both paths use the same
+canonical neighbour-sum order.  Against the oracle the bar is the single-graph
+one: same rounded set, exact independence and maximality, equal set objective,
+steps within 2."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_05330_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+SCHED = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4, check_every=1)
+
+
+def _lg():
+    from paper_2605_05330_amd import libgn
+    return libgn
+
+
+def _mixed_graphs():
+    gs, ws = [], []
+    for k in range(12):
+        n = [50, 51, 97, 130, 257, 400, 640, 800, 1200, 1500, 2047, 3000][k]
+        g = I.erdos_renyi(n, 6 / (n - 1), 100 + k) if k % 2 else I.unit_disk(n, 10, 100 + k)
+        gs.append(g)
+        ws.append(I.weights_uniform01(n, 100 + k))
+    # heavy rows (wavefront path inside the workgroup), an edgeless graph, a single vertex
+    h = I.hub_graph(900, [40, 90, 300], 4.0, 7)
+    gs.append(h)
+    ws.append(I.weights_uniform01(h.n, 7))
+    gs.append(I.csr_from_edges(5, np.zeros(0), np.zeros(0)))
+    ws.append(np.linspace(0.2, 1.0, 5).astype(F32))
+    gs.append(I.csr_from_edges(1, np.zeros(0), np.zeros(0)))
+    ws.append(np.ones(1, F32))
+    return gs, ws
+
+
+def _run_batch(B, gs, tuning=None, **sched):
+    import torch
+    tot = sum(g.n for g in gs)
+    x = torch.full((tot,), 0.5, device="cuda")
+    sel = torch.zeros(tot, dtype=torch.uint8, device="cuda")
+    st, res = B.solve(x, sel, tuning=tuning, **(sched or SCHED))
+    return st, res, x.cpu().numpy(), sel.cpu().numpy()
+
+
+def test_batch_bit_identical_to_single(gpu):
+    import torch
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    B = lg.Batch.from_graphs(gs, ws)
+    st, res, xb, sb = _run_batch(B, gs)
+    off = 0
+    for g, w, r in zip(gs, ws, res):
+        G = lg.Graph(g.n, g.row_ptr, g.col_idx, w)
+        x = torch.full((g.n,), 0.5, device="cuda")
+        sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        r1 = G.solve(x, sel, **SCHED)
+        assert r.steps == r1.steps and r.binarised == r1.binarised
+        assert np.array_equal(xb[off:off + g.n].view(np.uint32), x.cpu().numpy().view(np.uint32))
+        assert np.array_equal(sb[off:off + g.n], sel.cpu().numpy())
+        assert r.set_objective == pytest.approx(r1.set_objective, rel=1e-14)
+        assert r.relaxed_objective == pytest.approx(r1.relaxed_objective, rel=1e-12)
+        assert (r.conflicts, r.uncovered, r.set_size, r.fallback_count) == \
+               (r1.conflicts, r1.uncovered, r1.set_size, r1.fallback_count)
+        off += g.n
+
+
+def test_batch_vs_oracle(gpu):
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    B = lg.Batch.from_graphs(gs, ws)
+    st, res, xb, sb = _run_batch(B, gs)
+    off = 0
+    for g, w, r in zip(gs, ws, res):
+        ref = O.solve(g.n, g.row_ptr, g.col_idx, w.astype(np.float64), np.full(g.n, 0.5),
+                      gamma0=float(F32(0.9)), gamma1=1.5, ramp_steps=1000, max_steps=2000,
+                      tau=float(F32(1e-4)))
+        assert r.binarised and ref.binarised
+        assert r.conflicts == 0 and r.uncovered == 0
+        assert abs(r.steps - ref.steps) <= 2, (g.n, r.steps, ref.steps)
+        assert np.array_equal(sb[off:off + g.n].astype(bool), ref.sel)
+        assert r.set_objective == pytest.approx(ref.set_objective, rel=1e-12)
+        off += g.n
+
+
+def test_batch_results_independent_of_tuning(gpu):
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    B = lg.Batch.from_graphs(gs, ws)
+    base = _run_batch(B, gs)
+    t = B.autotune(**SCHED)
+    assert t.block_threads in (128, 256, 512) and 1 <= t.blocks_per_cu <= 4
+    shapes = [t, lg.gn_tuning(128, 1, 3000, 0), lg.gn_tuning(512, 2, 3000, 0),
+              lg.gn_tuning(256, 4, 100, 0),   # most graphs take the global-memory state path
+              lg.gn_tuning(256, 2, 0, 0)]     # every graph on the global-memory path
+    for tu in shapes:
+        st, res, xb, sb = _run_batch(B, gs, tuning=tu)
+        assert np.array_equal(xb.view(np.uint32), base[2].view(np.uint32))
+        assert np.array_equal(sb, base[3])
+        assert [r.steps for r in res] == [r.steps for r in base[1]]
+
+
+def test_batch_rejects_bad_x0(gpu):
+    import torch
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    B = lg.Batch.from_graphs(gs, ws)
+    tot = sum(g.n for g in gs)
+    x = torch.full((tot,), 0.5, device="cuda")
+    x[100:] = 0.0   # graph 1 (n = 51 starting at 50) has zero closed neighbourhoods
+    sel = torch.full((tot,), 7, dtype=torch.uint8, device="cuda")
+    before = x.clone()
+    with pytest.raises(lg.GNError) as e:
+        B.solve(x, sel, **SCHED)
+    assert e.value.status == lg.GN_E_NOT_NORMALIZABLE
+    assert torch.equal(x, before) and bool((sel == 7).all())
+    x = torch.full((tot,), 0.5, device="cuda")
+    x[3] = float("nan")
+    with pytest.raises(lg.GNError) as e:
+        B.solve(x, sel, **SCHED)
+    assert e.value.status == lg.GN_E_ARG
+
+
+def test_batch_union_graph_matches(gpu):
+    """The block-diagonal union graph solves to the same per-graph sets when every
+    graph is run for the same fixed number of steps (tau = 0)."""
+    import torch
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    B = lg.Batch.from_graphs(gs, ws)
+    fixed = dict(SCHED, max_steps=300, tau=0.0)
+    st, res, xb, sb = _run_batch(B, gs, **fixed)
+    h = B.graph_handle()
+    tot = sum(g.n for g in gs)
+    x = torch.full((tot,), 0.5, device="cuda")
+    sel = torch.zeros(tot, dtype=torch.uint8, device="cuda")
+    r = lg.gn_solve(h, lg.make_schedule(**fixed), x, sel)
+    assert r.steps == 300
+    assert np.array_equal(x.cpu().numpy().view(np.uint32), xb.view(np.uint32))
+
+
+def test_batch_full_4096(gpu):
+    """4,096 graphs, n log-uniform in [50, 5000], half ER (degree 6), half unit-disk
+    (degree 10): every graph binarises to an independent, maximal set; 24 sampled
+    graphs match the oracle's set."""
+    import torch
+    lg = _lg()
+    gs, ws = I.batch_workload(4096, seed=0)
+    B = lg.Batch.from_graphs(gs, ws)
+    B.autotune(**SCHED)
+    st, res, xb, sb = _run_batch(B, gs)
+    assert st == lg.GN_OK
+    assert all(r.binarised and r.conflicts == 0 and r.uncovered == 0 for r in res)
+    offs = np.concatenate([[0], np.cumsum([g.n for g in gs])])
+    rng = I.rng_for(0, 99)
+    for gi in rng.choice(4096, 24, replace=False):
+        g, w = gs[gi], ws[gi]
+        ref = O.solve(g.n, g.row_ptr, g.col_idx, w.astype(np.float64), np.full(g.n, 0.5),
+                      gamma0=float(F32(0.9)), gamma1=1.5, ramp_steps=1000, max_steps=2000,
+                      tau=float(F32(1e-4)))
+        assert np.array_equal(sb[offs[gi]:offs[gi + 1]].astype(bool), ref.sel), gi
+        assert abs(res[gi].steps - ref.steps) <= 2

@@ -1,0 +1,318 @@
+"""Parity of the HIP path (through the C-ABI) with the fp64 oracle.
+
+Tolerances (fp32 kernel vs fp64 oracle):
+  one step  |x_gpu - x_ref| <= 1e-5 |x_ref| + 1e-7, both from the same fp32 input.
+            The neighbour sum is fp32 in the canonical 64-lane order: a lane adds at
+            most ceil(deg/64) positive terms sequentially and the butterfly adds 6
+            levels, so its relative error is below (ceil(deg/64) + 6) 2^-24 < 1e-5
+            for every degree used here (<= 9001), plus a few roundings in the
+            epilogue.
+  solve     identical rounded sets on seeds whose trajectory has no near-tie, set
+            objective equal to 1e-12 relative (same set, fp64 sums in different
+            orders), steps within 2 of the oracle (the stopping test is a float
+            decision on trajectories computed in different precisions),
+            independence and maximality exact.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_05330_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+def _lib():
+    from paper_2605_05330_amd import libgn
+    return libgn
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _graph(g, w):
+    return _lib().Graph(g.n, g.row_ptr, g.col_idx, np.asarray(w, F32))
+
+
+def _step_parity(g, w, gamma, x):
+    import torch
+    G = _graph(g, w)
+    x32 = np.asarray(x, F32)
+    xd = dev(x32)
+    out = torch.empty_like(xd)
+    G.step(F32(gamma), xd, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref, fb = O.step(g.n, g.row_ptr, g.col_idx, np.asarray(w, F32).astype(np.float64), float(F32(gamma)),
+                     x32.astype(np.float64))
+    err = np.abs(got - ref)
+    bad = err > 1e-5 * np.abs(ref) + 1e-7
+    assert not bad.any(), (np.flatnonzero(bad)[:10], got[bad][:5], ref[bad][:5])
+    return got, ref
+
+
+def _rand_state(n, seed, zeros=0.0):
+    r = I.rng_for(seed, 77)
+    x = r.random(n) * 0.98 + 0.01
+    if zeros:
+        x[r.random(n) < zeros] = 0.0
+    return x
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_step_er1000(gpu, seed):
+    g = I.erdos_renyi(1000, 8 / 999, seed)
+    w = I.weights_uniform01(1000, seed)
+    for gamma in (0.9, 1.5):
+        _step_parity(g, w, gamma, _rand_state(1000, seed, zeros=0.05))
+
+
+def test_step_all_bins_ragged(gpu):
+    """Degrees 0 .. 9001: every bin, multi-chunk LDS staging (> 4096), partial tail
+    blocks in every bin."""
+    g = I.hub_graph(12000, [10, 20, 40, 100, 300, 600, 1500, 5000, 9000], 3.0, 1)
+    w = I.weights_uniform01(g.n, 1)
+    info = _graph(g, w).info()
+    assert all(v > 0 for k, v in info["bins"].items() if not k.startswith("unused")), info
+    _step_parity(g, w, 1.3, _rand_state(g.n, 4, zeros=0.1))
+
+
+def test_step_degree_sweep(gpu):
+    """Every degree 0..130 and a few bin edges: a union of stars, one per degree."""
+    degs = list(range(0, 131)) + [511, 512, 513, 4095, 4096, 4097]
+    src, dst, off = [], [], 0
+    for d in degs:
+        src += [off] * d
+        dst += list(range(off + 1, off + 1 + d))
+        off += d + 1
+    g = I.csr_from_edges(off, np.array(src), np.array(dst))
+    w = I.weights_uniform01(g.n, 5)
+    _step_parity(g, w, 1.1, _rand_state(g.n, 5))
+
+
+def test_step_fallback_and_zero_support(gpu):
+    """Safe division: nodes with an all-zero closed neighbourhood take 1/2; zeros with
+    a positive neighbour stay 0 (support invariance)."""
+    g = I.csr_from_edges(6, np.array([0, 1, 3]), np.array([1, 2, 4]))
+    w = np.array([1, 2, 0.5, 1, 1, 3], F32)
+    got, ref = _step_parity(g, w, 1.5, np.array([0.0, 0.4, 0.7, 0.0, 0.0, 0.9]))
+    assert got[3] == 0.5 and got[4] == 0.5 and got[0] == 0.0 and got[5] == 1.0
+
+
+def test_step_full_size_ba_and_rook(gpu):
+    """Full-size one-step parity on the two at-scale workloads, all rows."""
+    g = I.barabasi_albert(200_000, 5, 0)
+    w = I.weights_uniform01(g.n, 0)
+    _step_parity(g, w, 1.2, _rand_state(g.n, 8))
+    r = I.rook(256)
+    wr, _ = I.rook_weights(256, 0)
+    _step_parity(r, wr, 1.2, _rand_state(r.n, 9))
+
+
+def test_step_scale_invariance_bit_exact(gpu):
+    """Section 2 property iv on the GPU: scaling x by 2^k gives bit-identical output."""
+    import torch
+    g = I.barabasi_albert(20_000, 4, 3)
+    w = I.weights_uniform01(g.n, 3)
+    G = _graph(g, w)
+    x = dev(np.asarray(_rand_state(g.n, 3), F32))
+    a, b = torch.empty_like(x), torch.empty_like(x)
+    G.step(1.4, x, a)
+    G.step(1.4, x * 8.0, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def _solve_both(g, w, x0, **sch):
+    import torch
+    G = _graph(g, w)
+    x = dev(np.asarray(x0, F32))
+    sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+    res = G.solve(x, sel, **sch)
+    osch = dict(sch)
+    for k in ("gamma0", "gamma1", "tau"):
+        if k in osch:
+            osch[k] = float(F32(osch[k]))
+    ref = O.solve(g.n, g.row_ptr, g.col_idx, np.asarray(w, F32).astype(np.float64),
+                  np.asarray(x0, F32).astype(np.float64), **osch)
+    return G, res, x.cpu().numpy(), sel.cpu().numpy().astype(bool), ref
+
+
+SCHED_RAMP = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4, check_every=1)
+SCHED_CONST = dict(gamma0=1.5, gamma1=1.5, ramp_steps=1, max_steps=2000, tau=1e-4, check_every=1)
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("sched", ["ramp", "const"])
+def test_solve_er1000(gpu, seed, sched):
+    """ER n=1000, average degree 8, w uniform (0,1], x0 = 1/2."""
+    g = I.erdos_renyi(1000, 8 / 999, seed)
+    w = I.weights_uniform01(1000, seed)
+    S = SCHED_RAMP if sched == "ramp" else SCHED_CONST
+    G, res, x, sel, ref = _solve_both(g, w, np.full(1000, 0.5), **S)
+    assert res.binarised and ref.binarised
+    assert res.conflicts == 0 and res.uncovered == 0
+    assert abs(res.steps - ref.steps) <= 2, (res.steps, ref.steps)
+    assert np.array_equal(sel, ref.sel)
+    assert res.set_objective == pytest.approx(ref.set_objective, rel=1e-12)
+    assert res.set_size == int(ref.sel.sum())
+    assert res.stab > 1.0 - 1e-3
+    # final state within the stopping tolerance of the oracle's
+    assert np.max(np.abs(x - ref.x)) <= 2e-4
+    # selected set equals the rounding of the returned x
+    assert np.array_equal(sel, x > 0.5)
+
+
+def test_solve_same_steps_gives_same_relaxed_objective(gpu):
+    """With the number of steps fixed (tau = 0 never passes), the relaxed objective
+    after K steps matches the oracle to 1e-6 relative."""
+    g = I.erdos_renyi(1000, 8 / 999, 11)
+    w = I.weights_uniform01(1000, 11)
+    S = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=150, tau=0.0, check_every=1)
+    G, res, x, sel, ref = _solve_both(g, w, np.full(1000, 0.5), **S)
+    assert not res.binarised and res.steps == 150 and ref.steps == 150
+    assert res.relaxed_objective == pytest.approx(ref.relaxed_objective, rel=1e-6)
+
+
+def test_solve_check_every(gpu):
+    g = I.erdos_renyi(1000, 8 / 999, 2)
+    w = I.weights_uniform01(1000, 2)
+    S = dict(SCHED_CONST, check_every=8)
+    G, res, x, sel, ref = _solve_both(g, w, np.full(1000, 0.5), **S)
+    assert res.binarised and res.steps % 8 == 0 and ref.steps % 8 == 0
+    assert abs(res.steps - ref.steps) <= 8
+    assert np.array_equal(sel, ref.sel)
+
+
+def test_solve_ba200k_matches_oracle(gpu):
+    """Barabasi-Albert n=200,000, m=5, gamma-pursuit: the at-scale plain-GN workload."""
+    g = I.barabasi_albert(200_000, 5, 0)
+    w = I.weights_uniform01(g.n, 0)
+    G, res, x, sel, ref = _solve_both(g, w, np.full(g.n, 0.5), **SCHED_RAMP)
+    assert res.binarised and ref.binarised
+    assert res.conflicts == 0 and res.uncovered == 0
+    assert abs(res.steps - ref.steps) <= 2, (res.steps, ref.steps)
+    mism = int(np.sum(sel != ref.sel))
+    assert mism == 0, mism
+    assert res.set_objective == pytest.approx(ref.set_objective, rel=1e-12)
+
+
+def test_solve_rook256_permutation(gpu):
+    """Assignment instance 256x256: the result is a permutation matrix and the set is
+    independent and maximal (properties that hold at any size)."""
+    import torch
+    r = I.rook(256)
+    w, _ = I.rook_weights(256, 0)
+    G = _graph(r, w)
+    x = torch.full((r.n,), 0.5, device="cuda")
+    sel = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+    res = G.solve(x, sel, **SCHED_RAMP)
+    assert res.binarised and res.conflicts == 0 and res.uncovered == 0
+    P = sel.cpu().numpy().reshape(256, 256).astype(int)
+    assert (P.sum(0) == 1).all() and (P.sum(1) == 1).all()
+    assert res.set_objective == pytest.approx(float(w.astype(np.float64)[P.reshape(-1) == 1].sum()), rel=1e-12)
+
+
+def test_objective_and_check_vs_oracle(gpu):
+    import torch
+    g = I.hub_graph(5000, [100, 700, 3000], 6.0, 2)
+    w = I.weights_uniform01(g.n, 2)
+    G = _graph(g, w)
+    x = np.asarray(_rand_state(g.n, 2), F32)
+    assert G.objective(dev(x)) == pytest.approx(O.objective(w.astype(np.float64), x.astype(np.float64)),
+                                                rel=1e-12)
+    rng = I.rng_for(2, 5)
+    for p in (0.02, 0.2, 0.6):
+        s = (rng.random(g.n) < p).astype(np.uint8)
+        assert G.check(dev(s)) == O.check(g.n, g.row_ptr, g.col_idx, s)
+
+
+def test_solve_edge_cases(gpu):
+    import torch
+    lg = _lib()
+    # empty graph
+    G0 = lg.Graph(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, F32))
+    r0 = G0.solve(torch.zeros(0, device="cuda"), torch.zeros(0, dtype=torch.uint8, device="cuda"))
+    assert r0.binarised and r0.steps == 0
+    # edgeless: one step to all ones
+    g = I.csr_from_edges(5, np.zeros(0), np.zeros(0))
+    G, res, x, sel, ref = _solve_both(g, np.ones(5, F32), np.full(5, 0.3), **SCHED_CONST)
+    assert res.binarised and res.steps == ref.steps == 1 and sel.all()
+    # K_2 with equal weights from the symmetric start never binarises
+    k2 = I.csr_from_edges(2, np.array([0]), np.array([1]))
+    G, res, x, sel, ref = _solve_both(k2, np.ones(2, F32), np.full(2, 0.5),
+                                      **dict(SCHED_CONST, max_steps=300))
+    assert res.status == lg.GN_NOT_CONVERGED and not res.binarised and res.steps == 300
+    # max_steps = 0: nothing happens
+    g = I.erdos_renyi(50, 0.1, 1)
+    G, res, x, sel, ref = _solve_both(g, I.weights_uniform01(50, 1), np.full(50, 0.5),
+                                      **dict(SCHED_CONST, max_steps=0))
+    assert res.steps == 0 and not res.binarised and np.all(x == 0.5)
+
+
+def test_solve_rejects_bad_x0(gpu):
+    import torch
+    lg = _lib()
+    g = I.csr_from_edges(4, np.array([0, 2]), np.array([1, 3]))
+    G = _graph(g, np.ones(4, F32))
+    sel = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    x = dev(np.array([0.5, 0.5, 0.0, 0.0], F32))
+    with pytest.raises(lg.GNError) as e:
+        G.solve(x, sel)
+    assert e.value.status == lg.GN_E_NOT_NORMALIZABLE
+    assert torch.equal(x.cpu(), torch.tensor([0.5, 0.5, 0.0, 0.0]))  # untouched
+    x = dev(np.array([0.5, -0.1, 0.3, 0.3], F32))
+    with pytest.raises(lg.GNError) as e:
+        G.solve(x, sel)
+    assert e.value.status == lg.GN_E_ARG
+
+
+def test_step_rejects_aliasing(gpu):
+    import torch
+    lg = _lib()
+    g = I.erdos_renyi(30, 0.2, 0)
+    G = _graph(g, I.weights_uniform01(30, 0))
+    x = torch.full((30,), 0.5, device="cuda")
+    with pytest.raises(lg.GNError):
+        G.step(1.5, x, x)
+
+
+def test_device_input_graph_create(gpu):
+    """gn_graph_create from device-resident CSR + weights gives the same step."""
+    import torch
+    lg = _lib()
+    g = I.erdos_renyi(2000, 6 / 1999, 4)
+    w = I.weights_uniform01(g.n, 4)
+    Gh = _graph(g, w)
+    Gd = lg.Graph(g.n, dev(g.row_ptr), dev(g.col_idx), dev(w))
+    x = dev(np.asarray(_rand_state(g.n, 1), F32))
+    a, b = torch.empty_like(x), torch.empty_like(x)
+    Gh.step(1.2, x, a)
+    Gd.step(1.2, x, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(lg.GNError) as e:
+        lg.Graph(3, dev(np.array([0, 1, 1, 1], np.int32)), dev(np.array([1], np.int32)), dev(np.ones(3, F32)))
+    assert e.value.status == lg.GN_E_ASYMMETRIC
+
+
+def test_repeat_solve_deterministic(gpu):
+    import torch
+    g = I.barabasi_albert(50_000, 5, 9)
+    w = I.weights_uniform01(g.n, 9)
+    G = _graph(g, w)
+    outs = []
+    for _ in range(2):
+        x = torch.full((g.n,), 0.5, device="cuda")
+        sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        r = G.solve(x, sel, **SCHED_RAMP)
+        outs.append((r, x.cpu(), sel.cpu()))
+    assert outs[0][0] == outs[1][0]
+    assert torch.equal(outs[0][1], outs[1][1]) and torch.equal(outs[0][2], outs[1][2])
