@@ -203,6 +203,41 @@ gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_tuning* out,
  * (differentiable) calls and by single-graph diagnostics. */
 const gn_graph* gn_batch_graph(const gn_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Differentiable GN: T unrolled WRGN steps and their adjoint (reverse mode).
+ *
+ * The paper presents GN as a differentiable layer (abstract, Introduction,
+ * Conclusion); these calls provide its exact gradient.  For one step
+ * x' = y (/) s with y = v (.) x, s = (I + gamma A) y and an incoming gradient
+ * gbar = dL/dx', the chain rule gives t = gbar (.) y (/) s^2,
+ * dL/dy = gbar (/) s - (I + gamma A) t, dL/dx = v (.) dL/dy,
+ * dL/dv += x (.) dL/dy, and dL/dw = dL/dv (/) (2 v).  Rows that took the 1/2
+ * safe-division reset or the 2^-100 support bound pass no gradient.
+ * ------------------------------------------------------------------------- */
+
+/* Floats of checkpoint storage needed for T steps checkpointed every
+ * ckpt_every steps (ceil(T / ckpt_every) states of n floats; n when T = 0).
+ * Returns -1 on bad arguments. */
+int64_t gn_unrolled_ckpt_floats(const gn_graph* g, int32_t T, int32_t ckpt_every);
+
+/* Run T steps x^{k+1} = N_{gamma_k}(x^k) (no stopping test) from x0.
+ * w: device float[n] weights to use instead of the graph's own (for learning
+ * w), or NULL.  gammas: host float[T].  x0, xT: device float[n], user order, not
+ * aliased.  ckpt: device float[gn_unrolled_ckpt_floats(...)], written here and
+ * read by gn_unrolled_backward (layout private to the library).  x0 must be
+ * finite and >= 0.  ASYNC. */
+gn_status gn_unrolled_forward(const gn_graph* g, const float* w, const float* gammas, int32_t T,
+                              int32_t ckpt_every, const float* x0, float* xT, float* ckpt, hipStream_t stream);
+
+/* Gradient of <gxT, x^T> through the T steps of the matching forward call (same
+ * g, w, gammas, T, ckpt_every and its ckpt): gw = dL/dw through the dynamics
+ * (a direct dependence of L on w, e.g. L = w . x^T, is the caller's to add),
+ * gx0 = dL/dx0.  gxT, gw, gx0: device float[n], user order.  Segments of
+ * ckpt_every steps are recomputed from the checkpoints.  ASYNC. */
+gn_status gn_unrolled_backward(const gn_graph* g, const float* w, const float* gammas, int32_t T,
+                               int32_t ckpt_every, const float* ckpt, const float* gxT, float* gw, float* gx0,
+                               hipStream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char* gn_status_str(gn_status s);
 

@@ -1,0 +1,43 @@
+"""Differentiable GN layer: ``torch.autograd.Function`` over the library's unrolled
+forward and hand-written adjoint (gn_unrolled_forward / gn_unrolled_backward).
+
+Marshalling only: the steps and their adjoint run in HIP.  ``w`` (vertex weights)
+and ``x0`` may both require gradients; the returned ``x_T`` is the state after T
+WRGN steps with the given gamma schedule."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import libgn
+
+
+class GNUnrolled(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w, x0, graph_handle, gammas, ckpt_every):
+        gam = np.ascontiguousarray(np.asarray(gammas, dtype=np.float32))
+        w = w.detach().contiguous()
+        x0 = x0.detach().contiguous()
+        xT = torch.empty_like(x0)
+        ckpt = torch.empty(libgn.gn_unrolled_ckpt_floats(graph_handle, len(gam), ckpt_every),
+                           dtype=torch.float32, device=x0.device)
+        libgn.gn_unrolled_forward(graph_handle, w, gam, ckpt_every, x0, xT, ckpt)
+        ctx.save_for_backward(w, ckpt)
+        ctx.graph = graph_handle
+        ctx.gammas = gam
+        ctx.ckpt_every = ckpt_every
+        return xT
+
+    @staticmethod
+    def backward(ctx, gxT):
+        w, ckpt = ctx.saved_tensors
+        gxT = gxT.contiguous()
+        gw = torch.empty_like(w)
+        gx0 = torch.empty_like(gxT)
+        libgn.gn_unrolled_backward(ctx.graph, w, ctx.gammas, ctx.ckpt_every, ckpt, gxT, gw, gx0)
+        return gw, gx0, None, None, None
+
+
+def gn_unrolled(w, x0, graph_handle, gammas, ckpt_every=10):
+    """x_T after len(gammas) WRGN steps from x0 with weights w (differentiable in w, x0)."""
+    return GNUnrolled.apply(w, x0, graph_handle, gammas, ckpt_every)

@@ -157,6 +157,7 @@ extern "C" void gn_graph_destroy(gn_graph* g) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(g->device);
     (void)hipDeviceSynchronize();
+    gn_internal_free_unrolled(g);
     free_graph_buffers(g);
     delete g;
     (void)hipSetDevice(cur);

@@ -67,6 +67,7 @@ struct StepArgs {
     SolveState* st;
     int32_t* notconv;        // [max_steps+1] per-step "state failed the test" flags
     float* x_out_user;       // optional: x' in user order (single-step mode)
+    float* s_out;            // optional: closed sums s_i (internal order), for the adjoint
     const int32_t* perm;     // internal -> user vertex id
     BinLayout bins;
 };
@@ -107,6 +108,7 @@ struct gn_graph {
     BinLayout bins{};
     int32_t bin_count_rows[BIN_COUNT] = {0};
     mutable GraphWorkspace ws;   // work buffers; calls on one handle must not overlap
+    mutable void* unrolled = nullptr;  // adjoint work buffers (gn_unrolled.hip)
 };
 
 // Final statistics reduced on the device (fixed-order, deterministic).
@@ -128,3 +130,4 @@ gn_status gn_internal_final_stats(gn_graph* g, const float* y_fin, float gamma_f
 gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, FinalStats* host_out,
                                 hipStream_t s);
 int32_t gn_internal_grid_blocks(const BinLayout& b);
+void gn_internal_free_unrolled(gn_graph* g);

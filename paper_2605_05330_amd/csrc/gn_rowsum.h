@@ -39,7 +39,12 @@ __device__ __forceinline__ float bounded_ratio(float yi, float s) {
 // index inside the group.  Returns the canonical sum (valid in every thread of
 // the group) and ORs the sign bits (rounded-set membership) of the neighbours
 // into `sel` (per thread; the caller reduces it over the group).
-template <int G, int MAXD>
+// Values entering a sum: |y| for the sign-carrying state (ABS), raw values for
+// signed adjoint vectors.
+template <bool ABS>
+__device__ __forceinline__ float term(float v) { return ABS ? fabsf(v) : v; }
+
+template <int G, int MAXD, bool ABS = true>
 __device__ __forceinline__ float row_sum(const int32_t* __restrict__ cp, int d, const float* __restrict__ y, int t,
                                          unsigned& sel) {
     constexpr int NV = MAXD < 64 ? MAXD : 64;         // virtual lanes that can hold entries
@@ -63,8 +68,8 @@ __device__ __forceinline__ float row_sum(const int32_t* __restrict__ cp, int d, 
         for (int j = 0; j < NCH; ++j) {
             if (idx[m][j] >= 0) {
                 const float yv = y[idx[m][j]];
-                c[j] += fabsf(yv);
-                sel |= sign_of(yv);
+                c[j] += term<ABS>(yv);
+                if (ABS) sel |= sign_of(yv);
             }
         }
     // butterfly stages NV/2 .. G inside the thread
@@ -80,7 +85,7 @@ __device__ __forceinline__ float row_sum(const int32_t* __restrict__ cp, int d, 
 
 // One wavefront (G = 64) sums a row of any degree: each lane runs its chain in
 // batches of U independent loads.
-template <int U>
+template <int U, bool ABS = true>
 __device__ __forceinline__ float row_sum_wave(const int32_t* __restrict__ cp, int d, const float* __restrict__ y,
                                               int lane, unsigned& sel) {
     float acc = 0.0f;
@@ -94,14 +99,14 @@ __device__ __forceinline__ float row_sum_wave(const int32_t* __restrict__ cp, in
         for (int u = 0; u < U; ++u) v[u] = y[c[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            acc += fabsf(v[u]);
-            sel |= sign_of(v[u]);
+            acc += term<ABS>(v[u]);
+            if (ABS) sel |= sign_of(v[u]);
         }
     }
     for (; e < d; e += 64) {
         const float yv = y[cp[e]];
-        acc += fabsf(yv);
-        sel |= sign_of(yv);
+        acc += term<ABS>(yv);
+        if (ABS) sel |= sign_of(yv);
     }
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     return acc;
@@ -109,7 +114,7 @@ __device__ __forceinline__ float row_sum_wave(const int32_t* __restrict__ cp, in
 
 // One wavefront sums two rows of degree <= 64*U at once (all loads of both rows
 // in flight together); same canonical order as row_sum_wave.
-template <int U>
+template <int U, bool ABS = true>
 __device__ __forceinline__ void row_sum_wave2(const int32_t* __restrict__ cpa, int da, const int32_t* __restrict__ cpb,
                                               int db, const float* __restrict__ y, int lane, float& sa, float& sb,
                                               unsigned& sela, unsigned& selb) {
@@ -129,10 +134,12 @@ __device__ __forceinline__ void row_sum_wave2(const int32_t* __restrict__ cpa, i
     float a = 0.0f, b = 0.0f;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        a += fabsf(va[u]);
-        b += fabsf(vb[u]);
-        sela |= sign_of(va[u]);
-        selb |= sign_of(vb[u]);
+        a += term<ABS>(va[u]);
+        b += term<ABS>(vb[u]);
+        if (ABS) {
+            sela |= sign_of(va[u]);
+            selb |= sign_of(vb[u]);
+        }
     }
     for (int off = 32; off >= 1; off >>= 1) {
         a += __shfl_xor(a, off, 64);

@@ -26,6 +26,7 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, int i, float yraw,
     const float s = __fmaf_rn(g, sigma, yi);
     const bool fallback = !(s > 1e-9f);
     const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
+    if (a.s_out) a.s_out[i] = s;
     if (do_write) {
         if (a.y_out) {
             const float yn = vi * xn;

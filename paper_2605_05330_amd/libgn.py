@@ -79,6 +79,10 @@ def lib():
                                 ctypes.POINTER(gn_result), _vp], ctypes.c_int),
             "gn_batch_autotune": ([_vp, ctypes.POINTER(gn_schedule), ctypes.POINTER(gn_tuning), _vp], ctypes.c_int),
             "gn_batch_graph": ([_vp], _vp),
+            "gn_unrolled_ckpt_floats": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
+            "gn_unrolled_forward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "gn_unrolled_backward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp],
+                                     ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -354,3 +358,27 @@ class Batch:
 
     def graph_handle(self):
         return gn_batch_graph(self.handle)
+
+
+def gn_unrolled_ckpt_floats(h, T, ckpt_every) -> int:
+    r = lib().gn_unrolled_ckpt_floats(h, int(T), int(ckpt_every))
+    if r < 0:
+        raise GNError(GN_E_ARG, "gn_unrolled_ckpt_floats")
+    return int(r)
+
+
+def gn_unrolled_forward(h, w, gammas, ckpt_every, x0, xT, ckpt, stream=None):
+    import torch
+    gm, p_g = _hptr(gammas, np.float32)
+    _check(lib().gn_unrolled_forward(h, _dptr(w, torch.float32, "w") if w is not None else None, p_g, len(gm),
+                                     int(ckpt_every), _dptr(x0, torch.float32, "x0"), _dptr(xT, torch.float32, "xT"),
+                                     _dptr(ckpt, torch.float32, "ckpt"), _stream(stream)), "gn_unrolled_forward")
+
+
+def gn_unrolled_backward(h, w, gammas, ckpt_every, ckpt, gxT, gw, gx0, stream=None):
+    import torch
+    gm, p_g = _hptr(gammas, np.float32)
+    _check(lib().gn_unrolled_backward(h, _dptr(w, torch.float32, "w") if w is not None else None, p_g, len(gm),
+                                      int(ckpt_every), _dptr(ckpt, torch.float32, "ckpt"),
+                                      _dptr(gxT, torch.float32, "gxT"), _dptr(gw, torch.float32, "gw"),
+                                      _dptr(gx0, torch.float32, "gx0"), _stream(stream)), "gn_unrolled_backward")
