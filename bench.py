@@ -33,6 +33,8 @@ def _args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-rook", action="store_true")
     p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-warm", action="store_true")
+    p.add_argument("--no-grad", action="store_true")
     return p.parse_args()
 
 
@@ -144,6 +146,98 @@ def bench_batch(sched, reps):
             "speedup_vs_plain": plain_ms / ms, "sample_equal_objective": f"{same}/{len(sample)}"}
 
 
+def bench_warm():
+    """Learned warm start: trained on the GPU (own kernels) on GN's sets of 96
+    unit-disk graphs, n log-uniform in [10k, 100k], mean degree 10, w ~ U(0,1];
+    evaluated on 32 held-out graphs of 100,000 vertices (seeds 9000-9031) against
+    plain GN (x0 = 1/2, 1000-step gamma ramp).  Times include network inference."""
+    import torch
+    from paper_2605_05330_amd import inputs as I
+    from paper_2605_05330_amd import libgn, warmstart as WS
+    t0 = time.perf_counter()
+    ns = I.batch_sizes_loguniform(96, 10_000, 100_000, 123)
+    graphs, labels = [], []
+    for k, n in enumerate(ns):
+        g = I.unit_disk(int(n), 10, 1000 + k)
+        G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 1000 + k))
+        graphs.append(G)
+        labels.append(WS.gn_labels(G, WS.PLAIN_SCHEDULE)[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = WS.WarmStart(seed=0)
+    WS.train(net, graphs, labels, 2000, lr=3e-3)
+    tr = WS.train(net, graphs, labels, 1000, lr=1e-3, log_every=999)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del graphs, labels
+    rows = []
+    for e in range(32):
+        g = I.unit_disk(100_000, 10, 9000 + e)
+        G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 9000 + e))
+        sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        res = {}
+        for name in ("plain", "plain400", "warm"):
+            for rep in range(2):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                if name == "warm":
+                    r, _ = WS.warm_solve(net, G, sel)
+                else:
+                    x = torch.full((g.n,), 0.5, device="cuda")
+                    r = G.solve(x, sel, **(WS.PLAIN_SCHEDULE if name == "plain" else WS.WARM_SCHEDULE))
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - ts) * 1e3
+            res[name] = (r.steps, r.set_objective, dt, r.binarised)
+        rows.append(res)
+    def agg(name):
+        st = np.mean([r[name][0] for r in rows])
+        ms = np.mean([r[name][2] for r in rows])
+        gap = np.array([(r["plain"][1] - r[name][1]) / r["plain"][1] * 100 for r in rows])
+        return {"steps_mean": float(st), "time_to_binary_ms": float(ms), "gap_pct_mean": float(gap.mean()),
+                "gap_pct_max": float(gap.max()), "all_binarised": all(r[name][3] for r in rows)}
+    out = {"train_graphs": 96, "train_adam_steps": 3000, "train_s": train_s, "final_loss": tr[-1][1],
+           "data_s": t1 - t0, "eval_graphs": 32, "n": 100_000,
+           "plain_gn": agg("plain"), "plain_gn_400_step_ramp": agg("plain400"), "warm_gated_400_step_ramp": agg("warm"),
+           "gate": WS.GATE}
+    out["speedup_vs_plain"] = out["plain_gn"]["time_to_binary_ms"] / out["warm_gated_400_step_ramp"]["time_to_binary_ms"]
+    return out
+
+
+def bench_grad():
+    """Differentiable GN: 256 unit-disk graphs n = 2000 (mean degree 10) as one
+    block-diagonal graph, w ~ U(0.5, 1.5] requiring grad, T = 50 steps at gamma 1.5,
+    L = w . x_T, checkpoint every 10 steps: forward + adjoint time."""
+    import torch
+    from paper_2605_05330_amd import inputs as I
+    from paper_2605_05330_amd import libgn
+    from paper_2605_05330_amd.autograd import gn_unrolled
+    gs = [I.unit_disk(2000, 10, 5000 + k) for k in range(256)]
+    ws = [I.weights_uniform(2000, 0.5, 1.5, 5000 + k) for k in range(256)]
+    B = libgn.Batch.from_graphs(gs, ws)
+    h = B.graph_handle()
+    w0 = torch.tensor(np.concatenate(ws), device="cuda")
+    gam = np.full(50, 1.5, np.float32)
+    def once():
+        w = w0.clone().requires_grad_(True)
+        x0 = torch.full_like(w0, 0.5)
+        xT = gn_unrolled(w, x0, h, gam, 10)
+        (w * xT).sum().backward()
+        return w.grad
+    once()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    nnz = sum(g.nnz for g in gs)
+    return {"graphs": 256, "vertices": int(w0.numel()), "edges": nnz // 2, "T": 50, "ckpt_every": 10,
+            "fwd_bwd_ms": ms, "edges_iters_per_s": (nnz // 2) * 50 * 3 / (ms / 1e3),
+            "note": "edge-iterations count forward, recompute and adjoint passes (3 per step)"}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -215,6 +309,11 @@ def main():
 
     if not a.no_batch:
         out["batched4096"] = bench_batch(sched, a.steps)
+
+    if not a.no_warm:
+        out["learned_warm_start"] = bench_warm()
+    if not a.no_grad:
+        out["differentiable"] = bench_grad()
 
     if not a.no_cpu_baseline:
         import oracle as O

@@ -238,6 +238,52 @@ gn_status gn_unrolled_backward(const gn_graph* g, const float* w, const float* g
                                int32_t ckpt_every, const float* ckpt, const float* gxT, float* gw, float* gx0,
                                hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start.
+ *
+ * The paper warm-starts GN from fractional solutions of an LP solver (Section 6,
+ * "Randomized start and warm start"); here a small message-passing network,
+ * trained on GN's own results, predicts x0 instead.  Definition (hidden width
+ * 64): features h0_i = [w_i, deg_i/10, w_i / max_{N[i]} w, S_i/(w_i + S_i)] with
+ * S_i = sum_{N(i)} w;  h1 = ReLU([h0 | mean_{N(i)} h0 | 0_8] W1 + b1);
+ * h2 = ReLU([bf16(h1) | bf16(mean_{N(i)} bf16(h1))] W2 + b2);  z = h2 . u + c;
+ * p = sigmoid(z);  x0 = clamp(p, 1e-3, 1) where |p - 1/2| > gate, else 1/2 (the
+ * neutral start of GN keeps every vertex the network is not sure about; gate = 0
+ * gives the plain clamped prediction).  Matrix products run on the matrix cores with
+ * bfloat16 operands and fp32 accumulation.  Loss: mean binary cross-entropy of
+ * sigmoid(z) against 0/1 labels.
+ *
+ * Parameters: one fp32 vector of GN_MPNN_NPARAMS floats (device), laid out as
+ * W1 [16][64] (rows 0-3 self weights, 4-7 neighbour weights, 8-15 unused),
+ * b1 [64], W2 [128][64] (rows 0-63 self, 64-127 neighbour), b2 [64], u [64], c.
+ * ------------------------------------------------------------------------- */
+#define GN_MPNN_NPARAMS 9409
+
+/* Bytes of the device cache used by gn_mpnn_forward / gn_mpnn_backward for a
+ * graph of n vertices (activations and reduction partials); -1 if n < 0. */
+int64_t gn_mpnn_cache_bytes(int32_t n);
+
+/* Forward pass on graph g (its own weights): x0 (device float[n], user order)
+ * receives the warm start, z (device float[n] or NULL) the logits.  params:
+ * device fp32[GN_MPNN_NPARAMS]; gate in [0, 1/2).  cache: device buffer of
+ * gn_mpnn_cache_bytes(n) bytes, caller-owned, keeps the activations for the
+ * backward pass.  ASYNC. */
+gn_status gn_mpnn_forward(const gn_graph* g, const float* params, float gate, float* x0, float* z, void* cache,
+                          hipStream_t stream);
+
+/* Backward pass after gn_mpnn_forward with the same g, params and cache:
+ * labels (device float[n], user order, values in [0,1]) define the loss; grad
+ * (device fp32[GN_MPNN_NPARAMS]) receives dLoss/dparams, loss (device float[1])
+ * the loss.  Sums over vertices are reduced in a fixed order.  n must be > 0.
+ * ASYNC. */
+gn_status gn_mpnn_backward(const gn_graph* g, const float* params, const float* labels, void* cache, float* grad,
+                           float* loss, hipStream_t stream);
+
+/* One Adam step (Kingma and Ba) on count parameters: m, v updated in place, t
+ * counts steps from 1.  All pointers device fp32.  ASYNC. */
+gn_status gn_adam_step(float* params, const float* grad, float* m, float* v, int32_t count, float lr, float beta1,
+                       float beta2, float eps, int32_t t, hipStream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char* gn_status_str(gn_status s);
 

@@ -13,7 +13,8 @@ Definition (n vertices, hidden width H = 64):
   mean      M(H)_i = (1/deg_i) sum_{j in N(i)} H_j   (0 for isolated vertices)
   layer 1   X1 = [h0 | M(h0) | 0_8]   (n x 16),  h1 = ReLU(bf(X1) bf(W1) + b1)
   layer 2   H1 = bf(h1),  X2 = [H1 | bf(M(H1))] (n x 128),  h2 = ReLU(X2 bf(W2) + b2)
-  head      z = h2 bf(u) + c,   x0 = clamp(sigmoid(z), 1e-3, 1)
+  head      z = h2 bf(u) + c,   p = sigmoid(z),
+            x0 = clamp(p, 1e-3, 1) where |p - 1/2| > gate, else 1/2
   loss      L = mean_i [ softplus(z_i) - l_i z_i ]   (binary cross-entropy with labels l)
 where bf(.) rounds to bfloat16 (round to nearest even), the precision the
 matrix cores consume; products accumulate in full precision.  The backward
@@ -86,7 +87,7 @@ def _mean_op(n, row_ptr, col_idx):
     return sp.diags(inv) @ A
 
 
-def forward(n, row_ptr, col_idx, w, theta, rounding=True):
+def forward(n, row_ptr, col_idx, w, theta, rounding=True, gate=0.0):
     """Returns (x0, cache) with cache holding what backward needs."""
     rnd = bf16 if rounding else (lambda a: np.asarray(a, dtype=np.float64))
     W1, b1, W2, b2, u, c = unpack(theta)
@@ -104,7 +105,7 @@ def forward(n, row_ptr, col_idx, w, theta, rounding=True):
     h2 = np.maximum(pre2, 0.0)
     z = h2 @ rnd(u) + c
     sig = 1.0 / (1.0 + np.exp(-z))
-    x0 = np.clip(sig, 1e-3, 1.0)
+    x0 = np.where(np.abs(sig - 0.5) > gate, np.clip(sig, 1e-3, 1.0), 0.5)
     cache = dict(Mop=Mop, X1r=X1r, pre1=pre1, X2=X2, pre2=pre2, h2=h2, z=z, sig=sig)
     return x0, cache
 

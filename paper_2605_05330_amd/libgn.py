@@ -79,6 +79,11 @@ def lib():
                                 ctypes.POINTER(gn_result), _vp], ctypes.c_int),
             "gn_batch_autotune": ([_vp, ctypes.POINTER(gn_schedule), ctypes.POINTER(gn_tuning), _vp], ctypes.c_int),
             "gn_batch_graph": ([_vp], _vp),
+            "gn_mpnn_cache_bytes": ([ctypes.c_int32], ctypes.c_int64),
+            "gn_mpnn_forward": ([_vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "gn_mpnn_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "gn_adam_step": ([_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_int32, _vp], ctypes.c_int),
             "gn_unrolled_ckpt_floats": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
             "gn_unrolled_forward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
             "gn_unrolled_backward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp],
@@ -382,3 +387,34 @@ def gn_unrolled_backward(h, w, gammas, ckpt_every, ckpt, gxT, gw, gx0, stream=No
                                       int(ckpt_every), _dptr(ckpt, torch.float32, "ckpt"),
                                       _dptr(gxT, torch.float32, "gxT"), _dptr(gw, torch.float32, "gw"),
                                       _dptr(gx0, torch.float32, "gx0"), _stream(stream)), "gn_unrolled_backward")
+
+
+GN_MPNN_NPARAMS = 9409
+
+
+def gn_mpnn_cache_bytes(n) -> int:
+    r = lib().gn_mpnn_cache_bytes(int(n))
+    if r < 0:
+        raise GNError(GN_E_ARG, "gn_mpnn_cache_bytes")
+    return int(r)
+
+
+def gn_mpnn_forward(h, params, x0, z, cache, gate=0.0, stream=None):
+    import torch
+    _check(lib().gn_mpnn_forward(h, _dptr(params, torch.float32, "params"), float(gate), _dptr(x0, torch.float32, "x0"),
+                                 _dptr(z, torch.float32, "z") if z is not None else None,
+                                 _dptr(cache, torch.uint8, "cache"), _stream(stream)), "gn_mpnn_forward")
+
+
+def gn_mpnn_backward(h, params, labels, cache, grad, loss, stream=None):
+    import torch
+    _check(lib().gn_mpnn_backward(h, _dptr(params, torch.float32, "params"), _dptr(labels, torch.float32, "labels"),
+                                  _dptr(cache, torch.uint8, "cache"), _dptr(grad, torch.float32, "grad"),
+                                  _dptr(loss, torch.float32, "loss"), _stream(stream)), "gn_mpnn_backward")
+
+
+def gn_adam_step(params, grad, m, v, lr, beta1, beta2, eps, t, stream=None):
+    import torch
+    _check(lib().gn_adam_step(_dptr(params, torch.float32, "params"), _dptr(grad, torch.float32, "grad"),
+                              _dptr(m, torch.float32, "m"), _dptr(v, torch.float32, "v"), params.numel(), float(lr),
+                              float(beta1), float(beta2), float(eps), int(t), _stream(stream)), "gn_adam_step")

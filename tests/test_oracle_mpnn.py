@@ -141,3 +141,13 @@ def test_adam_matches_torch():
         p.grad = torch.tensor(gr)
         opt.step()
     np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_gate_keeps_only_confident_vertices():
+    g, w = _net(50, 8)
+    th = M.init_params(8)
+    th[M.OFF_C] = 3.0
+    x_all, C = M.forward(50, g.row_ptr, g.col_idx, w, th)
+    x_g, _ = M.forward(50, g.row_ptr, g.col_idx, w, th, gate=0.45)
+    conf = np.abs(C["sig"] - 0.5) > 0.45
+    assert np.array_equal(x_g[conf], x_all[conf]) and np.all(x_g[~conf] == 0.5)
