@@ -262,6 +262,14 @@ def main():
     t_step = fixed_step_time(G, x0, 1000, 1.2)
     bstep = step_bytes(g.n, g.nnz)
     achieved = bstep / (t_step / 1e3) / 1e9
+    # calibration for counter-based traffic: one plain copy of 64 MiB (read 64 MiB,
+    # write 64 MiB), untimed; its FETCH_SIZE / WRITE_SIZE under a counter run give
+    # the scale from counter units to bytes
+    src = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     out = {
         "metric": METRIC,

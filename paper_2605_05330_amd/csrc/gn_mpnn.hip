@@ -69,6 +69,8 @@ struct Cache {
     float* w2p;           // RED_BLOCKS x 8192
     float* w1p;           // RED_BLOCKS x 1024
     float* b1p;           // blocks(dH1) x 64
+    float* red;           // kGroups x 8192: stage-1 scratch of the fixed-order sums
+    float* headsum;       // 130
 };
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -102,6 +104,8 @@ size_t cache_layout(int32_t n, char* base, Cache* c) {
     t.w2p = (float*)take((size_t)RED_BLOCKS * 8192 * 4);
     t.w1p = (float*)take((size_t)RED_BLOCKS * 1024 * 4);
     t.b1p = (float*)take(dh1_blocks(np) * 64 * 4);
+    t.red = (float*)take((size_t)64 * 8192 * 4);
+    t.headsum = (float*)take(HEAD_PART * 4);
     if (c) *c = t;
     return off;
 }
@@ -445,14 +449,35 @@ __global__ __launch_bounds__(256) void dh1_kernel(int32_t n, int64_t npad, const
     }
 }
 
-// out[e] = sum_p in[p * stride + e], p in order
-__global__ void sum_parts_kernel(int64_t parts, int64_t stride, int32_t len, const float* __restrict__ in,
-                                 float* __restrict__ out, float scale_unused) {
+// Fixed-order sum of `parts` partial vectors: out[e] = sum_p in[p * stride + e].
+// Stage 1: group g of kGroups sums its contiguous run of parts in order into
+// scratch[g][e]; stage 2 sums the groups in order.  Same order on every run.
+constexpr int kGroups = 64;
+
+__global__ void sum_parts_stage1(int64_t parts, int64_t stride, int32_t len, const float* __restrict__ in,
+                                 float* __restrict__ scratch) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (e >= len) return;
+    const int64_t per = (parts + kGroups - 1) / kGroups;
+    const int64_t p0 = g * per, p1 = min(parts, p0 + per);
+    float s = 0.0f;
+    for (int64_t p = p0; p < p1; ++p) s += in[p * stride + e];
+    scratch[(int64_t)g * len + e] = s;
+}
+
+__global__ void sum_parts_stage2(int32_t len, const float* __restrict__ scratch, float* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= len) return;
     float s = 0.0f;
-    for (int64_t p = 0; p < parts; ++p) s += in[p * stride + e];
+    for (int g = 0; g < kGroups; ++g) s += scratch[(int64_t)g * len + e];
     out[e] = s;
+}
+
+void sum_parts(int64_t parts, int64_t stride, int32_t len, const float* in, float* out, float* scratch, hipStream_t s) {
+    const unsigned bx = (unsigned)((len + 255) / 256);
+    hipLaunchKernelGGL(sum_parts_stage1, dim3(bx, kGroups), dim3(256), 0, s, parts, stride, len, in, scratch);
+    hipLaunchKernelGGL(sum_parts_stage2, dim3(bx), dim3(256), 0, s, len, (const float*)scratch, out);
 }
 
 __global__ void assemble_grad_kernel(const float* __restrict__ head, float* __restrict__ grad, float* __restrict__ loss) {
@@ -520,23 +545,19 @@ extern "C" gn_status gn_mpnn_backward(const gn_graph* g, const float* params, co
     const int64_t np = npad_of(n), tiles = np / 16;
     hipLaunchKernelGGL(head_back_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, n, tiles, labels, g->perm,
                        c);
-    // du, db2, dc, loss: sum of tile partials in tile order (into the W1 partial area as scratch)
-    float* headsum = c.w1p;
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, s, tiles, (int64_t)HEAD_PART, HEAD_PART, c.headp,
-                       headsum, 0.0f);
-    hipLaunchKernelGGL(assemble_grad_kernel, dim3(1), dim3(64), 0, s, headsum, grad, loss);
+    // du, db2, dc, loss: fixed-order sum of the tile partials
+    sum_parts(tiles, (int64_t)HEAD_PART, HEAD_PART, c.headp, c.headsum, c.red, s);
+    hipLaunchKernelGGL(assemble_grad_kernel, dim3(1), dim3(64), 0, s, (const float*)c.headsum, grad, loss);
     // dW2 = X2^T DP2
     hipLaunchKernelGGL(wgrad_kernel<8>, dim3(RED_BLOCKS), dim3(256), 0, s, tiles, c.X2, 128, c.DP2, c.w2p);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(8192 / 256), dim3(256), 0, s, (int64_t)RED_BLOCKS, (int64_t)8192, 8192,
-                       c.w2p, grad + OFF_W2, 0.0f);
+    sum_parts((int64_t)RED_BLOCKS, (int64_t)8192, 8192, c.w2p, grad + OFF_W2, c.red, s);
     // dX2, dpre1 (+ db1), dW1
     hipLaunchKernelGGL(dx2_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, tiles, c);
     const int64_t nb1 = dh1_blocks(np);
     hipLaunchKernelGGL(dh1_kernel, dim3((unsigned)nb1), dim3(256), 0, s, n, np, g->row_ptr, g->col, c);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, s, nb1, (int64_t)64, 64, c.b1p, grad + OFF_B1, 0.0f);
+    sum_parts(nb1, (int64_t)64, 64, c.b1p, grad + OFF_B1, c.red, s);
     hipLaunchKernelGGL(wgrad_kernel<1>, dim3(RED_BLOCKS), dim3(256), 0, s, tiles, c.X1, 16, c.DP1, c.w1p);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1024 / 256), dim3(256), 0, s, (int64_t)RED_BLOCKS, (int64_t)1024, 1024,
-                       c.w1p, grad + OFF_W1, 0.0f);
+    sum_parts((int64_t)RED_BLOCKS, (int64_t)1024, 1024, c.w1p, grad + OFF_W1, c.red, s);
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;
 }

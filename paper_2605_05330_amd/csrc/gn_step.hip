@@ -68,6 +68,43 @@ __device__ __forceinline__ bool group_rows(const StepArgs& a, int rb, int re, in
     return false;
 }
 
+// Thread-per-row bin with coalesced column loads: each wavefront copies the
+// contiguous column segment of its 64 rows (at most 64 * MAXD entries) into LDS
+// with unit-stride loads, then every thread reads its own row from LDS.
+template <int MAXD>
+__device__ __forceinline__ bool lane_rows_staged(const StepArgs& a, int rb, int re, int lb, float g, bool do_test,
+                                                 bool do_write, float tau, int& fb, int32_t* seg) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int w0 = rb + lb * kBlock + wave * 64;    // first row of this wavefront
+    const int i = w0 + lane;
+    const bool valid = i < re;
+    const float* __restrict__ y = a.y_in;
+    int32_t* wseg = seg + wave * 64 * MAXD;
+    int start = 0, d = 0, base = 0;
+    float yraw = 0.0f, vi = 1.0f;
+    if (w0 < re) {
+        const int wl = min(w0 + 64, re);
+        base = gnk::ld_stream(a.row_ptr + w0);
+        const int total = gnk::ld_stream(a.row_ptr + wl) - base;
+        if (valid) {
+            start = gnk::ld_stream(a.row_ptr + i) - base;
+            d = gnk::ld_stream(a.row_ptr + i + 1) - base - start;
+            yraw = y[i];
+            vi = gnk::ld_stream(a.v + i);
+        }
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            const int p = lane + 64 * k;
+            if (p < total) wseg[p] = a.col[base + p];
+        }
+    }
+    __syncthreads();
+    unsigned sel = 0u;
+    const float sigma = gnk::row_sum<1, MAXD>(wseg + start, d, y, 0, sel);
+    if (valid) return row_update(a, i, yraw, vi, sigma, sel != 0u, g, do_test, do_write, tau, fb);
+    return false;
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
@@ -176,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
     } else if (b == BIN_LANE32) {
         viol = group_rows<2, 32>(a, rb, re, lb, g, do_test, do_write, tau, fb);
     } else {
-        viol = group_rows<1, 16>(a, rb, re, lb, g, do_test, do_write, tau, fb);
+        viol = lane_rows_staged<16>(a, rb, re, lb, g, do_test, do_write, tau, fb, reinterpret_cast<int32_t*>(stage));
     }
 
     if (a.solve) {
