@@ -23,6 +23,8 @@ import numpy as np
 
 METRIC = "edges·iters/s + time-to-binary at equal MWIS objective, learned/batched vs plain GN"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "wrgn_step_ba200k_traffic.txt")
 
 
 def _args():
@@ -246,7 +248,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_2605_05330_amd import inputs as I
-    from paper_2605_05330_amd import libgn
+    from paper_2605_05330_amd import libgn, profsum
 
     dev = torch.device("cuda:0")
     sched = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4, check_every=1)
@@ -270,6 +272,11 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter runs of
+    # this workload (copy-calibrated); None once the step kernel's sources changed
+    tr = profsum.read_traffic(TRAFFIC_SUMMARY)
+    traffic = tr["traffic_bytes"] if tr is not None else None
 
     out = {
         "metric": METRIC,
@@ -295,7 +302,7 @@ def main():
         "conflicts": res.conflicts,
         "uncovered": res.uncovered,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "wrgn_step_kernel", "avg_launch_us": t_step * 1e3,
                      "bytes_per_launch": bstep},
     }
