@@ -143,6 +143,7 @@ static gn_status dev_alloc(T** p, size_t count) {
 static void free_graph_buffers(gn_graph* g) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(g->row_ptr); f(g->col); f(g->v); f(g->w_int); f(g->w_user); f(g->perm); f(g->iperm);
+    f(g->sl_col); f(g->sl_off);
     GraphWorkspace& ws = g->ws;
     for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
     ws.chunks.clear();
@@ -240,13 +241,27 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
     BinLayout bl{};
     bl.row_begin[0] = 0;
     bl.blk_begin[0] = 0;
+    bl.slice_begin[0] = 0;
     for (int b = 0; b < BIN_COUNT; ++b) {
         g->bin_count_rows[b] = counts[b];
         bl.row_begin[b + 1] = bl.row_begin[b] + counts[b];
         int rpb = bin_rows_per_block(b);
         bl.blk_begin[b + 1] = bl.blk_begin[b] + (counts[b] + rpb - 1) / rpb;
+        const int G = bin_group(b);
+        bl.slice_begin[b + 1] = bl.slice_begin[b] + (G ? (counts[b] + 64 / G - 1) / (64 / G) : 0);
     }
     g->bins = bl;
+
+    // inside the sliced bins: decreasing degree within windows (less padding)
+    for (int b = 0; b < BIN_COUNT; ++b) {
+        if (!bin_group(b)) continue;
+        for (int32_t w0 = bl.row_begin[b]; w0 < bl.row_begin[b + 1]; w0 += kSortWindow) {
+            const int32_t w1 = std::min(bl.row_begin[b + 1], w0 + kSortWindow);
+            std::stable_sort(perm.begin() + w0, perm.begin() + w1,
+                             [&](int32_t a, int32_t c) { return deg[a] > deg[c]; });
+        }
+    }
+    iperm = inverse(perm);
 
     std::vector<int32_t> rp_int((size_t)n + 1), col_int((size_t)std::max<int64_t>(nnz, 1));
     std::vector<float> v_int((size_t)std::max(n, 1)), w_int((size_t)std::max(n, 1));
@@ -260,8 +275,53 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
         v_int[r] = (float)std::sqrt((double)wh[i]);
     }
 
+    // sliced columns: slice s of a group bin covers 64/G rows; line q of the slice
+    // holds, in lane G*r + t, entry t + G*q of row r (or -1)
+    const int32_t nslices = bl.slice_begin[BIN_COUNT];
+    std::vector<int32_t> sl_off((size_t)nslices + 1, 0);
+    for (int b = 0; b < BIN_COUNT; ++b) {
+        const int G = bin_group(b);
+        if (!G) continue;
+        const int RS = 64 / G;
+        for (int32_t s = bl.slice_begin[b]; s < bl.slice_begin[b + 1]; ++s) {
+            const int32_t r0 = bl.row_begin[b] + (s - bl.slice_begin[b]) * RS;
+            const int32_t r1 = std::min(bl.row_begin[b + 1], r0 + RS);
+            int32_t width = 0;
+            for (int32_t r = r0; r < r1; ++r) width = std::max(width, (rp_int[r + 1] - rp_int[r] + G - 1) / G);
+            sl_off[(size_t)s + 1] = width;
+        }
+    }
+    int64_t lines = 0;
+    for (int32_t s = 0; s < nslices; ++s) {
+        lines += sl_off[(size_t)s + 1];
+        if (lines > INT32_MAX / 64) {
+            delete g;
+            return GN_E_ARG;
+        }
+        sl_off[(size_t)s + 1] = (int32_t)lines;
+    }
+    std::vector<int32_t> sl_col((size_t)std::max<int64_t>(lines * 64, 1), -1);
+    for (int b = 0; b < BIN_COUNT; ++b) {
+        const int G = bin_group(b);
+        if (!G) continue;
+        const int RS = 64 / G;
+        for (int32_t s = bl.slice_begin[b]; s < bl.slice_begin[b + 1]; ++s) {
+            const int32_t r0 = bl.row_begin[b] + (s - bl.slice_begin[b]) * RS;
+            const int32_t r1 = std::min(bl.row_begin[b + 1], r0 + RS);
+            int32_t* base = sl_col.data() + (size_t)sl_off[s] * 64;
+            for (int32_t r = r0; r < r1; ++r) {
+                const int32_t d = rp_int[r + 1] - rp_int[r];
+                for (int32_t p = 0; p < d; ++p) {
+                    const int32_t q = p / G, lane = (r - r0) * G + p % G;
+                    base[(size_t)q * 64 + lane] = col_int[(size_t)rp_int[r] + p];
+                }
+            }
+        }
+    }
+
     st = GN_OK;
-    if ((st = dev_alloc(&g->row_ptr, (size_t)n + 1)) || (st = dev_alloc(&g->col, (size_t)nnz)) ||
+    if ((st = dev_alloc(&g->sl_col, sl_col.size())) || (st = dev_alloc(&g->sl_off, sl_off.size())) ||
+        (st = dev_alloc(&g->row_ptr, (size_t)n + 1)) || (st = dev_alloc(&g->col, (size_t)nnz)) ||
         (st = dev_alloc(&g->v, (size_t)n)) || (st = dev_alloc(&g->w_int, (size_t)n)) ||
         (st = dev_alloc(&g->w_user, (size_t)n)) || (st = dev_alloc(&g->perm, (size_t)n)) ||
         (st = dev_alloc(&g->iperm, (size_t)n))) {
@@ -280,6 +340,8 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
     up(g->w_user, wh.data(), sizeof(float) * (size_t)n);
     up(g->perm, perm.data(), sizeof(int32_t) * (size_t)n);
     up(g->iperm, iperm.data(), sizeof(int32_t) * (size_t)n);
+    up(g->sl_col, sl_col.data(), sizeof(int32_t) * sl_col.size());
+    up(g->sl_off, sl_off.data(), sizeof(int32_t) * sl_off.size());
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         free_graph_buffers(g);

@@ -83,6 +83,56 @@ __device__ __forceinline__ float row_sum(const int32_t* __restrict__ cp, int d, 
     return s;
 }
 
+// Same sum over the sliced layout, in two parts so that callers can issue the
+// column loads early.  `cp` points at this lane's word of the slice's first line;
+// `width` lines follow at a stride of 64 words, and -1 marks positions past the
+// row's end.  Line q holds entry t + G*q of the row, so the chain j of block m
+// (entry t + G*j + 64*m) sits in line j + m*NCH.
+template <int G, int MAXD>
+struct SlicedIdx {
+    static constexpr int NV = MAXD < 64 ? MAXD : 64;
+    static constexpr int NCH = NV / G;
+    static constexpr int PER = (MAXD + 63) / 64;
+    static_assert(NCH >= 1 && (NV % G) == 0, "bad group shape");
+    static_assert(PER == 1 || G * NCH == 64, "blocks of 64 entries must fill whole lines");
+    int idx[PER][NCH];
+
+    __device__ __forceinline__ void load(const int32_t* __restrict__ cp, int width) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m)
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int q = j + m * NCH;
+                idx[m][j] = q < width ? ld_stream(cp + 64 * q) : -1;
+            }
+    }
+
+    template <bool ABS>
+    __device__ __forceinline__ float sum(const float* __restrict__ y, unsigned& sel) const {
+        float c[NCH];
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) c[j] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < PER; ++m)
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                if (idx[m][j] >= 0) {
+                    const float yv = y[idx[m][j]];
+                    c[j] += term<ABS>(yv);
+                    if (ABS) sel |= sign_of(yv);
+                }
+            }
+#pragma unroll
+        for (int off = NV / 2; off >= G; off >>= 1)
+#pragma unroll
+            for (int j = 0; j < off / G; ++j) c[j] += c[j + off / G];
+        float s = c[0];
+#pragma unroll
+        for (int off = G / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        return s;
+    }
+};
+
 // One wavefront (G = 64) sums a row of any degree: each lane runs its chain in
 // batches of U independent loads.
 template <int U, bool ABS = true>

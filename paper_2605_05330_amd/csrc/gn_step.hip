@@ -19,15 +19,60 @@ using gnk::sign_of;
 
 namespace {
 
+// Per-launch control of one step.  In solve mode the kernel first reads the
+// solve state (done step, error bits, the previous step's test flag, gamma);
+// the decision to skip the step is taken only after each thread's first row
+// loads are in flight, so the two memory round trips overlap.
+struct StepCtl {
+    float g = 0.0f, tau = 0.0f;
+    bool do_test = false, do_write = true, solve = false;
+    int k = 0, km = 0, ms = 0, ce = 1, done = -1, err = 0, nc_prev = 1;
+
+    // Solve-mode loads.  Called after the thread has issued its column loads:
+    // scalar loads complete in any order, so a wait for the row offsets would
+    // otherwise also wait for these.
+    __device__ __forceinline__ void fetch(const StepArgs& a) {
+        if (!a.solve) {
+            g = a.gamma_scalar;
+            return;
+        }
+        const SolveState* st = a.st;
+        solve = true;
+        k = a.k;
+        km = a.k >= 1 ? a.k - 1 : 0;
+        done = st->done_step;
+        err = st->err;
+        ms = st->max_steps;
+        ce = st->check_every;
+        tau = st->tau;
+        nc_prev = a.notconv[km];
+        g = a.gamma[a.k];
+        do_test = k >= 1 && (k % ce == 0 || k == ms);
+        do_write = k < ms;
+    }
+
+    // false: this launch does no work (the solve has stopped, or the previous
+    // step's state passed the test, which block 0 records).  Uniform over the grid.
+    __device__ __forceinline__ bool proceed(const StepArgs& a) const {
+        if (!solve) return true;
+        if (k > ms || done >= 0 || err) return false;
+        if (k >= 2 && (km % ce == 0 || km == ms) && nc_prev == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.st->done_step = km;
+            return false;
+        }
+        return true;
+    }
+};
+
 // Row epilogue; returns true when the input state fails the stopping test at row i.
-__device__ __forceinline__ bool row_update(const StepArgs& a, int i, float yraw, float vi, float sigma, bool nbr_sel,
-                                           float g, bool do_test, bool do_write, float tau, int& fb) {
+__device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl& c, int i, float yraw, float vi,
+                                           float sigma, bool nbr_sel, int& fb) {
     const float yi = fabsf(yraw);
-    const float s = __fmaf_rn(g, sigma, yi);
+    const float s = __fmaf_rn(c.g, sigma, yi);
     const bool fallback = !(s > 1e-9f);
     const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
     if (a.s_out) a.s_out[i] = s;
-    if (do_write) {
+    if (c.do_write) {
         if (a.y_out) {
             const float yn = vi * xn;
             a.y_out[i] = xn > 0.5f ? -yn : yn;
@@ -35,112 +80,59 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, int i, float yraw,
         if (a.x_out_user) a.x_out_user[a.perm[i]] = xn;
         fb += fallback ? 1 : 0;
     }
-    if (!do_test) return false;
+    if (!c.do_test) return false;
     const bool in_s = sign_of(yraw) != 0u;
-    const float tv = tau * vi;
+    const float tv = c.tau * vi;
     const bool far = (yi > tv) && ((vi - yi) > tv);   // min(x, 1-x) > tau with x = y/v
     const bool uncovered = !in_s && !nbr_sel;
     const bool growing = !in_s && (yi > 0.0f) && !(s > vi);
     return far || uncovered || growing;
 }
 
-// Rows of one bin handled by groups of G threads, MAXD = the bin's degree bound.
+// Rows of a sliced bin: one wavefront per slice of 64/G rows, G threads per row,
+// MAXD = the bin's degree bound.  Returns -1 when the launch does no work, else
+// whether the thread's row failed the stopping test.
 template <int G, int MAXD>
-__device__ __forceinline__ bool group_rows(const StepArgs& a, int rb, int re, int lb, float g, bool do_test,
-                                           bool do_write, float tau, int& fb) {
-    constexpr int per_block = kBlock / G;
-    const int t = threadIdx.x & (G - 1);
-    const int i = rb + lb * per_block + threadIdx.x / G;
+__device__ __forceinline__ int sliced_rows(const StepArgs& a, StepCtl& c, int b, int rb, int re, int lb, int& fb) {
+    constexpr int RS = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int ls = lb * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // slice inside the bin
+    const int r0 = rb + ls * RS;
+    if (r0 >= re) {  // whole wavefront past the bin
+        c.fetch(a);
+        return c.proceed(a) ? 0 : -1;
+    }
+    const int t = lane & (G - 1);
+    const int i = r0 + lane / G;
     const bool valid = i < re;
-    const float* __restrict__ y = a.y_in;
+    const int gs = a.bins.slice_begin[b] + ls;
+    const int l0 = a.sl_off[gs];
+    const int width = a.sl_off[gs + 1] - l0;
     float yraw = 0.0f, vi = 1.0f;
-    int start = 0, d = 0;
     if (valid) {
-        start = gnk::ld_stream(a.row_ptr + i);
-        d = gnk::ld_stream(a.row_ptr + i + 1) - start;
-        yraw = y[i];
+        yraw = a.y_in[i];
         vi = gnk::ld_stream(a.v + i);
     }
+    gnk::SlicedIdx<G, MAXD> idx;
+    idx.load(a.sl_col + (size_t)l0 * 64 + lane, width);
+    c.fetch(a);
+    if (!c.proceed(a)) return -1;
     unsigned sel = 0u;
-    const float sigma = gnk::row_sum<G, MAXD>(a.col + start, d, y, t, sel);
+    const float sigma = idx.template sum<true>(a.y_in, sel);
     const bool any_sel = gnk::group_any<G>(sel != 0u);
-    if (valid && t == 0) return row_update(a, i, yraw, vi, sigma, any_sel, g, do_test, do_write, tau, fb);
-    return false;
-}
-
-// Thread-per-row bin with coalesced column loads: each wavefront copies the
-// contiguous column segment of its 64 rows (at most 64 * MAXD entries) into LDS
-// with unit-stride loads, then every thread reads its own row from LDS.
-template <int MAXD>
-__device__ __forceinline__ bool lane_rows_staged(const StepArgs& a, int rb, int re, int lb, float g, bool do_test,
-                                                 bool do_write, float tau, int& fb, int32_t* seg) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int w0 = rb + lb * kBlock + wave * 64;    // first row of this wavefront
-    const int i = w0 + lane;
-    const bool valid = i < re;
-    const float* __restrict__ y = a.y_in;
-    int32_t* wseg = seg + wave * 64 * MAXD;
-    int start = 0, d = 0, base = 0;
-    float yraw = 0.0f, vi = 1.0f;
-    if (w0 < re) {
-        const int wl = min(w0 + 64, re);
-        base = gnk::ld_stream(a.row_ptr + w0);
-        const int total = gnk::ld_stream(a.row_ptr + wl) - base;
-        if (valid) {
-            start = gnk::ld_stream(a.row_ptr + i) - base;
-            d = gnk::ld_stream(a.row_ptr + i + 1) - base - start;
-            yraw = y[i];
-            vi = gnk::ld_stream(a.v + i);
-        }
-#pragma unroll
-        for (int k = 0; k < MAXD; ++k) {
-            const int p = lane + 64 * k;
-            if (p < total) wseg[p] = a.col[base + p];
-        }
-    }
-    __syncthreads();
-    unsigned sel = 0u;
-    const float sigma = gnk::row_sum<1, MAXD>(wseg + start, d, y, 0, sel);
-    if (valid) return row_update(a, i, yraw, vi, sigma, sel != 0u, g, do_test, do_write, tau, fb);
-    return false;
+    if (valid && t == 0) return row_update(a, c, i, yraw, vi, sigma, any_sel, fb) ? 1 : 0;
+    return 0;
 }
 
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
     __shared__ float stage[kStage];
-    __shared__ int s_flag;
-    __shared__ int s_fb;
+    __shared__ int s_viol[kWaves];
+    __shared__ int s_fb[kWaves];
 
-    float g;
-    float tau = 0.0f;
-    bool do_test = false, do_write = true;
-    if (a.solve) {
-        // every value is loaded up front (independent loads); the gamma and flag
-        // tables cover every step index a captured chain can reach
-        const SolveState* st = a.st;
-        const int done = st->done_step, err = st->err, ms = st->max_steps, ce = st->check_every;
-        const float tau_s = st->tau;
-        const int km = a.k >= 1 ? a.k - 1 : 0;
-        const int nc_prev = a.notconv[km];
-        const float gk = a.gamma[a.k];
-        if (a.k > ms || done >= 0 || err) return;
-        if (a.k >= 2 && (km % ce == 0 || km == ms) && nc_prev == 0) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.st->done_step = km;
-            return;
-        }
-        do_test = a.k >= 1 && (a.k % ce == 0 || a.k == ms);
-        do_write = a.k < ms;
-        tau = tau_s;
-        g = gk;
-    } else {
-        g = a.gamma_scalar;
-    }
-    if (threadIdx.x == 0) {
-        s_flag = 0;
-        s_fb = 0;
-    }
-    __syncthreads();
+    // the gamma and flag tables cover every step index a captured chain can reach
+    StepCtl c;
 
     const int blk = blockIdx.x;
     int b = 0;
@@ -149,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rb = a.bins.row_begin[b], re = a.bins.row_begin[b + 1];
-    bool viol = false;
+    int r = 0;
     int fb = 0;
 
     if (b == BIN_BLOCK) {
@@ -160,6 +152,8 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
         const int d = gnk::ld_stream(a.row_ptr + i + 1) - start;
         const float yraw = a.y_in[i];
         const float vi = a.v[i];
+        c.fetch(a);
+        if (!c.proceed(a)) return;
         constexpr int PT = kStage / kBlock;  // entries per thread per chunk
         float acc = 0.0f;
         unsigned sel = 0u;
@@ -187,42 +181,66 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
         if (wave == 0) {
             for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
             const bool any_sel = __any(sel != 0u);
-            if (lane == 0) viol = row_update(a, i, yraw, vi, acc, any_sel, g, do_test, do_write, tau, fb);
+            if (lane == 0) r = row_update(a, c, i, yraw, vi, acc, any_sel, fb) ? 1 : 0;
         }
     } else if (b == BIN_WAVE) {
         // two rows per wavefront, all their loads in flight together
         const int ia = rb + (lb * kWaves + wave) * 2;
         const int ib = ia + 1;
-        if (ia < re) {
-            const bool hb = ib < re;
-            const int sa = gnk::ld_stream(a.row_ptr + ia), ea = gnk::ld_stream(a.row_ptr + ia + 1);
-            const int sb = hb ? ea : 0, eb = hb ? gnk::ld_stream(a.row_ptr + ib + 1) : 0;
-            const float ya = a.y_in[ia], va = a.v[ia];
-            const float yb = hb ? a.y_in[ib] : 0.0f, vb = hb ? a.v[ib] : 1.0f;
+        const bool act = ia < re, hb = ib < re;
+        int sa = 0, ea = 0, sb = 0, eb = 0;
+        float ya = 0.0f, va = 1.0f, yb = 0.0f, vb = 1.0f;
+        if (act) {
+            sa = gnk::ld_stream(a.row_ptr + ia);
+            ea = gnk::ld_stream(a.row_ptr + ia + 1);
+            ya = a.y_in[ia];
+            va = a.v[ia];
+            if (hb) {
+                sb = ea;
+                eb = gnk::ld_stream(a.row_ptr + ib + 1);
+                yb = a.y_in[ib];
+                vb = a.v[ib];
+            }
+        }
+        c.fetch(a);
+        if (!c.proceed(a)) return;
+        if (act) {
             unsigned sela = 0u, selb = 0u;
             float acca, accb;
             gnk::row_sum_wave2<kWaveMaxDeg / 64>(a.col + sa, ea - sa, a.col + sb, eb - sb, a.y_in, lane, acca, accb,
                                                  sela, selb);
             const bool anya = __any(sela != 0u);
             const bool anyb = __any(selb != 0u);
-            if (lane == 0) viol = row_update(a, ia, ya, va, acca, anya, g, do_test, do_write, tau, fb);
-            if (lane == 1 && hb) viol = row_update(a, ib, yb, vb, accb, anyb, g, do_test, do_write, tau, fb);
+            if (lane == 0) r = row_update(a, c, ia, ya, va, acca, anya, fb) ? 1 : 0;
+            if (lane == 1 && hb) r = row_update(a, c, ib, yb, vb, accb, anyb, fb) ? 1 : 0;
         }
-    } else if (b == BIN_G8) {
-        viol = group_rows<8, 128>(a, rb, re, lb, g, do_test, do_write, tau, fb);
-    } else if (b == BIN_LANE32) {
-        viol = group_rows<2, 32>(a, rb, re, lb, g, do_test, do_write, tau, fb);
     } else {
-        viol = lane_rows_staged<16>(a, rb, re, lb, g, do_test, do_write, tau, fb, reinterpret_cast<int32_t*>(stage));
+        if (b == BIN_G8) r = sliced_rows<8, 128>(a, c, b, rb, re, lb, fb);
+        else if (b == BIN_LANE32) r = sliced_rows<2, 32>(a, c, b, rb, re, lb, fb);
+        else r = sliced_rows<1, 16>(a, c, b, rb, re, lb, fb);
+        if (r < 0) return;  // uniform over the grid
     }
 
     if (a.solve) {
-        if (viol) s_flag = 1;
-        if (fb) atomicAdd(&s_fb, fb);
+        // per-wavefront ballots into one slot per wavefront (no initialisation
+        // needed), one barrier, one global write per block; each thread updates at
+        // most one row, so fb is 0 or 1
+        const bool wv = __ballot(r > 0) != 0ull;
+        const int wf = __popcll(__ballot(fb != 0));
+        if (lane == 0) {
+            s_viol[wave] = wv ? 1 : 0;
+            s_fb[wave] = wf;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            if (s_flag) a.notconv[a.k] = 1;
-            if (s_fb) atomicAdd(&a.st->fallback, (unsigned long long)s_fb);
+            int v = 0, f = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                v |= s_viol[w];
+                f += s_fb[w];
+            }
+            if (v) a.notconv[a.k] = 1;
+            if (f) atomicAdd(&a.st->fallback, (unsigned long long)f);
         }
     }
 }
@@ -304,6 +322,8 @@ static StepArgs base_args(const gn_graph* g) {
     a.col = g->col;
     a.v = g->v;
     a.perm = g->perm;
+    a.sl_col = g->sl_col;
+    a.sl_off = g->sl_off;
     a.bins = g->bins;
     return a;
 }

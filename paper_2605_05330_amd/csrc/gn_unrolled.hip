@@ -222,6 +222,8 @@ StepArgs fwd_args(const gn_graph* g, const float* v) {
     a.col = g->col;
     a.v = v;
     a.perm = g->perm;
+    a.sl_col = g->sl_col;
+    a.sl_off = g->sl_off;
     a.bins = g->bins;
     a.solve = 0;
     a.gamma = nullptr;
