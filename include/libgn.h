@@ -44,6 +44,7 @@ extern "C" {
 
 typedef struct gn_graph gn_graph; /* one graph: CSR, weights, degree bins, work buffers */
 typedef struct gn_batch gn_batch; /* many independent graphs solved in one launch        */
+typedef struct gn_rook gn_rook;   /* assignment instance: rows x cols weight matrix       */
 
 typedef enum {
     GN_OK = 0,
@@ -283,6 +284,54 @@ gn_status gn_mpnn_backward(const gn_graph* g, const float* params, const float* 
  * counts steps from 1.  All pointers device fp32.  ASYNC. */
 gn_status gn_adam_step(float* params, const float* grad, float* m, float* v, int32_t count, float lr, float beta1,
                        float beta2, float eps, int32_t t, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Assignment problem: matrix cross-normalization (Section 2).
+ *
+ * The graph is the line graph of the complete bipartite graph K_{rows,cols}:
+ * vertex (i, j) = i*cols + j carries the weight W_ij, and two entries conflict
+ * when they share a row or a column.  GN normalizes every entry by the mass of
+ * its row and column, so with R_i, C_j the row and column sums of y = v (.) x
+ *     s_ij = y_ij + gamma * ((R_i - y_ij) + (C_j - y_ij)),
+ * which costs O(rows*cols) per step; the results are those of gn_step / gn_solve
+ * on the same graph up to rounding (sums in another order, row and column sums
+ * in fp64).  The MWIS of this graph is a maximum-weight matching; for
+ * rows = cols the selected set is a permutation matrix.
+ * All matrices are row-major, rows*cols entries, device memory unless stated.
+ * ------------------------------------------------------------------------- */
+
+/* Create an assignment instance from a weight matrix w (rows >= 1, cols >= 1,
+ * rows*cols <= 2^31-1), host or device per flags (GN_INPUT_HOST /
+ * GN_INPUT_DEVICE).  Every W_ij must be finite and > 0.  The library copies w.
+ * SYNC.  Errors: GN_E_ARG, GN_E_WEIGHT, GN_E_NOMEM, GN_E_HIP; *out = NULL on
+ * error. */
+gn_status gn_rook_create(int32_t rows, int32_t cols, const float* w, uint32_t flags, hipStream_t stream,
+                         gn_rook** out);
+
+/* Free an assignment instance (NULL is allowed).  Waits for the device. */
+void gn_rook_destroy(gn_rook* r);
+
+/* One cross-normalization step at gamma: x_out = N(x_in), with the safe
+ * division of gn_step.  x_in, x_out: device float[rows*cols], must not alias;
+ * x_in finite and >= 0.  ASYNC. */
+gn_status gn_rook_step(gn_rook* r, float gamma, const float* x_in, float* x_out, hipStream_t stream);
+
+/* Iterate to binarisation under `sch`, with the stopping rule of gn_solve.
+ * x: device float[rows*cols], x^0 on entry, final state (clamped to [0,1]) on
+ * exit; sel: device uint8[rows*cols], (x > 1/2); res: host.  conflicts counts
+ * pairs of selected entries sharing a row or a column, uncovered the unselected
+ * entries whose row and column hold no selected entry, stab is the
+ * gamma-stability of the set under gamma_k.  x^0 must be finite, >= 0 and
+ * normalizable (no zero entry whose row and column are all zero), else GN_E_ARG /
+ * GN_E_NOT_NORMALIZABLE.  Returns GN_OK when binarised, GN_NOT_CONVERGED when
+ * max_steps ran out.  SYNC. */
+gn_status gn_rook_solve(gn_rook* r, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                        hipStream_t stream);
+
+/* Tuning: number of step launches captured in one replayed chain by gn_solve and
+ * gn_rook_solve (default 32, 1..4096).  A longer chain checks the stop flag less
+ * often from the host; results do not change.  Process-wide; not thread-safe. */
+gn_status gn_set_chunk_len(int32_t len);
 
 /* Human-readable name of a status code (static string). */
 const char* gn_status_str(gn_status s);

@@ -382,6 +382,11 @@ gn_status gn_internal_ensure_ws(gn_graph* g, int32_t steps_needed) {
             return GN_E_NOMEM;
         }
     }
+    return gn_internal_ensure_tables(ws, steps_needed);
+}
+
+// Step tables (test flags, gamma) of a solve workspace, grown on demand.
+gn_status gn_internal_ensure_tables(GraphWorkspace& ws, int32_t steps_needed) {
     if (steps_needed > ws.cap_steps) {
         int32_t cap = std::max(steps_needed, 2 * ws.cap_steps);
         if (ws.notconv) (void)hipFree(ws.notconv);

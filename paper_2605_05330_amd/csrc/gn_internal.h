@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "libgn.h"
@@ -149,4 +150,19 @@ gn_status gn_internal_final_stats(gn_graph* g, const float* y_fin, float gamma_f
 gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, FinalStats* host_out,
                                 hipStream_t s);
 int32_t gn_internal_grid_blocks(const BinLayout& b);
+
+// solve driver pieces shared by the graph and the assignment (rook) solvers
+// (gn_step.hip): schedule check, gamma table and state reset, the pipelined
+// replay of captured step chains, the stopping outcome and the result record
+extern int32_t g_chunk_len;
+float gn_internal_host_gamma(const gn_schedule* s, int32_t k);
+bool gn_internal_schedule_ok(const gn_schedule* sch);
+gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream);
+gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
+                                 const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
+                                 hipStream_t stream);
+gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_t* steps, bool* binarised);
+gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
+                                  gn_result* res);
+gn_status gn_internal_ensure_tables(GraphWorkspace& ws, int32_t steps_needed);
 void gn_internal_free_unrolled(gn_graph* g);

@@ -11,61 +11,18 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 #include "gn_internal.h"
+#include "gn_ctl.h"
 #include "gn_rowsum.h"
 
 using gnk::sign_of;
 
 namespace {
 
-// Per-launch control of one step.  In solve mode the kernel first reads the
-// solve state (done step, error bits, the previous step's test flag, gamma);
-// the decision to skip the step is taken only after each thread's first row
-// loads are in flight, so the two memory round trips overlap.
-struct StepCtl {
-    float g = 0.0f, tau = 0.0f;
-    bool do_test = false, do_write = true, solve = false;
-    int k = 0, km = 0, ms = 0, ce = 1, done = -1, err = 0, nc_prev = 1;
-
-    // Solve-mode loads.  Called after the thread has issued its column loads:
-    // scalar loads complete in any order, so a wait for the row offsets would
-    // otherwise also wait for these.
-    __device__ __forceinline__ void fetch(const StepArgs& a) {
-        if (!a.solve) {
-            g = a.gamma_scalar;
-            return;
-        }
-        const SolveState* st = a.st;
-        solve = true;
-        k = a.k;
-        km = a.k >= 1 ? a.k - 1 : 0;
-        done = st->done_step;
-        err = st->err;
-        ms = st->max_steps;
-        ce = st->check_every;
-        tau = st->tau;
-        nc_prev = a.notconv[km];
-        g = a.gamma[a.k];
-        do_test = k >= 1 && (k % ce == 0 || k == ms);
-        do_write = k < ms;
-    }
-
-    // false: this launch does no work (the solve has stopped, or the previous
-    // step's state passed the test, which block 0 records).  Uniform over the grid.
-    __device__ __forceinline__ bool proceed(const StepArgs& a) const {
-        if (!solve) return true;
-        if (k > ms || done >= 0 || err) return false;
-        if (k >= 2 && (km % ce == 0 || km == ms) && nc_prev == 0) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.st->done_step = km;
-            return false;
-        }
-        return true;
-    }
-};
-
 // Row epilogue; returns true when the input state fails the stopping test at row i.
-__device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl& c, int i, float yraw, float vi,
+__device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<StepArgs>& c, int i, float yraw, float vi,
                                            float sigma, bool nbr_sel, int& fb) {
     const float yi = fabsf(yraw);
     const float s = __fmaf_rn(c.g, sigma, yi);
@@ -93,7 +50,7 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl& c, 
 // MAXD = the bin's degree bound.  Returns -1 when the launch does no work, else
 // whether the thread's row failed the stopping test.
 template <int G, int MAXD>
-__device__ __forceinline__ int sliced_rows(const StepArgs& a, StepCtl& c, int b, int rb, int re, int lb, int& fb) {
+__device__ __forceinline__ int sliced_rows(const StepArgs& a, StepCtl<StepArgs>& c, int b, int rb, int re, int lb, int& fb) {
     constexpr int RS = 64 / G;
     const int lane = threadIdx.x & 63;
     const int ls = lb * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // slice inside the bin
@@ -132,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
     __shared__ int s_fb[kWaves];
 
     // the gamma and flag tables cover every step index a captured chain can reach
-    StepCtl c;
+    StepCtl<StepArgs> c;
 
     const int blk = blockIdx.x;
     int b = 0;
@@ -301,11 +258,104 @@ __global__ void init_solve_kernel(SolveState* st, int32_t* notconv, float* gamma
     }
 }
 
-static float host_gamma(const gn_schedule* s, int32_t k) {
+float gn_internal_host_gamma(const gn_schedule* s, int32_t k) {
     if (s->ramp_steps <= 1) return s->gamma1;
     const int32_t kk = k < s->ramp_steps - 1 ? k : s->ramp_steps - 1;
     const double p = (double)kk / (double)(s->ramp_steps - 1);
     return (float)(p * (double)s->gamma1 + (1.0 - p) * (double)s->gamma0);
+}
+
+bool gn_internal_schedule_ok(const gn_schedule* sch) {
+    return sch->max_steps >= 0 && sch->check_every >= 1 && sch->tau >= 0.0f && std::isfinite(sch->tau) &&
+           std::isfinite(sch->gamma0) && std::isfinite(sch->gamma1) && sch->gamma0 >= 0.0f && sch->gamma1 >= 0.0f &&
+           sch->max_steps <= (1 << 28);
+}
+
+gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream) {
+    const int32_t ms = sch->max_steps;
+    hipLaunchKernelGGL(init_solve_kernel, dim3(std::min((ms + 1 + 255) / 256, 1024)), dim3(256), 0, stream, ws.state,
+                       ws.notconv, ws.gamma, ms, sch->check_every, sch->tau, sch->gamma0, sch->gamma1,
+                       sch->ramp_steps);
+    GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
+}
+
+gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
+                                 const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
+                                 hipStream_t stream) {
+    if (ws.chunk_len != C) {
+        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        ws.chunks.clear();
+        ws.chunk_len = C;
+    }
+    if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
+    volatile int32_t* pin = (volatile int32_t*)ws.host_pinned;  // [slot][done_step, err]
+    hipEvent_t ev[2];
+    GN_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return GN_E_HIP;
+    }
+    gn_status rs = GN_OK;
+    for (int32_t c = 0; c < nchunks && rs == GN_OK; ++c) {
+        if (!ws.chunks[c]) {
+            rs = build(c, &ws.chunks[c]);
+            if (rs != GN_OK) break;
+        }
+        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess ||
+            hipMemcpyAsync((void*)(pin + 2 * (c & 1)), ws.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess ||
+            hipEventRecord(ev[c & 1], stream) != hipSuccess) {
+            rs = GN_E_HIP;
+            break;
+        }
+        if (c >= 1) {
+            const int p = (c - 1) & 1;
+            if (hipEventSynchronize(ev[p]) != hipSuccess) {
+                rs = GN_E_HIP;
+                break;
+            }
+            if (pin[2 * p] >= 0 || pin[2 * p + 1] != 0) break;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rs != GN_OK) return rs;
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    return GN_OK;
+}
+
+gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_t* steps, bool* binarised) {
+    SolveState hs;
+    int32_t nc_last = 1;
+    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    GN_HIP_TRY(hipMemcpy(&nc_last, ws.notconv + ms, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (hs.err & 1) return GN_E_ARG;
+    if (hs.err & 2) return GN_E_NOT_NORMALIZABLE;
+    if (hs.done_step >= 0) {
+        *steps = hs.done_step;
+        *binarised = true;
+    } else {
+        *steps = ms;
+        *binarised = ms >= 1 && nc_last == 0;
+    }
+    return GN_OK;
+}
+
+gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
+                                  gn_result* res) {
+    SolveState hs;
+    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    res->steps = steps;
+    res->binarised = binarised ? 1 : 0;
+    res->fallback_count = (int64_t)hs.fallback;
+    res->relaxed_objective = fs.relaxed_objective;
+    res->set_objective = fs.set_objective;
+    res->set_size = fs.set_size;
+    res->conflicts = fs.conflicts;
+    res->uncovered = fs.uncovered;
+    res->stab = fs.stab;
+    return binarised ? GN_OK : GN_NOT_CONVERGED;
 }
 
 gn_status gn_internal_launch_step(const gn_graph* g, const StepArgs& a, hipStream_t s) {
@@ -389,7 +439,7 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t
     return e == hipSuccess ? GN_OK : GN_E_HIP;
 }
 
-static int32_t g_chunk_len = 32;
+int32_t g_chunk_len = 32;
 
 extern "C" gn_status gn_set_chunk_len(int32_t len);
 gn_status gn_set_chunk_len(int32_t len) {
@@ -401,10 +451,7 @@ gn_status gn_set_chunk_len(int32_t len) {
 extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
                               hipStream_t stream) {
     if (!g || !sch || !res) return GN_E_ARG;
-    if (sch->max_steps < 0 || sch->check_every < 1 || !(sch->tau >= 0.0f) || !std::isfinite(sch->tau) ||
-        !std::isfinite(sch->gamma0) || !std::isfinite(sch->gamma1) || sch->gamma0 < 0.0f || sch->gamma1 < 0.0f ||
-        sch->max_steps > (1 << 28))
-        return GN_E_ARG;
+    if (!gn_internal_schedule_ok(sch)) return GN_E_ARG;
     std::memset(res, 0, sizeof(*res));
     if (g->n == 0) {
         res->binarised = 1;
@@ -420,10 +467,7 @@ extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uin
     GraphWorkspace& ws = g->ws;
     const int n = g->n;
 
-    hipLaunchKernelGGL(init_solve_kernel, dim3(std::min((ms + 1 + 255) / 256, 1024)), dim3(256), 0, stream, ws.state,
-                       ws.notconv, ws.gamma, ms, sch->check_every, sch->tau, sch->gamma0, sch->gamma1,
-                       sch->ramp_steps);
-    GN_HIP_TRY(hipGetLastError());
+    if ((st = gn_internal_init_solve(ws, sch, stream)) != GN_OK) return st;
     hipLaunchKernelGGL(prep_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, (const float*)x, g->perm,
                        g->v, ws.y[0], ws.state);
     GN_HIP_TRY(hipGetLastError());
@@ -431,71 +475,14 @@ extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uin
                        (const float*)x, g->perm, ws.state);
     GN_HIP_TRY(hipGetLastError());
 
-    if (ws.chunk_len != C) {
-        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
-        ws.chunks.clear();
-        ws.chunk_len = C;
-    }
-    if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
-    volatile int32_t* pin = (volatile int32_t*)ws.host_pinned;  // [slot][done_step, err]
-    hipEvent_t ev[2];
-    GN_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
-        (void)hipEventDestroy(ev[0]);
-        return GN_E_HIP;
-    }
-    gn_status rs = GN_OK;
-    for (int32_t c = 0; c < nchunks && rs == GN_OK; ++c) {
-        if (!ws.chunks[c]) {
-            rs = build_chunk(g, c, C, &ws.chunks[c]);
-            if (rs != GN_OK) break;
-        }
-        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess ||
-            hipMemcpyAsync((void*)(pin + 2 * (c & 1)), ws.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           stream) != hipSuccess ||
-            hipEventRecord(ev[c & 1], stream) != hipSuccess) {
-            rs = GN_E_HIP;
-            break;
-        }
-        if (c >= 1) {
-            const int p = (c - 1) & 1;
-            if (hipEventSynchronize(ev[p]) != hipSuccess) {
-                rs = GN_E_HIP;
-                break;
-            }
-            if (pin[2 * p] >= 0 || pin[2 * p + 1] != 0) break;
-        }
-    }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    if (rs != GN_OK) return rs;
-    GN_HIP_TRY(hipStreamSynchronize(stream));
-    SolveState hs;
-    int32_t nc_last = 1;
-    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
-    GN_HIP_TRY(hipMemcpy(&nc_last, ws.notconv + ms, sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (hs.err & 1) return GN_E_ARG;
-    if (hs.err & 2) return GN_E_NOT_NORMALIZABLE;
+    st = gn_internal_run_chunks(ws, nchunks, C,
+                                [g, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, out); }, stream);
+    if (st != GN_OK) return st;
     int32_t steps;
     bool binarised;
-    if (hs.done_step >= 0) {
-        steps = hs.done_step;
-        binarised = true;
-    } else {
-        steps = ms;
-        binarised = ms >= 1 && nc_last == 0;
-    }
+    if ((st = gn_internal_solve_outcome(ws, ms, &steps, &binarised)) != GN_OK) return st;
     FinalStats fs{};
-    st = gn_internal_final_stats(g, ws.y[steps & 1], host_gamma(sch, steps), x, sel, &fs, stream);
+    st = gn_internal_final_stats(g, ws.y[steps & 1], gn_internal_host_gamma(sch, steps), x, sel, &fs, stream);
     if (st != GN_OK) return st;
-    res->steps = steps;
-    res->binarised = binarised ? 1 : 0;
-    res->fallback_count = (int64_t)hs.fallback;
-    res->relaxed_objective = fs.relaxed_objective;
-    res->set_objective = fs.set_objective;
-    res->set_size = fs.set_size;
-    res->conflicts = fs.conflicts;
-    res->uncovered = fs.uncovered;
-    res->stab = fs.stab;
-    return binarised ? GN_OK : GN_NOT_CONVERGED;
+    return gn_internal_fill_result(ws, steps, binarised, fs, res);
 }

@@ -204,6 +204,30 @@ def rook(N: int) -> Graph:
     return Graph(n, row_ptr.astype(np.int32), cols.reshape(-1))
 
 
+def rook_rect(rows: int, cols: int) -> Graph:
+    """Line graph of K_{rows,cols} (a rows x cols rook board): cell (a, b) = a*cols + b,
+    adjacent to the other cells of its row and of its column; sorted CSR."""
+    n = rows * cols
+    deg = (rows - 1) + (cols - 1)
+    if n * deg > np.iinfo(np.int32).max:
+        raise ValueError("board too large for int32 CSR")
+    out = np.empty((rows, cols, deg), dtype=np.int32)
+    kr = np.arange(rows, dtype=np.int64) * cols
+    kc = np.arange(cols, dtype=np.int64)
+    for a in range(rows):
+        above, below = kr[:a], kr[a + 1:]
+        for b in range(cols):
+            out[a, b, :] = np.concatenate([above + b, np.delete(a * cols + kc, b), below + b])
+    return Graph(n, (np.arange(n + 1, dtype=np.int64) * deg).astype(np.int32), out.reshape(-1))
+
+
+def rook_weights_rect(rows: int, cols: int, seed: int, temperature: float = 0.1, stream: int = 1) -> np.ndarray:
+    """Assignment weights w = exp(-C / T), C uniform [0, 1) fp32, as a rows x cols
+    float32 matrix (row-major = cell order)."""
+    C = rng_for(seed, stream).random(size=(rows, cols), dtype=np.float32)
+    return np.exp(-C.astype(np.float64) / temperature).astype(np.float32)
+
+
 def hub_graph(n: int, hub_degrees, background_degree: float, seed: int, stream: int = 0) -> Graph:
     """Sparse ER background of the given mean degree plus one hub per entry of
     ``hub_degrees``, each joined to that many distinct random vertices: a

@@ -84,6 +84,12 @@ def lib():
             "gn_mpnn_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
             "gn_adam_step": ([_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_int32, _vp], ctypes.c_int),
+            "gn_rook_create": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
+                               ctypes.c_int),
+            "gn_rook_destroy": ([_vp], None),
+            "gn_rook_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
+            "gn_rook_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
+                              ctypes.c_int),
             "gn_unrolled_ckpt_floats": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
             "gn_unrolled_forward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
             "gn_unrolled_backward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp],
@@ -264,6 +270,68 @@ class Graph:
 
     def check(self, sel, stream=None):
         return gn_check_independent(self.handle, sel, stream)
+
+
+def gn_rook_create(rows, cols, w, stream=None):
+    """Assignment instance from a rows x cols weight matrix (row-major; host numpy
+    array or CUDA tensor, float32)."""
+    import torch
+    keep = None
+    if isinstance(w, torch.Tensor) and w.is_cuda:
+        p_w = _dptr(w, torch.float32, "w")
+        fl = GN_INPUT_DEVICE
+    else:
+        keep, p_w = _hptr(w, np.float32)
+        fl = GN_INPUT_HOST
+    h = ctypes.c_void_p()
+    _check(lib().gn_rook_create(int(rows), int(cols), p_w, fl, _stream(stream), ctypes.byref(h)), "gn_rook_create")
+    del keep
+    return h
+
+
+def gn_rook_destroy(h):
+    if h:
+        lib().gn_rook_destroy(h)
+
+
+def gn_rook_step(h, gamma, x_in, x_out, stream=None):
+    import torch
+    _check(lib().gn_rook_step(h, float(gamma), _dptr(x_in, torch.float32, "x_in"),
+                              _dptr(x_out, torch.float32, "x_out"), _stream(stream)), "gn_rook_step")
+
+
+def gn_rook_solve(h, schedule: gn_schedule, x, sel, stream=None) -> Result:
+    import torch
+    r = gn_result()
+    st = lib().gn_rook_solve(h, ctypes.byref(schedule), _dptr(x, torch.float32, "x"),
+                             _dptr(sel, torch.uint8, "sel"), ctypes.byref(r), _stream(stream))
+    _check(st, "gn_rook_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return _result(r, st)
+
+
+class Rook:
+    """Owning wrapper of a gn_rook handle (assignment by cross-normalization)."""
+
+    def __init__(self, rows, cols, w, stream=None):
+        self.rows, self.cols = int(rows), int(cols)
+        self.handle = gn_rook_create(rows, cols, w, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            gn_rook_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, gamma, x_in, x_out, stream=None):
+        gn_rook_step(self.handle, gamma, x_in, x_out, stream)
+
+    def solve(self, x, sel, stream=None, **sched) -> Result:
+        return gn_rook_solve(self.handle, make_schedule(**sched), x, sel, stream)
 
 
 def _result(r: gn_result, st: int) -> Result:
