@@ -90,6 +90,36 @@ def fixed_step_time(G, x0, nsteps, gamma):
     return e0.elapsed_time(e1) / nsteps
 
 
+def rook_step_bytes(N: int) -> int:
+    """Algorithmic HBM bytes of one cross-normalization step on an N x N matrix: y and v
+    read, y' written (fp32), plus the fp64 tile partial sums written and read once
+    (16-row x 64-column tiles: N * N/64 row partials and N * N/16 column partials)."""
+    parts = N * ((N + 63) // 64) + N * ((N + 15) // 16)
+    return 12 * N * N + 2 * 8 * parts
+
+
+def bench_rook_structured(N, w, sched, reps, csr_res):
+    """The assignment instance through the structured O(N^2) solver: time to
+    binarisation, and the step time against its algorithmic bytes."""
+    import torch
+    from paper_2605_05330_amd import libgn
+    R = libgn.Rook(N, N, np.asarray(w, np.float32).reshape(N, N))
+    x0 = torch.full((N * N,), 0.5, device="cuda")
+    res, ms, _ = timed_solves(R, x0, reps, 1, sched)
+    t = fixed_step_time(R, x0, 300, 1.2)
+    b = rook_step_bytes(N)
+    edges = N * N * (N - 1)
+    out = {"N": N, "gn_steps": res.steps, "time_to_binary_ms": ms, "binarised": res.binarised,
+           "set_objective": res.set_objective, "edges_iters_per_s": edges * res.steps / (ms / 1e3),
+           "step_us": t * 1e3, "step_bytes": b, "step_GBs": b / (t / 1e3) / 1e9,
+           "step_frac": b / (t / 1e3) / 1e9 / HBM_PEAK_GBS}
+    if csr_res is not None:
+        out["same_set_objective_as_csr"] = abs(res.set_objective - csr_res.set_objective) <= 1e-9 * abs(
+            csr_res.set_objective)
+    del R
+    return out
+
+
 def bench_batch(sched, reps):
     """4,096 graphs, n log-uniform in [50, 5000], half ER (degree 6) half unit-disk
     (degree 10), w ~ U(0,1], x0 = 1/2, same schedule: one persistent launch per
@@ -321,6 +351,9 @@ def main():
                           "step_us": rt * 1e3, "step_GBs": rb / (rt / 1e3) / 1e9,
                           "step_frac": rb / (rt / 1e3) / 1e9 / HBM_PEAK_GBS}
         del R
+        out["rook256"]["structured"] = bench_rook_structured(256, wr, sched, max(1, a.steps // 2), rres)
+        w4 = I.rook_weights_rect(4096, 4096, 0)
+        out["assignment4096_structured"] = bench_rook_structured(4096, w4, sched, 2, None)
 
     if not a.no_batch:
         out["batched4096"] = bench_batch(sched, a.steps)

@@ -135,7 +135,7 @@ def read_traffic(path: str):
     try:
         with open(path) as f:
             for line in f:
-                if line.startswith("TRAFFIC_JSON "):
+                if line.startswith("TRAFFIC_JSON {"):
                     doc = json.loads(line[len("TRAFFIC_JSON "):])
                     return doc if doc.get("source_hash") == kernel_source_hash() else None
     except OSError:
