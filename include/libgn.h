@@ -286,6 +286,38 @@ gn_status gn_adam_step(float* params, const float* grad, float* m, float* v, int
                        float beta2, float eps, int32_t t, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Multi-start: several starting points of one graph iterated together (the
+ * batched starts of the paper's PyTorch module, code appendix; the experiments of
+ * Section 6 run 16 random starts per instance and keep the best).
+ * ------------------------------------------------------------------------- */
+
+#define GN_MAX_STARTS 16
+
+/* Solve `starts` (1..GN_MAX_STARTS) independent GN runs of g at once.  x: device
+ * float[starts*n], start-major (start b occupies x[b*n .. b*n+n-1], user order):
+ * the starting points on entry, the final states (clamped to [0,1]) on exit; sel:
+ * device uint8[starts*n], same layout, (x > 1/2).  res: host gn_result[starts],
+ * one per start.  *best (host): the start with the largest set objective among
+ * the binarised ones (lowest index on ties; among all starts if none binarised).
+ * Every start stops on its own by the stopping rule of gn_solve, and its result
+ * is bit-identical to gn_solve from the same starting point (same arithmetic in
+ * the same order); the call returns when every start has stopped.  Random
+ * starting points are the caller's (the module draws -log U normalised by its
+ * maximum and clamped to [1e-3, 1]).  Errors as gn_solve (any start's x0 invalid
+ * or not normalizable fails the call).  Returns GN_OK when every start
+ * binarised, else GN_NOT_CONVERGED.  SYNC. */
+gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t starts, float* x, uint8_t* sel,
+                         gn_result* res, int32_t* best, hipStream_t stream);
+
+/* Random starting points of the paper's module (code appendix): for each start,
+ * x = clamp(e / max(e), 1e-3, 1) with e = -log(u), the maximum taken over that
+ * start's n values (the module normalises over the whole batch; per start is
+ * this library's reading).  u: device float[starts*n] start-major, every value in
+ * (0, 1] (GN_E_ARG otherwise); x: device float[starts*n], ready for
+ * gn_multi_solve.  e is computed with the device logf.  SYNC. */
+gn_status gn_random_starts(gn_graph* g, int32_t starts, const float* u, float* x, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Assignment problem: matrix cross-normalization (Section 2).
  *
  * The graph is the line graph of the complete bipartite graph K_{rows,cols}:

@@ -258,3 +258,20 @@ def solve_batch(ns, row_ptr_cat, col_idx_cat, w_cat, x0_cat, **sched) -> list[So
         co += nnz
         vo += n
     return out
+
+
+def random_start(u) -> np.ndarray:
+    """Random starting point of the paper's module (code appendix), one start:
+    e = -log(u) for u in (0, 1], normalised by its maximum and clamped to
+    [1e-3, 1]; all ones when every e is zero.  fp64."""
+    e = -np.log(np.asarray(u, dtype=np.float64))
+    e = np.maximum(e, 0.0)
+    m = e.max() if e.size else 0.0
+    if m <= 0.0:
+        return np.ones_like(e)
+    return np.clip(e / m, 1e-3, 1.0)
+
+
+def multi_solve(n, row_ptr, col_idx, w, x0s, **sched) -> list[SolveResult]:
+    """Independent solves from several starting points (rows of x0s), one by one."""
+    return [solve(n, row_ptr, col_idx, w, x0, **sched) for x0 in np.atleast_2d(np.asarray(x0s, dtype=np.float64))]

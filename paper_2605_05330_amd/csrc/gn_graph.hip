@@ -159,6 +159,7 @@ extern "C" void gn_graph_destroy(gn_graph* g) {
     (void)hipSetDevice(g->device);
     (void)hipDeviceSynchronize();
     gn_internal_free_unrolled(g);
+    gn_internal_free_multi(g);
     free_graph_buffers(g);
     delete g;
     (void)hipSetDevice(cur);

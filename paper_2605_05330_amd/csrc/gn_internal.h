@@ -129,6 +129,7 @@ struct gn_graph {
     int32_t bin_count_rows[BIN_COUNT] = {0};
     mutable GraphWorkspace ws;   // work buffers; calls on one handle must not overlap
     mutable void* unrolled = nullptr;  // adjoint work buffers (gn_unrolled.hip)
+    mutable void* multi = nullptr;     // multi-start work buffers (gn_multi.hip)
 };
 
 // Final statistics reduced on the device (fixed-order, deterministic).
@@ -166,3 +167,4 @@ gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool 
                                   gn_result* res);
 gn_status gn_internal_ensure_tables(GraphWorkspace& ws, int32_t steps_needed);
 void gn_internal_free_unrolled(gn_graph* g);
+void gn_internal_free_multi(gn_graph* g);

@@ -1,0 +1,670 @@
+// Multi-start GN: up to 16 starting points of one graph iterated together (the
+// batched starts of the paper's PyTorch module, code appendix; 16 starts per
+// instance in the experiments of Section 6).
+//
+// The 16 states are interleaved, Y[i*16 + b] for vertex i (internal order) and
+// start b, so the gather of one neighbour reads 64 contiguous bytes that serve
+// every start: the column stream and the gathered cache lines of one step are
+// shared by all starts.  Each start's neighbour sum follows the canonical order
+// of gn_rowsum.h and its update the arithmetic of the single-start step, so every
+// start is bit-identical to gn_solve from the same x0.  Each start has its own
+// stopping test and stops on its own: once start b passes at step k_b, its lanes
+// stop writing and its final state stays in the buffer of step k_b.
+//
+// A lane handles a quad of starts (16-byte loads; 4 lanes cover a vertex's 64
+// bytes).  Rows (internal order):
+//   heavy  deg > 128 : one workgroup per row; neighbour values of all starts are
+//                      staged through LDS in chunks of 512 entries, thread
+//                      (t, q) = (tid / 4, tid % 4) runs chain t
+//   mid    deg <= 128: one wavefront per row, 16 threads per quad (4 chains each)
+//   light  deg <= 32 : 16 rows per wavefront, one thread per (row, quad); rows of
+//                      degree <= 16 and <= 32 in separate blocks
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gn_internal.h"
+#include "gn_rowsum.h"
+
+using gnk::sign_of;
+
+namespace {
+
+constexpr int kStarts = 16;
+constexpr int kChunk = 512;  // heavy rows: entries staged per round
+
+struct MultiArgs {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const float* v;
+    const float* y_in;       // [n][16] signed weighted states
+    float* y_out;
+    const float* gamma;      // gamma table indexed by step
+    int32_t k;
+    SolveState* st;          // err, max_steps, check_every, tau; done_step >= 0 once every start has stopped
+    int32_t* done;           // [16] per-start done step (-1 while running)
+    int32_t* notconv;        // [(steps) * 16] per-step, per-start test flags
+    unsigned long long* fb;  // [16] fallback counts
+    int32_t n, heavy_end, mid_end;   // rows [0, heavy_end) heavy, [heavy_end, mid_end) mid, [mid_end, n) light
+    int32_t l16_begin;               // light rows of degree <= 16 start here
+    int32_t mid_blk, light_blk;      // first block of the mid and light parts
+    int32_t l16_blk;                 // light blocks before the degree <= 16 rows
+};
+
+// Lanes work on quads of starts: lane l handles starts 4q .. 4q+3 with q = l % 4
+// and moves them with one 16-byte load, so 4 lanes cover a vertex's 64 bytes.
+struct QuadCtl {
+    float g = 0.0f, tau = 0.0f;
+    bool do_test = false, do_write = false;
+    unsigned act = 0u;  // bit j: start 4q + j runs this step
+};
+
+// Control of this lane's quad at this launch.  Returns false when no start is
+// active (the launch does no work; uniform over the grid).  Block 0 records
+// newly stopped starts and, once none is left, the solve's stop.
+__device__ __forceinline__ bool quad_ctl(const MultiArgs& a, int q, QuadCtl& c) {
+    const SolveState* st = a.st;
+    const int err = st->err, ms = st->max_steps, ce = st->check_every;
+    const int k = a.k, km = k >= 1 ? k - 1 : 0;
+    const int4 done = reinterpret_cast<const int4*>(a.done)[q];
+    const int4 nc = reinterpret_cast<const int4*>(a.notconv + (size_t)km * kStarts)[q];
+    c.tau = st->tau;
+    c.g = a.gamma[k];
+    const int dv[4] = {done.x, done.y, done.z, done.w};
+    const int nv[4] = {nc.x, nc.y, nc.z, nc.w};
+    const bool check = k >= 2 && (km % ce == 0 || km == ms);
+    unsigned act = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        bool aj = !(k > ms || err) && dv[j] < 0;
+        if (aj && check && nv[j] == 0) {
+            aj = false;
+            if (blockIdx.x == 0) a.done[4 * q + j] = km;
+        }
+        act |= aj ? 1u << j : 0u;
+    }
+    c.act = act;
+    c.do_test = k >= 1 && (k % ce == 0 || k == ms);
+    c.do_write = k < ms;
+    if (__ballot(act != 0u) == 0ull) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.st->done_step = km;
+        return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ float comp(const float4& v, int j) { return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w; }
+__device__ __forceinline__ float4 abs4(const float4& v) { return make_float4(fabsf(v.x), fabsf(v.y), fabsf(v.z), fabsf(v.w)); }
+__device__ __forceinline__ float4 add4(const float4& a, const float4& b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ unsigned signs4(const float4& v) {
+    return sign_of(v.x) | (sign_of(v.y) << 1) | (sign_of(v.z) << 2) | (sign_of(v.w) << 3);
+}
+__device__ __forceinline__ float4 shfl4(const float4& v, int off) {
+    return make_float4(__shfl_xor(v.x, off, 64), __shfl_xor(v.y, off, 64), __shfl_xor(v.z, off, 64),
+                       __shfl_xor(v.w, off, 64));
+}
+
+// Epilogue of (row i, quad q): the arithmetic of the single-start step for each
+// active start; returns the quad's violation bits.  A stopped start keeps the
+// value already in y_out's slot (its final state may live there).
+__device__ __forceinline__ unsigned quad_update(const MultiArgs& a, const QuadCtl& c, int i, int q,
+                                                const float4& yraw, float vi, const float4& sigma, unsigned nbr_sel,
+                                                unsigned (&fb)[4]) {
+    unsigned viol = 0u;
+    float out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float yr = comp(yraw, j);
+        const float yi = fabsf(yr);
+        const float s = __fmaf_rn(c.g, comp(sigma, j), yi);
+        const bool fallback = !(s > 1e-9f);
+        const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
+        const float yn = vi * xn;
+        out[j] = xn > 0.5f ? -yn : yn;
+        const bool on = (c.act >> j) & 1u;
+        if (on && c.do_write) fb[j] += fallback ? 1u : 0u;
+        if (on && c.do_test) {
+            const bool in_s = sign_of(yr) != 0u;
+            const float tv = c.tau * vi;
+            const bool far = (yi > tv) && ((vi - yi) > tv);
+            const bool uncovered = !in_s && !((nbr_sel >> j) & 1u);
+            const bool growing = !in_s && (yi > 0.0f) && !(s > vi);
+            viol |= (far || uncovered || growing) ? 1u << j : 0u;
+        }
+    }
+    if (c.do_write) {
+        float* dst = a.y_out + (size_t)i * kStarts + 4 * q;
+        if (c.act == 0xFu) {
+            *reinterpret_cast<float4*>(dst) = make_float4(out[0], out[1], out[2], out[3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((c.act >> j) & 1u) dst[j] = out[j];
+        }
+    }
+    return viol;
+}
+
+// Violation bits of the 16 starts over a wavefront: bit 4q + j from lanes
+// l = q (mod 4) with bit j set.
+__device__ __forceinline__ unsigned wave_start_bits(unsigned v4) {
+    unsigned bits = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const unsigned long long m = __ballot((v4 >> j) & 1u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (m & (0x1111111111111111ull << q)) bits |= 1u << (4 * q + j);
+    }
+    return bits;
+}
+
+// Light rows: 16 rows per wavefront, lane (r, q) = (l / 4, l % 4) runs the whole
+// canonical sum of its row for 4 starts (G = 1: stage 16 pairs entries e and
+// e + 16, then the in-thread butterfly 8 .. 1).
+template <int MAXD>
+__device__ __forceinline__ unsigned light_rows(const MultiArgs& a, QuadCtl& c, int rb, int re, int lb, int wave,
+                                               int lane, unsigned (&fb)[4], bool& quit) {
+    const int q = lane & 3;
+    const int i = rb + (lb * kWaves + wave) * 16 + (lane >> 2);
+    const bool valid = i < re;
+    const float4* __restrict__ Y4 = reinterpret_cast<const float4*>(a.y_in);
+    int start = 0, d = 0;
+    float4 yraw = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float vi = 1.0f;
+    if (valid) {
+        start = gnk::ld_stream(a.row_ptr + i);
+        d = gnk::ld_stream(a.row_ptr + i + 1) - start;
+        yraw = Y4[(size_t)i * 4 + q];
+        vi = a.v[i];
+    }
+    int idx[MAXD];
+#pragma unroll
+    for (int p = 0; p < MAXD; ++p) idx[p] = p < d ? a.col[start + p] : -1;
+    if (!quad_ctl(a, q, c)) {
+        quit = true;
+        return 0u;
+    }
+    unsigned sel = 0u;
+    float4 cs[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        float4 v = idx[p] >= 0 ? Y4[(size_t)idx[p] * 4 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        sel |= signs4(v);
+        cs[p] = abs4(v);
+        if constexpr (MAXD > 16) {
+            const float4 w = idx[p + 16] >= 0 ? Y4[(size_t)idx[p + 16] * 4 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            sel |= signs4(w);
+            cs[p] = add4(cs[p], abs4(w));
+        }
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < off; ++j) cs[j] = add4(cs[j], cs[j + off]);
+    if (!valid) return 0u;
+    return quad_update(a, c, i, q, yraw, vi, cs[0], sel, fb);
+}
+
+__global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
+    __shared__ float4 stage[kChunk][kStarts / 4];
+    __shared__ float4 red[kBlock];
+    __shared__ unsigned s_mask[kWaves];
+    __shared__ unsigned s_sel[kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = tid & 3;
+    const int blk = blockIdx.x;
+    QuadCtl c;
+    unsigned viol = 0u;
+    unsigned fb[4] = {0u, 0u, 0u, 0u};
+
+    if (blk < a.mid_blk) {
+        // heavy row: thread (t, q) = (tid / 4, tid % 4) runs chain t for 4 starts
+        const int i = blk;
+        const int t = tid >> 2;
+        const int start = gnk::ld_stream(a.row_ptr + i);
+        const int d = gnk::ld_stream(a.row_ptr + i + 1) - start;
+        const float4 yraw = reinterpret_cast<const float4*>(a.y_in)[(size_t)i * 4 + q];
+        const float vi = a.v[i];
+        if (!quad_ctl(a, q, c)) return;
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        unsigned sel = 0u;
+        for (int c0 = 0; c0 < d; c0 += kChunk) {
+            const int cn = min(kChunk, d - c0);
+#pragma unroll
+            for (int u = 0; u < kChunk / kBlock; ++u) {
+                const int e = tid + kBlock * u;
+                if (e < cn) {
+                    const float4* src =
+                        reinterpret_cast<const float4*>(a.y_in + (size_t)a.col[start + c0 + e] * kStarts);
+#pragma unroll
+                    for (int h = 0; h < kStarts / 4; ++h) stage[e][h] = src[h];
+                }
+            }
+            __syncthreads();
+            for (int e = t; e < cn; e += 64) {
+                const float4 v = stage[e][q];
+                sel |= signs4(v);
+                acc = add4(acc, abs4(v));
+            }
+            __syncthreads();
+        }
+        // butterfly over the 64 chains: stages 32 and 16 across wavefronts (LDS),
+        // stages 8 .. 1 inside the wavefront (lane bits 5 .. 2)
+        red[tid] = acc;
+        __syncthreads();
+        acc = add4(acc, red[tid ^ 128]);
+        __syncthreads();
+        red[tid] = acc;
+        __syncthreads();
+        acc = add4(acc, red[tid ^ 64]);
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) acc = add4(acc, shfl4(acc, off * 4));
+        const unsigned ws = wave_start_bits(sel);
+        if (lane == 0) s_sel[wave] = ws;
+        __syncthreads();
+        const unsigned all = s_sel[0] | s_sel[1] | s_sel[2] | s_sel[3];
+        if (tid < 4) viol = quad_update(a, c, i, q, yraw, vi, acc, (all >> (4 * q)) & 0xFu, fb);
+    } else if (blk < a.light_blk) {
+        // mid row: one wavefront, lane (t, q) = (l / 4, l % 4) runs chains t, t+16,
+        // t+32, t+48 (two entries each) for 4 starts
+        const int i = a.heavy_end + (blk - a.mid_blk) * kWaves + wave;
+        const int t = lane >> 2;
+        const bool valid = i < a.mid_end;
+        const float4* __restrict__ Y4 = reinterpret_cast<const float4*>(a.y_in);
+        int start = 0, d = 0;
+        float4 yraw = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float vi = 1.0f;
+        if (valid) {
+            start = gnk::ld_stream(a.row_ptr + i);
+            d = gnk::ld_stream(a.row_ptr + i + 1) - start;
+            yraw = Y4[(size_t)i * 4 + q];
+            vi = a.v[i];
+        }
+        int idx[2][4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int p = t + 16 * jj + 64 * m;
+                idx[m][jj] = p < d ? a.col[start + p] : -1;
+            }
+        if (!quad_ctl(a, q, c)) return;
+        unsigned sel = 0u;
+        float4 ch[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) ch[jj] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if (idx[m][jj] >= 0) {
+                    const float4 v = Y4[(size_t)idx[m][jj] * 4 + q];
+                    sel |= signs4(v);
+                    ch[jj] = add4(ch[jj], abs4(v));
+                }
+        ch[0] = add4(ch[0], ch[2]);
+        ch[1] = add4(ch[1], ch[3]);
+        float4 s = add4(ch[0], ch[1]);
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) s = add4(s, shfl4(s, off * 4));
+        // neighbour selection: OR over the 16 lanes of this quad
+        unsigned any = 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned long long m = __ballot((sel >> j) & 1u);
+            any |= (m & (0x1111111111111111ull << q)) ? 1u << j : 0u;
+        }
+        if (valid && t == 0) viol = quad_update(a, c, i, q, yraw, vi, s, any, fb);
+    } else {
+        bool quit = false;
+        const int lb = blk - a.light_blk;
+        if (lb < a.l16_blk) {
+            viol = light_rows<32>(a, c, a.mid_end, a.l16_begin, lb, wave, lane, fb, quit);
+        } else {
+            viol = light_rows<16>(a, c, a.l16_begin, a.n, lb - a.l16_blk, wave, lane, fb, quit);
+        }
+        if (quit) return;  // uniform over the grid
+    }
+
+    // per-start test flags: one LDS slot per wavefront, one barrier, at most 16
+    // global writes per block; fallbacks are rare and counted directly
+    const unsigned wm = wave_start_bits(viol);
+    if (lane == 0) s_mask[wave] = wm;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (fb[j]) atomicAdd(&a.fb[4 * q + j], (unsigned long long)fb[j]);
+    __syncthreads();
+    if (tid < kStarts) {
+        const unsigned mm = s_mask[0] | s_mask[1] | s_mask[2] | s_mask[3];
+        if ((mm >> tid) & 1u) a.notconv[(size_t)a.k * kStarts + tid] = 1;
+    }
+}
+
+// Reset per-start state: starts >= count are stopped from the outset.
+__global__ void multi_init_kernel(int32_t count, int32_t* done, unsigned long long* fb, int32_t* notconv,
+                                  int32_t entries) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kStarts) {
+        done[t] = t < count ? -1 : 0;
+        fb[t] = 0ull;
+    }
+    for (int e = t; e < entries; e += gridDim.x * blockDim.x) notconv[e] = 0;
+}
+
+// x (start-major, user order) -> interleaved signed weighted states; flags
+// negative or non-finite entries (err bit 1).
+__global__ void multi_prep_kernel(int32_t n, int32_t count, const float* __restrict__ x_user,
+                                  const int32_t* __restrict__ perm, const float* __restrict__ v,
+                                  float* __restrict__ y, SolveState* st) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * kStarts) return;
+    const int i = (int)(e / kStarts), b = (int)(e % kStarts);
+    float yy = 0.0f;
+    if (b < count) {
+        float x = x_user[(size_t)b * n + perm[i]];
+        if (!(x >= 0.0f) || !isfinite(x)) {
+            atomicOr(&st->err, 1);
+            x = 0.0f;
+        }
+        yy = v[i] * x;
+        yy = x > 0.5f ? -yy : yy;
+    }
+    y[e] = yy;
+}
+
+// Normalizable (Section 2) for every start: some positive entry in each closed
+// neighbourhood; err bit 2 otherwise.
+__global__ void multi_normalizable_kernel(int32_t n, int32_t count, const int32_t* __restrict__ row_ptr,
+                                          const int32_t* __restrict__ col, const float* __restrict__ y,
+                                          SolveState* st) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * kStarts) return;
+    const int i = (int)(e / kStarts), b = (int)(e % kStarts);
+    if (b >= count || y[e] != 0.0f) return;
+    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
+        if (y[(size_t)col[q] * kStarts + b] != 0.0f) return;
+    atomicOr(&st->err, 2);
+}
+
+// start b's state out of the interleaved buffer
+__global__ void multi_extract_kernel(int32_t n, int32_t b, const float* __restrict__ y, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = y[(size_t)i * kStarts + b];
+}
+
+// Random starting points (code appendix): x = clamp(e / max(e), 1e-3, 1) with
+// e = -log(u), the maximum taken over each start's n values.  Non-negative floats
+// order like their bit patterns, so the maximum is an exact integer atomicMax.
+__global__ void random_max_kernel(int64_t total, int32_t n, const float* __restrict__ u,
+                                  unsigned* __restrict__ maxbits, SolveState* st) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float uu = u[e];
+        if (!(uu > 0.0f && uu <= 1.0f)) {
+            atomicOr(&st->err, 1);
+            continue;
+        }
+        const float l = -logf(uu);
+        atomicMax(&maxbits[e / n], __float_as_uint(l > 0.0f ? l : 0.0f));
+    }
+}
+
+__global__ void random_apply_kernel(int64_t total, int32_t n, const float* __restrict__ u,
+                                    const unsigned* __restrict__ maxbits, float* __restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float uu = u[e];
+        const float mx = __uint_as_float(maxbits[e / n]);
+        float l = (uu > 0.0f && uu <= 1.0f) ? -logf(uu) : 0.0f;
+        l = l > 0.0f ? l : 0.0f;
+        const float r = mx > 0.0f ? l / mx : 1.0f;
+        x[e] = fminf(fmaxf(r, 1e-3f), 1.0f);
+    }
+}
+
+__global__ void clear_kernel(unsigned* p, int32_t count, SolveState* st) {
+    const int t = threadIdx.x;
+    if (t < count) p[t] = 0u;
+    if (t == 0) st->err = 0;
+}
+
+struct MultiWS {
+    GraphWorkspace ws;       // state, gamma table, pinned staging, captured chains
+    unsigned* maxbits = nullptr;  // [16] random starts: per-start maxima
+    float* Y[2] = {nullptr, nullptr};
+    float* yb = nullptr;     // one start's state, contiguous
+    int32_t* done = nullptr;
+    unsigned long long* fb = nullptr;
+    int32_t* nc16 = nullptr;
+    int32_t nc16_cap = 0;    // steps covered by nc16
+    int32_t heavy_end = 0, mid_end = 0, l16_begin = 0, mid_blk = 0, light_blk = 0, l16_blk = 0, nblk = 0;
+};
+
+void free_ws(MultiWS* m) {
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+    m->ws.chunks.clear();
+    f(m->Y[0]); f(m->Y[1]); f(m->yb); f(m->done); f(m->fb); f(m->nc16); f(m->maxbits);
+    f(m->ws.state); f(m->ws.notconv); f(m->ws.gamma);
+    if (m->ws.host_pinned) (void)hipHostFree(m->ws.host_pinned);
+    delete m;
+}
+
+MultiWS* get_ws(gn_graph* g) {
+    if (g->multi) return (MultiWS*)g->multi;
+    MultiWS* m = new (std::nothrow) MultiWS();
+    if (!m) return nullptr;
+    const size_t n = (size_t)std::max(g->n, 1);
+    bool ok = hipMalloc(&m->Y[0], n * kStarts * 4) == hipSuccess &&
+              hipMalloc(&m->Y[1], n * kStarts * 4) == hipSuccess && hipMalloc(&m->yb, n * 4) == hipSuccess &&
+              hipMalloc(&m->done, kStarts * 4) == hipSuccess && hipMalloc(&m->fb, kStarts * 8) == hipSuccess &&
+              hipMalloc(&m->maxbits, kStarts * 4) == hipSuccess &&
+              hipMalloc(&m->ws.state, sizeof(SolveState)) == hipSuccess &&
+              hipHostMalloc(&m->ws.host_pinned, 4096, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_ws(m);
+        return nullptr;
+    }
+    const BinLayout& bl = g->bins;
+    m->heavy_end = bl.row_begin[BIN_G8];
+    m->mid_end = bl.row_begin[BIN_LANE32];
+    m->l16_begin = bl.row_begin[BIN_LANE16];
+    m->mid_blk = m->heavy_end;
+    m->light_blk = m->mid_blk + (m->mid_end - m->heavy_end + kWaves - 1) / kWaves;
+    constexpr int rows_per_block = 16 * kWaves;
+    m->l16_blk = (m->l16_begin - m->mid_end + rows_per_block - 1) / rows_per_block;
+    m->nblk = m->light_blk + m->l16_blk + (g->n - m->l16_begin + rows_per_block - 1) / rows_per_block;
+    g->multi = m;
+    return m;
+}
+
+gn_status ensure_tables(MultiWS* m, int32_t steps) {
+    gn_status st = gn_internal_ensure_tables(m->ws, steps);  // gamma (and single-start flags, unused)
+    if (st != GN_OK) return st;
+    if (steps > m->nc16_cap) {
+        const int32_t cap = std::max(steps, 2 * m->nc16_cap);
+        if (m->nc16) (void)hipFree(m->nc16);
+        m->nc16 = nullptr;
+        m->nc16_cap = 0;
+        if (hipMalloc(&m->nc16, (size_t)cap * kStarts * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            return GN_E_NOMEM;
+        }
+        m->nc16_cap = cap;
+        for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        m->ws.chunks.clear();
+    }
+    return GN_OK;
+}
+
+gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, hipGraphExec_t* out) {
+    hipGraph_t graph;
+    GN_HIP_TRY(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (int32_t q = 0; q < len; ++q) {
+        MultiArgs a{};
+        a.row_ptr = g->row_ptr;
+        a.col = g->col;
+        a.v = g->v;
+        a.k = c * len + q;
+        a.y_in = m->Y[a.k & 1];
+        a.y_out = m->Y[(a.k + 1) & 1];
+        a.gamma = m->ws.gamma;
+        a.st = m->ws.state;
+        a.done = m->done;
+        a.notconv = m->nc16;
+        a.fb = m->fb;
+        a.n = g->n;
+        a.heavy_end = m->heavy_end;
+        a.mid_end = m->mid_end;
+        a.l16_begin = m->l16_begin;
+        a.mid_blk = m->mid_blk;
+        a.light_blk = m->light_blk;
+        a.l16_blk = m->l16_blk;
+        void* args[] = {&a};
+        hipKernelNodeParams p{};
+        p.func = (void*)multi_step_kernel;
+        p.gridDim = dim3(m->nblk);
+        p.blockDim = dim3(kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return GN_E_HIP;
+        }
+        prev = node;
+    }
+    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e == hipSuccess ? GN_OK : GN_E_HIP;
+}
+
+}  // namespace
+
+void gn_internal_free_multi(gn_graph* g) {
+    if (g->multi) free_ws((MultiWS*)g->multi);
+    g->multi = nullptr;
+}
+
+extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t starts, float* x, uint8_t* sel,
+                                    gn_result* res, int32_t* best, hipStream_t stream) {
+    if (!g || !sch || !res || !best || starts < 1 || starts > GN_MAX_STARTS) return GN_E_ARG;
+    if (!gn_internal_schedule_ok(sch)) return GN_E_ARG;
+    std::memset(res, 0, sizeof(gn_result) * (size_t)starts);
+    *best = -1;
+    if (g->n == 0) {
+        for (int b = 0; b < starts; ++b) {
+            res[b].binarised = 1;
+            res[b].stab = INFINITY;
+        }
+        *best = 0;
+        return GN_OK;
+    }
+    if (!x || !sel) return GN_E_ARG;
+    gn_status st = gn_internal_ensure_ws(g, 1);  // the single-start buffers serve the final statistics
+    if (st != GN_OK) return st;
+    MultiWS* m = get_ws(g);
+    if (!m) return GN_E_NOMEM;
+    const int32_t ms = sch->max_steps;
+    const int32_t C = g_chunk_len;
+    const int32_t nchunks = (ms + 1 + C - 1) / C;
+    if ((st = ensure_tables(m, nchunks * C)) != GN_OK) return st;
+    const int n = g->n;
+
+    if ((st = gn_internal_init_solve(m->ws, sch, stream)) != GN_OK) return st;
+    const int32_t entries = nchunks * C * kStarts;
+    hipLaunchKernelGGL(multi_init_kernel, dim3(std::min((entries + 255) / 256, 1024)), dim3(256), 0, stream, starts,
+                       m->done, m->fb, m->nc16, entries);
+    GN_HIP_TRY(hipGetLastError());
+    const int64_t cells = (int64_t)n * kStarts;
+    const int cblocks = (int)((cells + 255) / 256);
+    hipLaunchKernelGGL(multi_prep_kernel, dim3(cblocks), dim3(256), 0, stream, n, starts, (const float*)x, g->perm,
+                       g->v, m->Y[0], m->ws.state);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(multi_normalizable_kernel, dim3(cblocks), dim3(256), 0, stream, n, starts, g->row_ptr, g->col,
+                       (const float*)m->Y[0], m->ws.state);
+    GN_HIP_TRY(hipGetLastError());
+
+    st = gn_internal_run_chunks(
+        m->ws, nchunks, C, [g, m, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, m, c, C, out); },
+        stream);
+    if (st != GN_OK) return st;
+
+    SolveState hs;
+    int32_t done[kStarts];
+    unsigned long long fbh[kStarts];
+    std::vector<int32_t> nc_last(kStarts, 1);
+    GN_HIP_TRY(hipMemcpy(&hs, m->ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    GN_HIP_TRY(hipMemcpy(done, m->done, sizeof(done), hipMemcpyDeviceToHost));
+    GN_HIP_TRY(hipMemcpy(fbh, m->fb, sizeof(fbh), hipMemcpyDeviceToHost));
+    GN_HIP_TRY(hipMemcpy(nc_last.data(), m->nc16 + (size_t)ms * kStarts, kStarts * 4, hipMemcpyDeviceToHost));
+    if (hs.err & 1) return GN_E_ARG;
+    if (hs.err & 2) return GN_E_NOT_NORMALIZABLE;
+
+    bool all_bin = true;
+    double best_w = -INFINITY;
+    int best_any = -1;
+    double best_any_w = -INFINITY;
+    for (int b = 0; b < starts; ++b) {
+        const bool bin = done[b] >= 0 || (ms >= 1 && nc_last[b] == 0);
+        const int32_t steps = done[b] >= 0 ? done[b] : ms;
+        hipLaunchKernelGGL(multi_extract_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, b,
+                           (const float*)m->Y[steps & 1], m->yb);
+        GN_HIP_TRY(hipGetLastError());
+        FinalStats fs{};
+        st = gn_internal_final_stats(g, m->yb, gn_internal_host_gamma(sch, steps), x + (size_t)b * n,
+                                     sel + (size_t)b * n, &fs, stream);
+        if (st != GN_OK) return st;
+        gn_result& r = res[b];
+        r.steps = steps;
+        r.binarised = bin ? 1 : 0;
+        r.fallback_count = (int64_t)fbh[b];
+        r.relaxed_objective = fs.relaxed_objective;
+        r.set_objective = fs.set_objective;
+        r.set_size = fs.set_size;
+        r.conflicts = fs.conflicts;
+        r.uncovered = fs.uncovered;
+        r.stab = fs.stab;
+        all_bin = all_bin && bin;
+        if (bin && fs.set_objective > best_w) {
+            best_w = fs.set_objective;
+            *best = b;
+        }
+        if (fs.set_objective > best_any_w) {
+            best_any_w = fs.set_objective;
+            best_any = b;
+        }
+    }
+    if (*best < 0) *best = best_any;
+    return all_bin ? GN_OK : GN_NOT_CONVERGED;
+}
+
+extern "C" gn_status gn_random_starts(gn_graph* g, int32_t starts, const float* u, float* x, hipStream_t stream) {
+    if (!g || starts < 1 || starts > GN_MAX_STARTS) return GN_E_ARG;
+    if (g->n == 0) return GN_OK;
+    if (!u || !x) return GN_E_ARG;
+    MultiWS* m = get_ws(g);
+    if (!m) return GN_E_NOMEM;
+    const int64_t total = (int64_t)starts * g->n;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, stream, m->maxbits, kStarts, m->ws.state);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(random_max_kernel, dim3(blocks), dim3(256), 0, stream, total, g->n, u, m->maxbits,
+                       m->ws.state);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(random_apply_kernel, dim3(blocks), dim3(256), 0, stream, total, g->n, u,
+                       (const unsigned*)m->maxbits, x);
+    GN_HIP_TRY(hipGetLastError());
+    int32_t err = 0;
+    GN_HIP_TRY(hipMemcpyAsync(m->ws.host_pinned, &m->ws.state->err, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    std::memcpy(&err, m->ws.host_pinned, sizeof(err));
+    return err ? GN_E_ARG : GN_OK;
+}

@@ -84,6 +84,9 @@ def lib():
             "gn_mpnn_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
             "gn_adam_step": ([_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_int32, _vp], ctypes.c_int),
+            "gn_multi_solve": ([_vp, ctypes.POINTER(gn_schedule), ctypes.c_int32, _vp, _vp, _vp,
+                                ctypes.POINTER(ctypes.c_int32), _vp], ctypes.c_int),
+            "gn_random_starts": ([_vp, ctypes.c_int32, _vp, _vp, _vp], ctypes.c_int),
             "gn_rook_create": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
                                ctypes.c_int),
             "gn_rook_destroy": ([_vp], None),
@@ -265,11 +268,40 @@ class Graph:
     def solve(self, x, sel, stream=None, **sched) -> Result:
         return gn_solve(self.handle, make_schedule(**sched), x, sel, stream)
 
+    def random_starts(self, starts, u, x, stream=None):
+        gn_random_starts(self.handle, starts, u, x, stream)
+
+    def multi_solve(self, starts, x, sel, stream=None, **sched):
+        """`starts` runs at once; x, sel start-major [starts * n]."""
+        return gn_multi_solve(self.handle, make_schedule(**sched), starts, x, sel, stream)
+
     def objective(self, x, stream=None) -> float:
         return gn_objective(self.handle, x, stream)
 
     def check(self, sel, stream=None):
         return gn_check_independent(self.handle, sel, stream)
+
+
+GN_MAX_STARTS = 16
+
+
+def gn_multi_solve(h, schedule: gn_schedule, starts: int, x, sel, stream=None) -> tuple[int, list[Result], int]:
+    """x: CUDA float32 [starts * n] start-major (in: starting points, out: final
+    states); sel: CUDA uint8 [starts * n].  Returns (status, per-start results, best)."""
+    import torch
+    res = (gn_result * int(starts))()
+    best = ctypes.c_int32(-1)
+    st = lib().gn_multi_solve(h, ctypes.byref(schedule), int(starts), _dptr(x, torch.float32, "x"),
+                              _dptr(sel, torch.uint8, "sel"), res, ctypes.byref(best), _stream(stream))
+    _check(st, "gn_multi_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return st, [_result(res[b], st) for b in range(int(starts))], best.value
+
+
+def gn_random_starts(h, starts: int, u, x, stream=None):
+    """x = clamp(-log u / max(-log u), 1e-3, 1) per start; u, x CUDA float32 [starts * n]."""
+    import torch
+    _check(lib().gn_random_starts(h, int(starts), _dptr(u, torch.float32, "u"), _dptr(x, torch.float32, "x"),
+                                  _stream(stream)), "gn_random_starts")
 
 
 def gn_rook_create(rows, cols, w, stream=None):

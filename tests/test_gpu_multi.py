@@ -1,0 +1,169 @@
+"""Multi-start GN through the C-ABI: every start is bit-identical to gn_solve from
+the same starting point (same arithmetic, same summation order), and the random
+starting points match the oracle's transform of the same uniforms."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_05330_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+RAMP = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4, check_every=1)
+
+
+def _lib():
+    from paper_2605_05330_amd import libgn
+    return libgn
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _uniforms(starts, n, seed):
+    return (1.0 - I.rng_for(seed, 41).random(starts * n)).astype(F32)  # in (0, 1]
+
+
+def _random_x0(G, starts, n, seed):
+    import torch
+    u = dev(_uniforms(starts, n, seed))
+    x = torch.empty_like(u)
+    G.random_starts(starts, u, x)
+    torch.cuda.synchronize()
+    return u, x
+
+
+def _multi_vs_single(g, w, starts, x0, sched):
+    """Run the multi-start solve and gn_solve per start; every field must agree exactly."""
+    import torch
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    x = x0.clone()
+    sel = torch.zeros(starts * g.n, dtype=torch.uint8, device="cuda")
+    st, res, best = G.multi_solve(starts, x, sel, **sched)
+    xs, ss = x.cpu().numpy().reshape(starts, g.n), sel.cpu().numpy().reshape(starts, g.n)
+    for b in range(starts):
+        xb = x0[b * g.n:(b + 1) * g.n].clone()
+        sb = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        r = G.solve(xb, sb, **sched)
+        assert res[b].steps == r.steps and res[b].binarised == r.binarised, (b, res[b].steps, r.steps)
+        assert np.array_equal(xs[b].view(np.uint32), xb.cpu().numpy().view(np.uint32)), b
+        assert np.array_equal(ss[b], sb.cpu().numpy()), b
+        assert res[b].set_objective == r.set_objective and res[b].relaxed_objective == r.relaxed_objective
+        assert res[b].fallback_count == r.fallback_count and res[b].stab == r.stab
+        assert res[b].conflicts == r.conflicts and res[b].uncovered == r.uncovered
+    objs = [r.set_objective if r.binarised else -np.inf for r in res]
+    if not any(r.binarised for r in res):
+        objs = [r.set_objective for r in res]
+    assert best == int(np.argmax(objs))
+    return res, best
+
+
+def test_random_starts_match_oracle(gpu):
+    g = I.erdos_renyi(3000, 6 / 2999, 2)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 2))
+    u, x = _random_x0(G, 16, g.n, 5)
+    un, xn = u.cpu().numpy().reshape(16, g.n), x.cpu().numpy().reshape(16, g.n)
+    for b in range(16):
+        ref = O.random_start(un[b].astype(np.float64))
+        np.testing.assert_allclose(xn[b], ref, rtol=1e-5, atol=0)
+        assert xn[b].max() == 1.0
+
+
+def test_multi_all_row_classes_bitexact(gpu):
+    """Heavy (workgroup per row, several LDS chunks), mid and light rows; 16 random
+    starts against 16 single solves."""
+    g = I.hub_graph(6000, [40, 100, 200, 600, 1500], 4.0, 3)
+    w = I.weights_uniform01(g.n, 3)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    _, x0 = _random_x0(G, 16, g.n, 6)
+    res, best = _multi_vs_single(g, w, 16, x0, RAMP)
+    assert all(r.binarised for r in res)
+
+
+@pytest.mark.parametrize("starts", [1, 5])
+def test_multi_fewer_starts_bitexact(gpu, starts):
+    g = I.unit_disk(4000, 10, 4)
+    w = I.weights_uniform01(g.n, 4)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    _, x0 = _random_x0(G, starts, g.n, 7)
+    x0[:g.n] = 0.5  # start 0 is the uniform start of plain GN
+    _multi_vs_single(g, w, starts, x0, RAMP)
+
+
+def test_multi_budget_exhausted_bitexact(gpu):
+    """max_steps reached before binarisation: every start reports max_steps and the
+    state after exactly that many steps."""
+    g = I.erdos_renyi(2000, 8 / 1999, 8)
+    w = I.weights_uniform01(g.n, 8)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    _, x0 = _random_x0(G, 16, g.n, 8)
+    res, _ = _multi_vs_single(g, w, 16, x0, dict(RAMP, max_steps=60))
+    assert all(r.steps == 60 and not r.binarised for r in res)
+
+
+def test_multi_matches_oracle(gpu):
+    g = I.erdos_renyi(1000, 8 / 999, 9)
+    w = I.weights_uniform01(g.n, 9)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    import torch
+    starts = 4
+    u, x0 = _random_x0(G, starts, g.n, 9)
+    x0n = x0.cpu().numpy().reshape(starts, g.n).astype(np.float64)
+    x = x0.clone()
+    sel = torch.zeros(starts * g.n, dtype=torch.uint8, device="cuda")
+    st, res, best = G.multi_solve(starts, x, sel, **RAMP)
+    osch = dict(RAMP, gamma0=float(F32(0.9)), tau=float(F32(1e-4)))
+    refs = O.multi_solve(g.n, g.row_ptr, g.col_idx, w.astype(np.float64), x0n, **osch)
+    ss = sel.cpu().numpy().reshape(starts, g.n).astype(bool)
+    for b in range(starts):
+        assert res[b].binarised and refs[b].binarised
+        assert abs(res[b].steps - refs[b].steps) <= 2, (b, res[b].steps, refs[b].steps)
+        assert np.array_equal(ss[b], refs[b].sel), b
+        assert res[b].set_objective == pytest.approx(refs[b].set_objective, rel=1e-12)
+
+
+def test_multi_ba200k_16_starts(gpu):
+    """The at-scale graph with the paper's 16 random starts: two starts checked
+    bit for bit against gn_solve, all binarised and independent."""
+    import torch
+    g = I.barabasi_albert(200_000, 5, 0)
+    w = I.weights_uniform01(g.n, 0)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    _, x0 = _random_x0(G, 16, g.n, 10)
+    x = x0.clone()
+    sel = torch.zeros(16 * g.n, dtype=torch.uint8, device="cuda")
+    st, res, best = G.multi_solve(16, x, sel, **RAMP)
+    assert all(r.binarised and r.conflicts == 0 and r.uncovered == 0 for r in res)
+    xs = x.cpu().numpy().reshape(16, g.n)
+    for b in (0, 15):
+        xb = x0[b * g.n:(b + 1) * g.n].clone()
+        sb = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        r = G.solve(xb, sb, **RAMP)
+        assert r.steps == res[b].steps and np.array_equal(xs[b], xb.cpu().numpy())
+
+
+def test_multi_errors(gpu):
+    import torch
+    libgn = _lib()
+    g = I.erdos_renyi(500, 6 / 499, 1)
+    w = I.weights_uniform01(g.n, 1)
+    G = libgn.Graph(g.n, g.row_ptr, g.col_idx, w)
+    x = torch.full((17 * g.n,), 0.5, device="cuda")
+    sel = torch.zeros(17 * g.n, dtype=torch.uint8, device="cuda")
+    for bad in (0, 17):
+        with pytest.raises(libgn.GNError) as e:
+            G.multi_solve(bad, x, sel, **RAMP)
+        assert e.value.status == libgn.GN_E_ARG
+    u = torch.full((2 * g.n,), 0.5, device="cuda")
+    u[7] = 0.0
+    with pytest.raises(libgn.GNError) as e:
+        G.random_starts(2, u, torch.empty_like(u))
+    assert e.value.status == libgn.GN_E_ARG
+    x2 = torch.full((3 * g.n,), 0.5, device="cuda")
+    x2[2 * g.n:] = 0.0  # start 2 is all zero: not normalizable
+    with pytest.raises(libgn.GNError) as e:
+        G.multi_solve(3, x2, sel, **RAMP)
+    assert e.value.status == libgn.GN_E_NOT_NORMALIZABLE

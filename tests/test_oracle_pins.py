@@ -480,3 +480,23 @@ def test_frozen_vertex_regrows_to_stable_set():
     r2 = O.solve(1500, g.row_ptr, g.col_idx, w, r.x, gamma0=1.5, gamma1=1.5, ramp_steps=1, max_steps=2000,
                  tau=0.0)
     assert np.array_equal(r2.sel, r.sel)
+
+
+def test_random_start_by_hand():
+    """u = exp(-k): e = k, so x = k / k_max clamped to [1e-3, 1]; u = 1 gives e = 0,
+    clamped up to 1e-3; the largest draw maps to exactly 1."""
+    k = np.array([0.0, 0.5, 1.0, 2.0, 4.0, 1e-4])
+    x = O.random_start(np.exp(-k))
+    np.testing.assert_allclose(x, [1e-3, 0.125, 0.25, 0.5, 1.0, 1e-3], rtol=1e-12)
+    assert x[4] == 1.0
+    assert np.array_equal(O.random_start(np.ones(5)), np.ones(5))
+
+
+def test_random_start_is_scale_free_draw():
+    """-log U with U uniform is Exp(1): the mean of e over many draws is 1 (within 1%),
+    and the normalised start is a point of (0, 1] with one coordinate at 1."""
+    u = 1.0 - I.rng_for(3, 40).random(200_000)
+    e = -np.log(u)
+    assert abs(e.mean() - 1.0) < 0.01
+    x = O.random_start(u)
+    assert x.max() == 1.0 and x.min() >= 1e-3
