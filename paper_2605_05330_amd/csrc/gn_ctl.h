@@ -5,7 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "gn_internal.h"
+#include "gn_types.h"
 
 namespace {
 

@@ -1,0 +1,290 @@
+// Solve driver of the graph solver and the pieces it shares with the assignment
+// and multi-start solvers: state preparation, the normalizable check, the gamma
+// table, captured chains of step launches replayed with a pipelined host check,
+// the stopping outcome and the result record.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "gn_internal.h"
+
+// defined in gn_step.hip
+__global__ void wrgn_step_kernel(StepArgs a);
+
+// x (user order) -> signed weighted state y (internal order); flags x < 0 or
+// non-finite (err bit 1).
+__global__ void prep_state_kernel(int32_t n, const float* __restrict__ x_user, const int32_t* __restrict__ perm,
+                                  const float* __restrict__ v, float* __restrict__ y, SolveState* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x = x_user[perm[i]];
+    if (!(x >= 0.0f) || !isfinite(x)) {
+        if (st) atomicOr(&st->err, 1);
+        x = 0.0f;
+    }
+    const float yy = v[i] * x;
+    y[i] = x > 0.5f ? -yy : yy;
+}
+
+// Normalizable (Section 2): (A + I) x > 0, i.e. x_i > 0 or some neighbour
+// x_j > 0.  Flags err bit 2 otherwise.
+__global__ void normalizable_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                    const float* __restrict__ x_user, const int32_t* __restrict__ perm,
+                                    SolveState* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (x_user[perm[i]] > 0.0f) return;
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+        if (x_user[perm[col[e]]] > 0.0f) return;
+    atomicOr(&st->err, 2);
+}
+
+// Reset the solve state and fill the gamma table (Section 6 gamma-pursuit,
+// evaluated in double and rounded once to fp32).
+__global__ void init_solve_kernel(SolveState* st, int32_t* notconv, float* gamma, int32_t max_steps,
+                                  int32_t check_every, float tau, float g0, float g1, int32_t ramp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        st->done_step = -1;
+        st->err = 0;
+        st->max_steps = max_steps;
+        st->check_every = check_every;
+        st->tau = tau;
+        st->pad = 0;
+        st->fallback = 0ull;
+    }
+    for (int k = t; k <= max_steps; k += gridDim.x * blockDim.x) {
+        notconv[k] = 0;
+        double gk;
+        if (ramp <= 1) {
+            gk = (double)g1;
+        } else {
+            const int kk = k < ramp - 1 ? k : ramp - 1;
+            const double p = (double)kk / (double)(ramp - 1);
+            gk = p * (double)g1 + (1.0 - p) * (double)g0;
+        }
+        gamma[k] = (float)gk;
+    }
+}
+
+float gn_internal_host_gamma(const gn_schedule* s, int32_t k) {
+    if (s->ramp_steps <= 1) return s->gamma1;
+    const int32_t kk = k < s->ramp_steps - 1 ? k : s->ramp_steps - 1;
+    const double p = (double)kk / (double)(s->ramp_steps - 1);
+    return (float)(p * (double)s->gamma1 + (1.0 - p) * (double)s->gamma0);
+}
+
+bool gn_internal_schedule_ok(const gn_schedule* sch) {
+    return sch->max_steps >= 0 && sch->check_every >= 1 && sch->tau >= 0.0f && std::isfinite(sch->tau) &&
+           std::isfinite(sch->gamma0) && std::isfinite(sch->gamma1) && sch->gamma0 >= 0.0f && sch->gamma1 >= 0.0f &&
+           sch->max_steps <= (1 << 28);
+}
+
+gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream) {
+    const int32_t ms = sch->max_steps;
+    hipLaunchKernelGGL(init_solve_kernel, dim3(std::min((ms + 1 + 255) / 256, 1024)), dim3(256), 0, stream, ws.state,
+                       ws.notconv, ws.gamma, ms, sch->check_every, sch->tau, sch->gamma0, sch->gamma1,
+                       sch->ramp_steps);
+    GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
+}
+
+gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
+                                 const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
+                                 hipStream_t stream) {
+    if (ws.chunk_len != C) {
+        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        ws.chunks.clear();
+        ws.chunk_len = C;
+    }
+    if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
+    volatile int32_t* pin = (volatile int32_t*)ws.host_pinned;  // [slot][done_step, err]
+    hipEvent_t ev[2];
+    GN_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return GN_E_HIP;
+    }
+    gn_status rs = GN_OK;
+    for (int32_t c = 0; c < nchunks && rs == GN_OK; ++c) {
+        if (!ws.chunks[c]) {
+            rs = build(c, &ws.chunks[c]);
+            if (rs != GN_OK) break;
+        }
+        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess ||
+            hipMemcpyAsync((void*)(pin + 2 * (c & 1)), ws.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess ||
+            hipEventRecord(ev[c & 1], stream) != hipSuccess) {
+            rs = GN_E_HIP;
+            break;
+        }
+        if (c >= 1) {
+            const int p = (c - 1) & 1;
+            if (hipEventSynchronize(ev[p]) != hipSuccess) {
+                rs = GN_E_HIP;
+                break;
+            }
+            if (pin[2 * p] >= 0 || pin[2 * p + 1] != 0) break;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rs != GN_OK) return rs;
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    return GN_OK;
+}
+
+gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_t* steps, bool* binarised) {
+    SolveState hs;
+    int32_t nc_last = 1;
+    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    GN_HIP_TRY(hipMemcpy(&nc_last, ws.notconv + ms, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (hs.err & 1) return GN_E_ARG;
+    if (hs.err & 2) return GN_E_NOT_NORMALIZABLE;
+    if (hs.done_step >= 0) {
+        *steps = hs.done_step;
+        *binarised = true;
+    } else {
+        *steps = ms;
+        *binarised = ms >= 1 && nc_last == 0;
+    }
+    return GN_OK;
+}
+
+gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
+                                  gn_result* res) {
+    SolveState hs;
+    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    res->steps = steps;
+    res->binarised = binarised ? 1 : 0;
+    res->fallback_count = (int64_t)hs.fallback;
+    res->relaxed_objective = fs.relaxed_objective;
+    res->set_objective = fs.set_objective;
+    res->set_size = fs.set_size;
+    res->conflicts = fs.conflicts;
+    res->uncovered = fs.uncovered;
+    res->stab = fs.stab;
+    return binarised ? GN_OK : GN_NOT_CONVERGED;
+}
+
+static StepArgs base_args(const gn_graph* g) {
+    StepArgs a{};
+    a.row_ptr = g->row_ptr;
+    a.col = g->col;
+    a.v = g->v;
+    a.perm = g->perm;
+    a.sl_col = g->sl_col;
+    a.sl_off = g->sl_off;
+    a.bins = g->bins;
+    return a;
+}
+
+extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, float* x_out,
+                             hipStream_t stream) {
+    if (!g) return GN_E_ARG;
+    if (!std::isfinite(gamma) || gamma < 0.0f) return GN_E_ARG;
+    if (g->n == 0) return GN_OK;
+    if (!x_in || !x_out || x_in == x_out) return GN_E_ARG;
+    gn_graph* gm = const_cast<gn_graph*>(g);
+    gn_status st = gn_internal_ensure_ws(gm, 1);
+    if (st != GN_OK) return st;
+    const int n = g->n;
+    hipLaunchKernelGGL(prep_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, x_in, g->perm, g->v,
+                       g->ws.y[0], (SolveState*)nullptr);
+    GN_HIP_TRY(hipGetLastError());
+    StepArgs a = base_args(g);
+    a.y_in = g->ws.y[0];
+    a.y_out = nullptr;
+    a.gamma = nullptr;
+    a.gamma_scalar = gamma;
+    a.solve = 0;
+    a.x_out_user = x_out;
+    return gn_internal_launch_step(g, a, stream);
+}
+
+// Captured chain of `len` step launches for steps [c*len, (c+1)*len).
+static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t* out) {
+    GraphWorkspace& ws = g->ws;
+    hipGraph_t graph;
+    GN_HIP_TRY(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    const int nblk = gn_internal_grid_blocks(g->bins);
+    for (int32_t j = 0; j < len; ++j) {
+        StepArgs a = base_args(g);
+        a.k = c * len + j;
+        a.y_in = ws.y[a.k & 1];
+        a.y_out = ws.y[(a.k + 1) & 1];
+        a.gamma = ws.gamma;
+        a.solve = 1;
+        a.st = ws.state;
+        a.notconv = ws.notconv;
+        a.x_out_user = nullptr;
+        void* args[] = {&a};
+        hipKernelNodeParams p{};
+        p.func = (void*)wrgn_step_kernel;
+        p.gridDim = dim3(nblk);
+        p.blockDim = dim3(kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return GN_E_HIP;
+        }
+        prev = node;
+    }
+    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e == hipSuccess ? GN_OK : GN_E_HIP;
+}
+
+int32_t g_chunk_len = 32;
+
+extern "C" gn_status gn_set_chunk_len(int32_t len);
+gn_status gn_set_chunk_len(int32_t len) {
+    if (len < 1 || len > 4096) return GN_E_ARG;
+    g_chunk_len = len;
+    return GN_OK;
+}
+
+extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                              hipStream_t stream) {
+    if (!g || !sch || !res) return GN_E_ARG;
+    if (!gn_internal_schedule_ok(sch)) return GN_E_ARG;
+    std::memset(res, 0, sizeof(*res));
+    if (g->n == 0) {
+        res->binarised = 1;
+        res->stab = INFINITY;
+        return GN_OK;
+    }
+    if (!x || !sel) return GN_E_ARG;
+    const int32_t ms = sch->max_steps;
+    const int32_t C = g_chunk_len;
+    const int32_t nchunks = (ms + 1 + C - 1) / C;
+    gn_status st = gn_internal_ensure_ws(g, nchunks * C);
+    if (st != GN_OK) return st;
+    GraphWorkspace& ws = g->ws;
+    const int n = g->n;
+
+    if ((st = gn_internal_init_solve(ws, sch, stream)) != GN_OK) return st;
+    hipLaunchKernelGGL(prep_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, (const float*)x, g->perm,
+                       g->v, ws.y[0], ws.state);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(normalizable_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, g->row_ptr, g->col,
+                       (const float*)x, g->perm, ws.state);
+    GN_HIP_TRY(hipGetLastError());
+
+    st = gn_internal_run_chunks(ws, nchunks, C,
+                                [g, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, out); }, stream);
+    if (st != GN_OK) return st;
+    int32_t steps;
+    bool binarised;
+    if ((st = gn_internal_solve_outcome(ws, ms, &steps, &binarised)) != GN_OK) return st;
+    FinalStats fs{};
+    st = gn_internal_final_stats(g, ws.y[steps & 1], gn_internal_host_gamma(sch, steps), x, sel, &fs, stream);
+    if (st != GN_OK) return st;
+    return gn_internal_fill_result(ws, steps, binarised, fs, res);
+}

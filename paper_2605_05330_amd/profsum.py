@@ -31,7 +31,7 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 64 * 1024 * 1024
 STEP_KERNEL = "wrgn_step_kernel"
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-STEP_SOURCES = ("gn_step.hip", "gn_rowsum.h", "gn_internal.h")
+STEP_SOURCES = ("gn_step.hip", "gn_rowsum.h", "gn_ctl.h", "gn_types.h")
 
 
 def kernel_source_hash() -> str:
