@@ -119,7 +119,7 @@ void gn_graph_destroy(gn_graph* g);
 
 /* Diagnostics: n, nnz, max degree and the number of rows in each degree bin
  * (bin_rows may be NULL; else GN_NUM_BINS entries, lightest first: one thread
- * per row (deg <= 16), one thread per row (deg <= 32), 8 threads per row
+ * per row (deg <= 16), 2 threads per row (deg <= 32), 8 threads per row
  * (deg <= 128), one wavefront per row (deg <= 512), one workgroup per row with
  * LDS staging (deg > 512), then unused zeros).  Host only. */
 gn_status gn_graph_info(const gn_graph* g, int32_t* n, int64_t* nnz, int32_t* max_degree,
@@ -164,8 +164,8 @@ gn_status gn_check_independent(const gn_graph* g, const uint8_t* sel, int64_t* c
 /* Launch shape of the batched kernel, chosen by gn_batch_autotune.  It changes
  * speed only, never results. */
 typedef struct {
-    int32_t block_threads;   /* threads per workgroup: 128, 256 or 512                      */
-    int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1 .. 4               */
+    int32_t block_threads;   /* threads per workgroup: 128, 256, 512 or 1024                 */
+    int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1 .. 4 (1 .. 2 with 1024) */
     int32_t lds_vertices;    /* graphs with n <= lds_vertices keep y and v in LDS            */
     int32_t reserved;
 } gn_tuning;

@@ -23,7 +23,7 @@ using gnk::sign_of;
 
 namespace {
 
-constexpr int kLightMaxDeg = 32;  // rows up to this degree run one per thread
+constexpr int kLightMaxDeg = 16;  // rows up to this degree run one per thread
 constexpr int kLdsBudget = 160 * 1024 - 2048;  // dynamic LDS per CU (static LDS of the kernel set aside)
 
 struct BatchDesc {
@@ -92,6 +92,7 @@ __device__ double block_sum_d(double x, double* sm) {
     if (lane == 0) sm[wave] = x;
     __syncthreads();
     double r = 0.0;
+#pragma unroll 1
     for (int w = 0; w < BT / 64; ++w) r += sm[w];
     return r;
 }
@@ -104,6 +105,7 @@ __device__ long long block_sum_ll(long long x, long long* sm) {
     if (lane == 0) sm[wave] = x;
     __syncthreads();
     long long r = 0;
+#pragma unroll 1
     for (int w = 0; w < BT / 64; ++w) r += sm[w];
     return r;
 }
@@ -116,6 +118,7 @@ __device__ float block_min_f(float x, float* sm) {
     if (lane == 0) sm[wave] = x;
     __syncthreads();
     float r = INFINITY;
+#pragma unroll 1
     for (int w = 0; w < BT / 64; ++w) r = fminf(r, sm[w]);
     return r;
 }
@@ -157,6 +160,7 @@ __device__ void solve_graph(const BatchArgs& a, int gi, float* lds) {
         const bool do_write = k < a.max_steps;
         const float g = a.gamma[k];
         bool viol = false;
+#pragma unroll 1
         for (int i = tid; i < d.n_light; i += BT) {
             const int s0 = gnk::ld_stream(rp + i);
             const int dd = gnk::ld_stream(rp + i + 1) - s0;
@@ -164,6 +168,7 @@ __device__ void solve_graph(const BatchArgs& a, int gi, float* lds) {
             const float sigma = gnk::row_sum<1, kLightMaxDeg>(col + s0, dd, yin, 0, sel);
             viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
         }
+#pragma unroll 1
         for (int i = d.n_light + wave; i < n; i += BT / 64) {
             const int s0 = gnk::ld_stream(rp + i);
             const int dd = gnk::ld_stream(rp + i + 1) - s0;
@@ -538,8 +543,10 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
 }
 
 static bool tuning_valid(const gn_tuning& t) {
-    return (t.block_threads == 128 || t.block_threads == 256 || t.block_threads == 512) && t.blocks_per_cu >= 1 &&
-           t.blocks_per_cu <= 4 && t.lds_vertices >= 0 && (size_t)t.lds_vertices * 12 * t.blocks_per_cu <= kLdsBudget;
+    const bool bt_ok = t.block_threads == 128 || t.block_threads == 256 || t.block_threads == 512 ||
+                       (t.block_threads == 1024 && t.blocks_per_cu <= 2);
+    return bt_ok && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 4 && t.lds_vertices >= 0 &&
+           (size_t)t.lds_vertices * 12 * t.blocks_per_cu <= kLdsBudget;
 }
 
 static gn_tuning default_tuning(const gn_batch* b) {
@@ -601,13 +608,18 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
         e = launch_batch<128>(dim3(blocks), lds, s, a);
     else if (t.block_threads == 512)
         e = launch_batch<512>(dim3(blocks), lds, s, a);
+    else if (t.block_threads == 1024)
+        e = launch_batch<1024>(dim3(blocks), lds, s, a);
     else
         e = launch_batch<256>(dim3(blocks), lds, s, a);
     return e == hipSuccess ? GN_OK : GN_E_HIP;
 }
 
 static void allow_lds(int bt, size_t bytes) {
-    const void* f = bt == 128 ? batch_kernel_ptr<128>() : bt == 512 ? batch_kernel_ptr<512>() : batch_kernel_ptr<256>();
+    const void* f = bt == 128    ? batch_kernel_ptr<128>()
+                    : bt == 512  ? batch_kernel_ptr<512>()
+                    : bt == 1024 ? batch_kernel_ptr<1024>()
+                                 : batch_kernel_ptr<256>();
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -680,7 +692,7 @@ extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_t
     gn_tuning best = default_tuning(b);
     float best_ms = INFINITY;
     st = GN_OK;
-    for (int bt : {128, 256, 512}) {
+    for (int bt : {128, 256, 512, 1024}) {
         for (int bpc : {1, 2, 4}) {
             gn_tuning t{};
             t.block_threads = bt;

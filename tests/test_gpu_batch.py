@@ -94,8 +94,9 @@ def test_batch_results_independent_of_tuning(gpu):
     B = lg.Batch.from_graphs(gs, ws)
     base = _run_batch(B, gs)
     t = B.autotune(**SCHED)
-    assert t.block_threads in (128, 256, 512) and 1 <= t.blocks_per_cu <= 4
-    shapes = [t, lg.gn_tuning(128, 1, 3000, 0), lg.gn_tuning(512, 2, 3000, 0),
+    assert t.block_threads in (128, 256, 512, 1024) and 1 <= t.blocks_per_cu <= 4
+    shapes = [t, lg.gn_tuning(128, 1, 3000, 0), lg.gn_tuning(512, 2, 3000, 0), lg.gn_tuning(1024, 1, 5000, 0),
+              lg.gn_tuning(1024, 2, 100, 0),
               lg.gn_tuning(256, 4, 100, 0),   # most graphs take the global-memory state path
               lg.gn_tuning(256, 2, 0, 0)]     # every graph on the global-memory path
     for tu in shapes:
