@@ -14,11 +14,12 @@
 // A lane handles a quad of starts (16-byte loads; 4 lanes cover a vertex's 64
 // bytes).  Rows (internal order):
 //   heavy  deg > 128 : one workgroup per row; neighbour values of all starts are
-//                      staged through LDS in chunks of 512 entries, thread
+//                      staged through LDS in chunks of 256 entries, thread
 //                      (t, q) = (tid / 4, tid % 4) runs chain t
 //   mid    deg <= 128: one wavefront per row, 16 threads per quad (4 chains each)
-//   light  deg <= 32 : 16 rows per wavefront, one thread per (row, quad); rows of
-//                      degree <= 16 and <= 32 in separate blocks
+//   light  deg <= 32 : rows of degree <= 16: 16 rows per wavefront, one thread per
+//                      (row, quad); degree 17..32: 8 rows per wavefront, two
+//                      threads per (row, quad)
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -32,7 +33,7 @@ using gnk::sign_of;
 namespace {
 
 constexpr int kStarts = 16;
-constexpr int kChunk = 512;  // heavy rows: entries staged per round
+constexpr int kChunk = 256;  // heavy rows: entries staged per round
 
 struct MultiArgs {
     const int32_t* row_ptr;
@@ -162,11 +163,10 @@ __device__ __forceinline__ unsigned wave_start_bits(unsigned v4) {
     return bits;
 }
 
-// Light rows: 16 rows per wavefront, lane (r, q) = (l / 4, l % 4) runs the whole
-// canonical sum of its row for 4 starts (G = 1: stage 16 pairs entries e and
-// e + 16, then the in-thread butterfly 8 .. 1).
-template <int MAXD>
-__device__ __forceinline__ unsigned light_rows(const MultiArgs& a, QuadCtl& c, int rb, int re, int lb, int wave,
+// Light rows of degree <= 16: 16 rows per wavefront, lane (r, q) = (l / 4, l % 4)
+// runs the whole canonical sum of its row for 4 starts (G = 1: the in-thread
+// butterfly 8 .. 1 over the 16 entries).
+__device__ __forceinline__ unsigned light_rows16(const MultiArgs& a, QuadCtl& c, int rb, int re, int lb, int wave,
                                                int lane, unsigned (&fb)[4], bool& quit) {
     const int q = lane & 3;
     const int i = rb + (lb * kWaves + wave) * 16 + (lane >> 2);
@@ -181,9 +181,9 @@ __device__ __forceinline__ unsigned light_rows(const MultiArgs& a, QuadCtl& c, i
         yraw = Y4[(size_t)i * 4 + q];
         vi = a.v[i];
     }
-    int idx[MAXD];
+    int idx[16];
 #pragma unroll
-    for (int p = 0; p < MAXD; ++p) idx[p] = p < d ? a.col[start + p] : -1;
+    for (int p = 0; p < 16; ++p) idx[p] = p < d ? a.col[start + p] : -1;
     if (!quad_ctl(a, q, c)) {
         quit = true;
         return 0u;
@@ -195,11 +195,6 @@ __device__ __forceinline__ unsigned light_rows(const MultiArgs& a, QuadCtl& c, i
         float4 v = idx[p] >= 0 ? Y4[(size_t)idx[p] * 4 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         sel |= signs4(v);
         cs[p] = abs4(v);
-        if constexpr (MAXD > 16) {
-            const float4 w = idx[p + 16] >= 0 ? Y4[(size_t)idx[p + 16] * 4 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            sel |= signs4(w);
-            cs[p] = add4(cs[p], abs4(w));
-        }
     }
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1)
@@ -207,6 +202,50 @@ __device__ __forceinline__ unsigned light_rows(const MultiArgs& a, QuadCtl& c, i
         for (int j = 0; j < off; ++j) cs[j] = add4(cs[j], cs[j + off]);
     if (!valid) return 0u;
     return quad_update(a, c, i, q, yraw, vi, cs[0], sel, fb);
+}
+
+// Light rows of degree 17..32: 8 rows per wavefront, lane (r, t, q) =
+// (l / 8, (l / 4) % 2, l % 4); the two threads t of a (row, quad) own chains t,
+// t+2, .. t+30 (G = 2), fold them in-thread (stages 16 .. 2) and finish with the
+// shuffle between t = 0 and t = 1 (stage 1, lane xor 4).
+__device__ __forceinline__ unsigned light_rows_g2(const MultiArgs& a, QuadCtl& c, int rb, int re, int lb, int wave,
+                                                  int lane, unsigned (&fb)[4], bool& quit) {
+    const int q = lane & 3, t = (lane >> 2) & 1;
+    const int i = rb + (lb * kWaves + wave) * 8 + (lane >> 3);
+    const bool valid = i < re;
+    const float4* __restrict__ Y4 = reinterpret_cast<const float4*>(a.y_in);
+    int start = 0, d = 0;
+    float4 yraw = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float vi = 1.0f;
+    if (valid) {
+        start = gnk::ld_stream(a.row_ptr + i);
+        d = gnk::ld_stream(a.row_ptr + i + 1) - start;
+        yraw = Y4[(size_t)i * 4 + q];
+        vi = a.v[i];
+    }
+    int idx[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) idx[j] = t + 2 * j < d ? a.col[start + t + 2 * j] : -1;
+    if (!quad_ctl(a, q, c)) {
+        quit = true;
+        return 0u;
+    }
+    unsigned sel = 0u;
+    float4 cs[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const float4 v = idx[j] >= 0 ? Y4[(size_t)idx[j] * 4 + q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        sel |= signs4(v);
+        cs[j] = abs4(v);
+    }
+#pragma unroll
+    for (int off = 16; off >= 2; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < off / 2; ++j) cs[j] = add4(cs[j], cs[j + off / 2]);
+    const float4 s = add4(cs[0], shfl4(cs[0], 4));
+    sel |= __shfl_xor(sel, 4, 64);
+    if (!valid || t != 0) return 0u;
+    return quad_update(a, c, i, q, yraw, vi, s, sel, fb);
 }
 
 __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
@@ -323,9 +362,9 @@ __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
         bool quit = false;
         const int lb = blk - a.light_blk;
         if (lb < a.l16_blk) {
-            viol = light_rows<32>(a, c, a.mid_end, a.l16_begin, lb, wave, lane, fb, quit);
+            viol = light_rows_g2(a, c, a.mid_end, a.l16_begin, lb, wave, lane, fb, quit);
         } else {
-            viol = light_rows<16>(a, c, a.l16_begin, a.n, lb - a.l16_blk, wave, lane, fb, quit);
+            viol = light_rows16(a, c, a.l16_begin, a.n, lb - a.l16_blk, wave, lane, fb, quit);
         }
         if (quit) return;  // uniform over the grid
     }
@@ -476,9 +515,9 @@ MultiWS* get_ws(gn_graph* g) {
     m->l16_begin = bl.row_begin[BIN_LANE16];
     m->mid_blk = m->heavy_end;
     m->light_blk = m->mid_blk + (m->mid_end - m->heavy_end + kWaves - 1) / kWaves;
-    constexpr int rows_per_block = 16 * kWaves;
-    m->l16_blk = (m->l16_begin - m->mid_end + rows_per_block - 1) / rows_per_block;
-    m->nblk = m->light_blk + m->l16_blk + (g->n - m->l16_begin + rows_per_block - 1) / rows_per_block;
+    constexpr int rows32 = 8 * kWaves, rows16 = 16 * kWaves;  // rows per block of the two light classes
+    m->l16_blk = (m->l16_begin - m->mid_end + rows32 - 1) / rows32;
+    m->nblk = m->light_blk + m->l16_blk + (g->n - m->l16_begin + rows16 - 1) / rows16;
     g->multi = m;
     return m;
 }
