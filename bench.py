@@ -154,9 +154,24 @@ def bench_multistart(G, g, sched, reps, plain_res):
         G.solve(xb, sb, **sched)
         torch.cuda.synchronize()
         seq += time.perf_counter() - t1
+    # one 16-start step at fixed gamma: tau = 0 never passes, so exactly 500 launches
+    x.copy_(x0)
+    fixed = dict(gamma0=1.2, gamma1=1.2, ramp_steps=1, max_steps=500, tau=0.0, check_every=1)
+    G.multi_solve(S, x, sel, **fixed)
+    x.copy_(x0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    G.multi_solve(S, x, sel, **fixed)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t2) / 500
+    # algorithmic bytes of a 16-start step: CSR once, the 64-byte state rows read
+    # and written, v
+    b_multi = 4 * (g.n + 1) + 4 * g.nnz + 64 * g.n + 64 * g.n + 4 * g.n
     edges = g.nnz // 2
     total_steps = sum(r.steps for r in res)
     return {"starts": S, "time_to_binary_ms": ms, "all_binarised": all(r.binarised for r in res),
+            "step_us": step_s * 1e6, "step_bytes": b_multi, "step_GBs": b_multi / step_s / 1e9,
+            "step_frac": b_multi / step_s / 1e9 / HBM_PEAK_GBS,
             "steps_mean": total_steps / S, "steps_max": max(r.steps for r in res),
             "edges_iters_per_s": edges * total_steps / (ms / 1e3),
             "best_start": best, "best_set_objective": res[best].set_objective,
@@ -197,6 +212,8 @@ def bench_batch(sched, reps):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     edge_iters = sum((g.nnz // 2) * r.steps for g, r in zip(gs, res))
+    # CSR bytes streamed over all graph-steps (the states live in LDS)
+    csr_bytes = sum((4 * (g.n + 1) + 4 * g.nnz) * r.steps for g, r in zip(gs, res))
     # plain single-graph solves of every 16th graph, scaled to the whole batch
     sample = list(range(0, 4096, 16))
     t_plain = 0.0
@@ -216,6 +233,7 @@ def bench_batch(sched, reps):
     plain_ms = t_plain * 1e3 * (4096 / len(sample))
     return {"graphs": 4096, "vertices": tot, "edges": edges, "time_to_binary_ms": ms,
             "edges_iters_per_s": edge_iters / (ms / 1e3), "all_binarised": st == 0,
+            "csr_stream_GBs": csr_bytes / (ms / 1e3) / 1e9,
             "steps_mean": float(np.mean([r.steps for r in res])), "steps_max": max(r.steps for r in res),
             "total_set_objective": float(sum(r.set_objective for r in res)),
             "tuning": {"block_threads": tun.block_threads, "blocks_per_cu": tun.blocks_per_cu,
@@ -268,6 +286,18 @@ def bench_warm():
                 dt = (time.perf_counter() - ts) * 1e3
             res[name] = (r.steps, r.set_objective, dt, r.binarised)
         rows.append(res)
+    # network inference alone on the last evaluation graph: matrix-core work of
+    # the two layers, 2 n (16*64 + 128*64) flops
+    for _ in range(2):
+        net.predict(G, WS.GATE)
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
+    for _ in range(10):
+        net.predict(G, WS.GATE)
+    torch.cuda.synchronize()
+    infer_ms = (time.perf_counter() - ti) / 10 * 1e3
+    flops = 2.0 * g.n * (16 * 64 + 128 * 64)
+
     def agg(name):
         st = np.mean([r[name][0] for r in rows])
         ms = np.mean([r[name][2] for r in rows])
@@ -277,7 +307,7 @@ def bench_warm():
     out = {"train_graphs": 96, "train_adam_steps": 3000, "train_s": train_s, "final_loss": tr[-1][1],
            "data_s": t1 - t0, "eval_graphs": 32, "n": 100_000,
            "plain_gn": agg("plain"), "plain_gn_400_step_ramp": agg("plain400"), "warm_gated_400_step_ramp": agg("warm"),
-           "gate": WS.GATE}
+           "gate": WS.GATE, "inference_ms": infer_ms, "inference_mfma_TFLOPs": flops / (infer_ms / 1e3) / 1e12}
     out["speedup_vs_plain"] = out["plain_gn"]["time_to_binary_ms"] / out["warm_gated_400_step_ramp"]["time_to_binary_ms"]
     return out
 
@@ -312,8 +342,17 @@ def bench_grad():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5
     nnz = sum(g.nnz for g in gs)
-    return {"graphs": 256, "vertices": int(w0.numel()), "edges": nnz // 2, "T": 50, "ckpt_every": 10,
-            "fwd_bwd_ms": ms, "edges_iters_per_s": (nnz // 2) * 50 * 3 / (ms / 1e3),
+    n = int(w0.numel())
+    T = 50
+    # algorithmic bytes: T forward steps, T recomputed steps that also store y and s,
+    # T adjoint steps (t gathered; y, s, gbar, gv, t' streamed)
+    b_step = step_bytes(n, nnz)
+    b_adj = 4 * (n + 1) + 4 * nnz + 32 * n
+    total = T * b_step + T * (b_step + 8 * n) + T * b_adj
+    return {"graphs": 256, "vertices": n, "edges": nnz // 2, "T": T, "ckpt_every": 10,
+            "fwd_bwd_ms": ms, "edges_iters_per_s": (nnz // 2) * T * 3 / (ms / 1e3),
+            "algorithmic_bytes": total, "GBs": total / (ms / 1e3) / 1e9,
+            "hbm_frac": total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "note": "edge-iterations count forward, recompute and adjoint passes (3 per step)"}
 
 

@@ -37,6 +37,8 @@ struct UnrolledWS {
 struct AdjArgs {
     const int32_t* row_ptr;
     const int32_t* col;
+    const int32_t* sl_col;   // sliced columns of the group bins (see gn_types.h)
+    const int32_t* sl_off;
     const float* v;
     BinLayout bins;
     const float* tt_in;   // t of step k (gathered)
@@ -75,20 +77,25 @@ __device__ __forceinline__ void adj_row(const AdjArgs& a, int i, float sigma) {
     }
 }
 
+// Rows of a sliced bin: one wavefront per slice of 64/G rows, columns from the
+// slice's lines (the layout of the forward step).
 template <int G, int MAXD>
-__device__ __forceinline__ void adj_group_rows(const AdjArgs& a, int rb, int re, int lb) {
-    constexpr int per_block = kBlock / G;
-    const int t = threadIdx.x & (G - 1);
-    const int i = rb + lb * per_block + threadIdx.x / G;
-    const bool valid = i < re;
-    int start = 0, d = 0;
-    if (valid) {
-        start = gnk::ld_stream(a.row_ptr + i);
-        d = gnk::ld_stream(a.row_ptr + i + 1) - start;
-    }
+__device__ __forceinline__ void adj_sliced_rows(const AdjArgs& a, int b, int rb, int re, int lb) {
+    constexpr int RS = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int ls = lb * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = rb + ls * RS;
+    if (r0 >= re) return;
+    const int t = lane & (G - 1);
+    const int i = r0 + lane / G;
+    const int gs = a.bins.slice_begin[b] + ls;
+    const int l0 = a.sl_off[gs];
+    const int width = a.sl_off[gs + 1] - l0;
+    gnk::SlicedIdx<G, MAXD> idx;
+    idx.load(a.sl_col + (size_t)l0 * 64 + lane, width);
     unsigned unused = 0u;
-    const float sigma = gnk::row_sum<G, MAXD, false>(a.col + start, d, a.tt_in, t, unused);
-    if (valid && t == 0) adj_row(a, i, sigma);
+    const float sigma = idx.template sum<false>(a.tt_in, unused);
+    if (i < re && t == 0) adj_row(a, i, sigma);
 }
 
 __global__ __launch_bounds__(kBlock) void wrgn_adjoint_kernel(AdjArgs a) {
@@ -141,11 +148,11 @@ __global__ __launch_bounds__(kBlock) void wrgn_adjoint_kernel(AdjArgs a) {
             if (lane == 1 && hb) adj_row(a, ib, accb);
         }
     } else if (b == BIN_G8) {
-        adj_group_rows<8, 128>(a, rb, re, lb);
+        adj_sliced_rows<8, 128>(a, b, rb, re, lb);
     } else if (b == BIN_LANE32) {
-        adj_group_rows<2, 32>(a, rb, re, lb);
+        adj_sliced_rows<2, 32>(a, b, rb, re, lb);
     } else {
-        adj_group_rows<1, 16>(a, rb, re, lb);
+        adj_sliced_rows<1, 16>(a, b, rb, re, lb);
     }
 }
 
@@ -335,6 +342,8 @@ extern "C" gn_status gn_unrolled_backward(const gn_graph* g, const float* w, con
             AdjArgs a{};
             a.row_ptr = g->row_ptr;
             a.col = g->col;
+            a.sl_col = g->sl_col;
+            a.sl_off = g->sl_off;
             a.v = v;
             a.bins = g->bins;
             a.tt_in = u->tt[tc];
