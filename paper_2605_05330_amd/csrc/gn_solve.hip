@@ -243,8 +243,7 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t
 
 int32_t g_chunk_len = 32;
 
-extern "C" gn_status gn_set_chunk_len(int32_t len);
-gn_status gn_set_chunk_len(int32_t len) {
+extern "C" gn_status gn_set_chunk_len(int32_t len) {
     if (len < 1 || len > 4096) return GN_E_ARG;
     g_chunk_len = len;
     return GN_OK;

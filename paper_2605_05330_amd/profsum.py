@@ -2,6 +2,7 @@
 
     python -m paper_2605_05330_amd.profsum trace DIR [--last N --grid G --kernel K]
     python -m paper_2605_05330_amd.profsum traffic FETCH_DIR WRITE_DIR [--grid G --last N]
+    python -m paper_2605_05330_amd.profsum counters DIR [DIR ...] [--kernel K --grid G --last N]
 
 `trace` reads `*kernel_trace.csv` and prints, per (kernel, grid size), the call
 count and the average / median / minimum duration; with --grid it also prints
@@ -129,6 +130,29 @@ def traffic(fetch_dir: str, write_dir: str, grid: str | None, last: int, kernel:
     return "\n".join(lines)
 
 
+def counters(dirs, kernel: str = STEP_KERNEL, grid: str | None = None, last: int = 1000) -> str:
+    """Mean of every counter over the last `last` dispatches of `kernel` (at grid
+    size `grid`, or its only grid size), from one or more counter runs."""
+    out = ["%-36s %14s %10s" % ("counter", "mean/dispatch", "dispatches")]
+    for d in dirs:
+        rows = _rows(d, "counter_collection.csv")
+        sel = [r for r in rows if r["Kernel_Name"].startswith(kernel)]
+        g = grid
+        if g is None:
+            grids = {r["Grid_Size"] for r in sel}
+            if len(grids) != 1:
+                raise SystemExit("%s ran at grid sizes %s: name one with --grid" % (kernel, sorted(grids)))
+            g = grids.pop()
+        by = collections.defaultdict(list)
+        for r in sel:
+            if r["Grid_Size"] == g:
+                by[r["Counter_Name"]].append(float(r["Counter_Value"]))
+        for name in sorted(by):
+            vals = by[name][-last:]
+            out.append("%-36s %14.1f %10d" % (name, sum(vals) / len(vals), len(vals)))
+    return "\n".join(out)
+
+
 def read_traffic(path: str):
     """The TRAFFIC_JSON record of a committed summary, or None when the file is
     missing or the step kernel's sources changed since the counters were taken."""
@@ -145,7 +169,7 @@ def read_traffic(path: str):
 
 def main():
     p = argparse.ArgumentParser()
-    p.add_argument("mode", choices=("trace", "traffic", "hash"))
+    p.add_argument("mode", choices=("trace", "traffic", "counters", "hash"))
     p.add_argument("dirs", nargs="*")
     p.add_argument("--kernel", default=STEP_KERNEL)
     p.add_argument("--grid", default=None)
@@ -155,6 +179,8 @@ def main():
         print(kernel_source_hash())
     elif a.mode == "trace":
         print(trace(a.dirs[0], a.kernel, a.grid, a.last))
+    elif a.mode == "counters":
+        print(counters(a.dirs, a.kernel, a.grid, a.last))
     else:
         print(traffic(a.dirs[0], a.dirs[1], a.grid, a.last, a.kernel))
 

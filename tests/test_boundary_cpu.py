@@ -107,6 +107,25 @@ def test_null_arguments():
     assert L.gn_objective(None, None, None, None) == libgn.GN_E_ARG
     assert L.gn_check_independent(None, None, None, None, None) == libgn.GN_E_ARG
     L.gn_graph_destroy(None)  # allowed
+    r = ctypes.c_void_p()
+    w = (ctypes.c_float * 4)(1, 1, 1, 1)
+    assert L.gn_rook_create(0, 4, w, 0, None, ctypes.byref(r)) == libgn.GN_E_ARG
+    assert L.gn_rook_create(2, 2, None, 0, None, ctypes.byref(r)) == libgn.GN_E_ARG
+    bad = (ctypes.c_float * 4)(1, 1, -1, 1)
+    assert L.gn_rook_create(2, 2, bad, 0, None, ctypes.byref(r)) == libgn.GN_E_WEIGHT  # host check, no device work
+    assert L.gn_rook_step(None, ctypes.c_float(1.0), None, None, None) == libgn.GN_E_ARG
+    assert L.gn_rook_solve(None, None, None, None, None, None) == libgn.GN_E_ARG
+    L.gn_rook_destroy(None)  # allowed
+    best = ctypes.c_int32()
+    assert L.gn_multi_solve(None, None, 16, None, None, None, ctypes.byref(best), None) == libgn.GN_E_ARG
+    assert L.gn_random_starts(None, 4, None, None, None) == libgn.GN_E_ARG
+
+
+def test_chunk_length_bounds():
+    L = libgn.lib()
+    assert L.gn_set_chunk_len(0) == libgn.GN_E_ARG
+    assert L.gn_set_chunk_len(4097) == libgn.GN_E_ARG
+    assert L.gn_set_chunk_len(32) == libgn.GN_OK
 
 
 def test_product_path_does_not_import_oracle():

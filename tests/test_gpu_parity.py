@@ -316,3 +316,26 @@ def test_repeat_solve_deterministic(gpu):
         outs.append((r, x.cpu(), sel.cpu()))
     assert outs[0][0] == outs[1][0]
     assert torch.equal(outs[0][1], outs[1][1]) and torch.equal(outs[0][2], outs[1][2])
+
+
+def test_solve_independent_of_chain_length(gpu):
+    """The number of step launches per replayed chain changes only how often the
+    host looks at the stop flag: steps, states and sets are identical."""
+    import torch
+    libgn = _lib()
+    g = I.erdos_renyi(3000, 7 / 2999, 21)
+    w = I.weights_uniform01(g.n, 21)
+    G = _graph(g, w)
+    outs = []
+    try:
+        for C in (1, 7, 32, 200):
+            libgn.gn_set_chunk_len(C)
+            x = dev(np.full(g.n, 0.5, F32))
+            sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+            r = G.solve(x, sel, **SCHED_RAMP)
+            outs.append((r.steps, r.fallback_count, x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
+    finally:
+        libgn.gn_set_chunk_len(32)
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1]
+        assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
