@@ -365,6 +365,15 @@ gn_status gn_rook_solve(gn_rook* r, const gn_schedule* sch, float* x, uint8_t* s
  * often from the host; results do not change.  Process-wide; not thread-safe. */
 gn_status gn_set_chunk_len(int32_t len);
 
+/* Tuning: gn_solve runs a graph with nnz + 2 n <= work_max (0 .. 40000, default
+ * 20000) in one workgroup and one launch, with its state and CSR in one compute
+ * unit's LDS (16 n + 4 nnz + 4 bytes, at most about 157 KB) and the steps
+ * separated by workgroup barriers instead of kernel boundaries.  That unit does
+ * all the work, so it pays only for small steps.  Other graphs replay chains of
+ * step launches.  Both paths compute the same bits; 0 disables the one-workgroup
+ * path.  Process-wide; not thread-safe. */
+gn_status gn_set_small_graph_limit(int32_t work_max);
+
 /* Human-readable name of a status code (static string). */
 const char* gn_status_str(gn_status s);
 

@@ -320,6 +320,97 @@ __global__ void batch_check_x0_kernel(int64_t total, const int32_t* __restrict__
     atomicOr(queue + 1, 2);
 }
 
+// One small graph, one workgroup: the whole solve in a single launch, steps
+// separated by workgroup barriers instead of kernel boundaries.  Works on the
+// graph handle's internal arrays: rows [0, light_begin) have degree > 16 and run
+// one wavefront per row, the rest one thread per row; y (ping-pong), v and the CSR
+// live in LDS (16 n + 4 nnz + 4 bytes).  One compute unit does all the work, so
+// this pays only while a step is small (it is bound by that unit's issue rate).  Same arithmetic and canonical sums as the step kernel, so
+// the result is bit-identical to the chained solve.  On entry y0 holds the signed
+// starting state (prep_state_kernel); on exit the final state is in
+// y0 or y1 by the parity of the step count, as after the chained solve.
+template <int BT>
+__global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz, int32_t light_begin,
+                                                         const int32_t* __restrict__ rp_g,
+                                                         const int32_t* __restrict__ col_g,
+                                                         const float* __restrict__ v, const float* __restrict__ gamma,
+                                                         SolveState* st, int32_t* notconv, float* y0, float* y1) {
+    extern __shared__ float lds[];
+    __shared__ int s_fb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (st->err) return;  // x0 rejected by the checks before this launch
+    const int ms = st->max_steps, ce = st->check_every;
+    const float tau = st->tau;
+    float* ya = lds;
+    float* yb = lds + n;
+    float* vv = lds + 2 * n;
+    // the CSR lives in LDS too: a step touches no global memory
+    int32_t* rp = reinterpret_cast<int32_t*>(lds + 3 * n);
+    int32_t* col = rp + (n + 1);
+    for (int i = tid; i < n; i += BT) {
+        ya[i] = y0[i];
+        vv[i] = v[i];
+    }
+    for (int i = tid; i <= n; i += BT) rp[i] = rp_g[i];
+    for (int e = tid; e < nnz; e += BT) col[e] = col_g[e];
+    if (tid == 0) s_fb = 0;
+    __syncthreads();
+    float* yin = ya;
+    float* yout = yb;
+    int fb = 0;
+    int steps = 0;
+    bool binarised = false;
+    float g_next = gamma[0];
+    for (int k = 0;; ++k) {
+        const bool do_test = k >= 1 && (k % ce == 0 || k == ms);
+        const bool do_write = k < ms;
+        // gamma of the next step is loaded one step ahead (the table covers
+        // indices 0 .. max_steps): no global round trip on the step's path
+        const float g = g_next;
+        if (k + 1 <= ms) g_next = gamma[k + 1];
+        bool viol = false;
+#pragma unroll 1
+        for (int i = light_begin + tid; i < n; i += BT) {
+            const int s0 = rp[i];
+            const int dd = rp[i + 1] - s0;
+            unsigned sel = 0u;
+            const float sigma = gnk::row_sum<1, 16>(col + s0, dd, yin, 0, sel);
+            viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, tau, yout, i, fb);
+        }
+#pragma unroll 1
+        for (int i = wave; i < light_begin; i += BT / 64) {
+            const int s0 = rp[i];
+            const int dd = rp[i + 1] - s0;
+            unsigned sel = 0u;
+            const float sigma = gnk::row_sum_wave<8>(col + s0, dd, yin, lane, sel);
+            const bool any_sel = __any(sel != 0u);
+            if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
+        }
+        const int any = __syncthreads_or(viol ? 1 : 0);
+        if (do_test && !any) {
+            binarised = true;
+            steps = k;
+            break;
+        }
+        if (!do_write) {
+            steps = k;
+            break;
+        }
+        float* t = yin;
+        yin = yout;
+        yout = t;
+    }
+    if (fb) atomicAdd(&s_fb, fb);
+    float* dst = (steps & 1) ? y1 : y0;
+    for (int i = tid; i < n; i += BT) dst[i] = yin[i];
+    __syncthreads();
+    if (tid == 0) {
+        st->fallback = (unsigned long long)s_fb;
+        if (binarised) st->done_step = steps;
+        else notconv[ms] = 1;
+    }
+}
+
 template <int BT>
 hipError_t launch_batch(dim3 grid, size_t lds_bytes, hipStream_t s, const BatchArgs& a) {
     hipLaunchKernelGGL(batch_solve_kernel<BT>, grid, dim3(BT), lds_bytes, s, a);
@@ -756,4 +847,23 @@ extern "C" const gn_graph* gn_batch_graph(const gn_batch* bc) {
         return nullptr;
     b->uni = u;
     return u;
+}
+
+// Small-graph path of gn_solve (declared in gn_internal.h).
+bool gn_internal_small_fits(const gn_graph* g) {
+    return (size_t)g->n * 16 + 4 + (size_t)g->nnz * 4 <= (size_t)kLdsBudget;
+}
+
+gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s) {
+    constexpr int BT = 1024;
+    if (!gn_internal_small_fits(g)) return GN_E_ARG;
+    const size_t lds = (size_t)g->n * 16 + 4 + (size_t)g->nnz * 4;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)small_solve_kernel<BT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL(small_solve_kernel<BT>, dim3(1), dim3(BT), lds, s, g->n, (int32_t)g->nnz,
+                       g->bins.row_begin[BIN_LANE16], g->row_ptr, g->col, g->v, g->ws.gamma, g->ws.state,
+                       g->ws.notconv, g->ws.y[0], g->ws.y[1]);
+    GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
 }

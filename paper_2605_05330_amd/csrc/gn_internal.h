@@ -87,5 +87,13 @@ gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_
 gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
                                   gn_result* res);
 gn_status gn_internal_ensure_tables(GraphWorkspace& ws, int32_t steps_needed);
+
+// small graphs: the whole solve in one workgroup (gn_batch.hip) while
+// nnz + 2 n <= g_small_limit (gn_set_small_graph_limit, gn_solve.hip) and the
+// state and CSR fit in LDS
+extern int32_t g_small_limit;
+constexpr int32_t kSmallWorkMax = 40000;
+gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s);
+bool gn_internal_small_fits(const gn_graph* g);  // y, v and the CSR fit one CU's LDS
 void gn_internal_free_unrolled(gn_graph* g);
 void gn_internal_free_multi(gn_graph* g);

@@ -243,6 +243,14 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t
 
 int32_t g_chunk_len = 32;
 
+int32_t g_small_limit = 20000;
+
+extern "C" gn_status gn_set_small_graph_limit(int32_t work_max) {
+    if (work_max < 0 || work_max > kSmallWorkMax) return GN_E_ARG;
+    g_small_limit = work_max;
+    return GN_OK;
+}
+
 extern "C" gn_status gn_set_chunk_len(int32_t len) {
     if (len < 1 || len > 4096) return GN_E_ARG;
     g_chunk_len = len;
@@ -276,8 +284,15 @@ extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uin
                        (const float*)x, g->perm, ws.state);
     GN_HIP_TRY(hipGetLastError());
 
-    st = gn_internal_run_chunks(ws, nchunks, C,
-                                [g, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, out); }, stream);
+    // one workgroup (one launch for the whole solve) while a step is small
+    if (g->nnz + 2 * (int64_t)n <= g_small_limit && gn_internal_small_fits(g)) {
+        st = gn_internal_small_solve(g, stream);
+        if (st == GN_OK && hipStreamSynchronize(stream) != hipSuccess) st = GN_E_HIP;
+    } else {
+        st = gn_internal_run_chunks(ws, nchunks, C,
+                                    [g, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, out); },
+                                    stream);
+    }
     if (st != GN_OK) return st;
     int32_t steps;
     bool binarised;

@@ -72,6 +72,7 @@ def lib():
                                       _vp], ctypes.c_int),
             "gn_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "gn_set_chunk_len": ([ctypes.c_int32], ctypes.c_int),
+            "gn_set_small_graph_limit": ([ctypes.c_int32], ctypes.c_int),
             "gn_batch_create": ([ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
                                 ctypes.c_int),
             "gn_batch_destroy": ([_vp], None),
@@ -239,6 +240,10 @@ def gn_check_independent(h, sel, stream=None) -> tuple[int, int]:
 
 def gn_set_chunk_len(length: int):
     _check(lib().gn_set_chunk_len(int(length)), "gn_set_chunk_len")
+
+
+def gn_set_small_graph_limit(work_max: int):
+    _check(lib().gn_set_small_graph_limit(int(work_max)), "gn_set_small_graph_limit")
 
 
 class Graph:

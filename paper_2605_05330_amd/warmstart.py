@@ -92,8 +92,9 @@ def gn_labels(graph: "libgn.Graph", schedule: dict, starts: int = 1, seed: int =
         if s == 0:
             x = torch.full((graph.n,), 0.5, device=dev)
         else:
-            e = -torch.log(torch.rand(graph.n, device=dev, generator=gen).clamp_min(1e-12))
-            x = (e / e.max()).clamp(1e-3, 1.0)
+            u = 1.0 - torch.rand(graph.n, device=dev, generator=gen)  # uniforms in (0, 1]
+            x = torch.empty_like(u)
+            graph.random_starts(1, u, x)
         sel = torch.zeros(graph.n, dtype=torch.uint8, device=dev)
         r = graph.solve(x, sel, **schedule)
         if best is None or r.set_objective > best.set_objective:

@@ -185,3 +185,20 @@ def test_trained_warm_start_gains_over_plain_gn(gpu):
     assert np.mean(steps_w) < 0.85 * np.mean(steps_p), (steps_w, steps_p)
     assert gap.mean() <= 1e-3, gap
     assert np.mean(W_w) > np.mean(W_p400), (W_w, W_p400)
+
+
+def test_labels_best_of_several_starts(gpu):
+    """gn_labels with random starts (the library's random-start transform) keeps the
+    best set: never worse than the uniform start alone, and a valid maximal
+    independent set."""
+    import torch
+    from paper_2605_05330_amd import libgn, warmstart
+    sched = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4)
+    g = I.unit_disk(3000, 10, 31)
+    G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 31))
+    lab1, r1 = warmstart.gn_labels(G, sched, starts=1)
+    lab4, r4 = warmstart.gn_labels(G, sched, starts=4, seed=3)
+    assert r4.set_objective >= r1.set_objective
+    sel = lab4.to(torch.uint8)
+    conf, unc = G.check(sel)
+    assert conf == 0 and unc == 0

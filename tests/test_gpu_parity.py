@@ -339,3 +339,46 @@ def test_solve_independent_of_chain_length(gpu):
     for o in outs[1:]:
         assert o[0] == outs[0][0] and o[1] == outs[0][1]
         assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
+
+
+@pytest.mark.parametrize("case", ["er1000", "hubs", "fits3000", "ud2500", "budget", "check_every"])
+def test_small_graph_path_bitexact(gpu, case):
+    """gn_solve runs small graphs in one workgroup (one launch, CSR in LDS);
+    forcing either path must give the same steps, states, sets, objectives and
+    fallback counts."""
+    import torch
+    libgn = _lib()
+    sch = dict(SCHED_RAMP)
+    if case == "er1000":
+        g = I.erdos_renyi(1000, 8 / 999, 0)
+    elif case == "hubs":
+        g = I.hub_graph(1200, [20, 60, 200, 700, 1100], 3.0, 5)  # rows of every class, one above 512
+    elif case == "fits3000":
+        g = I.erdos_renyi(3000, 6 / 2999, 6)   # CSR staged in LDS
+    elif case == "ud2500":
+        g = I.unit_disk(2500, 10, 9)          # 140 KB of LDS: near the budget
+    elif case == "budget":
+        g = I.erdos_renyi(900, 8 / 899, 7)
+        sch["max_steps"] = 40
+    else:
+        g = I.erdos_renyi(900, 8 / 899, 8)
+        sch["check_every"] = 5
+    w = I.weights_uniform01(g.n, 3)
+    G = _graph(g, w)
+    outs = []
+    try:
+        for limit in (0, 40000):
+            libgn.gn_set_small_graph_limit(limit)
+            x = dev(np.full(g.n, 0.5, F32))
+            sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+            r = G.solve(x, sel, **sch)
+            outs.append((r, x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
+    finally:
+        libgn.gn_set_small_graph_limit(20000)
+    (ra, xa, sa), (rb, xb, sb) = outs
+    assert (ra.steps, ra.binarised, ra.fallback_count) == (rb.steps, rb.binarised, rb.fallback_count)
+    assert np.array_equal(xa, xb) and np.array_equal(sa, sb)
+    assert ra.set_objective == rb.set_objective and ra.relaxed_objective == rb.relaxed_objective
+    assert ra.stab == rb.stab and ra.uncovered == rb.uncovered and ra.conflicts == rb.conflicts
+    if case == "budget":
+        assert ra.steps == 40 and not ra.binarised
