@@ -35,7 +35,7 @@ def _setup(n, seed, hub=False):
     return g, w, G, th
 
 
-@pytest.mark.parametrize("n,seed,hub", [(3000, 1, False), (2500, 2, True), (37, 3, False)])
+@pytest.mark.parametrize("n,seed,hub", [(3000, 1, False), (2500, 2, True), (37, 3, False), (100_000, 4, False)])
 def test_forward_backward_vs_oracle(gpu, n, seed, hub):
     import torch
     from paper_2605_05330_amd import libgn

@@ -167,3 +167,20 @@ def test_multi_errors(gpu):
     with pytest.raises(libgn.GNError) as e:
         G.multi_solve(3, x2, sel, **RAMP)
     assert e.value.status == libgn.GN_E_NOT_NORMALIZABLE
+
+
+def test_multi_zero_steps(gpu):
+    """max_steps = 0: every start returns its starting point, rounded."""
+    import torch
+    g = I.erdos_renyi(800, 6 / 799, 3)
+    w = I.weights_uniform01(g.n, 3)
+    G = _lib().Graph(g.n, g.row_ptr, g.col_idx, w)
+    _, x0 = _random_x0(G, 3, g.n, 4)
+    x = x0.clone()
+    sel = torch.zeros(3 * g.n, dtype=torch.uint8, device="cuda")
+    st, res, best = G.multi_solve(3, x, sel, **dict(RAMP, max_steps=0))
+    assert all(r.steps == 0 and not r.binarised for r in res)
+    xn = x0.cpu().numpy()
+    # the final state is |y| / v of the prepared state: x0 up to one rounding of v x / v
+    np.testing.assert_allclose(x.cpu().numpy(), xn, rtol=1e-6, atol=0)
+    assert np.array_equal(sel.cpu().numpy().astype(bool), xn > 0.5)

@@ -225,3 +225,23 @@ def test_solve_split_form_matches_csr_path(gpu):
     assert res.set_size == cols and np.all(S.sum(axis=0) == 1) and np.all(S.sum(axis=1) <= 1)
     assert res.conflicts == 0 and res.uncovered == 0
     assert res.set_objective == pytest.approx(rc.set_objective, rel=1e-12)
+
+
+def test_device_weights_and_zero_steps(gpu):
+    """Weights handed over in device memory give the same instance; max_steps = 0
+    returns the starting point, rounded, as not binarised."""
+    import torch
+    libgn = _lib()
+    rows, cols = 20, 30
+    w = I.rook_weights_rect(rows, cols, 13)
+    a = _solve(rows, cols, w, np.full(rows * cols, 0.5), **RAMP)
+    R = libgn.Rook(rows, cols, dev(w))
+    x = dev(np.full(rows * cols, 0.5, F32))
+    sel = torch.zeros(rows * cols, dtype=torch.uint8, device="cuda")
+    r = R.solve(x, sel, **RAMP)
+    assert r.steps == a[0].steps and np.array_equal(x.cpu().numpy(), a[1])
+    x0 = _state(rows * cols, 14)
+    res, x, sel = _solve(rows, cols, w, x0, **dict(RAMP, max_steps=0))
+    assert res.steps == 0 and not res.binarised
+    np.testing.assert_allclose(x, x0, rtol=1e-6, atol=0)  # |v x| / v: one rounding away from x0
+    assert np.array_equal(sel, x0 > 0.5)
