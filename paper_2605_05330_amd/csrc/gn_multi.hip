@@ -437,19 +437,35 @@ __global__ void multi_extract_kernel(int32_t n, int32_t b, const float* __restri
 
 // Random starting points (code appendix): x = clamp(e / max(e), 1e-3, 1) with
 // e = -log(u), the maximum taken over each start's n values.  Non-negative floats
-// order like their bit patterns, so the maximum is an exact integer atomicMax.
-__global__ void random_max_kernel(int64_t total, int32_t n, const float* __restrict__ u,
-                                  unsigned* __restrict__ maxbits, SolveState* st) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const float uu = u[e];
+// order like their bit patterns, so the maximum is an integer max.  Grid: x runs
+// over a start's values, y over the starts; each block reduces its part in
+// registers and LDS and makes one atomicMax (an atomic per value would serialise
+// millions of updates on 16 addresses).
+__global__ __launch_bounds__(256) void random_max_kernel(int32_t n, const float* __restrict__ u,
+                                                         unsigned* __restrict__ maxbits, SolveState* st) {
+    __shared__ unsigned s_max[4];
+    const int b = blockIdx.y;
+    const float* __restrict__ ub = u + (size_t)b * n;
+    unsigned m = 0u;
+    bool bad = false;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float uu = ub[i];
         if (!(uu > 0.0f && uu <= 1.0f)) {
-            atomicOr(&st->err, 1);
+            bad = true;
             continue;
         }
         const float l = -logf(uu);
-        atomicMax(&maxbits[e / n], __float_as_uint(l > 0.0f ? l : 0.0f));
+        m = max(m, __float_as_uint(l > 0.0f ? l : 0.0f));
     }
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool any_bad = __any(bad);
+    if (lane == 0) {
+        s_max[wave] = m;
+        if (any_bad) atomicOr(&st->err, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&maxbits[b], max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3])));
 }
 
 __global__ void random_apply_kernel(int64_t total, int32_t n, const float* __restrict__ u,
@@ -695,7 +711,8 @@ extern "C" gn_status gn_random_starts(gn_graph* g, int32_t starts, const float* 
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, stream, m->maxbits, kStarts, m->ws.state);
     GN_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(random_max_kernel, dim3(blocks), dim3(256), 0, stream, total, g->n, u, m->maxbits,
+    const int per_start = std::min((g->n + 255) / 256, 256);
+    hipLaunchKernelGGL(random_max_kernel, dim3(per_start, starts), dim3(256), 0, stream, g->n, u, m->maxbits,
                        m->ws.state);
     GN_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(random_apply_kernel, dim3(blocks), dim3(256), 0, stream, total, g->n, u,

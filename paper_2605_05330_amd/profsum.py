@@ -78,7 +78,8 @@ def trace(d: str, kernel: str, grid: str | None, last: int) -> str:
     if grid is not None:
         sel = [ds for (name, g), ds in groups.items() if name.startswith(kernel) and g == grid]
         if not sel:
-            raise SystemExit("no %s dispatch at grid %s" % (kernel, grid))
+            seen = sorted(g for (name, g) in groups if name.startswith(kernel))
+            raise SystemExit("no %s dispatch at grid %s (grid sizes seen: %s)" % (kernel, grid, seen))
         tail = sel[0][-last:]
         out.append("")
         out.append("%s at grid %s, last %d dispatches: avg %.3f us, median %.3f us" % (

@@ -61,12 +61,15 @@ def _multi_vs_single(g, w, starts, x0, sched):
     return res, best
 
 
-def test_random_starts_match_oracle(gpu):
-    g = I.erdos_renyi(3000, 6 / 2999, 2)
+@pytest.mark.parametrize("n,starts", [(3000, 16), (70001, 3)])
+def test_random_starts_match_oracle(gpu, n, starts):
+    """The per-start maximum is a block reduction: one block per start at n = 3000,
+    a grid-strided 256 blocks per start at n = 70001."""
+    g = I.erdos_renyi(n, 6 / (n - 1), 2)
     G = _lib().Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 2))
-    u, x = _random_x0(G, 16, g.n, 5)
-    un, xn = u.cpu().numpy().reshape(16, g.n), x.cpu().numpy().reshape(16, g.n)
-    for b in range(16):
+    u, x = _random_x0(G, starts, g.n, 5)
+    un, xn = u.cpu().numpy().reshape(starts, g.n), x.cpu().numpy().reshape(starts, g.n)
+    for b in range(starts):
         ref = O.random_start(un[b].astype(np.float64))
         np.testing.assert_allclose(xn[b], ref, rtol=1e-5, atol=0)
         assert xn[b].max() == 1.0
