@@ -123,8 +123,10 @@ gn_status ensure_partials(const gn_graph* g, int64_t count) {
     return GN_OK;
 }
 
-gn_status run_set_stats(const gn_graph* g, const float* y, const uint8_t* sel_int, float gamma, FinalStats* host_out,
-                        hipStream_t s) {
+// Set statistics of sel_int (and the relaxed objective of y when given), reduced
+// into dev_out on the device; no host synchronisation.
+gn_status launch_set_stats(const gn_graph* g, const float* y, const uint8_t* sel_int, float gamma,
+                           FinalStats* dev_out, hipStream_t s) {
     const int n = g->n;
     const int light_begin = g->bins.row_begin[BIN_LANE32];
     const int heavy_blocks = (light_begin + kWaves - 1) / kWaves;
@@ -138,9 +140,12 @@ gn_status run_set_stats(const gn_graph* g, const float* y, const uint8_t* sel_in
                            g->col, g->v, g->w_int, y, sel_int, part);
         GN_HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, nb, (const Partial*)part, gamma,
-                       (FinalStats*)g->ws.final_out);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, nb, (const Partial*)part, gamma, dev_out);
     GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
+}
+
+gn_status fetch_stats(const gn_graph* g, FinalStats* host_out, hipStream_t s) {
     GN_HIP_TRY(hipMemcpyAsync(g->ws.host_pinned, g->ws.final_out, sizeof(FinalStats), hipMemcpyDeviceToHost, s));
     GN_HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(host_out, g->ws.host_pinned, sizeof(FinalStats));
@@ -149,13 +154,20 @@ gn_status run_set_stats(const gn_graph* g, const float* y, const uint8_t* sel_in
 
 }  // namespace
 
-gn_status gn_internal_final_stats(gn_graph* g, const float* y_fin, float gamma_fin, float* x_user, uint8_t* sel_user,
-                                  FinalStats* host_out, hipStream_t s) {
+gn_status gn_internal_final_stats_launch(gn_graph* g, const float* y_fin, float gamma_fin, float* x_user,
+                                         uint8_t* sel_user, FinalStats* dev_out, hipStream_t s) {
     const int n = g->n;
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, y_fin, g->v, g->perm, x_user,
                        sel_user, g->ws.sel_int);
     GN_HIP_TRY(hipGetLastError());
-    return run_set_stats(g, y_fin, g->ws.sel_int, gamma_fin, host_out, s);
+    return launch_set_stats(g, y_fin, g->ws.sel_int, gamma_fin, dev_out, s);
+}
+
+gn_status gn_internal_final_stats(gn_graph* g, const float* y_fin, float gamma_fin, float* x_user, uint8_t* sel_user,
+                                  FinalStats* host_out, hipStream_t s) {
+    gn_status st = gn_internal_final_stats_launch(g, y_fin, gamma_fin, x_user, sel_user,
+                                                  (FinalStats*)g->ws.final_out, s);
+    return st != GN_OK ? st : fetch_stats(g, host_out, s);
 }
 
 gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, FinalStats* host_out, hipStream_t s) {
@@ -163,7 +175,8 @@ gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, Fina
     hipLaunchKernelGGL(gather_sel_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, sel_user, g->perm,
                        g->ws.sel_int);
     GN_HIP_TRY(hipGetLastError());
-    return run_set_stats(g, nullptr, g->ws.sel_int, 1.0f, host_out, s);
+    gn_status st = launch_set_stats(g, nullptr, g->ws.sel_int, 1.0f, (FinalStats*)g->ws.final_out, s);
+    return st != GN_OK ? st : fetch_stats(g, host_out, s);
 }
 
 extern "C" gn_status gn_objective(const gn_graph* g, const float* x, double* out, hipStream_t stream) {

@@ -69,6 +69,10 @@ gn_status gn_internal_ensure_ws(gn_graph* g, int32_t steps_needed);
 gn_status gn_internal_launch_step(const gn_graph* g, const StepArgs& a, hipStream_t s);
 gn_status gn_internal_final_stats(gn_graph* g, const float* y_fin, float gamma_fin, float* x_user,
                                   uint8_t* sel_user, FinalStats* host_out, hipStream_t s);
+// same, reduced into device memory without a host round trip (stream-ordered:
+// consecutive calls may share the graph's work buffers)
+gn_status gn_internal_final_stats_launch(gn_graph* g, const float* y_fin, float gamma_fin, float* x_user,
+                                         uint8_t* sel_user, FinalStats* dev_out, hipStream_t s);
 gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, FinalStats* host_out,
                                 hipStream_t s);
 int32_t gn_internal_grid_blocks(const BinLayout& b);

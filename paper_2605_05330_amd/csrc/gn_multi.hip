@@ -35,6 +35,11 @@ namespace {
 constexpr int kStarts = 16;
 constexpr int kChunk = 256;  // heavy rows: entries staged per round
 
+// Offsets in the 4 KiB pinned staging block of a multi-start solve.
+constexpr size_t kPinDone = 64, kPinFb = 128, kPinNc = 256, kPinStats = 512;
+static_assert(sizeof(SolveState) <= kPinDone && kPinStats + kStarts * sizeof(FinalStats) <= 4096,
+              "pinned staging layout");
+
 struct MultiArgs {
     const int32_t* row_ptr;
     const int32_t* col;
@@ -496,6 +501,7 @@ struct MultiWS {
     unsigned long long* fb = nullptr;
     int32_t* nc16 = nullptr;
     int32_t nc16_cap = 0;    // steps covered by nc16
+    FinalStats* stats = nullptr;  // [16] final statistics per start
     int32_t heavy_end = 0, mid_end = 0, l16_begin = 0, mid_blk = 0, light_blk = 0, l16_blk = 0, nblk = 0;
 };
 
@@ -503,7 +509,7 @@ void free_ws(MultiWS* m) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
     m->ws.chunks.clear();
-    f(m->Y[0]); f(m->Y[1]); f(m->yb); f(m->done); f(m->fb); f(m->nc16); f(m->maxbits);
+    f(m->Y[0]); f(m->Y[1]); f(m->yb); f(m->done); f(m->fb); f(m->nc16); f(m->maxbits); f(m->stats);
     f(m->ws.state); f(m->ws.notconv); f(m->ws.gamma);
     if (m->ws.host_pinned) (void)hipHostFree(m->ws.host_pinned);
     delete m;
@@ -518,6 +524,7 @@ MultiWS* get_ws(gn_graph* g) {
               hipMalloc(&m->Y[1], n * kStarts * 4) == hipSuccess && hipMalloc(&m->yb, n * 4) == hipSuccess &&
               hipMalloc(&m->done, kStarts * 4) == hipSuccess && hipMalloc(&m->fb, kStarts * 8) == hipSuccess &&
               hipMalloc(&m->maxbits, kStarts * 4) == hipSuccess &&
+              hipMalloc(&m->stats, kStarts * sizeof(FinalStats)) == hipSuccess &&
               hipMalloc(&m->ws.state, sizeof(SolveState)) == hipSuccess &&
               hipHostMalloc(&m->ws.host_pinned, 4096, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -652,31 +659,46 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
         stream);
     if (st != GN_OK) return st;
 
-    SolveState hs;
-    int32_t done[kStarts];
-    unsigned long long fbh[kStarts];
-    std::vector<int32_t> nc_last(kStarts, 1);
-    GN_HIP_TRY(hipMemcpy(&hs, m->ws.state, sizeof(hs), hipMemcpyDeviceToHost));
-    GN_HIP_TRY(hipMemcpy(done, m->done, sizeof(done), hipMemcpyDeviceToHost));
-    GN_HIP_TRY(hipMemcpy(fbh, m->fb, sizeof(fbh), hipMemcpyDeviceToHost));
-    GN_HIP_TRY(hipMemcpy(nc_last.data(), m->nc16 + (size_t)ms * kStarts, kStarts * 4, hipMemcpyDeviceToHost));
-    if (hs.err & 1) return GN_E_ARG;
-    if (hs.err & 2) return GN_E_NOT_NORMALIZABLE;
+    // solve state, per-start outcomes and the last step's flags in one round trip
+    // through the pinned staging block; the per-start statistics in a second one
+    char* hp = (char*)m->ws.host_pinned;
+    SolveState* hs = (SolveState*)hp;
+    int32_t* done = (int32_t*)(hp + kPinDone);
+    unsigned long long* fbh = (unsigned long long*)(hp + kPinFb);
+    int32_t* nc_last = (int32_t*)(hp + kPinNc);
+    FinalStats* fsh = (FinalStats*)(hp + kPinStats);
+    GN_HIP_TRY(hipMemcpyAsync(hs, m->ws.state, sizeof(SolveState), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipMemcpyAsync(done, m->done, kStarts * 4, hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipMemcpyAsync(fbh, m->fb, kStarts * 8, hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipMemcpyAsync(nc_last, m->nc16 + (size_t)ms * kStarts, kStarts * 4, hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    if (hs->err & 1) return GN_E_ARG;
+    if (hs->err & 2) return GN_E_NOT_NORMALIZABLE;
+
+    int32_t steps_of[kStarts];
+    bool bin_of[kStarts];
+    for (int b = 0; b < starts; ++b) {
+        bin_of[b] = done[b] >= 0 || (ms >= 1 && nc_last[b] == 0);
+        steps_of[b] = done[b] >= 0 ? done[b] : ms;
+        // stream order lets consecutive starts share the extraction and statistics buffers
+        hipLaunchKernelGGL(multi_extract_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, b,
+                           (const float*)m->Y[steps_of[b] & 1], m->yb);
+        GN_HIP_TRY(hipGetLastError());
+        st = gn_internal_final_stats_launch(g, m->yb, gn_internal_host_gamma(sch, steps_of[b]), x + (size_t)b * n,
+                                            sel + (size_t)b * n, m->stats + b, stream);
+        if (st != GN_OK) return st;
+    }
+    GN_HIP_TRY(hipMemcpyAsync(fsh, m->stats, sizeof(FinalStats) * (size_t)starts, hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
 
     bool all_bin = true;
     double best_w = -INFINITY;
     int best_any = -1;
     double best_any_w = -INFINITY;
     for (int b = 0; b < starts; ++b) {
-        const bool bin = done[b] >= 0 || (ms >= 1 && nc_last[b] == 0);
-        const int32_t steps = done[b] >= 0 ? done[b] : ms;
-        hipLaunchKernelGGL(multi_extract_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, b,
-                           (const float*)m->Y[steps & 1], m->yb);
-        GN_HIP_TRY(hipGetLastError());
-        FinalStats fs{};
-        st = gn_internal_final_stats(g, m->yb, gn_internal_host_gamma(sch, steps), x + (size_t)b * n,
-                                     sel + (size_t)b * n, &fs, stream);
-        if (st != GN_OK) return st;
+        const bool bin = bin_of[b];
+        const int32_t steps = steps_of[b];
+        const FinalStats fs = fsh[b];
         gn_result& r = res[b];
         r.steps = steps;
         r.binarised = bin ? 1 : 0;
