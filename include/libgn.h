@@ -166,7 +166,10 @@ gn_status gn_check_independent(const gn_graph* g, const uint8_t* sel, int64_t* c
 typedef struct {
     int32_t block_threads;   /* threads per workgroup: 128, 256, 512 or 1024                 */
     int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1 .. 4 (1 .. 2 with 1024) */
-    int32_t lds_vertices;    /* graphs with n <= lds_vertices keep y and v in LDS            */
+    int32_t lds_vertices;    /* LDS per workgroup = 12 * lds_vertices bytes, and
+                                lds_vertices * 12 * blocks_per_cu <= 158 KiB.  A graph with
+                                16 n + 4 + 4 nnz bytes <= that keeps y, v and its CSR in LDS;
+                                else, with n <= lds_vertices, y and v; else neither          */
     int32_t reserved;
 } gn_tuning;
 

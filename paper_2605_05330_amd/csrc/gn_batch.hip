@@ -4,7 +4,10 @@
 // iterated to its own binarisation by one workgroup: the workgroup pulls a
 // graph from a device work queue (largest graphs first), keeps the graph's
 // weighted state y (ping-pong) and v = sqrt(w) in LDS, and runs the fused WRGN
-// step with a workgroup barrier between steps instead of a grid-wide one.  Each
+// step with a workgroup barrier between steps instead of a grid-wide one.  A
+// graph whose CSR also fits in the workgroup's LDS is copied there once, so its
+// steps touch no global memory; a graph too large for the state falls back to
+// global ping-pong buffers.  Each
 // graph has its own step counter, gamma_k and stopping test; a finished graph
 // frees its workgroup for the next one.  Row sums use the library's canonical
 // order (gn_rowsum.h), so every graph's states, steps and selected set are
@@ -24,15 +27,29 @@ using gnk::sign_of;
 namespace {
 
 constexpr int kLightMaxDeg = 16;  // rows up to this degree run one per thread
+constexpr int kMidMaxDeg = 64;    // rows up to this degree run 8 threads per row (8 rows per wavefront)
 constexpr int kLdsBudget = 160 * 1024 - 2048;  // dynamic LDS per CU (static LDS of the kernel set aside)
 
 struct BatchDesc {
     int32_t n;        // vertices
     int32_t n_light;  // internal rows [0, n_light) have degree <= kLightMaxDeg
+    int32_t n_mid;    // rows [n_light, n_mid) have degree <= kMidMaxDeg, rows [n_mid, n) more
+    int32_t pad0;
     int64_t v_off;    // offset of the graph's vertices in the vertex arrays
     int64_t rp_off;   // offset of its row_ptr (n + 1 entries)
     int64_t e_off;    // offset of its columns
+    int32_t nnz;      // CSR entries
+    int32_t pad1;
 };
+
+// Where a graph's arrays live while its workgroup iterates it.
+enum BatchMode {
+    MODE_GLOBAL = 0,  // state in the global ping-pong buffers, CSR read from global memory
+    MODE_STATE = 1,   // y, y' and v in LDS (12 n bytes), CSR read from global memory
+    MODE_ALL = 2      // y, y', v, row_ptr and columns in LDS (16 n + 4 + 4 nnz bytes)
+};
+
+__host__ __device__ inline int64_t all_lds_bytes(int64_t n, int64_t nnz) { return 16 * n + 4 + 4 * nnz; }
 
 struct BatchRes {
     int32_t steps, binarised;
@@ -55,7 +72,7 @@ struct BatchArgs {
     const float* gamma;      // gamma table, >= max_steps + 1 entries
     int32_t max_steps, check_every;
     float tau;
-    int32_t lds_vertices;
+    int32_t lds_vertices;    // dynamic LDS per workgroup: 12 * lds_vertices bytes
     float* x_cat;            // user order; x0 in, final x out
     uint8_t* sel_cat;
     float* yg0;              // global ping-pong state for graphs above lds_vertices
@@ -123,22 +140,51 @@ __device__ float block_min_f(float x, float* sm) {
     return r;
 }
 
-template <int BT, bool LDS>
-__device__ void solve_graph(const BatchArgs& a, int gi, float* lds) {
+// Rows [rb, re) of degree <= MAXD: 8 threads per row, 8 rows per wavefront per
+// round (the loop bound is uniform over the wavefront, as the group shuffles
+// need).  Returns the rows' stopping-test failures.
+template <int BT, int MAXD, bool GLOBAL_RP>
+__device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                         const float* yin, const float* vv, float* yout, int rb, int re, float g,
+                                         bool do_test, bool do_write, float tau, int& fb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = lane & 7;
+    bool viol = false;
+#pragma unroll 1
+    for (int base = rb + wave * 8; base < re; base += (BT / 64) * 8) {
+        const int i = base + (lane >> 3);
+        const bool valid = i < re;
+        int s0 = 0, dd = 0;
+        if (valid) {
+            s0 = GLOBAL_RP ? gnk::ld_stream(rp + i) : rp[i];
+            dd = (GLOBAL_RP ? gnk::ld_stream(rp + i + 1) : rp[i + 1]) - s0;
+        }
+        unsigned sel = 0u;
+        const float sigma = gnk::row_sum<8, MAXD>(col + s0, dd, yin, t, sel);
+        const bool any_sel = gnk::group_any<8>(sel != 0u);
+        if (valid && t == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
+    }
+    return viol;
+}
+
+template <int BT, int MODE>
+__device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, float* lds) {
     __shared__ double sm_d[BT / 64];
     __shared__ long long sm_l[BT / 64];
     __shared__ float sm_f[BT / 64];
-    const BatchDesc d = a.desc[gi];
     const int n = d.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (n == 0) return;  // result filled on the host
-    const int32_t* __restrict__ rp = a.row_ptr + d.rp_off;
-    const int32_t* __restrict__ col = a.col + d.e_off;
+    const int32_t* __restrict__ rp_g = a.row_ptr + d.rp_off;
+    const int32_t* __restrict__ col_g = a.col + d.e_off;
     const int32_t* __restrict__ perm = a.perm + d.v_off;
-    const int L = a.lds_vertices;
+    constexpr bool LDS = MODE != MODE_GLOBAL;
     float* ya = LDS ? lds : a.yg0 + d.v_off;
-    float* yb = LDS ? lds + L : a.yg1 + d.v_off;
-    float* vv = LDS ? lds + 2 * L : const_cast<float*>(a.v) + d.v_off;
+    float* yb = LDS ? lds + n : a.yg1 + d.v_off;
+    float* vv = LDS ? lds + 2 * n : const_cast<float*>(a.v) + d.v_off;
+    int32_t* rp_l = reinterpret_cast<int32_t*>(lds + 3 * n);
+    int32_t* col_l = rp_l + (n + 1);
+    const int32_t* __restrict__ rp = MODE == MODE_ALL ? rp_l : rp_g;
+    const int32_t* __restrict__ col = MODE == MODE_ALL ? col_l : col_g;
     float* xg = a.x_cat + d.v_off;
 
     for (int i = tid; i < n; i += BT) {
@@ -147,6 +193,10 @@ __device__ void solve_graph(const BatchArgs& a, int gi, float* lds) {
         const float yy = vi * x;
         ya[i] = x > 0.5f ? -yy : yy;
         if (LDS) vv[i] = vi;
+    }
+    if (MODE == MODE_ALL) {
+        for (int i = tid; i <= n; i += BT) rp_l[i] = rp_g[i];
+        for (int e = tid; e < d.nnz; e += BT) col_l[e] = col_g[e];
     }
     __syncthreads();
 
@@ -162,16 +212,18 @@ __device__ void solve_graph(const BatchArgs& a, int gi, float* lds) {
         bool viol = false;
 #pragma unroll 1
         for (int i = tid; i < d.n_light; i += BT) {
-            const int s0 = gnk::ld_stream(rp + i);
-            const int dd = gnk::ld_stream(rp + i + 1) - s0;
+            const int s0 = MODE == MODE_ALL ? rp[i] : gnk::ld_stream(rp + i);
+            const int dd = (MODE == MODE_ALL ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
             unsigned sel = 0u;
             const float sigma = gnk::row_sum<1, kLightMaxDeg>(col + s0, dd, yin, 0, sel);
             viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
         }
+        viol |= mid_rows<BT, kMidMaxDeg, MODE != MODE_ALL>(rp, col, yin, vv, yout, d.n_light, d.n_mid, g, do_test, do_write,
+                                               a.tau, fb);
 #pragma unroll 1
-        for (int i = d.n_light + wave; i < n; i += BT / 64) {
-            const int s0 = gnk::ld_stream(rp + i);
-            const int dd = gnk::ld_stream(rp + i + 1) - s0;
+        for (int i = d.n_mid + wave; i < n; i += BT / 64) {
+            const int s0 = MODE == MODE_ALL ? rp[i] : gnk::ld_stream(rp + i);
+            const int dd = (MODE == MODE_ALL ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
             unsigned sel = 0u;
             const float sigma = gnk::row_sum_wave<8>(col + s0, dd, yin, lane, sel);
             const bool any_sel = __any(sel != 0u);
@@ -266,10 +318,13 @@ __global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
         __syncthreads();
         if (q >= a.count) break;
         const int gi = a.order[q];
-        if (a.desc[gi].n <= a.lds_vertices)
-            solve_graph<BT, true>(a, gi, lds);
+        const BatchDesc d = a.desc[gi];
+        if (all_lds_bytes(d.n, d.nnz) <= 12 * (int64_t)a.lds_vertices)
+            solve_graph<BT, MODE_ALL>(a, d, gi, lds);
+        else if (d.n <= a.lds_vertices)
+            solve_graph<BT, MODE_STATE>(a, d, gi, lds);
         else
-            solve_graph<BT, false>(a, gi, lds);
+            solve_graph<BT, MODE_GLOBAL>(a, d, gi, lds);
     }
 }
 
@@ -322,15 +377,16 @@ __global__ void batch_check_x0_kernel(int64_t total, const int32_t* __restrict__
 
 // One small graph, one workgroup: the whole solve in a single launch, steps
 // separated by workgroup barriers instead of kernel boundaries.  Works on the
-// graph handle's internal arrays: rows [0, light_begin) have degree > 16 and run
-// one wavefront per row, the rest one thread per row; y (ping-pong), v and the CSR
+// graph handle's internal arrays: rows [0, mid_begin) have degree > 128 and run
+// one wavefront per row, rows [mid_begin, light_begin) (degree 17 .. 128) 8
+// threads per row, the rest one thread per row; y (ping-pong), v and the CSR
 // live in LDS (16 n + 4 nnz + 4 bytes).  One compute unit does all the work, so
 // this pays only while a step is small (it is bound by that unit's issue rate).  Same arithmetic and canonical sums as the step kernel, so
 // the result is bit-identical to the chained solve.  On entry y0 holds the signed
 // starting state (prep_state_kernel); on exit the final state is in
 // y0 or y1 by the parity of the step count, as after the chained solve.
 template <int BT>
-__global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz, int32_t light_begin,
+__global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz, int32_t mid_begin, int32_t light_begin,
                                                          const int32_t* __restrict__ rp_g,
                                                          const int32_t* __restrict__ col_g,
                                                          const float* __restrict__ v, const float* __restrict__ gamma,
@@ -377,8 +433,10 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
             const float sigma = gnk::row_sum<1, 16>(col + s0, dd, yin, 0, sel);
             viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, tau, yout, i, fb);
         }
+        viol |= mid_rows<BT, 128, false>(rp, col, yin, vv, yout, mid_begin, light_begin, g, do_test, do_write, tau,
+                                         fb);
 #pragma unroll 1
-        for (int i = wave; i < light_begin; i += BT / 64) {
+        for (int i = wave; i < mid_begin; i += BT / 64) {
             const int s0 = rp[i];
             const int dd = rp[i + 1] - s0;
             unsigned sel = 0u;
@@ -525,7 +583,8 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
     }
 
     // validate each graph (same conditions as gn_graph_create) and relabel it:
-    // rows of degree <= kLightMaxDeg first, the rest after, each group in order
+    // rows of degree <= kLightMaxDeg first, then those of degree <= kMidMaxDeg,
+    // then the rest, each class in its original order
     std::vector<BatchDesc> desc((size_t)count);
     std::vector<int32_t> rp_int((size_t)trp), col_int((size_t)std::max<int64_t>(tnnz, 1)), perm((size_t)std::max<int64_t>(tn, 1));
     std::vector<int32_t> vgraph((size_t)std::max<int64_t>(tn, 1));
@@ -563,9 +622,16 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
             if (!(wg[i] > 0.0f) || !std::isfinite(wg[i])) { delete b; return GN_E_WEIGHT; }
         std::vector<int32_t> p((size_t)ng), q((size_t)ng);
         std::iota(p.begin(), p.end(), 0);
-        std::stable_partition(p.begin(), p.end(), [&](int32_t i) { return rp[i + 1] - rp[i] <= kLightMaxDeg; });
-        int32_t nl = 0;
-        for (int32_t i = 0; i < ng; ++i) nl += (rp[i + 1] - rp[i] <= kLightMaxDeg) ? 1 : 0;
+        auto cls = [&](int32_t i) {
+            const int32_t dg = rp[i + 1] - rp[i];
+            return dg <= kLightMaxDeg ? 0 : dg <= kMidMaxDeg ? 1 : 2;
+        };
+        std::stable_sort(p.begin(), p.end(), [&](int32_t i, int32_t j) { return cls(i) < cls(j); });
+        int32_t nl = 0, nm = 0;
+        for (int32_t i = 0; i < ng; ++i) {
+            nl += cls(i) == 0 ? 1 : 0;
+            nm += cls(i) <= 1 ? 1 : 0;
+        }
         for (int32_t r = 0; r < ng; ++r) q[p[r]] = r;
         int32_t* rpi = rp_int.data() + ro;
         rpi[0] = 0;
@@ -579,7 +645,7 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
             w_int[(size_t)(vo + r)] = wg[i];
             vgraph[(size_t)(vo + r)] = g;
         }
-        desc[g] = BatchDesc{ng, nl, vo, ro, eo};
+        desc[g] = BatchDesc{ng, nl, nm, 0, vo, ro, eo, (int32_t)nnz[g], 0};
         vo += ng;
         ro += (int64_t)ng + 1;
         eo += nnz[g];
@@ -644,7 +710,7 @@ static gn_tuning default_tuning(const gn_batch* b) {
     gn_tuning t{};
     t.block_threads = 256;
     t.blocks_per_cu = 2;
-    t.lds_vertices = std::min<int32_t>(b->max_n, kLdsBudget / (12 * 2));
+    t.lds_vertices = kLdsBudget / (12 * 2);
     t.reserved = 0;
     return t;
 }
@@ -657,6 +723,23 @@ static gn_status ensure_gamma(gn_batch* b, int32_t entries) {
     if (!dalloc(&b->gamma, (size_t)entries)) return GN_E_NOMEM;
     b->gamma_cap = entries;
     return GN_OK;
+}
+
+static const void* batch_kernel(int bt) {
+    return bt == 128 ? batch_kernel_ptr<128>() : bt == 512 ? batch_kernel_ptr<512>()
+         : bt == 1024 ? batch_kernel_ptr<1024>() : batch_kernel_ptr<256>();
+}
+
+// Workgroups of the batched kernel that fit on one compute unit at this shape
+// (registers and LDS).  The persistent grid never asks for more: a workgroup
+// beyond it would only start once the queue is empty.
+static int resident_blocks(int bt, size_t lds_bytes) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(bt), bt, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return std::max(nb, 1);
 }
 
 // Enqueue the whole batched solve (init, x0 checks, persistent kernel).
@@ -692,8 +775,9 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
     a.yg1 = b->yg1;
     a.queue = b->queue;
     a.res = b->res;
-    const int blocks = std::min<int64_t>((int64_t)b->cus * t.blocks_per_cu, b->count);
     const size_t lds = (size_t)t.lds_vertices * 3 * sizeof(float);
+    const int bpc = std::min(t.blocks_per_cu, resident_blocks(t.block_threads, lds));
+    const int blocks = std::min<int64_t>((int64_t)b->cus * bpc, b->count);
     hipError_t e;
     if (t.block_threads == 128)
         e = launch_batch<128>(dim3(blocks), lds, s, a);
@@ -707,11 +791,7 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
 }
 
 static void allow_lds(int bt, size_t bytes) {
-    const void* f = bt == 128    ? batch_kernel_ptr<128>()
-                    : bt == 512  ? batch_kernel_ptr<512>()
-                    : bt == 1024 ? batch_kernel_ptr<1024>()
-                                 : batch_kernel_ptr<256>();
-    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(batch_kernel(bt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 static gn_status check_schedule(const gn_schedule* sch) {
@@ -788,9 +868,10 @@ extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_t
             gn_tuning t{};
             t.block_threads = bt;
             t.blocks_per_cu = bpc;
-            t.lds_vertices = std::min<int32_t>(b->max_n, kLdsBudget / (12 * bpc));
+            t.lds_vertices = kLdsBudget / (12 * bpc);
             if (!tuning_valid(t)) continue;
             allow_lds(bt, (size_t)t.lds_vertices * 12);
+            if (resident_blocks(bt, (size_t)t.lds_vertices * 12) < bpc) continue;  // same launch as a smaller bpc
             float ms_sum = 0.0f;
             for (int rep = 0; rep < 2 && st == GN_OK; ++rep) {
                 if (hipMemcpyAsync(x, half.data(), sizeof(float) * b->total_n, hipMemcpyHostToDevice, stream) !=
@@ -862,7 +943,7 @@ gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s) {
         (void)hipFuncSetAttribute((const void*)small_solve_kernel<BT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     hipLaunchKernelGGL(small_solve_kernel<BT>, dim3(1), dim3(BT), lds, s, g->n, (int32_t)g->nnz,
-                       g->bins.row_begin[BIN_LANE16], g->row_ptr, g->col, g->v, g->ws.gamma, g->ws.state,
+                       g->bins.row_begin[BIN_G8], g->bins.row_begin[BIN_LANE16], g->row_ptr, g->col, g->v, g->ws.gamma, g->ws.state,
                        g->ws.notconv, g->ws.y[0], g->ws.y[1]);
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;

@@ -95,6 +95,10 @@ def test_batch_results_independent_of_tuning(gpu):
     base = _run_batch(B, gs)
     t = B.autotune(**SCHED)
     assert t.block_threads in (128, 256, 512, 1024) and 1 <= t.blocks_per_cu <= 4
+    # 12 * lds_vertices bytes of LDS per workgroup: graphs needing 16 n + 4 + 4 nnz bytes or
+    # less keep their CSR there too (the graphs up to ~1000 vertices at 5000, up to ~640
+    # at 3000, only the two edgeless ones at 100), others with n <= lds_vertices keep the
+    # state there, the rest run from global memory
     shapes = [t, lg.gn_tuning(128, 1, 3000, 0), lg.gn_tuning(512, 2, 3000, 0), lg.gn_tuning(1024, 1, 5000, 0),
               lg.gn_tuning(1024, 2, 100, 0),
               lg.gn_tuning(256, 4, 100, 0),   # most graphs take the global-memory state path
