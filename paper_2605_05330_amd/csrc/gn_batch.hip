@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "gn_internal.h"
@@ -46,10 +47,12 @@ struct BatchDesc {
 enum BatchMode {
     MODE_GLOBAL = 0,  // state in the global ping-pong buffers, CSR read from global memory
     MODE_STATE = 1,   // y, y' and v in LDS (12 n bytes), CSR read from global memory
-    MODE_ALL = 2      // y, y', v, row_ptr and columns in LDS (16 n + 4 + 4 nnz bytes)
+    MODE_ALL = 2      // y, y', v, row_ptr (int32) and columns (uint16) in LDS
 };
 
-__host__ __device__ inline int64_t all_lds_bytes(int64_t n, int64_t nnz) { return 16 * n + 4 + 4 * nnz; }
+// LDS bytes of MODE_ALL: 12 n (y, y', v) + 4 (n + 1) (row_ptr) + 2 nnz (columns);
+// a graph that fits has far fewer than 65536 vertices, so its ids fit in 16 bits.
+__host__ __device__ inline int64_t all_lds_bytes(int64_t n, int64_t nnz) { return 16 * n + 4 + 2 * nnz; }
 
 struct BatchRes {
     int32_t steps, binarised;
@@ -143,8 +146,8 @@ __device__ float block_min_f(float x, float* sm) {
 // Rows [rb, re) of degree <= MAXD: 8 threads per row, 8 rows per wavefront per
 // round (the loop bound is uniform over the wavefront, as the group shuffles
 // need).  Returns the rows' stopping-test failures.
-template <int BT, int MAXD, bool GLOBAL_RP>
-__device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+template <int BT, int MAXD, bool GLOBAL_RP, typename CT>
+__device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const CT* __restrict__ col,
                                          const float* yin, const float* vv, float* yout, int rb, int re, float g,
                                          bool do_test, bool do_write, float tau, int& fb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = lane & 7;
@@ -181,10 +184,13 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     float* ya = LDS ? lds : a.yg0 + d.v_off;
     float* yb = LDS ? lds + n : a.yg1 + d.v_off;
     float* vv = LDS ? lds + 2 * n : const_cast<float*>(a.v) + d.v_off;
+    using CT = std::conditional_t<MODE == MODE_ALL, uint16_t, int32_t>;  // column id type
     int32_t* rp_l = reinterpret_cast<int32_t*>(lds + 3 * n);
-    int32_t* col_l = rp_l + (n + 1);
+    uint16_t* col_l = reinterpret_cast<uint16_t*>(rp_l + (n + 1));
     const int32_t* __restrict__ rp = MODE == MODE_ALL ? rp_l : rp_g;
-    const int32_t* __restrict__ col = MODE == MODE_ALL ? col_l : col_g;
+    const CT* __restrict__ col;
+    if constexpr (MODE == MODE_ALL) col = col_l;
+    else col = col_g;
     float* xg = a.x_cat + d.v_off;
 
     for (int i = tid; i < n; i += BT) {
@@ -196,7 +202,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     }
     if (MODE == MODE_ALL) {
         for (int i = tid; i <= n; i += BT) rp_l[i] = rp_g[i];
-        for (int e = tid; e < d.nnz; e += BT) col_l[e] = col_g[e];
+        for (int e = tid; e < d.nnz; e += BT) col_l[e] = (uint16_t)col_g[e];
     }
     __syncthreads();
 

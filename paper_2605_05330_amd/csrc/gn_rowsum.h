@@ -40,12 +40,13 @@ __device__ __forceinline__ float bounded_ratio(float yi, float s) {
 // the group) and ORs the sign bits (rounded-set membership) of the neighbours
 // into `sel` (per thread; the caller reduces it over the group).
 // Values entering a sum: |y| for the sign-carrying state (ABS), raw values for
-// signed adjoint vectors.
+// signed adjoint vectors.  Column ids are int32, or uint16 for a graph of at most
+// 65536 vertices whose columns are staged in LDS.
 template <bool ABS>
 __device__ __forceinline__ float term(float v) { return ABS ? fabsf(v) : v; }
 
-template <int G, int MAXD, bool ABS = true>
-__device__ __forceinline__ float row_sum(const int32_t* __restrict__ cp, int d, const float* __restrict__ y, int t,
+template <int G, int MAXD, bool ABS = true, typename IT = int32_t>
+__device__ __forceinline__ float row_sum(const IT* __restrict__ cp, int d, const float* __restrict__ y, int t,
                                          unsigned& sel) {
     constexpr int NV = MAXD < 64 ? MAXD : 64;         // virtual lanes that can hold entries
     constexpr int NCH = NV / G;                       // virtual lanes (chains) per thread
@@ -135,8 +136,8 @@ struct SlicedIdx {
 
 // One wavefront (G = 64) sums a row of any degree: each lane runs its chain in
 // batches of U independent loads.
-template <int U, bool ABS = true>
-__device__ __forceinline__ float row_sum_wave(const int32_t* __restrict__ cp, int d, const float* __restrict__ y,
+template <int U, bool ABS = true, typename IT = int32_t>
+__device__ __forceinline__ float row_sum_wave(const IT* __restrict__ cp, int d, const float* __restrict__ y,
                                               int lane, unsigned& sel) {
     float acc = 0.0f;
     int e = lane;
