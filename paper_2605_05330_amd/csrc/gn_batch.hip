@@ -65,8 +65,9 @@ struct BatchRes {
 
 struct BatchArgs {
     const BatchDesc* desc;
-    const int32_t* order;    // processing order (graph ids, most entries first)
+    const int32_t* order;    // graph ids this launch processes, most entries first
     int32_t count;
+    int32_t qslot;           // queue counter this launch draws from
     const int32_t* row_ptr;  // internal, per graph
     const int32_t* col;      // internal local ids
     const float* v;          // internal order
@@ -80,7 +81,7 @@ struct BatchArgs {
     uint8_t* sel_cat;
     float* yg0;              // global ping-pong state for graphs above lds_vertices
     float* yg1;
-    int32_t* queue;          // [0]: next queue slot, [1]: error bits
+    int32_t* queue;          // [0]: next slot of the LDS launch, [1]: error bits, [2]: next slot of the global launch
     BatchRes* res;
 };
 
@@ -312,25 +313,31 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     __syncthreads();
 }
 
-template <int BT>
+// The persistent kernel.  BIG = false: graphs whose state fits in LDS (MODE_ALL
+// or MODE_STATE); BIG = true: the graphs above that (MODE_GLOBAL), in a launch of
+// their own, because the 64-bit gathers of that path would otherwise raise the
+// register count of the common one.
+template <int BT, bool BIG>
 __global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
     extern __shared__ float lds[];
     __shared__ int s_g;
     if (a.queue[1] != 0) return;  // x0 rejected: leave every output untouched
     for (;;) {
-        if (threadIdx.x == 0) s_g = atomicAdd(a.queue, 1);
+        if (threadIdx.x == 0) s_g = atomicAdd(a.queue + a.qslot, 1);
         __syncthreads();
         const int q = s_g;
         __syncthreads();
         if (q >= a.count) break;
         const int gi = a.order[q];
         const BatchDesc d = a.desc[gi];
-        if (all_lds_bytes(d.n, d.nnz) <= 12 * (int64_t)a.lds_vertices)
-            solve_graph<BT, MODE_ALL>(a, d, gi, lds);
-        else if (d.n <= a.lds_vertices)
-            solve_graph<BT, MODE_STATE>(a, d, gi, lds);
-        else
+        if constexpr (BIG) {
             solve_graph<BT, MODE_GLOBAL>(a, d, gi, lds);
+        } else {
+            if (all_lds_bytes(d.n, d.nnz) <= 12 * (int64_t)a.lds_vertices)
+                solve_graph<BT, MODE_ALL>(a, d, gi, lds);
+            else
+                solve_graph<BT, MODE_STATE>(a, d, gi, lds);
+        }
     }
 }
 
@@ -340,6 +347,7 @@ __global__ void batch_init_kernel(int32_t* queue, float* gamma, int32_t max_step
     if (t == 0) {
         queue[0] = 0;
         queue[1] = 0;
+        queue[2] = 0;
     }
     for (int k = t; k <= max_steps; k += gridDim.x * blockDim.x) {
         double gk;
@@ -475,15 +483,15 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
     }
 }
 
-template <int BT>
+template <int BT, bool BIG>
 hipError_t launch_batch(dim3 grid, size_t lds_bytes, hipStream_t s, const BatchArgs& a) {
-    hipLaunchKernelGGL(batch_solve_kernel<BT>, grid, dim3(BT), lds_bytes, s, a);
+    hipLaunchKernelGGL((batch_solve_kernel<BT, BIG>), grid, dim3(BT), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <int BT>
+template <int BT, bool BIG>
 const void* batch_kernel_ptr() {
-    return (const void*)batch_solve_kernel<BT>;
+    return (const void*)batch_solve_kernel<BT, BIG>;
 }
 
 }  // namespace
@@ -495,7 +503,10 @@ struct gn_batch {
     int device = 0;
     int32_t cus = 0;
     BatchDesc* desc = nullptr;
-    int32_t* order = nullptr;
+    int32_t* order = nullptr;      // graphs that fit the LDS state size, then the others (for split_lds)
+    std::vector<int32_t> h_order;  // all graphs, most entries first
+    int32_t split_lds = -1;        // lds_vertices the device order was split for
+    int32_t n_fit = 0;             // graphs with n <= split_lds
     int32_t* vgraph = nullptr;
     int32_t* row_ptr = nullptr;
     int32_t* col = nullptr;
@@ -672,7 +683,7 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
     b->cus = cus > 0 ? cus : 256;
     bool ok = dalloc(&b->desc, count) && dalloc(&b->order, count) && dalloc(&b->vgraph, tn) &&
               dalloc(&b->row_ptr, trp) && dalloc(&b->col, tnnz) && dalloc(&b->v, tn) && dalloc(&b->w, tn) &&
-              dalloc(&b->perm, tn) && dalloc(&b->yg0, tn) && dalloc(&b->yg1, tn) && dalloc(&b->queue, 2) &&
+              dalloc(&b->perm, tn) && dalloc(&b->yg0, tn) && dalloc(&b->yg1, tn) && dalloc(&b->queue, 3) &&
               dalloc(&b->res, count);
     if (ok && hipHostMalloc((void**)&b->res_host, sizeof(BatchRes) * count, hipHostMallocDefault) != hipSuccess) {
         b->res_host = nullptr;
@@ -688,7 +699,7 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
     };
     up(b->desc, desc.data(), sizeof(BatchDesc) * count);
-    up(b->order, order.data(), sizeof(int32_t) * count);
+    b->h_order = order;
     up(b->vgraph, vgraph.data(), sizeof(int32_t) * tn);
     up(b->row_ptr, rp_int.data(), sizeof(int32_t) * trp);
     up(b->col, col_int.data(), sizeof(int32_t) * tnnz);
@@ -731,17 +742,20 @@ static gn_status ensure_gamma(gn_batch* b, int32_t entries) {
     return GN_OK;
 }
 
-static const void* batch_kernel(int bt) {
-    return bt == 128 ? batch_kernel_ptr<128>() : bt == 512 ? batch_kernel_ptr<512>()
-         : bt == 1024 ? batch_kernel_ptr<1024>() : batch_kernel_ptr<256>();
+static const void* batch_kernel(int bt, bool big = false) {
+    if (big)
+        return bt == 128 ? batch_kernel_ptr<128, true>() : bt == 512 ? batch_kernel_ptr<512, true>()
+             : bt == 1024 ? batch_kernel_ptr<1024, true>() : batch_kernel_ptr<256, true>();
+    return bt == 128 ? batch_kernel_ptr<128, false>() : bt == 512 ? batch_kernel_ptr<512, false>()
+         : bt == 1024 ? batch_kernel_ptr<1024, false>() : batch_kernel_ptr<256, false>();
 }
 
 // Workgroups of the batched kernel that fit on one compute unit at this shape
 // (registers and LDS).  The persistent grid never asks for more: a workgroup
 // beyond it would only start once the queue is empty.
-static int resident_blocks(int bt, size_t lds_bytes) {
+static int resident_blocks(int bt, size_t lds_bytes, bool big = false) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(bt), bt, lds_bytes) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(bt, big), bt, lds_bytes) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
@@ -761,10 +775,26 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
                            b->total_n, b->vgraph, b->desc, b->row_ptr, b->col, b->perm, x_cat, b->queue);
         GN_HIP_TRY(hipGetLastError());
     }
+    if (t.lds_vertices != b->split_lds) {
+        // device order: graphs whose state fits in LDS first, then the others,
+        // each part most entries first
+        std::vector<int32_t> split;
+        split.reserve(b->h_order.size());
+        for (int32_t g : b->h_order)
+            if (b->h_n[g] <= t.lds_vertices) split.push_back(g);
+        const int32_t nf = (int32_t)split.size();
+        for (int32_t g : b->h_order)
+            if (b->h_n[g] > t.lds_vertices) split.push_back(g);
+        GN_HIP_TRY(hipMemcpyAsync(b->order, split.data(), sizeof(int32_t) * split.size(), hipMemcpyHostToDevice, s));
+        GN_HIP_TRY(hipStreamSynchronize(s));  // the host vector goes out of scope
+        b->split_lds = t.lds_vertices;
+        b->n_fit = nf;
+    }
     BatchArgs a{};
     a.desc = b->desc;
     a.order = b->order;
-    a.count = b->count;
+    a.count = b->n_fit;
+    a.qslot = 0;
     a.row_ptr = b->row_ptr;
     a.col = b->col;
     a.v = b->v;
@@ -782,18 +812,24 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
     a.queue = b->queue;
     a.res = b->res;
     const size_t lds = (size_t)t.lds_vertices * 3 * sizeof(float);
-    const int bpc = std::min(t.blocks_per_cu, resident_blocks(t.block_threads, lds));
-    const int blocks = std::min<int64_t>((int64_t)b->cus * bpc, b->count);
-    hipError_t e;
-    if (t.block_threads == 128)
-        e = launch_batch<128>(dim3(blocks), lds, s, a);
-    else if (t.block_threads == 512)
-        e = launch_batch<512>(dim3(blocks), lds, s, a);
-    else if (t.block_threads == 1024)
-        e = launch_batch<1024>(dim3(blocks), lds, s, a);
-    else
-        e = launch_batch<256>(dim3(blocks), lds, s, a);
-    return e == hipSuccess ? GN_OK : GN_E_HIP;
+    auto launch = [&](bool big, size_t lds_bytes, int count) -> hipError_t {
+        const int bpc = std::min(t.blocks_per_cu, resident_blocks(t.block_threads, lds_bytes, big));
+        const dim3 grid((unsigned)std::min<int64_t>((int64_t)b->cus * bpc, count));
+        switch (t.block_threads) {
+            case 128: return big ? launch_batch<128, true>(grid, 0, s, a) : launch_batch<128, false>(grid, lds_bytes, s, a);
+            case 512: return big ? launch_batch<512, true>(grid, 0, s, a) : launch_batch<512, false>(grid, lds_bytes, s, a);
+            case 1024: return big ? launch_batch<1024, true>(grid, 0, s, a) : launch_batch<1024, false>(grid, lds_bytes, s, a);
+            default: return big ? launch_batch<256, true>(grid, 0, s, a) : launch_batch<256, false>(grid, lds_bytes, s, a);
+        }
+    };
+    if (b->n_fit > 0) GN_HIP_TRY(launch(false, lds, b->n_fit));
+    if (b->n_fit < b->count) {
+        a.order = b->order + b->n_fit;
+        a.count = b->count - b->n_fit;
+        a.qslot = 2;
+        GN_HIP_TRY(launch(true, 0, b->count - b->n_fit));
+    }
+    return GN_OK;
 }
 
 static void allow_lds(int bt, size_t bytes) {
