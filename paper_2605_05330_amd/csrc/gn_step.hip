@@ -51,6 +51,7 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<Step
 template <int G, int MAXD>
 __device__ __forceinline__ int sliced_rows(const StepArgs& a, StepCtl<StepArgs>& c, int b, int rb, int re, int lb, int& fb) {
     constexpr int RS = 64 / G;
+    lb = swizzle_block(lb, a.bins.blk_begin[b + 1] - a.bins.blk_begin[b]);
     const int lane = threadIdx.x & 63;
     const int ls = lb * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // slice inside the bin
     const int r0 = rb + ls * RS;

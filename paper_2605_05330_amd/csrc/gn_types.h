@@ -32,6 +32,24 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kWaveMaxDeg = 512;         // rows above this degree get a whole workgroup
 constexpr int kStage = 4096;             // LDS staging chunk for BIN_BLOCK rows (floats)
 constexpr int kSortWindow = 2048;        // degree-sort window of the sliced bins (rows)
+constexpr int kSwizzle = 128;            // block groups of the sliced bins' block-to-rows map
+
+// Block-to-rows map of a sliced bin.  Workgroups are handed to the XCDs round
+// robin (workgroup j to XCD j mod 8) and, inside an XCD, to its compute units in
+// turn, so workgroups j and j + kSwizzle tend to share an XCD and a group of
+// compute units.  Physical block j of a bin of nb blocks therefore works on
+// logical block c (S - 1) + min(c, R) + s, with c = j mod kSwizzle,
+// s = j / kSwizzle, S = ceil(nb / kSwizzle) and R = nb - kSwizzle (S - 1): the
+// blocks of one residue class take consecutive row ranges, and with the rows in
+// locality order their neighbour gathers share cache lines.  A bijection on
+// [0, nb); which block computes a row never changes the row's result.
+__host__ __device__ inline int swizzle_block(int j, int nb) {
+    if (nb <= kSwizzle) return j;
+    const int S = (nb + kSwizzle - 1) / kSwizzle;
+    const int R = nb - kSwizzle * (S - 1);
+    const int c = j % kSwizzle, s = j / kSwizzle;
+    return c * (S - 1) + (c < R ? c : R) + s;
+}
 
 __host__ __device__ constexpr int bin_rows_per_block(int b) {
     return b == BIN_BLOCK ? 1 : b == BIN_WAVE ? 2 * kWaves : b == BIN_G8 ? 8 * kWaves

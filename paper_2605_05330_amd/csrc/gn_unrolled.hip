@@ -81,6 +81,7 @@ __device__ __forceinline__ void adj_row(const AdjArgs& a, int i, float sigma) {
 // slice's lines (the layout of the forward step).
 template <int G, int MAXD>
 __device__ __forceinline__ void adj_sliced_rows(const AdjArgs& a, int b, int rb, int re, int lb) {
+    lb = swizzle_block(lb, a.bins.blk_begin[b + 1] - a.bins.blk_begin[b]);  // same map as the step kernel
     constexpr int RS = 64 / G;
     const int lane = threadIdx.x & 63;
     const int ls = lb * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
