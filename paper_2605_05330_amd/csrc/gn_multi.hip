@@ -365,11 +365,15 @@ __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
         if (valid && t == 0) viol = quad_update(a, c, i, q, yraw, vi, s, any, fb);
     } else {
         bool quit = false;
+        // the block-to-rows map of the single-start step (swizzle_block): blocks
+        // that share an XCD work on neighbouring rows
         const int lb = blk - a.light_blk;
+        const int nl = (int)gridDim.x - a.light_blk;
         if (lb < a.l16_blk) {
-            viol = light_rows_g2(a, c, a.mid_end, a.l16_begin, lb, wave, lane, fb, quit);
+            viol = light_rows_g2(a, c, a.mid_end, a.l16_begin, swizzle_block(lb, a.l16_blk), wave, lane, fb, quit);
         } else {
-            viol = light_rows16(a, c, a.l16_begin, a.n, lb - a.l16_blk, wave, lane, fb, quit);
+            viol = light_rows16(a, c, a.l16_begin, a.n, swizzle_block(lb - a.l16_blk, nl - a.l16_blk), wave, lane, fb,
+                                quit);
         }
         if (quit) return;  // uniform over the grid
     }

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+from collections.abc import Sequence
 from dataclasses import dataclass
 
 import numpy as np
@@ -376,6 +377,29 @@ def _result(r: gn_result, st: int) -> Result:
                   r.set_size, r.conflicts, r.uncovered, float(r.stab))
 
 
+class Results(Sequence):
+    """Read-only sequence over a gn_result array filled by the library.  Elements
+    become Result objects only when read, so a call that returns thousands of
+    results does not build (and later garbage-collect) thousands of objects."""
+
+    def __init__(self, arr, st: int):
+        self._arr = arr
+        self._st = st
+
+    def __len__(self) -> int:
+        return len(self._arr)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [_result(self._arr[k], self._st) for k in range(*i.indices(len(self._arr)))]
+        n = len(self._arr)
+        if i < 0:
+            i += n
+        if not 0 <= i < n:
+            raise IndexError(i)
+        return _result(self._arr[i], self._st)
+
+
 def gn_batch_create(n, nnz, row_ptr_cat, col_idx_cat, w_cat, validate=True, stream=None):
     """Batch handle from per-graph sizes (host) and concatenated local CSR + weights
     (host numpy arrays or CUDA tensors)."""
@@ -408,14 +432,14 @@ def gn_batch_destroy(h):
 
 
 def gn_batch_solve(h, count, schedule: gn_schedule, x_cat, sel_cat, tuning: gn_tuning | None = None,
-                   stream=None) -> tuple[int, list[Result]]:
+                   stream=None) -> tuple[int, Results]:
     import torch
     res = (gn_result * count)()
     st = lib().gn_batch_solve(h, ctypes.byref(schedule), ctypes.byref(tuning) if tuning is not None else None,
                               _dptr(x_cat, torch.float32, "x_cat"), _dptr(sel_cat, torch.uint8, "sel_cat"), res,
                               _stream(stream))
     _check(st, "gn_batch_solve", allow=(GN_OK, GN_NOT_CONVERGED))
-    return st, [_result(res[g], st) for g in range(count)]
+    return st, Results(res, st)
 
 
 def gn_batch_autotune(h, schedule: gn_schedule, stream=None) -> gn_tuning:

@@ -139,3 +139,21 @@ def test_product_path_does_not_import_oracle():
         assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), path
     for path in glob.glob(os.path.join(pkg, "csrc", "*")):
         assert "gn_oracle" not in open(path).read(), path
+
+
+def test_batch_results_view():
+    """The batched solve returns its results as a lazy view over the library's
+    gn_result array: length, indexing (negative too), slices and iteration."""
+    arr = (libgn.gn_result * 5)()
+    for k in range(5):
+        arr[k].steps = 10 + k
+        arr[k].binarised = k % 2
+        arr[k].set_objective = 0.5 * k
+    res = libgn.Results(arr, libgn.GN_OK)
+    assert len(res) == 5
+    assert res[0].steps == 10 and res[-1].steps == 14 and res[3].binarised is True
+    assert [r.steps for r in res] == [10, 11, 12, 13, 14]
+    assert [r.set_objective for r in res[1:3]] == [0.5, 1.0]
+    with pytest.raises(IndexError):
+        res[5]
+    assert all(r.status == libgn.GN_OK for r in res)
