@@ -55,18 +55,31 @@ struct RookArgs {
 
 __device__ __forceinline__ double encode(double sum, bool sel) { return sel ? -sum : sum; }
 
-// Partial sums of the new state over this tile: rows by a butterfly over the 64
-// lanes, columns over the lane's 4 rows in order and then the 4 wavefronts in
-// order.
+// Partial sums of the new state over this tile.  Rows: the wavefront's 4 rows
+// are reduced together by a reduce-scatter butterfly over the 64 lanes.  At xor 32
+// a lane keeps rows {0, 1} (lane bit 5 clear) or {2, 3} and adds its partner's
+// values of those rows; at xor 16 it keeps one of the two; xor 8 .. 1 finish that
+// row over the lane's group of 16, whose first lane writes it (row 2 bit5 + bit4).
+// Columns: over the lane's 4 rows in order, then the 4 wavefronts in order.
 __device__ __forceinline__ void write_partials(const RookArgs& a, int tr, int tc, int lane, int wave,
                                                const int (&iw)[4], const bool (&ok)[4], const float (&yn)[4],
                                                double (*pc)[kTC], int (*pcs)[kTC]) {
+    double val[4];
+    unsigned long long selm[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        double val = ok[m] ? (double)fabsf(yn[m]) : 0.0;
-        for (int off = 32; off >= 1; off >>= 1) val += __shfl_xor(val, off, 64);
-        const bool any = __ballot(ok[m] && gnk::sign_of(yn[m])) != 0ull;
-        if (lane == 0 && iw[m] < a.rows) a.rp_out[(size_t)iw[m] * a.ntc + tc] = encode(val, any);
+        val[m] = ok[m] ? (double)fabsf(yn[m]) : 0.0;
+        selm[m] = __ballot(ok[m] && gnk::sign_of(yn[m]));
+    }
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+    const double k0 = (b5 ? val[2] : val[0]) + __shfl_xor(b5 ? val[0] : val[2], 32, 64);
+    const double k1 = (b5 ? val[3] : val[1]) + __shfl_xor(b5 ? val[1] : val[3], 32, 64);
+    double r = (b4 ? k1 : k0) + __shfl_xor(b4 ? k0 : k1, 16, 64);
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
+    if ((lane & 15) == 0) {
+        const int m = (b5 ? 2 : 0) + (b4 ? 1 : 0);
+        if (iw[m] < a.rows) a.rp_out[(size_t)iw[m] * a.ntc + tc] = encode(r, selm[m] != 0ull);
     }
     double cacc = 0.0;
     int csel = 0;
@@ -280,45 +293,47 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     }
     __syncthreads();
 
+    // every lane computes all 4 entries (entries outside the matrix hold y = 0,
+    // v = 1 and are masked out of stores, flags and partials), so the loop has
+    // no divergent branches
     float yn[4];
     int viol = 0, fb = 0;
     bool unnormalizable = false;
+    const double C = fC[lane];
+    const bool csel = fCs[lane] != 0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        yn[m] = 0.0f;
-        if (!ok[m]) continue;
-        const size_t e = (size_t)iw[m] * a.cols + j;
-        const double R = fR[wave + 4 * m], C = fC[lane];
+        const double R = fR[wave + 4 * m];
         const float yi = fabsf(yraw[m]);
         const float sigma = (float)((R - (double)yi) + (C - (double)yi));
         const float s = __fmaf_rn(c.g, sigma, yi);
         const bool fallback = !(s > 1e-9f);
         const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
         const float yv = vi[m] * xn;
-        yn[m] = xn > 0.5f ? -yv : yv;
-        if (c.do_write) {
-            if (a.y_out) a.y_out[e] = yn[m];
+        const float y_new = xn > 0.5f ? -yv : yv;
+        yn[m] = ok[m] ? y_new : 0.0f;
+        if (c.do_write && ok[m]) {
+            const size_t e = (size_t)iw[m] * a.cols + j;
+            if (a.y_out) a.y_out[e] = y_new;
             if (a.x_out) a.x_out[e] = xn;
-            fb += fallback ? 1 : 0;
         }
-        if (c.solve && c.k == 0 && yi == 0.0f && R == 0.0 && C == 0.0) unnormalizable = true;
-        if (c.do_test) {
-            const bool in_s = gnk::sign_of(yraw[m]) != 0u;
-            const bool nbr_sel = fRs[wave + 4 * m] != 0 || fCs[lane] != 0;
-            const float tv = c.tau * vi[m];
-            const bool far = (yi > tv) && ((vi[m] - yi) > tv);
-            const bool uncovered = !in_s && !nbr_sel;
-            const bool growing = !in_s && (yi > 0.0f) && !(s > vi[m]);
-            viol |= (far || uncovered || growing) ? 1 : 0;
-        }
+        fb += (c.do_write && ok[m] && fallback) ? 1 : 0;
+        if (c.solve && c.k == 0 && ok[m] && yi == 0.0f && R == 0.0 && C == 0.0) unnormalizable = true;
+        const bool in_s = gnk::sign_of(yraw[m]) != 0u;
+        const bool nbr_sel = fRs[wave + 4 * m] != 0 || csel;
+        const float tv = c.tau * vi[m];
+        const bool far = (yi > tv) && ((vi[m] - yi) > tv);
+        const bool uncovered = !in_s && !nbr_sel;
+        const bool growing = !in_s && (yi > 0.0f) && !(s > vi[m]);
+        viol |= (c.do_test && ok[m] && (far || uncovered || growing)) ? 1 : 0;
     }
     if (unnormalizable) atomicOr(&a.st->err, 2);
     if (c.do_write && a.rp_out) write_partials(a, tr, tc, lane, wave, iw, ok, yn, pc, pcs);
 
     if (a.solve) {
         const bool wv = __ballot(viol != 0) != 0ull;
-        int wf = fb;
-        for (int off = 32; off >= 1; off >>= 1) wf += __shfl_xor(wf, off, 64);
+        // fb is 0..4 per lane: three ballots count it over the wavefront
+        const int wf = __popcll(__ballot(fb & 1)) + 2 * __popcll(__ballot(fb & 2)) + 4 * __popcll(__ballot(fb & 4));
         if (lane == 0) {
             s_viol[wave] = wv ? 1 : 0;
             s_fb[wave] = wf;
