@@ -6,8 +6,8 @@
 // R_i and C_j the row and column sums of |y|, so one step costs O(rows*cols)
 // instead of the O(rows*cols*(rows+cols)) of a CSR pass over the same graph.
 //
-// Tiles of 16 rows x 64 columns (one block of 256 threads; wavefront w holds tile
-// rows w, w+4, w+8, w+12, lane l column l).  Each step
+// Tiles of 32 rows x 64 columns (one block of 256 threads; wavefront w holds tile
+// rows w, w+4, .., w+28, lane l column l).  Each step
 //   1. reduces the row and column sums of the input state from per-tile partial
 //      sums (fp64, fixed order; the sign bit of a partial carries "some entry of
 //      this segment is in the rounded set") -- inside the step kernel for small
@@ -29,8 +29,11 @@
 
 namespace {
 
-constexpr int kTR = 16;  // tile rows
-constexpr int kTC = 64;  // tile columns (one wavefront)
+constexpr int kTR = 32;              // tile rows
+constexpr int kTC = 64;              // tile columns (one wavefront)
+constexpr int kRPW = kTR / kWaves;   // tile rows per wavefront (a power of two)
+constexpr int kRowThreads = kBlock / kTR;  // fused form: threads per row of a tile's row sums
+static_assert((kRPW & (kRPW - 1)) == 0 && kRPW <= 32, "rows per wavefront");
 
 struct RookArgs {
     int32_t rows, cols, ntr, ntc;  // tiles: ntr x ntc
@@ -55,36 +58,52 @@ struct RookArgs {
 
 __device__ __forceinline__ double encode(double sum, bool sel) { return sel ? -sum : sum; }
 
-// Partial sums of the new state over this tile.  Rows: the wavefront's 4 rows
+// Partial sums of the new state over this tile.  Rows: the wavefront's kRPW rows
 // are reduced together by a reduce-scatter butterfly over the 64 lanes.  At xor 32
-// a lane keeps rows {0, 1} (lane bit 5 clear) or {2, 3} and adds its partner's
-// values of those rows; at xor 16 it keeps one of the two; xor 8 .. 1 finish that
-// row over the lane's group of 16, whose first lane writes it (row 2 bit5 + bit4).
-// Columns: over the lane's 4 rows in order, then the 4 wavefronts in order.
+// a lane keeps the upper half of its rows (lane bit 5 set) or the lower half and
+// adds its partner's values of those rows; each following stage halves again,
+// until one row is left per lane; the remaining xor stages finish that row over a
+// group of 64 / kRPW lanes, whose first lane writes it.  The row a lane ends with
+// is (lane / (64 / kRPW)) in the wavefront's row order.
+// Columns: over the lane's rows in order, then the 4 wavefronts in order.
 __device__ __forceinline__ void write_partials(const RookArgs& a, int tr, int tc, int lane, int wave,
-                                               const int (&iw)[4], const bool (&ok)[4], const float (&yn)[4],
-                                               double (*pc)[kTC], int (*pcs)[kTC]) {
-    double val[4];
-    unsigned long long selm[4];
+                                               const int (&iw)[kRPW], const bool (&ok)[kRPW],
+                                               const float (&yn)[kRPW], double (*pc)[kTC], int (*pcs)[kTC]) {
+    constexpr int GRP = 64 / kRPW;  // lanes per row after the splitting stages
+    double cur[kRPW];
+    unsigned selbits = 0u;          // bit m: some entry of row m is selected (uniform)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        val[m] = ok[m] ? (double)fabsf(yn[m]) : 0.0;
-        selm[m] = __ballot(ok[m] && gnk::sign_of(yn[m]));
+    for (int m = 0; m < kRPW; ++m) {
+        cur[m] = ok[m] ? (double)fabsf(yn[m]) : 0.0;
+        selbits |= __ballot(ok[m] && gnk::sign_of(yn[m])) != 0ull ? 1u << m : 0u;
     }
-    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
-    const double k0 = (b5 ? val[2] : val[0]) + __shfl_xor(b5 ? val[0] : val[2], 32, 64);
-    const double k1 = (b5 ? val[3] : val[1]) + __shfl_xor(b5 ? val[1] : val[3], 32, 64);
-    double r = (b4 ? k1 : k0) + __shfl_xor(b4 ? k0 : k1, 16, 64);
+    // both pair sums are formed and one is selected: selecting the operand
+    // instead would let the compiler turn it into a lane-dependent index into
+    // cur[], which it lowers to a compare-and-select per element
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
-    if ((lane & 15) == 0) {
-        const int m = (b5 ? 2 : 0) + (b4 ? 1 : 0);
-        if (iw[m] < a.rows) a.rp_out[(size_t)iw[m] * a.ntc + tc] = encode(r, selm[m] != 0ull);
+    for (int h = kRPW / 2, off = 32; h >= 1; h >>= 1, off >>= 1) {
+        const bool up = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const double lo = cur[i] + __shfl_xor(cur[i], off, 64);
+            const double hi = cur[h + i] + __shfl_xor(cur[h + i], off, 64);
+            cur[i] = up ? hi : lo;
+        }
+    }
+    double r = cur[0];
+#pragma unroll
+    for (int off = GRP / 2; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
+    if ((lane & (GRP - 1)) == 0) {
+        // the lane's row, computed rather than looked up (a lane-dependent index
+        // into a register array costs a compare-and-select per element)
+        const int m = lane / GRP;
+        const int i = tr * kTR + wave + kWaves * m;
+        if (i < a.rows) a.rp_out[(size_t)i * a.ntc + tc] = encode(r, ((selbits >> m) & 1u) != 0u);
     }
     double cacc = 0.0;
     int csel = 0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < kRPW; ++m)
         if (ok[m]) {
             cacc += (double)fabsf(yn[m]);
             csel |= (int)gnk::sign_of(yn[m]);
@@ -113,13 +132,13 @@ __global__ __launch_bounds__(kBlock) void rook_prep_kernel(RookArgs a) {
     const int tr = blockIdx.x / a.ntc, tc = blockIdx.x - tr * a.ntc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = tc * kTC + lane;
-    int iw[4];
-    bool ok[4];
-    float yn[4];
+    int iw[kRPW];
+    bool ok[kRPW];
+    float yn[kRPW];
     bool bad = false;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        iw[m] = tr * kTR + wave + 4 * m;
+    for (int m = 0; m < kRPW; ++m) {
+        iw[m] = tr * kTR + wave + kWaves * m;
         ok[m] = j < a.cols && iw[m] < a.rows;
         yn[m] = 0.0f;
         if (ok[m]) {
@@ -182,8 +201,8 @@ template <bool FUSED>
 __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     __shared__ double sC[kWaves][kTC];
     __shared__ int sCs[kWaves][kTC];
-    __shared__ double sR[kTR][16];
-    __shared__ int sRs[kTR][16];
+    __shared__ double sR[kTR][kRowThreads];
+    __shared__ int sRs[kTR][kRowThreads];
     __shared__ double fC[kTC];
     __shared__ int fCs[kTC];
     __shared__ double fR[kTR];
@@ -196,12 +215,12 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     const int tr = blockIdx.x / a.ntc, tc = blockIdx.x - tr * a.ntc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = tc * kTC + lane;
-    int iw[4];
-    bool ok[4];
-    float yraw[4], vi[4];
+    int iw[kRPW];
+    bool ok[kRPW];
+    float yraw[kRPW], vi[kRPW];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        iw[m] = tr * kTR + wave + 4 * m;
+    for (int m = 0; m < kRPW; ++m) {
+        iw[m] = tr * kTR + wave + kWaves * m;
         ok[m] = j < a.cols && iw[m] < a.rows;
         yraw[m] = 0.0f;
         vi[m] = 1.0f;
@@ -214,8 +233,9 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     StepCtl<RookArgs> c;
     if (FUSED) {
         // column sums of this tile's 64 columns: 4 threads per column, each over a
-        // contiguous quarter of the tile rows; row sums of its 16 rows: 16 threads
-        // per row, each over a contiguous sixteenth of the tile columns
+        // contiguous quarter of the tile rows; row sums of its kTR rows:
+        // kRowThreads threads per row, each over a contiguous share of the tile
+        // columns
         {
             const int cc = threadIdx.x & 63, q = threadIdx.x >> 6;
             const int jj = tc * kTC + cc;
@@ -233,9 +253,9 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
             sCs[q][cc] = sl;
         }
         {
-            const int r = threadIdx.x >> 4, u = threadIdx.x & 15;
+            const int r = threadIdx.x / kRowThreads, u = threadIdx.x % kRowThreads;
             const int ii = tr * kTR + r;
-            const int per = (a.ntc + 15) >> 4;
+            const int per = (a.ntc + kRowThreads - 1) / kRowThreads;
             const int t0 = u * per, t1 = min(a.ntc, t0 + per);
             double acc = 0.0;
             int sl = 0;
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
             const int r = threadIdx.x - kTC;
             double t = sR[r][0];
             int sl = sRs[r][0];
-            for (int u = 1; u < 16; ++u) {
+            for (int u = 1; u < kRowThreads; ++u) {
                 t += sR[r][u];
                 sl |= sRs[r][u];
             }
@@ -296,14 +316,14 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     // every lane computes all 4 entries (entries outside the matrix hold y = 0,
     // v = 1 and are masked out of stores, flags and partials), so the loop has
     // no divergent branches
-    float yn[4];
+    float yn[kRPW];
     int viol = 0, fb = 0;
     bool unnormalizable = false;
     const double C = fC[lane];
     const bool csel = fCs[lane] != 0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const double R = fR[wave + 4 * m];
+    for (int m = 0; m < kRPW; ++m) {
+        const double R = fR[wave + kWaves * m];
         const float yi = fabsf(yraw[m]);
         const float sigma = (float)((R - (double)yi) + (C - (double)yi));
         const float s = __fmaf_rn(c.g, sigma, yi);
@@ -320,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
         fb += (c.do_write && ok[m] && fallback) ? 1 : 0;
         if (c.solve && c.k == 0 && ok[m] && yi == 0.0f && R == 0.0 && C == 0.0) unnormalizable = true;
         const bool in_s = gnk::sign_of(yraw[m]) != 0u;
-        const bool nbr_sel = fRs[wave + 4 * m] != 0 || csel;
+        const bool nbr_sel = fRs[wave + kWaves * m] != 0 || csel;
         const float tv = c.tau * vi[m];
         const bool far = (yi > tv) && ((vi[m] - yi) > tv);
         const bool uncovered = !in_s && !nbr_sel;
@@ -332,8 +352,10 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
 
     if (a.solve) {
         const bool wv = __ballot(viol != 0) != 0ull;
-        // fb is 0..4 per lane: three ballots count it over the wavefront
-        const int wf = __popcll(__ballot(fb & 1)) + 2 * __popcll(__ballot(fb & 2)) + 4 * __popcll(__ballot(fb & 4));
+        // fb is 0..kRPW per lane: one ballot per bit counts it over the wavefront
+        int wf = 0;
+#pragma unroll
+        for (int bit = 1; bit <= kRPW; bit <<= 1) wf += bit * __popcll(__ballot(fb & bit));
         if (lane == 0) {
             s_viol[wave] = wv ? 1 : 0;
             s_fb[wave] = wf;
@@ -398,21 +420,61 @@ __global__ __launch_bounds__(kBlock) void rook_rows_kernel(int32_t rows, int32_t
     block_reduce_store(p, out);
 }
 
-// columns: one thread per column, rows in order.
-__global__ __launch_bounds__(kBlock) void rook_cols_kernel(int32_t rows, int32_t cols, const uint8_t* __restrict__ sel,
-                                                           const float* __restrict__ v, int32_t* __restrict__ ccnt,
+// columns, first pass: block b covers column group g = b mod ncg (columns 64g ..
+// 64g+63, one lane each) and row block y = b / ncg (rows kColRows*y ..
+// +kColRows; a 1-D grid, so neither count is bounded by the y grid limit);
+// wavefront w takes a contiguous quarter of
+// those rows in order, and the 4 wavefronts combine in order.  Per (row block,
+// column): the selected count and the sum of v over the selected entries.
+constexpr int kColRows = 64;
+__global__ __launch_bounds__(kBlock) void rook_cols_part_kernel(int32_t rows, int32_t cols, int32_t ncg,
+                                                                const uint8_t* __restrict__ sel,
+                                                                const float* __restrict__ v, int32_t* __restrict__ pcnt,
+                                                                float* __restrict__ pvs) {
+    __shared__ int s_cnt[kWaves][64];
+    __shared__ float s_vs[kWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = (int)(blockIdx.x % (unsigned)ncg), y = (int)(blockIdx.x / (unsigned)ncg);
+    const int j = g * 64 + lane;
+    constexpr int per = kColRows / kWaves;
+    const int i0 = y * kColRows + wave * per;
+    const int i1 = min(rows, i0 + per);
+    int cnt = 0;
+    float vs = 0.0f;
+    if (j < cols)
+        for (int i = i0; i < i1; ++i) {
+            const size_t e = (size_t)i * cols + j;
+            if (sel[e]) {
+                cnt += 1;
+                vs += v[e];
+            }
+        }
+    s_cnt[wave][lane] = cnt;
+    s_vs[wave][lane] = vs;
+    __syncthreads();
+    if (wave == 0 && j < cols) {
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            cnt += s_cnt[w][lane];
+            vs += s_vs[w][lane];
+        }
+        pcnt[(size_t)y * cols + j] = cnt;
+        pvs[(size_t)y * cols + j] = vs;
+    }
+}
+
+// columns, second pass: one thread per column adds its row blocks in order.
+__global__ __launch_bounds__(kBlock) void rook_cols_kernel(int32_t cols, int32_t nrb, const int32_t* __restrict__ pcnt,
+                                                           const float* __restrict__ pvs, int32_t* __restrict__ ccnt,
                                                            float* __restrict__ cvs, Partial* out) {
     Partial p{0.0, 0.0, 0, 0, 0, INFINITY, 0};
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j < cols) {
         long long cnt = 0;
         float vs = 0.0f;
-        for (int i = 0; i < rows; ++i) {
-            const size_t e = (size_t)i * cols + j;
-            if (sel[e]) {
-                cnt += 1;
-                vs += v[e];
-            }
+        for (int b = 0; b < nrb; ++b) {
+            cnt += pcnt[(size_t)b * cols + j];
+            vs += pvs[(size_t)b * cols + j];
         }
         ccnt[j] = (int32_t)cnt;
         cvs[j] = vs;
@@ -456,6 +518,8 @@ struct gn_rook {
     int32_t* ccnt = nullptr;
     float* rvs = nullptr;
     float* cvs = nullptr;
+    int32_t* colpart_cnt = nullptr;  // [ceil(rows / kColRows)][cols] per row block
+    float* colpart_vs = nullptr;
     Partial* partials = nullptr;
     int32_t npartials = 0;
     GraphWorkspace ws;
@@ -464,7 +528,7 @@ struct gn_rook {
 static void rook_free(gn_rook* r) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(r->w); f(r->v); f(r->rpart[0]); f(r->rpart[1]); f(r->cpart[0]); f(r->cpart[1]); f(r->rsum); f(r->csum);
-    f(r->rcnt); f(r->ccnt); f(r->rvs); f(r->cvs); f(r->partials);
+    f(r->rcnt); f(r->ccnt); f(r->rvs); f(r->cvs); f(r->colpart_cnt); f(r->colpart_vs); f(r->partials);
     GraphWorkspace& ws = r->ws;
     for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
     ws.chunks.clear();
@@ -533,6 +597,8 @@ extern "C" gn_status gn_rook_create(int32_t rows, int32_t cols, const float* w, 
               rook_alloc(&r->rsum, rows) && rook_alloc(&r->csum, cols) &&
               rook_alloc(&r->rcnt, rows) && rook_alloc(&r->ccnt, cols) && rook_alloc(&r->rvs, rows) &&
               rook_alloc(&r->cvs, cols) && rook_alloc(&r->partials, (size_t)r->npartials) &&
+              rook_alloc(&r->colpart_cnt, (size_t)((rows + kColRows - 1) / kColRows) * cols) &&
+              rook_alloc(&r->colpart_vs, (size_t)((rows + kColRows - 1) / kColRows) * cols) &&
               rook_alloc(&ws.y[0], n) && rook_alloc(&ws.y[1], n) && rook_alloc(&ws.state, 1) &&
               rook_alloc((FinalStats**)&ws.final_out, 1);
     if (ok && hipHostMalloc(&ws.host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -656,8 +722,14 @@ static gn_status rook_final_stats(gn_rook* r, const float* y, float gamma_fin, f
     hipLaunchKernelGGL(rook_rows_kernel, dim3(nbr), dim3(kBlock), 0, s, r->rows, r->cols, y, r->v, r->w, x, sel,
                        r->rcnt, r->rvs, r->partials);
     GN_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(rook_cols_kernel, dim3(nbc), dim3(kBlock), 0, s, r->rows, r->cols, (const uint8_t*)sel, r->v,
-                       r->ccnt, r->cvs, r->partials + nbr);
+    const int32_t nrb = (r->rows + kColRows - 1) / kColRows;
+    const int32_t ncg = (r->cols + 63) / 64;
+    hipLaunchKernelGGL(rook_cols_part_kernel, dim3((unsigned)((int64_t)ncg * nrb)), dim3(kBlock), 0, s, r->rows,
+                       r->cols, ncg, (const uint8_t*)sel, r->v, r->colpart_cnt, r->colpart_vs);
+    GN_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(rook_cols_kernel, dim3(nbc), dim3(kBlock), 0, s, r->cols, nrb,
+                       (const int32_t*)r->colpart_cnt, (const float*)r->colpart_vs, r->ccnt, r->cvs,
+                       r->partials + nbr);
     GN_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(rook_cover_kernel, dim3(nbe), dim3(kBlock), 0, s, r->rows, r->cols, (const uint8_t*)sel, r->v,
                        (const int32_t*)r->rcnt, (const float*)r->rvs, (const int32_t*)r->ccnt, (const float*)r->cvs,
