@@ -198,7 +198,11 @@ def test_errors(gpu):
     assert e.value.status == libgn.GN_E_ARG
 
 
-SPLIT = (520, 200)  # large enough that each step runs as a reduction kernel plus the step kernel
+# large enough that each step runs as a reduction kernel plus the step kernel: with
+# 32 x 64 tiles the tiles' re-reads of the partial sums exceed 16 bytes per entry
+# when cols / 2 + 2 rows > 4096
+SPLIT = (2100, 12)
+assert SPLIT[1] / 2 + 2 * SPLIT[0] > 4096
 
 
 def test_step_split_form_matches_oracle(gpu):
@@ -208,7 +212,7 @@ def test_step_split_form_matches_oracle(gpu):
 
 
 def test_solve_split_form_matches_csr_path(gpu):
-    """The split form against the CSR solver on the same 74.7M-entry rook graph."""
+    """The split form against the CSR solver on the same 53.2M-entry rook graph."""
     import torch
     rows, cols = SPLIT
     w = I.rook_weights_rect(rows, cols, 12)
