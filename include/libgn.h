@@ -168,8 +168,9 @@ typedef struct {
     int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1 .. 4 (1 .. 2 with 1024) */
     int32_t lds_vertices;    /* LDS per workgroup = 12 * lds_vertices bytes, and
                                 lds_vertices * 12 * blocks_per_cu <= 158 KiB.  A graph with
-                                16 n + 4 + 4 nnz bytes <= that keeps y, v and its CSR in LDS;
-                                else, with n <= lds_vertices, y and v; else neither          */
+                                16 n + 4 + 2 nnz bytes <= that keeps y, v and its CSR (16-bit
+                                column ids) in LDS; else, with n <= lds_vertices, y and v;
+                                else neither                                                 */
     int32_t reserved;
 } gn_tuning;
 
