@@ -105,6 +105,36 @@ def test_step_full_size_256(gpu):
     _step_parity(256, 256, w.reshape(256, 256), 1.2, _state(256 * 256, 9))
 
 
+def test_step_4096_sampled_entries(gpu):
+    """The benchmark's 4096 x 4096 instance (split form), one step from a random
+    state: 24 sampled entries against the oracle's step on each entry's star graph
+    (the entry and its 8190 row and column mates), whose centre sees exactly its
+    closed neighbourhood in the full instance."""
+    import torch
+    N = 4096
+    w = I.rook_weights_rect(N, N, 0)
+    x = _state(N * N, 21, zeros=0.05)
+    R = _lib().Rook(N, N, w)
+    xd = dev(x)
+    out = torch.empty_like(xd)
+    gamma = F32(1.3)
+    R.step(gamma, xd, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    wf, xf = w.reshape(-1).astype(np.float64), x.astype(np.float64)
+    rng = I.rng_for(22, 79)
+    for _ in range(24):
+        i, j = (int(t) for t in rng.integers(0, N, size=2))
+        mates = np.concatenate([i * N + np.delete(np.arange(N), j), np.delete(np.arange(N), i) * N + j])
+        ids = np.concatenate([[i * N + j], mates])
+        m = len(mates)
+        rp = np.concatenate([[0, m], m + np.arange(1, m + 1)]).astype(np.int32)
+        ci = np.concatenate([np.arange(1, m + 1), np.zeros(m)]).astype(np.int32)
+        ref, _ = O.step(m + 1, rp, ci, wf[ids], float(gamma), xf[ids])
+        e = i * N + j
+        assert abs(got[e] - ref[0]) <= 1e-5 * abs(ref[0]) + 1e-7, (i, j, got[e], ref[0])
+
+
 def _solve(rows, cols, w, x0, **sch):
     import torch
     R = _lib().Rook(rows, cols, w)
