@@ -318,7 +318,9 @@ def bench_warm():
 def bench_grad():
     """Differentiable GN: 256 unit-disk graphs n = 2000 (mean degree 10) as one
     block-diagonal graph, w ~ U(0.5, 1.5] requiring grad, T = 50 steps at gamma 1.5,
-    L = w . x_T, checkpoint every 10 steps: forward + adjoint time."""
+    L = w . x_T: forward + adjoint time with a checkpoint every 10 steps (the
+    backward recomputes each segment), and with y and s of every step kept
+    (ckpt_every = 1: 2 T n floats, no recompute)."""
     import torch
     from paper_2605_05330_amd import inputs as I
     from paper_2605_05330_amd import libgn
@@ -329,21 +331,24 @@ def bench_grad():
     h = B.graph_handle()
     w0 = torch.tensor(np.concatenate(ws), device="cuda")
     gam = np.full(50, 1.5, np.float32)
-    def once():
+    def once(K):
         w = w0.clone().requires_grad_(True)
         x0 = torch.full_like(w0, 0.5)
-        xT = gn_unrolled(w, x0, h, gam, 10)
+        xT = gn_unrolled(w, x0, h, gam, K)
         (w * xT).sum().backward()
         return w.grad
-    once()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        once()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / 5
+    def timed(K):
+        once(K)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            once(K)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 5
+    ms = timed(10)
+    ms_stored = timed(1)  # y and s of every step kept (2 T n floats): no recompute
     nnz = sum(g.nnz for g in gs)
     n = int(w0.numel())
     T = 50
@@ -353,7 +358,8 @@ def bench_grad():
     b_adj = 4 * (n + 1) + 4 * nnz + 32 * n
     total = T * b_step + T * (b_step + 8 * n) + T * b_adj
     return {"graphs": 256, "vertices": n, "edges": nnz // 2, "T": T, "ckpt_every": 10,
-            "fwd_bwd_ms": ms, "edges_iters_per_s": (nnz // 2) * T * 3 / (ms / 1e3),
+            "fwd_bwd_ms": ms, "fwd_bwd_ms_all_states_kept": ms_stored,
+            "edges_iters_per_s": (nnz // 2) * T * 3 / (ms / 1e3),
             "algorithmic_bytes": total, "GBs": total / (ms / 1e3) / 1e9,
             "hbm_frac": total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "note": "edge-iterations count forward, recompute and adjoint passes (3 per step)"}

@@ -221,8 +221,10 @@ const gn_graph* gn_batch_graph(const gn_batch* b);
  * ------------------------------------------------------------------------- */
 
 /* Floats of checkpoint storage needed for T steps checkpointed every
- * ckpt_every steps (ceil(T / ckpt_every) states of n floats; n when T = 0).
- * Returns -1 on bad arguments. */
+ * ckpt_every steps: ceil(T / ckpt_every) states of n floats (n when T = 0).
+ * ckpt_every = 1 keeps instead y and the closed sums s of every step,
+ * 2 T n floats, and the backward then recomputes nothing.  Returns -1 on bad
+ * arguments. */
 int64_t gn_unrolled_ckpt_floats(const gn_graph* g, int32_t T, int32_t ckpt_every);
 
 /* Run T steps x^{k+1} = N_{gamma_k}(x^k) (no stopping test) from x0.
@@ -238,7 +240,8 @@ gn_status gn_unrolled_forward(const gn_graph* g, const float* w, const float* ga
  * g, w, gammas, T, ckpt_every and its ckpt): gw = dL/dw through the dynamics
  * (a direct dependence of L on w, e.g. L = w . x^T, is the caller's to add),
  * gx0 = dL/dx0.  gxT, gw, gx0: device float[n], user order.  Segments of
- * ckpt_every steps are recomputed from the checkpoints.  ASYNC. */
+ * ckpt_every steps are recomputed from the checkpoints (no recompute when
+ * ckpt_every = 1).  The result does not depend on ckpt_every.  ASYNC. */
 gn_status gn_unrolled_backward(const gn_graph* g, const float* w, const float* gammas, int32_t T,
                                int32_t ckpt_every, const float* ckpt, const float* gxT, float* gw, float* gx0,
                                hipStream_t stream);

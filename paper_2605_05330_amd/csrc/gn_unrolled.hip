@@ -264,8 +264,10 @@ void gn_internal_free_unrolled(gn_graph* g) {
 
 extern "C" int64_t gn_unrolled_ckpt_floats(const gn_graph* g, int32_t T, int32_t ckpt_every) {
     if (!g || T < 0 || ckpt_every < 1) return -1;
+    const int64_t n = std::max(g->n, 1);
+    if (T >= 1 && ckpt_every == 1) return 2 * (int64_t)T * n;  // y and s of every step: no recompute
     const int64_t segs = T == 0 ? 1 : (T + ckpt_every - 1) / ckpt_every;
-    return segs * (int64_t)std::max(g->n, 1);
+    return segs * n;
 }
 
 extern "C" gn_status gn_unrolled_forward(const gn_graph* g, const float* w, const float* gammas, int32_t T,
@@ -280,6 +282,24 @@ extern "C" gn_status gn_unrolled_forward(const gn_graph* g, const float* w, cons
     if (!u) return GN_E_NOMEM;
     const float* v = weights_v(g, u, w, stream);
     GN_HIP_TRY(hipGetLastError());
+    if (T >= 1 && ckpt_every == 1) {
+        // every step's y and s go straight into ckpt ([T][n] y, then [T][n] s),
+        // so the backward recomputes nothing
+        hipLaunchKernelGGL(weighted_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, x0, g->perm, v,
+                           ckpt);
+        GN_HIP_TRY(hipGetLastError());
+        for (int32_t t = 0; t < T; ++t) {
+            StepArgs a = fwd_args(g, v);
+            a.y_in = ckpt + (size_t)t * n;
+            a.y_out = t + 1 < T ? ckpt + (size_t)(t + 1) * n : u->y[0];
+            a.s_out = ckpt + (size_t)(T + t) * n;
+            a.gamma_scalar = gammas[t];
+            a.x_out_user = t == T - 1 ? xT : nullptr;
+            st = gn_internal_launch_step(g, a, stream);
+            if (st != GN_OK) return st;
+        }
+        return GN_OK;
+    }
     hipLaunchKernelGGL(weighted_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, x0, g->perm, v, u->y[0]);
     GN_HIP_TRY(hipGetLastError());
     GN_HIP_TRY(hipMemcpyAsync(ckpt, u->y[0], sizeof(float) * n, hipMemcpyDeviceToDevice, stream));
@@ -321,23 +341,32 @@ extern "C" gn_status gn_unrolled_backward(const gn_graph* g, const float* w, con
     hipLaunchKernelGGL(fill_kernel, eg, eb, 0, stream, (int64_t)n, u->gv, 0.0f);
     GN_HIP_TRY(hipGetLastError());
     const int nblk = gn_internal_grid_blocks(g->bins);
-    const int32_t nseg = (T + K - 1) / K;
+    // ckpt_every = 1: the forward kept y and s of every step, and the whole run is
+    // one segment that needs no recompute
+    const bool stored = K == 1;
+    const int32_t seglen = stored ? T : K;
+    const int32_t nseg = (T + seglen - 1) / seglen;
     for (int32_t c = nseg - 1; c >= 0; --c) {
-        const int32_t t0 = c * K, t1 = std::min(T, t0 + K);
-        // recompute the segment from its checkpoint, keeping y^t and s^t
-        GN_HIP_TRY(hipMemcpyAsync(u->seg_y, ckpt + (size_t)c * n, sizeof(float) * n, hipMemcpyDeviceToDevice, stream));
-        for (int32_t t = t0; t < t1; ++t) {
-            StepArgs a = fwd_args(g, v);
-            a.y_in = u->seg_y + (size_t)(t - t0) * n;
-            a.y_out = t + 1 < t1 ? u->seg_y + (size_t)(t + 1 - t0) * n : u->y[0];
-            a.s_out = u->seg_s + (size_t)(t - t0) * n;
-            a.gamma_scalar = gammas[t];
-            st = gn_internal_launch_step(g, a, stream);
-            if (st != GN_OK) return st;
+        const int32_t t0 = c * seglen, t1 = std::min(T, t0 + seglen);
+        const float* sy = stored ? ckpt : u->seg_y;                 // y^t at sy + (t - t0) n
+        const float* ss = stored ? ckpt + (size_t)T * n : u->seg_s;  // s^t likewise
+        if (!stored) {
+            // recompute the segment from its checkpoint, keeping y^t and s^t
+            GN_HIP_TRY(hipMemcpyAsync(u->seg_y, ckpt + (size_t)c * n, sizeof(float) * n, hipMemcpyDeviceToDevice,
+                                      stream));
+            for (int32_t t = t0; t < t1; ++t) {
+                StepArgs a = fwd_args(g, v);
+                a.y_in = u->seg_y + (size_t)(t - t0) * n;
+                a.y_out = t + 1 < t1 ? u->seg_y + (size_t)(t + 1 - t0) * n : u->y[0];
+                a.s_out = u->seg_s + (size_t)(t - t0) * n;
+                a.gamma_scalar = gammas[t];
+                st = gn_internal_launch_step(g, a, stream);
+                if (st != GN_OK) return st;
+            }
         }
         int tc = 0;
-        hipLaunchKernelGGL(adjoint_seed_kernel, eg, eb, 0, stream, n, u->gb[cur], u->seg_y + (size_t)(t1 - 1 - t0) * n,
-                           u->seg_s + (size_t)(t1 - 1 - t0) * n, u->tt[tc]);
+        hipLaunchKernelGGL(adjoint_seed_kernel, eg, eb, 0, stream, n, u->gb[cur], sy + (size_t)(t1 - 1 - t0) * n,
+                           ss + (size_t)(t1 - 1 - t0) * n, u->tt[tc]);
         GN_HIP_TRY(hipGetLastError());
         for (int32_t t = t1 - 1; t >= t0; --t) {
             AdjArgs a{};
@@ -352,10 +381,10 @@ extern "C" gn_status gn_unrolled_backward(const gn_graph* g, const float* w, con
             a.gb_in = u->gb[cur];
             a.gb_out = u->gb[cur ^ 1];
             a.gv = u->gv;
-            a.y_k = u->seg_y + (size_t)(t - t0) * n;
-            a.s_k = u->seg_s + (size_t)(t - t0) * n;
-            a.y_p = t - 1 >= t0 ? u->seg_y + (size_t)(t - 1 - t0) * n : nullptr;
-            a.s_p = t - 1 >= t0 ? u->seg_s + (size_t)(t - 1 - t0) * n : nullptr;
+            a.y_k = sy + (size_t)(t - t0) * n;
+            a.s_k = ss + (size_t)(t - t0) * n;
+            a.y_p = t - 1 >= t0 ? sy + (size_t)(t - 1 - t0) * n : nullptr;
+            a.s_p = t - 1 >= t0 ? ss + (size_t)(t - 1 - t0) * n : nullptr;
             a.gamma = gammas[t];
             if (nblk > 0) hipLaunchKernelGGL(wrgn_adjoint_kernel, dim3(nblk), dim3(kBlock), 0, stream, a);
             GN_HIP_TRY(hipGetLastError());
