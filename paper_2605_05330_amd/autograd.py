@@ -38,6 +38,23 @@ class GNUnrolled(torch.autograd.Function):
         return gw, gx0, None, None, None
 
 
-def gn_unrolled(w, x0, graph_handle, gammas, ckpt_every=10):
-    """x_T after len(gammas) WRGN steps from x0 with weights w (differentiable in w, x0)."""
+# default memory for keeping every step's y and s (ckpt_every = 1, no recompute in
+# the backward); above it the default checkpoints every ~sqrt(T) steps
+KEEP_ALL_BYTES = 1 << 30
+
+
+def default_ckpt_every(n: int, T: int) -> int:
+    """1 (keep y and s of every step, 8 T n bytes) while that fits KEEP_ALL_BYTES,
+    else ceil(sqrt(T)) (about 2 sqrt(T) n floats of checkpoints and segments)."""
+    if T <= 1 or 8 * T * n <= KEEP_ALL_BYTES:
+        return 1
+    return int(np.ceil(np.sqrt(T)))
+
+
+def gn_unrolled(w, x0, graph_handle, gammas, ckpt_every=None):
+    """x_T after len(gammas) WRGN steps from x0 with weights w (differentiable in w, x0).
+    ckpt_every: checkpoint interval of the backward's recompute; None picks
+    default_ckpt_every.  The gradient does not depend on it."""
+    if ckpt_every is None:
+        ckpt_every = default_ckpt_every(int(x0.numel()), len(gammas))
     return GNUnrolled.apply(w, x0, graph_handle, gammas, ckpt_every)

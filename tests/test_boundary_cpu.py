@@ -157,3 +157,13 @@ def test_batch_results_view():
     with pytest.raises(IndexError):
         res[5]
     assert all(r.status == libgn.GN_OK for r in res)
+
+
+def test_default_checkpoint_interval():
+    """The differentiable layer keeps every state while 8 T n bytes fit the budget,
+    else checkpoints every ceil(sqrt(T)) steps."""
+    from paper_2605_05330_amd import autograd as A
+    assert A.default_ckpt_every(512_000, 50) == 1          # 205 MB
+    assert A.default_ckpt_every(10_000_000, 50) == 8       # 4 GB > 1 GiB
+    assert A.default_ckpt_every(10_000_000, 1) == 1
+    assert A.default_ckpt_every(A.KEEP_ALL_BYTES // 8, 1) == 1
