@@ -191,7 +191,9 @@ void gn_batch_destroy(gn_batch* b);
 /* Solve every graph of the batch to binarisation under one schedule.  x_cat:
  * device float[sum n], x^0 on entry (user order within each graph), final
  * states on exit; sel_cat: device uint8[sum n]; res: host gn_result[count].
- * tuning may be NULL (then the cached or default shape is used).  If any
+ * tuning may be NULL (then the cached or default shape is used).  The solve's
+ * launches are kept as one HIP graph in the handle and replayed while the
+ * tuning, schedule and buffers are unchanged.  If any
  * graph's x^0 is negative, non-finite or not normalizable the call returns
  * GN_E_ARG / GN_E_NOT_NORMALIZABLE and leaves x_cat, sel_cat unchanged.
  * Returns GN_OK when every graph binarised, GN_NOT_CONVERGED otherwise.  SYNC. */

@@ -484,17 +484,21 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
 }
 
 template <int BT, bool BIG>
-hipError_t launch_batch(dim3 grid, size_t lds_bytes, hipStream_t s, const BatchArgs& a) {
-    hipLaunchKernelGGL((batch_solve_kernel<BT, BIG>), grid, dim3(BT), lds_bytes, s, a);
-    return hipGetLastError();
-}
-
-template <int BT, bool BIG>
 const void* batch_kernel_ptr() {
     return (const void*)batch_solve_kernel<BT, BIG>;
 }
 
 }  // namespace
+
+// The executable graph of the last solve and what it was built for.
+struct BatchLaunch {
+    hipGraphExec_t exec = nullptr;
+    gn_tuning t{};
+    gn_schedule sch{};
+    const float* x = nullptr;
+    const uint8_t* sel = nullptr;
+    const float* gamma = nullptr;
+};
 
 struct gn_batch {
     int32_t count = 0;
@@ -522,6 +526,7 @@ struct gn_batch {
     BatchRes* res_host = nullptr;  // pinned
     bool tuned = false;
     gn_tuning tuning{};
+    BatchLaunch launch;
     // host copies of the caller's CSR for the block-diagonal union graph
     std::vector<int32_t> h_n;
     std::vector<int64_t> h_nnz;
@@ -535,6 +540,7 @@ static void batch_free(gn_batch* b) {
     f(b->desc); f(b->order); f(b->vgraph); f(b->row_ptr); f(b->col); f(b->v); f(b->w); f(b->perm);
     f(b->yg0); f(b->yg1); f(b->queue); f(b->gamma); f(b->res);
     if (b->res_host) (void)hipHostFree(b->res_host);
+    if (b->launch.exec) (void)hipGraphExecDestroy(b->launch.exec);
     if (b->uni) gn_graph_destroy(b->uni);
 }
 
@@ -762,22 +768,13 @@ static int resident_blocks(int bt, size_t lds_bytes, bool big = false) {
     return std::max(nb, 1);
 }
 
-// Enqueue the whole batched solve (init, x0 checks, persistent kernel).
-static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, float* x_cat, uint8_t* sel_cat,
-                               hipStream_t s) {
+// Host-side preparation of a solve: the gamma table's size and the device
+// processing order for this LDS size (graphs whose state fits first, then the
+// others, each part most entries first).  May synchronise `s`.
+static gn_status prepare_batch(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, hipStream_t s) {
     gn_status st = ensure_gamma(b, sch->max_steps + 1);
     if (st != GN_OK) return st;
-    hipLaunchKernelGGL(batch_init_kernel, dim3(std::min((sch->max_steps + 1 + 255) / 256, 1024)), dim3(256), 0, s,
-                       b->queue, b->gamma, sch->max_steps, sch->gamma0, sch->gamma1, sch->ramp_steps);
-    GN_HIP_TRY(hipGetLastError());
-    if (b->total_n > 0) {
-        hipLaunchKernelGGL(batch_check_x0_kernel, dim3((unsigned)((b->total_n + 255) / 256)), dim3(256), 0, s,
-                           b->total_n, b->vgraph, b->desc, b->row_ptr, b->col, b->perm, x_cat, b->queue);
-        GN_HIP_TRY(hipGetLastError());
-    }
     if (t.lds_vertices != b->split_lds) {
-        // device order: graphs whose state fits in LDS first, then the others,
-        // each part most entries first
         std::vector<int32_t> split;
         split.reserve(b->h_order.size());
         for (int32_t g : b->h_order)
@@ -789,6 +786,38 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
         GN_HIP_TRY(hipStreamSynchronize(s));  // the host vector goes out of scope
         b->split_lds = t.lds_vertices;
         b->n_fit = nf;
+    }
+    return GN_OK;
+}
+
+// The kernels of one solve in order (init, x0 checks, the persistent launch of
+// the graphs whose state fits in LDS, then the one of the others), handed to
+// `emit(func, grid, block, lds_bytes, args)`: launched directly or added to a HIP
+// graph.  The argument storage lives until the function returns.
+template <typename Emit>
+static gn_status batch_kernels(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, float* x_cat,
+                               uint8_t* sel_cat, Emit&& emit) {
+    {
+        int32_t* queue = b->queue;
+        float* gamma = b->gamma;
+        int32_t ms = sch->max_steps, ramp = sch->ramp_steps;
+        float g0 = sch->gamma0, g1 = sch->gamma1;
+        void* args[] = {&queue, &gamma, &ms, &g0, &g1, &ramp};
+        GN_HIP_TRY(emit((const void*)batch_init_kernel, dim3(std::min((sch->max_steps + 1 + 255) / 256, 1024)),
+                        dim3(256), 0, args));
+    }
+    if (b->total_n > 0) {
+        int64_t total = b->total_n;
+        const int32_t* vgraph = b->vgraph;
+        const BatchDesc* desc = b->desc;
+        const int32_t* rp = b->row_ptr;
+        const int32_t* col = b->col;
+        const int32_t* perm = b->perm;
+        const float* xc = x_cat;
+        int32_t* queue = b->queue;
+        void* args[] = {&total, &vgraph, &desc, &rp, &col, &perm, &xc, &queue};
+        GN_HIP_TRY(emit((const void*)batch_check_x0_kernel, dim3((unsigned)((b->total_n + 255) / 256)), dim3(256), 0,
+                        args));
     }
     BatchArgs a{};
     a.desc = b->desc;
@@ -812,23 +841,88 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
     a.queue = b->queue;
     a.res = b->res;
     const size_t lds = (size_t)t.lds_vertices * 3 * sizeof(float);
-    auto launch = [&](bool big, size_t lds_bytes, int count) -> hipError_t {
-        const int bpc = std::min(t.blocks_per_cu, resident_blocks(t.block_threads, lds_bytes, big));
-        const dim3 grid((unsigned)std::min<int64_t>((int64_t)b->cus * bpc, count));
-        switch (t.block_threads) {
-            case 128: return big ? launch_batch<128, true>(grid, 0, s, a) : launch_batch<128, false>(grid, lds_bytes, s, a);
-            case 512: return big ? launch_batch<512, true>(grid, 0, s, a) : launch_batch<512, false>(grid, lds_bytes, s, a);
-            case 1024: return big ? launch_batch<1024, true>(grid, 0, s, a) : launch_batch<1024, false>(grid, lds_bytes, s, a);
-            default: return big ? launch_batch<256, true>(grid, 0, s, a) : launch_batch<256, false>(grid, lds_bytes, s, a);
-        }
-    };
-    if (b->n_fit > 0) GN_HIP_TRY(launch(false, lds, b->n_fit));
-    if (b->n_fit < b->count) {
-        a.order = b->order + b->n_fit;
-        a.count = b->count - b->n_fit;
-        a.qslot = 2;
-        GN_HIP_TRY(launch(true, 0, b->count - b->n_fit));
+    if (b->n_fit > 0) {
+        const int bpc = std::min(t.blocks_per_cu, resident_blocks(t.block_threads, lds, false));
+        void* args[] = {&a};
+        GN_HIP_TRY(emit(batch_kernel(t.block_threads, false),
+                        dim3((unsigned)std::min<int64_t>((int64_t)b->cus * bpc, b->n_fit)), dim3(t.block_threads),
+                        lds, args));
     }
+    if (b->n_fit < b->count) {
+        BatchArgs big = a;
+        big.order = b->order + b->n_fit;
+        big.count = b->count - b->n_fit;
+        big.qslot = 2;
+        const int bpc = std::min(t.blocks_per_cu, resident_blocks(t.block_threads, 0, true));
+        void* args[] = {&big};
+        GN_HIP_TRY(emit(batch_kernel(t.block_threads, true),
+                        dim3((unsigned)std::min<int64_t>((int64_t)b->cus * bpc, big.count)), dim3(t.block_threads), 0,
+                        args));
+    }
+    return GN_OK;
+}
+
+// Enqueue the whole batched solve with direct launches (the autotuner's timing runs).
+static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, float* x_cat, uint8_t* sel_cat,
+                               hipStream_t s) {
+    gn_status st = prepare_batch(b, sch, t, s);
+    if (st != GN_OK) return st;
+    return batch_kernels(b, sch, t, x_cat, sel_cat,
+                         [s](const void* f, dim3 grid, dim3 block, size_t lds, void** args) {
+                             return hipLaunchKernel(f, grid, block, args, lds, s);
+                         });
+}
+
+// The solve as one HIP graph, kept in the handle while the tuning, the
+// schedule, the buffers and the gamma table stay the same; a repeated solve is
+// then a single graph launch.
+static bool same_launch(const BatchLaunch& k, const gn_tuning& t, const gn_schedule* sch, const float* x,
+                        const uint8_t* sel, const float* gamma) {
+    return k.exec && k.t.block_threads == t.block_threads && k.t.blocks_per_cu == t.blocks_per_cu &&
+           k.t.lds_vertices == t.lds_vertices && k.sch.gamma0 == sch->gamma0 && k.sch.gamma1 == sch->gamma1 &&
+           k.sch.ramp_steps == sch->ramp_steps && k.sch.max_steps == sch->max_steps && k.sch.tau == sch->tau &&
+           k.sch.check_every == sch->check_every && k.x == x && k.sel == sel && k.gamma == gamma;
+}
+
+static gn_status launch_batch_graph(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, float* x_cat,
+                                    uint8_t* sel_cat, hipStream_t s) {
+    gn_status st = prepare_batch(b, sch, t, s);
+    if (st != GN_OK) return st;
+    BatchLaunch& k = b->launch;
+    if (!same_launch(k, t, sch, x_cat, sel_cat, b->gamma)) {
+        if (k.exec) (void)hipGraphExecDestroy(k.exec);
+        k.exec = nullptr;
+        hipGraph_t graph;
+        GN_HIP_TRY(hipGraphCreate(&graph, 0));
+        hipGraphNode_t prev = nullptr;
+        st = batch_kernels(b, sch, t, x_cat, sel_cat,
+                           [&](const void* f, dim3 grid, dim3 block, size_t lds, void** args) {
+                               hipKernelNodeParams p{};
+                               p.func = const_cast<void*>(f);
+                               p.gridDim = grid;
+                               p.blockDim = block;
+                               p.sharedMemBytes = (unsigned)lds;
+                               p.kernelParams = args;
+                               p.extra = nullptr;
+                               hipGraphNode_t node;
+                               hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+                               if (e == hipSuccess) prev = node;
+                               return e;
+                           });
+        hipError_t e = st == GN_OK ? hipGraphInstantiate(&k.exec, graph, nullptr, nullptr, 0) : hipSuccess;
+        (void)hipGraphDestroy(graph);
+        if (st != GN_OK) return st;
+        if (e != hipSuccess) {
+            k.exec = nullptr;
+            return GN_E_HIP;
+        }
+        k.t = t;
+        k.sch = *sch;
+        k.x = x_cat;
+        k.sel = sel_cat;
+        k.gamma = b->gamma;
+    }
+    GN_HIP_TRY(hipGraphLaunch(k.exec, s));
     return GN_OK;
 }
 
@@ -853,7 +947,7 @@ extern "C" gn_status gn_batch_solve(gn_batch* b, const gn_schedule* sch, const g
     gn_tuning t = tuning ? *tuning : (b->tuned ? b->tuning : default_tuning(b));
     if (!tuning_valid(t)) return GN_E_ARG;
     allow_lds(t.block_threads, (size_t)t.lds_vertices * 12);
-    st = enqueue_batch(b, sch, t, x_cat, sel_cat, stream);
+    st = launch_batch_graph(b, sch, t, x_cat, sel_cat, stream);
     if (st != GN_OK) return st;
     int32_t qh[2];
     GN_HIP_TRY(hipMemcpyAsync(b->res_host, b->res, sizeof(BatchRes) * b->count, hipMemcpyDeviceToHost, stream));

@@ -170,3 +170,35 @@ def test_batch_full_4096(gpu):
                       tau=float(F32(1e-4)))
         assert np.array_equal(sb[offs[gi]:offs[gi + 1]].astype(bool), ref.sel), gi
         assert abs(res[gi].steps - ref.steps) <= 2
+
+
+def test_batch_graph_reuse(gpu):
+    """gn_batch_solve keeps its launches as one HIP graph while the tuning, the
+    schedule and the buffers stay the same.  A repeated solve (graph replay), a
+    solve into other buffers and one under another schedule (rebuilt graphs), and a
+    return to the first schedule, all give the results of a fresh handle."""
+    import torch
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    tot = sum(g.n for g in gs)
+    short = dict(SCHED, max_steps=60)
+
+    def run(B, sched, x=None, sel=None):
+        x = torch.full((tot,), 0.5, device="cuda") if x is None else x.fill_(0.5)
+        sel = torch.zeros(tot, dtype=torch.uint8, device="cuda") if sel is None else sel.zero_()
+        st, res = B.solve(x, sel, **sched)
+        return [r.steps for r in res], x.cpu().numpy().copy(), sel.cpu().numpy().copy()
+
+    def same(a, b):
+        return a[0] == b[0] and np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32)) and np.array_equal(a[2], b[2])
+
+    ref = run(lg.Batch.from_graphs(gs, ws), SCHED)
+    ref_short = run(lg.Batch.from_graphs(gs, ws), short)
+    B = lg.Batch.from_graphs(gs, ws)
+    x = torch.empty(tot, device="cuda")
+    sel = torch.empty(tot, dtype=torch.uint8, device="cuda")
+    assert same(run(B, SCHED, x, sel), ref)
+    assert same(run(B, SCHED, x, sel), ref)           # replay of the kept graph
+    assert same(run(B, SCHED), ref)                   # other buffers: rebuilt
+    assert same(run(B, short, x, sel), ref_short)     # other schedule: rebuilt
+    assert same(run(B, SCHED, x, sel), ref)
