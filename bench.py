@@ -470,14 +470,16 @@ def main():
 
     if not a.no_cpu_baseline:
         import oracle as O
+        reps = 3  # about 11 s of host work
         t0 = time.perf_counter()
-        ores = O.solve(g.n, g.row_ptr, g.col_idx, w.astype(np.float64), np.full(g.n, 0.5),
-                       gamma0=float(np.float32(0.9)), gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4)
-        dt = time.perf_counter() - t0
+        for _ in range(reps):
+            ores = O.solve(g.n, g.row_ptr, g.col_idx, w.astype(np.float64), np.full(g.n, 0.5),
+                           gamma0=float(np.float32(0.9)), gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4)
+        dt = (time.perf_counter() - t0) / reps
         out["cpu_baseline"] = {"value": n_edges * ores.steps / dt, "unit": "edges*iters/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": "one full fp64 solve of the same BA n=200000 graph on one host core "
-                                         "(%d steps, %.2f s)" % (ores.steps, dt)}
+                               "sample": "%d full fp64 solves of the same BA n=200000 graph on one host core "
+                                         "(%d steps, %.2f s each)" % (reps, ores.steps, dt)}
     print(json.dumps(out))
 
 
