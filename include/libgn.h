@@ -169,8 +169,9 @@ typedef struct {
     int32_t lds_vertices;    /* LDS per workgroup = 12 * lds_vertices bytes, and
                                 lds_vertices * 12 * blocks_per_cu <= 158 KiB.  A graph with
                                 16 n + 4 + 2 nnz bytes <= that keeps y, v and its CSR (16-bit
-                                column ids) in LDS; else, with n <= lds_vertices, y and v;
-                                else neither                                                 */
+                                column ids) in LDS; else, with 16 n + 4 bytes, y, v and the
+                                row offsets; else, with n <= lds_vertices, y and v; else
+                                neither                                                      */
     int32_t reserved;
 } gn_tuning;
 

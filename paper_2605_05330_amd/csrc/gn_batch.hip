@@ -47,7 +47,8 @@ struct BatchDesc {
 enum BatchMode {
     MODE_GLOBAL = 0,  // state in the global ping-pong buffers, CSR read from global memory
     MODE_STATE = 1,   // y, y' and v in LDS (12 n bytes), CSR read from global memory
-    MODE_ALL = 2      // y, y', v, row_ptr (int32) and columns (uint16) in LDS
+    MODE_ALL = 2,     // y, y', v, row_ptr (int32) and columns (uint16) in LDS
+    MODE_ROWS = 3     // y, y', v and row_ptr in LDS (16 n + 4 bytes), columns read from global memory
 };
 
 // LDS bytes of MODE_ALL: 12 n (y, y', v) + 4 (n + 1) (row_ptr) + 2 nnz (columns);
@@ -186,9 +187,10 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     float* yb = LDS ? lds + n : a.yg1 + d.v_off;
     float* vv = LDS ? lds + 2 * n : const_cast<float*>(a.v) + d.v_off;
     using CT = std::conditional_t<MODE == MODE_ALL, uint16_t, int32_t>;  // column id type
+    constexpr bool RP_LDS = MODE == MODE_ALL || MODE == MODE_ROWS;       // row offsets in LDS
     int32_t* rp_l = reinterpret_cast<int32_t*>(lds + 3 * n);
     uint16_t* col_l = reinterpret_cast<uint16_t*>(rp_l + (n + 1));
-    const int32_t* __restrict__ rp = MODE == MODE_ALL ? rp_l : rp_g;
+    const int32_t* __restrict__ rp = RP_LDS ? rp_l : rp_g;
     const CT* __restrict__ col;
     if constexpr (MODE == MODE_ALL) col = col_l;
     else col = col_g;
@@ -201,8 +203,10 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         ya[i] = x > 0.5f ? -yy : yy;
         if (LDS) vv[i] = vi;
     }
-    if (MODE == MODE_ALL) {
+    if (RP_LDS) {
         for (int i = tid; i <= n; i += BT) rp_l[i] = rp_g[i];
+    }
+    if (MODE == MODE_ALL) {
         for (int e = tid; e < d.nnz; e += BT) col_l[e] = (uint16_t)col_g[e];
     }
     __syncthreads();
@@ -219,18 +223,18 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         bool viol = false;
 #pragma unroll 1
         for (int i = tid; i < d.n_light; i += BT) {
-            const int s0 = MODE == MODE_ALL ? rp[i] : gnk::ld_stream(rp + i);
-            const int dd = (MODE == MODE_ALL ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
+            const int s0 = RP_LDS ? rp[i] : gnk::ld_stream(rp + i);
+            const int dd = (RP_LDS ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
             unsigned sel = 0u;
             const float sigma = gnk::row_sum<1, kLightMaxDeg>(col + s0, dd, yin, 0, sel);
             viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
         }
-        viol |= mid_rows<BT, kMidMaxDeg, MODE != MODE_ALL>(rp, col, yin, vv, yout, d.n_light, d.n_mid, g, do_test, do_write,
+        viol |= mid_rows<BT, kMidMaxDeg, !RP_LDS>(rp, col, yin, vv, yout, d.n_light, d.n_mid, g, do_test, do_write,
                                                a.tau, fb);
 #pragma unroll 1
         for (int i = d.n_mid + wave; i < n; i += BT / 64) {
-            const int s0 = MODE == MODE_ALL ? rp[i] : gnk::ld_stream(rp + i);
-            const int dd = (MODE == MODE_ALL ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
+            const int s0 = RP_LDS ? rp[i] : gnk::ld_stream(rp + i);
+            const int dd = (RP_LDS ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
             unsigned sel = 0u;
             const float sigma = gnk::row_sum_wave<8>(col + s0, dd, yin, lane, sel);
             const bool any_sel = __any(sel != 0u);
@@ -313,8 +317,8 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     __syncthreads();
 }
 
-// The persistent kernel.  BIG = false: graphs whose state fits in LDS (MODE_ALL
-// or MODE_STATE); BIG = true: the graphs above that (MODE_GLOBAL), in a launch of
+// The persistent kernel.  BIG = false: graphs whose state fits in LDS (MODE_ALL,
+// MODE_ROWS or MODE_STATE); BIG = true: the graphs above that (MODE_GLOBAL), in a launch of
 // their own, because the 64-bit gathers of that path would otherwise raise the
 // register count of the common one.
 template <int BT, bool BIG>
@@ -333,8 +337,11 @@ __global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
         if constexpr (BIG) {
             solve_graph<BT, MODE_GLOBAL>(a, d, gi, lds);
         } else {
-            if (all_lds_bytes(d.n, d.nnz) <= 12 * (int64_t)a.lds_vertices)
+            const int64_t lds_bytes = 12 * (int64_t)a.lds_vertices;
+            if (all_lds_bytes(d.n, d.nnz) <= lds_bytes)
                 solve_graph<BT, MODE_ALL>(a, d, gi, lds);
+            else if (16 * (int64_t)d.n + 4 <= lds_bytes)
+                solve_graph<BT, MODE_ROWS>(a, d, gi, lds);
             else
                 solve_graph<BT, MODE_STATE>(a, d, gi, lds);
         }
