@@ -182,6 +182,24 @@ def bench_multistart(G, g, sched, reps, plain_res):
             and res[0].set_objective == plain_res.set_objective}
 
 
+def _sliced_lds_bytes(g) -> int:
+    """LDS bytes of a graph fully resident in the batched kernel: y and y' with
+    their zero slot (8 n + 8), the slice table (4 per slice + 4) and the column
+    lines (128 bytes each).  Rows split into degree classes <= 16, <= 64 and
+    above, each sorted by decreasing degree; slices of 64, 8 and 1 rows; a
+    slice's lines are its widest row's positions, rounded up to even."""
+    d = np.diff(g.row_ptr.astype(np.int64))
+    light = np.sort(d[d <= 16])[::-1]
+    mid = np.sort(d[(d > 16) & (d <= 64)])[::-1]
+    heavy = d[d > 64]
+    even = lambda k: (k + 1) // 2 * 2
+    lines = sum(even(int(light[s])) for s in range(0, len(light), 64))
+    lines += sum(even(-(-int(mid[s]) // 8)) for s in range(0, len(mid), 8))
+    lines += sum(even(-(-int(h) // 64)) for h in heavy)
+    slices = -(-len(light) // 64) + -(-len(mid) // 8) + len(heavy)
+    return 8 * g.n + 12 + 4 * slices + 128 * lines
+
+
 def bench_batch(sched, reps):
     """4,096 graphs, n log-uniform in [50, 5000], half ER (degree 6) half unit-disk
     (degree 10), w ~ U(0,1], x0 = 1/2, same schedule: one persistent launch per
@@ -213,10 +231,10 @@ def bench_batch(sched, reps):
     ms = e0.elapsed_time(e1) / reps
     edge_iters = sum((g.nnz // 2) * r.steps for g, r in zip(gs, res))
     graph_steps = sum(r.steps for r in res)
-    # graphs whose state, row offsets and 16-bit columns fit the workgroup's LDS
+    # graphs whose state, slice table and column lines fit the workgroup's LDS
     # share (12 * lds_vertices bytes) make no global accesses inside their steps
     lds_bytes = 12 * tun.lds_vertices
-    resident = sum(1 for g in gs if 16 * g.n + 4 + 2 * g.nnz <= lds_bytes)
+    resident = sum(1 for g in gs if g.n <= 65535 and _sliced_lds_bytes(g) <= lds_bytes)
     # plain single-graph solves of every 16th graph, scaled to the whole batch
     sample = list(range(0, 4096, 16))
     t_plain = 0.0

@@ -167,11 +167,15 @@ typedef struct {
     int32_t block_threads;   /* threads per workgroup: 128, 256, 512 or 1024                 */
     int32_t blocks_per_cu;   /* persistent workgroups per compute unit: 1 .. 4 (1 .. 2 with 1024) */
     int32_t lds_vertices;    /* LDS per workgroup = 12 * lds_vertices bytes, and
-                                lds_vertices * 12 * blocks_per_cu <= 158 KiB.  A graph with
-                                16 n + 4 + 2 nnz bytes <= that keeps y, v and its CSR (16-bit
-                                column ids) in LDS; else, with 16 n + 4 bytes, y, v and the
-                                row offsets; else, with n <= lds_vertices, y and v; else
-                                neither                                                      */
+                                lds_vertices * 12 * blocks_per_cu <= 158 KiB.  Graphs of at
+                                most 65535 vertices have a sliced column layout: S slices
+                                (64 rows of degree <= 16, 8 rows of degree <= 64, or one
+                                heavier row each) of L lines of 64 16-bit ids in all.  With
+                                8 n + 12 + 4 S + 128 L bytes <= that, a graph keeps its
+                                state, slice table and lines in LDS; else, with
+                                8 n + 12 + 4 S bytes, its state and slice table (the lines
+                                stream from global memory); else, or above 65535 vertices,
+                                it runs from global memory in a launch of its own          */
     int32_t reserved;
 } gn_tuning;
 
@@ -201,9 +205,10 @@ void gn_batch_destroy(gn_batch* b);
 gn_status gn_batch_solve(gn_batch* b, const gn_schedule* sch, const gn_tuning* tuning, float* x_cat,
                          uint8_t* sel_cat, gn_result* res, hipStream_t stream);
 
-/* Time candidate launch shapes on this batch (a bounded number of steps from
- * x0 = 1/2) and return the fastest; the choice is cached in the batch handle
- * and used by later gn_batch_solve calls with tuning == NULL.  SYNC. */
+/* Time candidate launch shapes on this batch (per shape a warm-up run of at
+ * most 64 steps, then one full solve under `sch`, from x0 = 1/2) and return
+ * the fastest; the choice is cached in the batch handle and used by later
+ * gn_batch_solve calls with tuning == NULL.  SYNC. */
 gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_tuning* out, hipStream_t stream);
 
 /* The batch as one block-diagonal graph (vertex ids offset graph by graph),

@@ -3,16 +3,30 @@
 // Components do not interact (Section 2, property iii), so every graph is
 // iterated to its own binarisation by one workgroup: the workgroup pulls a
 // graph from a device work queue (largest graphs first), keeps the graph's
-// weighted state y (ping-pong) and v = sqrt(w) in LDS, and runs the fused WRGN
+// weighted state y (ping-pong) in LDS, and runs the fused WRGN
 // step with a workgroup barrier between steps instead of a grid-wide one.  A
-// graph whose CSR also fits in the workgroup's LDS is copied there once, so its
-// steps touch no global memory; a graph too large for the state falls back to
-// global ping-pong buffers.  Each
-// graph has its own step counter, gamma_k and stopping test; a finished graph
-// frees its workgroup for the next one.  Row sums use the library's canonical
-// order (gn_rowsum.h), so every graph's states, steps and selected set are
-// bit-identical to gn_solve on that graph alone.
+// graph whose column lines also fit in the workgroup's LDS is copied there
+// once, so its steps touch no global memory; a graph too large for the state
+// falls back to global ping-pong buffers.  Each graph has its own step
+// counter, gamma_k and stopping test; a finished graph frees its workgroup for
+// the next one.  Row sums use the library's canonical order (gn_rowsum.h), so
+// every graph's states, steps and selected set are bit-identical to gn_solve
+// on that graph alone.
+//
+// Sliced column layout (graphs of at most 65535 vertices).  Each degree class
+// of rows is cut into slices: 64 light rows (one per lane), 8 mid rows (8 lanes
+// each) or one heavy row (the whole wavefront).  A slice is a run of lines of
+// 64 16-bit ids, an even number of them; in line q, lane l holds entry q of
+// its light row, entry t + 8q of mid row l / 8 (t = l mod 8), or entry l + 64q
+// of the heavy row: the entry that chain q of that thread takes in the
+// canonical order.
+// Positions past a row's end hold n, the id of a state slot that stays zero,
+// so they add exactly 0 and mark no selection.  Rows are sorted by degree
+// inside each class, which keeps the padding small.  A line is read by one
+// 128-byte access, the wavefront needs no row offsets inside a step, and the
+// per-position predicates of the plain CSR walk disappear.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -27,33 +41,45 @@ using gnk::sign_of;
 
 namespace {
 
-constexpr int kLightMaxDeg = 16;  // rows up to this degree run one per thread
-constexpr int kMidMaxDeg = 64;    // rows up to this degree run 8 threads per row (8 rows per wavefront)
+constexpr int kLightMaxDeg = 16;  // rows up to this degree run one per thread (64 rows per slice)
+constexpr int kMidMaxDeg = 64;    // rows up to this degree run 8 threads per row (8 rows per slice)
 constexpr int kLdsBudget = 160 * 1024 - 2048;  // dynamic LDS per CU (static LDS of the kernel set aside)
+constexpr int32_t kMaxSlicedN = 65535;          // largest graph with a sliced layout (ids and the zero slot fit 16 bits)
 
 struct BatchDesc {
     int32_t n;        // vertices
     int32_t n_light;  // internal rows [0, n_light) have degree <= kLightMaxDeg
     int32_t n_mid;    // rows [n_light, n_mid) have degree <= kMidMaxDeg, rows [n_mid, n) more
-    int32_t pad0;
+    int32_t n_lines;  // lines of the sliced layout (0 without one)
     int64_t v_off;    // offset of the graph's vertices in the vertex arrays
     int64_t rp_off;   // offset of its row_ptr (n + 1 entries)
     int64_t e_off;    // offset of its columns
+    int64_t ln_off;   // first line of its sliced layout
+    int64_t so_off;   // offset of its slice table: first line of each slice (relative to ln_off), slices + 1 entries
     int32_t nnz;      // CSR entries
     int32_t pad1;
 };
 
+// Slices of a graph: light slices, then mid slices, then one per heavy row.
+__host__ __device__ inline int32_t slice_count(int32_t n, int32_t nl, int32_t nm) {
+    return (nl + 63) / 64 + (nm - nl + 7) / 8 + (n - nm);
+}
+
+// LDS bytes of a graph in the LDS launch: y and y' (n + 1 words each, the last
+// one the zero slot) and the slice table; MODE_ALL adds the lines.  v is read
+// from global memory: only its own row reads it, once per step, with a load
+// that does not wait on anything else.
+__host__ __device__ inline int64_t state_lds_bytes(int64_t n, int64_t slices) { return 8 * n + 8 + 4 * (slices + 1); }
+__host__ __device__ inline int64_t all_lds_bytes(int64_t n, int64_t slices, int64_t lines) {
+    return state_lds_bytes(n, slices) + 128 * lines;
+}
+
 // Where a graph's arrays live while its workgroup iterates it.
 enum BatchMode {
     MODE_GLOBAL = 0,  // state in the global ping-pong buffers, CSR read from global memory
-    MODE_STATE = 1,   // y, y' and v in LDS (12 n bytes), CSR read from global memory
-    MODE_ALL = 2,     // y, y', v, row_ptr (int32) and columns (uint16) in LDS
-    MODE_ROWS = 3     // y, y', v and row_ptr in LDS (16 n + 4 bytes), columns read from global memory
+    MODE_STREAM = 1,  // state and slice table in LDS, column lines read from global memory
+    MODE_ALL = 2      // state, slice table and column lines in LDS: the steps touch no global memory
 };
-
-// LDS bytes of MODE_ALL: 12 n (y, y', v) + 4 (n + 1) (row_ptr) + 2 nnz (columns);
-// a graph that fits has far fewer than 65536 vertices, so its ids fit in 16 bits.
-__host__ __device__ inline int64_t all_lds_bytes(int64_t n, int64_t nnz) { return 16 * n + 4 + 2 * nnz; }
 
 struct BatchRes {
     int32_t steps, binarised;
@@ -71,6 +97,8 @@ struct BatchArgs {
     int32_t qslot;           // queue counter this launch draws from
     const int32_t* row_ptr;  // internal, per graph
     const int32_t* col;      // internal local ids
+    const uint16_t* lines;   // sliced layouts, 64 ids per line
+    const int32_t* slices;   // slice tables
     const float* v;          // internal order
     const float* w;          // internal order
     const int32_t* perm;     // internal row -> user local id, per graph
@@ -80,7 +108,7 @@ struct BatchArgs {
     int32_t lds_vertices;    // dynamic LDS per workgroup: 12 * lds_vertices bytes
     float* x_cat;            // user order; x0 in, final x out
     uint8_t* sel_cat;
-    float* yg0;              // global ping-pong state for graphs above lds_vertices
+    float* yg0;              // global ping-pong state for the graphs of the global launch
     float* yg1;
     int32_t* queue;          // [0]: next slot of the LDS launch, [1]: error bits, [2]: next slot of the global launch
     BatchRes* res;
@@ -145,9 +173,9 @@ __device__ float block_min_f(float x, float* sm) {
     return r;
 }
 
-// Rows [rb, re) of degree <= MAXD: 8 threads per row, 8 rows per wavefront per
-// round (the loop bound is uniform over the wavefront, as the group shuffles
-// need).  Returns the rows' stopping-test failures.
+// Rows [rb, re) of degree <= MAXD in CSR form: 8 threads per row, 8 rows per
+// wavefront per round (the loop bound is uniform over the wavefront, as the
+// group shuffles need).  Returns the rows' stopping-test failures.
 template <int BT, int MAXD, bool GLOBAL_RP, typename CT>
 __device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const CT* __restrict__ col,
                                          const float* yin, const float* vv, float* yout, int rb, int re, float g,
@@ -171,43 +199,141 @@ __device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const C
     return viol;
 }
 
+// Row sum over the first K lines of a light (G = 1, NQ = 16) or mid (G = 8,
+// NQ = 8) slice in the canonical order: chain q of the thread takes line q, the
+// chains meet in the in-thread butterfly, then the group's shuffles.  `ln`
+// points at this lane's id in the slice's first line; the lines are 64 ids
+// apart.  ORs the raw bits of the gathered values into `bits` (bit 31: some
+// neighbour is selected).  Straight-line code: the K id loads, then the K
+// gathers, each phase back to back.  Chains at or past K are zero, and adding
+// zero to a sum of magnitudes (never -0) changes nothing, so those additions
+// of the butterfly are left out.
+template <int G, int NQ, int K, typename LT>
+__device__ __forceinline__ float slice_sum_k(const LT* __restrict__ ln, const float* __restrict__ y,
+                                             unsigned& bits) {
+    int id[K > 0 ? K : 1];
+    float c[NQ];
+#pragma unroll
+    for (int q = 0; q < K; ++q) id[q] = ln[64 * q];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c[q] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const float yv = y[id[q]];
+        c[q] = fabsf(yv);
+        bits |= __float_as_uint(yv);
+    }
+#pragma unroll
+    for (int h = NQ / 2; h >= 1; h >>= 1)
+#pragma unroll
+        for (int j = 0; j < h; ++j)
+            if (j + h < K) c[j] += c[j + h];
+    float s = c[0];
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+// The same for a slice of W lines, W even (slices are padded to an even number
+// of lines) and uniform over the wavefront: one straight-line variant per W.
+template <int G, int NQ, typename LT>
+__device__ __forceinline__ float slice_sum(const LT* __restrict__ ln, int W, const float* __restrict__ y,
+                                           unsigned& bits) {
+    static_assert(NQ == 8 || NQ == 16, "slice widths");
+    switch (W) {
+        case 2: return slice_sum_k<G, NQ, 2>(ln, y, bits);
+        case 4: return slice_sum_k<G, NQ, 4>(ln, y, bits);
+        case 6: return slice_sum_k<G, NQ, 6>(ln, y, bits);
+        case 8: return slice_sum_k<G, NQ, 8>(ln, y, bits);
+        case 10: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 10>(ln, y, bits); else break;
+        case 12: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 12>(ln, y, bits); else break;
+        case 14: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 14>(ln, y, bits); else break;
+        case 16: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 16>(ln, y, bits); else break;
+        default: break;
+    }
+    return slice_sum_k<G, NQ, 0>(ln, y, bits);
+}
+
+// K lines of a heavy slice added to the lane's chain, in line order.
+template <int K, typename LT>
+__device__ __forceinline__ void heavy_lines(const LT* __restrict__ ln, const float* __restrict__ y, float& acc,
+                                            unsigned& bits) {
+    int id[K];
+    float yv[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) id[q] = ln[64 * q];
+#pragma unroll
+    for (int q = 0; q < K; ++q) yv[q] = y[id[q]];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        acc += fabsf(yv[q]);
+        bits |= __float_as_uint(yv[q]);
+    }
+}
+
+// Row sum over a heavy slice (one row, the whole wavefront; W even): lane l
+// adds entries l + 64q in increasing q (the chain of virtual lane l), eight
+// lines in flight at a time, then the 64-lane butterfly.
+template <typename LT>
+__device__ __forceinline__ float heavy_sum(const LT* __restrict__ ln, int W, const float* __restrict__ y,
+                                           unsigned& bits) {
+    float acc = 0.0f;
+    int q0 = 0;
+#pragma unroll 1
+    for (; q0 + 8 <= W; q0 += 8) heavy_lines<8>(ln + 64 * q0, y, acc, bits);
+    switch (W - q0) {
+        case 2: heavy_lines<2>(ln + 64 * q0, y, acc, bits); break;
+        case 4: heavy_lines<4>(ln + 64 * q0, y, acc, bits); break;
+        case 6: heavy_lines<6>(ln + 64 * q0, y, acc, bits); break;
+        default: break;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return acc;
+}
+
 template <int BT, int MODE>
 __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, float* lds) {
     __shared__ double sm_d[BT / 64];
     __shared__ long long sm_l[BT / 64];
     __shared__ float sm_f[BT / 64];
+    constexpr int NW = BT / 64;
+    constexpr bool SL = MODE != MODE_GLOBAL;  // sliced layout, state in LDS
     const int n = d.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (n == 0) return;  // result filled on the host
     const int32_t* __restrict__ rp_g = a.row_ptr + d.rp_off;
     const int32_t* __restrict__ col_g = a.col + d.e_off;
     const int32_t* __restrict__ perm = a.perm + d.v_off;
-    constexpr bool LDS = MODE != MODE_GLOBAL;
-    float* ya = LDS ? lds : a.yg0 + d.v_off;
-    float* yb = LDS ? lds + n : a.yg1 + d.v_off;
-    float* vv = LDS ? lds + 2 * n : const_cast<float*>(a.v) + d.v_off;
-    using CT = std::conditional_t<MODE == MODE_ALL, uint16_t, int32_t>;  // column id type
-    constexpr bool RP_LDS = MODE == MODE_ALL || MODE == MODE_ROWS;       // row offsets in LDS
-    int32_t* rp_l = reinterpret_cast<int32_t*>(lds + 3 * n);
-    uint16_t* col_l = reinterpret_cast<uint16_t*>(rp_l + (n + 1));
-    const int32_t* __restrict__ rp = RP_LDS ? rp_l : rp_g;
-    const CT* __restrict__ col;
-    if constexpr (MODE == MODE_ALL) col = col_l;
-    else col = col_g;
+    float* ya = SL ? lds : a.yg0 + d.v_off;
+    float* yb = SL ? lds + (n + 1) : a.yg1 + d.v_off;
+    const float* __restrict__ vv = a.v + d.v_off;
+    const int nL = (d.n_light + 63) / 64, nM = (d.n_mid - d.n_light + 7) / 8;
+    const int nS = nL + nM + (n - d.n_mid);
+    int32_t* so = reinterpret_cast<int32_t*>(lds + 2 * n + 2);
+    uint16_t* ln_l = reinterpret_cast<uint16_t*>(so + nS + 1);
+    const uint16_t* __restrict__ ln_g = a.lines + d.ln_off * 64;
+    const uint16_t* __restrict__ ln;
+    if constexpr (MODE == MODE_ALL) ln = ln_l;
+    else ln = ln_g;
     float* xg = a.x_cat + d.v_off;
 
     for (int i = tid; i < n; i += BT) {
-        const float vi = a.v[d.v_off + i];
+        const float vi = vv[i];
         const float x = xg[perm[i]];
         const float yy = vi * x;
         ya[i] = x > 0.5f ? -yy : yy;
-        if (LDS) vv[i] = vi;
     }
-    if (RP_LDS) {
-        for (int i = tid; i <= n; i += BT) rp_l[i] = rp_g[i];
-    }
-    if (MODE == MODE_ALL) {
-        for (int e = tid; e < d.nnz; e += BT) col_l[e] = (uint16_t)col_g[e];
+    if constexpr (SL) {
+        if (tid == 0) {
+            ya[n] = 0.0f;
+            yb[n] = 0.0f;
+        }
+        for (int s = tid; s <= nS; s += BT) so[s] = a.slices[d.so_off + s];
+        if constexpr (MODE == MODE_ALL) {
+            const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(ln_g);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(ln_l);
+            for (int w = tid; w < d.n_lines * 32; w += BT) dst[w] = src[w];
+        }
     }
     __syncthreads();
 
@@ -221,24 +347,62 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         const bool do_write = k < a.max_steps;
         const float g = a.gamma[k];
         bool viol = false;
+        if constexpr (SL) {
 #pragma unroll 1
-        for (int i = tid; i < d.n_light; i += BT) {
-            const int s0 = RP_LDS ? rp[i] : gnk::ld_stream(rp + i);
-            const int dd = (RP_LDS ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
-            unsigned sel = 0u;
-            const float sigma = gnk::row_sum<1, kLightMaxDeg>(col + s0, dd, yin, 0, sel);
-            viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
-        }
-        viol |= mid_rows<BT, kMidMaxDeg, !RP_LDS>(rp, col, yin, vv, yout, d.n_light, d.n_mid, g, do_test, do_write,
-                                               a.tau, fb);
+            for (int s = wave; s < nL; s += NW) {
+                const int i = 64 * s + lane;
+                const bool valid = i < d.n_light;
+                const float vi = valid ? vv[i] : 1.0f;
+                const int o = so[s];
+                const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
+                unsigned bits = 0u;
+                const float sigma = slice_sum<1, kLightMaxDeg>(ln + o * 64 + lane, W, yin, bits);
+                if (valid)
+                    viol |= step_row(yin[i], vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, a.tau, yout, i, fb);
+            }
 #pragma unroll 1
-        for (int i = d.n_mid + wave; i < n; i += BT / 64) {
-            const int s0 = RP_LDS ? rp[i] : gnk::ld_stream(rp + i);
-            const int dd = (RP_LDS ? rp[i + 1] : gnk::ld_stream(rp + i + 1)) - s0;
-            unsigned sel = 0u;
-            const float sigma = gnk::row_sum_wave<8>(col + s0, dd, yin, lane, sel);
-            const bool any_sel = __any(sel != 0u);
-            if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+            for (int s = wave; s < nM; s += NW) {
+                const int i = d.n_light + 8 * s + (lane >> 3);
+                const bool valid = i < d.n_mid && (lane & 7) == 0;
+                const float vi = valid ? vv[i] : 1.0f;
+                const int o = so[nL + s];
+                const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
+                unsigned bits = 0u;
+                const float sigma = slice_sum<8, kMidMaxDeg / 8>(ln + o * 64 + lane, W, yin, bits);
+                const bool any_sel = gnk::group_any<8>((bits >> 31) != 0u);
+                if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+            }
+#pragma unroll 1
+            for (int s = wave; s < n - d.n_mid; s += NW) {
+                const int i = d.n_mid + s;
+                const float vi = lane == 0 ? vv[i] : 1.0f;
+                const int o = so[nL + nM + s];
+                const int W = __builtin_amdgcn_readfirstlane(so[nL + nM + s + 1] - o);
+                unsigned bits = 0u;
+                const float sigma = heavy_sum(ln + o * 64 + lane, W, yin, bits);
+                const bool any_sel = __any((bits >> 31) != 0u);
+                if (lane == 0) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+            }
+        } else {
+#pragma unroll 1
+            for (int i = tid; i < d.n_light; i += BT) {
+                const int s0 = gnk::ld_stream(rp_g + i);
+                const int dd = gnk::ld_stream(rp_g + i + 1) - s0;
+                unsigned sel = 0u;
+                const float sigma = gnk::row_sum<1, kLightMaxDeg>(col_g + s0, dd, yin, 0, sel);
+                viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
+            }
+            viol |= mid_rows<BT, kMidMaxDeg, true>(rp_g, col_g, yin, vv, yout, d.n_light, d.n_mid, g, do_test,
+                                                   do_write, a.tau, fb);
+#pragma unroll 1
+            for (int i = d.n_mid + wave; i < n; i += NW) {
+                const int s0 = gnk::ld_stream(rp_g + i);
+                const int dd = gnk::ld_stream(rp_g + i + 1) - s0;
+                unsigned sel = 0u;
+                const float sigma = gnk::row_sum_wave<8>(col_g + s0, dd, yin, lane, sel);
+                const bool any_sel = __any(sel != 0u);
+                if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+            }
         }
         const int any = __syncthreads_or(viol ? 1 : 0);
         if (do_test && !any) {
@@ -255,7 +419,8 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         yout = t;
     }
 
-    // final state, rounded set, and the statistics of the set (one more pass)
+    // final state, rounded set, and the statistics of the set (one more pass,
+    // over the CSR in global memory)
     for (int i = tid; i < n; i += BT) {
         float x = fabsf(yin[i]) / vv[i];
         x = fminf(fmaxf(x, 0.0f), 1.0f);
@@ -276,8 +441,8 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         relaxed += (double)wi * (double)x;
         bool any = false;
         float vsum = 0.0f;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int j = col[e];
+        for (int e = rp_g[i]; e < rp_g[i + 1]; ++e) {
+            const int j = col_g[e];
             if (yout[j] != 0.0f) {
                 any = true;
                 if (in_s && j > i) conf += 1;
@@ -317,10 +482,10 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     __syncthreads();
 }
 
-// The persistent kernel.  BIG = false: graphs whose state fits in LDS (MODE_ALL,
-// MODE_ROWS or MODE_STATE); BIG = true: the graphs above that (MODE_GLOBAL), in a launch of
-// their own, because the 64-bit gathers of that path would otherwise raise the
-// register count of the common one.
+// The persistent kernel.  BIG = false: graphs whose state fits in LDS
+// (MODE_ALL or MODE_STREAM); BIG = true: the others (MODE_GLOBAL), in a launch
+// of their own, because the 64-bit gathers of that path would otherwise raise
+// the register count of the common one.
 template <int BT, bool BIG>
 __global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
     extern __shared__ float lds[];
@@ -337,13 +502,11 @@ __global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
         if constexpr (BIG) {
             solve_graph<BT, MODE_GLOBAL>(a, d, gi, lds);
         } else {
-            const int64_t lds_bytes = 12 * (int64_t)a.lds_vertices;
-            if (all_lds_bytes(d.n, d.nnz) <= lds_bytes)
+            const int64_t slices = slice_count(d.n, d.n_light, d.n_mid);
+            if (all_lds_bytes(d.n, slices, d.n_lines) <= 12 * (int64_t)a.lds_vertices)
                 solve_graph<BT, MODE_ALL>(a, d, gi, lds);
-            else if (16 * (int64_t)d.n + 4 <= lds_bytes)
-                solve_graph<BT, MODE_ROWS>(a, d, gi, lds);
             else
-                solve_graph<BT, MODE_STATE>(a, d, gi, lds);
+                solve_graph<BT, MODE_STREAM>(a, d, gi, lds);
         }
     }
 }
@@ -517,10 +680,13 @@ struct gn_batch {
     int32_t* order = nullptr;      // graphs that fit the LDS state size, then the others (for split_lds)
     std::vector<int32_t> h_order;  // all graphs, most entries first
     int32_t split_lds = -1;        // lds_vertices the device order was split for
-    int32_t n_fit = 0;             // graphs with n <= split_lds
+    int32_t n_fit = 0;             // graphs whose LDS state fits 12 * split_lds bytes
+    std::vector<int64_t> h_state;  // per graph: state_lds_bytes, or INT64_MAX without a sliced layout
     int32_t* vgraph = nullptr;
     int32_t* row_ptr = nullptr;
     int32_t* col = nullptr;
+    uint16_t* lines = nullptr;  // sliced layouts
+    int32_t* slices = nullptr;  // slice tables
     float* v = nullptr;
     float* w = nullptr;
     int32_t* perm = nullptr;
@@ -544,7 +710,7 @@ struct gn_batch {
 
 static void batch_free(gn_batch* b) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
-    f(b->desc); f(b->order); f(b->vgraph); f(b->row_ptr); f(b->col); f(b->v); f(b->w); f(b->perm);
+    f(b->desc); f(b->order); f(b->vgraph); f(b->row_ptr); f(b->col); f(b->lines); f(b->slices); f(b->v); f(b->w); f(b->perm);
     f(b->yg0); f(b->yg1); f(b->queue); f(b->gamma); f(b->res);
     if (b->res_host) (void)hipHostFree(b->res_host);
     if (b->launch.exec) (void)hipGraphExecDestroy(b->launch.exec);
@@ -614,11 +780,15 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
 
     // validate each graph (same conditions as gn_graph_create) and relabel it:
     // rows of degree <= kLightMaxDeg first, then those of degree <= kMidMaxDeg,
-    // then the rest, each class in its original order
+    // then the rest, each class by decreasing degree (ties in the original
+    // order); each row keeps its entries in the caller's order
     std::vector<BatchDesc> desc((size_t)count);
     std::vector<int32_t> rp_int((size_t)trp), col_int((size_t)std::max<int64_t>(tnnz, 1)), perm((size_t)std::max<int64_t>(tn, 1));
     std::vector<int32_t> vgraph((size_t)std::max<int64_t>(tn, 1));
     std::vector<float> v_int((size_t)std::max<int64_t>(tn, 1)), w_int((size_t)std::max<int64_t>(tn, 1));
+    std::vector<uint16_t> lines;
+    std::vector<int32_t> slices;
+    std::vector<int64_t> state_bytes((size_t)count, INT64_MAX);
     int64_t vo = 0, ro = 0, eo = 0;
     for (int32_t g = 0; g < count; ++g) {
         const int32_t ng = n[g];
@@ -656,7 +826,10 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
             const int32_t dg = rp[i + 1] - rp[i];
             return dg <= kLightMaxDeg ? 0 : dg <= kMidMaxDeg ? 1 : 2;
         };
-        std::stable_sort(p.begin(), p.end(), [&](int32_t i, int32_t j) { return cls(i) < cls(j); });
+        std::stable_sort(p.begin(), p.end(), [&](int32_t i, int32_t j) {
+            const int ci_ = cls(i), cj_ = cls(j);
+            return ci_ != cj_ ? ci_ < cj_ : rp[i + 1] - rp[i] > rp[j + 1] - rp[j];
+        });
         int32_t nl = 0, nm = 0;
         for (int32_t i = 0; i < ng; ++i) {
             nl += cls(i) == 0 ? 1 : 0;
@@ -675,7 +848,52 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
             w_int[(size_t)(vo + r)] = wg[i];
             vgraph[(size_t)(vo + r)] = g;
         }
-        desc[g] = BatchDesc{ng, nl, nm, 0, vo, ro, eo, (int32_t)nnz[g], 0};
+        // sliced layout (see the head of this file)
+        const int64_t ln0 = (int64_t)(lines.size() / 64), so0 = (int64_t)slices.size();
+        int32_t nlines = 0;
+        if (ng <= kMaxSlicedN) {
+            const int32_t nL = (nl + 63) / 64, nM = (nm - nl + 7) / 8, nH = ng - nm;
+            auto deg = [&](int32_t r) { return rpi[r + 1] - rpi[r]; };
+            int64_t acc = 0;
+            slices.push_back(0);
+            for (int32_t sl = 0; sl < nL; ++sl) {
+                int32_t wdt = 0;
+                for (int32_t r = 64 * sl; r < std::min(64 * sl + 64, nl); ++r) wdt = std::max(wdt, deg(r));
+                acc += (wdt + 1) & ~1;
+                slices.push_back((int32_t)acc);
+            }
+            for (int32_t sl = 0; sl < nM; ++sl) {
+                int32_t wdt = 0;
+                for (int32_t r = nl + 8 * sl; r < std::min(nl + 8 * sl + 8, nm); ++r) wdt = std::max(wdt, (deg(r) + 7) / 8);
+                acc += (wdt + 1) & ~1;
+                slices.push_back((int32_t)acc);
+            }
+            for (int32_t sl = 0; sl < nH; ++sl) {
+                acc += (((deg(nm + sl) + 63) / 64) + 1) & ~1;
+                slices.push_back((int32_t)acc);
+            }
+            if (acc > INT32_MAX / 64) { delete b; return GN_E_ARG; }
+            nlines = (int32_t)acc;
+            lines.resize(lines.size() + (size_t)acc * 64, (uint16_t)ng);
+            uint16_t* lg = lines.data() + ln0 * 64;
+            const int32_t* so = slices.data() + so0;
+            auto cid = [&](int32_t r, int32_t e) { return (uint16_t)col_int[(size_t)(eo + rpi[r] + e)]; };
+            for (int32_t sl = 0; sl < nL; ++sl)
+                for (int32_t l = 0; l < 64 && 64 * sl + l < nl; ++l)
+                    for (int32_t e = 0; e < deg(64 * sl + l); ++e)
+                        lg[(size_t)(so[sl] + e) * 64 + l] = cid(64 * sl + l, e);
+            for (int32_t sl = 0; sl < nM; ++sl)
+                for (int32_t l = 0; l < 64 && nl + 8 * sl + l / 8 < nm; ++l) {
+                    const int32_t r = nl + 8 * sl + l / 8, t = l % 8;
+                    for (int32_t e = t; e < deg(r); e += 8) lg[(size_t)(so[nL + sl] + e / 8) * 64 + l] = cid(r, e);
+                }
+            for (int32_t sl = 0; sl < nH; ++sl) {
+                const int32_t r = nm + sl;
+                for (int32_t e = 0; e < deg(r); ++e) lg[(size_t)(so[nL + nM + sl] + e / 64) * 64 + e % 64] = cid(r, e);
+            }
+            state_bytes[g] = state_lds_bytes(ng, slice_count(ng, nl, nm));
+        }
+        desc[g] = BatchDesc{ng, nl, nm, nlines, vo, ro, eo, ln0, so0, (int32_t)nnz[g], 0};
         vo += ng;
         ro += (int64_t)ng + 1;
         eo += nnz[g];
@@ -695,7 +913,8 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     b->cus = cus > 0 ? cus : 256;
     bool ok = dalloc(&b->desc, count) && dalloc(&b->order, count) && dalloc(&b->vgraph, tn) &&
-              dalloc(&b->row_ptr, trp) && dalloc(&b->col, tnnz) && dalloc(&b->v, tn) && dalloc(&b->w, tn) &&
+              dalloc(&b->row_ptr, trp) && dalloc(&b->col, tnnz) && dalloc(&b->lines, std::max<size_t>(lines.size(), 64)) &&
+              dalloc(&b->slices, slices.size()) && dalloc(&b->v, tn) && dalloc(&b->w, tn) &&
               dalloc(&b->perm, tn) && dalloc(&b->yg0, tn) && dalloc(&b->yg1, tn) && dalloc(&b->queue, 3) &&
               dalloc(&b->res, count);
     if (ok && hipHostMalloc((void**)&b->res_host, sizeof(BatchRes) * count, hipHostMallocDefault) != hipSuccess) {
@@ -716,6 +935,9 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
     up(b->vgraph, vgraph.data(), sizeof(int32_t) * tn);
     up(b->row_ptr, rp_int.data(), sizeof(int32_t) * trp);
     up(b->col, col_int.data(), sizeof(int32_t) * tnnz);
+    up(b->lines, lines.data(), sizeof(uint16_t) * lines.size());
+    up(b->slices, slices.data(), sizeof(int32_t) * slices.size());
+    b->h_state = std::move(state_bytes);
     up(b->v, v_int.data(), sizeof(float) * tn);
     up(b->w, w_int.data(), sizeof(float) * tn);
     up(b->perm, perm.data(), sizeof(int32_t) * tn);
@@ -785,10 +1007,10 @@ static gn_status prepare_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
         std::vector<int32_t> split;
         split.reserve(b->h_order.size());
         for (int32_t g : b->h_order)
-            if (b->h_n[g] <= t.lds_vertices) split.push_back(g);
+            if (b->h_state[g] <= 12 * (int64_t)t.lds_vertices) split.push_back(g);
         const int32_t nf = (int32_t)split.size();
         for (int32_t g : b->h_order)
-            if (b->h_n[g] > t.lds_vertices) split.push_back(g);
+            if (b->h_state[g] > 12 * (int64_t)t.lds_vertices) split.push_back(g);
         GN_HIP_TRY(hipMemcpyAsync(b->order, split.data(), sizeof(int32_t) * split.size(), hipMemcpyHostToDevice, s));
         GN_HIP_TRY(hipStreamSynchronize(s));  // the host vector goes out of scope
         b->split_lds = t.lds_vertices;
@@ -833,6 +1055,8 @@ static gn_status batch_kernels(gn_batch* b, const gn_schedule* sch, const gn_tun
     a.qslot = 0;
     a.row_ptr = b->row_ptr;
     a.col = b->col;
+    a.lines = b->lines;
+    a.slices = b->slices;
     a.v = b->v;
     a.w = b->w;
     a.perm = b->perm;
@@ -990,9 +1214,11 @@ extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_t
     if (!b || !out) return GN_E_ARG;
     gn_status st = check_schedule(sch);
     if (st != GN_OK) return st;
-    // bounded timing runs: at most 64 steps, from x0 = 1/2
-    gn_schedule ts = *sch;
-    ts.max_steps = std::min<int32_t>(sch->max_steps, 64);
+    // per candidate: a warm-up run of at most 64 steps, then one timed full
+    // solve, from x0 = 1/2 (the largest graphs set the wall time, and only a
+    // full solve shows their tail)
+    gn_schedule ws = *sch;
+    ws.max_steps = std::min<int32_t>(sch->max_steps, 64);
     float* x = nullptr;
     uint8_t* sel = nullptr;
     if (!dalloc(&x, (size_t)b->total_n) || !dalloc(&sel, (size_t)b->total_n)) {
@@ -1023,7 +1249,7 @@ extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_t
                     break;
                 }
                 (void)hipEventRecord(e0, stream);
-                st = enqueue_batch(b, &ts, t, x, sel, stream);
+                st = enqueue_batch(b, rep == 0 ? &ws : sch, t, x, sel, stream);
                 (void)hipEventRecord(e1, stream);
                 if (hipEventSynchronize(e1) != hipSuccess) st = GN_E_HIP;
                 float ms = 0.0f;
