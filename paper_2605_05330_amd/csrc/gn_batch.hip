@@ -134,6 +134,22 @@ __device__ __forceinline__ bool step_row(float yraw, float vi, float sigma, bool
     return far || uncovered || growing;
 }
 
+// Workgroup vote "some row failed the stopping test" with one barrier per step.
+// A wavefront with a failure sets flags[f]; every thread reads it after the
+// barrier; thread 0 then clears flags[(f + 2) mod 3], which was read before this
+// barrier and is written again only after the next one.  The three flags must
+// be zero before the first step.  The barrier also orders the step's state
+// writes before the next step's reads.
+__device__ __forceinline__ bool block_any_step(bool viol, int* flags, int& f) {
+    if (__ballot(viol) != 0ull && (threadIdx.x & 63) == 0) flags[f] = 1;
+    __syncthreads();
+    const bool any = flags[f] != 0;
+    const int nx = f == 2 ? 0 : f + 1;
+    if (threadIdx.x == 0) flags[nx == 2 ? 0 : nx + 1] = 0;
+    f = nx;
+    return any;
+}
+
 template <int BT>
 __device__ double block_sum_d(double x, double* sm) {
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -296,6 +312,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     __shared__ double sm_d[BT / 64];
     __shared__ long long sm_l[BT / 64];
     __shared__ float sm_f[BT / 64];
+    __shared__ int s_flags[3];
     constexpr int NW = BT / 64;
     constexpr bool SL = MODE != MODE_GLOBAL;  // sliced layout, state in LDS
     const int n = d.n;
@@ -332,9 +349,18 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         if constexpr (MODE == MODE_ALL) {
             const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(ln_g);
             uint32_t* dst = reinterpret_cast<uint32_t*>(ln_l);
-            for (int w = tid; w < d.n_lines * 32; w += BT) dst[w] = src[w];
+            const int nw = d.n_lines * 32;
+            for (int w = tid; w < nw; w += 4 * BT) {
+                uint32_t t[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) t[u] = w + u * BT < nw ? src[w + u * BT] : 0u;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (w + u * BT < nw) dst[w + u * BT] = t[u];
+            }
         }
     }
+    if (tid < 3) s_flags[tid] = 0;
     __syncthreads();
 
     float* yin = ya;
@@ -342,8 +368,9 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     int fb = 0;
     int steps = 0;
     bool binarised = false;
+    int fslot = 0, kc = 0;  // vote slot; k mod check_every
     for (int k = 0;; ++k) {
-        const bool do_test = k >= 1 && (k % a.check_every == 0 || k == a.max_steps);
+        const bool do_test = k >= 1 && (kc == 0 || k == a.max_steps);
         const bool do_write = k < a.max_steps;
         const float g = a.gamma[k];
         bool viol = false;
@@ -404,7 +431,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
             }
         }
-        const int any = __syncthreads_or(viol ? 1 : 0);
+        const bool any = block_any_step(viol, s_flags, fslot);
         if (do_test && !any) {
             binarised = true;
             steps = k;
@@ -417,6 +444,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
         float* t = yin;
         yin = yout;
         yout = t;
+        kc = kc + 1 == a.check_every ? 0 : kc + 1;
     }
 
     // final state, rounded set, and the statistics of the set (one more pass,
@@ -577,6 +605,7 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
                                                          SolveState* st, int32_t* notconv, float* y0, float* y1) {
     extern __shared__ float lds[];
     __shared__ int s_fb;
+    __shared__ int s_flags[3];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (st->err) return;  // x0 rejected by the checks before this launch
     const int ms = st->max_steps, ce = st->check_every;
@@ -594,6 +623,7 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
     for (int i = tid; i <= n; i += BT) rp[i] = rp_g[i];
     for (int e = tid; e < nnz; e += BT) col[e] = col_g[e];
     if (tid == 0) s_fb = 0;
+    if (tid < 3) s_flags[tid] = 0;
     __syncthreads();
     float* yin = ya;
     float* yout = yb;
@@ -601,8 +631,9 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
     int steps = 0;
     bool binarised = false;
     float g_next = gamma[0];
+    int fslot = 0, kc = 0;  // vote slot; k mod check_every
     for (int k = 0;; ++k) {
-        const bool do_test = k >= 1 && (k % ce == 0 || k == ms);
+        const bool do_test = k >= 1 && (kc == 0 || k == ms);
         const bool do_write = k < ms;
         // gamma of the next step is loaded one step ahead (the table covers
         // indices 0 .. max_steps): no global round trip on the step's path
@@ -628,7 +659,7 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
             const bool any_sel = __any(sel != 0u);
             if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
         }
-        const int any = __syncthreads_or(viol ? 1 : 0);
+        const bool any = block_any_step(viol, s_flags, fslot);
         if (do_test && !any) {
             binarised = true;
             steps = k;
@@ -641,6 +672,7 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
         float* t = yin;
         yin = yout;
         yout = t;
+        kc = kc + 1 == ce ? 0 : kc + 1;
     }
     if (fb) atomicAdd(&s_fb, fb);
     float* dst = (steps & 1) ? y1 : y0;
