@@ -316,7 +316,8 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     constexpr int NW = BT / 64;
     constexpr bool SL = MODE != MODE_GLOBAL;  // sliced layout, state in LDS
     const int n = d.n;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wavefront index is uniform: stated, the slice loops compile to scalar branches
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (n == 0) return;  // result filled on the host
     const int32_t* __restrict__ rp_g = a.row_ptr + d.rp_off;
     const int32_t* __restrict__ col_g = a.col + d.e_off;
@@ -326,6 +327,8 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     const float* __restrict__ vv = a.v + d.v_off;
     const int nL = (d.n_light + 63) / 64, nM = (d.n_mid - d.n_light + 7) / 8;
     const int nS = nL + nM + (n - d.n_mid);
+    const int w_mid = (wave - nL % NW + NW) % NW;          // first mid slice of this wavefront
+    const int w_heavy = (wave - (nL + nM) % NW + NW) % NW;  // first heavy slice
     int32_t* so = reinterpret_cast<int32_t*>(lds + 2 * n + 2);
     uint16_t* ln_l = reinterpret_cast<uint16_t*>(so + nS + 1);
     const uint16_t* __restrict__ ln_g = a.lines + d.ln_off * 64;
@@ -369,12 +372,19 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     int steps = 0;
     bool binarised = false;
     int fslot = 0, kc = 0;  // vote slot; k mod check_every
+    float g_next = a.gamma[0];
     for (int k = 0;; ++k) {
         const bool do_test = k >= 1 && (kc == 0 || k == a.max_steps);
         const bool do_write = k < a.max_steps;
-        const float g = a.gamma[k];
+        // gamma of the next step is loaded one step ahead (the table covers
+        // indices 0 .. max_steps): its scalar load never holds up the step's
+        // LDS waits
+        const float g = g_next;
+        if (k + 1 <= a.max_steps) g_next = a.gamma[k + 1];
         bool viol = false;
         if constexpr (SL) {
+            // slices are dealt round robin over the wavefronts across the three
+            // classes in turn, so no wavefront takes more than ceil(slices / NW)
 #pragma unroll 1
             for (int s = wave; s < nL; s += NW) {
                 const int i = 64 * s + lane;
@@ -388,7 +398,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                     viol |= step_row(yin[i], vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, a.tau, yout, i, fb);
             }
 #pragma unroll 1
-            for (int s = wave; s < nM; s += NW) {
+            for (int s = w_mid; s < nM; s += NW) {
                 const int i = d.n_light + 8 * s + (lane >> 3);
                 const bool valid = i < d.n_mid && (lane & 7) == 0;
                 const float vi = valid ? vv[i] : 1.0f;
@@ -400,7 +410,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
             }
 #pragma unroll 1
-            for (int s = wave; s < n - d.n_mid; s += NW) {
+            for (int s = w_heavy; s < n - d.n_mid; s += NW) {
                 const int i = d.n_mid + s;
                 const float vi = lane == 0 ? vv[i] : 1.0f;
                 const int o = so[nL + nM + s];
