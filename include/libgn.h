@@ -380,13 +380,15 @@ gn_status gn_rook_solve(gn_rook* r, const gn_schedule* sch, float* x, uint8_t* s
  * often from the host; results do not change.  Process-wide; not thread-safe. */
 gn_status gn_set_chunk_len(int32_t len);
 
-/* Tuning: gn_solve runs a graph with nnz + 2 n <= work_max (0 .. 40000, default
- * 20000) in one workgroup and one launch, with its state and CSR in one compute
- * unit's LDS (16 n + 4 nnz + 4 bytes, at most about 157 KB) and the steps
- * separated by workgroup barriers instead of kernel boundaries.  That unit does
- * all the work, so it pays only for small steps.  Other graphs replay chains of
- * step launches.  Both paths compute the same bits; 0 disables the one-workgroup
- * path.  Process-wide; not thread-safe. */
+/* Tuning: gn_solve runs a graph with nnz + 2 n <= work_max (0 .. 1048576, the
+ * default) in one workgroup and one launch when the graph has an LDS image that
+ * fits one compute unit: at most 65535 vertices, and y (ping-pong) plus the
+ * sliced 16-bit column lines of its internal order (8 n + 12 + 4 S + 128 L
+ * bytes for S slices of L lines in all) within about 158 KB.  The image is
+ * built at graph creation.  The steps are separated by workgroup barriers
+ * instead of kernel boundaries.  Other graphs replay chains of step launches.
+ * Both paths compute the same bits; 0 disables the one-workgroup path.
+ * Process-wide; not thread-safe. */
 gn_status gn_set_small_graph_limit(int32_t work_max);
 
 /* Human-readable name of a status code (static string). */

@@ -216,14 +216,15 @@ __device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const C
 }
 
 // Row sum over the first K lines of a light (G = 1, NQ = 16) or mid (G = 8,
-// NQ = 8) slice in the canonical order: chain q of the thread takes line q, the
-// chains meet in the in-thread butterfly, then the group's shuffles.  `ln`
-// points at this lane's id in the slice's first line; the lines are 64 ids
-// apart.  ORs the raw bits of the gathered values into `bits` (bit 31: some
-// neighbour is selected).  Straight-line code: the K id loads, then the K
-// gathers, each phase back to back.  Chains at or past K are zero, and adding
-// zero to a sum of magnitudes (never -0) changes nothing, so those additions
-// of the butterfly are left out.
+// NQ = 8) slice in the canonical order: line q feeds chain q mod NQ of the
+// thread, in increasing q (a mid row of degree up to 128 has two lines per
+// chain), the chains meet in the in-thread butterfly, then the group's
+// shuffles.  `ln` points at this lane's id in the slice's first line; the
+// lines are 64 ids apart.  ORs the raw bits of the gathered values into `bits`
+// (bit 31: some neighbour is selected).  Straight-line code: the K id loads,
+// then the K gathers, each phase back to back.  Chains without a line are
+// zero, and adding zero to a sum of magnitudes (never -0) changes nothing, so
+// those additions of the butterfly are left out.
 template <int G, int NQ, int K, typename LT>
 __device__ __forceinline__ float slice_sum_k(const LT* __restrict__ ln, const float* __restrict__ y,
                                              unsigned& bits) {
@@ -236,7 +237,8 @@ __device__ __forceinline__ float slice_sum_k(const LT* __restrict__ ln, const fl
 #pragma unroll
     for (int q = 0; q < K; ++q) {
         const float yv = y[id[q]];
-        c[q] = fabsf(yv);
+        if (q < NQ) c[q] = fabsf(yv);
+        else c[q % NQ] += fabsf(yv);
         bits |= __float_as_uint(yv);
     }
 #pragma unroll
@@ -251,20 +253,21 @@ __device__ __forceinline__ float slice_sum_k(const LT* __restrict__ ln, const fl
 }
 
 // The same for a slice of W lines, W even (slices are padded to an even number
-// of lines) and uniform over the wavefront: one straight-line variant per W.
-template <int G, int NQ, typename LT>
+// of lines), at most MAXL and uniform over the wavefront: one straight-line
+// variant per W.
+template <int G, int NQ, int MAXL, typename LT>
 __device__ __forceinline__ float slice_sum(const LT* __restrict__ ln, int W, const float* __restrict__ y,
                                            unsigned& bits) {
-    static_assert(NQ == 8 || NQ == 16, "slice widths");
+    static_assert(MAXL % 2 == 0 && MAXL <= 16, "slice widths");
     switch (W) {
         case 2: return slice_sum_k<G, NQ, 2>(ln, y, bits);
         case 4: return slice_sum_k<G, NQ, 4>(ln, y, bits);
         case 6: return slice_sum_k<G, NQ, 6>(ln, y, bits);
         case 8: return slice_sum_k<G, NQ, 8>(ln, y, bits);
-        case 10: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 10>(ln, y, bits); else break;
-        case 12: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 12>(ln, y, bits); else break;
-        case 14: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 14>(ln, y, bits); else break;
-        case 16: if constexpr (NQ == 16) return slice_sum_k<G, NQ, 16>(ln, y, bits); else break;
+        case 10: if constexpr (MAXL >= 10) return slice_sum_k<G, NQ, 10>(ln, y, bits); else break;
+        case 12: if constexpr (MAXL >= 12) return slice_sum_k<G, NQ, 12>(ln, y, bits); else break;
+        case 14: if constexpr (MAXL >= 14) return slice_sum_k<G, NQ, 14>(ln, y, bits); else break;
+        case 16: if constexpr (MAXL >= 16) return slice_sum_k<G, NQ, 16>(ln, y, bits); else break;
         default: break;
     }
     return slice_sum_k<G, NQ, 0>(ln, y, bits);
@@ -393,7 +396,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 const int o = so[s];
                 const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
                 unsigned bits = 0u;
-                const float sigma = slice_sum<1, kLightMaxDeg>(ln + o * 64 + lane, W, yin, bits);
+                const float sigma = slice_sum<1, 16, kLightMaxDeg>(ln + o * 64 + lane, W, yin, bits);
                 if (valid)
                     viol |= step_row(yin[i], vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, a.tau, yout, i, fb);
             }
@@ -405,7 +408,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 const int o = so[nL + s];
                 const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
                 unsigned bits = 0u;
-                const float sigma = slice_sum<8, kMidMaxDeg / 8>(ln + o * 64 + lane, W, yin, bits);
+                const float sigma = slice_sum<8, 8, kMidMaxDeg / 8>(ln + o * 64 + lane, W, yin, bits);
                 const bool any_sel = gnk::group_any<8>((bits >> 31) != 0u);
                 if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
             }
@@ -599,40 +602,70 @@ __global__ void batch_check_x0_kernel(int64_t total, const int32_t* __restrict__
 
 // One small graph, one workgroup: the whole solve in a single launch, steps
 // separated by workgroup barriers instead of kernel boundaries.  Works on the
-// graph handle's internal arrays: rows [0, mid_begin) have degree > 128 and run
-// one wavefront per row, rows [mid_begin, light_begin) (degree 17 .. 128) 8
-// threads per row, the rest one thread per row; y (ping-pong), v and the CSR
-// live in LDS (16 n + 4 nnz + 4 bytes).  One compute unit does all the work, so
-// this pays only while a step is small (it is bound by that unit's issue rate).  Same arithmetic and canonical sums as the step kernel, so
-// the result is bit-identical to the chained solve.  On entry y0 holds the signed
-// starting state (prep_state_kernel); on exit the final state is in
-// y0 or y1 by the parity of the step count, as after the chained solve.
+// graph handle's internal order: rows [0, mid_begin) have degree > 128 (one
+// wavefront each), rows [mid_begin, light_begin) degree 17 .. 128 (8 threads
+// each), the rest degree <= 16 (a thread each).  The graph's LDS image -- the
+// sliced layout of the head of this file, lines of up to 16 per mid slice --
+// is copied into LDS with y (ping-pong, n + 1 words each with the zero slot);
+// v is read from global memory by its own row.  Same arithmetic and canonical
+// sums as the step kernel, so the result is bit-identical to the chained
+// solve.  One compute unit does all the work, so this pays only while a step
+// is small.  On entry y0 holds the signed starting state (prep_state_kernel);
+// on exit the final state is in y0 or y1 by the parity of the step count, as
+// after the chained solve.
+struct SmallArgs {
+    int32_t n, mid_begin, light_begin, n_lines;
+    const int32_t* slices;   // slice table: light, mid, then heavy slices
+    const uint16_t* lines;   // the slices' lines
+    const float* v;
+    const float* gamma;
+    SolveState* st;
+    int32_t* notconv;
+    float* y0;
+    float* y1;
+};
+
 template <int BT>
-__global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz, int32_t mid_begin, int32_t light_begin,
-                                                         const int32_t* __restrict__ rp_g,
-                                                         const int32_t* __restrict__ col_g,
-                                                         const float* __restrict__ v, const float* __restrict__ gamma,
-                                                         SolveState* st, int32_t* notconv, float* y0, float* y1) {
+__global__ __launch_bounds__(BT) void small_solve_kernel(SmallArgs a) {
     extern __shared__ float lds[];
     __shared__ int s_fb;
     __shared__ int s_flags[3];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = BT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    SolveState* st = a.st;
     if (st->err) return;  // x0 rejected by the checks before this launch
     const int ms = st->max_steps, ce = st->check_every;
     const float tau = st->tau;
+    const int n = a.n, mb = a.mid_begin, lb = a.light_begin;
+    const int nL = (n - lb + 63) / 64, nM = (lb - mb + 7) / 8, nH = mb;
+    const int nS = nL + nM + nH;
+    const int w_mid = (wave - nL % NW + NW) % NW;
+    const int w_heavy = (wave - (nL + nM) % NW + NW) % NW;
     float* ya = lds;
-    float* yb = lds + n;
-    float* vv = lds + 2 * n;
-    // the CSR lives in LDS too: a step touches no global memory
-    int32_t* rp = reinterpret_cast<int32_t*>(lds + 3 * n);
-    int32_t* col = rp + (n + 1);
-    for (int i = tid; i < n; i += BT) {
-        ya[i] = y0[i];
-        vv[i] = v[i];
+    float* yb = lds + (n + 1);
+    int32_t* so = reinterpret_cast<int32_t*>(lds + 2 * n + 2);
+    uint16_t* ln = reinterpret_cast<uint16_t*>(so + nS + 1);
+    const float* __restrict__ vv = a.v;
+    for (int i = tid; i < n; i += BT) ya[i] = a.y0[i];
+    if (tid == 0) {
+        ya[n] = 0.0f;
+        yb[n] = 0.0f;
+        s_fb = 0;
     }
-    for (int i = tid; i <= n; i += BT) rp[i] = rp_g[i];
-    for (int e = tid; e < nnz; e += BT) col[e] = col_g[e];
-    if (tid == 0) s_fb = 0;
+    for (int s = tid; s <= nS; s += BT) so[s] = a.slices[s];
+    {
+        const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(a.lines);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(ln);
+        const int nw = a.n_lines * 32;
+        for (int w = tid; w < nw; w += 4 * BT) {
+            uint32_t t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] = w + u * BT < nw ? src[w + u * BT] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (w + u * BT < nw) dst[w + u * BT] = t[u];
+        }
+    }
     if (tid < 3) s_flags[tid] = 0;
     __syncthreads();
     float* yin = ya;
@@ -640,7 +673,7 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
     int fb = 0;
     int steps = 0;
     bool binarised = false;
-    float g_next = gamma[0];
+    float g_next = a.gamma[0];
     int fslot = 0, kc = 0;  // vote slot; k mod check_every
     for (int k = 0;; ++k) {
         const bool do_test = k >= 1 && (kc == 0 || k == ms);
@@ -648,26 +681,41 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
         // gamma of the next step is loaded one step ahead (the table covers
         // indices 0 .. max_steps): no global round trip on the step's path
         const float g = g_next;
-        if (k + 1 <= ms) g_next = gamma[k + 1];
+        if (k + 1 <= ms) g_next = a.gamma[k + 1];
         bool viol = false;
 #pragma unroll 1
-        for (int i = light_begin + tid; i < n; i += BT) {
-            const int s0 = rp[i];
-            const int dd = rp[i + 1] - s0;
-            unsigned sel = 0u;
-            const float sigma = gnk::row_sum<1, 16>(col + s0, dd, yin, 0, sel);
-            viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, tau, yout, i, fb);
+        for (int s = wave; s < nL; s += NW) {
+            const int i = lb + 64 * s + lane;
+            const bool valid = i < n;
+            const float vi = valid ? vv[i] : 1.0f;
+            const int o = so[s];
+            const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
+            unsigned bits = 0u;
+            const float sigma = slice_sum<1, 16, 16>(ln + o * 64 + lane, W, yin, bits);
+            if (valid) viol |= step_row(yin[i], vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, tau, yout, i, fb);
         }
-        viol |= mid_rows<BT, 128, false>(rp, col, yin, vv, yout, mid_begin, light_begin, g, do_test, do_write, tau,
-                                         fb);
 #pragma unroll 1
-        for (int i = wave; i < mid_begin; i += BT / 64) {
-            const int s0 = rp[i];
-            const int dd = rp[i + 1] - s0;
-            unsigned sel = 0u;
-            const float sigma = gnk::row_sum_wave<8>(col + s0, dd, yin, lane, sel);
-            const bool any_sel = __any(sel != 0u);
-            if (lane == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
+        for (int s = w_mid; s < nM; s += NW) {
+            const int i = mb + 8 * s + (lane >> 3);
+            const bool valid = i < lb && (lane & 7) == 0;
+            const float vi = valid ? vv[i] : 1.0f;
+            const int o = so[nL + s];
+            const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
+            unsigned bits = 0u;
+            const float sigma = slice_sum<8, 8, 16>(ln + o * 64 + lane, W, yin, bits);
+            const bool any_sel = gnk::group_any<8>((bits >> 31) != 0u);
+            if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
+        }
+#pragma unroll 1
+        for (int s = w_heavy; s < nH; s += NW) {
+            const int i = s;
+            const float vi = lane == 0 ? vv[i] : 1.0f;
+            const int o = so[nL + nM + s];
+            const int W = __builtin_amdgcn_readfirstlane(so[nL + nM + s + 1] - o);
+            unsigned bits = 0u;
+            const float sigma = heavy_sum(ln + o * 64 + lane, W, yin, bits);
+            const bool any_sel = __any((bits >> 31) != 0u);
+            if (lane == 0) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
         }
         const bool any = block_any_step(viol, s_flags, fslot);
         if (do_test && !any) {
@@ -685,13 +733,13 @@ __global__ __launch_bounds__(BT) void small_solve_kernel(int32_t n, int32_t nnz,
         kc = kc + 1 == ce ? 0 : kc + 1;
     }
     if (fb) atomicAdd(&s_fb, fb);
-    float* dst = (steps & 1) ? y1 : y0;
+    float* dst = (steps & 1) ? a.y1 : a.y0;
     for (int i = tid; i < n; i += BT) dst[i] = yin[i];
     __syncthreads();
     if (tid == 0) {
         st->fallback = (unsigned long long)s_fb;
         if (binarised) st->done_step = steps;
-        else notconv[ms] = 1;
+        else a.notconv[ms] = 1;
     }
 }
 
@@ -775,6 +823,57 @@ static bool dalloc(T** p, size_t count) {
         return false;
     }
     return true;
+}
+
+// Appends the sliced layout of one graph (see the head of this file) to
+// `lines` and its slice table to `slices`: light rows [lb, le) in slices of 64,
+// mid rows [mb, me) in slices of 8, heavy rows [hb, he) one per slice, in this
+// order; row r holds entries col[rp[r] .. rp[r+1]) of a graph of n vertices
+// (n <= kMaxSlicedN).  Widths are rounded up to even; padding holds n.
+// Returns the graph's line count.
+static int64_t build_slices(int32_t n, const int32_t* rp, const int32_t* col, int32_t lb, int32_t le, int32_t mb,
+                            int32_t me, int32_t hb, int32_t he, std::vector<uint16_t>& lines,
+                            std::vector<int32_t>& slices) {
+    const int32_t nL = (le - lb + 63) / 64, nM = (me - mb + 7) / 8, nH = he - hb;
+    auto deg = [&](int32_t r) { return rp[r + 1] - rp[r]; };
+    const size_t ln0 = lines.size() / 64, so0 = slices.size();
+    int64_t acc = 0;
+    slices.push_back(0);
+    for (int32_t sl = 0; sl < nL; ++sl) {
+        int32_t wdt = 0;
+        for (int32_t r = lb + 64 * sl; r < std::min(lb + 64 * sl + 64, le); ++r) wdt = std::max(wdt, deg(r));
+        acc += (wdt + 1) & ~1;
+        slices.push_back((int32_t)acc);
+    }
+    for (int32_t sl = 0; sl < nM; ++sl) {
+        int32_t wdt = 0;
+        for (int32_t r = mb + 8 * sl; r < std::min(mb + 8 * sl + 8, me); ++r) wdt = std::max(wdt, (deg(r) + 7) / 8);
+        acc += (wdt + 1) & ~1;
+        slices.push_back((int32_t)acc);
+    }
+    for (int32_t sl = 0; sl < nH; ++sl) {
+        acc += (((deg(hb + sl) + 63) / 64) + 1) & ~1;
+        slices.push_back((int32_t)acc);
+    }
+    lines.resize(lines.size() + (size_t)acc * 64, (uint16_t)n);
+    uint16_t* lg = lines.data() + ln0 * 64;
+    const int32_t* so = slices.data() + so0;
+    auto cid = [&](int32_t r, int32_t e) { return (uint16_t)col[rp[r] + e]; };
+    for (int32_t sl = 0; sl < nL; ++sl)
+        for (int32_t l = 0; l < 64 && lb + 64 * sl + l < le; ++l) {
+            const int32_t r = lb + 64 * sl + l;
+            for (int32_t e = 0; e < deg(r); ++e) lg[(size_t)(so[sl] + e) * 64 + l] = cid(r, e);
+        }
+    for (int32_t sl = 0; sl < nM; ++sl)
+        for (int32_t l = 0; l < 64 && mb + 8 * sl + l / 8 < me; ++l) {
+            const int32_t r = mb + 8 * sl + l / 8, t = l % 8;
+            for (int32_t e = t; e < deg(r); e += 8) lg[(size_t)(so[nL + sl] + e / 8) * 64 + l] = cid(r, e);
+        }
+    for (int32_t sl = 0; sl < nH; ++sl) {
+        const int32_t r = hb + sl;
+        for (int32_t e = 0; e < deg(r); ++e) lg[(size_t)(so[nL + nM + sl] + e / 64) * 64 + e % 64] = cid(r, e);
+    }
+    return acc;
 }
 
 extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int64_t* nnz, const int32_t* row_ptr_cat,
@@ -894,45 +993,9 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
         const int64_t ln0 = (int64_t)(lines.size() / 64), so0 = (int64_t)slices.size();
         int32_t nlines = 0;
         if (ng <= kMaxSlicedN) {
-            const int32_t nL = (nl + 63) / 64, nM = (nm - nl + 7) / 8, nH = ng - nm;
-            auto deg = [&](int32_t r) { return rpi[r + 1] - rpi[r]; };
-            int64_t acc = 0;
-            slices.push_back(0);
-            for (int32_t sl = 0; sl < nL; ++sl) {
-                int32_t wdt = 0;
-                for (int32_t r = 64 * sl; r < std::min(64 * sl + 64, nl); ++r) wdt = std::max(wdt, deg(r));
-                acc += (wdt + 1) & ~1;
-                slices.push_back((int32_t)acc);
-            }
-            for (int32_t sl = 0; sl < nM; ++sl) {
-                int32_t wdt = 0;
-                for (int32_t r = nl + 8 * sl; r < std::min(nl + 8 * sl + 8, nm); ++r) wdt = std::max(wdt, (deg(r) + 7) / 8);
-                acc += (wdt + 1) & ~1;
-                slices.push_back((int32_t)acc);
-            }
-            for (int32_t sl = 0; sl < nH; ++sl) {
-                acc += (((deg(nm + sl) + 63) / 64) + 1) & ~1;
-                slices.push_back((int32_t)acc);
-            }
+            const int64_t acc = build_slices(ng, rpi, col_int.data() + eo, 0, nl, nl, nm, nm, ng, lines, slices);
             if (acc > INT32_MAX / 64) { delete b; return GN_E_ARG; }
             nlines = (int32_t)acc;
-            lines.resize(lines.size() + (size_t)acc * 64, (uint16_t)ng);
-            uint16_t* lg = lines.data() + ln0 * 64;
-            const int32_t* so = slices.data() + so0;
-            auto cid = [&](int32_t r, int32_t e) { return (uint16_t)col_int[(size_t)(eo + rpi[r] + e)]; };
-            for (int32_t sl = 0; sl < nL; ++sl)
-                for (int32_t l = 0; l < 64 && 64 * sl + l < nl; ++l)
-                    for (int32_t e = 0; e < deg(64 * sl + l); ++e)
-                        lg[(size_t)(so[sl] + e) * 64 + l] = cid(64 * sl + l, e);
-            for (int32_t sl = 0; sl < nM; ++sl)
-                for (int32_t l = 0; l < 64 && nl + 8 * sl + l / 8 < nm; ++l) {
-                    const int32_t r = nl + 8 * sl + l / 8, t = l % 8;
-                    for (int32_t e = t; e < deg(r); e += 8) lg[(size_t)(so[nL + sl] + e / 8) * 64 + l] = cid(r, e);
-                }
-            for (int32_t sl = 0; sl < nH; ++sl) {
-                const int32_t r = nm + sl;
-                for (int32_t e = 0; e < deg(r); ++e) lg[(size_t)(so[nL + nM + sl] + e / 64) * 64 + e % 64] = cid(r, e);
-            }
             state_bytes[g] = state_lds_bytes(ng, slice_count(ng, nl, nm));
         }
         desc[g] = BatchDesc{ng, nl, nm, nlines, vo, ro, eo, ln0, so0, (int32_t)nnz[g], 0};
@@ -1341,21 +1404,80 @@ extern "C" const gn_graph* gn_batch_graph(const gn_batch* bc) {
     return u;
 }
 
-// Small-graph path of gn_solve (declared in gn_internal.h).
+// Small-graph path of gn_solve (declared in gn_internal.h).  The graph's LDS
+// image (slice table and lines over its internal order) is built at graph
+// creation from the host copies of the internal CSR, and kept in the handle.
+struct SmallImage {
+    int32_t slices = 0, lines = 0;
+    int64_t lds = INT64_MAX;  // LDS bytes of the solve; INT64_MAX: no image
+    int32_t* so = nullptr;
+    uint16_t* ln = nullptr;
+};
+
+void gn_internal_build_small(gn_graph* g, const int32_t* rp, const int32_t* col, hipStream_t s) {
+    SmallImage* im = new (std::nothrow) SmallImage();
+    if (!im) return;
+    g->small = im;
+    const int32_t n = g->n;
+    // a cheap bound first: the lines hold at least the nnz ids
+    if (n == 0 || n > kMaxSlicedN || 8 * (int64_t)n + 12 + 2 * g->nnz > kLdsBudget) return;
+    const int32_t mb = g->bins.row_begin[BIN_G8], lb = g->bins.row_begin[BIN_LANE16];
+    std::vector<uint16_t> lines;
+    std::vector<int32_t> slices;
+    const int64_t nl = build_slices(n, rp, col, lb, n, mb, lb, 0, mb, lines, slices);
+    const int64_t bytes = 8 * (int64_t)n + 8 + 4 * (int64_t)slices.size() + 128 * nl;
+    if (bytes > kLdsBudget) return;
+    bool ok = dalloc(&im->so, slices.size()) && dalloc(&im->ln, std::max<size_t>(lines.size(), 64)) &&
+              hipMemcpyAsync(im->so, slices.data(), sizeof(int32_t) * slices.size(), hipMemcpyHostToDevice, s) ==
+                  hipSuccess &&
+              (lines.empty() || hipMemcpyAsync(im->ln, lines.data(), sizeof(uint16_t) * lines.size(),
+                                               hipMemcpyHostToDevice, s) == hipSuccess) &&
+              hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return;  // no image: the graph takes the chained path
+    }
+    im->slices = (int32_t)slices.size() - 1;
+    im->lines = (int32_t)nl;
+    im->lds = bytes;
+}
+
+void gn_internal_free_small(gn_graph* g) {
+    SmallImage* im = static_cast<SmallImage*>(g->small);
+    if (!im) return;
+    if (im->so) (void)hipFree(im->so);
+    if (im->ln) (void)hipFree(im->ln);
+    delete im;
+    g->small = nullptr;
+}
+
 bool gn_internal_small_fits(const gn_graph* g) {
-    return (size_t)g->n * 16 + 4 + (size_t)g->nnz * 4 <= (size_t)kLdsBudget;
+    const SmallImage* im = static_cast<const SmallImage*>(g->small);
+    return im && im->lds <= kLdsBudget;
 }
 
 gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s) {
     constexpr int BT = 1024;
     if (!gn_internal_small_fits(g)) return GN_E_ARG;
-    const size_t lds = (size_t)g->n * 16 + 4 + (size_t)g->nnz * 4;
+    const SmallImage* im = static_cast<const SmallImage*>(g->small);
+    const size_t lds = (size_t)im->lds;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)small_solve_kernel<BT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-    hipLaunchKernelGGL(small_solve_kernel<BT>, dim3(1), dim3(BT), lds, s, g->n, (int32_t)g->nnz,
-                       g->bins.row_begin[BIN_G8], g->bins.row_begin[BIN_LANE16], g->row_ptr, g->col, g->v, g->ws.gamma, g->ws.state,
-                       g->ws.notconv, g->ws.y[0], g->ws.y[1]);
+    SmallArgs a{};
+    a.n = g->n;
+    a.mid_begin = g->bins.row_begin[BIN_G8];
+    a.light_begin = g->bins.row_begin[BIN_LANE16];
+    a.n_lines = im->lines;
+    a.slices = im->so;
+    a.lines = im->ln;
+    a.v = g->v;
+    a.gamma = g->ws.gamma;
+    a.st = g->ws.state;
+    a.notconv = g->ws.notconv;
+    a.y0 = g->ws.y[0];
+    a.y1 = g->ws.y[1];
+    hipLaunchKernelGGL(small_solve_kernel<BT>, dim3(1), dim3(BT), lds, s, a);
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;
 }

@@ -160,6 +160,7 @@ extern "C" void gn_graph_destroy(gn_graph* g) {
     (void)hipDeviceSynchronize();
     gn_internal_free_unrolled(g);
     gn_internal_free_multi(g);
+    gn_internal_free_small(g);
     free_graph_buffers(g);
     delete g;
     (void)hipSetDevice(cur);
@@ -349,6 +350,7 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
         delete g;
         return GN_E_HIP;
     }
+    gn_internal_build_small(g, rp_int.data(), col_int.data(), stream);
     *out = g;
     return GN_OK;
 }

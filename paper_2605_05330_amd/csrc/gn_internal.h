@@ -51,6 +51,7 @@ struct gn_graph {
     mutable GraphWorkspace ws;   // work buffers; calls on one handle must not overlap
     mutable void* unrolled = nullptr;  // adjoint work buffers (gn_unrolled.hip)
     mutable void* multi = nullptr;     // multi-start work buffers (gn_multi.hip)
+    void* small = nullptr;             // LDS image of the single-workgroup solve (gn_batch.hip)
 };
 
 // Final statistics reduced on the device (fixed-order, deterministic).
@@ -96,8 +97,12 @@ gn_status gn_internal_ensure_tables(GraphWorkspace& ws, int32_t steps_needed);
 // nnz + 2 n <= g_small_limit (gn_set_small_graph_limit, gn_solve.hip) and the
 // state and CSR fit in LDS
 extern int32_t g_small_limit;
-constexpr int32_t kSmallWorkMax = 40000;
+constexpr int32_t kSmallWorkMax = 1 << 20;
 gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s);
-bool gn_internal_small_fits(const gn_graph* g);  // y, v and the CSR fit one CU's LDS
+bool gn_internal_small_fits(const gn_graph* g);  // the graph has an LDS image that fits one CU
+// builds that image at graph creation from the host copies of the internal CSR
+// (synchronises `s`); on any failure the graph has none and takes the chained path
+void gn_internal_build_small(gn_graph* g, const int32_t* rp, const int32_t* col, hipStream_t s);
+void gn_internal_free_small(gn_graph* g);
 void gn_internal_free_unrolled(gn_graph* g);
 void gn_internal_free_multi(gn_graph* g);

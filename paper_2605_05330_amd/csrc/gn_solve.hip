@@ -243,7 +243,7 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t
 
 int32_t g_chunk_len = 32;
 
-int32_t g_small_limit = 20000;
+int32_t g_small_limit = kSmallWorkMax;
 
 extern "C" gn_status gn_set_small_graph_limit(int32_t work_max) {
     if (work_max < 0 || work_max > kSmallWorkMax) return GN_E_ARG;

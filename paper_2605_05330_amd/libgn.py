@@ -243,6 +243,11 @@ def gn_set_chunk_len(length: int):
     _check(lib().gn_set_chunk_len(int(length)), "gn_set_chunk_len")
 
 
+# default (and largest) work bound of gn_solve's one-workgroup path: it is taken
+# whenever the graph's LDS image fits
+SMALL_LIMIT_DEFAULT = 1 << 20
+
+
 def gn_set_small_graph_limit(work_max: int):
     _check(lib().gn_set_small_graph_limit(int(work_max)), "gn_set_small_graph_limit")
 

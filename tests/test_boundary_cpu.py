@@ -127,8 +127,9 @@ def test_chunk_length_bounds():
     assert L.gn_set_chunk_len(4097) == libgn.GN_E_ARG
     assert L.gn_set_chunk_len(32) == libgn.GN_OK
     assert L.gn_set_small_graph_limit(-1) == libgn.GN_E_ARG
-    assert L.gn_set_small_graph_limit(40001) == libgn.GN_E_ARG
+    assert L.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT + 1) == libgn.GN_E_ARG
     assert L.gn_set_small_graph_limit(20000) == libgn.GN_OK
+    assert L.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT) == libgn.GN_OK
 
 
 def test_product_path_does_not_import_oracle():

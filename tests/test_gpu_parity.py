@@ -341,11 +341,12 @@ def test_solve_independent_of_chain_length(gpu):
         assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
 
 
-@pytest.mark.parametrize("case", ["er1000", "hubs", "fits3000", "ud2500", "budget", "check_every"])
+@pytest.mark.parametrize("case", ["er1000", "hubs", "fits3000", "ud2500", "ud3000", "ba3000", "budget",
+                                  "check_every"])
 def test_small_graph_path_bitexact(gpu, case):
-    """gn_solve runs small graphs in one workgroup (one launch, CSR in LDS);
-    forcing either path must give the same steps, states, sets, objectives and
-    fallback counts."""
+    """gn_solve runs small graphs in one workgroup (one launch, the graph's
+    sliced column lines in LDS); forcing either path must give the same steps,
+    states, sets, objectives and fallback counts."""
     import torch
     libgn = _lib()
     sch = dict(SCHED_RAMP)
@@ -356,7 +357,11 @@ def test_small_graph_path_bitexact(gpu, case):
     elif case == "fits3000":
         g = I.erdos_renyi(3000, 6 / 2999, 6)   # CSR staged in LDS
     elif case == "ud2500":
-        g = I.unit_disk(2500, 10, 9)          # 140 KB of LDS: near the budget
+        g = I.unit_disk(2500, 10, 9)
+    elif case == "ud3000":
+        g = I.unit_disk(3000, 10, 10)         # about 100 KB of LDS image
+    elif case == "ba3000":
+        g = I.barabasi_albert(3000, 5, 11)    # hubs: rows of degree > 128 in heavy slices
     elif case == "budget":
         g = I.erdos_renyi(900, 8 / 899, 7)
         sch["max_steps"] = 40
@@ -367,14 +372,14 @@ def test_small_graph_path_bitexact(gpu, case):
     G = _graph(g, w)
     outs = []
     try:
-        for limit in (0, 40000):
+        for limit in (0, libgn.SMALL_LIMIT_DEFAULT):
             libgn.gn_set_small_graph_limit(limit)
             x = dev(np.full(g.n, 0.5, F32))
             sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
             r = G.solve(x, sel, **sch)
             outs.append((r, x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
     finally:
-        libgn.gn_set_small_graph_limit(20000)
+        libgn.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT)
     (ra, xa, sa), (rb, xb, sb) = outs
     assert (ra.steps, ra.binarised, ra.fallback_count) == (rb.steps, rb.binarised, rb.fallback_count)
     assert np.array_equal(xa, xb) and np.array_equal(sa, sb)
