@@ -375,6 +375,36 @@ gn_status gn_rook_step(gn_rook* r, float gamma, const float* x_in, float* x_out,
 gn_status gn_rook_solve(gn_rook* r, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
                         hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Census of GN atoms (Appendix A, Table atoms_10).
+ *
+ * An atom is a fixed point of GN with full support on a connected graph: with
+ * B = A + I, a solution x > 0 of B x = 1.  A connected graph is atomic when it
+ * has one; its atomic spectrum is discrete when det B != 0 (the single point
+ * B^-1 1) and continuous otherwise; it is regular when all degrees are equal.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t connected;             /* connected graphs on n vertices, up to isomorphism */
+    int64_t irregular_discrete;    /* atomic graphs by class, up to isomorphism         */
+    int64_t irregular_continuous;
+    int64_t regular_discrete;
+    int64_t regular_continuous;
+    int64_t atomic;                /* the four classes together                         */
+    int64_t labelled_evaluated;    /* labelled graphs the kernel classified             */
+} gn_atom_counts;
+
+/* Count the connected graphs on n vertices (1 <= n <= 8) and their atomic
+ * classes, up to isomorphism.  By Burnside's lemma over the cycle types of the
+ * vertex permutations, each labelled graph fixed by a representative
+ * permutation is classified on the device (one thread each: 2^28 graphs at
+ * n = 8), exactly (fraction-free elimination of [B | 1], whose entries stay
+ * below 2^24); the weighted sums are divided by n! on the host.  Allocates and
+ * frees its own device buffers.  Errors: GN_E_ARG (n out of range, out NULL),
+ * GN_E_NOMEM, GN_E_HIP, GN_E_NUMERIC (a weighted sum not divisible by n!: an
+ * internal inconsistency, never expected).  SYNC. */
+gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t stream);
+
 /* Tuning: number of step launches captured in one replayed chain by gn_solve and
  * gn_rook_solve (default 32, 1..4096).  A longer chain checks the stop flag less
  * often from the host; results do not change.  Process-wide; not thread-safe. */

@@ -1,0 +1,223 @@
+// Census of GN atoms: the per-graph classification and the enumeration of
+// cycle types, shared by the census kernel and its host check (host and device).
+// See gn_atoms.hip for the method.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+constexpr int kAtomMaxN = 8;
+
+// Per-graph counters: connected graphs, then atomic irregular discrete,
+// irregular continuous, regular discrete, regular continuous.
+constexpr int kAtomCounters = 5;
+
+// Fraction-free elimination of [B_S | 1], B = A + I, S = the columns in
+// `colmask` (the others read as zero); `rows` holds the adjacency rows (byte i =
+// neighbours of vertex i).  rank: rank of B_S; consistent: 1 lies in the span of
+// B_S.  When B_S has full column rank and the system is consistent, pos / neg
+// receive the columns of S whose (unique) solution component is > 0 / < 0.
+template <int N>
+__host__ __device__ inline void atom_eliminate(const uint64_t rows, const unsigned colmask, int& rank,
+                                               bool& consistent, unsigned& pos, unsigned& neg) {
+    float M[N][N + 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const unsigned a = i == j ? 1u : (unsigned)((rows >> (8 * i + j)) & 1u);
+            M[i][j] = ((colmask >> j) & 1u) ? (float)a : 0.0f;
+        }
+        M[i][N] = 1.0f;
+    }
+    unsigned used = 0u;  // pivot rows
+    int pr[N];           // pivot row of column c, or -1
+    float prev = 1.0f;   // previous pivot (the Bareiss divisor)
+    rank = 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        int p = -1;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (p < 0 && !((used >> i) & 1u) && M[i][c] != 0.0f) p = i;
+        pr[c] = p;
+        if (p >= 0) {
+            used |= 1u << p;
+            ++rank;
+            float pv[N + 1];
+#pragma unroll
+            for (int j = 0; j <= N; ++j) {
+                float v = 0.0f;
+#pragma unroll
+                for (int i = 0; i < N; ++i) v = i == p ? M[i][j] : v;
+                pv[j] = v;
+            }
+            const float pc = pv[c];
+            const float inv = 1.0f / prev;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if ((used >> i) & 1u) continue;
+                const float f = M[i][c];
+#pragma unroll
+                for (int j = c + 1; j <= N; ++j) M[i][j] = rintf((pc * M[i][j] - f * pv[j]) * inv);
+                M[i][c] = 0.0f;
+            }
+            prev = pc;
+        }
+    }
+    consistent = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (!((used >> i) & 1u) && M[i][N] != 0.0f) consistent = false;
+    pos = 0u;
+    neg = 0u;
+    if (!consistent || rank != __builtin_popcount(colmask)) return;
+    // fraction-free back substitution: y_c = D x_c with D the last pivot
+    const float D = prev;
+    float y[N];
+#pragma unroll
+    for (int c = N - 1; c >= 0; --c) {
+        y[c] = 0.0f;
+        const int p = pr[c];
+        if (p < 0) continue;
+        float row[N + 1];
+#pragma unroll
+        for (int j = 0; j <= N; ++j) {
+            float v = 0.0f;
+#pragma unroll
+            for (int i = 0; i < N; ++i) v = i == p ? M[i][j] : v;
+            row[j] = v;
+        }
+        float num = D * row[N];
+#pragma unroll
+        for (int j = c + 1; j < N; ++j) num -= row[j] * y[j];
+        y[c] = rintf(num * (1.0f / row[c]));
+    }
+    // accumulated in locals with selects: no store through a chosen output
+    unsigned ps = 0u, ng = 0u;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        const float s = pr[c] < 0 ? 0.0f : y[c] * D;
+        ps |= s > 0.0f ? 1u << c : 0u;
+        ng |= s < 0.0f ? 1u << c : 0u;
+    }
+    pos = ps;
+    neg = ng;
+}
+
+// Class of one connected graph: -1 not atomic, else 0 discrete / 1 continuous.
+template <int N>
+__host__ __device__ inline int atom_class(const uint64_t rows) {
+    constexpr unsigned full = (1u << N) - 1u;
+    int r;
+    bool cons;
+    unsigned pos, neg;
+    atom_eliminate<N>(rows, full, r, cons, pos, neg);
+    if (!cons) return -1;
+    if (r == N) return pos == full ? 0 : -1;
+    unsigned cover = 0u;
+    for (unsigned S = 1u; S <= full; ++S) {
+        if (__builtin_popcount(S) != r) continue;
+        int r2;
+        bool c2;
+        unsigned p2, n2;
+        atom_eliminate<N>(rows, S, r2, c2, p2, n2);
+        if (r2 == r && c2 && n2 == 0u) cover |= p2;
+    }
+    return cover == full ? 1 : -1;
+}
+
+// Adds one labelled graph to the counters.
+template <int N>
+__host__ __device__ inline void atom_evaluate(const uint64_t rows, unsigned (&cnt)[kAtomCounters]) {
+    constexpr unsigned full = (1u << N) - 1u;
+    // connected: grow the set reachable from vertex 0
+    unsigned reach = 1u;
+#pragma unroll
+    for (int it = 0; it < N - 1; ++it) {
+        unsigned nx = reach;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if ((reach >> i) & 1u) nx |= (unsigned)((rows >> (8 * i)) & 255u);
+        reach = nx;
+    }
+    if (reach != full) return;
+    cnt[0] += 1u;
+    const int d0 = __builtin_popcount((unsigned)(rows & 255u));
+    bool regular = true;
+#pragma unroll
+    for (int i = 1; i < N; ++i) regular = regular && __builtin_popcount((unsigned)((rows >> (8 * i)) & 255u)) == d0;
+    const int cls = atom_class<N>(rows);
+    const int idx = cls < 0 ? -1 : 1 + (regular ? 2 : 0) + cls;
+#pragma unroll
+    for (int k = 1; k < kAtomCounters; ++k) cnt[k] += idx == k ? 1u : 0u;  // fixed indices: no scratch array
+}
+
+// One cycle type of the permutations of n vertices: its weight n!/z (the
+// number of permutations of that type) and the orbits of a representative
+// permutation on vertex pairs, each as adjacency rows (byte i = neighbours of i).
+struct AtomCycleType {
+    long long weight;
+    std::vector<uint64_t> orbit_rows;
+};
+
+inline void atom_partitions(int n, int maxp, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
+    if (n == 0) {
+        out.push_back(cur);
+        return;
+    }
+    for (int p = (n < maxp ? n : maxp); p >= 1; --p) {
+        cur.push_back(p);
+        atom_partitions(n - p, p, cur, out);
+        cur.pop_back();
+    }
+}
+
+// All cycle types of n vertices (1 <= n <= kAtomMaxN); nfact receives n!.
+inline std::vector<AtomCycleType> atom_cycle_types(int n, long long& nfact) {
+    std::vector<std::vector<int>> types;
+    std::vector<int> cur;
+    atom_partitions(n, n, cur, types);
+    nfact = 1;
+    for (int k = 2; k <= n; ++k) nfact *= k;
+    std::vector<AtomCycleType> out;
+    for (const auto& parts : types) {
+        // representative permutation: cycles on consecutive vertices
+        std::vector<int> perm(n);
+        std::vector<int> mult(n + 1, 0);
+        long long z = 1;
+        int v = 0;
+        for (int len : parts) {
+            for (int k = 0; k < len; ++k) perm[v + k] = v + (k + 1) % len;
+            v += len;
+            z *= len;
+            mult[len] += 1;
+        }
+        for (int len = 1; len <= n; ++len)
+            for (int k = 2; k <= mult[len]; ++k) z *= k;
+        AtomCycleType t;
+        t.weight = nfact / z;
+        std::vector<int> orbit(n * n, -1);
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                if (orbit[i * n + j] >= 0) continue;
+                const int o = (int)t.orbit_rows.size();
+                uint64_t rows = 0;
+                int a = i, b = j;
+                while (orbit[(a < b ? a : b) * n + (a < b ? b : a)] < 0) {
+                    const int lo = a < b ? a : b, hi = a < b ? b : a;
+                    orbit[lo * n + hi] = o;
+                    rows |= 1ull << (8 * lo + hi);
+                    rows |= 1ull << (8 * hi + lo);
+                    a = perm[a];
+                    b = perm[b];
+                }
+                t.orbit_rows.push_back(rows);
+            }
+        out.push_back(t);
+    }
+    return out;
+}

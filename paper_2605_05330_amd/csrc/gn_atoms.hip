@@ -1,0 +1,162 @@
+// Census of GN atoms on connected graphs of up to 8 vertices (Appendix A,
+// Table atoms_10).
+//
+// A fixed point of GN with full support on a connected graph is an atom; with
+// B = A + I the atoms are the solutions x > 0 of B x = 1.  A connected graph is
+// atomic when it has one; its spectrum is discrete when det B != 0 (the single
+// point B^-1 1) and continuous otherwise.  The census counts, up to
+// isomorphism, the connected graphs on n vertices and the atomic ones split
+// into irregular / regular x discrete / continuous.
+//
+// Counting up to isomorphism without an isomorphism-free generator: every
+// property counted here is invariant under relabelling, so by Burnside's
+// lemma the number of isomorphism classes with the property is
+//     (1/n!) sum over permutations p of #{labelled graphs fixed by p with it},
+// and conjugate permutations fix isomorphic families, so the sum runs over
+// cycle types with weights n!/z (z = prod_k k^{m_k} m_k!).  The graphs fixed
+// by p are the unions of the orbits of p on vertex pairs.  One GPU thread
+// evaluates one such graph: 2^28 labelled graphs for the identity at n = 8.
+//
+// Deciding atomicity exactly: fraction-free (Bareiss) elimination of [B | 1].
+// Every entry it produces is a minor of that 0/1 matrix (Sylvester's identity),
+// at most 144 in magnitude for size <= 9, so products stay below 2^24 and fp32
+// arithmetic is exact; each exact division is a multiply by the reciprocal and
+// a round to the nearest integer.  When B is invertible the graph is atomic iff
+// every component of B^-1 1 is positive.  When B is singular, the set
+// P = {x >= 0 : B x = 1} is a polytope (B x = 1 with x >= 0 bounds x by 1); some
+// point of P is positive iff the supports of P's vertices cover every vertex of
+// the graph (the mean of one positive-in-i vertex per i is in P and positive).
+// The vertices are the non-negative basic solutions: for every set S of
+// rank(B) independent columns with B_S x_S = 1 solvable, x_S >= 0.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "gn_atoms.h"
+#include "gn_internal.h"
+
+namespace {
+
+constexpr int kAtomBlock = 256;
+
+// One thread per labelled graph g in [0, count): its edges are the orbits
+// whose bits are set in g; `tab` holds, for each byte of g, the adjacency rows
+// (byte i = neighbours of vertex i) of every combination of that byte's orbits.
+template <int N>
+__global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t* __restrict__ tab, int nbytes,
+                                                                 uint64_t count,
+                                                                 unsigned long long* __restrict__ acc) {
+    __shared__ uint64_t s_tab[4 * 256];
+    __shared__ unsigned s_red[kAtomBlock / 64][kAtomCounters];
+    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = tab[k];
+    __syncthreads();
+    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; g < count; g += stride) {
+        uint64_t rows = 0;
+        for (int b = 0; b < nbytes; ++b) rows |= s_tab[b * 256 + ((g >> (8 * b)) & 255u)];
+        atom_evaluate<N>(rows, cnt);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kAtomCounters; ++k) {
+        unsigned v = cnt[k];
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) s_red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kAtomCounters) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kAtomBlock / 64; ++w) t += s_red[w][threadIdx.x];
+        if (t) atomicAdd(acc + threadIdx.x, t);
+    }
+}
+
+template <int N>
+gn_status launch_census(const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc, hipStream_t s) {
+    const uint64_t blocks = std::min<uint64_t>((count + kAtomBlock - 1) / kAtomBlock, 256 * 64);
+    hipLaunchKernelGGL(atom_census_kernel<N>, dim3((unsigned)blocks), dim3(kAtomBlock), 0, s, tab, nbytes, count,
+                       acc);
+    GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
+}
+
+gn_status launch_census_n(int n, const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc,
+                          hipStream_t s) {
+    switch (n) {
+        case 1: return launch_census<1>(tab, nbytes, count, acc, s);
+        case 2: return launch_census<2>(tab, nbytes, count, acc, s);
+        case 3: return launch_census<3>(tab, nbytes, count, acc, s);
+        case 4: return launch_census<4>(tab, nbytes, count, acc, s);
+        case 5: return launch_census<5>(tab, nbytes, count, acc, s);
+        case 6: return launch_census<6>(tab, nbytes, count, acc, s);
+        case 7: return launch_census<7>(tab, nbytes, count, acc, s);
+        default: return launch_census<8>(tab, nbytes, count, acc, s);
+    }
+}
+
+}  // namespace
+
+extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t stream) {
+    if (!out || n < 1 || n > kAtomMaxN) return GN_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    long long nfact = 1;
+    const std::vector<AtomCycleType> types = atom_cycle_types(n, nfact);
+    const size_t T = types.size();
+    unsigned long long* acc = nullptr;  // per cycle type: kAtomCounters counters
+    uint64_t* tab = nullptr;            // per cycle type: 4 x 256 adjacency-row words
+    if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * T) != hipSuccess ||
+        hipMalloc((void**)&tab, sizeof(uint64_t) * 4 * 256 * T) != hipSuccess) {
+        (void)hipGetLastError();
+        if (acc) (void)hipFree(acc);
+        return GN_E_NOMEM;
+    }
+    gn_status st = GN_OK;
+    // per cycle type and byte b of the graph index: the adjacency rows of every
+    // combination of orbits 8b .. 8b + 7
+    std::vector<uint64_t> htab(4 * 256 * T, 0);
+    std::vector<int> nbytes(T);
+    std::vector<uint64_t> counts(T);
+    for (size_t t = 0; t < T; ++t) {
+        const int m = (int)types[t].orbit_rows.size();
+        counts[t] = 1ull << m;
+        nbytes[t] = m > 8 ? (m + 7) / 8 : 1;
+        for (int b = 0; b < nbytes[t]; ++b)
+            for (int c = 0; c < 256; ++c) {
+                uint64_t rows = 0;
+                for (int q = 0; q < 8; ++q)
+                    if (((c >> q) & 1) && 8 * b + q < m) rows |= types[t].orbit_rows[8 * b + q];
+                htab[(t * 4 + b) * 256 + c] = rows;
+            }
+    }
+    if (hipMemcpyAsync(tab, htab.data(), sizeof(uint64_t) * htab.size(), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * T, stream) != hipSuccess)
+        st = GN_E_HIP;
+    for (size_t t = 0; t < T && st == GN_OK; ++t)
+        st = launch_census_n(n, tab + t * 4 * 256, nbytes[t], counts[t], acc + t * kAtomCounters, stream);
+    std::vector<unsigned long long> h(kAtomCounters * T, 0);
+    if (st == GN_OK &&
+        (hipMemcpyAsync(h.data(), acc, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, stream) !=
+             hipSuccess ||
+         hipStreamSynchronize(stream) != hipSuccess))
+        st = GN_E_HIP;
+    (void)hipFree(acc);
+    (void)hipFree(tab);
+    if (st != GN_OK) return st;
+    // Burnside: the weighted sums are n! times the class counts
+    long long sum[kAtomCounters] = {0, 0, 0, 0, 0};
+    for (size_t t = 0; t < T; ++t) {
+        for (int k = 0; k < kAtomCounters; ++k) sum[k] += (long long)h[t * kAtomCounters + k] * types[t].weight;
+        out->labelled_evaluated += (int64_t)counts[t];
+    }
+    for (int k = 0; k < kAtomCounters; ++k)
+        if (sum[k] % nfact != 0) return GN_E_NUMERIC;  // never expected: Burnside sums are multiples of n!
+    out->connected = sum[0] / nfact;
+    out->irregular_discrete = sum[1] / nfact;
+    out->irregular_continuous = sum[2] / nfact;
+    out->regular_discrete = sum[3] / nfact;
+    out->regular_continuous = sum[4] / nfact;
+    out->atomic = out->irregular_discrete + out->irregular_continuous + out->regular_discrete + out->regular_continuous;
+    return GN_OK;
+}

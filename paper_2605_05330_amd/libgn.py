@@ -43,6 +43,13 @@ class gn_result(ctypes.Structure):
                 ("stab", ctypes.c_float)]
 
 
+class gn_atom_counts(ctypes.Structure):
+    _fields_ = [("connected", ctypes.c_int64), ("irregular_discrete", ctypes.c_int64),
+                ("irregular_continuous", ctypes.c_int64), ("regular_discrete", ctypes.c_int64),
+                ("regular_continuous", ctypes.c_int64), ("atomic", ctypes.c_int64),
+                ("labelled_evaluated", ctypes.c_int64)]
+
+
 class gn_tuning(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("lds_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -74,6 +81,7 @@ def lib():
             "gn_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "gn_set_chunk_len": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_small_graph_limit": ([ctypes.c_int32], ctypes.c_int),
+            "gn_atom_census": ([ctypes.c_int32, ctypes.POINTER(gn_atom_counts), _vp], ctypes.c_int),
             "gn_batch_create": ([ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
                                 ctypes.c_int),
             "gn_batch_destroy": ([_vp], None),
@@ -241,6 +249,14 @@ def gn_check_independent(h, sel, stream=None) -> tuple[int, int]:
 
 def gn_set_chunk_len(length: int):
     _check(lib().gn_set_chunk_len(int(length)), "gn_set_chunk_len")
+
+
+def gn_atom_census(n: int, stream=None) -> gn_atom_counts:
+    """Connected graphs on n vertices (1..8) up to isomorphism and their GN-atomic
+    classes (Appendix A, Table atoms_10), counted on the device."""
+    out = gn_atom_counts()
+    _check(lib().gn_atom_census(int(n), ctypes.byref(out), _stream(stream)), "gn_atom_census")
+    return out
 
 
 # default (and largest) work bound of gn_solve's one-workgroup path: it is taken

@@ -23,8 +23,9 @@ def table():
 
 def test_table_is_consistent():
     # the four classes add up to the printed total on every row but n = 8, where
-    # they add up to 247 against a printed total of 230 (which the printed
-    # density, 2.1% of 11,117, agrees with): the table is at odds with itself there
+    # they add up to 247 against a printed total of 230 (and a printed density
+    # of 2.1% = 230 / 11,117): the table is at odds with itself there.  The GPU
+    # census (test_gpu_atoms.py) reproduces all four printed classes at n = 8.
     for n, (conn, idisc, icont, rdisc, rcont, total) in table().items():
         s = idisc + icont + rdisc + rcont
         assert s == (247 if n == 8 else total), n
