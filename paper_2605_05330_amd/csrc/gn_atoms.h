@@ -108,9 +108,11 @@ __host__ __device__ inline void atom_eliminate(const uint64_t rows, const unsign
     neg = ng;
 }
 
-// Class of one connected graph: -1 not atomic, else 0 discrete / 1 continuous.
+// First part of the class of a connected graph, from the elimination of
+// [B | 1]: -1 not atomic, 0 atomic and discrete, or the rank of B (>= 1) when B
+// is singular and 1 lies in its span, which atom_singular_class decides.
 template <int N>
-__host__ __device__ inline int atom_class(const uint64_t rows) {
+__host__ __device__ inline int atom_class_first(const uint64_t rows) {
     constexpr unsigned full = (1u << N) - 1u;
     int r;
     bool cons;
@@ -118,24 +120,44 @@ __host__ __device__ inline int atom_class(const uint64_t rows) {
     atom_eliminate<N>(rows, full, r, cons, pos, neg);
     if (!cons) return -1;
     if (r == N) return pos == full ? 0 : -1;
+    return r;
+}
+
+// Singular B of rank r with 1 in its span: atomic (continuous, returns 1) iff
+// the non-negative basic solutions of B x = 1 cover every vertex, else -1.
+// The subsets of size r are walked in increasing order by the next-combination
+// step (Gosper), so lanes of a wavefront with different ranks each eliminate
+// their own subset in the same trip; a lane stops once its cover is complete.
+template <int N>
+__host__ __device__ inline int atom_singular_class(const uint64_t rows, const int r) {
+    constexpr unsigned full = (1u << N) - 1u;
     unsigned cover = 0u;
-    for (unsigned S = 1u; S <= full; ++S) {
-        if (__builtin_popcount(S) != r) continue;
+    for (unsigned S = (1u << r) - 1u; S <= full;) {
         int r2;
         bool c2;
         unsigned p2, n2;
         atom_eliminate<N>(rows, S, r2, c2, p2, n2);
         if (r2 == r && c2 && n2 == 0u) cover |= p2;
+        if (cover == full) break;
+        const unsigned low = S & (0u - S);  // lowest set bit
+        const unsigned up = S + low;
+        S = up | (((up ^ S) >> 2) >> __builtin_ctz(low));
     }
     return cover == full ? 1 : -1;
 }
 
-// Adds one labelled graph to the counters.
+// Class of one connected graph: -1 not atomic, else 0 discrete / 1 continuous.
 template <int N>
-__host__ __device__ inline void atom_evaluate(const uint64_t rows, unsigned (&cnt)[kAtomCounters]) {
+__host__ __device__ inline int atom_class(const uint64_t rows) {
+    const int f = atom_class_first<N>(rows);
+    return f <= 0 ? f : atom_singular_class<N>(rows, f);
+}
+
+// Whether the graph is connected, and whether it is regular.
+template <int N>
+__host__ __device__ inline bool atom_connected(const uint64_t rows) {
     constexpr unsigned full = (1u << N) - 1u;
-    // connected: grow the set reachable from vertex 0
-    unsigned reach = 1u;
+    unsigned reach = 1u;  // grow the set reachable from vertex 0
 #pragma unroll
     for (int it = 0; it < N - 1; ++it) {
         unsigned nx = reach;
@@ -144,16 +166,31 @@ __host__ __device__ inline void atom_evaluate(const uint64_t rows, unsigned (&cn
             if ((reach >> i) & 1u) nx |= (unsigned)((rows >> (8 * i)) & 255u);
         reach = nx;
     }
-    if (reach != full) return;
-    cnt[0] += 1u;
+    return reach == full;
+}
+
+template <int N>
+__host__ __device__ inline bool atom_regular(const uint64_t rows) {
     const int d0 = __builtin_popcount((unsigned)(rows & 255u));
     bool regular = true;
 #pragma unroll
     for (int i = 1; i < N; ++i) regular = regular && __builtin_popcount((unsigned)((rows >> (8 * i)) & 255u)) == d0;
-    const int cls = atom_class<N>(rows);
+    return regular;
+}
+
+// Adds an atomic class (0 discrete / 1 continuous) to the counters.
+__host__ __device__ inline void atom_count(const int cls, const bool regular, unsigned (&cnt)[kAtomCounters]) {
     const int idx = cls < 0 ? -1 : 1 + (regular ? 2 : 0) + cls;
 #pragma unroll
     for (int k = 1; k < kAtomCounters; ++k) cnt[k] += idx == k ? 1u : 0u;  // fixed indices: no scratch array
+}
+
+// Adds one labelled graph to the counters.
+template <int N>
+__host__ __device__ inline void atom_evaluate(const uint64_t rows, unsigned (&cnt)[kAtomCounters]) {
+    if (!atom_connected<N>(rows)) return;
+    cnt[0] += 1u;
+    atom_count(atom_class<N>(rows), atom_regular<N>(rows), cnt);
 }
 
 // One cycle type of the permutations of n vertices: its weight n!/z (the

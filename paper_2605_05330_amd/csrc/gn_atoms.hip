@@ -39,24 +39,17 @@ namespace {
 
 constexpr int kAtomBlock = 256;
 
-// One thread per labelled graph g in [0, count): its edges are the orbits
-// whose bits are set in g; `tab` holds, for each byte of g, the adjacency rows
-// (byte i = neighbours of vertex i) of every combination of that byte's orbits.
-template <int N>
-__global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t* __restrict__ tab, int nbytes,
-                                                                 uint64_t count,
-                                                                 unsigned long long* __restrict__ acc) {
-    __shared__ uint64_t s_tab[4 * 256];
-    __shared__ unsigned s_red[kAtomBlock / 64][kAtomCounters];
-    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = tab[k];
-    __syncthreads();
-    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
-    const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
-    for (uint64_t g = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; g < count; g += stride) {
-        uint64_t rows = 0;
-        for (int b = 0; b < nbytes; ++b) rows |= s_tab[b * 256 + ((g >> (8 * b)) & 255u)];
-        atom_evaluate<N>(rows, cnt);
-    }
+constexpr uint64_t kAtomChunk = 1ull << 24;  // graphs per first-pass launch (queue capacity)
+
+__device__ __forceinline__ uint64_t atom_rows(const uint64_t* s_tab, int nbytes, uint64_t g) {
+    uint64_t rows = 0;
+    for (int b = 0; b < nbytes; ++b) rows |= s_tab[b * 256 + ((g >> (8 * b)) & 255u)];
+    return rows;
+}
+
+template <int BT>
+__device__ __forceinline__ void atom_flush(unsigned (&cnt)[kAtomCounters], unsigned long long* acc) {
+    __shared__ unsigned s_red[BT / 64][kAtomCounters];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kAtomCounters; ++k) {
@@ -67,31 +60,104 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t*
     __syncthreads();
     if (threadIdx.x < kAtomCounters) {
         unsigned long long t = 0;
-        for (int w = 0; w < kAtomBlock / 64; ++w) t += s_red[w][threadIdx.x];
+        for (int w = 0; w < BT / 64; ++w) t += s_red[w][threadIdx.x];
         if (t) atomicAdd(acc + threadIdx.x, t);
     }
 }
 
+// First pass, one thread per labelled graph g in [base, base + count): its
+// edges are the orbits whose bits are set in g; `tab` holds, for each byte of
+// g, the adjacency rows (byte i = neighbours of vertex i) of every combination
+// of that byte's orbits.  Counts connected graphs and discrete atoms; a
+// connected graph whose B is singular with 1 in its span goes to the queue as
+// (g - base) | rank << 28 | regular << 31, appended a wavefront at a time, so
+// that the subset search of the second pass runs with every lane busy instead
+// of stalling the wavefronts of the first.
 template <int N>
-gn_status launch_census(const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc, hipStream_t s) {
-    const uint64_t blocks = std::min<uint64_t>((count + kAtomBlock - 1) / kAtomBlock, 256 * 64);
-    hipLaunchKernelGGL(atom_census_kernel<N>, dim3((unsigned)blocks), dim3(kAtomBlock), 0, s, tab, nbytes, count,
-                       acc);
-    GN_HIP_TRY(hipGetLastError());
+__global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t* __restrict__ tab, int nbytes,
+                                                                 uint64_t base, uint64_t count,
+                                                                 unsigned long long* __restrict__ acc,
+                                                                 uint32_t* __restrict__ queue,
+                                                                 unsigned* __restrict__ qcount) {
+    __shared__ uint64_t s_tab[4 * 256];
+    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = tab[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
+    for (uint64_t k = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; k < count; k += stride) {
+        const uint64_t rows = atom_rows(s_tab, nbytes, base + k);
+        int f = -1;
+        bool regular = false;
+        if (atom_connected<N>(rows)) {
+            cnt[0] += 1u;
+            regular = atom_regular<N>(rows);
+            f = atom_class_first<N>(rows);
+            if (f == 0) atom_count(0, regular, cnt);
+        }
+        const bool want = f > 0;
+        const uint64_t mask = __ballot(want);
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            unsigned at = 0u;
+            if (lane == leader) at = atomicAdd(qcount, (unsigned)__popcll(mask));
+            at = __shfl(at, leader, 64);
+            if (want)
+                queue[at + __popcll(mask & ((1ull << lane) - 1ull))] =
+                    (uint32_t)k | (uint32_t)f << 28 | (regular ? 1u << 31 : 0u);
+        }
+    }
+    atom_flush<kAtomBlock>(cnt, acc);
+}
+
+// Second pass over the queue of the first: continuous atoms.
+template <int N>
+__global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const uint64_t* __restrict__ tab, int nbytes,
+                                                                   uint64_t base, const uint32_t* __restrict__ queue,
+                                                                   const unsigned* __restrict__ qcount,
+                                                                   unsigned long long* __restrict__ acc) {
+    __shared__ uint64_t s_tab[4 * 256];
+    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = tab[k];
+    __syncthreads();
+    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    const unsigned total = *qcount;
+    for (unsigned i = blockIdx.x * kAtomBlock + threadIdx.x; i < total; i += gridDim.x * kAtomBlock) {
+        const uint32_t e = queue[i];
+        const uint64_t rows = atom_rows(s_tab, nbytes, base + (e & 0x0fffffffu));
+        atom_count(atom_singular_class<N>(rows, (int)((e >> 28) & 7u)), (e >> 31) != 0u, cnt);
+    }
+    atom_flush<kAtomBlock>(cnt, acc);
+}
+
+template <int N>
+gn_status launch_census(const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc, uint32_t* queue,
+                        unsigned* qcount, hipStream_t s) {
+    for (uint64_t base = 0; base < count; base += kAtomChunk) {
+        const uint64_t c = std::min(kAtomChunk, count - base);
+        GN_HIP_TRY(hipMemsetAsync(qcount, 0, sizeof(unsigned), s));
+        const uint64_t blocks = std::min<uint64_t>((c + kAtomBlock - 1) / kAtomBlock, 256 * 64);
+        hipLaunchKernelGGL(atom_census_kernel<N>, dim3((unsigned)blocks), dim3(kAtomBlock), 0, s, tab, nbytes, base,
+                           c, acc, queue, qcount);
+        GN_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(atom_singular_kernel<N>, dim3((unsigned)std::min<uint64_t>(blocks, 256 * 16)),
+                           dim3(kAtomBlock), 0, s, tab, nbytes, base, (const uint32_t*)queue,
+                           (const unsigned*)qcount, acc);
+        GN_HIP_TRY(hipGetLastError());
+    }
     return GN_OK;
 }
 
 gn_status launch_census_n(int n, const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc,
-                          hipStream_t s) {
+                          uint32_t* queue, unsigned* qcount, hipStream_t s) {
     switch (n) {
-        case 1: return launch_census<1>(tab, nbytes, count, acc, s);
-        case 2: return launch_census<2>(tab, nbytes, count, acc, s);
-        case 3: return launch_census<3>(tab, nbytes, count, acc, s);
-        case 4: return launch_census<4>(tab, nbytes, count, acc, s);
-        case 5: return launch_census<5>(tab, nbytes, count, acc, s);
-        case 6: return launch_census<6>(tab, nbytes, count, acc, s);
-        case 7: return launch_census<7>(tab, nbytes, count, acc, s);
-        default: return launch_census<8>(tab, nbytes, count, acc, s);
+        case 1: return launch_census<1>(tab, nbytes, count, acc, queue, qcount, s);
+        case 2: return launch_census<2>(tab, nbytes, count, acc, queue, qcount, s);
+        case 3: return launch_census<3>(tab, nbytes, count, acc, queue, qcount, s);
+        case 4: return launch_census<4>(tab, nbytes, count, acc, queue, qcount, s);
+        case 5: return launch_census<5>(tab, nbytes, count, acc, queue, qcount, s);
+        case 6: return launch_census<6>(tab, nbytes, count, acc, queue, qcount, s);
+        case 7: return launch_census<7>(tab, nbytes, count, acc, queue, qcount, s);
+        default: return launch_census<8>(tab, nbytes, count, acc, queue, qcount, s);
     }
 }
 
@@ -105,10 +171,22 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     const size_t T = types.size();
     unsigned long long* acc = nullptr;  // per cycle type: kAtomCounters counters
     uint64_t* tab = nullptr;            // per cycle type: 4 x 256 adjacency-row words
-    if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * T) != hipSuccess ||
-        hipMalloc((void**)&tab, sizeof(uint64_t) * 4 * 256 * T) != hipSuccess) {
-        (void)hipGetLastError();
+    uint32_t* queue = nullptr;          // singular graphs of one chunk
+    unsigned* qcount = nullptr;
+    auto release = [&]() {
         if (acc) (void)hipFree(acc);
+        if (tab) (void)hipFree(tab);
+        if (queue) (void)hipFree(queue);
+        if (qcount) (void)hipFree(qcount);
+    };
+    uint64_t most = 0;
+    for (const AtomCycleType& t : types) most = std::max<uint64_t>(most, 1ull << t.orbit_rows.size());
+    if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * T) != hipSuccess ||
+        hipMalloc((void**)&tab, sizeof(uint64_t) * 4 * 256 * T) != hipSuccess ||
+        hipMalloc((void**)&queue, sizeof(uint32_t) * std::min(most, kAtomChunk)) != hipSuccess ||
+        hipMalloc((void**)&qcount, sizeof(unsigned)) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
         return GN_E_NOMEM;
     }
     gn_status st = GN_OK;
@@ -134,15 +212,15 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
         hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * T, stream) != hipSuccess)
         st = GN_E_HIP;
     for (size_t t = 0; t < T && st == GN_OK; ++t)
-        st = launch_census_n(n, tab + t * 4 * 256, nbytes[t], counts[t], acc + t * kAtomCounters, stream);
+        st = launch_census_n(n, tab + t * 4 * 256, nbytes[t], counts[t], acc + t * kAtomCounters, queue, qcount,
+                             stream);
     std::vector<unsigned long long> h(kAtomCounters * T, 0);
     if (st == GN_OK &&
         (hipMemcpyAsync(h.data(), acc, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, stream) !=
              hipSuccess ||
          hipStreamSynchronize(stream) != hipSuccess))
         st = GN_E_HIP;
-    (void)hipFree(acc);
-    (void)hipFree(tab);
+    release();
     if (st != GN_OK) return st;
     // Burnside: the weighted sums are n! times the class counts
     long long sum[kAtomCounters] = {0, 0, 0, 0, 0};
