@@ -38,6 +38,7 @@ def _args():
     p.add_argument("--no-warm", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-multi", action="store_true")
+    p.add_argument("--no-atoms", action="store_true")
     return p.parse_args()
 
 
@@ -264,6 +265,33 @@ def bench_batch(sched, reps):
             "speedup_vs_plain": plain_ms / ms, "sample_equal_objective": f"{same}/{len(sample)}"}
 
 
+def bench_atoms(reps=3):
+    """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..8 on the
+    device; n = 8 timed.  Compared with the table's rows (tests/golden)."""
+    rows = {}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "atoms_table.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = [int(t) for t in line.split()]
+                rows[v[0]] = v[1:]
+    match = []
+    for n in range(1, 9):
+        c = libgn.gn_atom_census(n)
+        got = [c.connected, c.irregular_discrete, c.irregular_continuous, c.regular_discrete, c.regular_continuous]
+        match.append(got == rows[n][:5])
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c = libgn.gn_atom_census(8)
+    dt = (time.perf_counter() - t0) / reps
+    return {"n": 8, "connected": c.connected, "irregular_discrete": c.irregular_discrete,
+            "irregular_continuous": c.irregular_continuous, "regular_discrete": c.regular_discrete,
+            "regular_continuous": c.regular_continuous, "atomic": c.atomic,
+            "labelled_graphs": c.labelled_evaluated, "ms": dt * 1e3,
+            "labelled_graphs_per_s": c.labelled_evaluated / dt,
+            "classes_match_table_n1_to_8": all(match),
+            "note": "Burnside sum over cycle types; the table's n = 8 classes add up to 247, its printed total is 230"}
+
+
 def bench_warm():
     """Learned warm start: trained on the GPU (own kernels) on GN's sets of 96
     unit-disk graphs, n log-uniform in [10k, 100k], mean degree 10, w ~ U(0,1];
@@ -483,6 +511,8 @@ def main():
 
     if not a.no_warm:
         out["learned_warm_start"] = bench_warm()
+    if not a.no_atoms:
+        out["atom_census8"] = bench_atoms()
     if not a.no_grad:
         out["differentiable"] = bench_grad()
 
