@@ -268,6 +268,7 @@ def bench_batch(sched, reps):
 def bench_atoms(reps=3):
     """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..8 on the
     device; n = 8 timed.  Compared with the table's rows (tests/golden)."""
+    from paper_2605_05330_amd import libgn
     rows = {}
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "atoms_table.txt")) as f:
         for line in f:
