@@ -366,12 +366,13 @@ def bench_grad():
     """Differentiable GN: 256 unit-disk graphs n = 2000 (mean degree 10) as one
     block-diagonal graph, w ~ U(0.5, 1.5] requiring grad, T = 50 steps at gamma 1.5,
     L = w . x_T: forward + adjoint time with a checkpoint every 10 steps (the
-    backward recomputes each segment), and with y and s of every step kept
-    (ckpt_every = 1: 2 T n floats, no recompute)."""
+    backward recomputes each segment), with y and s of every step kept
+    (ckpt_every = 1: 2 T n floats, no recompute), and with the batched calls (one
+    workgroup per graph, one launch per pass; same gradient bit for bit)."""
     import torch
     from paper_2605_05330_amd import inputs as I
     from paper_2605_05330_amd import libgn
-    from paper_2605_05330_amd.autograd import gn_unrolled
+    from paper_2605_05330_amd.autograd import gn_unrolled, gn_unrolled_batch
     gs = [I.unit_disk(2000, 10, 5000 + k) for k in range(256)]
     ws = [I.weights_uniform(2000, 0.5, 1.5, 5000 + k) for k in range(256)]
     B = libgn.Batch.from_graphs(gs, ws)
@@ -381,7 +382,7 @@ def bench_grad():
     def once(K):
         w = w0.clone().requires_grad_(True)
         x0 = torch.full_like(w0, 0.5)
-        xT = gn_unrolled(w, x0, h, gam, K)
+        xT = gn_unrolled(w, x0, h, gam, K) if K else gn_unrolled_batch(w, x0, B.handle, gam)
         (w * xT).sum().backward()
         return w.grad
     def timed(K):
@@ -396,6 +397,8 @@ def bench_grad():
         return e0.elapsed_time(e1) / 5
     ms = timed(10)
     ms_stored = timed(1)  # y and s of every step kept (2 T n floats): no recompute
+    ms_batched = timed(0)  # one workgroup per graph, all steps in one launch per pass
+    same = bool(torch.equal(once(1).view(torch.int32), once(0).view(torch.int32)))
     nnz = sum(g.nnz for g in gs)
     n = int(w0.numel())
     T = 50
@@ -406,6 +409,7 @@ def bench_grad():
     total = T * b_step + T * (b_step + 8 * n) + T * b_adj
     return {"graphs": 256, "vertices": n, "edges": nnz // 2, "T": T, "ckpt_every": 10,
             "fwd_bwd_ms": ms, "fwd_bwd_ms_all_states_kept": ms_stored,
+            "fwd_bwd_ms_batched": ms_batched, "batched_gradient_bit_identical": same,
             "edges_iters_per_s": (nnz // 2) * T * 3 / (ms / 1e3),
             "algorithmic_bytes": total, "GBs": total / (ms / 1e3) / 1e9,
             "hbm_frac": total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,

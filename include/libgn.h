@@ -254,6 +254,30 @@ gn_status gn_unrolled_backward(const gn_graph* g, const float* w, const float* g
                                int32_t ckpt_every, const float* ckpt, const float* gxT, float* gw, float* gx0,
                                hipStream_t stream);
 
+/* The same unrolled steps for every graph of a batch, one workgroup per graph
+ * with its state in LDS: one launch per call instead of one per step.  xT,
+ * gw and gx0 are bit-identical to gn_unrolled_forward / gn_unrolled_backward
+ * with ckpt_every = 1 on gn_batch_graph(b) (same arithmetic, same canonical
+ * sums).  w_cat (weights to use instead of the batch's own, or NULL), x0_cat,
+ * xT_cat, gxT_cat, gw_cat, gx0_cat: device float[total vertices], the graphs'
+ * user orders back to back (the layout of gn_batch_solve's x_cat); x0_cat and
+ * xT_cat not aliased.  gammas: host float[T], finite and >= 0.  store: device
+ * float[gn_batch_unrolled_store_floats(b, T)] (y and s of every step, layout
+ * private to the library), written by the forward call and read by the
+ * backward call with the same b, w_cat, gammas and T.  Every graph must have
+ * at most 65535 vertices and an adjoint state that fits one compute unit's LDS
+ * (16 n + 12 + 4 S bytes <= about 158 KB for S slices of its sliced layout,
+ * see gn_tuning), else GN_E_ARG.  T = 0 copies x0 to xT (forward) and gxT to
+ * gx0 with gw = 0 (backward).  ASYNC, except that a call whose gammas differ
+ * from the previous call's synchronises `stream` to upload them.  Calls on one
+ * batch must not overlap. */
+int64_t gn_batch_unrolled_store_floats(const gn_batch* b, int32_t T);
+gn_status gn_batch_unrolled_forward(gn_batch* b, const float* w_cat, const float* gammas, int32_t T,
+                                    const float* x0_cat, float* xT_cat, float* store, hipStream_t stream);
+gn_status gn_batch_unrolled_backward(gn_batch* b, const float* w_cat, const float* gammas, int32_t T,
+                                     const float* store, const float* gxT_cat, float* gw_cat, float* gx0_cat,
+                                     hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Learned warm start.
  *

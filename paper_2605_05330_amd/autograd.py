@@ -58,3 +58,36 @@ def gn_unrolled(w, x0, graph_handle, gammas, ckpt_every=None):
     if ckpt_every is None:
         ckpt_every = default_ckpt_every(int(x0.numel()), len(gammas))
     return GNUnrolled.apply(w, x0, graph_handle, gammas, ckpt_every)
+
+
+class GNUnrolledBatch(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w, x0, batch_handle, gammas):
+        gam = np.ascontiguousarray(np.asarray(gammas, dtype=np.float32))
+        w = w.detach().contiguous()
+        x0 = x0.detach().contiguous()
+        xT = torch.empty_like(x0)
+        store = torch.empty(libgn.gn_batch_unrolled_store_floats(batch_handle, len(gam)), dtype=torch.float32,
+                            device=x0.device)
+        libgn.gn_batch_unrolled_forward(batch_handle, w, gam, x0, xT, store)
+        ctx.save_for_backward(w, store)
+        ctx.batch = batch_handle
+        ctx.gammas = gam
+        return xT
+
+    @staticmethod
+    def backward(ctx, gxT):
+        w, store = ctx.saved_tensors
+        gxT = gxT.contiguous()
+        gw = torch.empty_like(w)
+        gx0 = torch.empty_like(gxT)
+        libgn.gn_batch_unrolled_backward(ctx.batch, w, ctx.gammas, store, gxT, gw, gx0)
+        return gw, gx0, None, None
+
+
+def gn_unrolled_batch(w, x0, batch_handle, gammas):
+    """The same for every graph of a batch (vertex vectors: the graphs' user
+    orders back to back), one workgroup per graph: x_T and both gradients are
+    bit-identical to gn_unrolled on the batch's union graph with every state
+    kept."""
+    return GNUnrolledBatch.apply(w, x0, batch_handle, gammas)

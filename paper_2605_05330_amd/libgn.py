@@ -104,6 +104,9 @@ def lib():
             "gn_rook_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
                               ctypes.c_int),
             "gn_unrolled_ckpt_floats": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
+            "gn_batch_unrolled_store_floats": ([_vp, ctypes.c_int32], ctypes.c_int64),
+            "gn_batch_unrolled_forward": ([_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "gn_batch_unrolled_backward": ([_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
             "gn_unrolled_forward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
             "gn_unrolled_backward": ([_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp],
                                      ctypes.c_int),
@@ -537,6 +540,35 @@ def gn_unrolled_backward(h, w, gammas, ckpt_every, ckpt, gxT, gw, gx0, stream=No
                                       int(ckpt_every), _dptr(ckpt, torch.float32, "ckpt"),
                                       _dptr(gxT, torch.float32, "gxT"), _dptr(gw, torch.float32, "gw"),
                                       _dptr(gx0, torch.float32, "gx0"), _stream(stream)), "gn_unrolled_backward")
+
+
+def gn_batch_unrolled_store_floats(h, T) -> int:
+    r = lib().gn_batch_unrolled_store_floats(h, int(T))
+    if r < 0:
+        raise GNError(GN_E_ARG, "gn_batch_unrolled_store_floats")
+    return int(r)
+
+
+def gn_batch_unrolled_forward(h, w_cat, gammas, x0_cat, xT_cat, store, stream=None):
+    import torch
+    gm, p_g = _hptr(gammas, np.float32)
+    _check(lib().gn_batch_unrolled_forward(h, _dptr(w_cat, torch.float32, "w_cat") if w_cat is not None else None,
+                                           p_g, len(gm), _dptr(x0_cat, torch.float32, "x0_cat"),
+                                           _dptr(xT_cat, torch.float32, "xT_cat"),
+                                           _dptr(store, torch.float32, "store") if store is not None else None,
+                                           _stream(stream)), "gn_batch_unrolled_forward")
+
+
+def gn_batch_unrolled_backward(h, w_cat, gammas, store, gxT_cat, gw_cat, gx0_cat, stream=None):
+    import torch
+    gm, p_g = _hptr(gammas, np.float32)
+    _check(lib().gn_batch_unrolled_backward(h, _dptr(w_cat, torch.float32, "w_cat") if w_cat is not None else None,
+                                            p_g, len(gm),
+                                            _dptr(store, torch.float32, "store") if store is not None else None,
+                                            _dptr(gxT_cat, torch.float32, "gxT_cat"),
+                                            _dptr(gw_cat, torch.float32, "gw_cat"),
+                                            _dptr(gx0_cat, torch.float32, "gx0_cat"), _stream(stream)),
+           "gn_batch_unrolled_backward")
 
 
 GN_MPNN_NPARAMS = 9409
