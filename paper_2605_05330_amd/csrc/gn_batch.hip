@@ -593,11 +593,14 @@ __device__ __forceinline__ bool unrolled_quotient(float y, float s) {
     return !(y > 0.0f && y / s < gnk::kXMin);
 }
 
-// Slice loops of one step over a graph's sliced layout: `row(i, sigma)` runs for
-// every valid row with its neighbour sum over `src` (absolute values when ABS).
-template <int BT, bool ABS, typename LT, typename Row>
+// Slice loops of one step over a graph's sliced layout: for every valid row,
+// `load(i)` (the row's own global values, issued before the neighbour sum so
+// that their latency hides behind it), then `row(i, sigma, loaded)` with the
+// neighbour sum over `src` (absolute values when ABS).
+template <int BT, bool ABS, typename LT, typename Load, typename Row>
 __device__ __forceinline__ void unrolled_slices(const BatchDesc& d, const int32_t* so, const LT* __restrict__ ln,
-                                                const float* src, Row&& row) {
+                                                const float* src, Load&& load, Row&& row) {
+    using Pre = decltype(load(0));
     constexpr int NW = BT / 64;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = d.n;
@@ -607,30 +610,46 @@ __device__ __forceinline__ void unrolled_slices(const BatchDesc& d, const int32_
 #pragma unroll 1
     for (int s = wave; s < nL; s += NW) {
         const int i = 64 * s + lane;
+        const bool valid = i < d.n_light;
+        Pre pre{};
+        if (valid) pre = load(i);
         const int o = so[s];
         const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
         unsigned bits = 0u;
         const float sigma = slice_sum<1, 16, kLightMaxDeg, ABS>(ln + o * 64 + lane, W, src, bits);
-        if (i < d.n_light) row(i, sigma);
+        if (valid) row(i, sigma, pre);
     }
 #pragma unroll 1
     for (int s = w_mid; s < nM; s += NW) {
         const int i = d.n_light + 8 * s + (lane >> 3);
+        const bool valid = i < d.n_mid && (lane & 7) == 0;
+        Pre pre{};
+        if (valid) pre = load(i);
         const int o = so[nL + s];
         const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
         unsigned bits = 0u;
         const float sigma = slice_sum<8, 8, kMidMaxDeg / 8, ABS>(ln + o * 64 + lane, W, src, bits);
-        if (i < d.n_mid && (lane & 7) == 0) row(i, sigma);
+        if (valid) row(i, sigma, pre);
     }
 #pragma unroll 1
     for (int s = w_heavy; s < n - d.n_mid; s += NW) {
+        const int i = d.n_mid + s;
+        Pre pre{};
+        if (lane == 0) pre = load(i);
         const int o = so[nL + nM + s];
         const int W = __builtin_amdgcn_readfirstlane(so[nL + nM + s + 1] - o);
         unsigned bits = 0u;
         const float sigma = heavy_sum<ABS>(ln + o * 64 + lane, W, src, bits);
-        if (lane == 0) row(d.n_mid + s, sigma);
+        if (lane == 0) row(i, sigma, pre);
     }
 }
+
+struct FwdPre {
+    float v;
+};
+struct BwdPre {
+    float v, y, s, yp, sp;
+};
 
 // Copies a graph's slice table (and, MODE_ALL, its lines) into LDS at `so`.
 template <int BT, int MODE>
@@ -679,17 +698,19 @@ __device__ void unrolled_fwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
         float* ys = a.store + (int64_t)t * a.total_n + d.v_off;
         float* ss = a.store + (int64_t)(a.T + t) * a.total_n + d.v_off;
         float* xT = t == a.T - 1 ? a.xT + d.v_off : nullptr;
-        unrolled_slices<BT, true>(d, so, ln, yin, [&](int i, float sigma) {
-            const float yraw = yin[i];
-            const float yi = fabsf(yraw);
-            const float s = __fmaf_rn(g, sigma, yi);
-            const float xn = !(s > 1e-9f) ? 0.5f : gnk::bounded_ratio(yi, s);
-            ys[i] = yraw;
-            ss[i] = s;
-            const float yn = vv[i] * xn;
-            yout[i] = xn > 0.5f ? -yn : yn;
-            if (xT) xT[perm[i]] = xn;
-        });
+        unrolled_slices<BT, true>(
+            d, so, ln, yin, [&](int i) { return FwdPre{vv[i]}; },
+            [&](int i, float sigma, const FwdPre& p) {
+                const float yraw = yin[i];
+                const float yi = fabsf(yraw);
+                const float s = __fmaf_rn(g, sigma, yi);
+                const float xn = !(s > 1e-9f) ? 0.5f : gnk::bounded_ratio(yi, s);
+                ys[i] = yraw;
+                ss[i] = s;
+                const float yn = p.v * xn;
+                yout[i] = xn > 0.5f ? -yn : yn;
+                if (xT) xT[perm[i]] = xn;
+            });
         __syncthreads();
         float* tmp = yin;
         yin = yout;
@@ -737,22 +758,26 @@ __device__ void unrolled_bwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
         const float* sk = a.store + (int64_t)(T + t) * a.total_n + d.v_off;
         const float* yp = t > 0 ? a.store + (int64_t)(t - 1) * a.total_n + d.v_off : nullptr;
         const float* sp = t > 0 ? a.store + (int64_t)(T + t - 1) * a.total_n + d.v_off : nullptr;
-        unrolled_slices<BT, false>(d, so, ln, tin, [&](int i, float sigma) {
-            const float g = gb[i];
-            const float y = fabsf(yk[i]);
-            const float s = sk[i];
-            const float vi = vv[i];
-            const float ai = unrolled_quotient(y, s) ? g / s : 0.0f;
-            const float gy = ai - __fmaf_rn(gam, sigma, tin[i]);
-            const float gx = vi * gy;
-            gb[i] = gx;
-            gv[i] += (y / vi) * gy;
-            if (yp) {
-                const float ypi = fabsf(yp[i]);
-                const float spi = sp[i];
-                tout[i] = unrolled_quotient(ypi, spi) ? (gx / spi) * (ypi / spi) : 0.0f;
-            }
-        });
+        unrolled_slices<BT, false>(
+            d, so, ln, tin,
+            [&](int i) {
+                BwdPre p;
+                p.v = vv[i];
+                p.y = fabsf(yk[i]);
+                p.s = sk[i];
+                p.yp = yp ? fabsf(yp[i]) : 0.0f;
+                p.sp = yp ? sp[i] : 0.0f;
+                return p;
+            },
+            [&](int i, float sigma, const BwdPre& p) {
+                const float g = gb[i];
+                const float ai = unrolled_quotient(p.y, p.s) ? g / p.s : 0.0f;
+                const float gy = ai - __fmaf_rn(gam, sigma, tin[i]);
+                const float gx = p.v * gy;
+                gb[i] = gx;
+                gv[i] += (p.y / p.v) * gy;
+                if (yp) tout[i] = unrolled_quotient(p.yp, p.sp) ? (gx / p.sp) * (p.yp / p.sp) : 0.0f;
+            });
         __syncthreads();
         float* tmp = tin;
         tin = tout;
@@ -1681,7 +1706,15 @@ const void* unrolled_kernel_ptr() {
     return (const void*)batch_unrolled_kernel<BT, BWD>;
 }
 
-constexpr int kUnrolledBlock = 512;
+// Workgroup size of the unrolled kernels: 1024 threads when every graph has a
+// compute unit to itself (more wavefronts share a graph's slices), else 512 so
+// that two graphs share one.  Results do not depend on it.
+static int unrolled_block(const gn_batch* b) { return b->count <= b->cus ? 1024 : 512; }
+
+static const void* unrolled_kernel(int bt, bool bwd) {
+    if (bt == 1024) return bwd ? unrolled_kernel_ptr<1024, true>() : unrolled_kernel_ptr<1024, false>();
+    return bwd ? unrolled_kernel_ptr<512, true>() : unrolled_kernel_ptr<512, false>();
+}
 
 static gn_status unrolled_prepare(gn_batch* b, const float* w_cat, const float* gammas, int32_t T, bool bwd,
                                   hipStream_t s, UnrolledArgs& a, dim3& grid, size_t& lds) {
@@ -1695,7 +1728,8 @@ static gn_status unrolled_prepare(gn_batch* b, const float* w_cat, const float* 
         maxall = std::max(maxall, st + 128 * (int64_t)b->h_lines[g]);
     }
     if (maxstate > kLdsBudget) return GN_E_ARG;
-    const int bpc_want = maxstate <= kLdsBudget / 2 ? 2 : 1;
+    const int bt = unrolled_block(b);
+    const int bpc_want = bt == 512 && maxstate <= kLdsBudget / 2 ? 2 : 1;
     lds = (size_t)((std::min<int64_t>(std::max(maxall, maxstate), kLdsBudget / bpc_want) + 15) / 16 * 16);
     if (!b->u_order) {
         if (!dalloc(&b->u_order, (size_t)b->count) || !dalloc(&b->u_queue, 1)) return GN_E_NOMEM;
@@ -1725,10 +1759,10 @@ static gn_status unrolled_prepare(gn_batch* b, const float* w_cat, const float* 
         v = b->u_v;
     }
     GN_HIP_TRY(hipMemsetAsync(b->u_queue, 0, sizeof(int32_t), s));
-    const void* k = bwd ? unrolled_kernel_ptr<kUnrolledBlock, true>() : unrolled_kernel_ptr<kUnrolledBlock, false>();
+    const void* k = unrolled_kernel(bt, bwd);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kUnrolledBlock, lds) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, bt, lds) != hipSuccess) {
         (void)hipGetLastError();
         nb = 1;
     }
@@ -1780,7 +1814,9 @@ extern "C" gn_status gn_batch_unrolled_forward(gn_batch* b, const float* w_cat, 
     a.x0 = x0_cat;
     a.xT = xT_cat;
     a.store = store;
-    hipLaunchKernelGGL((batch_unrolled_kernel<kUnrolledBlock, false>), grid, dim3(kUnrolledBlock), lds, stream, a);
+    const int bt = unrolled_block(b);
+    void* args[] = {&a};
+    GN_HIP_TRY(hipLaunchKernel(unrolled_kernel(bt, false), grid, dim3(bt), args, lds, stream));
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;
 }
@@ -1806,7 +1842,9 @@ extern "C" gn_status gn_batch_unrolled_backward(gn_batch* b, const float* w_cat,
     a.gxT = gxT_cat;
     a.gx0 = gx0_cat;
     a.gw = gw_cat;
-    hipLaunchKernelGGL((batch_unrolled_kernel<kUnrolledBlock, true>), grid, dim3(kUnrolledBlock), lds, stream, a);
+    const int bt = unrolled_block(b);
+    void* args[] = {&a};
+    GN_HIP_TRY(hipLaunchKernel(unrolled_kernel(bt, true), grid, dim3(bt), args, lds, stream));
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;
 }

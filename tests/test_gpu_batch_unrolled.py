@@ -104,3 +104,32 @@ def test_autograd_batch_matches_chained(gpu):
         grads.append((xT.detach().clone(), w.grad.clone(), x0.grad.clone()))
     for a, b in zip(*grads):
         assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_batch_unrolled_many_graphs(gpu):
+    """More graphs than compute units: the 512-thread kernels (two graphs per
+    compute unit); same bit-identity with the chained path."""
+    import torch
+    from paper_2605_05330_amd import libgn
+    gs = [I.erdos_renyi(20 + 7 * k, 5 / (19 + 7 * k), 100 + k) if k % 2 else I.unit_disk(30 + 5 * k, 8, 100 + k)
+          for k in range(320)]
+    ws = [I.weights_uniform01(g.n, 400 + k) for k, g in enumerate(gs)]
+    B = libgn.Batch.from_graphs(gs, ws)
+    U = B.graph_handle()
+    N = B.total_n
+    T = 8
+    gammas = np.linspace(1.0, 1.5, T).astype(F32)
+    rng = np.random.default_rng(1)
+    x0 = torch.tensor(rng.uniform(0.05, 1.0, N).astype(F32), device="cuda")
+    gxT = torch.tensor(rng.standard_normal(N).astype(F32), device="cuda")
+    ck = torch.empty(libgn.gn_unrolled_ckpt_floats(U, T, 1), device="cuda")
+    xT_u, gw_u, gx0_u = (torch.empty(N, device="cuda") for _ in range(3))
+    libgn.gn_unrolled_forward(U, None, gammas, 1, x0, xT_u, ck)
+    libgn.gn_unrolled_backward(U, None, gammas, 1, ck, gxT, gw_u, gx0_u)
+    store = torch.empty(libgn.gn_batch_unrolled_store_floats(B.handle, T), device="cuda")
+    xT_b, gw_b, gx0_b = (torch.empty(N, device="cuda") for _ in range(3))
+    libgn.gn_batch_unrolled_forward(B.handle, None, gammas, x0, xT_b, store)
+    libgn.gn_batch_unrolled_backward(B.handle, None, gammas, store, gxT, gw_b, gx0_b)
+    torch.cuda.synchronize()
+    for a, b in ((xT_u, xT_b), (gw_u, gw_b), (gx0_u, gx0_b)):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
