@@ -218,16 +218,31 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     int iw[kRPW];
     bool ok[kRPW];
     float yraw[kRPW], vi[kRPW];
+    // a tile inside the matrix (uniform over the block) loads and stores
+    // without per-entry predicates
+    const bool full = (tr + 1) * kTR <= a.rows && (tc + 1) * kTC <= a.cols;
 #pragma unroll
     for (int m = 0; m < kRPW; ++m) {
         iw[m] = tr * kTR + wave + kWaves * m;
         ok[m] = j < a.cols && iw[m] < a.rows;
-        yraw[m] = 0.0f;
-        vi[m] = 1.0f;
-        if (ok[m]) {
+    }
+    if (full) {
+#pragma unroll
+        for (int m = 0; m < kRPW; ++m) {
             const size_t e = (size_t)iw[m] * a.cols + j;
             yraw[m] = a.y_in[e];
             vi[m] = gnk::ld_stream(a.v + e);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < kRPW; ++m) {
+            yraw[m] = 0.0f;
+            vi[m] = 1.0f;
+            if (ok[m]) {
+                const size_t e = (size_t)iw[m] * a.cols + j;
+                yraw[m] = a.y_in[e];
+                vi[m] = gnk::ld_stream(a.v + e);
+            }
         }
     }
     StepCtl<RookArgs> c;
@@ -316,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     // every lane computes all 4 entries (entries outside the matrix hold y = 0,
     // v = 1 and are masked out of stores, flags and partials), so the loop has
     // no divergent branches
-    float yn[kRPW];
+    float yn[kRPW], ynew[kRPW], xo[kRPW];
     int viol = 0, fb = 0;
     bool unnormalizable = false;
     const double C = fC[lane];
@@ -332,11 +347,8 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
         const float yv = vi[m] * xn;
         const float y_new = xn > 0.5f ? -yv : yv;
         yn[m] = ok[m] ? y_new : 0.0f;
-        if (c.do_write && ok[m]) {
-            const size_t e = (size_t)iw[m] * a.cols + j;
-            if (a.y_out) a.y_out[e] = y_new;
-            if (a.x_out) a.x_out[e] = xn;
-        }
+        ynew[m] = y_new;
+        xo[m] = xn;
         fb += (c.do_write && ok[m] && fallback) ? 1 : 0;
         if (c.solve && c.k == 0 && ok[m] && yi == 0.0f && R == 0.0 && C == 0.0) unnormalizable = true;
         const bool in_s = gnk::sign_of(yraw[m]) != 0u;
@@ -346,6 +358,18 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
         const bool uncovered = !in_s && !nbr_sel;
         const bool growing = !in_s && (yi > 0.0f) && !(s > vi[m]);
         viol |= (c.do_test && ok[m] && (far || uncovered || growing)) ? 1 : 0;
+    }
+    if (c.do_write) {
+        // outputs: one uniform test per array, then the entries
+        for (int o = 0; o < 2; ++o) {
+            float* out = o == 0 ? a.y_out : a.x_out;
+            if (!out) continue;
+#pragma unroll
+            for (int m = 0; m < kRPW; ++m) {
+                const size_t e = (size_t)iw[m] * a.cols + j;
+                if (full || ok[m]) out[e] = o == 0 ? ynew[m] : xo[m];
+            }
+        }
     }
     if (unnormalizable) atomicOr(&a.st->err, 2);
     if (c.do_write && a.rp_out) write_partials(a, tr, tc, lane, wave, iw, ok, yn, pc, pcs);
