@@ -12,19 +12,8 @@
 // the next one.  Row sums use the library's canonical order (gn_rowsum.h), so
 // every graph's states, steps and selected set are bit-identical to gn_solve
 // on that graph alone.
-//
-// Sliced column layout (graphs of at most 65535 vertices).  Each degree class
-// of rows is cut into slices: 64 light rows (one per lane), 8 mid rows (8 lanes
-// each) or one heavy row (the whole wavefront).  A slice is a run of lines of
-// 64 16-bit ids, an even number of them; in line q, lane l holds entry q of
-// its light row, entry t + 8q of mid row l / 8 (t = l mod 8), or entry l + 64q
-// of the heavy row: the entry that chain q of that thread takes in the
-// canonical order.
-// Positions past a row's end hold n, the id of a state slot that stays zero,
-// so they add exactly 0 and mark no selection.  Rows are sorted by degree
-// inside each class, which keeps the padding small.  A line is read by one
-// 128-byte access, the wavefront needs no row offsets inside a step, and the
-// per-position predicates of the plain CSR walk disappear.
+
+// The sliced layout and its row sums are in gn_slices.h.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -34,61 +23,14 @@
 #include <type_traits>
 #include <vector>
 
+#include "gn_batch_internal.h"
 #include "gn_internal.h"
 #include "gn_rowsum.h"
+#include "gn_slices.h"
 
-using gnk::sign_of;
+using namespace gnsl;
 
 namespace {
-
-constexpr int kLightMaxDeg = 16;  // rows up to this degree run one per thread (64 rows per slice)
-constexpr int kMidMaxDeg = 64;    // rows up to this degree run 8 threads per row (8 rows per slice)
-constexpr int kLdsBudget = 160 * 1024 - 2048;  // dynamic LDS per CU (static LDS of the kernel set aside)
-constexpr int32_t kMaxSlicedN = 65535;          // largest graph with a sliced layout (ids and the zero slot fit 16 bits)
-
-struct BatchDesc {
-    int32_t n;        // vertices
-    int32_t n_light;  // internal rows [0, n_light) have degree <= kLightMaxDeg
-    int32_t n_mid;    // rows [n_light, n_mid) have degree <= kMidMaxDeg, rows [n_mid, n) more
-    int32_t n_lines;  // lines of the sliced layout (0 without one)
-    int64_t v_off;    // offset of the graph's vertices in the vertex arrays
-    int64_t rp_off;   // offset of its row_ptr (n + 1 entries)
-    int64_t e_off;    // offset of its columns
-    int64_t ln_off;   // first line of its sliced layout
-    int64_t so_off;   // offset of its slice table: first line of each slice (relative to ln_off), slices + 1 entries
-    int32_t nnz;      // CSR entries
-    int32_t pad1;
-};
-
-// Slices of a graph: light slices, then mid slices, then one per heavy row.
-__host__ __device__ inline int32_t slice_count(int32_t n, int32_t nl, int32_t nm) {
-    return (nl + 63) / 64 + (nm - nl + 7) / 8 + (n - nm);
-}
-
-// LDS bytes of a graph in the LDS launch: y and y' (n + 1 words each, the last
-// one the zero slot) and the slice table; MODE_ALL adds the lines.  v is read
-// from global memory: only its own row reads it, once per step, with a load
-// that does not wait on anything else.
-__host__ __device__ inline int64_t state_lds_bytes(int64_t n, int64_t slices) { return 8 * n + 8 + 4 * (slices + 1); }
-__host__ __device__ inline int64_t all_lds_bytes(int64_t n, int64_t slices, int64_t lines) {
-    return state_lds_bytes(n, slices) + 128 * lines;
-}
-
-// Where a graph's arrays live while its workgroup iterates it.
-enum BatchMode {
-    MODE_GLOBAL = 0,  // state in the global ping-pong buffers, CSR read from global memory
-    MODE_STREAM = 1,  // state and slice table in LDS, column lines read from global memory
-    MODE_ALL = 2      // state, slice table and column lines in LDS: the steps touch no global memory
-};
-
-struct BatchRes {
-    int32_t steps, binarised;
-    long long fallback;
-    double relaxed, set_w;
-    long long size, conflicts, uncovered;
-    float stab;
-    int32_t pad;
-};
 
 struct BatchArgs {
     const BatchDesc* desc;
@@ -113,42 +55,6 @@ struct BatchArgs {
     int32_t* queue;          // [0]: next slot of the LDS launch, [1]: error bits, [2]: next slot of the global launch
     BatchRes* res;
 };
-
-__device__ __forceinline__ bool step_row(float yraw, float vi, float sigma, bool nbr_sel, float g, bool do_test,
-                                         bool do_write, float tau, float* y_out, int i, int& fb) {
-    const float yi = fabsf(yraw);
-    const float s = __fmaf_rn(g, sigma, yi);
-    const bool fallback = !(s > 1e-9f);
-    const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
-    if (do_write) {
-        const float yn = vi * xn;
-        y_out[i] = xn > 0.5f ? -yn : yn;
-        fb += fallback ? 1 : 0;
-    }
-    if (!do_test) return false;
-    const bool in_s = sign_of(yraw) != 0u;
-    const float tv = tau * vi;
-    const bool far = (yi > tv) && ((vi - yi) > tv);
-    const bool uncovered = !in_s && !nbr_sel;
-    const bool growing = !in_s && (yi > 0.0f) && !(s > vi);
-    return far || uncovered || growing;
-}
-
-// Workgroup vote "some row failed the stopping test" with one barrier per step.
-// A wavefront with a failure sets flags[f]; every thread reads it after the
-// barrier; thread 0 then clears flags[(f + 2) mod 3], which was read before this
-// barrier and is written again only after the next one.  The three flags must
-// be zero before the first step.  The barrier also orders the step's state
-// writes before the next step's reads.
-__device__ __forceinline__ bool block_any_step(bool viol, int* flags, int& f) {
-    if (__ballot(viol) != 0ull && (threadIdx.x & 63) == 0) flags[f] = 1;
-    __syncthreads();
-    const bool any = flags[f] != 0;
-    const int nx = f == 2 ? 0 : f + 1;
-    if (threadIdx.x == 0) flags[nx == 2 ? 0 : nx + 1] = 0;
-    f = nx;
-    return any;
-}
 
 template <int BT>
 __device__ double block_sum_d(double x, double* sm) {
@@ -213,104 +119,6 @@ __device__ __forceinline__ bool mid_rows(const int32_t* __restrict__ rp, const C
         if (valid && t == 0) viol |= step_row(yin[i], vv[i], sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
     }
     return viol;
-}
-
-// Row sum over the first K lines of a light (G = 1, NQ = 16) or mid (G = 8,
-// NQ = 8) slice in the canonical order: line q feeds chain q mod NQ of the
-// thread, in increasing q (a mid row of degree up to 128 has two lines per
-// chain), the chains meet in the in-thread butterfly, then the group's
-// shuffles.  `ln` points at this lane's id in the slice's first line; the
-// lines are 64 ids apart.  ORs the raw bits of the gathered values into `bits`
-// (bit 31: some neighbour is selected).  Straight-line code: the K id loads,
-// then the K gathers, each phase back to back.  Chains without a line are
-// zero, and adding zero to a sum of magnitudes (never -0) changes nothing, so
-// those additions of the butterfly are left out.  ABS = false sums the raw
-// (signed) values, as the adjoint does: every chain starts at +0 and adds, so
-// no partial sum is ever -0 (round to nearest) and the skipped additions of
-// zero still change nothing.
-template <int G, int NQ, int K, bool ABS = true, typename LT>
-__device__ __forceinline__ float slice_sum_k(const LT* __restrict__ ln, const float* __restrict__ y,
-                                             unsigned& bits) {
-    int id[K > 0 ? K : 1];
-    float c[NQ];
-#pragma unroll
-    for (int q = 0; q < K; ++q) id[q] = ln[64 * q];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) c[q] = 0.0f;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        const float yv = y[id[q]];
-        if (q < NQ) c[q] = ABS ? fabsf(yv) : 0.0f + yv;
-        else c[q % NQ] += ABS ? fabsf(yv) : yv;
-        if (ABS) bits |= __float_as_uint(yv);
-    }
-#pragma unroll
-    for (int h = NQ / 2; h >= 1; h >>= 1)
-#pragma unroll
-        for (int j = 0; j < h; ++j)
-            if (j + h < K) c[j] += c[j + h];
-    float s = c[0];
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    return s;
-}
-
-// The same for a slice of W lines, W even (slices are padded to an even number
-// of lines), at most MAXL and uniform over the wavefront: one straight-line
-// variant per W.
-template <int G, int NQ, int MAXL, bool ABS = true, typename LT>
-__device__ __forceinline__ float slice_sum(const LT* __restrict__ ln, int W, const float* __restrict__ y,
-                                           unsigned& bits) {
-    static_assert(MAXL % 2 == 0 && MAXL <= 16, "slice widths");
-    switch (W) {
-        case 2: return slice_sum_k<G, NQ, 2, ABS>(ln, y, bits);
-        case 4: return slice_sum_k<G, NQ, 4, ABS>(ln, y, bits);
-        case 6: return slice_sum_k<G, NQ, 6, ABS>(ln, y, bits);
-        case 8: return slice_sum_k<G, NQ, 8, ABS>(ln, y, bits);
-        case 10: if constexpr (MAXL >= 10) return slice_sum_k<G, NQ, 10, ABS>(ln, y, bits); else break;
-        case 12: if constexpr (MAXL >= 12) return slice_sum_k<G, NQ, 12, ABS>(ln, y, bits); else break;
-        case 14: if constexpr (MAXL >= 14) return slice_sum_k<G, NQ, 14, ABS>(ln, y, bits); else break;
-        case 16: if constexpr (MAXL >= 16) return slice_sum_k<G, NQ, 16, ABS>(ln, y, bits); else break;
-        default: break;
-    }
-    return slice_sum_k<G, NQ, 0, ABS>(ln, y, bits);
-}
-
-// K lines of a heavy slice added to the lane's chain, in line order.
-template <int K, bool ABS = true, typename LT>
-__device__ __forceinline__ void heavy_lines(const LT* __restrict__ ln, const float* __restrict__ y, float& acc,
-                                            unsigned& bits) {
-    int id[K];
-    float yv[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) id[q] = ln[64 * q];
-#pragma unroll
-    for (int q = 0; q < K; ++q) yv[q] = y[id[q]];
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        acc += ABS ? fabsf(yv[q]) : yv[q];
-        if (ABS) bits |= __float_as_uint(yv[q]);
-    }
-}
-
-// Row sum over a heavy slice (one row, the whole wavefront; W even): lane l
-// adds entries l + 64q in increasing q (the chain of virtual lane l), eight
-// lines in flight at a time, then the 64-lane butterfly.
-template <bool ABS = true, typename LT>
-__device__ __forceinline__ float heavy_sum(const LT* __restrict__ ln, int W, const float* __restrict__ y,
-                                           unsigned& bits) {
-    float acc = 0.0f;
-    int q0 = 0;
-#pragma unroll 1
-    for (; q0 + 8 <= W; q0 += 8) heavy_lines<8, ABS>(ln + 64 * q0, y, acc, bits);
-    switch (W - q0) {
-        case 2: heavy_lines<2, ABS>(ln + 64 * q0, y, acc, bits); break;
-        case 4: heavy_lines<4, ABS>(ln + 64 * q0, y, acc, bits); break;
-        case 6: heavy_lines<6, ABS>(ln + 64 * q0, y, acc, bits); break;
-        default: break;
-    }
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    return acc;
 }
 
 template <int BT, int MODE>
@@ -555,282 +363,6 @@ __global__ __launch_bounds__(BT) void batch_solve_kernel(BatchArgs a) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Unrolled (differentiable) steps of a whole batch: every graph's T forward
-// steps, or its T adjoint steps, in one workgroup with its state in LDS.  The
-// arithmetic repeats the chained unrolled path (gn_unrolled.hip) operation for
-// operation -- y = v x, s = y + gamma sum |y_j|, x' = y / s with the safe
-// division and support bound; t = gbar y / s^2, dL/dy = gbar / s - (t + gamma
-// sum t_j), dL/dx = v dL/dy, dL/dv += x dL/dy, dL/dw = dL/dv / (2 v) -- with the
-// same canonical sums, so results are bit-identical to it on the batch's
-// block-diagonal union graph.
-// ---------------------------------------------------------------------------
-struct UnrolledArgs {
-    const BatchDesc* desc;
-    const int32_t* order;    // graphs, most entries first
-    int32_t count;
-    int32_t* queue;          // next graph to take
-    const int32_t* perm;
-    const uint16_t* lines;
-    const int32_t* slices;
-    const float* v;          // sqrt(w), internal order
-    const float* gamma;      // [T]
-    int32_t T;
-    int32_t lds_bytes;       // dynamic LDS per workgroup
-    int64_t total_n;
-    const float* x0;         // forward: x0 and xT, user order
-    float* xT;
-    float* store;            // y of every step ([T][total_n]), then s ([T][total_n]), internal order
-    const float* gxT;        // backward: dL/dx^T in, dL/dx^0 and dL/dw out, user order
-    float* gx0;
-    float* gw;
-};
-
-// Whether the forward step took the quotient branch at this row (the same test
-// on the same fp32 values as the chained adjoint).
-__device__ __forceinline__ bool unrolled_quotient(float y, float s) {
-    if (!(s > 1e-9f)) return false;
-    return !(y > 0.0f && y / s < gnk::kXMin);
-}
-
-// Slice loops of one step over a graph's sliced layout: for every valid row,
-// `load(i)` (the row's own global values, issued before the neighbour sum so
-// that their latency hides behind it), then `row(i, sigma, loaded)` with the
-// neighbour sum over `src` (absolute values when ABS).
-template <int BT, bool ABS, typename LT, typename Load, typename Row>
-__device__ __forceinline__ void unrolled_slices(const BatchDesc& d, const int32_t* so, const LT* __restrict__ ln,
-                                                const float* src, Load&& load, Row&& row) {
-    using Pre = decltype(load(0));
-    constexpr int NW = BT / 64;
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int n = d.n;
-    const int nL = (d.n_light + 63) / 64, nM = (d.n_mid - d.n_light + 7) / 8;
-    const int w_mid = (wave - nL % NW + NW) % NW;
-    const int w_heavy = (wave - (nL + nM) % NW + NW) % NW;
-#pragma unroll 1
-    for (int s = wave; s < nL; s += NW) {
-        const int i = 64 * s + lane;
-        const bool valid = i < d.n_light;
-        Pre pre{};
-        if (valid) pre = load(i);
-        const int o = so[s];
-        const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
-        unsigned bits = 0u;
-        const float sigma = slice_sum<1, 16, kLightMaxDeg, ABS>(ln + o * 64 + lane, W, src, bits);
-        if (valid) row(i, sigma, pre);
-    }
-#pragma unroll 1
-    for (int s = w_mid; s < nM; s += NW) {
-        const int i = d.n_light + 8 * s + (lane >> 3);
-        const bool valid = i < d.n_mid && (lane & 7) == 0;
-        Pre pre{};
-        if (valid) pre = load(i);
-        const int o = so[nL + s];
-        const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
-        unsigned bits = 0u;
-        const float sigma = slice_sum<8, 8, kMidMaxDeg / 8, ABS>(ln + o * 64 + lane, W, src, bits);
-        if (valid) row(i, sigma, pre);
-    }
-#pragma unroll 1
-    for (int s = w_heavy; s < n - d.n_mid; s += NW) {
-        const int i = d.n_mid + s;
-        Pre pre{};
-        if (lane == 0) pre = load(i);
-        const int o = so[nL + nM + s];
-        const int W = __builtin_amdgcn_readfirstlane(so[nL + nM + s + 1] - o);
-        unsigned bits = 0u;
-        const float sigma = heavy_sum<ABS>(ln + o * 64 + lane, W, src, bits);
-        if (lane == 0) row(i, sigma, pre);
-    }
-}
-
-struct FwdPre {
-    float v;
-};
-struct BwdPre {
-    float v, y, s, yp, sp;
-};
-
-// Copies a graph's slice table (and, MODE_ALL, its lines) into LDS at `so`.
-template <int BT, int MODE>
-__device__ __forceinline__ const uint16_t* unrolled_stage(const UnrolledArgs& a, const BatchDesc& d, int32_t* so) {
-    const int tid = threadIdx.x;
-    const int nS = slice_count(d.n, d.n_light, d.n_mid);
-    uint16_t* ln_l = reinterpret_cast<uint16_t*>(so + nS + 1);
-    const uint16_t* ln_g = a.lines + d.ln_off * 64;
-    for (int s = tid; s <= nS; s += BT) so[s] = a.slices[d.so_off + s];
-    if constexpr (MODE == MODE_ALL) {
-        const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(ln_g);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(ln_l);
-        const int nw = d.n_lines * 32;
-        for (int w = tid; w < nw; w += BT) dst[w] = src[w];
-        return ln_l;
-    } else {
-        return ln_g;
-    }
-}
-
-// T forward steps of one graph; LDS: y, y' (n + 1 words each, the last the zero
-// slot), slice table, lines (MODE_ALL).
-template <int BT, int MODE>
-__device__ void unrolled_fwd_graph(const UnrolledArgs& a, const BatchDesc& d, float* lds) {
-    const int n = d.n;
-    if (n == 0) return;
-    const int tid = threadIdx.x;
-    float* ya = lds;
-    float* yb = lds + (n + 1);
-    int32_t* so = reinterpret_cast<int32_t*>(lds + 2 * n + 2);
-    const float* __restrict__ vv = a.v + d.v_off;
-    const int32_t* __restrict__ perm = a.perm + d.v_off;
-    for (int i = tid; i < n; i += BT) ya[i] = vv[i] * a.x0[d.v_off + perm[i]];
-    if (tid == 0) {
-        ya[n] = 0.0f;
-        yb[n] = 0.0f;
-    }
-    const uint16_t* ln;
-    if constexpr (MODE == MODE_ALL) ln = unrolled_stage<BT, MODE>(a, d, so);
-    else ln = unrolled_stage<BT, MODE>(a, d, so);
-    __syncthreads();
-    float* yin = ya;
-    float* yout = yb;
-    for (int t = 0; t < a.T; ++t) {
-        const float g = a.gamma[t];
-        float* ys = a.store + (int64_t)t * a.total_n + d.v_off;
-        float* ss = a.store + (int64_t)(a.T + t) * a.total_n + d.v_off;
-        float* xT = t == a.T - 1 ? a.xT + d.v_off : nullptr;
-        unrolled_slices<BT, true>(
-            d, so, ln, yin, [&](int i) { return FwdPre{vv[i]}; },
-            [&](int i, float sigma, const FwdPre& p) {
-                const float yraw = yin[i];
-                const float yi = fabsf(yraw);
-                const float s = __fmaf_rn(g, sigma, yi);
-                const float xn = !(s > 1e-9f) ? 0.5f : gnk::bounded_ratio(yi, s);
-                ys[i] = yraw;
-                ss[i] = s;
-                const float yn = p.v * xn;
-                yout[i] = xn > 0.5f ? -yn : yn;
-                if (xT) xT[perm[i]] = xn;
-            });
-        __syncthreads();
-        float* tmp = yin;
-        yin = yout;
-        yout = tmp;
-    }
-}
-
-// T adjoint steps of one graph, last to first; LDS: t (ping-pong, n + 1 words
-// each with the zero slot), dL/dx, dL/dv (n words each), slice table, lines.
-template <int BT, int MODE>
-__device__ void unrolled_bwd_graph(const UnrolledArgs& a, const BatchDesc& d, float* lds) {
-    const int n = d.n;
-    if (n == 0) return;
-    const int tid = threadIdx.x;
-    float* ta = lds;
-    float* tb = lds + (n + 1);
-    float* gb = lds + 2 * (n + 1);
-    float* gv = gb + n;
-    int32_t* so = reinterpret_cast<int32_t*>(gv + n);
-    const float* __restrict__ vv = a.v + d.v_off;
-    const int32_t* __restrict__ perm = a.perm + d.v_off;
-    const int T = a.T;
-    const float* ylast = a.store + (int64_t)(T - 1) * a.total_n + d.v_off;
-    const float* slast = a.store + (int64_t)(2 * T - 1) * a.total_n + d.v_off;
-    for (int i = tid; i < n; i += BT) {
-        const float g = a.gxT[d.v_off + perm[i]];
-        gb[i] = g;
-        gv[i] = 0.0f;
-        const float yy = fabsf(ylast[i]), s = slast[i];
-        ta[i] = unrolled_quotient(yy, s) ? (g / s) * (yy / s) : 0.0f;
-    }
-    if (tid == 0) {
-        ta[n] = 0.0f;
-        tb[n] = 0.0f;
-    }
-    const uint16_t* ln;
-    if constexpr (MODE == MODE_ALL) ln = unrolled_stage<BT, MODE>(a, d, so);
-    else ln = unrolled_stage<BT, MODE>(a, d, so);
-    __syncthreads();
-    float* tin = ta;
-    float* tout = tb;
-    for (int t = T - 1; t >= 0; --t) {
-        const float gam = a.gamma[t];
-        const float* yk = a.store + (int64_t)t * a.total_n + d.v_off;
-        const float* sk = a.store + (int64_t)(T + t) * a.total_n + d.v_off;
-        const float* yp = t > 0 ? a.store + (int64_t)(t - 1) * a.total_n + d.v_off : nullptr;
-        const float* sp = t > 0 ? a.store + (int64_t)(T + t - 1) * a.total_n + d.v_off : nullptr;
-        unrolled_slices<BT, false>(
-            d, so, ln, tin,
-            [&](int i) {
-                BwdPre p;
-                p.v = vv[i];
-                p.y = fabsf(yk[i]);
-                p.s = sk[i];
-                p.yp = yp ? fabsf(yp[i]) : 0.0f;
-                p.sp = yp ? sp[i] : 0.0f;
-                return p;
-            },
-            [&](int i, float sigma, const BwdPre& p) {
-                const float g = gb[i];
-                const float ai = unrolled_quotient(p.y, p.s) ? g / p.s : 0.0f;
-                const float gy = ai - __fmaf_rn(gam, sigma, tin[i]);
-                const float gx = p.v * gy;
-                gb[i] = gx;
-                gv[i] += (p.y / p.v) * gy;
-                if (yp) tout[i] = unrolled_quotient(p.yp, p.sp) ? (gx / p.sp) * (p.yp / p.sp) : 0.0f;
-            });
-        __syncthreads();
-        float* tmp = tin;
-        tin = tout;
-        tout = tmp;
-    }
-    for (int i = tid; i < n; i += BT) {
-        a.gx0[d.v_off + perm[i]] = gb[i];
-        a.gw[d.v_off + perm[i]] = gv[i] / (2.0f * vv[i]);
-    }
-    __syncthreads();
-}
-
-// LDS bytes of one graph in the unrolled kernels: the state words of the
-// forward (2) or adjoint (4) pass per vertex, the zero slots, the slice table,
-// and -- with lines -- the lines.
-__host__ __device__ inline int64_t unrolled_state_bytes(bool bwd, int64_t n, int64_t slices) {
-    return (bwd ? 16 : 8) * n + 8 + 4 * (slices + 1);
-}
-
-template <int BT, bool BWD>
-__global__ __launch_bounds__(BT) void batch_unrolled_kernel(UnrolledArgs a) {
-    extern __shared__ float lds[];
-    __shared__ int s_g;
-    for (;;) {
-        if (threadIdx.x == 0) s_g = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int q = s_g;
-        __syncthreads();
-        if (q >= a.count) break;
-        const BatchDesc d = a.desc[a.order[q]];
-        const int64_t slices = slice_count(d.n, d.n_light, d.n_mid);
-        const bool all = unrolled_state_bytes(BWD, d.n, slices) + 128 * (int64_t)d.n_lines <= a.lds_bytes;
-        if constexpr (BWD) {
-            if (all) unrolled_bwd_graph<BT, MODE_ALL>(a, d, lds);
-            else unrolled_bwd_graph<BT, MODE_STREAM>(a, d, lds);
-        } else {
-            if (all) unrolled_fwd_graph<BT, MODE_ALL>(a, d, lds);
-            else unrolled_fwd_graph<BT, MODE_STREAM>(a, d, lds);
-        }
-    }
-}
-
-// sqrt of caller weights (user order within each graph) into the batch's
-// internal order: the same (float)sqrt((double)w) as the graph handles use.
-__global__ void batch_sqrt_weights_kernel(int64_t total, const int32_t* __restrict__ vgraph,
-                                          const BatchDesc* __restrict__ desc, const int32_t* __restrict__ perm,
-                                          const float* __restrict__ w_cat, float* __restrict__ v) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const BatchDesc d = desc[vgraph[t]];
-    v[t] = (float)sqrt((double)w_cat[d.v_off + perm[t]]);
-}
-
 // Reset queue / error bits and fill the gamma table (Section 6 gamma-pursuit).
 __global__ void batch_init_kernel(int32_t* queue, float* gamma, int32_t max_steps, float g0, float g1, int32_t ramp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -879,212 +411,12 @@ __global__ void batch_check_x0_kernel(int64_t total, const int32_t* __restrict__
     atomicOr(queue + 1, 2);
 }
 
-// One small graph, one workgroup: the whole solve in a single launch, steps
-// separated by workgroup barriers instead of kernel boundaries.  Works on the
-// graph handle's internal order: rows [0, mid_begin) have degree > 128 (one
-// wavefront each), rows [mid_begin, light_begin) degree 17 .. 128 (8 threads
-// each), the rest degree <= 16 (a thread each).  The graph's LDS image -- the
-// sliced layout of the head of this file, lines of up to 16 per mid slice --
-// is copied into LDS with y (ping-pong, n + 1 words each with the zero slot);
-// v is read from global memory by its own row.  Same arithmetic and canonical
-// sums as the step kernel, so the result is bit-identical to the chained
-// solve.  One compute unit does all the work, so this pays only while a step
-// is small.  On entry y0 holds the signed starting state (prep_state_kernel);
-// on exit the final state is in y0 or y1 by the parity of the step count, as
-// after the chained solve.
-struct SmallArgs {
-    int32_t n, mid_begin, light_begin, n_lines;
-    const int32_t* slices;   // slice table: light, mid, then heavy slices
-    const uint16_t* lines;   // the slices' lines
-    const float* v;
-    const float* gamma;
-    SolveState* st;
-    int32_t* notconv;
-    float* y0;
-    float* y1;
-};
-
-template <int BT>
-__global__ __launch_bounds__(BT) void small_solve_kernel(SmallArgs a) {
-    extern __shared__ float lds[];
-    __shared__ int s_fb;
-    __shared__ int s_flags[3];
-    constexpr int NW = BT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    SolveState* st = a.st;
-    if (st->err) return;  // x0 rejected by the checks before this launch
-    const int ms = st->max_steps, ce = st->check_every;
-    const float tau = st->tau;
-    const int n = a.n, mb = a.mid_begin, lb = a.light_begin;
-    const int nL = (n - lb + 63) / 64, nM = (lb - mb + 7) / 8, nH = mb;
-    const int nS = nL + nM + nH;
-    const int w_mid = (wave - nL % NW + NW) % NW;
-    const int w_heavy = (wave - (nL + nM) % NW + NW) % NW;
-    float* ya = lds;
-    float* yb = lds + (n + 1);
-    int32_t* so = reinterpret_cast<int32_t*>(lds + 2 * n + 2);
-    uint16_t* ln = reinterpret_cast<uint16_t*>(so + nS + 1);
-    const float* __restrict__ vv = a.v;
-    for (int i = tid; i < n; i += BT) ya[i] = a.y0[i];
-    if (tid == 0) {
-        ya[n] = 0.0f;
-        yb[n] = 0.0f;
-        s_fb = 0;
-    }
-    for (int s = tid; s <= nS; s += BT) so[s] = a.slices[s];
-    {
-        const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(a.lines);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(ln);
-        const int nw = a.n_lines * 32;
-        for (int w = tid; w < nw; w += 4 * BT) {
-            uint32_t t[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) t[u] = w + u * BT < nw ? src[w + u * BT] : 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (w + u * BT < nw) dst[w + u * BT] = t[u];
-        }
-    }
-    if (tid < 3) s_flags[tid] = 0;
-    __syncthreads();
-    float* yin = ya;
-    float* yout = yb;
-    int fb = 0;
-    int steps = 0;
-    bool binarised = false;
-    float g_next = a.gamma[0];
-    int fslot = 0, kc = 0;  // vote slot; k mod check_every
-    for (int k = 0;; ++k) {
-        const bool do_test = k >= 1 && (kc == 0 || k == ms);
-        const bool do_write = k < ms;
-        // gamma of the next step is loaded one step ahead (the table covers
-        // indices 0 .. max_steps): no global round trip on the step's path
-        const float g = g_next;
-        if (k + 1 <= ms) g_next = a.gamma[k + 1];
-        bool viol = false;
-#pragma unroll 1
-        for (int s = wave; s < nL; s += NW) {
-            const int i = lb + 64 * s + lane;
-            const bool valid = i < n;
-            const float vi = valid ? vv[i] : 1.0f;
-            const int o = so[s];
-            const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
-            unsigned bits = 0u;
-            const float sigma = slice_sum<1, 16, 16>(ln + o * 64 + lane, W, yin, bits);
-            if (valid) viol |= step_row(yin[i], vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, tau, yout, i, fb);
-        }
-#pragma unroll 1
-        for (int s = w_mid; s < nM; s += NW) {
-            const int i = mb + 8 * s + (lane >> 3);
-            const bool valid = i < lb && (lane & 7) == 0;
-            const float vi = valid ? vv[i] : 1.0f;
-            const int o = so[nL + s];
-            const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
-            unsigned bits = 0u;
-            const float sigma = slice_sum<8, 8, 16>(ln + o * 64 + lane, W, yin, bits);
-            const bool any_sel = gnk::group_any<8>((bits >> 31) != 0u);
-            if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
-        }
-#pragma unroll 1
-        for (int s = w_heavy; s < nH; s += NW) {
-            const int i = s;
-            const float vi = lane == 0 ? vv[i] : 1.0f;
-            const int o = so[nL + nM + s];
-            const int W = __builtin_amdgcn_readfirstlane(so[nL + nM + s + 1] - o);
-            unsigned bits = 0u;
-            const float sigma = heavy_sum(ln + o * 64 + lane, W, yin, bits);
-            const bool any_sel = __any((bits >> 31) != 0u);
-            if (lane == 0) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, tau, yout, i, fb);
-        }
-        const bool any = block_any_step(viol, s_flags, fslot);
-        if (do_test && !any) {
-            binarised = true;
-            steps = k;
-            break;
-        }
-        if (!do_write) {
-            steps = k;
-            break;
-        }
-        float* t = yin;
-        yin = yout;
-        yout = t;
-        kc = kc + 1 == ce ? 0 : kc + 1;
-    }
-    if (fb) atomicAdd(&s_fb, fb);
-    float* dst = (steps & 1) ? a.y1 : a.y0;
-    for (int i = tid; i < n; i += BT) dst[i] = yin[i];
-    __syncthreads();
-    if (tid == 0) {
-        st->fallback = (unsigned long long)s_fb;
-        if (binarised) st->done_step = steps;
-        else a.notconv[ms] = 1;
-    }
-}
-
 template <int BT, bool BIG>
 const void* batch_kernel_ptr() {
     return (const void*)batch_solve_kernel<BT, BIG>;
 }
 
 }  // namespace
-
-// The executable graph of the last solve and what it was built for.
-struct BatchLaunch {
-    hipGraphExec_t exec = nullptr;
-    gn_tuning t{};
-    gn_schedule sch{};
-    const float* x = nullptr;
-    const uint8_t* sel = nullptr;
-    const float* gamma = nullptr;
-};
-
-struct gn_batch {
-    int32_t count = 0;
-    int64_t total_n = 0, total_nnz = 0;
-    int32_t max_n = 0;
-    int device = 0;
-    int32_t cus = 0;
-    BatchDesc* desc = nullptr;
-    int32_t* order = nullptr;      // graphs that fit the LDS state size, then the others (for split_lds)
-    std::vector<int32_t> h_order;  // all graphs, most entries first
-    int32_t split_lds = -1;        // lds_vertices the device order was split for
-    int32_t n_fit = 0;             // graphs whose LDS state fits 12 * split_lds bytes
-    std::vector<int64_t> h_state;  // per graph: state_lds_bytes, or INT64_MAX without a sliced layout
-    std::vector<int32_t> h_slices, h_lines;  // per graph: slices and lines of the sliced layout (-1 without)
-    // unrolled (differentiable) calls: graph order, queue counter, gamma table,
-    // sqrt of caller weights; allocated on first use
-    int32_t* u_order = nullptr;
-    int32_t* u_queue = nullptr;
-    float* u_gamma = nullptr;
-    int32_t u_gamma_cap = 0;
-    std::vector<float> u_gamma_host;  // the table's current contents
-    float* u_v = nullptr;
-    int32_t* vgraph = nullptr;
-    int32_t* row_ptr = nullptr;
-    int32_t* col = nullptr;
-    uint16_t* lines = nullptr;  // sliced layouts
-    int32_t* slices = nullptr;  // slice tables
-    float* v = nullptr;
-    float* w = nullptr;
-    int32_t* perm = nullptr;
-    float* yg0 = nullptr;
-    float* yg1 = nullptr;
-    int32_t* queue = nullptr;
-    float* gamma = nullptr;
-    int32_t gamma_cap = 0;
-    BatchRes* res = nullptr;
-    BatchRes* res_host = nullptr;  // pinned
-    bool tuned = false;
-    gn_tuning tuning{};
-    BatchLaunch launch;
-    // host copies of the caller's CSR for the block-diagonal union graph
-    std::vector<int32_t> h_n;
-    std::vector<int64_t> h_nnz;
-    std::vector<int32_t> h_rp, h_ci;
-    std::vector<float> h_w;
-    gn_graph* uni = nullptr;
-};
 
 static void batch_free(gn_batch* b) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
@@ -1101,68 +433,6 @@ extern "C" void gn_batch_destroy(gn_batch* b) {
     (void)hipDeviceSynchronize();
     batch_free(b);
     delete b;
-}
-
-template <typename T>
-static bool dalloc(T** p, size_t count) {
-    if (count == 0) count = 1;
-    if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return false;
-    }
-    return true;
-}
-
-// Appends the sliced layout of one graph (see the head of this file) to
-// `lines` and its slice table to `slices`: light rows [lb, le) in slices of 64,
-// mid rows [mb, me) in slices of 8, heavy rows [hb, he) one per slice, in this
-// order; row r holds entries col[rp[r] .. rp[r+1]) of a graph of n vertices
-// (n <= kMaxSlicedN).  Widths are rounded up to even; padding holds n.
-// Returns the graph's line count.
-static int64_t build_slices(int32_t n, const int32_t* rp, const int32_t* col, int32_t lb, int32_t le, int32_t mb,
-                            int32_t me, int32_t hb, int32_t he, std::vector<uint16_t>& lines,
-                            std::vector<int32_t>& slices) {
-    const int32_t nL = (le - lb + 63) / 64, nM = (me - mb + 7) / 8, nH = he - hb;
-    auto deg = [&](int32_t r) { return rp[r + 1] - rp[r]; };
-    const size_t ln0 = lines.size() / 64, so0 = slices.size();
-    int64_t acc = 0;
-    slices.push_back(0);
-    for (int32_t sl = 0; sl < nL; ++sl) {
-        int32_t wdt = 0;
-        for (int32_t r = lb + 64 * sl; r < std::min(lb + 64 * sl + 64, le); ++r) wdt = std::max(wdt, deg(r));
-        acc += (wdt + 1) & ~1;
-        slices.push_back((int32_t)acc);
-    }
-    for (int32_t sl = 0; sl < nM; ++sl) {
-        int32_t wdt = 0;
-        for (int32_t r = mb + 8 * sl; r < std::min(mb + 8 * sl + 8, me); ++r) wdt = std::max(wdt, (deg(r) + 7) / 8);
-        acc += (wdt + 1) & ~1;
-        slices.push_back((int32_t)acc);
-    }
-    for (int32_t sl = 0; sl < nH; ++sl) {
-        acc += (((deg(hb + sl) + 63) / 64) + 1) & ~1;
-        slices.push_back((int32_t)acc);
-    }
-    lines.resize(lines.size() + (size_t)acc * 64, (uint16_t)n);
-    uint16_t* lg = lines.data() + ln0 * 64;
-    const int32_t* so = slices.data() + so0;
-    auto cid = [&](int32_t r, int32_t e) { return (uint16_t)col[rp[r] + e]; };
-    for (int32_t sl = 0; sl < nL; ++sl)
-        for (int32_t l = 0; l < 64 && lb + 64 * sl + l < le; ++l) {
-            const int32_t r = lb + 64 * sl + l;
-            for (int32_t e = 0; e < deg(r); ++e) lg[(size_t)(so[sl] + e) * 64 + l] = cid(r, e);
-        }
-    for (int32_t sl = 0; sl < nM; ++sl)
-        for (int32_t l = 0; l < 64 && mb + 8 * sl + l / 8 < me; ++l) {
-            const int32_t r = mb + 8 * sl + l / 8, t = l % 8;
-            for (int32_t e = t; e < deg(r); e += 8) lg[(size_t)(so[nL + sl] + e / 8) * 64 + l] = cid(r, e);
-        }
-    for (int32_t sl = 0; sl < nH; ++sl) {
-        const int32_t r = hb + sl;
-        for (int32_t e = 0; e < deg(r); ++e) lg[(size_t)(so[nL + nM + sl] + e / 64) * 64 + e % 64] = cid(r, e);
-    }
-    return acc;
 }
 
 extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int64_t* nnz, const int32_t* row_ptr_cat,
@@ -1279,7 +549,7 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
             w_int[(size_t)(vo + r)] = wg[i];
             vgraph[(size_t)(vo + r)] = g;
         }
-        // sliced layout (see the head of this file)
+        // sliced layout (gn_slices.h)
         const int64_t ln0 = (int64_t)(lines.size() / 64), so0 = (int64_t)slices.size();
         int32_t nlines = 0;
         if (ng <= kMaxSlicedN) {
@@ -1309,11 +579,11 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     b->cus = cus > 0 ? cus : 256;
-    bool ok = dalloc(&b->desc, count) && dalloc(&b->order, count) && dalloc(&b->vgraph, tn) &&
-              dalloc(&b->row_ptr, trp) && dalloc(&b->col, tnnz) && dalloc(&b->lines, std::max<size_t>(lines.size(), 64)) &&
-              dalloc(&b->slices, slices.size()) && dalloc(&b->v, tn) && dalloc(&b->w, tn) &&
-              dalloc(&b->perm, tn) && dalloc(&b->yg0, tn) && dalloc(&b->yg1, tn) && dalloc(&b->queue, 3) &&
-              dalloc(&b->res, count);
+    bool ok = gn_dalloc(&b->desc, count) && gn_dalloc(&b->order, count) && gn_dalloc(&b->vgraph, tn) &&
+              gn_dalloc(&b->row_ptr, trp) && gn_dalloc(&b->col, tnnz) && gn_dalloc(&b->lines, std::max<size_t>(lines.size(), 64)) &&
+              gn_dalloc(&b->slices, slices.size()) && gn_dalloc(&b->v, tn) && gn_dalloc(&b->w, tn) &&
+              gn_dalloc(&b->perm, tn) && gn_dalloc(&b->yg0, tn) && gn_dalloc(&b->yg1, tn) && gn_dalloc(&b->queue, 3) &&
+              gn_dalloc(&b->res, count);
     if (ok && hipHostMalloc((void**)&b->res_host, sizeof(BatchRes) * count, hipHostMallocDefault) != hipSuccess) {
         b->res_host = nullptr;
         ok = false;
@@ -1371,7 +641,7 @@ static gn_status ensure_gamma(gn_batch* b, int32_t entries) {
     if (b->gamma) (void)hipFree(b->gamma);
     b->gamma = nullptr;
     b->gamma_cap = 0;
-    if (!dalloc(&b->gamma, (size_t)entries)) return GN_E_NOMEM;
+    if (!gn_dalloc(&b->gamma, (size_t)entries)) return GN_E_NOMEM;
     b->gamma_cap = entries;
     return GN_OK;
 }
@@ -1620,7 +890,7 @@ extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_t
     ws.max_steps = std::min<int32_t>(sch->max_steps, 64);
     float* x = nullptr;
     uint8_t* sel = nullptr;
-    if (!dalloc(&x, (size_t)b->total_n) || !dalloc(&sel, (size_t)b->total_n)) {
+    if (!gn_dalloc(&x, (size_t)b->total_n) || !gn_dalloc(&sel, (size_t)b->total_n)) {
         if (x) (void)hipFree(x);
         return GN_E_NOMEM;
     }
@@ -1698,231 +968,3 @@ extern "C" const gn_graph* gn_batch_graph(const gn_batch* bc) {
     return u;
 }
 
-// ---------------------------------------------------------------------------
-// Unrolled (differentiable) calls on a batch.
-// ---------------------------------------------------------------------------
-template <int BT, bool BWD>
-const void* unrolled_kernel_ptr() {
-    return (const void*)batch_unrolled_kernel<BT, BWD>;
-}
-
-// Workgroup size of the unrolled kernels: 1024 threads when every graph has a
-// compute unit to itself (more wavefronts share a graph's slices), else 512 so
-// that two graphs share one.  Results do not depend on it.
-static int unrolled_block(const gn_batch* b) { return b->count <= b->cus ? 1024 : 512; }
-
-static const void* unrolled_kernel(int bt, bool bwd) {
-    if (bt == 1024) return bwd ? unrolled_kernel_ptr<1024, true>() : unrolled_kernel_ptr<1024, false>();
-    return bwd ? unrolled_kernel_ptr<512, true>() : unrolled_kernel_ptr<512, false>();
-}
-
-static gn_status unrolled_prepare(gn_batch* b, const float* w_cat, const float* gammas, int32_t T, bool bwd,
-                                  hipStream_t s, UnrolledArgs& a, dim3& grid, size_t& lds) {
-    // every graph needs a sliced layout whose state fits one workgroup's LDS
-    int64_t maxstate = 0, maxall = 0;
-    for (int32_t g = 0; g < b->count; ++g) {
-        if (b->h_n[g] == 0) continue;
-        if (b->h_slices[g] < 0) return GN_E_ARG;
-        const int64_t st = unrolled_state_bytes(bwd, b->h_n[g], b->h_slices[g]);
-        maxstate = std::max(maxstate, st);
-        maxall = std::max(maxall, st + 128 * (int64_t)b->h_lines[g]);
-    }
-    if (maxstate > kLdsBudget) return GN_E_ARG;
-    const int bt = unrolled_block(b);
-    const int bpc_want = bt == 512 && maxstate <= kLdsBudget / 2 ? 2 : 1;
-    lds = (size_t)((std::min<int64_t>(std::max(maxall, maxstate), kLdsBudget / bpc_want) + 15) / 16 * 16);
-    if (!b->u_order) {
-        if (!dalloc(&b->u_order, (size_t)b->count) || !dalloc(&b->u_queue, 1)) return GN_E_NOMEM;
-        GN_HIP_TRY(hipMemcpy(b->u_order, b->h_order.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice));
-    }
-    if (T > b->u_gamma_cap) {
-        if (b->u_gamma) (void)hipFree(b->u_gamma);
-        b->u_gamma = nullptr;
-        b->u_gamma_cap = 0;
-        b->u_gamma_host.clear();
-        if (!dalloc(&b->u_gamma, (size_t)T)) return GN_E_NOMEM;
-        b->u_gamma_cap = T;
-    }
-    // the table is uploaded (blocking) only when the gammas change
-    if (b->u_gamma_host.size() != (size_t)T || !std::equal(gammas, gammas + T, b->u_gamma_host.begin())) {
-        GN_HIP_TRY(hipStreamSynchronize(s));
-        GN_HIP_TRY(hipMemcpy(b->u_gamma, gammas, sizeof(float) * T, hipMemcpyHostToDevice));
-        b->u_gamma_host.assign(gammas, gammas + T);
-    }
-    const float* v = b->v;
-    if (w_cat) {
-        if (!b->u_v && !dalloc(&b->u_v, (size_t)b->total_n)) return GN_E_NOMEM;
-        hipLaunchKernelGGL(batch_sqrt_weights_kernel, dim3((unsigned)((b->total_n + 255) / 256)), dim3(256), 0, s,
-                           (int64_t)b->total_n, (const int32_t*)b->vgraph, (const BatchDesc*)b->desc,
-                           (const int32_t*)b->perm, w_cat, b->u_v);
-        GN_HIP_TRY(hipGetLastError());
-        v = b->u_v;
-    }
-    GN_HIP_TRY(hipMemsetAsync(b->u_queue, 0, sizeof(int32_t), s));
-    const void* k = unrolled_kernel(bt, bwd);
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, bt, lds) != hipSuccess) {
-        (void)hipGetLastError();
-        nb = 1;
-    }
-    const int bpc = std::max(1, std::min(bpc_want, nb));
-    grid = dim3((unsigned)std::min<int64_t>((int64_t)b->cus * bpc, b->count));
-    a = UnrolledArgs{};
-    a.desc = b->desc;
-    a.order = b->u_order;
-    a.count = b->count;
-    a.queue = b->u_queue;
-    a.perm = b->perm;
-    a.lines = b->lines;
-    a.slices = b->slices;
-    a.v = v;
-    a.gamma = b->u_gamma;
-    a.T = T;
-    a.lds_bytes = (int32_t)lds;
-    a.total_n = b->total_n;
-    return GN_OK;
-}
-
-static gn_status check_gammas(const float* gammas, int32_t T) {
-    if (T < 0 || (T > 0 && !gammas)) return GN_E_ARG;
-    for (int32_t t = 0; t < T; ++t)
-        if (!std::isfinite(gammas[t]) || gammas[t] < 0.0f) return GN_E_ARG;
-    return GN_OK;
-}
-
-extern "C" int64_t gn_batch_unrolled_store_floats(const gn_batch* b, int32_t T) {
-    if (!b || T < 0) return -1;
-    return 2 * (int64_t)T * b->total_n;
-}
-
-extern "C" gn_status gn_batch_unrolled_forward(gn_batch* b, const float* w_cat, const float* gammas, int32_t T,
-                                               const float* x0_cat, float* xT_cat, float* store, hipStream_t stream) {
-    if (!b) return GN_E_ARG;
-    gn_status st = check_gammas(gammas, T);
-    if (st != GN_OK) return st;
-    if (b->total_n == 0) return GN_OK;
-    if (!x0_cat || !xT_cat || x0_cat == xT_cat || (T > 0 && !store)) return GN_E_ARG;
-    if (T == 0) {
-        GN_HIP_TRY(hipMemcpyAsync(xT_cat, x0_cat, sizeof(float) * b->total_n, hipMemcpyDeviceToDevice, stream));
-        return GN_OK;
-    }
-    UnrolledArgs a;
-    dim3 grid;
-    size_t lds = 0;
-    if ((st = unrolled_prepare(b, w_cat, gammas, T, false, stream, a, grid, lds)) != GN_OK) return st;
-    a.x0 = x0_cat;
-    a.xT = xT_cat;
-    a.store = store;
-    const int bt = unrolled_block(b);
-    void* args[] = {&a};
-    GN_HIP_TRY(hipLaunchKernel(unrolled_kernel(bt, false), grid, dim3(bt), args, lds, stream));
-    GN_HIP_TRY(hipGetLastError());
-    return GN_OK;
-}
-
-extern "C" gn_status gn_batch_unrolled_backward(gn_batch* b, const float* w_cat, const float* gammas, int32_t T,
-                                                const float* store, const float* gxT_cat, float* gw_cat,
-                                                float* gx0_cat, hipStream_t stream) {
-    if (!b) return GN_E_ARG;
-    gn_status st = check_gammas(gammas, T);
-    if (st != GN_OK) return st;
-    if (b->total_n == 0) return GN_OK;
-    if (!gxT_cat || !gw_cat || !gx0_cat || (T > 0 && !store)) return GN_E_ARG;
-    if (T == 0) {
-        GN_HIP_TRY(hipMemcpyAsync(gx0_cat, gxT_cat, sizeof(float) * b->total_n, hipMemcpyDeviceToDevice, stream));
-        GN_HIP_TRY(hipMemsetAsync(gw_cat, 0, sizeof(float) * b->total_n, stream));
-        return GN_OK;
-    }
-    UnrolledArgs a;
-    dim3 grid;
-    size_t lds = 0;
-    if ((st = unrolled_prepare(b, w_cat, gammas, T, true, stream, a, grid, lds)) != GN_OK) return st;
-    a.store = const_cast<float*>(store);  // read only by the adjoint pass
-    a.gxT = gxT_cat;
-    a.gx0 = gx0_cat;
-    a.gw = gw_cat;
-    const int bt = unrolled_block(b);
-    void* args[] = {&a};
-    GN_HIP_TRY(hipLaunchKernel(unrolled_kernel(bt, true), grid, dim3(bt), args, lds, stream));
-    GN_HIP_TRY(hipGetLastError());
-    return GN_OK;
-}
-
-// Small-graph path of gn_solve (declared in gn_internal.h).  The graph's LDS
-// image (slice table and lines over its internal order) is built at graph
-// creation from the host copies of the internal CSR, and kept in the handle.
-struct SmallImage {
-    int32_t slices = 0, lines = 0;
-    int64_t lds = INT64_MAX;  // LDS bytes of the solve; INT64_MAX: no image
-    int32_t* so = nullptr;
-    uint16_t* ln = nullptr;
-};
-
-void gn_internal_build_small(gn_graph* g, const int32_t* rp, const int32_t* col, hipStream_t s) {
-    SmallImage* im = new (std::nothrow) SmallImage();
-    if (!im) return;
-    g->small = im;
-    const int32_t n = g->n;
-    // a cheap bound first: the lines hold at least the nnz ids
-    if (n == 0 || n > kMaxSlicedN || 8 * (int64_t)n + 12 + 2 * g->nnz > kLdsBudget) return;
-    const int32_t mb = g->bins.row_begin[BIN_G8], lb = g->bins.row_begin[BIN_LANE16];
-    std::vector<uint16_t> lines;
-    std::vector<int32_t> slices;
-    const int64_t nl = build_slices(n, rp, col, lb, n, mb, lb, 0, mb, lines, slices);
-    const int64_t bytes = 8 * (int64_t)n + 8 + 4 * (int64_t)slices.size() + 128 * nl;
-    if (bytes > kLdsBudget) return;
-    bool ok = dalloc(&im->so, slices.size()) && dalloc(&im->ln, std::max<size_t>(lines.size(), 64)) &&
-              hipMemcpyAsync(im->so, slices.data(), sizeof(int32_t) * slices.size(), hipMemcpyHostToDevice, s) ==
-                  hipSuccess &&
-              (lines.empty() || hipMemcpyAsync(im->ln, lines.data(), sizeof(uint16_t) * lines.size(),
-                                               hipMemcpyHostToDevice, s) == hipSuccess) &&
-              hipStreamSynchronize(s) == hipSuccess;
-    if (!ok) {
-        (void)hipGetLastError();
-        return;  // no image: the graph takes the chained path
-    }
-    im->slices = (int32_t)slices.size() - 1;
-    im->lines = (int32_t)nl;
-    im->lds = bytes;
-}
-
-void gn_internal_free_small(gn_graph* g) {
-    SmallImage* im = static_cast<SmallImage*>(g->small);
-    if (!im) return;
-    if (im->so) (void)hipFree(im->so);
-    if (im->ln) (void)hipFree(im->ln);
-    delete im;
-    g->small = nullptr;
-}
-
-bool gn_internal_small_fits(const gn_graph* g) {
-    const SmallImage* im = static_cast<const SmallImage*>(g->small);
-    return im && im->lds <= kLdsBudget;
-}
-
-gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s) {
-    constexpr int BT = 1024;
-    if (!gn_internal_small_fits(g)) return GN_E_ARG;
-    const SmallImage* im = static_cast<const SmallImage*>(g->small);
-    const size_t lds = (size_t)im->lds;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)small_solve_kernel<BT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    SmallArgs a{};
-    a.n = g->n;
-    a.mid_begin = g->bins.row_begin[BIN_G8];
-    a.light_begin = g->bins.row_begin[BIN_LANE16];
-    a.n_lines = im->lines;
-    a.slices = im->so;
-    a.lines = im->ln;
-    a.v = g->v;
-    a.gamma = g->ws.gamma;
-    a.st = g->ws.state;
-    a.notconv = g->ws.notconv;
-    a.y0 = g->ws.y[0];
-    a.y1 = g->ws.y[1];
-    hipLaunchKernelGGL(small_solve_kernel<BT>, dim3(1), dim3(BT), lds, s, a);
-    GN_HIP_TRY(hipGetLastError());
-    return GN_OK;
-}

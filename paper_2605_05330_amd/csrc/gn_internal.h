@@ -51,7 +51,7 @@ struct gn_graph {
     mutable GraphWorkspace ws;   // work buffers; calls on one handle must not overlap
     mutable void* unrolled = nullptr;  // adjoint work buffers (gn_unrolled.hip)
     mutable void* multi = nullptr;     // multi-start work buffers (gn_multi.hip)
-    void* small = nullptr;             // LDS image of the single-workgroup solve (gn_batch.hip)
+    void* small = nullptr;             // LDS image of the single-workgroup solve (gn_small.hip)
 };
 
 // Final statistics reduced on the device (fixed-order, deterministic).
@@ -64,6 +64,19 @@ struct FinalStats {
     float stab;
     int32_t pad;
 };
+
+// Device allocation of count elements (at least one); false and a cleared HIP
+// error on failure.
+template <typename T>
+inline bool gn_dalloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    return true;
+}
 
 // internal helpers implemented in gn_graph.hip / gn_step.hip / gn_check.hip
 gn_status gn_internal_ensure_ws(gn_graph* g, int32_t steps_needed);
@@ -93,9 +106,9 @@ gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool 
                                   gn_result* res);
 gn_status gn_internal_ensure_tables(GraphWorkspace& ws, int32_t steps_needed);
 
-// small graphs: the whole solve in one workgroup (gn_batch.hip) while
+// small graphs: the whole solve in one workgroup (gn_small.hip) while
 // nnz + 2 n <= g_small_limit (gn_set_small_graph_limit, gn_solve.hip) and the
-// state and CSR fit in LDS
+// graph's LDS image fits one compute unit
 extern int32_t g_small_limit;
 constexpr int32_t kSmallWorkMax = 1 << 20;
 gn_status gn_internal_small_solve(const gn_graph* g, hipStream_t s);
