@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
 benchmark's CPU-baseline leg.  The product path (``paper_2605_05330_amd``) never
 imports it.  The compiled part is ``gn_oracle.c`` (plain C, gcc); this module
 holds its ctypes binding.  The message-passing warm-start reference lives in
-``oracle/mpnn.py``, the census of GN atoms (Appendix A) in ``oracle/atoms.py``.
+``oracle/mpnn.py``, the census of GN atoms (Appendix A) in ``oracle/atoms.py``, the fractional
+clique-LP warm start (Section 6) in ``oracle/lp.py``.
 
 Parity status of every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py``; none is "parity unpinned".

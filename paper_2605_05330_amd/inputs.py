@@ -301,3 +301,69 @@ def batch_workload(count: int = 4096, seed: int = 0, n_lo: int = 50, n_hi: int =
         graphs.append(gr)
         weights.append(weights_uniform01(n, gseed))
     return graphs, weights
+
+
+@dataclass
+class CliqueInstance:
+    """MWIS instance given by clique constraints (the form of the paper's AVR /
+    MSCD benchmarks): clique k is members[ptr[k]:ptr[k+1]] (sorted, distinct);
+    every vertex lies in at least one clique.  ``graph`` is the conflict graph,
+    an edge between two vertices that share a clique."""
+    n: int
+    ptr: np.ndarray      # int32 [m+1]
+    members: np.ndarray  # int32 [ptr[-1]]
+    graph: Graph
+
+    @property
+    def m(self) -> int:
+        return len(self.ptr) - 1
+
+
+def clique_cover_instance(n: int, items: int, k_lo: int, k_hi: int, seed: int, stream: int = 11,
+                          zipf: float = 0.0) -> CliqueInstance:
+    """Routes and stops: vertex i (a route) covers k_i ~ U{k_lo..k_hi} distinct
+    items (stops), drawn without replacement with probability proportional to
+    (rank + 1)^-zipf (zipf = 0: uniform); the routes covering an item form a
+    clique.  Empty items are dropped; cliques keep item order."""
+    rng = rng_for(seed, stream)
+    p = (np.arange(items, dtype=np.float64) + 1.0) ** -float(zipf)
+    p /= p.sum()
+    k = rng.integers(k_lo, k_hi + 1, size=n)
+    rows, cols = [], []
+    for i in range(n):
+        its = rng.choice(items, size=int(k[i]), replace=False, p=p)
+        rows.append(np.full(its.size, i, dtype=np.int64))
+        cols.append(its.astype(np.int64))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    order = np.lexsort((r, c))                # by item, then vertex
+    r, c = r[order], c[order]
+    sizes = np.bincount(c, minlength=items)
+    sizes = sizes[sizes > 0]
+    ptr = np.zeros(sizes.size + 1, dtype=np.int64)
+    np.cumsum(sizes, out=ptr[1:])
+    members = r.astype(np.int32)
+    # conflict graph: all pairs inside each clique
+    src, dst = [], []
+    for q in range(sizes.size):
+        mem = members[ptr[q]:ptr[q + 1]].astype(np.int64)
+        if mem.size > 1:
+            a, b = np.triu_indices(mem.size, 1)
+            src.append(mem[a])
+            dst.append(mem[b])
+    g = csr_from_edges(n, np.concatenate(src) if src else np.zeros(0, np.int64),
+                       np.concatenate(dst) if dst else np.zeros(0, np.int64), dedup=True)
+    return CliqueInstance(n, ptr.astype(np.int32), members, g)
+
+
+def class_orders(starts: int, n_classes: int, seed: int, stream: int = 12) -> np.ndarray:
+    """One uniformly random permutation of the clique classes per start (int32
+    [starts, n_classes]): the randomized clique order of the LP warm start."""
+    rng = rng_for(seed, stream)
+    return np.stack([rng.permutation(n_classes) for _ in range(starts)]).astype(np.int32)
+
+
+def jittered_temperatures(starts: int, lo: float, hi: float, seed: int, stream: int = 13) -> np.ndarray:
+    """Initial temperatures uniform on [lo, hi) per start, fp32."""
+    u = rng_for(seed, stream).random(size=starts)
+    return (lo + (hi - lo) * u).astype(np.float32)
