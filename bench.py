@@ -39,6 +39,7 @@ def _args():
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-multi", action="store_true")
     p.add_argument("--no-atoms", action="store_true")
+    p.add_argument("--no-lp", action="store_true")
     return p.parse_args()
 
 
@@ -293,6 +294,65 @@ def bench_atoms(reps=3):
             "note": "Burnside sum over cycle types; the table's n = 8 classes add up to 247, its printed total is 230"}
 
 
+def bench_lp(with_oracle=True):
+    """Fractional warm start (Section 6): 16 clique-LP solves of a routes-and-stops
+    instance (10,000 routes, 2,000 stops, 3-8 stops per route) to a 1% duality gap,
+    then GN multi-start from them against 16 random starts."""
+    import torch
+    from paper_2605_05330_amd import inputs as I
+    from paper_2605_05330_amd import libgn
+    inst = I.clique_cover_instance(10000, 2000, 3, 8, 0)
+    c = I.weights_uniform01(inst.n, 0)
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    S = 16
+    K = L.info["n_classes"]
+    orders = I.class_orders(S, K, 0)
+    t0 = I.jittered_temperatures(S, 1.0, 1.1, 0)
+    x = torch.empty(S * inst.n, dtype=torch.float32, device="cuda")
+    L.solve(t0, orders, x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, res = L.solve(t0, orders, x)
+    lp_ms = (time.perf_counter() - t) * 1e3
+    passes = [r.passes for r in res]
+    bound = min(r.dual for r in res)
+    G = libgn.Graph(inst.n, inst.graph.row_ptr, inst.graph.col_idx, c)
+    sched = libgn.make_schedule(0.9, 1.5, 1000, 2000, 1e-4, 1)
+    sel = torch.zeros(S * inst.n, dtype=torch.uint8, device="cuda")
+
+    def gn_from(x0):
+        xs = x0.clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, out, best = libgn.gn_multi_solve(G.handle, sched, S, xs, sel)
+        ms = (time.perf_counter() - t1) * 1e3
+        ok = [r for r in out if r.binarised and r.conflicts == 0]
+        return {"best_set_objective": out[best].set_objective, "best_over_lp_bound": out[best].set_objective / bound,
+                "mean_set_objective": float(np.mean([r.set_objective for r in out])),
+                "binarised_independent": len(ok), "max_steps": max(r.steps for r in out), "ms": ms}
+
+    u = torch.from_numpy((1.0 - I.rng_for(0, 14).random(S * inst.n, dtype=np.float32))).cuda()
+    xr = torch.empty_like(x)
+    libgn.gn_random_starts(G.handle, S, u, xr)
+    out = {"instance": {"routes": inst.n, "stops": inst.m, "memberships": int(inst.members.size),
+                        "conflict_edges": inst.graph.nnz // 2, "clique_classes": K},
+           "lp": {"starts": S, "ms": lp_ms, "passes_min": min(passes), "passes_max": max(passes),
+                  "us_per_pass": lp_ms * 1e3 / max(passes), "gap_max": max(r.gap for r in res),
+                  "best_bound": bound, "converged": int(sum(r.converged for r in res))},
+           "gn_from_lp": gn_from(x), "gn_from_random": gn_from(xr)}
+    if with_oracle:
+        import oracle.lp as OL
+        cl = OL.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
+        classes = OL.colour_classes(cl)
+        Lam, lam = np.zeros(cl.n), np.zeros(cl.m)
+        reps = 20
+        t = time.perf_counter()
+        for p in range(reps):
+            OL.run_pass(cl, c.astype(np.float64), Lam, lam, classes, list(orders[0]), OL.temperature(float(t0[0]), 0.99, 1e-4, p))
+        out["oracle_ms_per_pass_one_start"] = (time.perf_counter() - t) * 1e3 / reps
+    return out
+
+
 def bench_warm():
     """Learned warm start: trained on the GPU (own kernels) on GN's sets of 96
     unit-disk graphs, n log-uniform in [10k, 100k], mean degree 10, w ~ U(0,1];
@@ -518,6 +578,8 @@ def main():
         out["learned_warm_start"] = bench_warm()
     if not a.no_atoms:
         out["atom_census8"] = bench_atoms()
+    if not a.no_lp:
+        out["lp_warm_start"] = bench_lp(not a.no_cpu_baseline)
     if not a.no_grad:
         out["differentiable"] = bench_grad()
 

@@ -429,6 +429,70 @@ typedef struct {
  * internal inconsistency, never expected).  SYNC. */
 gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Fractional warm start (Section 6, "Randomized start and warm start"): the
+ * MWIS LP relaxation over clique constraints,
+ *     LP* = max c.x  s.t.  sum_{i in C} x_i <= 1 for every clique C,  x >= 0,
+ * smoothed by entropy at a temperature T and solved by a Bregman-Sinkhorn scheme
+ * alone (no rounding).  With multipliers lam_C >= 0 and Lam_i the sum of those
+ * of the cliques holding i, the smoothed primal is x_i = exp((c_i - Lam_i)/T);
+ * updating clique C sets lam_C' = max(0, lam_C + T log sum_{i in C} x_i) and
+ * adds lam_C' - lam_C to its members' Lam (exact minimisation of the smoothed
+ * dual in lam_C).  Cliques are coloured first-fit in input order into classes
+ * of vertex-disjoint cliques; a pass updates the classes in the start's order,
+ * the cliques of a class in parallel.  Pass p runs at
+ * T_p = max(t_min, t0 * drop^p).  Diversity across starts: the class order (the
+ * randomized clique order) and t0 (the jittered initial temperature) are the
+ * caller's, per start.
+ * ------------------------------------------------------------------------- */
+
+typedef struct gn_lp gn_lp;   /* clique-constrained LP instance and its work buffers */
+
+typedef struct {
+    int32_t passes;       /* passes run                                                  */
+    int32_t converged;    /* 1 when gap <= gap_tol at a check                            */
+    float temperature;    /* temperature of the last pass                                */
+    float pad;
+    double dual;          /* D = sum_C lam_C + sum_i max(0, c_i - Lam_i), an upper bound  */
+    double primal;        /* P = c.xf of the feasible point returned                     */
+    double gap;           /* (D - P) / D                                                 */
+} gn_lp_result;
+
+/* Create an LP instance.  Host arrays: clique k is members[clique_ptr[k] ..
+ * clique_ptr[k+1]-1] (m >= 1 cliques, each non-empty with strictly increasing
+ * vertex ids in [0, n)); cost: float[n], finite and > 0 (the vertex weights);
+ * every vertex must lie in some clique (a singleton clique is allowed), else the
+ * LP is unbounded.  The library copies everything and colours the cliques.
+ * Errors: GN_E_ARG (null, sizes, an uncovered vertex), GN_E_CSR (clique_ptr not
+ * starting at 0 or not increasing, ids out of range or not increasing),
+ * GN_E_WEIGHT, GN_E_NOMEM, GN_E_HIP; *out = NULL on error.  SYNC. */
+gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_ptr, const int32_t* members, const float* cost,
+                       hipStream_t stream, gn_lp** out);
+
+/* Free an LP instance (NULL is allowed).  Waits for the device. */
+void gn_lp_destroy(gn_lp* lp);
+
+/* Number of clique classes (the length of each start's order), of cliques, and
+ * the size of the largest class.  Any output may be NULL. */
+gn_status gn_lp_info(const gn_lp* lp, int32_t* n_classes, int32_t* n_cliques, int32_t* max_class);
+
+/* Run `starts` (1..GN_MAX_STARTS) independent solves.  t0: host float[starts],
+ * finite and > 0; order: host int32[starts * n_classes], row s a permutation of
+ * the classes; drop in (0, 1]; t_min > 0; max_passes >= 1; check_every >= 1;
+ * gap_tol >= 0; x_floor in [0, 1).  Lam and lam start at zero.  After pass p
+ * with (p + 1) % check_every == 0, and after the last pass, each running start
+ * evaluates at T_p the feasible point xf_i = x_i / max(1, max_{C holds i}
+ * sum_{j in C} x_j) (x's exponent capped at 60), D and P = c.xf, and stops when
+ * (D - P) / D <= gap_tol.  x: device float[starts * n], start-major (user vertex
+ * ids), receives max(xf, x_floor) of the stopping check: a starting point for
+ * gn_multi_solve on the conflict graph (an edge between two vertices sharing a
+ * clique).  res: host gn_lp_result[starts].  fp32 state, fp64 sums of D and P.
+ * Returns GN_OK when every start met gap_tol, else GN_NOT_CONVERGED; GN_E_ARG
+ * on bad arguments, GN_E_NUMERIC if D or P is not finite.  SYNC. */
+gn_status gn_lp_solve(gn_lp* lp, int32_t starts, const float* t0, const int32_t* order, float drop, float t_min,
+                      int32_t max_passes, int32_t check_every, float gap_tol, float x_floor, float* x,
+                      gn_lp_result* res, hipStream_t stream);
+
 /* Tuning: number of step launches captured in one replayed chain by gn_solve and
  * gn_rook_solve (default 32, 1..4096).  A longer chain checks the stop flag less
  * often from the host; results do not change.  Process-wide; not thread-safe. */

@@ -124,8 +124,10 @@ def evaluate(cl: Cliques, c, Lam, lam, T: float):
 
 
 def solve(cl: Cliques, c: np.ndarray, t0: float, order, drop: float, t_min: float, max_passes: int,
-          check_every: int, gap_tol: float, x_floor: float, classes: np.ndarray | None = None):
-    """One start: (warm start max(xf, x_floor), LPResult, lam, Lam)."""
+          check_every: int, gap_tol: float, x_floor: float, classes: np.ndarray | None = None,
+          trace: list | None = None):
+    """One start: (warm start max(xf, x_floor), LPResult, lam, Lam).  trace, when
+    given, receives (passes, D, P, gap) of every check."""
     c = np.asarray(c, dtype=np.float64)
     if classes is None:
         classes = colour_classes(cl)
@@ -138,6 +140,8 @@ def solve(cl: Cliques, c: np.ndarray, t0: float, order, drop: float, t_min: floa
         if (p + 1) % check_every == 0 or last:
             D, P, xf = evaluate(cl, c, Lam, lam, T)
             gap = (D - P) / D
+            if trace is not None:
+                trace.append((p + 1, D, P, gap))
             if gap <= gap_tol or last:
                 return np.maximum(xf, x_floor), LPResult(p + 1, T, D, P, gap, gap <= gap_tol), lam, Lam
     raise AssertionError("unreachable")

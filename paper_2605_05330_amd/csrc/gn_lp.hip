@@ -1,0 +1,474 @@
+// Fractional warm start: the MWIS LP relaxation over clique constraints,
+// smoothed by entropy at a temperature T and solved by exact block-coordinate
+// minimisation of its dual (a Bregman-Sinkhorn scheme run alone, without
+// rounding; Section 6, "Randomized start and warm start").
+//
+//   LP* = max c.x  s.t.  sum_{i in C} x_i <= 1 for every clique C,  x >= 0.
+//
+// State per start: a multiplier lam_C >= 0 per clique and Lam_i, the sum of the
+// multipliers of the cliques holding i.  The smoothed primal is
+// x_i = exp((c_i - Lam_i) / T).  Updating clique C sets
+// lam_C' = max(0, lam_C + T log sum_{i in C} x_i) and adds lam_C' - lam_C to
+// Lam_i of its members, after which the clique's x sum to at most 1.
+//
+// Cliques are coloured first-fit into classes of vertex-disjoint cliques at
+// creation; a pass visits the classes in the start's order (the caller's
+// permutation), one launch per class for all starts together, a wavefront per
+// clique.  Disjointness makes the members' Lam updates race-free and the result
+// independent of the order inside a class.  Pass p runs at
+// T_p = max(t_min, t0 drop^p).
+//
+// The check (every check_every passes and after the last) bounds LP* from both
+// sides: D = sum lam_C + sum_i max(0, c_i - Lam_i) >= LP*, and the feasible
+// point xf_i = x_i / max(1, max_{C holds i} sum_{j in C} x_j) gives P = c.xf.
+// A start stops when (D - P) / D <= gap_tol; its warm start is max(xf, floor).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gn_internal.h"
+
+namespace {
+
+constexpr int kLpWaves = 4;                  // cliques per workgroup of the class launches
+constexpr int kLpBlock = 64 * kLpWaves;
+constexpr int kLpVBlock = 256;               // vertex kernel
+constexpr int kLpFBlock = 256;               // finish kernel
+constexpr float kExpCap = 60.0f;             // cap of the check's exponent (keeps sums finite)
+
+struct LpState {
+    int32_t done;
+    int32_t passes;
+    int32_t converged;
+    float temperature;
+    double dual;
+    double primal;
+    double gap;
+};
+
+struct LpArgs {
+    const float* cost;       // [n]
+    const int32_t* cptr;     // [m + 1], cliques in class order
+    const int32_t* cmem;     // members
+    const int32_t* class_ptr;// [K + 1]
+    const int32_t* vptr;     // [n + 1] vertex -> cliques
+    const int32_t* vcl;
+    const int32_t* order;    // [S][K]
+    const float* t0;         // [S]
+    float* Lam;              // [S][n]
+    float* lam;              // [S][m]
+    float* csum;             // [S][m]
+    double* part;            // [S][2 * nbv]
+    LpState* st;             // [S]
+    float* x_out;            // [S][n]
+    int32_t n, m, K, nbv;
+    float drop, t_min, gap_tol, x_floor;
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float pass_temperature(const LpArgs& a, int s, int p) {
+    return fmaxf(a.t_min, a.t0[s] * powf(a.drop, (float)p));
+}
+
+// One class of one start: a wavefront per clique.
+__global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, int32_t r, int32_t p) {
+    const int s = blockIdx.y;
+    if (a.st[s].done) return;
+    const int cls = a.order[(size_t)s * a.K + r];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int k = a.class_ptr[cls] + blockIdx.x * kLpWaves + wave;
+    if (k >= a.class_ptr[cls + 1]) return;
+    const float T = pass_temperature(a, s, p);
+    const int b = a.cptr[k], e = a.cptr[k + 1];
+    float* L = a.Lam + (size_t)s * a.n;
+    float mx = -INFINITY;
+    for (int j = b + lane; j < e; j += 64) {
+        const int i = a.cmem[j];
+        mx = fmaxf(mx, (a.cost[i] - L[i]) / T);
+    }
+    mx = wave_max(mx);
+    float sum = 0.0f;
+    for (int j = b + lane; j < e; j += 64) {
+        const int i = a.cmem[j];
+        sum += expf((a.cost[i] - L[i]) / T - mx);
+    }
+    sum = wave_sum(sum);
+    float* lp = a.lam + (size_t)s * a.m + k;
+    const float old = *lp;
+    const float nw = fmaxf(0.0f, old + T * (mx + logf(sum)));
+    const float d = nw - old;
+    for (int j = b + lane; j < e; j += 64) L[a.cmem[j]] += d;
+    if (lane == 0) *lp = nw;
+}
+
+// Check, part 1: the clique sums of the smoothed primal.
+__global__ __launch_bounds__(kLpBlock) void lp_csum_kernel(LpArgs a, int32_t p) {
+    const int s = blockIdx.y;
+    if (a.st[s].done) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * kLpWaves + wave;
+    if (k >= a.m) return;
+    const float T = pass_temperature(a, s, p);
+    const float* L = a.Lam + (size_t)s * a.n;
+    float sum = 0.0f;
+    for (int j = a.cptr[k] + lane; j < a.cptr[k + 1]; j += 64) {
+        const int i = a.cmem[j];
+        sum += expf(fminf((a.cost[i] - L[i]) / T, kExpCap));
+    }
+    sum = wave_sum(sum);
+    if (lane == 0) a.csum[(size_t)s * a.m + k] = sum;
+}
+
+// Check, part 2: the feasible point, written as the warm start, and per-block
+// partial sums of c.xf and of max(0, c - Lam) (fp64, fixed order).
+__global__ __launch_bounds__(kLpVBlock) void lp_vertex_kernel(LpArgs a, int32_t p) {
+    const int s = blockIdx.y;
+    if (a.st[s].done) return;
+    __shared__ double red[2][kLpVBlock / 64];
+    const int i = blockIdx.x * kLpVBlock + threadIdx.x;
+    double pv = 0.0, dv = 0.0;
+    if (i < a.n) {
+        const float T = pass_temperature(a, s, p);
+        const float c = a.cost[i];
+        const float Li = a.Lam[(size_t)s * a.n + i];
+        const float x = expf(fminf((c - Li) / T, kExpCap));
+        float mx = 1.0f;
+        const float* cs = a.csum + (size_t)s * a.m;
+        for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) mx = fmaxf(mx, cs[a.vcl[q]]);
+        const float xf = x / mx;
+        a.x_out[(size_t)s * a.n + i] = fmaxf(xf, a.x_floor);
+        pv = (double)c * (double)xf;
+        dv = (double)fmaxf(0.0f, c - Li);
+    }
+    pv = wave_sum_d(pv);
+    dv = wave_sum_d(dv);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = pv;
+        red[1][w] = dv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double P = 0.0, D = 0.0;
+        for (int q = 0; q < kLpVBlock / 64; ++q) {
+            P += red[0][q];
+            D += red[1][q];
+        }
+        a.part[(size_t)s * 2 * a.nbv + 2 * blockIdx.x] = P;
+        a.part[(size_t)s * 2 * a.nbv + 2 * blockIdx.x + 1] = D;
+    }
+}
+
+// Check, part 3: one workgroup per start reduces the bound and the primal value
+// and decides the stop.
+__global__ __launch_bounds__(kLpFBlock) void lp_finish_kernel(LpArgs a, int32_t p, int32_t last) {
+    const int s = blockIdx.x;
+    if (a.st[s].done) return;
+    __shared__ double red[3][kLpFBlock / 64];
+    double sl = 0.0, P = 0.0, D = 0.0;
+    const float* lam = a.lam + (size_t)s * a.m;
+    for (int k = threadIdx.x; k < a.m; k += kLpFBlock) sl += (double)lam[k];
+    const double* part = a.part + (size_t)s * 2 * a.nbv;
+    for (int q = threadIdx.x; q < a.nbv; q += kLpFBlock) {
+        P += part[2 * q];
+        D += part[2 * q + 1];
+    }
+    sl = wave_sum_d(sl);
+    P = wave_sum_d(P);
+    D = wave_sum_d(D);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = sl;
+        red[1][w] = P;
+        red[2][w] = D;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double L = 0.0, Pt = 0.0, Dt = 0.0;
+        for (int q = 0; q < kLpFBlock / 64; ++q) {
+            L += red[0][q];
+            Pt += red[1][q];
+            Dt += red[2][q];
+        }
+        Dt += L;
+        const double gap = (Dt - Pt) / Dt;
+        const bool conv = gap <= (double)a.gap_tol;
+        if (conv || last) {
+            LpState o;
+            o.done = 1;
+            o.passes = p + 1;
+            o.converged = conv ? 1 : 0;
+            o.temperature = pass_temperature(a, s, p);
+            o.dual = Dt;
+            o.primal = Pt;
+            o.gap = gap;
+            a.st[s] = o;
+        }
+    }
+}
+
+__global__ void lp_reset_kernel(LpArgs a, int32_t starts) {
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t q = tid; q < (size_t)starts * a.n; q += stride) a.Lam[q] = 0.0f;
+    for (size_t q = tid; q < (size_t)starts * a.m; q += stride) a.lam[q] = 0.0f;
+    if (tid < (size_t)starts) {
+        LpState o{};
+        a.st[tid] = o;
+    }
+}
+
+}  // namespace
+
+struct gn_lp {
+    int device = 0;
+    int32_t n = 0, m = 0, K = 0, max_class = 0;
+    int64_t nnzc = 0;
+    std::vector<int32_t> class_ptr_h;  // [K + 1]
+    float* cost = nullptr;
+    int32_t* cptr = nullptr;
+    int32_t* cmem = nullptr;
+    int32_t* class_ptr = nullptr;
+    int32_t* vptr = nullptr;
+    int32_t* vcl = nullptr;
+    int32_t* order = nullptr;
+    float* t0 = nullptr;
+    float* Lam = nullptr;
+    float* lam = nullptr;
+    float* csum = nullptr;
+    double* part = nullptr;
+    LpState* st = nullptr;
+    LpState* st_host = nullptr;  // pinned
+};
+
+static void lp_free(gn_lp* L) {
+    hipFree(L->cost);
+    hipFree(L->cptr);
+    hipFree(L->cmem);
+    hipFree(L->class_ptr);
+    hipFree(L->vptr);
+    hipFree(L->vcl);
+    hipFree(L->order);
+    hipFree(L->t0);
+    hipFree(L->Lam);
+    hipFree(L->lam);
+    hipFree(L->csum);
+    hipFree(L->part);
+    hipFree(L->st);
+    if (L->st_host) hipHostFree(L->st_host);
+}
+
+static int32_t lp_nbv(int32_t n) { return (n + kLpVBlock - 1) / kLpVBlock; }
+
+extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_ptr, const int32_t* members,
+                                  const float* cost, hipStream_t stream, gn_lp** out) {
+    if (!out) return GN_E_ARG;
+    *out = nullptr;
+    if (n < 1 || m < 1 || !clique_ptr || !members || !cost) return GN_E_ARG;
+    if (clique_ptr[0] != 0) return GN_E_CSR;
+    for (int32_t k = 0; k < m; ++k)
+        if (clique_ptr[k + 1] <= clique_ptr[k]) return GN_E_CSR;  // empty clique or not monotone
+    const int64_t nnzc = clique_ptr[m];
+    std::vector<int32_t> cover(n, 0);
+    for (int32_t k = 0; k < m; ++k)
+        for (int32_t j = clique_ptr[k]; j < clique_ptr[k + 1]; ++j) {
+            const int32_t i = members[j];
+            if (i < 0 || i >= n) return GN_E_CSR;
+            if (j > clique_ptr[k] && i <= members[j - 1]) return GN_E_CSR;
+            ++cover[i];
+        }
+    for (int32_t i = 0; i < n; ++i) {
+        if (cover[i] == 0) return GN_E_ARG;  // a vertex outside every clique leaves the LP unbounded
+        if (!(cost[i] > 0.0f) || !std::isfinite(cost[i])) return GN_E_WEIGHT;
+    }
+    // first-fit colouring in input order: the lowest class none of whose
+    // cliques holds a member of clique k
+    std::vector<std::vector<int32_t>> used(n);
+    std::vector<int32_t> cls(m);
+    std::vector<char> taken;
+    int32_t K = 0;
+    for (int32_t k = 0; k < m; ++k) {
+        taken.assign((size_t)K + 1, 0);
+        for (int32_t j = clique_ptr[k]; j < clique_ptr[k + 1]; ++j)
+            for (int32_t c : used[members[j]]) taken[c] = 1;
+        int32_t c = 0;
+        while (taken[c]) ++c;
+        cls[k] = c;
+        K = std::max(K, c + 1);
+        for (int32_t j = clique_ptr[k]; j < clique_ptr[k + 1]; ++j) used[members[j]].push_back(c);
+    }
+    // cliques grouped by class, input order inside a class
+    std::vector<int32_t> class_ptr(K + 1, 0), pos(K), perm(m);
+    for (int32_t k = 0; k < m; ++k) ++class_ptr[cls[k] + 1];
+    for (int32_t c = 0; c < K; ++c) class_ptr[c + 1] += class_ptr[c];
+    for (int32_t c = 0; c < K; ++c) pos[c] = class_ptr[c];
+    for (int32_t k = 0; k < m; ++k) perm[pos[cls[k]]++] = k;
+    std::vector<int32_t> cptr(m + 1, 0), cmem((size_t)nnzc);
+    for (int32_t q = 0; q < m; ++q) {
+        const int32_t k = perm[q];
+        const int32_t sz = clique_ptr[k + 1] - clique_ptr[k];
+        std::memcpy(&cmem[cptr[q]], &members[clique_ptr[k]], sizeof(int32_t) * sz);
+        cptr[q + 1] = cptr[q] + sz;
+    }
+    std::vector<int32_t> vptr(n + 1, 0), vcl((size_t)nnzc), vpos(n);
+    for (int32_t i = 0; i < n; ++i) vptr[i + 1] = vptr[i] + cover[i];
+    for (int32_t i = 0; i < n; ++i) vpos[i] = vptr[i];
+    for (int32_t q = 0; q < m; ++q)
+        for (int32_t j = cptr[q]; j < cptr[q + 1]; ++j) vcl[vpos[cmem[j]]++] = q;
+
+    gn_lp* L = new (std::nothrow) gn_lp();
+    if (!L) return GN_E_NOMEM;
+    (void)hipGetDevice(&L->device);
+    L->n = n;
+    L->m = m;
+    L->K = K;
+    L->nnzc = nnzc;
+    L->class_ptr_h = class_ptr;
+    for (int32_t c = 0; c < K; ++c) L->max_class = std::max(L->max_class, class_ptr[c + 1] - class_ptr[c]);
+    const size_t S = GN_MAX_STARTS;
+    bool ok = gn_dalloc(&L->cost, n) && gn_dalloc(&L->cptr, (size_t)m + 1) && gn_dalloc(&L->cmem, (size_t)nnzc) &&
+              gn_dalloc(&L->class_ptr, (size_t)K + 1) && gn_dalloc(&L->vptr, (size_t)n + 1) &&
+              gn_dalloc(&L->vcl, (size_t)nnzc) && gn_dalloc(&L->order, S * K) && gn_dalloc(&L->t0, S) &&
+              gn_dalloc(&L->Lam, S * n) && gn_dalloc(&L->lam, S * m) && gn_dalloc(&L->csum, S * m) &&
+              gn_dalloc(&L->part, S * 2 * (size_t)lp_nbv(n)) && gn_dalloc(&L->st, S);
+    if (ok && hipHostMalloc((void**)&L->st_host, sizeof(LpState) * S, hipHostMallocDefault) != hipSuccess) {
+        L->st_host = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        lp_free(L);
+        delete L;
+        return GN_E_NOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(L->cost, cost, sizeof(float) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(L->cptr, cptr.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(L->cmem, cmem.data(), sizeof(int32_t) * nnzc, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L->class_ptr, class_ptr.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(L->vptr, vptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(L->vcl, vcl.data(), sizeof(int32_t) * nnzc, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        lp_free(L);
+        delete L;
+        return GN_E_HIP;
+    }
+    *out = L;
+    return GN_OK;
+}
+
+extern "C" void gn_lp_destroy(gn_lp* L) {
+    if (!L) return;
+    (void)hipDeviceSynchronize();
+    lp_free(L);
+    delete L;
+}
+
+extern "C" gn_status gn_lp_info(const gn_lp* L, int32_t* n_classes, int32_t* n_cliques, int32_t* max_class) {
+    if (!L) return GN_E_ARG;
+    if (n_classes) *n_classes = L->K;
+    if (n_cliques) *n_cliques = L->m;
+    if (max_class) *max_class = L->max_class;
+    return GN_OK;
+}
+
+extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, const int32_t* order, float drop,
+                                 float t_min, int32_t max_passes, int32_t check_every, float gap_tol, float x_floor,
+                                 float* x, gn_lp_result* res, hipStream_t stream) {
+    if (!L || !t0 || !order || !x || !res || starts < 1 || starts > GN_MAX_STARTS || max_passes < 1 ||
+        check_every < 1)
+        return GN_E_ARG;
+    if (!(drop > 0.0f && drop <= 1.0f) || !(t_min > 0.0f) || !std::isfinite(t_min) || !(gap_tol >= 0.0f) ||
+        !std::isfinite(gap_tol) || !(x_floor >= 0.0f && x_floor < 1.0f))
+        return GN_E_ARG;
+    const int32_t K = L->K;
+    std::vector<char> seen(K);
+    std::vector<int32_t> gx(K, 0);  // blocks of the class launched at position r
+    for (int32_t s = 0; s < starts; ++s) {
+        if (!(t0[s] > 0.0f) || !std::isfinite(t0[s])) return GN_E_ARG;
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int32_t r = 0; r < K; ++r) {
+            const int32_t c = order[(size_t)s * K + r];
+            if (c < 0 || c >= K || seen[c]) return GN_E_ARG;  // not a permutation of the classes
+            seen[c] = 1;
+            const int32_t size = L->class_ptr_h[c + 1] - L->class_ptr_h[c];
+            gx[r] = std::max(gx[r], (size + kLpWaves - 1) / kLpWaves);
+        }
+    }
+    LpArgs a;
+    a.cost = L->cost;
+    a.cptr = L->cptr;
+    a.cmem = L->cmem;
+    a.class_ptr = L->class_ptr;
+    a.vptr = L->vptr;
+    a.vcl = L->vcl;
+    a.order = L->order;
+    a.t0 = L->t0;
+    a.Lam = L->Lam;
+    a.lam = L->lam;
+    a.csum = L->csum;
+    a.part = L->part;
+    a.st = L->st;
+    a.x_out = x;
+    a.n = L->n;
+    a.m = L->m;
+    a.K = K;
+    a.nbv = lp_nbv(L->n);
+    a.drop = drop;
+    a.t_min = t_min;
+    a.gap_tol = gap_tol;
+    a.x_floor = x_floor;
+    GN_HIP_TRY(hipMemcpyAsync(L->order, order, sizeof(int32_t) * starts * K, hipMemcpyHostToDevice, stream));
+    GN_HIP_TRY(hipMemcpyAsync(L->t0, t0, sizeof(float) * starts, hipMemcpyHostToDevice, stream));
+    lp_reset_kernel<<<1024, 256, 0, stream>>>(a, starts);
+    GN_HIP_TRY(hipGetLastError());
+    const dim3 gcs((L->m + kLpWaves - 1) / kLpWaves, starts), gv(a.nbv, starts);
+    for (int32_t p = 0; p < max_passes; ++p) {
+        for (int32_t r = 0; r < K; ++r) lp_round_kernel<<<dim3(gx[r], starts), kLpBlock, 0, stream>>>(a, r, p);
+        const bool last = p + 1 == max_passes;
+        if ((p + 1) % check_every != 0 && !last) continue;
+        lp_csum_kernel<<<gcs, kLpBlock, 0, stream>>>(a, p);
+        lp_vertex_kernel<<<gv, kLpVBlock, 0, stream>>>(a, p);
+        lp_finish_kernel<<<starts, kLpFBlock, 0, stream>>>(a, p, last ? 1 : 0);
+        GN_HIP_TRY(hipGetLastError());
+        GN_HIP_TRY(hipMemcpyAsync(L->st_host, L->st, sizeof(LpState) * starts, hipMemcpyDeviceToHost, stream));
+        GN_HIP_TRY(hipStreamSynchronize(stream));
+        bool all = true;
+        for (int32_t s = 0; s < starts; ++s) all = all && L->st_host[s].done;
+        if (all) break;
+    }
+    bool conv = true;
+    for (int32_t s = 0; s < starts; ++s) {
+        const LpState& o = L->st_host[s];
+        if (!std::isfinite(o.dual) || !std::isfinite(o.primal)) return GN_E_NUMERIC;
+        res[s].passes = o.passes;
+        res[s].converged = o.converged;
+        res[s].temperature = o.temperature;
+        res[s].pad = 0.0f;
+        res[s].dual = o.dual;
+        res[s].primal = o.primal;
+        res[s].gap = o.gap;
+        conv = conv && o.converged;
+    }
+    return conv ? GN_OK : GN_NOT_CONVERGED;
+}

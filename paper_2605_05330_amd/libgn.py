@@ -50,6 +50,12 @@ class gn_atom_counts(ctypes.Structure):
                 ("labelled_evaluated", ctypes.c_int64)]
 
 
+class gn_lp_result(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("converged", ctypes.c_int32), ("temperature", ctypes.c_float),
+                ("pad", ctypes.c_float), ("dual", ctypes.c_double), ("primal", ctypes.c_double),
+                ("gap", ctypes.c_double)]
+
+
 class gn_tuning(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("lds_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -100,6 +106,13 @@ def lib():
             "gn_rook_create": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
                                ctypes.c_int),
             "gn_rook_destroy": ([_vp], None),
+            "gn_lp_create": ([ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+            "gn_lp_destroy": ([_vp], None),
+            "gn_lp_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "gn_lp_solve": ([_vp, ctypes.c_int32, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                             ctypes.c_int32, ctypes.c_float, ctypes.c_float, _vp, ctypes.POINTER(gn_lp_result), _vp],
+                            ctypes.c_int),
             "gn_rook_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
             "gn_rook_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
                               ctypes.c_int),
@@ -332,6 +345,64 @@ def gn_random_starts(h, starts: int, u, x, stream=None):
     import torch
     _check(lib().gn_random_starts(h, int(starts), _dptr(u, torch.float32, "u"), _dptr(x, torch.float32, "x"),
                                   _stream(stream)), "gn_random_starts")
+
+
+def gn_lp_create(n, clique_ptr, members, cost, stream=None):
+    """Clique-constrained LP instance from host arrays (int32 CSR of cliques, float32 costs)."""
+    cp = np.ascontiguousarray(clique_ptr, dtype=np.int32)
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    if c.size != int(n) or cp.size < 2 or int(cp[-1]) != mem.size:
+        raise GNError(GN_E_ARG, "gn_lp_create: sizes")
+    h = _vp()
+    _check(lib().gn_lp_create(int(n), int(cp.size - 1), _vp(cp.ctypes.data), _vp(mem.ctypes.data),
+                              _vp(c.ctypes.data), _stream(stream), ctypes.byref(h)), "gn_lp_create")
+    return h
+
+
+def gn_lp_destroy(h):
+    if h:
+        lib().gn_lp_destroy(h)
+
+
+def gn_lp_info(h) -> dict:
+    k, m, mc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().gn_lp_info(h, ctypes.byref(k), ctypes.byref(m), ctypes.byref(mc)), "gn_lp_info")
+    return {"n_classes": k.value, "n_cliques": m.value, "max_class": mc.value}
+
+
+def gn_lp_solve(h, t0, order, x, drop=0.99, t_min=1e-4, max_passes=3000, check_every=10, gap_tol=1e-2,
+                x_floor=1e-3, stream=None):
+    """t0: host float32 [starts]; order: host int32 [starts, n_classes]; x: CUDA
+    float32 [starts * n] (out).  Returns (status, list of gn_lp_result)."""
+    import torch
+    t = np.ascontiguousarray(t0, dtype=np.float32).reshape(-1)
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    starts = t.size
+    res = (gn_lp_result * max(starts, 1))()
+    st = lib().gn_lp_solve(h, int(starts), _vp(t.ctypes.data), _vp(o.ctypes.data), float(drop), float(t_min),
+                           int(max_passes), int(check_every), float(gap_tol), float(x_floor),
+                           _dptr(x, torch.float32, "x"), res, _stream(stream))
+    _check(st, "gn_lp_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return st, [res[s] for s in range(starts)]
+
+
+class LP:
+    """Owning wrapper of a gn_lp handle (fractional warm start by the clique LP)."""
+
+    def __init__(self, n, clique_ptr, members, cost, stream=None):
+        self.n = int(n)
+        self.handle = gn_lp_create(n, clique_ptr, members, cost, stream)
+        self.info = gn_lp_info(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            gn_lp_destroy(h)
+            self.handle = None
+
+    def solve(self, t0, order, x, **kw):
+        return gn_lp_solve(self.handle, t0, order, x, **kw)
 
 
 def gn_rook_create(rows, cols, w, stream=None):

@@ -168,3 +168,37 @@ def test_default_checkpoint_interval():
     assert A.default_ckpt_every(10_000_000, 50) == 8       # 4 GB > 1 GiB
     assert A.default_ckpt_every(10_000_000, 1) == 1
     assert A.default_ckpt_every(A.KEEP_ALL_BYTES // 8, 1) == 1
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("uncovered", libgn.GN_E_ARG),
+    ("empty_clique", libgn.GN_E_CSR),
+    ("ptr_start", libgn.GN_E_CSR),
+    ("id_range", libgn.GN_E_CSR),
+    ("id_order", libgn.GN_E_CSR),
+    ("cost_zero", libgn.GN_E_WEIGHT),
+    ("cost_nan", libgn.GN_E_WEIGHT),
+])
+def test_lp_create_rejects_malformed_cliques_on_host(case, expect):
+    """gn_lp_create validates the cliques and costs before any device call."""
+    n, ptr, mem, cost = 4, [0, 2, 4], [0, 1, 2, 3], [0.5, 0.5, 0.5, 0.5]
+    if case == "uncovered":
+        ptr, mem = [0, 2, 3], [0, 1, 2]
+    elif case == "empty_clique":
+        ptr = [0, 2, 2, 4]
+    elif case == "ptr_start":
+        ptr = [1, 2, 4]
+    elif case == "id_range":
+        mem = [0, 1, 2, 4]
+    elif case == "id_order":
+        mem = [1, 0, 2, 3]
+    elif case == "cost_zero":
+        cost = [0.5, 0.0, 0.5, 0.5]
+    elif case == "cost_nan":
+        cost = [0.5, float("nan"), 0.5, 0.5]
+    p = np.ascontiguousarray(ptr, np.int32)
+    m = np.ascontiguousarray(mem, np.int32)
+    c = np.ascontiguousarray(cost, np.float32)
+    h = ctypes.c_void_p(123)
+    st = libgn.lib().gn_lp_create(n, p.size - 1, p.ctypes.data, m.ctypes.data, c.ctypes.data, None, ctypes.byref(h))
+    assert st == expect and not h.value

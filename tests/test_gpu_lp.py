@@ -1,0 +1,173 @@
+"""Parity of the LP warm start (gn_lp_*) with the fp64 oracle (oracle/lp.py),
+through the C ABI.
+
+Element-wise: the warm start, the bound D and the primal value P after a fixed
+number of passes, on instances spanning several class launches, cliques longer
+than a wavefront and every start count up to 16.  At the benchmark's size
+(10,000 routes, 2,000 stops): the stopping pass against the oracle's and the
+properties that hold at any size (weak duality against HiGHS, feasibility).
+Tolerances: the state is fp32 against fp64, x = exp((c - Lam) / T) magnifies an
+error in Lam by 1/T, and T stays >= 0.04 in the element-wise cases, so
+|dx| / x <= ~1e-4 for |dLam| of a few ulps of 1 accumulated over 60 passes;
+the tests allow 2e-3 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import lp as olp
+from paper_2605_05330_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2605_05330_amd import libgn
+    return libgn
+
+
+def _instance(n, items, klo, khi, seed):
+    inst = inputs.clique_cover_instance(n, items, klo, khi, seed)
+    c = inputs.weights_uniform01(n, seed)
+    return inst, c
+
+
+def _oracle(inst, c, t0, order, **kw):
+    cl = olp.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
+    classes = olp.colour_classes(cl)
+    return olp.solve(cl, c.astype(np.float64), float(t0), list(order), classes=classes, **kw)
+
+
+def _gpu(inst, c, t0, orders, **kw):
+    import torch
+    libgn = _lib()
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    x = torch.empty(len(t0) * inst.n, dtype=torch.float32, device="cuda")
+    st, res = L.solve(t0, orders, x, **kw)
+    return L, st, res, x.cpu().numpy().reshape(len(t0), inst.n)
+
+
+@pytest.mark.parametrize("n,items,klo,khi,starts,seed", [
+    (300, 80, 2, 4, 4, 0),      # a few dozen cliques per class
+    (2000, 300, 3, 8, 16, 1),   # 16 starts, cliques of ~30-60 members
+    (400, 6, 1, 3, 3, 2),       # cliques of ~100-200 members: several chunks per wavefront
+])
+def test_fixed_passes_match_oracle(gpu, n, items, klo, khi, starts, seed):
+    inst, c = _instance(n, items, klo, khi, seed)
+    kw = dict(drop=0.95, t_min=1e-3, max_passes=60, check_every=20, gap_tol=0.0, x_floor=1e-3)
+    libgn = _lib()
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    K = L.info["n_classes"]
+    cl = olp.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
+    assert K == int(olp.colour_classes(cl).max()) + 1
+    orders = inputs.class_orders(starts, K, seed)
+    t0 = inputs.jittered_temperatures(starts, 1.0, 1.1, seed)
+    _, st, res, x = _gpu(inst, c, t0, orders, **kw)
+    assert st == libgn.GN_NOT_CONVERGED
+    for s in range(starts):
+        xo, ro, _, _ = _oracle(inst, c, t0[s], orders[s], **kw)
+        assert res[s].passes == 60 and ro.passes == 60
+        assert res[s].temperature == pytest.approx(ro.temperature, rel=1e-5)
+        np.testing.assert_allclose(x[s], xo, rtol=2e-3, atol=1e-6)
+        assert res[s].dual == pytest.approx(ro.dual, rel=1e-4)
+        assert res[s].primal == pytest.approx(ro.primal, rel=1e-4)
+
+
+def test_single_clique_softmax_and_singletons(gpu):
+    """One clique over everything: one pass leaves softmax(c / t0).  Singleton
+    cliques only: every vertex reaches x = 1 (lam_i = c_i) and the gap is 0."""
+    import torch
+    libgn = _lib()
+    n = 150  # longer than a wavefront
+    c = inputs.weights_uniform01(n, 9)
+    L = libgn.LP(n, np.array([0, n]), np.arange(n), c)
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    st, res = L.solve(np.array([0.3], np.float32), np.zeros((1, 1), np.int32), x, max_passes=1, check_every=1,
+                      gap_tol=0.0, x_floor=0.0)
+    e = np.exp((c.astype(np.float64) - c.max()) / np.float64(np.float32(0.3)))
+    np.testing.assert_allclose(x.cpu().numpy(), e / e.sum(), rtol=1e-5, atol=1e-9)
+    S = libgn.LP(n, np.arange(n + 1), np.arange(n), c)
+    assert S.info["n_classes"] == 1
+    st, res = S.solve(np.array([0.5], np.float32), np.zeros((1, 1), np.int32), x, max_passes=3, check_every=1,
+                      gap_tol=1e-6)
+    assert st == libgn.GN_OK and res[0].passes == 1
+    np.testing.assert_allclose(x.cpu().numpy(), 1.0, rtol=1e-6)
+    assert res[0].dual == pytest.approx(float(c.astype(np.float64).sum()), rel=1e-6)
+
+
+def test_stopping_pass_and_duality_at_benchmark_size(gpu):
+    """10,000 routes and 2,000 stops (the benchmark's instance), 16 starts to a 1%
+    gap: D >= LP* >= P against HiGHS and the returned point is feasible
+    (x_floor = 0) for every start; for start 0, D and P at the GPU's stopping
+    pass match the oracle's at that pass, whose gap is within 5% of the
+    tolerance on the right side there and one check earlier."""
+    from scipy.optimize import linprog
+    from scipy.sparse import csr_matrix
+    inst, c = _instance(10000, 2000, 3, 8, 0)
+    libgn = _lib()
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    K = L.info["n_classes"]
+    orders = inputs.class_orders(16, K, 0)
+    t0 = inputs.jittered_temperatures(16, 1.0, 1.1, 0)
+    tol = 1e-2
+    kw = dict(drop=0.99, t_min=1e-4, max_passes=3000, check_every=10, gap_tol=tol, x_floor=0.0)
+    _, st, res, x = _gpu(inst, c, t0, orders, **kw)
+    assert st == libgn.GN_OK
+    A = csr_matrix((np.ones(inst.members.size), inst.members, inst.ptr), shape=(inst.m, inst.n))
+    r = linprog(-c.astype(np.float64), A_ub=A, b_ub=np.ones(inst.m), bounds=(0, None), method="highs")
+    opt = -r.fun
+    for s in range(16):
+        assert res[s].converged and res[s].gap <= tol
+        assert res[s].dual >= opt * (1 - 1e-5) and res[s].primal <= opt * (1 + 1e-5)
+        assert res[s].primal == pytest.approx(float(c.astype(np.float64) @ x[s]), rel=1e-5)
+        assert (A @ x[s].astype(np.float64)).max() <= 1 + 1e-5
+    trace = []
+    pg = res[0].passes
+    _oracle(inst, c, t0[0], orders[0], **dict(kw, max_passes=pg, gap_tol=0.0), trace=trace)
+    passes, D, P, gap = trace[-1]
+    assert passes == pg
+    assert res[0].dual == pytest.approx(D, rel=1e-3) and res[0].primal == pytest.approx(P, rel=1e-3)
+    assert gap <= tol * 1.05
+    if len(trace) > 1:
+        assert trace[-2][3] > tol * 0.95
+
+
+def test_warm_start_feeds_multi_start(gpu):
+    """The LP points start gn_multi_solve on the conflict graph: every start
+    binarises to an independent set."""
+    import torch
+    libgn = _lib()
+    inst, c = _instance(2000, 400, 3, 6, 3)
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    starts = 8
+    orders = inputs.class_orders(starts, L.info["n_classes"], 3)
+    t0 = inputs.jittered_temperatures(starts, 1.0, 1.1, 3)
+    x = torch.empty(starts * inst.n, dtype=torch.float32, device="cuda")
+    st, res = L.solve(t0, orders, x)
+    assert st == libgn.GN_OK
+    G = libgn.Graph(inst.n, inst.graph.row_ptr, inst.graph.col_idx, c)
+    sel = torch.zeros(starts * inst.n, dtype=torch.uint8, device="cuda")
+    sched = libgn.make_schedule(0.9, 1.5, 1000, 3000, 1e-4, 1)
+    st, out, best = libgn.gn_multi_solve(G.handle, sched, starts, x, sel)
+    for r in out:
+        assert r.conflicts == 0
+    assert out[best].set_objective > 0
+
+
+def test_solve_rejects_bad_arguments(gpu):
+    import torch
+    libgn = _lib()
+    inst, c = _instance(200, 40, 2, 3, 4)
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    K = L.info["n_classes"]
+    x = torch.empty(2 * inst.n, dtype=torch.float32, device="cuda")
+    good = np.stack([np.arange(K), np.arange(K)[::-1]]).astype(np.int32)
+    t0 = np.array([1.0, 1.0], np.float32)
+    bad_order = good.copy()
+    bad_order[1, 0] = bad_order[1, 1]
+    for kw in (dict(order=bad_order), dict(t0=np.array([1.0, 0.0], np.float32)), dict(drop=1.5),
+               dict(t_min=0.0), dict(max_passes=0), dict(check_every=0), dict(x_floor=1.0), dict(gap_tol=-1.0)):
+        a = dict(t0=t0, order=good, x=x)
+        a.update({k: v for k, v in kw.items() if k in ("order", "t0")})
+        rest = {k: v for k, v in kw.items() if k not in ("order", "t0")}
+        with pytest.raises(libgn.GNError):
+            L.solve(a["t0"], a["order"], a["x"], **rest)
