@@ -16,7 +16,8 @@
 // permutation), one launch per class for all starts together, a wavefront per
 // clique.  Disjointness makes the members' Lam updates race-free and the result
 // independent of the order inside a class.  Pass p runs at
-// T_p = max(t_min, t0 drop^p).
+// T_p = max(t_min, t0 drop^p), computed on the host in fp64 and passed by value
+// with each launch's clique ranges.
 //
 // The check (every check_every passes and after the last) bounds LP* from both
 // sides: D = sum lam_C + sum_i max(0, c_i - Lam_i) >= LP*, and the feasible
@@ -50,15 +51,21 @@ struct LpState {
     double gap;
 };
 
+// Per launch, by value: for each start the range of cliques (in class order)
+// the launch updates, empty for starts that have stopped, and the pass's
+// temperature.  The kernels then need no dependent loads to find their work.
+struct LpRound {
+    int32_t beg[GN_MAX_STARTS];
+    int32_t end[GN_MAX_STARTS];
+    float T[GN_MAX_STARTS];
+};
+
 struct LpArgs {
     const float* cost;       // [n]
     const int32_t* cptr;     // [m + 1], cliques in class order
     const int32_t* cmem;     // members
-    const int32_t* class_ptr;// [K + 1]
     const int32_t* vptr;     // [n + 1] vertex -> cliques
     const int32_t* vcl;
-    const int32_t* order;    // [S][K]
-    const float* t0;         // [S]
     float* Lam;              // [S][n]
     float* lam;              // [S][m]
     float* csum;             // [S][m]
@@ -66,7 +73,7 @@ struct LpArgs {
     LpState* st;             // [S]
     float* x_out;            // [S][n]
     int32_t n, m, K, nbv;
-    float drop, t_min, gap_tol, x_floor;
+    float gap_tol, x_floor;
 };
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -84,22 +91,32 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-__device__ __forceinline__ float pass_temperature(const LpArgs& a, int s, int p) {
-    return fmaxf(a.t_min, a.t0[s] * powf(a.drop, (float)p));
-}
-
-// One class of one start: a wavefront per clique.
-__global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, int32_t r, int32_t p) {
+// One class of every running start: a wavefront per clique.  A clique of at
+// most 64 members is held in registers (one member per lane); longer ones are
+// swept in chunks of 64.
+__global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, LpRound rd) {
     const int s = blockIdx.y;
-    if (a.st[s].done) return;
-    const int cls = a.order[(size_t)s * a.K + r];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int k = a.class_ptr[cls] + blockIdx.x * kLpWaves + wave;
-    if (k >= a.class_ptr[cls + 1]) return;
-    const float T = pass_temperature(a, s, p);
+    const int k = rd.beg[s] + blockIdx.x * kLpWaves + wave;
+    if (k >= rd.end[s]) return;
+    const float T = rd.T[s];
     const int b = a.cptr[k], e = a.cptr[k + 1];
     float* L = a.Lam + (size_t)s * a.n;
+    float* lp = a.lam + (size_t)s * a.m + k;
+    const float old = *lp;
+    if (e - b <= 64) {
+        const bool on = b + lane < e;
+        const int i = on ? a.cmem[b + lane] : 0;
+        const float Li = on ? L[i] : 0.0f;
+        const float ai = on ? (a.cost[i] - Li) / T : -INFINITY;
+        const float mx = wave_max(ai);
+        const float sum = wave_sum(on ? expf(ai - mx) : 0.0f);
+        const float nw = fmaxf(0.0f, old + T * (mx + logf(sum)));
+        if (on) L[i] = Li + (nw - old);
+        if (lane == 0) *lp = nw;
+        return;
+    }
     float mx = -INFINITY;
     for (int j = b + lane; j < e; j += 64) {
         const int i = a.cmem[j];
@@ -112,8 +129,6 @@ __global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, int32_t r,
         sum += expf((a.cost[i] - L[i]) / T - mx);
     }
     sum = wave_sum(sum);
-    float* lp = a.lam + (size_t)s * a.m + k;
-    const float old = *lp;
     const float nw = fmaxf(0.0f, old + T * (mx + logf(sum)));
     const float d = nw - old;
     for (int j = b + lane; j < e; j += 64) L[a.cmem[j]] += d;
@@ -121,14 +136,14 @@ __global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, int32_t r,
 }
 
 // Check, part 1: the clique sums of the smoothed primal.
-__global__ __launch_bounds__(kLpBlock) void lp_csum_kernel(LpArgs a, int32_t p) {
+__global__ __launch_bounds__(kLpBlock) void lp_csum_kernel(LpArgs a, LpRound rd) {
     const int s = blockIdx.y;
     if (a.st[s].done) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * kLpWaves + wave;
     if (k >= a.m) return;
-    const float T = pass_temperature(a, s, p);
+    const float T = rd.T[s];
     const float* L = a.Lam + (size_t)s * a.n;
     float sum = 0.0f;
     for (int j = a.cptr[k] + lane; j < a.cptr[k + 1]; j += 64) {
@@ -141,14 +156,14 @@ __global__ __launch_bounds__(kLpBlock) void lp_csum_kernel(LpArgs a, int32_t p) 
 
 // Check, part 2: the feasible point, written as the warm start, and per-block
 // partial sums of c.xf and of max(0, c - Lam) (fp64, fixed order).
-__global__ __launch_bounds__(kLpVBlock) void lp_vertex_kernel(LpArgs a, int32_t p) {
+__global__ __launch_bounds__(kLpVBlock) void lp_vertex_kernel(LpArgs a, LpRound rd) {
     const int s = blockIdx.y;
     if (a.st[s].done) return;
     __shared__ double red[2][kLpVBlock / 64];
     const int i = blockIdx.x * kLpVBlock + threadIdx.x;
     double pv = 0.0, dv = 0.0;
     if (i < a.n) {
-        const float T = pass_temperature(a, s, p);
+        const float T = rd.T[s];
         const float c = a.cost[i];
         const float Li = a.Lam[(size_t)s * a.n + i];
         const float x = expf(fminf((c - Li) / T, kExpCap));
@@ -181,7 +196,7 @@ __global__ __launch_bounds__(kLpVBlock) void lp_vertex_kernel(LpArgs a, int32_t 
 
 // Check, part 3: one workgroup per start reduces the bound and the primal value
 // and decides the stop.
-__global__ __launch_bounds__(kLpFBlock) void lp_finish_kernel(LpArgs a, int32_t p, int32_t last) {
+__global__ __launch_bounds__(kLpFBlock) void lp_finish_kernel(LpArgs a, LpRound rd, int32_t p, int32_t last) {
     const int s = blockIdx.x;
     if (a.st[s].done) return;
     __shared__ double red[3][kLpFBlock / 64];
@@ -218,7 +233,7 @@ __global__ __launch_bounds__(kLpFBlock) void lp_finish_kernel(LpArgs a, int32_t 
             o.done = 1;
             o.passes = p + 1;
             o.converged = conv ? 1 : 0;
-            o.temperature = pass_temperature(a, s, p);
+            o.temperature = rd.T[s];
             o.dual = Dt;
             o.primal = Pt;
             o.gap = gap;
@@ -248,11 +263,8 @@ struct gn_lp {
     float* cost = nullptr;
     int32_t* cptr = nullptr;
     int32_t* cmem = nullptr;
-    int32_t* class_ptr = nullptr;
     int32_t* vptr = nullptr;
     int32_t* vcl = nullptr;
-    int32_t* order = nullptr;
-    float* t0 = nullptr;
     float* Lam = nullptr;
     float* lam = nullptr;
     float* csum = nullptr;
@@ -265,11 +277,8 @@ static void lp_free(gn_lp* L) {
     hipFree(L->cost);
     hipFree(L->cptr);
     hipFree(L->cmem);
-    hipFree(L->class_ptr);
     hipFree(L->vptr);
     hipFree(L->vcl);
-    hipFree(L->order);
-    hipFree(L->t0);
     hipFree(L->Lam);
     hipFree(L->lam);
     hipFree(L->csum);
@@ -347,8 +356,8 @@ extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_pt
     for (int32_t c = 0; c < K; ++c) L->max_class = std::max(L->max_class, class_ptr[c + 1] - class_ptr[c]);
     const size_t S = GN_MAX_STARTS;
     bool ok = gn_dalloc(&L->cost, n) && gn_dalloc(&L->cptr, (size_t)m + 1) && gn_dalloc(&L->cmem, (size_t)nnzc) &&
-              gn_dalloc(&L->class_ptr, (size_t)K + 1) && gn_dalloc(&L->vptr, (size_t)n + 1) &&
-              gn_dalloc(&L->vcl, (size_t)nnzc) && gn_dalloc(&L->order, S * K) && gn_dalloc(&L->t0, S) &&
+              gn_dalloc(&L->vptr, (size_t)n + 1) &&
+              gn_dalloc(&L->vcl, (size_t)nnzc) &&
               gn_dalloc(&L->Lam, S * n) && gn_dalloc(&L->lam, S * m) && gn_dalloc(&L->csum, S * m) &&
               gn_dalloc(&L->part, S * 2 * (size_t)lp_nbv(n)) && gn_dalloc(&L->st, S);
     if (ok && hipHostMalloc((void**)&L->st_host, sizeof(LpState) * S, hipHostMallocDefault) != hipSuccess) {
@@ -363,8 +372,6 @@ extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_pt
     hipError_t e = hipMemcpyAsync(L->cost, cost, sizeof(float) * n, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(L->cptr, cptr.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(L->cmem, cmem.data(), sizeof(int32_t) * nnzc, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(L->class_ptr, class_ptr.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(L->vptr, vptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(L->vcl, vcl.data(), sizeof(int32_t) * nnzc, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -403,7 +410,6 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
         return GN_E_ARG;
     const int32_t K = L->K;
     std::vector<char> seen(K);
-    std::vector<int32_t> gx(K, 0);  // blocks of the class launched at position r
     for (int32_t s = 0; s < starts; ++s) {
         if (!(t0[s] > 0.0f) || !std::isfinite(t0[s])) return GN_E_ARG;
         std::fill(seen.begin(), seen.end(), 0);
@@ -411,19 +417,14 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
             const int32_t c = order[(size_t)s * K + r];
             if (c < 0 || c >= K || seen[c]) return GN_E_ARG;  // not a permutation of the classes
             seen[c] = 1;
-            const int32_t size = L->class_ptr_h[c + 1] - L->class_ptr_h[c];
-            gx[r] = std::max(gx[r], (size + kLpWaves - 1) / kLpWaves);
         }
     }
     LpArgs a;
     a.cost = L->cost;
     a.cptr = L->cptr;
     a.cmem = L->cmem;
-    a.class_ptr = L->class_ptr;
     a.vptr = L->vptr;
     a.vcl = L->vcl;
-    a.order = L->order;
-    a.t0 = L->t0;
     a.Lam = L->Lam;
     a.lam = L->lam;
     a.csum = L->csum;
@@ -434,27 +435,39 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
     a.m = L->m;
     a.K = K;
     a.nbv = lp_nbv(L->n);
-    a.drop = drop;
-    a.t_min = t_min;
     a.gap_tol = gap_tol;
     a.x_floor = x_floor;
-    GN_HIP_TRY(hipMemcpyAsync(L->order, order, sizeof(int32_t) * starts * K, hipMemcpyHostToDevice, stream));
-    GN_HIP_TRY(hipMemcpyAsync(L->t0, t0, sizeof(float) * starts, hipMemcpyHostToDevice, stream));
     lp_reset_kernel<<<1024, 256, 0, stream>>>(a, starts);
     GN_HIP_TRY(hipGetLastError());
     const dim3 gcs((L->m + kLpWaves - 1) / kLpWaves, starts), gv(a.nbv, starts);
+    std::vector<char> running(starts, 1);
+    LpRound rd{};
     for (int32_t p = 0; p < max_passes; ++p) {
-        for (int32_t r = 0; r < K; ++r) lp_round_kernel<<<dim3(gx[r], starts), kLpBlock, 0, stream>>>(a, r, p);
+        for (int32_t s = 0; s < starts; ++s)
+            rd.T[s] = (float)std::max((double)t_min, (double)t0[s] * std::pow((double)drop, (double)p));
+        for (int32_t r = 0; r < K; ++r) {
+            int32_t gx = 0;
+            for (int32_t s = 0; s < starts; ++s) {
+                const int32_t c = order[(size_t)s * K + r];
+                rd.beg[s] = L->class_ptr_h[c];
+                rd.end[s] = running[s] ? L->class_ptr_h[c + 1] : rd.beg[s];
+                gx = std::max(gx, (rd.end[s] - rd.beg[s] + kLpWaves - 1) / kLpWaves);
+            }
+            lp_round_kernel<<<dim3(gx, starts), kLpBlock, 0, stream>>>(a, rd);
+        }
         const bool last = p + 1 == max_passes;
         if ((p + 1) % check_every != 0 && !last) continue;
-        lp_csum_kernel<<<gcs, kLpBlock, 0, stream>>>(a, p);
-        lp_vertex_kernel<<<gv, kLpVBlock, 0, stream>>>(a, p);
-        lp_finish_kernel<<<starts, kLpFBlock, 0, stream>>>(a, p, last ? 1 : 0);
+        lp_csum_kernel<<<gcs, kLpBlock, 0, stream>>>(a, rd);
+        lp_vertex_kernel<<<gv, kLpVBlock, 0, stream>>>(a, rd);
+        lp_finish_kernel<<<starts, kLpFBlock, 0, stream>>>(a, rd, p, last ? 1 : 0);
         GN_HIP_TRY(hipGetLastError());
         GN_HIP_TRY(hipMemcpyAsync(L->st_host, L->st, sizeof(LpState) * starts, hipMemcpyDeviceToHost, stream));
         GN_HIP_TRY(hipStreamSynchronize(stream));
         bool all = true;
-        for (int32_t s = 0; s < starts; ++s) all = all && L->st_host[s].done;
+        for (int32_t s = 0; s < starts; ++s) {
+            running[s] = !L->st_host[s].done;
+            all = all && !running[s];
+        }
         if (all) break;
     }
     bool conv = true;
