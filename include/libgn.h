@@ -493,6 +493,54 @@ gn_status gn_lp_solve(gn_lp* lp, int32_t starts, const float* t0, const int32_t*
                       int32_t max_passes, int32_t check_every, float gap_tol, float x_floor, float* x,
                       gn_lp_result* res, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * GN under hyperedge constraints (the extension to hypergraph constraints left
+ * to future work in the Conclusion; no formula in the paper, so this is the
+ * library's reading).  Hyperedges are clique constraints (at most one selected
+ * vertex each, the form of the paper's instances) and every vertex is
+ * normalised by the mass of the hyperedges holding it, as the cross-
+ * normalization of the assignment problem (Section 2) does with rows and
+ * columns.  With y = v (.) x and Y_e = sum_{j in e} y_j:
+ *     s_i = y_i + gamma * sum_{e holds i} (Y_e - y_i),   x'_i = y_i / s_i,
+ * with the safe division and support floor of gn_step.  This is gn_step on the
+ * conflict graph whose edge (i, j) counts the hyperedges holding both; it costs
+ * O(memberships) per step instead of O(conflict edges), and equals gn_step on
+ * the plain conflict graph when no two vertices share two hyperedges (rows and
+ * columns of an assignment instance, for instance).
+ * ------------------------------------------------------------------------- */
+
+typedef struct gn_hyper gn_hyper;  /* hyperedges, weights, work buffers */
+
+/* Create an instance.  Host arrays: hyperedge e is members[edge_ptr[e] ..
+ * edge_ptr[e+1]-1] (m >= 1, each non-empty with strictly increasing ids in
+ * [0, n)); every vertex must lie in some hyperedge (a singleton is allowed);
+ * w: float[n], finite and > 0.  The library copies everything.  Errors:
+ * GN_E_ARG, GN_E_CSR, GN_E_WEIGHT (as gn_lp_create), GN_E_NOMEM, GN_E_HIP;
+ * *out = NULL on error.  SYNC. */
+gn_status gn_hyper_create(int32_t n, int32_t m, const int32_t* edge_ptr, const int32_t* members, const float* w,
+                          hipStream_t stream, gn_hyper** out);
+
+/* Free an instance (NULL is allowed).  Waits for the device. */
+void gn_hyper_destroy(gn_hyper* h);
+
+/* One step at gamma (finite, >= 0): x_out = N(x_in), device float[n] each, not
+ * aliased, x_in finite and >= 0.  ASYNC. */
+gn_status gn_hyper_step(gn_hyper* h, float gamma, const float* x_in, float* x_out, hipStream_t stream);
+
+/* Iterate to binarisation under `sch` with the stopping rule of gn_solve, read
+ * on the hyperedge-weighted conflict graph: a vertex is covered when one of its
+ * hyperedges holds a member above 1/2.  x: device float[n], x^0 on entry (finite,
+ * >= 0, every vertex with mass in its hyperedges, else GN_E_ARG /
+ * GN_E_NOT_NORMALIZABLE), the final state clamped to [0,1] on exit; sel: device
+ * uint8[n], (x > 1/2); res: host.  In res, conflicts counts pairs of selected
+ * vertices per hyperedge holding both, uncovered the unselected vertices whose
+ * hyperedges hold no selected vertex, and stab is gamma_k * min over unselected
+ * i of sum_{e holds i} sum_{j in e, selected} v_j / v_i (+inf when every
+ * vertex is selected).  Returns GN_OK when binarised, GN_NOT_CONVERGED when
+ * max_steps ran out.  SYNC. */
+gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                         hipStream_t stream);
+
 /* Tuning: number of step launches captured in one replayed chain by gn_solve and
  * gn_rook_solve (default 32, 1..4096).  A longer chain checks the stop flag less
  * often from the host; results do not change.  Process-wide; not thread-safe. */

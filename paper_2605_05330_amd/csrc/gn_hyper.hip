@@ -1,0 +1,548 @@
+// GN under hyperedge constraints (the hypergraph extension left to future work
+// in the Conclusion; no formula in the paper).  Hyperedges are clique
+// constraints, at most one selected vertex each, and every vertex is
+// normalised by the mass of the hyperedges holding it, as the
+// cross-normalization of the assignment problem (Section 2) does with rows and
+// columns:
+//
+//     Y_e = sum_{j in e} y_j,   s_i = y_i + gamma * sum_{e holds i} (Y_e - y_i),
+//
+// x'_i = y_i / s_i with the safe division and support floor of the WRGN step.
+// This is WRGN on the conflict graph whose edge (i, j) counts the hyperedges
+// holding both, at O(memberships) per step instead of O(conflict edges).
+//
+// A step is two launches: a wavefront per hyperedge forms Y_e and the count of
+// members above 1/2; a thread per vertex sums its hyperedges and writes x'.  In
+// a solve, the vertex kernel of step k also evaluates the stopping test of
+// gn_solve on x^k (tau, uncovered, growing) into a per-step violation count,
+// and the hyperedge kernel of step k+1 stops the solve when step k was a check
+// step with no violation: every later launch then returns at once, so the host
+// enqueues the steps in chains and looks at the stop flag between chains.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gn_internal.h"
+
+namespace {
+
+constexpr int kHWaves = 4;           // hyperedges per workgroup
+constexpr int kHBlock = 64 * kHWaves;
+constexpr int kHVBlock = 256;        // vertex kernels
+constexpr int kHChain = 64;          // steps enqueued between looks at the stop flag
+constexpr float kSafeDiv = 1e-9f;    // safe division threshold of the WRGN step
+constexpr float kXMin = 0x1p-100f;   // support floor of a positive coordinate
+
+struct HState {
+    int32_t done;
+    int32_t step;
+    int32_t binarised;
+    int32_t pad;
+    unsigned long long fallback;
+};
+
+struct HPart {
+    double relaxed;
+    double W;
+    long long size;
+    long long uncovered;
+    long long conflicts;
+    float stab;
+    int32_t pad;
+};
+
+struct HArgs {
+    const float* v;
+    const float* w;
+    const int32_t* eptr;
+    const int32_t* emem;
+    const int32_t* vptr;
+    const int32_t* vedge;
+    float* Y;          // [m]
+    int32_t* cnt;      // [m] members with x > 1/2
+    float* vs;         // [m] sum of v over selected members (final statistics)
+    int32_t* viol;     // [max_steps + 1]
+    HState* st;
+    HPart* part;       // [max(nbv, nbe)]
+    int32_t n, m, nbv, nbe;
+    int32_t check_every;
+    float tau;
+};
+
+__device__ __forceinline__ float hwave_sum(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int hwave_sum_i(int v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Hyperedge sums of y = v x and counts of members above 1/2.  In a solve
+// (solve = 1) the launch of step k first settles the check of step k - 1.
+__global__ __launch_bounds__(kHBlock) void hyper_edge_kernel(HArgs a, const float* x, int32_t k, int32_t solve) {
+    if (solve) {
+        if (a.st->done) return;
+        const int kp = k - 1;
+        if (kp >= 1 && kp % a.check_every == 0 && a.viol[kp] == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                a.st->step = kp;
+                a.st->binarised = 1;
+                a.st->done = 1;
+            }
+            return;
+        }
+    }
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * kHWaves + wave;
+    if (e >= a.m) return;
+    float Y = 0.0f;
+    int c = 0;
+    for (int j = a.eptr[e] + lane; j < a.eptr[e + 1]; j += 64) {
+        const int i = a.emem[j];
+        const float xi = x[i];
+        Y += a.v[i] * xi;
+        c += xi > 0.5f ? 1 : 0;
+    }
+    Y = hwave_sum(Y);
+    c = hwave_sum_i(c);
+    if (lane == 0) {
+        a.Y[e] = Y;
+        a.cnt[e] = c;
+    }
+}
+
+// x' from the hyperedge sums (write = 1), and in a solve at a check step the
+// stopping test on x (check = 1), counted into viol[k] once per workgroup.
+__global__ __launch_bounds__(kHVBlock) void hyper_vertex_kernel(HArgs a, const float* x, float* xo, float gamma,
+                                                               int32_t k, int32_t solve, int32_t check,
+                                                               int32_t write) {
+    if (solve && a.st->done) return;
+    const int i = blockIdx.x * kHVBlock + threadIdx.x;
+    bool bad = false, fb = false;
+    if (i < a.n) {
+        const float xi = x[i];
+        const float vi = a.v[i];
+        const float y = vi * xi;
+        float nb = 0.0f;
+        int cov = 0;
+        for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) {
+            const int e = a.vedge[q];
+            nb += a.Y[e] - y;
+            cov += a.cnt[e];
+        }
+        const float s = gamma * nb + y;
+        if (write) {
+            float xn;
+            if (s > kSafeDiv) {
+                xn = y / s;
+                if (y > 0.0f && xn < kXMin) xn = kXMin;
+            } else {
+                xn = 0.5f;
+                fb = true;
+            }
+            xo[i] = xn;
+        }
+        if (check) {
+            const float d = fminf(xi, 1.0f - xi);
+            bad = d > a.tau;
+            if (xi <= 0.5f) {
+                bad = bad || cov == 0;                        // uncovered
+                bad = bad || (xi > 0.0f && !(s > vi));         // growing
+            }
+        }
+    }
+    if (solve && write) {
+        const unsigned long long nf = __popcll(__ballot(fb));
+        if (nf && (threadIdx.x & 63) == 0) atomicAdd(&a.st->fallback, nf);
+    }
+    if (check) {
+        if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicAdd(&a.viol[k], 1);
+    }
+}
+
+// A solve that ran to max_steps: the check of x^max_steps decides.
+__global__ void hyper_resolve_kernel(HArgs a, int32_t max_steps, int32_t checked) {
+    if (a.st->done) return;
+    a.st->step = max_steps;
+    a.st->binarised = (checked && a.viol[max_steps] == 0) ? 1 : 0;
+    a.st->done = 1;
+}
+
+// Final statistics, part 1: per hyperedge the selected count and the sum of v
+// over its selected members; per workgroup the conflicts (pairs of selected
+// members, counted per hyperedge).
+__global__ __launch_bounds__(kHBlock) void hyper_stats_edge_kernel(HArgs a, const float* x) {
+    __shared__ long long red[kHWaves];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * kHWaves + wave;
+    long long conf = 0;
+    if (e < a.m) {
+        float vs = 0.0f;
+        int c = 0;
+        for (int j = a.eptr[e] + lane; j < a.eptr[e + 1]; j += 64) {
+            const int i = a.emem[j];
+            if (fminf(fmaxf(x[i], 0.0f), 1.0f) > 0.5f) {
+                vs += a.v[i];
+                ++c;
+            }
+        }
+        vs = hwave_sum(vs);
+        c = hwave_sum_i(c);
+        if (lane == 0) {
+            a.vs[e] = vs;
+            a.cnt[e] = c;
+        }
+        conf = (long long)c * (c - 1) / 2;
+    }
+    if (lane == 0) red[wave] = conf;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int q = 0; q < kHWaves; ++q) t += red[q];
+        a.part[blockIdx.x].conflicts = t;
+    }
+}
+
+// Part 2: the clamped state and the set, per-workgroup sums of the relaxed
+// objective, W(S), |S|, the uncovered vertices and the minimum stability term
+// gamma * sum_{e holds i} (sum of v over e's selected members) / v_i over i
+// outside S.  The conflicts of part 1 are kept in the same slot.
+__global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, const float* x, float* x_user,
+                                                                     uint8_t* sel, float gamma) {
+    __shared__ HPart red[kHVBlock / 64];
+    const int i = blockIdx.x * kHVBlock + threadIdx.x;
+    double rel = 0.0, W = 0.0;
+    long long sz = 0, unc = 0;
+    float stab = INFINITY;
+    if (i < a.n) {
+        const float xc = fminf(fmaxf(x[i], 0.0f), 1.0f);
+        const bool in = xc > 0.5f;
+        x_user[i] = xc;
+        sel[i] = in ? 1 : 0;
+        const float wi = a.w[i];
+        rel = (double)wi * (double)xc;
+        if (in) {
+            W = (double)wi;
+            sz = 1;
+        } else {
+            int cov = 0;
+            float t = 0.0f;
+            for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) {
+                const int e = a.vedge[q];
+                cov += a.cnt[e];
+                t += a.vs[e];
+            }
+            unc = cov == 0 ? 1 : 0;
+            stab = gamma * t / a.v[i];
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        rel += __shfl_xor(rel, o, 64);
+        W += __shfl_xor(W, o, 64);
+        sz += __shfl_xor(sz, o, 64);
+        unc += __shfl_xor(unc, o, 64);
+        stab = fminf(stab, __shfl_xor(stab, o, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w].relaxed = rel;
+        red[w].W = W;
+        red[w].size = sz;
+        red[w].uncovered = unc;
+        red[w].stab = stab;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        HPart t{};
+        t.stab = INFINITY;
+        for (int q = 0; q < kHVBlock / 64; ++q) {
+            t.relaxed += red[q].relaxed;
+            t.W += red[q].W;
+            t.size += red[q].size;
+            t.uncovered += red[q].uncovered;
+            t.stab = fminf(t.stab, red[q].stab);
+        }
+        HPart& o = a.part[blockIdx.x];
+        o.relaxed = t.relaxed;
+        o.W = t.W;
+        o.size = t.size;
+        o.uncovered = t.uncovered;
+        o.stab = t.stab;
+    }
+}
+
+// Part 3: one workgroup reduces the partials in a fixed order into out.
+__global__ __launch_bounds__(256) void hyper_stats_finish_kernel(HArgs a, HPart* out) {
+    __shared__ HPart red[256 / 64];
+    HPart t{};
+    t.stab = INFINITY;
+    const int nb = max(a.nbv, a.nbe);
+    for (int q = threadIdx.x; q < nb; q += 256) {
+        const HPart& p = a.part[q];
+        if (q < a.nbv) {
+            t.relaxed += p.relaxed;
+            t.W += p.W;
+            t.size += p.size;
+            t.uncovered += p.uncovered;
+            t.stab = fminf(t.stab, p.stab);
+        }
+        if (q < a.nbe) t.conflicts += p.conflicts;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        t.relaxed += __shfl_xor(t.relaxed, o, 64);
+        t.W += __shfl_xor(t.W, o, 64);
+        t.size += __shfl_xor(t.size, o, 64);
+        t.uncovered += __shfl_xor(t.uncovered, o, 64);
+        t.conflicts += __shfl_xor(t.conflicts, o, 64);
+        t.stab = fminf(t.stab, __shfl_xor(t.stab, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        HPart r{};
+        r.stab = INFINITY;
+        for (int q = 0; q < 256 / 64; ++q) {
+            r.relaxed += red[q].relaxed;
+            r.W += red[q].W;
+            r.size += red[q].size;
+            r.uncovered += red[q].uncovered;
+            r.conflicts += red[q].conflicts;
+            r.stab = fminf(r.stab, red[q].stab);
+        }
+        *out = r;
+    }
+}
+
+}  // namespace
+
+struct gn_hyper {
+    int device = 0;
+    int32_t n = 0, m = 0;
+    int64_t nnzc = 0;
+    std::vector<int32_t> eptr_h, emem_h, vptr_h, vedge_h;  // host copies (normalizable check)
+    std::vector<float> v_h;
+    float* v = nullptr;
+    float* w = nullptr;
+    int32_t* eptr = nullptr;
+    int32_t* emem = nullptr;
+    int32_t* vptr = nullptr;
+    int32_t* vedge = nullptr;
+    float* Y = nullptr;
+    int32_t* cnt = nullptr;
+    float* vs = nullptr;
+    float* buf[2] = {nullptr, nullptr};
+    int32_t* viol = nullptr;
+    int32_t viol_cap = 0;
+    HState* st = nullptr;
+    HPart* part = nullptr;
+    HPart* out = nullptr;
+    void* host = nullptr;  // pinned: HState + HPart
+};
+
+static void hyper_free(gn_hyper* h) {
+    hipFree(h->v);
+    hipFree(h->w);
+    hipFree(h->eptr);
+    hipFree(h->emem);
+    hipFree(h->vptr);
+    hipFree(h->vedge);
+    hipFree(h->Y);
+    hipFree(h->cnt);
+    hipFree(h->vs);
+    hipFree(h->buf[0]);
+    hipFree(h->buf[1]);
+    hipFree(h->viol);
+    hipFree(h->st);
+    hipFree(h->part);
+    hipFree(h->out);
+    if (h->host) hipHostFree(h->host);
+}
+
+static int32_t hyper_nbv(int32_t n) { return (n + kHVBlock - 1) / kHVBlock; }
+static int32_t hyper_nbe(int32_t m) { return (m + kHWaves - 1) / kHWaves; }
+
+static HArgs hyper_args(gn_hyper* h) {
+    HArgs a;
+    a.v = h->v;
+    a.w = h->w;
+    a.eptr = h->eptr;
+    a.emem = h->emem;
+    a.vptr = h->vptr;
+    a.vedge = h->vedge;
+    a.Y = h->Y;
+    a.cnt = h->cnt;
+    a.vs = h->vs;
+    a.viol = h->viol;
+    a.st = h->st;
+    a.part = h->part;
+    a.n = h->n;
+    a.m = h->m;
+    a.nbv = hyper_nbv(h->n);
+    a.nbe = hyper_nbe(h->m);
+    a.check_every = 1;
+    a.tau = 0.0f;
+    return a;
+}
+
+extern "C" gn_status gn_hyper_create(int32_t n, int32_t m, const int32_t* edge_ptr, const int32_t* members,
+                                     const float* w, hipStream_t stream, gn_hyper** out) {
+    if (!out) return GN_E_ARG;
+    *out = nullptr;
+    std::vector<int32_t> cover;
+    const gn_status vs = gn_internal_check_cliques(n, m, edge_ptr, members, w, cover);
+    if (vs != GN_OK) return vs;
+    gn_hyper* h = new (std::nothrow) gn_hyper();
+    if (!h) return GN_E_NOMEM;
+    (void)hipGetDevice(&h->device);
+    h->n = n;
+    h->m = m;
+    h->nnzc = edge_ptr[m];
+    h->eptr_h.assign(edge_ptr, edge_ptr + m + 1);
+    h->emem_h.assign(members, members + h->nnzc);
+    h->vptr_h.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) h->vptr_h[i + 1] = h->vptr_h[i] + cover[i];
+    h->vedge_h.assign((size_t)h->nnzc, 0);
+    std::vector<int32_t> pos(h->vptr_h.begin(), h->vptr_h.end() - 1);
+    for (int32_t e = 0; e < m; ++e)
+        for (int32_t j = edge_ptr[e]; j < edge_ptr[e + 1]; ++j) h->vedge_h[pos[members[j]]++] = e;
+    h->v_h.resize(n);
+    for (int32_t i = 0; i < n; ++i) h->v_h[i] = (float)std::sqrt((double)w[i]);
+    const size_t nparts = (size_t)std::max(hyper_nbv(n), hyper_nbe(m));
+    bool ok = gn_dalloc(&h->v, n) && gn_dalloc(&h->w, n) && gn_dalloc(&h->eptr, (size_t)m + 1) &&
+              gn_dalloc(&h->emem, (size_t)h->nnzc) && gn_dalloc(&h->vptr, (size_t)n + 1) &&
+              gn_dalloc(&h->vedge, (size_t)h->nnzc) && gn_dalloc(&h->Y, m) && gn_dalloc(&h->cnt, m) &&
+              gn_dalloc(&h->vs, m) && gn_dalloc(&h->buf[0], n) && gn_dalloc(&h->buf[1], n) &&
+              gn_dalloc(&h->st, 1) && gn_dalloc(&h->part, nparts) && gn_dalloc(&h->out, 1);
+    if (ok && hipHostMalloc(&h->host, sizeof(HState) + sizeof(HPart), hipHostMallocDefault) != hipSuccess) {
+        h->host = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        hyper_free(h);
+        delete h;
+        return GN_E_NOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(h->v, h->v_h.data(), sizeof(float) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->w, w, sizeof(float) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->eptr, edge_ptr, sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->emem, members, sizeof(int32_t) * h->nnzc, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->vptr, h->vptr_h.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->vedge, h->vedge_h.data(), sizeof(int32_t) * h->nnzc, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        hyper_free(h);
+        delete h;
+        return GN_E_HIP;
+    }
+    *out = h;
+    return GN_OK;
+}
+
+extern "C" void gn_hyper_destroy(gn_hyper* h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    hyper_free(h);
+    delete h;
+}
+
+extern "C" gn_status gn_hyper_step(gn_hyper* h, float gamma, const float* x_in, float* x_out, hipStream_t stream) {
+    if (!h || !x_in || !x_out || x_in == x_out) return GN_E_ARG;
+    if (!std::isfinite(gamma) || gamma < 0.0f) return GN_E_ARG;
+    HArgs a = hyper_args(h);
+    hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, x_in, 0, 0);
+    hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, x_in, x_out, gamma, 0, 0, 0, 1);
+    GN_HIP_TRY(hipGetLastError());
+    return GN_OK;
+}
+
+extern "C" gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                                    hipStream_t stream) {
+    if (!h || !sch || !res || !x || !sel) return GN_E_ARG;
+    if (!gn_internal_schedule_ok(sch)) return GN_E_ARG;
+    std::memset(res, 0, sizeof(*res));
+    const int32_t n = h->n, ms = sch->max_steps;
+    // x^0: finite, >= 0 and normalizable (every closed neighbourhood has mass),
+    // checked on the host
+    std::vector<float> x0(n);
+    GN_HIP_TRY(hipMemcpyAsync(x0.data(), x, sizeof(float) * n, hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    for (int32_t i = 0; i < n; ++i)
+        if (!(x0[i] >= 0.0f) || !std::isfinite(x0[i])) return GN_E_ARG;
+    std::vector<double> X(h->m, 0.0);
+    for (int32_t e = 0; e < h->m; ++e)
+        for (int32_t j = h->eptr_h[e]; j < h->eptr_h[e + 1]; ++j) X[e] += x0[h->emem_h[j]];
+    for (int32_t i = 0; i < n; ++i) {
+        double s = x0[i];
+        for (int32_t q = h->vptr_h[i]; q < h->vptr_h[i + 1]; ++q) s += X[h->vedge_h[q]] - x0[i];
+        if (!(s > 0.0)) return GN_E_NOT_NORMALIZABLE;
+    }
+    if (ms + 1 > h->viol_cap) {
+        hipFree(h->viol);
+        h->viol = nullptr;
+        h->viol_cap = 0;
+        if (!gn_dalloc(&h->viol, (size_t)ms + 1)) return GN_E_NOMEM;
+        h->viol_cap = ms + 1;
+    }
+    HArgs a = hyper_args(h);
+    a.check_every = sch->check_every;
+    a.tau = sch->tau;
+    GN_HIP_TRY(hipMemsetAsync(h->viol, 0, sizeof(int32_t) * (ms + 1), stream));
+    GN_HIP_TRY(hipMemsetAsync(h->st, 0, sizeof(HState), stream));
+    GN_HIP_TRY(hipMemcpyAsync(h->buf[0], x, sizeof(float) * n, hipMemcpyDeviceToDevice, stream));
+    HState* hs = (HState*)h->host;
+    HPart* hp = (HPart*)((char*)h->host + sizeof(HState));
+    bool done = false;
+    for (int32_t k0 = 0; k0 < ms && !done; k0 += kHChain) {
+        const int32_t k1 = std::min(ms, k0 + kHChain);
+        for (int32_t k = k0; k < k1; ++k) {
+            const float g = gn_internal_host_gamma(sch, k);
+            const int32_t chk = k >= 1 && k % sch->check_every == 0;
+            hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, h->buf[k & 1], k, 1);
+            hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, h->buf[k & 1], h->buf[(k + 1) & 1], g, k, 1, chk,
+                                                                1);
+        }
+        GN_HIP_TRY(hipGetLastError());
+        GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState), hipMemcpyDeviceToHost, stream));
+        GN_HIP_TRY(hipStreamSynchronize(stream));
+        done = hs->done != 0;
+    }
+    // the last check: a pending check of step ms - 1, then x^ms itself
+    hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, h->buf[ms & 1], ms, 1);
+    hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, h->buf[ms & 1], nullptr, gn_internal_host_gamma(sch, ms),
+                                                        ms, 1, ms >= 1 ? 1 : 0, 0);
+    hyper_resolve_kernel<<<1, 1, 0, stream>>>(a, ms, ms >= 1 ? 1 : 0);
+    GN_HIP_TRY(hipGetLastError());
+    GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    const int32_t steps = hs->step;
+    const float* xf = h->buf[steps & 1];
+    const float gf = gn_internal_host_gamma(sch, steps);
+    hyper_stats_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, xf);
+    hyper_stats_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, xf, x, sel, gf);
+    hyper_stats_finish_kernel<<<1, 256, 0, stream>>>(a, h->out);
+    GN_HIP_TRY(hipGetLastError());
+    GN_HIP_TRY(hipMemcpyAsync(hp, h->out, sizeof(HPart), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    res->steps = steps;
+    res->binarised = hs->binarised;
+    res->fallback_count = (int64_t)hs->fallback;
+    res->relaxed_objective = hp->relaxed;
+    res->set_objective = hp->W;
+    res->set_size = hp->size;
+    res->conflicts = hp->conflicts;
+    res->uncovered = hp->uncovered;
+    res->stab = hp->stab;
+    if (!std::isfinite(res->relaxed_objective)) return GN_E_NUMERIC;
+    return res->binarised ? GN_OK : GN_NOT_CONVERGED;
+}

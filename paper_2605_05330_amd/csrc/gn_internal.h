@@ -65,6 +65,14 @@ struct FinalStats {
     int32_t pad;
 };
 
+// Validation of clique (hyperedge) constraints given on the host: clique k is
+// members[ptr[k] .. ptr[k+1]-1], non-empty, ids strictly increasing in [0, n);
+// every vertex in some clique; w finite and > 0.  cover receives each vertex's
+// clique count.  GN_E_ARG / GN_E_CSR / GN_E_WEIGHT as the clique entry points
+// document.  (gn_lp.hip)
+gn_status gn_internal_check_cliques(int32_t n, int32_t m, const int32_t* ptr, const int32_t* members,
+                                    const float* w, std::vector<int32_t>& cover);
+
 // Device allocation of count elements (at least one); false and a cleared HIP
 // error on failure.
 template <typename T>

@@ -287,29 +287,38 @@ static void lp_free(gn_lp* L) {
     if (L->st_host) hipHostFree(L->st_host);
 }
 
+gn_status gn_internal_check_cliques(int32_t n, int32_t m, const int32_t* ptr, const int32_t* members,
+                                    const float* w, std::vector<int32_t>& cover) {
+    if (n < 1 || m < 1 || !ptr || !members || !w) return GN_E_ARG;
+    if (ptr[0] != 0) return GN_E_CSR;
+    for (int32_t k = 0; k < m; ++k)
+        if (ptr[k + 1] <= ptr[k]) return GN_E_CSR;  // empty clique or not monotone
+    cover.assign(n, 0);
+    for (int32_t k = 0; k < m; ++k)
+        for (int32_t j = ptr[k]; j < ptr[k + 1]; ++j) {
+            const int32_t i = members[j];
+            if (i < 0 || i >= n) return GN_E_CSR;
+            if (j > ptr[k] && i <= members[j - 1]) return GN_E_CSR;
+            ++cover[i];
+        }
+    for (int32_t i = 0; i < n; ++i) {
+        if (cover[i] == 0) return GN_E_ARG;  // a vertex outside every clique
+        if (!(w[i] > 0.0f) || !std::isfinite(w[i])) return GN_E_WEIGHT;
+    }
+    return GN_OK;
+}
+
 static int32_t lp_nbv(int32_t n) { return (n + kLpVBlock - 1) / kLpVBlock; }
 
 extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_ptr, const int32_t* members,
                                   const float* cost, hipStream_t stream, gn_lp** out) {
     if (!out) return GN_E_ARG;
     *out = nullptr;
-    if (n < 1 || m < 1 || !clique_ptr || !members || !cost) return GN_E_ARG;
-    if (clique_ptr[0] != 0) return GN_E_CSR;
-    for (int32_t k = 0; k < m; ++k)
-        if (clique_ptr[k + 1] <= clique_ptr[k]) return GN_E_CSR;  // empty clique or not monotone
+    if (!cost) return GN_E_ARG;
+    std::vector<int32_t> cover;
+    const gn_status vs = gn_internal_check_cliques(n, m, clique_ptr, members, cost, cover);
+    if (vs != GN_OK) return vs;
     const int64_t nnzc = clique_ptr[m];
-    std::vector<int32_t> cover(n, 0);
-    for (int32_t k = 0; k < m; ++k)
-        for (int32_t j = clique_ptr[k]; j < clique_ptr[k + 1]; ++j) {
-            const int32_t i = members[j];
-            if (i < 0 || i >= n) return GN_E_CSR;
-            if (j > clique_ptr[k] && i <= members[j - 1]) return GN_E_CSR;
-            ++cover[i];
-        }
-    for (int32_t i = 0; i < n; ++i) {
-        if (cover[i] == 0) return GN_E_ARG;  // a vertex outside every clique leaves the LP unbounded
-        if (!(cost[i] > 0.0f) || !std::isfinite(cost[i])) return GN_E_WEIGHT;
-    }
     // first-fit colouring in input order: the lowest class none of whose
     // cliques holds a member of clique k
     std::vector<std::vector<int32_t>> used(n);

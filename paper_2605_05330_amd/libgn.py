@@ -108,6 +108,12 @@ def lib():
             "gn_rook_destroy": ([_vp], None),
             "gn_lp_create": ([ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
             "gn_lp_destroy": ([_vp], None),
+            "gn_hyper_create": ([ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)],
+                                ctypes.c_int),
+            "gn_hyper_destroy": ([_vp], None),
+            "gn_hyper_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
+            "gn_hyper_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
+                               ctypes.c_int),
             "gn_lp_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "gn_lp_solve": ([_vp, ctypes.c_int32, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
@@ -403,6 +409,60 @@ class LP:
 
     def solve(self, t0, order, x, **kw):
         return gn_lp_solve(self.handle, t0, order, x, **kw)
+
+
+def gn_hyper_create(n, edge_ptr, members, w, stream=None):
+    """Hyperedge-constrained instance from host arrays (int32 CSR of hyperedges,
+    float32 weights)."""
+    ep = np.ascontiguousarray(edge_ptr, dtype=np.int32)
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.float32)
+    if ww.size != int(n) or ep.size < 2 or int(ep[-1]) != mem.size:
+        raise GNError(GN_E_ARG, "gn_hyper_create: sizes")
+    h = _vp()
+    _check(lib().gn_hyper_create(int(n), int(ep.size - 1), _vp(ep.ctypes.data), _vp(mem.ctypes.data),
+                                 _vp(ww.ctypes.data), _stream(stream), ctypes.byref(h)), "gn_hyper_create")
+    return h
+
+
+def gn_hyper_destroy(h):
+    if h:
+        lib().gn_hyper_destroy(h)
+
+
+def gn_hyper_step(h, gamma, x_in, x_out, stream=None):
+    import torch
+    _check(lib().gn_hyper_step(h, float(gamma), _dptr(x_in, torch.float32, "x_in"),
+                               _dptr(x_out, torch.float32, "x_out"), _stream(stream)), "gn_hyper_step")
+
+
+def gn_hyper_solve(h, schedule: gn_schedule, x, sel, stream=None) -> Result:
+    import torch
+    res = gn_result()
+    st = lib().gn_hyper_solve(h, ctypes.byref(schedule), _dptr(x, torch.float32, "x"),
+                              _dptr(sel, torch.uint8, "sel"), ctypes.byref(res), _stream(stream))
+    _check(st, "gn_hyper_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return _result(res, st)
+
+
+class Hyper:
+    """Owning wrapper of a gn_hyper handle (GN under hyperedge constraints)."""
+
+    def __init__(self, n, edge_ptr, members, w, stream=None):
+        self.n = int(n)
+        self.handle = gn_hyper_create(n, edge_ptr, members, w, stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            gn_hyper_destroy(h)
+            self.handle = None
+
+    def step(self, gamma, x_in, x_out, stream=None):
+        gn_hyper_step(self.handle, gamma, x_in, x_out, stream)
+
+    def solve(self, x, sel, stream=None, **sched) -> Result:
+        return gn_hyper_solve(self.handle, make_schedule(**sched), x, sel, stream)
 
 
 def gn_rook_create(rows, cols, w, stream=None):
