@@ -131,3 +131,27 @@ def test_solve_input_errors(gpu):
         H.step(-1.0, x, torch.empty_like(x))
     with pytest.raises(libgn.GNError):
         H.step(1.0, x, x)
+
+
+@pytest.mark.parametrize("n,ptr,mem,w", [
+    (1, [0, 1], [0], [0.7]),                          # one vertex: selected at the first check, stab +inf
+    (3, [0, 3], [0, 1, 2], [0.2, 0.9, 0.5]),          # one hyperedge: the heaviest vertex wins
+    (4, [0, 1, 2, 3, 4], [0, 1, 2, 3], [0.3, 0.6, 0.9, 0.1]),  # singletons only: everything selected
+])
+def test_degenerate_instances(gpu, n, ptr, mem, w):
+    import torch
+    libgn = _lib()
+    w = np.asarray(w, np.float32)
+    H = libgn.Hyper(n, np.asarray(ptr), np.asarray(mem), w)
+    x = torch.full((n,), 0.5, device="cuda")
+    sel = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    res = H.solve(x, sel)
+    ref = OH.solve(n, np.asarray(ptr), np.asarray(mem), w.astype(np.float64), np.full(n, 0.5),
+                   gamma0=float(np.float32(0.9)))
+    assert res.binarised and ref.binarised and abs(res.steps - ref.steps) <= 2
+    assert np.array_equal(sel.cpu().numpy().astype(bool), ref.sel)
+    assert res.set_objective == pytest.approx(ref.set_objective, rel=1e-12)
+    if np.isinf(ref.stab):
+        assert np.isinf(res.stab)
+    else:
+        assert res.stab == pytest.approx(ref.stab, rel=1e-5)

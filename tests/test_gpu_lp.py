@@ -153,6 +153,18 @@ def test_warm_start_feeds_multi_start(gpu):
     assert out[best].set_objective > 0
 
 
+def test_one_vertex(gpu):
+    """n = 1 with its singleton clique: lam = c after one pass, x = 1, gap 0."""
+    import torch
+    libgn = _lib()
+    L = libgn.LP(1, np.array([0, 1]), np.array([0]), np.array([0.5], np.float32))
+    x = torch.empty(1, dtype=torch.float32, device="cuda")
+    st, res = L.solve(np.array([0.8], np.float32), np.zeros((1, 1), np.int32), x, check_every=1, gap_tol=1e-6)
+    assert st == libgn.GN_OK and res[0].passes == 1
+    assert float(x.cpu()[0]) == pytest.approx(1.0, rel=1e-6)
+    assert res[0].dual == pytest.approx(0.5, rel=1e-6)
+
+
 def test_solve_rejects_bad_arguments(gpu):
     import torch
     libgn = _lib()
