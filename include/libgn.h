@@ -541,6 +541,20 @@ gn_status gn_hyper_step(gn_hyper* h, float gamma, const float* x_in, float* x_ou
 gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
                          hipStream_t stream);
 
+/* gn_hyper_solve for `starts` (1..GN_MAX_STARTS) starting points at once, one
+ * launch per step pass for all of them (the batched starts of the paper's
+ * experiments, Section 6).  x: device float[starts*n], start-major, the
+ * starting points on entry and the final states on exit; sel: device
+ * uint8[starts*n]; res: host gn_result[starts].  Every start stops on its own
+ * and its result is that of gn_hyper_solve from the same point (the same
+ * arithmetic in the same order).  *best (host, may be NULL): the start with the
+ * largest set objective among the binarised ones (lowest index on ties; among
+ * all starts if none binarised).  Errors as gn_hyper_solve; any invalid start
+ * fails the call.  Returns GN_OK when every start binarised, else
+ * GN_NOT_CONVERGED.  SYNC. */
+gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t starts, float* x, uint8_t* sel,
+                               gn_result* res, int32_t* best, hipStream_t stream);
+
 /* Tuning: number of step launches captured in one replayed chain by gn_solve and
  * gn_rook_solve (default 32, 1..4096).  A longer chain checks the stop flag less
  * often from the host; results do not change.  Process-wide; not thread-safe. */

@@ -62,15 +62,22 @@ struct HArgs {
     const int32_t* emem;
     const int32_t* vptr;
     const int32_t* vedge;
-    float* Y;          // [m]
-    int32_t* cnt;      // [m] members with x > 1/2
-    float* vs;         // [m] sum of v over selected members (final statistics)
-    int32_t* viol;     // [max_steps + 1]
-    HState* st;
-    HPart* part;       // [max(nbv, nbe)]
-    int32_t n, m, nbv, nbe;
+    float* Y;          // [S][m]
+    int32_t* cnt;      // [S][m] members with x > 1/2
+    float* vs;         // [S][m] sum of v over selected members (final statistics)
+    int32_t* viol;     // [S][vstride], vstride = max_steps + 1
+    HState* st;        // [S]
+    HPart* part;       // [S][nparts]
+    int32_t n, m, nbv, nbe, nparts, vstride;
     int32_t check_every;
     float tau;
+};
+
+// Per start, by value: the buffer holding its final state (0 or 1) and gamma
+// of its final step.
+struct HFinal {
+    int32_t buf[GN_MAX_STARTS];
+    float gamma[GN_MAX_STARTS];
 };
 
 __device__ __forceinline__ float hwave_sum(float v) {
@@ -83,17 +90,20 @@ __device__ __forceinline__ int hwave_sum_i(int v) {
     return v;
 }
 
-// Hyperedge sums of y = v x and counts of members above 1/2.  In a solve
-// (solve = 1) the launch of step k first settles the check of step k - 1.
+// Hyperedge sums of y = v x and counts of members above 1/2 for start
+// blockIdx.y (states start-major, n apart).  In a solve (solve = 1) the launch
+// of step k first settles the start's check of step k - 1.
 __global__ __launch_bounds__(kHBlock) void hyper_edge_kernel(HArgs a, const float* x, int32_t k, int32_t solve) {
+    const int s = blockIdx.y;
     if (solve) {
-        if (a.st->done) return;
+        HState* st = a.st + s;
+        if (st->done) return;
         const int kp = k - 1;
-        if (kp >= 1 && kp % a.check_every == 0 && a.viol[kp] == 0) {
+        if (kp >= 1 && kp % a.check_every == 0 && a.viol[(size_t)s * a.vstride + kp] == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
-                a.st->step = kp;
-                a.st->binarised = 1;
-                a.st->done = 1;
+                st->step = kp;
+                st->binarised = 1;
+                st->done = 1;
             }
             return;
         }
@@ -102,6 +112,7 @@ __global__ __launch_bounds__(kHBlock) void hyper_edge_kernel(HArgs a, const floa
     const int lane = threadIdx.x & 63;
     const int e = blockIdx.x * kHWaves + wave;
     if (e >= a.m) return;
+    x += (size_t)s * a.n;
     float Y = 0.0f;
     int c = 0;
     for (int j = a.eptr[e] + lane; j < a.eptr[e + 1]; j += 64) {
@@ -113,73 +124,81 @@ __global__ __launch_bounds__(kHBlock) void hyper_edge_kernel(HArgs a, const floa
     Y = hwave_sum(Y);
     c = hwave_sum_i(c);
     if (lane == 0) {
-        a.Y[e] = Y;
-        a.cnt[e] = c;
+        a.Y[(size_t)s * a.m + e] = Y;
+        a.cnt[(size_t)s * a.m + e] = c;
     }
 }
 
 // x' from the hyperedge sums (write = 1), and in a solve at a check step the
-// stopping test on x (check = 1), counted into viol[k] once per workgroup.
+// stopping test on x (check = 1), counted into the start's viol[k] once per
+// workgroup.
 __global__ __launch_bounds__(kHVBlock) void hyper_vertex_kernel(HArgs a, const float* x, float* xo, float gamma,
                                                                int32_t k, int32_t solve, int32_t check,
                                                                int32_t write) {
-    if (solve && a.st->done) return;
+    const int s = blockIdx.y;
+    if (solve && a.st[s].done) return;
     const int i = blockIdx.x * kHVBlock + threadIdx.x;
+    const float* Ys = a.Y + (size_t)s * a.m;
+    const int32_t* cs = a.cnt + (size_t)s * a.m;
     bool bad = false, fb = false;
     if (i < a.n) {
-        const float xi = x[i];
+        const float xi = x[(size_t)s * a.n + i];
         const float vi = a.v[i];
         const float y = vi * xi;
         float nb = 0.0f;
         int cov = 0;
         for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) {
             const int e = a.vedge[q];
-            nb += a.Y[e] - y;
-            cov += a.cnt[e];
+            nb += Ys[e] - y;
+            cov += cs[e];
         }
-        const float s = gamma * nb + y;
+        const float sv = gamma * nb + y;
         if (write) {
             float xn;
-            if (s > kSafeDiv) {
-                xn = y / s;
+            if (sv > kSafeDiv) {
+                xn = y / sv;
                 if (y > 0.0f && xn < kXMin) xn = kXMin;
             } else {
                 xn = 0.5f;
                 fb = true;
             }
-            xo[i] = xn;
+            xo[(size_t)s * a.n + i] = xn;
         }
         if (check) {
             const float d = fminf(xi, 1.0f - xi);
             bad = d > a.tau;
             if (xi <= 0.5f) {
                 bad = bad || cov == 0;                        // uncovered
-                bad = bad || (xi > 0.0f && !(s > vi));         // growing
+                bad = bad || (xi > 0.0f && !(sv > vi));        // growing
             }
         }
     }
     if (solve && write) {
         const unsigned long long nf = __popcll(__ballot(fb));
-        if (nf && (threadIdx.x & 63) == 0) atomicAdd(&a.st->fallback, nf);
+        if (nf && (threadIdx.x & 63) == 0) atomicAdd(&a.st[s].fallback, nf);
     }
     if (check) {
-        if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicAdd(&a.viol[k], 1);
+        if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicAdd(&a.viol[(size_t)s * a.vstride + k], 1);
     }
 }
 
-// A solve that ran to max_steps: the check of x^max_steps decides.
+// A start that ran to max_steps: the check of x^max_steps decides.
 __global__ void hyper_resolve_kernel(HArgs a, int32_t max_steps, int32_t checked) {
-    if (a.st->done) return;
-    a.st->step = max_steps;
-    a.st->binarised = (checked && a.viol[max_steps] == 0) ? 1 : 0;
-    a.st->done = 1;
+    HState* st = a.st + blockIdx.x;
+    if (st->done) return;
+    st->step = max_steps;
+    st->binarised = (checked && a.viol[(size_t)blockIdx.x * a.vstride + max_steps] == 0) ? 1 : 0;
+    st->done = 1;
 }
 
 // Final statistics, part 1: per hyperedge the selected count and the sum of v
 // over its selected members; per workgroup the conflicts (pairs of selected
 // members, counted per hyperedge).
-__global__ __launch_bounds__(kHBlock) void hyper_stats_edge_kernel(HArgs a, const float* x) {
+__global__ __launch_bounds__(kHBlock) void hyper_stats_edge_kernel(HArgs a, const float* buf0, const float* buf1,
+                                                                  HFinal f) {
     __shared__ long long red[kHWaves];
+    const int s = blockIdx.y;
+    const float* x = (f.buf[s] ? buf1 : buf0) + (size_t)s * a.n;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int e = blockIdx.x * kHWaves + wave;
@@ -197,8 +216,8 @@ __global__ __launch_bounds__(kHBlock) void hyper_stats_edge_kernel(HArgs a, cons
         vs = hwave_sum(vs);
         c = hwave_sum_i(c);
         if (lane == 0) {
-            a.vs[e] = vs;
-            a.cnt[e] = c;
+            a.vs[(size_t)s * a.m + e] = vs;
+            a.cnt[(size_t)s * a.m + e] = c;
         }
         conf = (long long)c * (c - 1) / 2;
     }
@@ -207,7 +226,7 @@ __global__ __launch_bounds__(kHBlock) void hyper_stats_edge_kernel(HArgs a, cons
     if (threadIdx.x == 0) {
         long long t = 0;
         for (int q = 0; q < kHWaves; ++q) t += red[q];
-        a.part[blockIdx.x].conflicts = t;
+        a.part[(size_t)s * a.nparts + blockIdx.x].conflicts = t;
     }
 }
 
@@ -215,9 +234,14 @@ __global__ __launch_bounds__(kHBlock) void hyper_stats_edge_kernel(HArgs a, cons
 // objective, W(S), |S|, the uncovered vertices and the minimum stability term
 // gamma * sum_{e holds i} (sum of v over e's selected members) / v_i over i
 // outside S.  The conflicts of part 1 are kept in the same slot.
-__global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, const float* x, float* x_user,
-                                                                     uint8_t* sel, float gamma) {
+__global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, const float* buf0, const float* buf1,
+                                                                     HFinal f, float* x_user, uint8_t* sel) {
     __shared__ HPart red[kHVBlock / 64];
+    const int s = blockIdx.y;
+    const float* x = (f.buf[s] ? buf1 : buf0) + (size_t)s * a.n;
+    const float gamma = f.gamma[s];
+    const float* vss = a.vs + (size_t)s * a.m;
+    const int32_t* cs = a.cnt + (size_t)s * a.m;
     const int i = blockIdx.x * kHVBlock + threadIdx.x;
     double rel = 0.0, W = 0.0;
     long long sz = 0, unc = 0;
@@ -225,8 +249,8 @@ __global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, c
     if (i < a.n) {
         const float xc = fminf(fmaxf(x[i], 0.0f), 1.0f);
         const bool in = xc > 0.5f;
-        x_user[i] = xc;
-        sel[i] = in ? 1 : 0;
+        x_user[(size_t)s * a.n + i] = xc;
+        sel[(size_t)s * a.n + i] = in ? 1 : 0;
         const float wi = a.w[i];
         rel = (double)wi * (double)xc;
         if (in) {
@@ -237,8 +261,8 @@ __global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, c
             float t = 0.0f;
             for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) {
                 const int e = a.vedge[q];
-                cov += a.cnt[e];
-                t += a.vs[e];
+                cov += cs[e];
+                t += vss[e];
             }
             unc = cov == 0 ? 1 : 0;
             stab = gamma * t / a.v[i];
@@ -270,7 +294,7 @@ __global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, c
             t.uncovered += red[q].uncovered;
             t.stab = fminf(t.stab, red[q].stab);
         }
-        HPart& o = a.part[blockIdx.x];
+        HPart& o = a.part[(size_t)s * a.nparts + blockIdx.x];
         o.relaxed = t.relaxed;
         o.W = t.W;
         o.size = t.size;
@@ -279,14 +303,16 @@ __global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, c
     }
 }
 
-// Part 3: one workgroup reduces the partials in a fixed order into out.
+// Part 3: one workgroup per start reduces its partials in a fixed order.
 __global__ __launch_bounds__(256) void hyper_stats_finish_kernel(HArgs a, HPart* out) {
     __shared__ HPart red[256 / 64];
+    const int s = blockIdx.x;
+    const HPart* part = a.part + (size_t)s * a.nparts;
     HPart t{};
     t.stab = INFINITY;
     const int nb = max(a.nbv, a.nbe);
     for (int q = threadIdx.x; q < nb; q += 256) {
-        const HPart& p = a.part[q];
+        const HPart& p = part[q];
         if (q < a.nbv) {
             t.relaxed += p.relaxed;
             t.W += p.W;
@@ -317,7 +343,7 @@ __global__ __launch_bounds__(256) void hyper_stats_finish_kernel(HArgs a, HPart*
             r.conflicts += red[q].conflicts;
             r.stab = fminf(r.stab, red[q].stab);
         }
-        *out = r;
+        out[s] = r;
     }
 }
 
@@ -335,16 +361,16 @@ struct gn_hyper {
     int32_t* emem = nullptr;
     int32_t* vptr = nullptr;
     int32_t* vedge = nullptr;
-    float* Y = nullptr;
+    float* Y = nullptr;      // [GN_MAX_STARTS][m]
     int32_t* cnt = nullptr;
     float* vs = nullptr;
-    float* buf[2] = {nullptr, nullptr};
-    int32_t* viol = nullptr;
+    float* buf[2] = {nullptr, nullptr};  // [GN_MAX_STARTS][n] each
+    int32_t* viol = nullptr;             // [GN_MAX_STARTS][viol_cap]
     int32_t viol_cap = 0;
-    HState* st = nullptr;
-    HPart* part = nullptr;
-    HPart* out = nullptr;
-    void* host = nullptr;  // pinned: HState + HPart
+    HState* st = nullptr;                // [GN_MAX_STARTS]
+    HPart* part = nullptr;               // [GN_MAX_STARTS][nparts]
+    HPart* out = nullptr;                // [GN_MAX_STARTS]
+    void* host = nullptr;                // pinned: HState[GN_MAX_STARTS] + HPart[GN_MAX_STARTS]
 };
 
 static void hyper_free(gn_hyper* h) {
@@ -387,6 +413,8 @@ static HArgs hyper_args(gn_hyper* h) {
     a.m = h->m;
     a.nbv = hyper_nbv(h->n);
     a.nbe = hyper_nbe(h->m);
+    a.nparts = std::max(a.nbv, a.nbe);
+    a.vstride = h->viol_cap;
     a.check_every = 1;
     a.tau = 0.0f;
     return a;
@@ -415,13 +443,14 @@ extern "C" gn_status gn_hyper_create(int32_t n, int32_t m, const int32_t* edge_p
         for (int32_t j = edge_ptr[e]; j < edge_ptr[e + 1]; ++j) h->vedge_h[pos[members[j]]++] = e;
     h->v_h.resize(n);
     for (int32_t i = 0; i < n; ++i) h->v_h[i] = (float)std::sqrt((double)w[i]);
+    const size_t S = GN_MAX_STARTS;
     const size_t nparts = (size_t)std::max(hyper_nbv(n), hyper_nbe(m));
     bool ok = gn_dalloc(&h->v, n) && gn_dalloc(&h->w, n) && gn_dalloc(&h->eptr, (size_t)m + 1) &&
               gn_dalloc(&h->emem, (size_t)h->nnzc) && gn_dalloc(&h->vptr, (size_t)n + 1) &&
-              gn_dalloc(&h->vedge, (size_t)h->nnzc) && gn_dalloc(&h->Y, m) && gn_dalloc(&h->cnt, m) &&
-              gn_dalloc(&h->vs, m) && gn_dalloc(&h->buf[0], n) && gn_dalloc(&h->buf[1], n) &&
-              gn_dalloc(&h->st, 1) && gn_dalloc(&h->part, nparts) && gn_dalloc(&h->out, 1);
-    if (ok && hipHostMalloc(&h->host, sizeof(HState) + sizeof(HPart), hipHostMallocDefault) != hipSuccess) {
+              gn_dalloc(&h->vedge, (size_t)h->nnzc) && gn_dalloc(&h->Y, S * m) && gn_dalloc(&h->cnt, S * m) &&
+              gn_dalloc(&h->vs, S * m) && gn_dalloc(&h->buf[0], S * n) && gn_dalloc(&h->buf[1], S * n) &&
+              gn_dalloc(&h->st, S) && gn_dalloc(&h->part, S * nparts) && gn_dalloc(&h->out, S);
+    if (ok && hipHostMalloc(&h->host, S * (sizeof(HState) + sizeof(HPart)), hipHostMallocDefault) != hipSuccess) {
         h->host = nullptr;
         ok = false;
     }
@@ -466,83 +495,104 @@ extern "C" gn_status gn_hyper_step(gn_hyper* h, float gamma, const float* x_in, 
     return GN_OK;
 }
 
-extern "C" gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
-                                    hipStream_t stream) {
-    if (!h || !sch || !res || !x || !sel) return GN_E_ARG;
+extern "C" gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t starts, float* x, uint8_t* sel,
+                                          gn_result* res, int32_t* best, hipStream_t stream) {
+    if (!h || !sch || !res || !x || !sel || starts < 1 || starts > GN_MAX_STARTS) return GN_E_ARG;
     if (!gn_internal_schedule_ok(sch)) return GN_E_ARG;
-    std::memset(res, 0, sizeof(*res));
+    std::memset(res, 0, sizeof(gn_result) * starts);
     const int32_t n = h->n, ms = sch->max_steps;
-    // x^0: finite, >= 0 and normalizable (every closed neighbourhood has mass),
-    // checked on the host
-    std::vector<float> x0(n);
-    GN_HIP_TRY(hipMemcpyAsync(x0.data(), x, sizeof(float) * n, hipMemcpyDeviceToHost, stream));
+    // every x^0: finite, >= 0 and normalizable (every vertex has mass in its
+    // hyperedges), checked on the host
+    std::vector<float> x0((size_t)starts * n);
+    GN_HIP_TRY(hipMemcpyAsync(x0.data(), x, sizeof(float) * x0.size(), hipMemcpyDeviceToHost, stream));
     GN_HIP_TRY(hipStreamSynchronize(stream));
-    for (int32_t i = 0; i < n; ++i)
-        if (!(x0[i] >= 0.0f) || !std::isfinite(x0[i])) return GN_E_ARG;
-    std::vector<double> X(h->m, 0.0);
-    for (int32_t e = 0; e < h->m; ++e)
-        for (int32_t j = h->eptr_h[e]; j < h->eptr_h[e + 1]; ++j) X[e] += x0[h->emem_h[j]];
-    for (int32_t i = 0; i < n; ++i) {
-        double s = x0[i];
-        for (int32_t q = h->vptr_h[i]; q < h->vptr_h[i + 1]; ++q) s += X[h->vedge_h[q]] - x0[i];
-        if (!(s > 0.0)) return GN_E_NOT_NORMALIZABLE;
+    std::vector<double> X(h->m);
+    for (int32_t s = 0; s < starts; ++s) {
+        const float* xs = x0.data() + (size_t)s * n;
+        for (int32_t i = 0; i < n; ++i)
+            if (!(xs[i] >= 0.0f) || !std::isfinite(xs[i])) return GN_E_ARG;
+        std::fill(X.begin(), X.end(), 0.0);
+        for (int32_t e = 0; e < h->m; ++e)
+            for (int32_t j = h->eptr_h[e]; j < h->eptr_h[e + 1]; ++j) X[e] += xs[h->emem_h[j]];
+        for (int32_t i = 0; i < n; ++i) {
+            double sm = xs[i];
+            for (int32_t q = h->vptr_h[i]; q < h->vptr_h[i + 1]; ++q) sm += X[h->vedge_h[q]] - xs[i];
+            if (!(sm > 0.0)) return GN_E_NOT_NORMALIZABLE;
+        }
     }
     if (ms + 1 > h->viol_cap) {
         hipFree(h->viol);
         h->viol = nullptr;
         h->viol_cap = 0;
-        if (!gn_dalloc(&h->viol, (size_t)ms + 1)) return GN_E_NOMEM;
+        if (!gn_dalloc(&h->viol, (size_t)GN_MAX_STARTS * (ms + 1))) return GN_E_NOMEM;
         h->viol_cap = ms + 1;
     }
     HArgs a = hyper_args(h);
     a.check_every = sch->check_every;
     a.tau = sch->tau;
-    GN_HIP_TRY(hipMemsetAsync(h->viol, 0, sizeof(int32_t) * (ms + 1), stream));
-    GN_HIP_TRY(hipMemsetAsync(h->st, 0, sizeof(HState), stream));
-    GN_HIP_TRY(hipMemcpyAsync(h->buf[0], x, sizeof(float) * n, hipMemcpyDeviceToDevice, stream));
+    GN_HIP_TRY(hipMemsetAsync(h->viol, 0, sizeof(int32_t) * (size_t)starts * a.vstride, stream));
+    GN_HIP_TRY(hipMemsetAsync(h->st, 0, sizeof(HState) * starts, stream));
+    GN_HIP_TRY(hipMemcpyAsync(h->buf[0], x, sizeof(float) * (size_t)starts * n, hipMemcpyDeviceToDevice, stream));
     HState* hs = (HState*)h->host;
-    HPart* hp = (HPart*)((char*)h->host + sizeof(HState));
+    HPart* hp = (HPart*)((char*)h->host + GN_MAX_STARTS * sizeof(HState));
+    const dim3 ge(a.nbe, starts), gv(a.nbv, starts);
     bool done = false;
     for (int32_t k0 = 0; k0 < ms && !done; k0 += kHChain) {
         const int32_t k1 = std::min(ms, k0 + kHChain);
         for (int32_t k = k0; k < k1; ++k) {
             const float g = gn_internal_host_gamma(sch, k);
             const int32_t chk = k >= 1 && k % sch->check_every == 0;
-            hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, h->buf[k & 1], k, 1);
-            hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, h->buf[k & 1], h->buf[(k + 1) & 1], g, k, 1, chk,
-                                                                1);
+            hyper_edge_kernel<<<ge, kHBlock, 0, stream>>>(a, h->buf[k & 1], k, 1);
+            hyper_vertex_kernel<<<gv, kHVBlock, 0, stream>>>(a, h->buf[k & 1], h->buf[(k + 1) & 1], g, k, 1, chk, 1);
         }
         GN_HIP_TRY(hipGetLastError());
-        GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState), hipMemcpyDeviceToHost, stream));
+        GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState) * starts, hipMemcpyDeviceToHost, stream));
         GN_HIP_TRY(hipStreamSynchronize(stream));
-        done = hs->done != 0;
+        done = true;
+        for (int32_t s = 0; s < starts; ++s) done = done && hs[s].done != 0;
     }
     // the last check: a pending check of step ms - 1, then x^ms itself
-    hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, h->buf[ms & 1], ms, 1);
-    hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, h->buf[ms & 1], nullptr, gn_internal_host_gamma(sch, ms),
-                                                        ms, 1, ms >= 1 ? 1 : 0, 0);
-    hyper_resolve_kernel<<<1, 1, 0, stream>>>(a, ms, ms >= 1 ? 1 : 0);
+    hyper_edge_kernel<<<ge, kHBlock, 0, stream>>>(a, h->buf[ms & 1], ms, 1);
+    hyper_vertex_kernel<<<gv, kHVBlock, 0, stream>>>(a, h->buf[ms & 1], nullptr, gn_internal_host_gamma(sch, ms), ms,
+                                                     1, ms >= 1 ? 1 : 0, 0);
+    hyper_resolve_kernel<<<starts, 1, 0, stream>>>(a, ms, ms >= 1 ? 1 : 0);
     GN_HIP_TRY(hipGetLastError());
-    GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState) * starts, hipMemcpyDeviceToHost, stream));
     GN_HIP_TRY(hipStreamSynchronize(stream));
-    const int32_t steps = hs->step;
-    const float* xf = h->buf[steps & 1];
-    const float gf = gn_internal_host_gamma(sch, steps);
-    hyper_stats_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, xf);
-    hyper_stats_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, xf, x, sel, gf);
-    hyper_stats_finish_kernel<<<1, 256, 0, stream>>>(a, h->out);
+    HFinal f{};
+    for (int32_t s = 0; s < starts; ++s) {
+        f.buf[s] = hs[s].step & 1;
+        f.gamma[s] = gn_internal_host_gamma(sch, hs[s].step);
+    }
+    hyper_stats_edge_kernel<<<ge, kHBlock, 0, stream>>>(a, h->buf[0], h->buf[1], f);
+    hyper_stats_vertex_kernel<<<gv, kHVBlock, 0, stream>>>(a, h->buf[0], h->buf[1], f, x, sel);
+    hyper_stats_finish_kernel<<<starts, 256, 0, stream>>>(a, h->out);
     GN_HIP_TRY(hipGetLastError());
-    GN_HIP_TRY(hipMemcpyAsync(hp, h->out, sizeof(HPart), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipMemcpyAsync(hp, h->out, sizeof(HPart) * starts, hipMemcpyDeviceToHost, stream));
     GN_HIP_TRY(hipStreamSynchronize(stream));
-    res->steps = steps;
-    res->binarised = hs->binarised;
-    res->fallback_count = (int64_t)hs->fallback;
-    res->relaxed_objective = hp->relaxed;
-    res->set_objective = hp->W;
-    res->set_size = hp->size;
-    res->conflicts = hp->conflicts;
-    res->uncovered = hp->uncovered;
-    res->stab = hp->stab;
-    if (!std::isfinite(res->relaxed_objective)) return GN_E_NUMERIC;
-    return res->binarised ? GN_OK : GN_NOT_CONVERGED;
+    bool all = true;
+    int32_t b = -1, b_any = 0;
+    for (int32_t s = 0; s < starts; ++s) {
+        gn_result& r = res[s];
+        r.steps = hs[s].step;
+        r.binarised = hs[s].binarised;
+        r.fallback_count = (int64_t)hs[s].fallback;
+        r.relaxed_objective = hp[s].relaxed;
+        r.set_objective = hp[s].W;
+        r.set_size = hp[s].size;
+        r.conflicts = hp[s].conflicts;
+        r.uncovered = hp[s].uncovered;
+        r.stab = hp[s].stab;
+        if (!std::isfinite(r.relaxed_objective)) return GN_E_NUMERIC;
+        all = all && r.binarised;
+        if (r.binarised && (b < 0 || r.set_objective > res[b].set_objective)) b = s;
+        if (r.set_objective > res[b_any].set_objective) b_any = s;
+    }
+    if (best) *best = b >= 0 ? b : b_any;
+    return all ? GN_OK : GN_NOT_CONVERGED;
+}
+
+extern "C" gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
+                                    hipStream_t stream) {
+    return gn_hyper_multi_solve(h, sch, 1, x, sel, res, nullptr, stream);
 }

@@ -111,6 +111,8 @@ def lib():
             "gn_hyper_create": ([ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)],
                                 ctypes.c_int),
             "gn_hyper_destroy": ([_vp], None),
+            "gn_hyper_multi_solve": ([_vp, ctypes.POINTER(gn_schedule), ctypes.c_int32, _vp, _vp, _vp,
+                                      ctypes.POINTER(ctypes.c_int32), _vp], ctypes.c_int),
             "gn_hyper_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
             "gn_hyper_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
                                ctypes.c_int),
@@ -445,6 +447,18 @@ def gn_hyper_solve(h, schedule: gn_schedule, x, sel, stream=None) -> Result:
     return _result(res, st)
 
 
+def gn_hyper_multi_solve(h, schedule: gn_schedule, starts: int, x, sel, stream=None):
+    """x: CUDA float32 [starts * n] start-major (in: starting points, out: final
+    states); sel: CUDA uint8 [starts * n].  Returns (status, per-start results, best)."""
+    import torch
+    res = (gn_result * int(starts))()
+    best = ctypes.c_int32(-1)
+    st = lib().gn_hyper_multi_solve(h, ctypes.byref(schedule), int(starts), _dptr(x, torch.float32, "x"),
+                                    _dptr(sel, torch.uint8, "sel"), res, ctypes.byref(best), _stream(stream))
+    _check(st, "gn_hyper_multi_solve", allow=(GN_OK, GN_NOT_CONVERGED))
+    return st, [_result(res[b], st) for b in range(int(starts))], best.value
+
+
 class Hyper:
     """Owning wrapper of a gn_hyper handle (GN under hyperedge constraints)."""
 
@@ -463,6 +477,9 @@ class Hyper:
 
     def solve(self, x, sel, stream=None, **sched) -> Result:
         return gn_hyper_solve(self.handle, make_schedule(**sched), x, sel, stream)
+
+    def multi_solve(self, starts, x, sel, stream=None, **sched):
+        return gn_hyper_multi_solve(self.handle, make_schedule(**sched), starts, x, sel, stream)
 
 
 def gn_rook_create(rows, cols, w, stream=None):

@@ -155,3 +155,36 @@ def test_degenerate_instances(gpu, n, ptr, mem, w):
         assert np.isinf(res.stab)
     else:
         assert res.stab == pytest.approx(ref.stab, rel=1e-5)
+
+
+@pytest.mark.parametrize("case,starts", [("routes2000", 16), ("long500", 5)])
+def test_multi_solve_matches_single_starts(gpu, case, starts):
+    """Every start of a multi-start solve is the single-start solve from its
+    point: the oracle's set and W(S), steps within 2; best is the heaviest
+    binarised start."""
+    import torch
+    libgn = _lib()
+    n, ptr, mem = _cases()[case]
+    w = inputs.weights_uniform01(n, 7)
+    H = libgn.Hyper(n, ptr, mem, w)
+    u = 1.0 - inputs.rng_for(7, 23).random((starts, n))
+    e = -np.log(u)
+    x0 = np.clip(e / e.max(axis=1, keepdims=True), 1e-3, 1.0).astype(np.float32)
+    x = torch.from_numpy(x0.reshape(-1)).cuda()
+    sel = torch.zeros(starts * n, dtype=torch.uint8, device="cuda")
+    st, res, best = H.multi_solve(starts, x, sel, max_steps=3000)
+    s_all = sel.cpu().numpy().reshape(starts, n).astype(bool)
+    for b in range(starts):
+        ref = OH.solve(n, ptr, mem, w.astype(np.float64), x0[b].astype(np.float64), gamma0=float(np.float32(0.9)),
+                       max_steps=3000)
+        assert res[b].binarised == ref.binarised and abs(res[b].steps - ref.steps) <= 2
+        assert np.array_equal(s_all[b], ref.sel)
+        assert res[b].set_objective == pytest.approx(ref.set_objective, rel=1e-12)
+    objs = [r.set_objective if r.binarised else -1 for r in res]
+    assert best == int(np.argmax(objs))
+    # one start through the multi-start call equals the single-start call
+    x1 = torch.from_numpy(x0[3 % starts].copy()).cuda()
+    s1 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    r1 = H.solve(x1, s1, max_steps=3000)
+    assert r1.steps == res[3 % starts].steps and r1.set_objective == res[3 % starts].set_objective
+    assert np.array_equal(s1.cpu().numpy().astype(bool), s_all[3 % starts])
