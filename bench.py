@@ -341,6 +341,16 @@ def bench_lp(with_oracle=True):
                   "us_per_pass": lp_ms * 1e3 / max(passes), "gap_max": max(r.gap for r in res),
                   "best_bound": bound, "converged": int(sum(r.converged for r in res))},
            "gn_from_lp": gn_from(x), "gn_from_random": gn_from(xr)}
+    # the same LP points through the hyperedge form (the stops as hyperedges)
+    H = libgn.Hyper(inst.n, inst.ptr, inst.members, c)
+    xs = x.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, hres, hbest = libgn.gn_hyper_multi_solve(H.handle, sched, S, xs, sel)
+    out["hyper_gn_from_lp"] = {"best_set_objective": hres[hbest].set_objective,
+                               "best_over_lp_bound": hres[hbest].set_objective / bound,
+                               "binarised_independent": sum(1 for r in hres if r.binarised and r.conflicts == 0),
+                               "max_steps": max(r.steps for r in hres), "ms": (time.perf_counter() - t) * 1e3}
     if with_oracle:
         import oracle.lp as OL
         cl = OL.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
