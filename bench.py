@@ -364,7 +364,7 @@ def bench_lp(with_oracle=True):
     return out
 
 
-def bench_hyper(reps=3):
+def bench_hyper(reps=3, with_oracle=True):
     """GN under hyperedge constraints on two routes-and-stops instances (10,000
     routes, 3-8 stops each, over 2,000 stops and over 200 stops): gn_hyper_solve
     against gn_solve on the plain conflict graph, both from x0 = 1/2 with the
@@ -420,6 +420,18 @@ def bench_hyper(reps=3):
         out[name]["graph_16starts"] = {"ms": ms_mg, "best_set_objective": mg[1][mg[2]].set_objective,
                                        "max_steps": max(r.steps for r in mg[1]),
                                        "all_binarised": all(r.binarised for r in mg[1])}
+        if with_oracle and stops == 2000:
+            import oracle as O
+            from oracle import hyper as OH
+            rp, ci = OH.multigraph(inst.n, inst.ptr, inst.members)
+            t = time.perf_counter()
+            ores = O.solve(inst.n, rp, ci, w.astype(np.float64), np.full(inst.n, 0.5),
+                           **dict(sched, gamma0=float(np.float32(0.9))))
+            out[name]["oracle"] = {"ms": (time.perf_counter() - t) * 1e3, "steps": ores.steps, "cores": 1,
+                                   "set_objective": ores.set_objective,
+                                   "same_set_objective_as_gpu": abs(ores.set_objective - rh.set_objective)
+                                   <= 1e-9 * abs(ores.set_objective),
+                                   "note": "fp64 C oracle on the conflict multigraph, one host core"}
         del H, G
     return out
 
@@ -652,7 +664,7 @@ def main():
     if not a.no_lp:
         out["lp_warm_start"] = bench_lp(not a.no_cpu_baseline)
     if not a.no_hyper:
-        out["hyperedge_gn"] = bench_hyper()
+        out["hyperedge_gn"] = bench_hyper(with_oracle=not a.no_cpu_baseline)
     if not a.no_grad:
         out["differentiable"] = bench_grad()
 
