@@ -94,6 +94,10 @@ def _load():
         lib.orc_unrolled_vjp.argtypes = [ctypes.c_int32, _i32p, _i32p, _f64p, _f64p, ctypes.c_int32,
                                          _f64p, _f64p, _f64p, _f64p]
         lib.orc_unrolled_vjp.restype = None
+        lib.orc_set_x_floor.argtypes = [ctypes.c_double]
+        lib.orc_set_x_floor.restype = None
+        lib.orc_get_x_floor.argtypes = []
+        lib.orc_get_x_floor.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -119,6 +123,18 @@ def validate(n, row_ptr, col_idx, w) -> int:
     rp, ci = _csr(row_ptr, col_idx)
     return _load().orc_validate(n, int(np.asarray(row_ptr)[-1]) if n >= 0 else 0,
                                 _p(rp, _i32p), _p(ci, _i32p), _p(_f64(w), _f64p))
+
+
+def x_floor() -> float:
+    """The level at which a positive coordinate is held instead of underflowing
+    (fp64's smallest normal number, 2^-1022, unless a test moved it)."""
+    return _load().orc_get_x_floor()
+
+
+def set_x_floor(f: float) -> None:
+    """Move the support floor (tests only: they show that results do not depend on
+    it); a non-positive value restores 2^-1022."""
+    _load().orc_set_x_floor(float(f))
 
 
 def gamma(gamma0, gamma1, ramp, k) -> float:

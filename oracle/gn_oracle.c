@@ -12,6 +12,7 @@
  * B = I + gamma A.  Every loop below runs in CSR order, single-threaded, in
  * double precision; no blocking, fusion or reordering.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -30,13 +31,18 @@
  * a closed-neighbourhood sum at or below 1e-9 resets the node to 1/2. */
 static const double ORC_SAFE_DIV = 1e-9;
 static const double ORC_FALLBACK_X = 0.5;
-/* Support invariance (Section 2, property ii) in finite precision: a positive
- * state never becomes an exact zero.  Without this bound a decaying value
- * underflows to 0 and is then frozen forever (0 is a fixed point), so a vertex
- * that later should regrow (its neighbourhood lost the set) cannot, and the
- * iteration can stop on a set that is not gamma-stable.  2^-100 is exact in
- * fp32 and fp64 and far below every threshold of the method. */
-static const double ORC_X_MIN = 7.888609052210118e-31; /* 2^-100 */
+/* Support invariance (Section 2, property ii): a positive coordinate stays
+ * positive, since x'_i = y_i / s_i > 0 whenever y_i > 0.  fp64 breaks this only
+ * by underflow: a decaying value would reach an exact 0, which is a fixed point,
+ * and a vertex that later should regrow (its neighbourhood lost the set) could
+ * not.  So a positive x'_i below fp64's smallest normal number 2^-1022 is held
+ * at 2^-1022; above it the map is computed as written.  The level can be moved
+ * (orc_set_x_floor) only so that tests can show that results do not depend on
+ * it. */
+static double orc_x_floor = DBL_MIN; /* 2^-1022 */
+
+void orc_set_x_floor(double f) { orc_x_floor = f > 0.0 ? f : DBL_MIN; }
+double orc_get_x_floor(void) { return orc_x_floor; }
 
 /* ---------------------------------------------------------------------------
  * Problem statement checks (Section 2): A is the adjacency matrix of a simple
@@ -87,7 +93,7 @@ double orc_gamma(double gamma0, double gamma1, int32_t ramp, int64_t k) {
  * safe division of the code appendix):
  *     y_i = v_i x_i,  s_i = y_i + gamma * sum_{j in N(i)} y_j,
  *     x'_i = y_i / s_i   if s_i > 1e-9,   x'_i = 1/2 otherwise,
- * and a positive x'_i is kept >= 2^-100 (support invariance, see ORC_X_MIN).
+ * and a positive x'_i is kept >= 2^-1022 (support invariance, see orc_x_floor).
  * Returns how many nodes took the 1/2 fallback.  x and x_out may alias. */
 int64_t orc_step(int32_t n, const int32_t* rp, const int32_t* ci, const double* v,
                  double gamma, const double* x, double* x_out) {
@@ -100,7 +106,7 @@ int64_t orc_step(int32_t n, const int32_t* rp, const int32_t* ci, const double* 
         double s = gamma * nb + y[i];
         if (s > ORC_SAFE_DIV) {
             double xn = y[i] / s;
-            if (y[i] > 0.0 && xn < ORC_X_MIN) xn = ORC_X_MIN;
+            if (y[i] > 0.0 && xn < orc_x_floor) xn = orc_x_floor;
             x_out[i] = xn;
         } else {
             x_out[i] = ORC_FALLBACK_X;
@@ -315,7 +321,7 @@ int64_t orc_unrolled_forward(int32_t n, const int32_t* rp, const int32_t* ci, co
  *   dL/dy = gbar (/) s - (I + gamma A) t,   t = gbar (.) y (/) s^2
  * (I + gamma A is symmetric), dL/dx = v (.) dL/dy, dL/dv += x (.) dL/dy, and
  * dL/dw = dL/dv (/) (2 v) since v = sqrt(w).  Rows that took the 1/2 fallback
- * or sit at the 2^-100 bound are constant and pass no gradient.  gxT = dL/dx^T on input; outputs the
+ * or sit at the 2^-1022 floor are constant and pass no gradient.  gxT = dL/dx^T on input; outputs the
  * gradient through the dynamics only (gw, gx0). */
 void orc_unrolled_vjp(int32_t n, const int32_t* rp, const int32_t* ci, const double* w,
                       const double* gammas, int32_t T, const double* x0, const double* gxT,
@@ -340,7 +346,7 @@ void orc_unrolled_vjp(int32_t n, const int32_t* rp, const int32_t* ci, const dou
             double nb = 0.0;
             for (int64_t e = rp[i]; e < rp[i + 1]; ++e) nb += y[ci[e]];
             s[i] = g * nb + y[i];
-            if (s[i] > ORC_SAFE_DIV && !(y[i] > 0.0 && y[i] / s[i] < ORC_X_MIN)) {
+            if (s[i] > ORC_SAFE_DIV && !(y[i] > 0.0 && y[i] / s[i] < orc_x_floor)) {
                 a[i] = gbar[i] / s[i];
                 t[i] = gbar[i] * y[i] / (s[i] * s[i]);
             } else {

@@ -446,8 +446,9 @@ def test_batched_reference_is_per_graph():
 
 
 def test_support_invariance_over_long_runs():
-    """Section 2 property ii: supp(N(x)) = supp(x).  In finite precision positive states
-    are held at >= 2^-100 instead of underflowing to 0; exact zeros stay 0."""
+    """Section 2 property ii: supp(N(x)) = supp(x).  Positive states are computed at
+    their own magnitude far below any fp32 range and are held at fp64's smallest
+    normal number 2^-1022 only where fp64 would underflow; exact zeros stay 0."""
     g = I.erdos_renyi(300, 8 / 299, 21)
     w = I.weights_uniform01(300, 21).astype(np.float64)
     x = I.rng_for(21, 1).random(300) * 0.9 + 0.05
@@ -455,16 +456,64 @@ def test_support_invariance_over_long_runs():
     zeros = [i for i in range(300) if deg[i] > 0][:20:2]   # spaced out: each keeps positive neighbours
     x[zeros] = 0.0
     assert O.is_normalizable(300, g.row_ptr, g.col_idx, x) == O.OK
+    assert O.x_floor() == 2.0 ** -1022
     xs = O.unrolled_forward(300, g.row_ptr, g.col_idx, w, np.full(3000, 1.5), x)
     pos = np.setdiff1d(np.arange(300), zeros)
-    assert np.all(xs[:, pos] >= 2.0 ** -100)      # positives never underflow to 0
-    # zeros stay 0 as long as their closed-neighbourhood sum is above the 1e-9 reset
+    assert np.all(xs[:, pos] >= 2.0 ** -1022)     # positives never underflow to 0
+    assert np.any((xs[:, pos] > 0) & (xs[:, pos] < 2.0 ** -300))   # and are carried far below fp32's range
+    # a value above the floor is the quotient itself: x' = y / s exactly as fp64 rounds it
     v = np.sqrt(w)
     A = _sparse(g)
+    for k in (10, 200, 2999):
+        y = v * xs[k]
+        s_k = y + 1.5 * (A @ y)
+        q = y / s_k
+        above = (q >= 2.0 ** -1022) & (s_k > 1e-9)
+        np.testing.assert_array_equal(xs[k + 1, above], q[above])
+    # zeros stay 0 as long as their closed-neighbourhood sum is above the 1e-9 reset
     for k in range(3000):
         s_k = 1.5 * (A @ (v * xs[k]))
         live = [z for z in zeros if s_k[z] > 1e-9]
         assert np.all(xs[k + 1, live] == 0.0)
+
+
+def _floor_cases():
+    """Instances whose solves take vertices below 2^-300 and back (ER n = 1500,
+    seed 109; rook 16 x 16 and 48 x 48 with the test weights of those shapes)."""
+    er = I.erdos_renyi(1500, 6 / 1499, 109)
+    yield "er1500", er, I.weights_uniform01(1500, 109)
+    for N in (16, 48):
+        yield f"rook{N}", I.rook_rect(N, N), I.rook_weights_rect(N, N, 7 * N + N).reshape(-1)
+
+
+SCHED_RAMP = dict(gamma0=float(np.float32(0.9)), gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4)
+
+
+def test_result_does_not_depend_on_a_deep_floor():
+    """The support floor is where fp64 runs out (2^-1022), not a level chosen in the
+    method's range: holding positives at 2^-100 or 2^-300 changes steps (and on rook
+    48 x 48 the permutation), while moving the floor between 2^-1000, 2^-1010 and
+    2^-1022 changes neither the set nor, except on the rook instance that takes the
+    safe-division reset at the bottom of its range, the step count."""
+    steps = {}
+    try:
+        for name, g, w in _floor_cases():
+            w = w.astype(np.float64)
+            for f in (2.0 ** -100, 2.0 ** -1000, 2.0 ** -1010, 2.0 ** -1022):
+                O.set_x_floor(f)
+                r = O.solve(g.n, g.row_ptr, g.col_idx, w, np.full(g.n, 0.5), **SCHED_RAMP)
+                assert r.binarised and r.conflicts == 0 and r.uncovered == 0
+                steps[name, f] = (r.steps, r.sel.tobytes())
+    finally:
+        O.set_x_floor(0.0)
+    assert O.x_floor() == 2.0 ** -1022
+    for name in ("er1500", "rook16", "rook48"):
+        deep = [steps[name, f] for f in (2.0 ** -1000, 2.0 ** -1010, 2.0 ** -1022)]
+        assert all(d[1] == deep[-1][1] for d in deep)                 # same set
+        assert steps[name, 2.0 ** -100][0] != deep[-1][0]            # a 2^-100 floor is not the map
+    assert steps["er1500", 2.0 ** -1000][0] == steps["er1500", 2.0 ** -1022][0] == 1459
+    assert steps["rook16", 2.0 ** -1000][0] == steps["rook16", 2.0 ** -1022][0] == 402
+    assert steps["rook48", 2.0 ** -100][1] != steps["rook48", 2.0 ** -1022][1]   # another permutation
 
 
 def test_frozen_vertex_regrows_to_stable_set():
