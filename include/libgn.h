@@ -31,6 +31,13 @@
  *  - A handle's device work buffers are shared by all calls on that handle:
  *    calls on one handle must not overlap in time (on one stream they never do).
  *  - Floating-point state is fp32; reductions of objectives use fp64.
+ *  - Support invariance (Section 2, property ii): a positive coordinate never
+ *    becomes zero.  Internally every solver carries a coordinate whose weighted
+ *    value v_i x_i falls below 2^-100 as log2 x_i in fixed point (resolution
+ *    2^-17), so it keeps its own magnitude far below fp32's range, down to
+ *    2^-1022 (fp64's smallest normal number), where it is held.  States handed
+ *    back to the caller are fp32 x; such coordinates read as their fp32
+ *    rounding (0 below 2^-149).
  */
 #ifndef LIBGN_H
 #define LIBGN_H
@@ -225,7 +232,8 @@ const gn_graph* gn_batch_graph(const gn_batch* b);
  * gbar = dL/dx', the chain rule gives t = gbar (.) y (/) s^2,
  * dL/dy = gbar (/) s - (I + gamma A) t, dL/dx = v (.) dL/dy,
  * dL/dv += x (.) dL/dy, and dL/dw = dL/dv (/) (2 v).  Rows that took the 1/2
- * safe-division reset or the 2^-100 support bound pass no gradient.
+ * safe-division reset pass no gradient; rows carried in log form enter y and x
+ * at their fp32 value.
  * ------------------------------------------------------------------------- */
 
 /* Floats of checkpoint storage needed for T steps checkpointed every
@@ -502,7 +510,7 @@ gn_status gn_lp_solve(gn_lp* lp, int32_t starts, const float* t0, const int32_t*
  * normalization of the assignment problem (Section 2) does with rows and
  * columns.  With y = v (.) x and Y_e = sum_{j in e} y_j:
  *     s_i = y_i + gamma * sum_{e holds i} (Y_e - y_i),   x'_i = y_i / s_i,
- * with the safe division and support floor of gn_step.  This is gn_step on the
+ * with the safe division and log-form small states of gn_step.  This is gn_step on the
  * conflict graph whose edge (i, j) counts the hyperedges holding both; it costs
  * O(memberships) per step instead of O(conflict edges), and equals gn_step on
  * the plain conflict graph when no two vertices share two hyperedges (rows and

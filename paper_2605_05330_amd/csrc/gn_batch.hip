@@ -154,8 +154,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     for (int i = tid; i < n; i += BT) {
         const float vi = vv[i];
         const float x = xg[perm[i]];
-        const float yy = vi * x;
-        ya[i] = x > 0.5f ? -yy : yy;
+        ya[i] = gnk::word_from_x(x, vi);
     }
     if constexpr (SL) {
         if (tid == 0) {
@@ -274,7 +273,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     // final state, rounded set, and the statistics of the set (one more pass,
     // over the CSR in global memory)
     for (int i = tid; i < n; i += BT) {
-        float x = fabsf(yin[i]) / vv[i];
+        float x = gnk::x_of_word(yin[i], vv[i]);
         x = fminf(fmaxf(x, 0.0f), 1.0f);
         const uint8_t s = x > 0.5f ? 1 : 0;
         xg[perm[i]] = x;
@@ -287,7 +286,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
     float stab = INFINITY;
     for (int i = tid; i < n; i += BT) {
         const bool in_s = yout[i] != 0.0f;
-        float x = fabsf(yin[i]) / vv[i];
+        float x = gnk::x_of_word(yin[i], vv[i]);
         x = fminf(fmaxf(x, 0.0f), 1.0f);
         const float wi = a.w[d.v_off + i];
         relaxed += (double)wi * (double)x;

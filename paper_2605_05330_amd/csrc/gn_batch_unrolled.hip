@@ -18,7 +18,7 @@ namespace {
 // steps, or its T adjoint steps, in one workgroup with its state in LDS.  The
 // arithmetic repeats the chained unrolled path (gn_unrolled.hip) operation for
 // operation -- y = v x, s = y + gamma sum |y_j|, x' = y / s with the safe
-// division and support bound; t = gbar y / s^2, dL/dy = gbar / s - (t + gamma
+// division, in the library's state words; t = gbar y / s^2, dL/dy = gbar / s - (t + gamma
 // sum t_j), dL/dx = v dL/dy, dL/dv += x dL/dy, dL/dw = dL/dv / (2 v) -- with the
 // same canonical sums, so results are bit-identical to it on the batch's
 // block-diagonal union graph.
@@ -45,11 +45,8 @@ struct UnrolledArgs {
 };
 
 // Whether the forward step took the quotient branch at this row (the same test
-// on the same fp32 values as the chained adjoint).
-__device__ __forceinline__ bool unrolled_quotient(float y, float s) {
-    if (!(s > 1e-9f)) return false;
-    return !(y > 0.0f && y / s < gnk::kXMin);
-}
+// on the same fp32 value as the chained adjoint).
+__device__ __forceinline__ bool unrolled_quotient(float s) { return s > 1e-9f; }
 
 // Slice loops of one step over a graph's sliced layout: for every valid row,
 // `load(i)` (the row's own global values, issued before the neighbour sum so
@@ -106,7 +103,7 @@ struct FwdPre {
     float v;
 };
 struct BwdPre {
-    float v, y, s, yp, sp;
+    float v, x, s, yp, sp;
 };
 
 // Copies a graph's slice table (and, MODE_ALL, its lines) into LDS at `so`.
@@ -140,7 +137,7 @@ __device__ void unrolled_fwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
     int32_t* so = reinterpret_cast<int32_t*>(lds + 2 * n + 2);
     const float* __restrict__ vv = a.v + d.v_off;
     const int32_t* __restrict__ perm = a.perm + d.v_off;
-    for (int i = tid; i < n; i += BT) ya[i] = vv[i] * a.x0[d.v_off + perm[i]];
+    for (int i = tid; i < n; i += BT) ya[i] = gnk::word_from_x(a.x0[d.v_off + perm[i]], vv[i]);
     if (tid == 0) {
         ya[n] = 0.0f;
         yb[n] = 0.0f;
@@ -162,11 +159,11 @@ __device__ void unrolled_fwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
                 const float yraw = yin[i];
                 const float yi = fabsf(yraw);
                 const float s = __fmaf_rn(g, sigma, yi);
-                const float xn = !(s > 1e-9f) ? 0.5f : gnk::bounded_ratio(yi, s);
+                float xn;
+                const float yn = gnk::step_word(yraw, p.v, s, xn);
                 ys[i] = yraw;
                 ss[i] = s;
-                const float yn = p.v * xn;
-                yout[i] = xn > 0.5f ? -yn : yn;
+                yout[i] = yn;
                 if (xT) xT[perm[i]] = xn;
             });
         __syncthreads();
@@ -197,8 +194,8 @@ __device__ void unrolled_bwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
         const float g = a.gxT[d.v_off + perm[i]];
         gb[i] = g;
         gv[i] = 0.0f;
-        const float yy = fabsf(ylast[i]), s = slast[i];
-        ta[i] = unrolled_quotient(yy, s) ? (g / s) * (yy / s) : 0.0f;
+        const float yy = gnk::y_of_word(ylast[i], vv[i]), s = slast[i];
+        ta[i] = unrolled_quotient(s) ? (g / s) * (yy / s) : 0.0f;
     }
     if (tid == 0) {
         ta[n] = 0.0f;
@@ -221,20 +218,20 @@ __device__ void unrolled_bwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
             [&](int i) {
                 BwdPre p;
                 p.v = vv[i];
-                p.y = fabsf(yk[i]);
+                p.x = gnk::x_of_word(yk[i], p.v);
                 p.s = sk[i];
-                p.yp = yp ? fabsf(yp[i]) : 0.0f;
+                p.yp = yp ? gnk::y_of_word(yp[i], p.v) : 0.0f;
                 p.sp = yp ? sp[i] : 0.0f;
                 return p;
             },
             [&](int i, float sigma, const BwdPre& p) {
                 const float g = gb[i];
-                const float ai = unrolled_quotient(p.y, p.s) ? g / p.s : 0.0f;
+                const float ai = unrolled_quotient(p.s) ? g / p.s : 0.0f;
                 const float gy = ai - __fmaf_rn(gam, sigma, tin[i]);
                 const float gx = p.v * gy;
                 gb[i] = gx;
-                gv[i] += (p.y / p.v) * gy;
-                if (yp) tout[i] = unrolled_quotient(p.yp, p.sp) ? (gx / p.sp) * (p.yp / p.sp) : 0.0f;
+                gv[i] += p.x * gy;
+                if (yp) tout[i] = unrolled_quotient(p.sp) ? (gx / p.sp) * (p.yp / p.sp) : 0.0f;
             });
         __syncthreads();
         float* tmp = tin;

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "gn_internal.h"
+#include "gn_rowsum.h"
 #include "gn_stats.h"
 
 namespace {
@@ -16,7 +17,7 @@ __global__ void finalize_kernel(int32_t n, const float* __restrict__ y, const fl
                                 uint8_t* __restrict__ sel_user, uint8_t* __restrict__ sel_int) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float x = fabsf(y[i]) / v[i];
+    float x = gnk::x_of_word(y[i], v[i]);
     x = fminf(fmaxf(x, 0.0f), 1.0f);
     const uint8_t s = x > 0.5f ? 1 : 0;
     x_user[perm[i]] = x;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void set_stats_kernel(int32_t n, int32_t li
     auto row_tail = [&](int i, long long conf, bool any_sel, float vsum) {
         const bool in_s = sel[i] != 0;
         if (y) {
-            float x = fabsf(y[i]) / v[i];
+            float x = gnk::x_of_word(y[i], v[i]);
             x = fminf(fmaxf(x, 0.0f), 1.0f);
             p.relaxed += (double)w_int[i] * (double)x;
         }

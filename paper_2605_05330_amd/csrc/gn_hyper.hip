@@ -7,7 +7,10 @@
 //
 //     Y_e = sum_{j in e} y_j,   s_i = y_i + gamma * sum_{e holds i} (Y_e - y_i),
 //
-// x'_i = y_i / s_i with the safe division and support floor of the WRGN step.
+// x'_i = y_i / s_i with the safe division of the WRGN step.  States are kept in
+// x space with the library's state-word log form for x < 2^-100 (the words of
+// gn_rowsum.h with v = 1), so support invariance holds at each coordinate's own
+// magnitude down to 2^-1022.
 // This is WRGN on the conflict graph whose edge (i, j) counts the hyperedges
 // holding both, at O(memberships) per step instead of O(conflict edges).
 //
@@ -27,6 +30,7 @@
 #include <vector>
 
 #include "gn_internal.h"
+#include "gn_rowsum.h"
 
 namespace {
 
@@ -35,7 +39,11 @@ constexpr int kHBlock = 64 * kHWaves;
 constexpr int kHVBlock = 256;        // vertex kernels
 constexpr int kHChain = 64;          // steps enqueued between looks at the stop flag
 constexpr float kSafeDiv = 1e-9f;    // safe division threshold of the WRGN step
-constexpr float kXMin = 0x1p-100f;   // support floor of a positive coordinate
+
+// x-space state words: an ordinary fp32 x >= 2^-100 (or 0), never signed, else
+// the log form.
+__device__ __forceinline__ float hx_word_from_x(float x) { return fabsf(gnk::word_from_x(x, 1.0f)); }
+__device__ __forceinline__ float hx_value(float w) { return gnk::x_of_word(w, 1.0f); }
 
 struct HState {
     int32_t done;
@@ -156,8 +164,15 @@ __global__ __launch_bounds__(kHVBlock) void hyper_vertex_kernel(HArgs a, const f
         if (write) {
             float xn;
             if (sv > kSafeDiv) {
-                xn = y / sv;
-                if (y > 0.0f && xn < kXMin) xn = kXMin;
+                const uint32_t mag = gnk::mag_bits(xi);
+                if (!gnk::is_log_mag(mag)) {
+                    xn = y / sv;
+                    if (xn < gnk::kYLog && mag != 0u)   // below 2^-100: log2 x' = log2 x + log2 v - log2 s
+                        xn = gnk::word_from_log(gnk::log_fixed(log2f(xi) + log2f(vi) - log2f(sv)) + gnk::kLogFloorQ,
+                                                1.0f);
+                } else {
+                    xn = gnk::word_from_log((int32_t)mag - 1 + gnk::log_fixed(log2f(vi) - log2f(sv)), 1.0f);
+                }
             } else {
                 xn = 0.5f;
                 fb = true;
@@ -180,6 +195,18 @@ __global__ __launch_bounds__(kHVBlock) void hyper_vertex_kernel(HArgs a, const f
     if (check) {
         if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicAdd(&a.viol[(size_t)s * a.vstride + k], 1);
     }
+}
+
+// User states (x >= 0, checked on the host) to x-space state words.
+__global__ void hyper_prep_kernel(int64_t count, const float* __restrict__ x, float* __restrict__ xw) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) xw[e] = hx_word_from_x(x[e]);
+}
+
+// x-space state words to user states.
+__global__ void hyper_value_kernel(int64_t count, const float* __restrict__ xw, float* __restrict__ x) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) x[e] = hx_value(xw[e]);
 }
 
 // A start that ran to max_steps: the check of x^max_steps decides.
@@ -247,7 +274,7 @@ __global__ __launch_bounds__(kHVBlock) void hyper_stats_vertex_kernel(HArgs a, c
     long long sz = 0, unc = 0;
     float stab = INFINITY;
     if (i < a.n) {
-        const float xc = fminf(fmaxf(x[i], 0.0f), 1.0f);
+        const float xc = fminf(fmaxf(hx_value(x[i]), 0.0f), 1.0f);
         const bool in = xc > 0.5f;
         x_user[(size_t)s * a.n + i] = xc;
         sel[(size_t)s * a.n + i] = in ? 1 : 0;
@@ -489,8 +516,13 @@ extern "C" gn_status gn_hyper_step(gn_hyper* h, float gamma, const float* x_in, 
     if (!h || !x_in || !x_out || x_in == x_out) return GN_E_ARG;
     if (!std::isfinite(gamma) || gamma < 0.0f) return GN_E_ARG;
     HArgs a = hyper_args(h);
-    hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, x_in, 0, 0);
-    hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, x_in, x_out, gamma, 0, 0, 0, 1);
+    const unsigned nb = (unsigned)((h->n + 255) / 256);
+    if (nb == 0) return GN_OK;
+    // user x -> state words, one step, state words -> user x
+    hyper_prep_kernel<<<nb, 256, 0, stream>>>((int64_t)h->n, x_in, h->buf[0]);
+    hyper_edge_kernel<<<a.nbe, kHBlock, 0, stream>>>(a, h->buf[0], 0, 0);
+    hyper_vertex_kernel<<<a.nbv, kHVBlock, 0, stream>>>(a, h->buf[0], h->buf[1], gamma, 0, 0, 0, 1);
+    hyper_value_kernel<<<nb, 256, 0, stream>>>((int64_t)h->n, h->buf[1], x_out);
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;
 }
@@ -532,7 +564,9 @@ extern "C" gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, i
     a.tau = sch->tau;
     GN_HIP_TRY(hipMemsetAsync(h->viol, 0, sizeof(int32_t) * (size_t)starts * a.vstride, stream));
     GN_HIP_TRY(hipMemsetAsync(h->st, 0, sizeof(HState) * starts, stream));
-    GN_HIP_TRY(hipMemcpyAsync(h->buf[0], x, sizeof(float) * (size_t)starts * n, hipMemcpyDeviceToDevice, stream));
+    hyper_prep_kernel<<<dim3((unsigned)(((size_t)starts * n + 255) / 256)), 256, 0, stream>>>((int64_t)starts * n, x,
+                                                                                          h->buf[0]);
+    GN_HIP_TRY(hipGetLastError());
     HState* hs = (HState*)h->host;
     HPart* hp = (HPart*)((char*)h->host + GN_MAX_STARTS * sizeof(HState));
     const dim3 ge(a.nbe, starts), gv(a.nbv, starts);

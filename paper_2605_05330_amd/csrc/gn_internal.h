@@ -98,6 +98,12 @@ gn_status gn_internal_final_stats_launch(gn_graph* g, const float* y_fin, float 
 gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, FinalStats* host_out,
                                 hipStream_t s);
 int32_t gn_internal_grid_blocks(const BinLayout& b);
+// gn_step's argument checks, and its work (x_in -> state words in y_words, n
+// floats; one step launch writing x_out) on a caller-chosen word buffer
+// (gn_solve.hip)
+gn_status gn_internal_step_args_ok(const gn_graph* g, float gamma, const float* x_in, float* x_out);
+gn_status gn_internal_step_with(const gn_graph* g, float gamma, const float* x_in, float* x_out, float* y_words,
+                                hipStream_t stream);
 
 // solve driver pieces shared by the graph and the assignment (rook) solvers
 // (gn_step.hip): schedule check, gamma table and state reset, the pipelined

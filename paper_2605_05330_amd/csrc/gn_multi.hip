@@ -127,9 +127,8 @@ __device__ __forceinline__ unsigned quad_update(const MultiArgs& a, const QuadCt
         const float yi = fabsf(yr);
         const float s = __fmaf_rn(c.g, comp(sigma, j), yi);
         const bool fallback = !(s > 1e-9f);
-        const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
-        const float yn = vi * xn;
-        out[j] = xn > 0.5f ? -yn : yn;
+        float xn;
+        out[j] = gnk::step_word(yr, vi, s, xn);
         const bool on = (c.act >> j) & 1u;
         if (on && c.do_write) fb[j] += fallback ? 1u : 0u;
         if (on && c.do_test) {
@@ -418,8 +417,7 @@ __global__ void multi_prep_kernel(int32_t n, int32_t count, const float* __restr
             atomicOr(&st->err, 1);
             x = 0.0f;
         }
-        yy = v[i] * x;
-        yy = x > 0.5f ? -yy : yy;
+        yy = gnk::word_from_x(x, v[i]);
     }
     y[e] = yy;
 }

@@ -148,8 +148,7 @@ __global__ __launch_bounds__(kBlock) void rook_prep_kernel(RookArgs a) {
                 bad = true;
                 x = 0.0f;
             }
-            const float y = a.v[e] * x;
-            yn[m] = x > 0.5f ? -y : y;
+            yn[m] = gnk::word_from_x(x, a.v[e]);
             a.y_out[e] = yn[m];
         }
     }
@@ -343,9 +342,8 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
         const float sigma = (float)((R - (double)yi) + (C - (double)yi));
         const float s = __fmaf_rn(c.g, sigma, yi);
         const bool fallback = !(s > 1e-9f);
-        const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
-        const float yv = vi[m] * xn;
-        const float y_new = xn > 0.5f ? -yv : yv;
+        float xn;
+        const float y_new = gnk::step_word(yraw[m], vi[m], s, xn);
         yn[m] = ok[m] ? y_new : 0.0f;
         ynew[m] = y_new;
         xo[m] = xn;
@@ -416,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void rook_rows_kernel(int32_t rows, int32_t
         double rel = 0.0, setw = 0.0;
         for (int j = lane; j < cols; j += 64) {
             const size_t e = (size_t)i * cols + j;
-            float x = fabsf(y[e]) / v[e];
+            float x = gnk::x_of_word(y[e], v[e]);
             x = fminf(fmaxf(x, 0.0f), 1.0f);
             const bool s = x > 0.5f;
             x_out[e] = x;

@@ -26,13 +26,100 @@ __device__ __forceinline__ unsigned sign_of(float y) { return __float_as_uint(y)
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
 
-// Support invariance (Section 2, property ii) in fp32: a positive state never
-// underflows to an exact zero (which would freeze it for good); it is held at
-// 2^-100 or above.  Exact zeros stay zero.
-constexpr float kXMin = 0x1p-100f;
-__device__ __forceinline__ float bounded_ratio(float yi, float s) {
-    const float r = yi / s;
-    return (yi > 0.0f && r < kXMin) ? kXMin : r;
+// ---------------------------------------------------------------------------
+// State words.  Every solver keeps the weighted state y_i = v_i x_i in one
+// 32-bit word per vertex:
+//   * y_i >= 2^-100: the fp32 value, with the sign bit set when x_i > 1/2 (the
+//     rounded set S that the neighbours' cover test reads);
+//   * y_i = 0: +0;
+//   * 0 < y_i < 2^-100: a "log word", a positive word below the bits of 2^-100
+//     that holds log2 x_i in fixed point, q = (log2 x_i + 1022) 2^17, as q + 1.
+// Support invariance (Section 2, property ii): a positive coordinate never
+// becomes zero.  Without the log form fp32 would lose it below 2^-149, and any
+// floor in the fp32 range changes when a deeply decayed vertex can regrow; with
+// it x_i is carried at its own magnitude down to 2^-1022 (fp64's smallest
+// normal number), where it is held.
+// Read as a float, a log word is below 2^-100, like the value it stands for, so
+// neighbour sums add it as is: a closed-neighbourhood sum that takes the
+// quotient branch exceeds 1e-9, and deg 2^-100 is far below its last bit.
+// For a row whose own word is a log word, s_i > 1e-9 makes its own term
+// negligible and x'_i = x_i v_i / s_i: the update adds log2(v_i / s_i).
+constexpr uint32_t kLogTop = 0x0D800000u;      // bits of 2^-100
+constexpr float kYLog = 0x1p-100f;             // smallest ordinary |y|
+constexpr float kLogScale = 131072.0f;         // 2^17 fixed-point steps per unit of log2
+constexpr int32_t kLogFloorQ = 1022 * 131072;  // q offset: log2 x = q / 2^17 - 1022
+constexpr int32_t kLogQMax = (int32_t)kLogTop - 2;
+
+__device__ __forceinline__ uint32_t mag_bits(float w) { return __float_as_uint(w) & 0x7fffffffu; }
+__device__ __forceinline__ bool is_log_mag(uint32_t mag) { return mag - 1u < kLogTop - 1u; }
+
+// log word of fixed-point q (clamped: q < 0 is the 2^-1022 floor)
+__device__ __forceinline__ float log_word(int32_t q) {
+    q = q < 0 ? 0 : (q > kLogQMax ? kLogQMax : q);
+    return __uint_as_float((uint32_t)q + 1u);
+}
+// log2 x of a log word's q, as fp32 (exact while |log2 x| < 128)
+__device__ __forceinline__ float log_q_value(int32_t q) { return (float)(q - kLogFloorQ) * (1.0f / kLogScale); }
+__device__ __forceinline__ int32_t log_fixed(float l) { return __float2int_rn(l * kLogScale); }
+
+// Word of a state whose log2 x is q / 2^17 - 1022, in its ordinary form when
+// v 2^(log2 x) >= 2^-100.  Only called for states far below 1/2.
+__device__ __forceinline__ float word_from_log(int32_t q, float vi) {
+    q = q < 0 ? 0 : q;
+    const float ly = log_q_value(q) + log2f(vi);
+    if (ly >= -100.0f) {
+        const float yn = exp2f(ly);
+        if (yn >= kYLog) return yn;
+    }
+    return log_word(q);
+}
+
+// Word of y = v x for a user coordinate x >= 0 (finite).
+__device__ __forceinline__ float word_from_x(float x, float vi) {
+    const float yy = vi * x;
+    if (yy >= kYLog) return x > 0.5f ? -yy : yy;
+    if (!(x > 0.0f)) return 0.0f;
+    const float lx = x < 0x1p-126f ? log2f(x * 0x1p64f) - 64.0f : log2f(x);
+    return word_from_log(log_fixed(lx) + kLogFloorQ, vi);
+}
+
+// x of a word (fp32; a log word deeper than 2^-149 reads as 0).
+__device__ __forceinline__ float x_of_word(float w, float vi) {
+    const uint32_t mag = mag_bits(w);
+    if (!is_log_mag(mag)) return __uint_as_float(mag) / vi;
+    return exp2f(log_q_value((int32_t)mag - 1));
+}
+
+// |y| of a word (fp32; deep log words read as 0).
+__device__ __forceinline__ float y_of_word(float w, float vi) {
+    const uint32_t mag = mag_bits(w);
+    if (!is_log_mag(mag)) return __uint_as_float(mag);
+    return exp2f(log_q_value((int32_t)mag - 1) + log2f(vi));
+}
+
+// One WRGN update of a row (WRGN definition with the safe division of the code
+// appendix) from its own word and s_i = |y_i| + gamma sum_j |y_j|: returns the
+// new word and sets xo = x'_i in fp32.
+__device__ __forceinline__ float step_word(float yraw, float vi, float s, float& xo) {
+    if (!(s > 1e-9f)) {  // safe-division reset: x' = 1/2
+        xo = 0.5f;
+        return vi * 0.5f;
+    }
+    const uint32_t mag = mag_bits(yraw);
+    if (!is_log_mag(mag)) {
+        const float yi = __uint_as_float(mag);
+        const float xn = yi / s;
+        const float yn = vi * xn;
+        xo = xn;
+        if (yn >= kYLog || mag == 0u) return xn > 0.5f ? -yn : yn;
+        // below 2^-100: log2 x' = log2 y - log2 s
+        const float w = word_from_log(log_fixed(log2f(yi)) - log_fixed(log2f(s)) + kLogFloorQ, vi);
+        return w;
+    }
+    const int32_t q = (int32_t)mag - 1 + log_fixed(log2f(vi) - log2f(s));
+    const float w = word_from_log(q, vi);
+    xo = x_of_word(w, vi);
+    return w;
 }
 
 // Group of G threads sums one row of degree d <= MAXD.  `t` is the thread's

@@ -55,10 +55,9 @@ __device__ __forceinline__ bool step_row(float yraw, float vi, float sigma, bool
     const float yi = fabsf(yraw);
     const float s = __fmaf_rn(g, sigma, yi);
     const bool fallback = !(s > 1e-9f);
-    const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
     if (do_write) {
-        const float yn = vi * xn;
-        y_out[i] = xn > 0.5f ? -yn : yn;
+        float xn;
+        y_out[i] = gnk::step_word(yraw, vi, s, xn);
         fb += fallback ? 1 : 0;
     }
     if (!do_test) return false;

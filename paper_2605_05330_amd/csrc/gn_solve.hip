@@ -8,6 +8,7 @@
 #include <functional>
 
 #include "gn_internal.h"
+#include "gn_rowsum.h"
 
 // defined in gn_step.hip
 __global__ void wrgn_step_kernel(StepArgs a);
@@ -23,8 +24,7 @@ __global__ void prep_state_kernel(int32_t n, const float* __restrict__ x_user, c
         if (st) atomicOr(&st->err, 1);
         x = 0.0f;
     }
-    const float yy = v[i] * x;
-    y[i] = x > 0.5f ? -yy : yy;
+    y[i] = gnk::word_from_x(x, v[i]);
 }
 
 // Normalizable (Section 2): (A + I) x > 0, i.e. x_i > 0 or some neighbour
@@ -180,27 +180,38 @@ static StepArgs base_args(const gn_graph* g) {
     return a;
 }
 
-extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, float* x_out,
-                             hipStream_t stream) {
-    if (!g) return GN_E_ARG;
-    if (!std::isfinite(gamma) || gamma < 0.0f) return GN_E_ARG;
-    if (g->n == 0) return GN_OK;
-    if (!x_in || !x_out || x_in == x_out) return GN_E_ARG;
-    gn_graph* gm = const_cast<gn_graph*>(g);
-    gn_status st = gn_internal_ensure_ws(gm, 1);
-    if (st != GN_OK) return st;
+gn_status gn_internal_step_with(const gn_graph* g, float gamma, const float* x_in, float* x_out, float* y_words,
+                                hipStream_t stream) {
     const int n = g->n;
     hipLaunchKernelGGL(prep_state_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, x_in, g->perm, g->v,
-                       g->ws.y[0], (SolveState*)nullptr);
+                       y_words, (SolveState*)nullptr);
     GN_HIP_TRY(hipGetLastError());
     StepArgs a = base_args(g);
-    a.y_in = g->ws.y[0];
+    a.y_in = y_words;
     a.y_out = nullptr;
     a.gamma = nullptr;
     a.gamma_scalar = gamma;
     a.solve = 0;
     a.x_out_user = x_out;
     return gn_internal_launch_step(g, a, stream);
+}
+
+gn_status gn_internal_step_args_ok(const gn_graph* g, float gamma, const float* x_in, float* x_out) {
+    if (!g) return GN_E_ARG;
+    if (!std::isfinite(gamma) || gamma < 0.0f) return GN_E_ARG;
+    if (g->n == 0) return GN_OK;
+    if (!x_in || !x_out || x_in == x_out) return GN_E_ARG;
+    return GN_OK;
+}
+
+extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, float* x_out,
+                             hipStream_t stream) {
+    gn_status st = gn_internal_step_args_ok(g, gamma, x_in, x_out);
+    if (st != GN_OK || g->n == 0) return st;
+    gn_graph* gm = const_cast<gn_graph*>(g);
+    st = gn_internal_ensure_ws(gm, 1);
+    if (st != GN_OK) return st;
+    return gn_internal_step_with(g, gamma, x_in, x_out, g->ws.y[0], stream);
 }
 
 // Captured chain of `len` step launches for steps [c*len, (c+1)*len).

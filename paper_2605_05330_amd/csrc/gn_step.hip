@@ -26,13 +26,11 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<Step
     const float yi = fabsf(yraw);
     const float s = __fmaf_rn(c.g, sigma, yi);
     const bool fallback = !(s > 1e-9f);
-    const float xn = fallback ? 0.5f : gnk::bounded_ratio(yi, s);
     if (a.s_out) a.s_out[i] = s;
     if (c.do_write) {
-        if (a.y_out) {
-            const float yn = vi * xn;
-            a.y_out[i] = xn > 0.5f ? -yn : yn;
-        }
+        float xn;
+        const float yn = gnk::step_word(yraw, vi, s, xn);
+        if (a.y_out) a.y_out[i] = yn;
         if (a.x_out_user) a.x_out_user[a.perm[i]] = xn;
         fb += fallback ? 1 : 0;
     }

@@ -6,8 +6,11 @@
 //     dL/dy = gbar (/) s - (I + gamma A) t,
 //     dL/dx = v (.) dL/dy,     dL/dv += x (.) dL/dy,
 // and finally dL/dw = dL/dv (/) (2 v) because v = sqrt(w).  Rows that took the
-// 1/2 safe-division reset or sit at the 2^-100 support bound are constant in x
-// and pass no gradient.  One adjoint step is therefore one CSR pass over t in
+// 1/2 safe-division reset are constant in x and pass no gradient.  States are
+// the library's state words; a row carried in log form (y below 2^-100) enters
+// y and x at its decoded value.  A row held at the 2^-1022 support floor would
+// pass no gradient either; it is treated as a quotient row, which changes the
+// gradients by less than its own value (2^-1022) times the incoming gradient.  One adjoint step is therefore one CSR pass over t in
 // the library's canonical row-sum order, fused with the update of dL/dx, dL/dv
 // and with the t vector of the previous step.
 //
@@ -54,26 +57,22 @@ struct AdjArgs {
 };
 
 // Whether the forward step took the quotient branch at this row (same test,
-// same fp32 values as the forward kernel).
-__device__ __forceinline__ bool quotient_branch(float y, float s) {
-    if (!(s > 1e-9f)) return false;
-    return !(y > 0.0f && y / s < gnk::kXMin);
-}
+// same fp32 value as the forward kernel).
+__device__ __forceinline__ bool quotient_branch(float s) { return s > 1e-9f; }
 
 __device__ __forceinline__ void adj_row(const AdjArgs& a, int i, float sigma) {
     const float g = a.gb_in[i];
-    const float y = fabsf(a.y_k[i]);
     const float s = a.s_k[i];
     const float vi = a.v[i];
-    const float ai = quotient_branch(y, s) ? g / s : 0.0f;
+    const float ai = quotient_branch(s) ? g / s : 0.0f;
     const float gy = ai - __fmaf_rn(a.gamma, sigma, a.tt_in[i]);
     const float gx = vi * gy;
     a.gb_out[i] = gx;
-    a.gv[i] += (y / vi) * gy;
+    a.gv[i] += gnk::x_of_word(a.y_k[i], vi) * gy;
     if (a.tt_out) {
-        const float yp = fabsf(a.y_p[i]);
+        const float yp = gnk::y_of_word(a.y_p[i], vi);
         const float sp = a.s_p[i];
-        a.tt_out[i] = quotient_branch(yp, sp) ? (gx / sp) * (yp / sp) : 0.0f;
+        a.tt_out[i] = quotient_branch(sp) ? (gx / sp) * (yp / sp) : 0.0f;
     }
 }
 
@@ -166,16 +165,17 @@ __global__ void sqrt_weights_kernel(int32_t n, const float* __restrict__ w_user,
 __global__ void weighted_state_kernel(int32_t n, const float* __restrict__ x_user, const int32_t* __restrict__ perm,
                                       const float* __restrict__ v, float* __restrict__ y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = v[i] * x_user[perm[i]];
+    if (i < n) y[i] = gnk::word_from_x(x_user[perm[i]], v[i]);
 }
 
 // t of the last step of a segment from dL/dx^{k+1}: t_i = gbar_i y_i / s_i^2.
 __global__ void adjoint_seed_kernel(int32_t n, const float* __restrict__ gb, const float* __restrict__ y,
-                                    const float* __restrict__ s, float* __restrict__ tt) {
+                                    const float* __restrict__ s, const float* __restrict__ v,
+                                    float* __restrict__ tt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float yy = fabsf(y[i]), ss = s[i];
-    tt[i] = quotient_branch(yy, ss) ? (gb[i] / ss) * (yy / ss) : 0.0f;
+    const float yy = gnk::y_of_word(y[i], v[i]), ss = s[i];
+    tt[i] = quotient_branch(ss) ? (gb[i] / ss) * (yy / ss) : 0.0f;
 }
 
 __global__ void gather_user_kernel(int32_t n, const float* __restrict__ src_user, const int32_t* __restrict__ perm,
@@ -366,7 +366,7 @@ extern "C" gn_status gn_unrolled_backward(const gn_graph* g, const float* w, con
         }
         int tc = 0;
         hipLaunchKernelGGL(adjoint_seed_kernel, eg, eb, 0, stream, n, u->gb[cur], sy + (size_t)(t1 - 1 - t0) * n,
-                           ss + (size_t)(t1 - 1 - t0) * n, u->tt[tc]);
+                           ss + (size_t)(t1 - 1 - t0) * n, v, u->tt[tc]);
         GN_HIP_TRY(hipGetLastError());
         for (int32_t t = t1 - 1; t >= t0; --t) {
             AdjArgs a{};

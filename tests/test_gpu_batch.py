@@ -85,6 +85,7 @@ def test_batch_vs_oracle(gpu):
         assert abs(r.steps - ref.steps) <= 2, (g.n, r.steps, ref.steps)
         assert np.array_equal(sb[off:off + g.n].astype(bool), ref.sel)
         assert r.set_objective == pytest.approx(ref.set_objective, rel=1e-12)
+        assert r.stab == pytest.approx(ref.stab, rel=1e-5)
         off += g.n
 
 
@@ -151,25 +152,33 @@ def test_batch_union_graph_matches(gpu):
 
 def test_batch_full_4096(gpu):
     """4,096 graphs, n log-uniform in [50, 5000], half ER (degree 6), half unit-disk
-    (degree 10): every graph binarises to an independent, maximal set; 24 sampled
-    graphs match the oracle's set."""
+    (degree 10): every graph ends on an independent set; every graph but the few
+    that the plain map does not binarise within 2,000 steps binarises to a maximal
+    one (those few are checked against the oracle: same verdict, same state
+    rounding); 24 sampled graphs match the oracle's set and steps."""
     import torch
     lg = _lg()
     gs, ws = I.batch_workload(4096, seed=0)
     B = lg.Batch.from_graphs(gs, ws)
     B.autotune(**SCHED)
     st, res, xb, sb = _run_batch(B, gs)
-    assert st == lg.GN_OK
-    assert all(r.binarised and r.conflicts == 0 and r.uncovered == 0 for r in res)
     offs = np.concatenate([[0], np.cumsum([g.n for g in gs])])
+    assert all(r.conflicts == 0 for r in res)
+    open_ = [i for i, r in enumerate(res) if not r.binarised]
+    assert st == (lg.GN_NOT_CONVERGED if open_ else lg.GN_OK)
+    assert len(open_) <= 4, open_
+    assert all(r.uncovered == 0 for i, r in enumerate(res) if r.binarised)
     rng = I.rng_for(0, 99)
-    for gi in rng.choice(4096, 24, replace=False):
+    check = sorted(set(rng.choice(4096, 24, replace=False).tolist()) | set(open_))
+    for gi in check:
         g, w = gs[gi], ws[gi]
         ref = O.solve(g.n, g.row_ptr, g.col_idx, w.astype(np.float64), np.full(g.n, 0.5),
                       gamma0=float(F32(0.9)), gamma1=1.5, ramp_steps=1000, max_steps=2000,
                       tau=float(F32(1e-4)))
+        assert res[gi].binarised == ref.binarised, gi
         assert np.array_equal(sb[offs[gi]:offs[gi + 1]].astype(bool), ref.sel), gi
         assert abs(res[gi].steps - ref.steps) <= 2
+        assert res[gi].stab == pytest.approx(ref.stab, rel=1e-5)
 
 
 def test_batch_graph_reuse(gpu):
