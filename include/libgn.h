@@ -65,7 +65,8 @@ typedef enum {
     GN_E_NOT_NORMALIZABLE = -6,  /* x0 has a closed neighbourhood of zero mass            */
     GN_E_NUMERIC = -7,           /* non-finite value produced                             */
     GN_E_HIP = -8,               /* a HIP runtime call failed                             */
-    GN_E_NOMEM = -9              /* device or host allocation failed                      */
+    GN_E_NOMEM = -9,             /* device or host allocation failed                      */
+    GN_E_SIZE = -10              /* input larger than a fixed-capacity entry point allows */
 } gn_status;
 
 /* flags of gn_graph_create / gn_batch_create */
@@ -137,6 +138,18 @@ gn_status gn_graph_info(const gn_graph* g, int32_t* n, int64_t* nnz, int32_t* ma
  * alias (GN_E_ARG).  x_in must be finite and >= 0; vertices whose closed
  * neighbourhood sum is <= 1e-9 take x = 1/2.  ASYNC. */
 gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, float* x_out, hipStream_t stream);
+
+/* gn_step for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step, bit for bit, but its work buffer (the n state words gn_step keeps in
+ * the graph's workspace) is a static device array of gn_step_static_max_n()
+ * words that each GPU holds until the process ends; the call allocates nothing
+ * and frees nothing.  The graph must have been created on the current device
+ * (GN_E_ARG otherwise); n above the capacity gives GN_E_SIZE.  All calls on one
+ * GPU share its array: calls that overlap in time on one GPU (several streams
+ * or threads) race on it and must be serialised by the caller.  ASYNC. */
+gn_status gn_step_static(const gn_graph* g, float gamma, const float* x_in, float* x_out, hipStream_t stream);
+int32_t gn_step_static_max_n(void);
 
 /* Iterate WRGN from x to binarisation under `sch`.  x: device float[n], x^0 on
  * entry and the final state on exit (clamped to [0,1]); sel: device uint8[n],

@@ -20,6 +20,7 @@ extern "C" const char* gn_status_str(gn_status s) {
         case GN_E_NUMERIC: return "GN_E_NUMERIC: non-finite value";
         case GN_E_HIP: return "GN_E_HIP: HIP runtime error";
         case GN_E_NOMEM: return "GN_E_NOMEM: allocation failed";
+        case GN_E_SIZE: return "GN_E_SIZE: input larger than this entry point's fixed capacity";
     }
     return "unknown gn_status";
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libgn.so")
 
 GN_OK, GN_NOT_CONVERGED = 0, 1
 GN_E_ARG, GN_E_CSR, GN_E_SELF_LOOP, GN_E_ASYMMETRIC, GN_E_WEIGHT = -1, -2, -3, -4, -5
-GN_E_NOT_NORMALIZABLE, GN_E_NUMERIC, GN_E_HIP, GN_E_NOMEM = -6, -7, -8, -9
+GN_E_NOT_NORMALIZABLE, GN_E_NUMERIC, GN_E_HIP, GN_E_NOMEM, GN_E_SIZE = -6, -7, -8, -9, -10
 GN_INPUT_HOST, GN_INPUT_DEVICE, GN_NO_VALIDATE = 0, 1, 2
 GN_NUM_BINS = 7
 
@@ -79,6 +79,8 @@ def lib():
             "gn_graph_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "gn_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
+            "gn_step_static": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
+            "gn_step_static_max_n": ([], ctypes.c_int32),
             "gn_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
                          ctypes.c_int),
             "gn_objective": ([_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp], ctypes.c_int),
@@ -225,6 +227,18 @@ def gn_step(h, gamma, x_in, x_out, stream=None):
     import torch
     _check(lib().gn_step(h, float(gamma), _dptr(x_in, torch.float32, "x_in"), _dptr(x_out, torch.float32, "x_out"),
                          _stream(stream)), "gn_step")
+
+
+def gn_step_static(h, gamma, x_in, x_out, stream=None):
+    """gn_step with its work buffer in the library's static device array (no
+    allocation; calls on one GPU must not overlap)."""
+    import torch
+    _check(lib().gn_step_static(h, float(gamma), _dptr(x_in, torch.float32, "x_in"),
+                                _dptr(x_out, torch.float32, "x_out"), _stream(stream)), "gn_step_static")
+
+
+def gn_step_static_max_n() -> int:
+    return int(lib().gn_step_static_max_n())
 
 
 def make_schedule(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000, tau=1e-4, check_every=1) -> gn_schedule:
