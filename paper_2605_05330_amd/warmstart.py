@@ -5,7 +5,7 @@ features, trained on the sets that GN itself reaches.
 Protocol (measured on held-out unit-disk graphs of 100,000 vertices): the start
 keeps only the network's confident vertices (gate 0.49: p < 0.01 or p > 0.99),
 every other vertex starts at the neutral 1/2 of plain GN, and GN then runs a
-400-step gamma ramp 0.9 -> 1.5 instead of the paper's 1000 steps.
+300-step gamma ramp 0.9 -> 1.5 instead of the paper's 1000 steps.
 
 Every computation runs in libgn (gn_mpnn_forward / gn_mpnn_backward /
 gn_adam_step / gn_solve); this module holds parameters and drives the loop.
@@ -103,8 +103,8 @@ def gn_labels(graph: "libgn.Graph", schedule: dict, starts: int = 1, seed: int =
 
 
 GATE = 0.49
-WARM_SCHEDULE = dict(gamma0=0.9, gamma1=1.5, ramp_steps=400, max_steps=3000, tau=1e-4, check_every=1)
-PLAIN_SCHEDULE = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=3000, tau=1e-4, check_every=1)
+WARM_SCHEDULE = dict(gamma0=0.9, gamma1=1.5, ramp_steps=300, max_steps=4000, tau=1e-4, check_every=1)
+PLAIN_SCHEDULE = dict(gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=4000, tau=1e-4, check_every=1)
 
 
 def warm_solve(net: WarmStart, graph: "libgn.Graph", sel: torch.Tensor, gate: float = GATE, schedule=None):

@@ -147,44 +147,73 @@ def test_gated_forward_vs_oracle(gpu):
     assert np.max(np.abs(xg[keep] - xr[keep])) <= 1e-2
 
 
+def _timed_solve(fn, reps=3):
+    import time
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    return r, best
+
+
 def test_trained_warm_start_gains_over_plain_gn(gpu):
-    """What the trained network gains (unit-disk graphs, mean degree 10, w ~ U(0,1]):
-    trained on GN's own sets of 24 graphs (n in [10k, 40k]), then on 4 held-out
-    graphs of 40,000 vertices the gated warm start with a 400-step gamma ramp
-    reaches binarisation in fewer steps on average than plain GN (x0 = 1/2, the
-    paper's 1000-step ramp) at a mean objective within 0.1% of it, and a better
-    objective than plain GN with the same 400-step ramp."""
+    """What the trained network gains, at equal objective, on the learned-warm-start
+    workload (unit-disk graphs, mean degree 10, w ~ U(0,1]).  The network is
+    trained on the GPU on GN's own sets of 96 graphs (n log-uniform in
+    [10k, 100k]); on the 32 held-out graphs of 100,000 vertices plain GN (x0 = 1/2)
+    runs gamma ramps of 400 .. 1000 steps, and T* is the shortest ramp that
+    binarises every graph with a worst-graph objective gap of at most 0.1% to the
+    paper's 1000-step ramp.  The gated warm start (300-step ramp), network
+    inference included, must binarise every graph within that 0.1% too, in less
+    total time than plain GN at T*."""
     import torch
     from paper_2605_05330_amd import libgn, warmstart as WS
-    ns = I.batch_sizes_loguniform(24, 10_000, 40_000, 321)
+    ns = I.batch_sizes_loguniform(96, 10_000, 100_000, 123)
     graphs, labels = [], []
     for k, n in enumerate(ns):
-        g = I.unit_disk(int(n), 10, 2000 + k)
-        G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 2000 + k))
+        g = I.unit_disk(int(n), 10, 1000 + k)
+        G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 1000 + k))
         graphs.append(G)
         labels.append(WS.gn_labels(G, WS.PLAIN_SCHEDULE)[0])
     net = WS.WarmStart(seed=0)
-    WS.train(net, graphs, labels, 1500, lr=3e-3)
-    WS.train(net, graphs, labels, 500, lr=1e-3)
-    steps_p, steps_w, W_p, W_w, W_p400 = [], [], [], [], []
-    for e in range(4):
-        g = I.unit_disk(40_000, 10, 8000 + e)
-        G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 8000 + e))
+    WS.train(net, graphs, labels, 2000, lr=3e-3)
+    WS.train(net, graphs, labels, 1000, lr=1e-3)
+    del graphs, labels
+    ramps = (400, 500, 600, 800, 1000)
+    W = {T: [] for T in ramps}
+    done = {T: True for T in ramps}
+    t_plain = {T: 0.0 for T in ramps}
+    W_warm, t_warm, steps_warm = [], 0.0, []
+    for e in range(32):
+        g = I.unit_disk(100_000, 10, 9000 + e)
+        G = libgn.Graph(g.n, g.row_ptr, g.col_idx, I.weights_uniform01(g.n, 9000 + e))
         sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
-        rp = G.solve(torch.full((g.n,), 0.5, device="cuda"), sel, **WS.PLAIN_SCHEDULE)
-        r4 = G.solve(torch.full((g.n,), 0.5, device="cuda"), sel, **WS.WARM_SCHEDULE)
-        rw, _ = WS.warm_solve(net, G, sel)
-        assert rp.binarised and rw.binarised and rw.conflicts == 0 and rw.uncovered == 0
-        steps_p.append(rp.steps)
-        steps_w.append(rw.steps)
-        W_p.append(rp.set_objective)
-        W_w.append(rw.set_objective)
-        W_p400.append(r4.set_objective)
-    gap = (np.array(W_p) - np.array(W_w)) / np.array(W_p)
-    print("steps warm", steps_w, "plain", steps_p, "gap", gap, "W plain400", W_p400, "W warm", W_w)
-    assert np.mean(steps_w) < 0.85 * np.mean(steps_p), (steps_w, steps_p)
-    assert gap.mean() <= 1e-3, gap
-    assert np.mean(W_w) > np.mean(W_p400), (W_w, W_p400)
+        for T in ramps:
+            sch = dict(WS.PLAIN_SCHEDULE, ramp_steps=T)
+            r, dt = _timed_solve(lambda: G.solve(torch.full((g.n,), 0.5, device="cuda"), sel, **sch))
+            assert r.conflicts == 0
+            done[T] = done[T] and r.binarised and r.uncovered == 0
+            W[T].append(r.set_objective)
+            t_plain[T] += dt
+        r, dt = _timed_solve(lambda: WS.warm_solve(net, G, sel)[0])
+        assert r.binarised and r.conflicts == 0 and r.uncovered == 0, (e, r)
+        W_warm.append(r.set_objective)
+        steps_warm.append(r.steps)
+        t_warm += dt
+    assert done[1000]
+    ref = np.array(W[1000])
+    worst = {T: float(np.max((ref - np.array(W[T])) / ref)) for T in ramps}
+    t_star = min(T for T in ramps if done[T] and worst[T] <= 1e-3)
+    worst_warm = float(np.max((ref - np.array(W_warm)) / ref))
+    print("worst gaps", worst, "binarised", done, "T*", t_star, "plain ms", {T: round(v * 1e3, 2) for T, v in t_plain.items()},
+          "warm ms", round(t_warm * 1e3, 2), "warm gap", worst_warm, "warm steps", steps_warm)
+    assert worst_warm <= 1e-3, worst_warm
+    assert t_warm < t_plain[t_star], (t_warm, t_star, t_plain)
 
 
 def test_labels_best_of_several_starts(gpu):
