@@ -22,24 +22,30 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gn_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "_build", "liboracle_omp.so")   # all-core build (CPU baseline only)
 
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_CSR, E_SELF_LOOP, E_ASYMMETRIC, E_WEIGHT, E_NOT_NORMALIZABLE = -1, -2, -3, -4, -5, -6
 
 
-def build(force: bool = False) -> str:
+def build(force: bool = False, omp: bool = False) -> str:
     """Compile the oracle with gcc (no optimisation flags beyond -O2; fp contraction off
-    so each operation rounds as written)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-        tmp = _LIB + f".tmp{os.getpid()}"
+    so each operation rounds as written).  omp=True builds the all-core variant
+    (-fopenmp) that the benchmark times as its second CPU baseline."""
+    lib = _LIB_OMP if omp else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(lib), exist_ok=True)
+        tmp = lib + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               *(["-fopenmp"] if omp else []), "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, lib)
+    if force and not omp:
+        build(force=True, omp=True)
+    return lib
 
 
 _lib = None
+_lib_omp = None
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -62,10 +68,19 @@ class _Result(ctypes.Structure):
                 ("residual", ctypes.c_double), ("growing", ctypes.c_int64)]
 
 
-def _load():
-    global _lib
+def _load(omp: bool = False):
+    global _lib, _lib_omp
+    if omp:
+        if _lib_omp is None:
+            _lib_omp = _bind(ctypes.CDLL(build(omp=True)))
+        return _lib_omp
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        _lib = _bind(ctypes.CDLL(build()))
+    return _lib
+
+
+def _bind(lib):
+    if True:
         lib.orc_validate.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p]
         lib.orc_validate.restype = ctypes.c_int
         lib.orc_gamma.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int64]
@@ -98,8 +113,14 @@ def _load():
         lib.orc_set_x_floor.restype = None
         lib.orc_get_x_floor.argtypes = []
         lib.orc_get_x_floor.restype = ctypes.c_double
-        _lib = lib
-    return _lib
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
+    return lib
+
+
+def threads(omp: bool = True) -> int:
+    """Threads the row loops of the all-core build use (OMP_NUM_THREADS or all cores)."""
+    return _load(omp).orc_threads()
 
 
 def _p(a, t):
@@ -220,14 +241,14 @@ class SolveResult:
 
 
 def solve(n, row_ptr, col_idx, w, x0, gamma0=0.9, gamma1=1.5, ramp_steps=1000, max_steps=2000,
-          tau=1e-4, check_every=1) -> SolveResult:
+          tau=1e-4, check_every=1, omp=False) -> SolveResult:
     rp, ci = _csr(row_ptr, col_idx)
     x = np.array(np.asarray(x0, dtype=np.float64), copy=True)
     xb = x if x.size else np.zeros(1, np.float64)
     sel = np.zeros(max(n, 1), np.uint8)
     sch = _Schedule(gamma0, gamma1, ramp_steps, max_steps, tau, check_every)
     res = _Result()
-    st = _load().orc_solve(n, _p(rp, _i32p), _p(ci, _i32p), _p(_f64(w), _f64p), ctypes.byref(sch),
+    st = _load(omp).orc_solve(n, _p(rp, _i32p), _p(ci, _i32p), _p(_f64(w), _f64p), ctypes.byref(sch),
                            _p(xb, _f64p), _p(sel, _u8p), ctypes.byref(res))
     return SolveResult(st, xb[:n].copy(), sel[:n].astype(bool), res.steps, bool(res.binarised),
                        res.fallback_count, res.relaxed_objective, res.set_objective, res.set_size,

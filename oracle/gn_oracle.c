@@ -9,11 +9,20 @@
  *
  * Notation follows the paper: G = (A, w) simple undirected, w > 0, v = sqrt(w),
  * state x in [0,1]^n, weighted state y = v (.) x, closed regularized adjacency
- * B = I + gamma A.  Every loop below runs in CSR order, single-threaded, in
- * double precision; no blocking, fusion or reordering.
+ * B = I + gamma A.  Every loop below runs in CSR order in double precision; no
+ * blocking, fusion or reordering.
+ *
+ * The same source also builds an all-core variant (gcc -fopenmp) used only as
+ * the benchmark's second CPU baseline: the per-row loops of a step and of the
+ * stopping test then run their rows on several threads.  Each row's sum keeps
+ * its CSR order and the only reductions across rows are max, min and integer
+ * counts, so both builds return bit-identical results (tested).
  */
 #include <float.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -43,6 +52,15 @@ static double orc_x_floor = DBL_MIN; /* 2^-1022 */
 
 void orc_set_x_floor(double f) { orc_x_floor = f > 0.0 ? f : DBL_MIN; }
 double orc_get_x_floor(void) { return orc_x_floor; }
+
+/* Threads the row loops use: 1 in the plain build. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------------
  * Problem statement checks (Section 2): A is the adjacency matrix of a simple
@@ -100,6 +118,7 @@ int64_t orc_step(int32_t n, const int32_t* rp, const int32_t* ci, const double* 
     double* y = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     for (int32_t i = 0; i < n; ++i) y[i] = v[i] * x[i];
     int64_t fallback = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : fallback)
     for (int32_t i = 0; i < n; ++i) {
         double nb = 0.0;
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) nb += y[ci[e]];
@@ -146,6 +165,7 @@ void orc_binarisation(int32_t n, const int32_t* rp, const int32_t* ci, const dou
                       int64_t* growing_out) {
     double r = 0.0;
     int64_t unc = 0, grow = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(max : r) reduction(+ : unc, grow)
     for (int32_t i = 0; i < n; ++i) {
         double d = x[i] < 1.0 - x[i] ? x[i] : 1.0 - x[i];
         if (d > r) r = d;

@@ -549,3 +549,20 @@ def test_random_start_is_scale_free_draw():
     assert abs(e.mean() - 1.0) < 0.01
     x = O.random_start(u)
     assert x.max() == 1.0 and x.min() >= 1e-3
+
+
+def test_all_core_build_is_bit_identical():
+    """The all-core build of the oracle (the benchmark's second CPU baseline) runs
+    the rows of a step and of the stopping test on several threads; each row keeps
+    its CSR order and the cross-row reductions are max and counts, so every output
+    is bit-identical to the single-thread build (ER n=1500 seed 109, which
+    regrows from deep decay, and rook 48 x 48, which takes the safe-division reset)."""
+    for name, g, w in _floor_cases():
+        if name == "rook16":
+            continue
+        w = w.astype(np.float64)
+        a = O.solve(g.n, g.row_ptr, g.col_idx, w, np.full(g.n, 0.5), **SCHED_RAMP)
+        b = O.solve(g.n, g.row_ptr, g.col_idx, w, np.full(g.n, 0.5), omp=True, **SCHED_RAMP)
+        assert (a.steps, a.fallback_count, a.growing) == (b.steps, b.fallback_count, b.growing)
+        assert np.array_equal(a.x.view(np.uint64), b.x.view(np.uint64))
+        assert a.stab == b.stab and a.residual == b.residual and a.relaxed_objective == b.relaxed_objective
