@@ -196,6 +196,14 @@ typedef struct {
                                 8 n + 12 + 4 S bytes, its state and slice table (the lines
                                 stream from global memory); else, or above 65535 vertices,
                                 it runs from global memory in a launch of its own          */
+    int32_t light_max_deg;   /* bin schedule: rows of degree <= light_max_deg run a lane each,
+                                64 per slice: 8 or 16 (0 = 16)                              */
+    int32_t mid_max_deg;     /* rows of degree <= mid_max_deg (and above light_max_deg) run
+                                8 lanes each, 8 per slice: 32, 64 or 128 (0 = 64); heavier
+                                rows a wavefront each.  The bounds set how each graph's rows
+                                are relabelled and sliced (rebuilt when they change, a host
+                                step that synchronises the stream); every row keeps its
+                                canonical sum order, so results do not depend on them      */
     int32_t reserved;
 } gn_tuning;
 
@@ -225,11 +233,23 @@ void gn_batch_destroy(gn_batch* b);
 gn_status gn_batch_solve(gn_batch* b, const gn_schedule* sch, const gn_tuning* tuning, float* x_cat,
                          uint8_t* sel_cat, gn_result* res, hipStream_t stream);
 
-/* Time candidate launch shapes on this batch (per shape a warm-up run of at
- * most 64 steps, then one full solve under `sch`, from x0 = 1/2) and return
- * the fastest; the choice is cached in the batch handle and used by later
- * gn_batch_solve calls with tuning == NULL.  SYNC. */
+/* Autotuner of the batched solve: times candidate tunings on this batch (per
+ * candidate a warm-up run of at most 64 steps, then one full solve under
+ * `sch`, from x0 = 1/2) and returns the fastest.  It searches the launch shapes
+ * (block_threads x blocks_per_cu) at the default bin bounds, then the bin
+ * schedule (light_max_deg in {8, 16} x mid_max_deg in {32, 64, 128}) at the best
+ * shape, then the shapes again at the best bounds.  The choice is kept in the
+ * handle (used by later gn_batch_solve calls with tuning == NULL, the layout
+ * left in its bounds) and in a process-wide cache keyed by the batch's bucket:
+ * graph count, total vertices and entries (powers of two), the degree
+ * histogram (fractions of rows of degree <= 8, 16, 32, 64, 128 and above, in
+ * steps of 1/32) and max_steps (power of two).  A batch whose bucket is cached
+ * takes that tuning without timing anything.  SYNC. */
 gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_tuning* out, hipStream_t stream);
+
+/* Entries of the autotuner's process-wide cache, and clearing it (host only). */
+int32_t gn_batch_tuning_cache_size(void);
+void gn_batch_tuning_cache_clear(void);
 
 /* The batch as one block-diagonal graph (vertex ids offset graph by graph),
  * owned by the batch: valid until gn_batch_destroy.  Used by the unrolled

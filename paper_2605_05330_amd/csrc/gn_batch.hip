@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <type_traits>
 #include <vector>
@@ -218,7 +219,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 const int o = so[nL + s];
                 const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
                 unsigned bits = 0u;
-                const float sigma = slice_sum<8, 8, kMidMaxDeg / 8>(ln + o * 64 + lane, W, yin, bits);
+                const float sigma = slice_sum<8, 8, kMidMaxDegCap / 8>(ln + o * 64 + lane, W, yin, bits);
                 const bool any_sel = gnk::group_any<8>((bits >> 31) != 0u);
                 if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
             }
@@ -242,7 +243,7 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 const float sigma = gnk::row_sum<1, kLightMaxDeg>(col_g + s0, dd, yin, 0, sel);
                 viol |= step_row(yin[i], vv[i], sigma, sel != 0u, g, do_test, do_write, a.tau, yout, i, fb);
             }
-            viol |= mid_rows<BT, kMidMaxDeg, true>(rp_g, col_g, yin, vv, yout, d.n_light, d.n_mid, g, do_test,
+            viol |= mid_rows<BT, kMidMaxDegCap, true>(rp_g, col_g, yin, vv, yout, d.n_light, d.n_mid, g, do_test,
                                                    do_write, a.tau, fb);
 #pragma unroll 1
             for (int i = d.n_mid + wave; i < n; i += NW) {
@@ -434,6 +435,118 @@ extern "C" void gn_batch_destroy(gn_batch* b) {
     delete b;
 }
 
+// Relabelling and sliced layout of every graph for the degree bounds of the
+// bin schedule: rows of degree <= light first (a lane each, 64 per slice), then
+// those of degree <= mid (8 lanes each, 8 per slice), then the rest (a
+// wavefront each), each class by decreasing degree (ties in the original
+// order); every row keeps its entries in the caller's order, so the canonical
+// sums, and with them all results, do not depend on the bounds.  Uploads the
+// layout; the previous one (and the solve graph built on it) is dropped.  SYNC.
+static gn_status build_layout(gn_batch* b, int32_t light, int32_t mid, hipStream_t stream) {
+    const int32_t count = b->count;
+    const int64_t tn = b->total_n, tnnz = b->total_nnz;
+    int64_t trp = 0;
+    for (int32_t g = 0; g < count; ++g) trp += (int64_t)b->h_n[g] + 1;
+    std::vector<BatchDesc> desc((size_t)count);
+    std::vector<int32_t> rp_int((size_t)trp), col_int((size_t)std::max<int64_t>(tnnz, 1)), perm((size_t)std::max<int64_t>(tn, 1));
+    std::vector<int32_t> vgraph((size_t)std::max<int64_t>(tn, 1));
+    std::vector<float> v_int((size_t)std::max<int64_t>(tn, 1)), w_int((size_t)std::max<int64_t>(tn, 1));
+    std::vector<uint16_t> lines;
+    std::vector<int32_t> slices;
+    std::vector<int64_t> state_bytes((size_t)count, INT64_MAX);
+    std::vector<int32_t> h_slices((size_t)count, -1), h_lines((size_t)count, -1);
+    int64_t vo = 0, ro = 0, eo = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const int32_t ng = b->h_n[g];
+        const int32_t* rp = b->h_rp.data() + ro;
+        const int32_t* ci = b->h_ci.data() + eo;
+        const float* wg = b->h_w.data() + vo;
+        std::vector<int32_t> p((size_t)ng), q((size_t)ng);
+        std::iota(p.begin(), p.end(), 0);
+        auto cls = [&](int32_t i) {
+            const int32_t dg = rp[i + 1] - rp[i];
+            return dg <= light ? 0 : dg <= mid ? 1 : 2;
+        };
+        std::stable_sort(p.begin(), p.end(), [&](int32_t i, int32_t j) {
+            const int ci_ = cls(i), cj_ = cls(j);
+            return ci_ != cj_ ? ci_ < cj_ : rp[i + 1] - rp[i] > rp[j + 1] - rp[j];
+        });
+        int32_t nl = 0, nm = 0;
+        for (int32_t i = 0; i < ng; ++i) {
+            nl += cls(i) == 0 ? 1 : 0;
+            nm += cls(i) <= 1 ? 1 : 0;
+        }
+        for (int32_t r = 0; r < ng; ++r) q[p[r]] = r;
+        int32_t* rpi = rp_int.data() + ro;
+        rpi[0] = 0;
+        for (int32_t r = 0; r < ng; ++r) {
+            const int32_t i = p[r];
+            const int32_t dg = rp[i + 1] - rp[i];
+            for (int32_t e = 0; e < dg; ++e) col_int[(size_t)(eo + rpi[r] + e)] = q[ci[rp[i] + e]];
+            rpi[r + 1] = rpi[r] + dg;
+            perm[(size_t)(vo + r)] = i;
+            v_int[(size_t)(vo + r)] = (float)std::sqrt((double)wg[i]);
+            w_int[(size_t)(vo + r)] = wg[i];
+            vgraph[(size_t)(vo + r)] = g;
+        }
+        // sliced layout (gn_slices.h)
+        const int64_t ln0 = (int64_t)(lines.size() / 64), so0 = (int64_t)slices.size();
+        int32_t nlines = 0;
+        if (ng <= kMaxSlicedN) {
+            const int64_t acc = build_slices(ng, rpi, col_int.data() + eo, 0, nl, nl, nm, nm, ng, lines, slices);
+            if (acc > INT32_MAX / 64) return GN_E_ARG;
+            nlines = (int32_t)acc;
+            state_bytes[g] = state_lds_bytes(ng, slice_count(ng, nl, nm));
+            h_slices[g] = slice_count(ng, nl, nm);
+            h_lines[g] = nlines;
+        }
+        desc[g] = BatchDesc{ng, nl, nm, nlines, vo, ro, eo, ln0, so0, (int32_t)b->h_nnz[g], 0};
+        vo += ng;
+        ro += (int64_t)ng + 1;
+        eo += b->h_nnz[g];
+    }
+    // the layout's variable-size arrays grow on demand
+    const size_t nlw = std::max<size_t>(lines.size(), 64), nsl = std::max<size_t>(slices.size(), 1);
+    if (nlw > b->lines_cap) {
+        if (b->lines) (void)hipFree(b->lines);
+        b->lines = nullptr;
+        b->lines_cap = 0;
+        if (!gn_dalloc(&b->lines, nlw)) return GN_E_NOMEM;
+        b->lines_cap = nlw;
+    }
+    if (nsl > b->slices_cap) {
+        if (b->slices) (void)hipFree(b->slices);
+        b->slices = nullptr;
+        b->slices_cap = 0;
+        if (!gn_dalloc(&b->slices, nsl)) return GN_E_NOMEM;
+        b->slices_cap = nsl;
+    }
+    hipError_t e = hipStreamSynchronize(stream);   // no earlier work may still read the old layout
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    up(b->desc, desc.data(), sizeof(BatchDesc) * count);
+    up(b->vgraph, vgraph.data(), sizeof(int32_t) * tn);
+    up(b->row_ptr, rp_int.data(), sizeof(int32_t) * trp);
+    up(b->col, col_int.data(), sizeof(int32_t) * tnnz);
+    up(b->lines, lines.data(), sizeof(uint16_t) * lines.size());
+    up(b->slices, slices.data(), sizeof(int32_t) * slices.size());
+    up(b->v, v_int.data(), sizeof(float) * tn);
+    up(b->w, w_int.data(), sizeof(float) * tn);
+    up(b->perm, perm.data(), sizeof(int32_t) * tn);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return GN_E_HIP;
+    b->h_state = std::move(state_bytes);
+    b->h_slices = std::move(h_slices);
+    b->h_lines = std::move(h_lines);
+    b->lay_light = light;
+    b->lay_mid = mid;
+    b->split_lds = -1;   // the processing order depends on the graphs' LDS sizes
+    if (b->launch.exec) (void)hipGraphExecDestroy(b->launch.exec);
+    b->launch.exec = nullptr;
+    return GN_OK;
+}
+
 extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int64_t* nnz, const int32_t* row_ptr_cat,
                                      const int32_t* col_idx_cat, const float* w_cat, uint32_t flags, hipStream_t stream,
                                      gn_batch** out) {
@@ -477,18 +590,7 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
         if (tn) std::memcpy(b->h_w.data(), w_cat, sizeof(float) * tn);
     }
 
-    // validate each graph (same conditions as gn_graph_create) and relabel it:
-    // rows of degree <= kLightMaxDeg first, then those of degree <= kMidMaxDeg,
-    // then the rest, each class by decreasing degree (ties in the original
-    // order); each row keeps its entries in the caller's order
-    std::vector<BatchDesc> desc((size_t)count);
-    std::vector<int32_t> rp_int((size_t)trp), col_int((size_t)std::max<int64_t>(tnnz, 1)), perm((size_t)std::max<int64_t>(tn, 1));
-    std::vector<int32_t> vgraph((size_t)std::max<int64_t>(tn, 1));
-    std::vector<float> v_int((size_t)std::max<int64_t>(tn, 1)), w_int((size_t)std::max<int64_t>(tn, 1));
-    std::vector<uint16_t> lines;
-    std::vector<int32_t> slices;
-    std::vector<int64_t> state_bytes((size_t)count, INT64_MAX);
-    std::vector<int32_t> h_slices((size_t)count, -1), h_lines((size_t)count, -1);
+    // validate each graph (same conditions as gn_graph_create)
     int64_t vo = 0, ro = 0, eo = 0;
     for (int32_t g = 0; g < count; ++g) {
         const int32_t ng = n[g];
@@ -520,46 +622,6 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
         }
         for (int32_t i = 0; i < ng; ++i)
             if (!(wg[i] > 0.0f) || !std::isfinite(wg[i])) { delete b; return GN_E_WEIGHT; }
-        std::vector<int32_t> p((size_t)ng), q((size_t)ng);
-        std::iota(p.begin(), p.end(), 0);
-        auto cls = [&](int32_t i) {
-            const int32_t dg = rp[i + 1] - rp[i];
-            return dg <= kLightMaxDeg ? 0 : dg <= kMidMaxDeg ? 1 : 2;
-        };
-        std::stable_sort(p.begin(), p.end(), [&](int32_t i, int32_t j) {
-            const int ci_ = cls(i), cj_ = cls(j);
-            return ci_ != cj_ ? ci_ < cj_ : rp[i + 1] - rp[i] > rp[j + 1] - rp[j];
-        });
-        int32_t nl = 0, nm = 0;
-        for (int32_t i = 0; i < ng; ++i) {
-            nl += cls(i) == 0 ? 1 : 0;
-            nm += cls(i) <= 1 ? 1 : 0;
-        }
-        for (int32_t r = 0; r < ng; ++r) q[p[r]] = r;
-        int32_t* rpi = rp_int.data() + ro;
-        rpi[0] = 0;
-        for (int32_t r = 0; r < ng; ++r) {
-            const int32_t i = p[r];
-            const int32_t dg = rp[i + 1] - rp[i];
-            for (int32_t e = 0; e < dg; ++e) col_int[(size_t)(eo + rpi[r] + e)] = q[ci[rp[i] + e]];
-            rpi[r + 1] = rpi[r] + dg;
-            perm[(size_t)(vo + r)] = i;
-            v_int[(size_t)(vo + r)] = (float)std::sqrt((double)wg[i]);
-            w_int[(size_t)(vo + r)] = wg[i];
-            vgraph[(size_t)(vo + r)] = g;
-        }
-        // sliced layout (gn_slices.h)
-        const int64_t ln0 = (int64_t)(lines.size() / 64), so0 = (int64_t)slices.size();
-        int32_t nlines = 0;
-        if (ng <= kMaxSlicedN) {
-            const int64_t acc = build_slices(ng, rpi, col_int.data() + eo, 0, nl, nl, nm, nm, ng, lines, slices);
-            if (acc > INT32_MAX / 64) { delete b; return GN_E_ARG; }
-            nlines = (int32_t)acc;
-            state_bytes[g] = state_lds_bytes(ng, slice_count(ng, nl, nm));
-            h_slices[g] = slice_count(ng, nl, nm);
-            h_lines[g] = nlines;
-        }
-        desc[g] = BatchDesc{ng, nl, nm, nlines, vo, ro, eo, ln0, so0, (int32_t)nnz[g], 0};
         vo += ng;
         ro += (int64_t)ng + 1;
         eo += nnz[g];
@@ -574,13 +636,13 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
     b->total_n = tn;
     b->total_nnz = tnnz;
     b->max_n = maxn;
+    b->h_order = order;
     (void)hipGetDevice(&b->device);
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     b->cus = cus > 0 ? cus : 256;
     bool ok = gn_dalloc(&b->desc, count) && gn_dalloc(&b->order, count) && gn_dalloc(&b->vgraph, tn) &&
-              gn_dalloc(&b->row_ptr, trp) && gn_dalloc(&b->col, tnnz) && gn_dalloc(&b->lines, std::max<size_t>(lines.size(), 64)) &&
-              gn_dalloc(&b->slices, slices.size()) && gn_dalloc(&b->v, tn) && gn_dalloc(&b->w, tn) &&
+              gn_dalloc(&b->row_ptr, trp) && gn_dalloc(&b->col, tnnz) && gn_dalloc(&b->v, tn) && gn_dalloc(&b->w, tn) &&
               gn_dalloc(&b->perm, tn) && gn_dalloc(&b->yg0, tn) && gn_dalloc(&b->yg1, tn) && gn_dalloc(&b->queue, 3) &&
               gn_dalloc(&b->res, count);
     if (ok && hipHostMalloc((void**)&b->res_host, sizeof(BatchRes) * count, hipHostMallocDefault) != hipSuccess) {
@@ -592,37 +654,26 @@ extern "C" gn_status gn_batch_create(int32_t count, const int32_t* n, const int6
         delete b;
         return GN_E_NOMEM;
     }
-    hipError_t e = hipSuccess;
-    auto up = [&](void* dst, const void* src, size_t bytes) {
-        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
-    };
-    up(b->desc, desc.data(), sizeof(BatchDesc) * count);
-    b->h_order = order;
-    up(b->vgraph, vgraph.data(), sizeof(int32_t) * tn);
-    up(b->row_ptr, rp_int.data(), sizeof(int32_t) * trp);
-    up(b->col, col_int.data(), sizeof(int32_t) * tnnz);
-    up(b->lines, lines.data(), sizeof(uint16_t) * lines.size());
-    up(b->slices, slices.data(), sizeof(int32_t) * slices.size());
-    b->h_state = std::move(state_bytes);
-    b->h_slices = std::move(h_slices);
-    b->h_lines = std::move(h_lines);
-    up(b->v, v_int.data(), sizeof(float) * tn);
-    up(b->w, w_int.data(), sizeof(float) * tn);
-    up(b->perm, perm.data(), sizeof(int32_t) * tn);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) {
+    const gn_status st = build_layout(b, kLightMaxDeg, kMidMaxDeg, stream);
+    if (st != GN_OK) {
         batch_free(b);
         delete b;
-        return GN_E_HIP;
+        return st;
     }
     *out = b;
     return GN_OK;
 }
 
+// The bin schedule's degree bounds of a tuning (0 selects the default).
+static int32_t light_bound(const gn_tuning& t) { return t.light_max_deg ? t.light_max_deg : kLightMaxDeg; }
+static int32_t mid_bound(const gn_tuning& t) { return t.mid_max_deg ? t.mid_max_deg : kMidMaxDeg; }
+
 static bool tuning_valid(const gn_tuning& t) {
     const bool bt_ok = t.block_threads == 128 || t.block_threads == 256 || t.block_threads == 512 ||
                        (t.block_threads == 1024 && t.blocks_per_cu <= 2);
-    return bt_ok && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 4 && t.lds_vertices >= 0 &&
+    const int32_t lb = light_bound(t), mb = mid_bound(t);
+    const bool bins_ok = (lb == 8 || lb == 16) && (mb == 32 || mb == 64 || mb == kMidMaxDegCap);
+    return bt_ok && bins_ok && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 4 && t.lds_vertices >= 0 &&
            (size_t)t.lds_vertices * 12 * t.blocks_per_cu <= kLdsBudget;
 }
 
@@ -631,8 +682,15 @@ static gn_tuning default_tuning(const gn_batch* b) {
     t.block_threads = 256;
     t.blocks_per_cu = 2;
     t.lds_vertices = kLdsBudget / (12 * 2);
-    t.reserved = 0;
+    t.light_max_deg = kLightMaxDeg;
+    t.mid_max_deg = kMidMaxDeg;
     return t;
+}
+
+// The layout of a tuning's bin bounds, rebuilt when they differ from the current one.
+static gn_status ensure_layout(gn_batch* b, const gn_tuning& t, hipStream_t s) {
+    if (b->lay_light == light_bound(t) && b->lay_mid == mid_bound(t)) return GN_OK;
+    return build_layout(b, light_bound(t), mid_bound(t), s);
 }
 
 static gn_status ensure_gamma(gn_batch* b, int32_t entries) {
@@ -671,6 +729,7 @@ static int resident_blocks(int bt, size_t lds_bytes, bool big = false) {
 static gn_status prepare_batch(gn_batch* b, const gn_schedule* sch, const gn_tuning& t, hipStream_t s) {
     gn_status st = ensure_gamma(b, sch->max_steps + 1);
     if (st != GN_OK) return st;
+    if ((st = ensure_layout(b, t, s)) != GN_OK) return st;
     if (t.lds_vertices != b->split_lds) {
         std::vector<int32_t> split;
         split.reserve(b->h_order.size());
@@ -778,7 +837,8 @@ static gn_status enqueue_batch(gn_batch* b, const gn_schedule* sch, const gn_tun
 static bool same_launch(const BatchLaunch& k, const gn_tuning& t, const gn_schedule* sch, const float* x,
                         const uint8_t* sel, const float* gamma) {
     return k.exec && k.t.block_threads == t.block_threads && k.t.blocks_per_cu == t.blocks_per_cu &&
-           k.t.lds_vertices == t.lds_vertices && k.sch.gamma0 == sch->gamma0 && k.sch.gamma1 == sch->gamma1 &&
+           k.t.lds_vertices == t.lds_vertices && light_bound(k.t) == light_bound(t) &&
+           mid_bound(k.t) == mid_bound(t) && k.sch.gamma0 == sch->gamma0 && k.sch.gamma1 == sch->gamma1 &&
            k.sch.ramp_steps == sch->ramp_steps && k.sch.max_steps == sch->max_steps && k.sch.tau == sch->tau &&
            k.sch.check_every == sch->check_every && k.x == x && k.sel == sel && k.gamma == gamma;
 }
@@ -878,13 +938,71 @@ extern "C" gn_status gn_batch_solve(gn_batch* b, const gn_schedule* sch, const g
     return all ? GN_OK : GN_NOT_CONVERGED;
 }
 
+// Tunings found by gn_batch_autotune, kept for the process and keyed by a
+// signature of the batch: graph count, total vertices and entries (each by its
+// power of two), the degree histogram (the fraction of rows of degree <= 8,
+// <= 16, <= 32, <= 64, <= 128 and above, in steps of 1/32), and the schedule's
+// step budget (by its power of two).
+static std::mutex g_tune_mu;
+static std::map<std::vector<int64_t>, gn_tuning> g_tune_cache;
+
+static int64_t log2_bucket(int64_t v) {
+    int64_t k = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+static std::vector<int64_t> batch_signature(const gn_batch* b, const gn_schedule* sch) {
+    int64_t hist[6] = {0, 0, 0, 0, 0, 0};
+    int64_t ro = 0;
+    for (int32_t g = 0; g < b->count; ++g) {
+        const int32_t* rp = b->h_rp.data() + ro;
+        for (int32_t i = 0; i < b->h_n[g]; ++i) {
+            const int32_t d = rp[i + 1] - rp[i];
+            hist[d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : 5]++;
+        }
+        ro += (int64_t)b->h_n[g] + 1;
+    }
+    std::vector<int64_t> sig = {log2_bucket(b->count), log2_bucket(b->total_n), log2_bucket(b->total_nnz),
+                                log2_bucket(sch->max_steps)};
+    for (int64_t h : hist) sig.push_back(b->total_n ? (h * 32 + b->total_n / 2) / b->total_n : 0);
+    return sig;
+}
+
+extern "C" int32_t gn_batch_tuning_cache_size(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return (int32_t)g_tune_cache.size();
+}
+
+extern "C" void gn_batch_tuning_cache_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache.clear();
+}
+
 extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_tuning* out, hipStream_t stream) {
     if (!b || !out) return GN_E_ARG;
     gn_status st = check_schedule(sch);
     if (st != GN_OK) return st;
+    const std::vector<int64_t> sig = batch_signature(b, sch);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(sig);
+        if (it != g_tune_cache.end()) {
+            if ((st = ensure_layout(b, it->second, stream)) != GN_OK) return st;
+            b->tuning = it->second;
+            b->tuned = true;
+            *out = it->second;
+            return GN_OK;
+        }
+    }
     // per candidate: a warm-up run of at most 64 steps, then one timed full
     // solve, from x0 = 1/2 (the largest graphs set the wall time, and only a
-    // full solve shows their tail)
+    // full solve shows their tail).  The launch shapes are searched at the
+    // default bin bounds, then the bounds at the best shape, then the shapes
+    // again at the best bounds.
     gn_schedule ws = *sch;
     ws.max_steps = std::min<int32_t>(sch->max_steps, 64);
     float* x = nullptr;
@@ -900,46 +1018,75 @@ extern "C" gn_status gn_batch_autotune(gn_batch* b, const gn_schedule* sch, gn_t
     gn_tuning best = default_tuning(b);
     float best_ms = INFINITY;
     st = GN_OK;
-    for (int bt : {128, 256, 512, 1024}) {
-        for (int bpc : {1, 2, 4}) {
-            gn_tuning t{};
-            t.block_threads = bt;
-            t.blocks_per_cu = bpc;
-            t.lds_vertices = kLdsBudget / (12 * bpc);
-            if (!tuning_valid(t)) continue;
-            allow_lds(bt, (size_t)t.lds_vertices * 12);
-            if (resident_blocks(bt, (size_t)t.lds_vertices * 12) < bpc) continue;  // same launch as a smaller bpc
-            float ms_sum = 0.0f;
-            for (int rep = 0; rep < 2 && st == GN_OK; ++rep) {
-                if (hipMemcpyAsync(x, half.data(), sizeof(float) * b->total_n, hipMemcpyHostToDevice, stream) !=
-                    hipSuccess) {
-                    st = GN_E_HIP;
-                    break;
-                }
-                (void)hipEventRecord(e0, stream);
-                st = enqueue_batch(b, rep == 0 ? &ws : sch, t, x, sel, stream);
-                (void)hipEventRecord(e1, stream);
-                if (hipEventSynchronize(e1) != hipSuccess) st = GN_E_HIP;
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rep == 1) ms_sum += ms;
+    auto time_one = [&](const gn_tuning& t) -> float {
+        allow_lds(t.block_threads, (size_t)t.lds_vertices * 12);
+        float ms_sum = 0.0f;
+        for (int rep = 0; rep < 2 && st == GN_OK; ++rep) {
+            if (hipMemcpyAsync(x, half.data(), sizeof(float) * b->total_n, hipMemcpyHostToDevice, stream) !=
+                hipSuccess) {
+                st = GN_E_HIP;
+                break;
             }
-            if (st != GN_OK) break;
-            if (ms_sum < best_ms) {
-                best_ms = ms_sum;
+            if ((st = ensure_layout(b, t, stream)) != GN_OK) break;  // rebuilds outside the timed region
+            (void)hipEventRecord(e0, stream);
+            st = enqueue_batch(b, rep == 0 ? &ws : sch, t, x, sel, stream);
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) st = GN_E_HIP;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep == 1) ms_sum += ms;
+        }
+        return st == GN_OK ? ms_sum : INFINITY;
+    };
+    auto search_shapes = [&](int32_t lb, int32_t mb) {
+        for (int bt : {128, 256, 512, 1024}) {
+            for (int bpc : {1, 2, 4}) {
+                gn_tuning t{};
+                t.block_threads = bt;
+                t.blocks_per_cu = bpc;
+                t.lds_vertices = kLdsBudget / (12 * bpc);
+                t.light_max_deg = lb;
+                t.mid_max_deg = mb;
+                if (!tuning_valid(t)) continue;
+                allow_lds(bt, (size_t)t.lds_vertices * 12);
+                if (resident_blocks(bt, (size_t)t.lds_vertices * 12) < bpc) continue;  // same launch as a smaller bpc
+                const float ms = time_one(t);
+                if (st != GN_OK) return;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+        }
+    };
+    search_shapes(kLightMaxDeg, kMidMaxDeg);
+    const gn_tuning shape = best;
+    for (int32_t lb : {8, 16}) {
+        for (int32_t mb : {32, 64, kMidMaxDegCap}) {
+            if (st != GN_OK || (lb == kLightMaxDeg && mb == kMidMaxDeg)) continue;
+            gn_tuning t = shape;
+            t.light_max_deg = lb;
+            t.mid_max_deg = mb;
+            const float ms = time_one(t);
+            if (st == GN_OK && ms < best_ms) {
+                best_ms = ms;
                 best = t;
             }
         }
-        if (st != GN_OK) break;
     }
+    if (st == GN_OK && (light_bound(best) != kLightMaxDeg || mid_bound(best) != kMidMaxDeg))
+        search_shapes(light_bound(best), mid_bound(best));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(x);
     (void)hipFree(sel);
     if (st != GN_OK) return st;
+    if ((st = ensure_layout(b, best, stream)) != GN_OK) return st;
     b->tuning = best;
     b->tuned = true;
     *out = best;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[sig] = best;
     return GN_OK;
 }
 

@@ -8,8 +8,8 @@
 
 struct BatchDesc {
     int32_t n;        // vertices
-    int32_t n_light;  // internal rows [0, n_light) have degree <= kLightMaxDeg
-    int32_t n_mid;    // rows [n_light, n_mid) have degree <= kMidMaxDeg, rows [n_mid, n) more
+    int32_t n_light;  // internal rows [0, n_light) have degree <= the light bound of the layout
+    int32_t n_mid;    // rows [n_light, n_mid) have degree <= its mid bound, rows [n_mid, n) more
     int32_t n_lines;  // lines of the sliced layout (0 without one)
     int64_t v_off;    // offset of the graph's vertices in the vertex arrays
     int64_t rp_off;   // offset of its row_ptr (n + 1 entries)
@@ -72,6 +72,8 @@ struct gn_batch {
     int32_t* col = nullptr;
     uint16_t* lines = nullptr;  // sliced layouts
     int32_t* slices = nullptr;  // slice tables
+    size_t lines_cap = 0, slices_cap = 0;  // their allocated entries
+    int32_t lay_light = 0, lay_mid = 0;    // degree bounds of the current layout
     float* v = nullptr;
     float* w = nullptr;
     int32_t* perm = nullptr;

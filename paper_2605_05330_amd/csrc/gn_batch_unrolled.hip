@@ -83,7 +83,7 @@ __device__ __forceinline__ void unrolled_slices(const BatchDesc& d, const int32_
         const int o = so[nL + s];
         const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
         unsigned bits = 0u;
-        const float sigma = slice_sum<8, 8, kMidMaxDeg / 8, ABS>(ln + o * 64 + lane, W, src, bits);
+        const float sigma = slice_sum<8, 8, kMidMaxDegCap / 8, ABS>(ln + o * 64 + lane, W, src, bits);
         if (valid) row(i, sigma, pre);
     }
 #pragma unroll 1

@@ -28,8 +28,14 @@ namespace gnsl {
 
 using gnk::sign_of;
 
-constexpr int kLightMaxDeg = 16;  // rows up to this degree run one per thread (64 rows per slice)
-constexpr int kMidMaxDeg = 64;    // rows up to this degree run 8 threads per row (8 rows per slice)
+// Degree classes of the sliced layout (the bin schedule): rows up to the light
+// bound run one per thread (64 rows per slice), rows up to the mid bound 8
+// threads per row (8 rows per slice), heavier rows a wavefront each.  The
+// batched solve takes its bounds from its tuning; these are the defaults and
+// the largest bounds the kernels are built for.
+constexpr int kLightMaxDeg = 16;     // default light bound, and its cap (16 lines per slice)
+constexpr int kMidMaxDeg = 64;       // default mid bound
+constexpr int kMidMaxDegCap = 128;   // largest mid bound (16 lines per slice, two per chain)
 constexpr int kLdsBudget = 160 * 1024 - 2048;  // dynamic LDS per CU (static LDS of the kernel set aside)
 constexpr int32_t kMaxSlicedN = 65535;          // largest graph with a sliced layout (ids and the zero slot fit 16 bits)
 

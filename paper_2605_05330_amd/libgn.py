@@ -58,7 +58,8 @@ class gn_lp_result(ctypes.Structure):
 
 class gn_tuning(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("lds_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_vertices", ctypes.c_int32), ("light_max_deg", ctypes.c_int32),
+                ("mid_max_deg", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -96,6 +97,8 @@ def lib():
             "gn_batch_solve": ([_vp, ctypes.POINTER(gn_schedule), ctypes.POINTER(gn_tuning), _vp, _vp,
                                 ctypes.POINTER(gn_result), _vp], ctypes.c_int),
             "gn_batch_autotune": ([_vp, ctypes.POINTER(gn_schedule), ctypes.POINTER(gn_tuning), _vp], ctypes.c_int),
+            "gn_batch_tuning_cache_size": ([], ctypes.c_int32),
+            "gn_batch_tuning_cache_clear": ([], None),
             "gn_batch_graph": ([_vp], _vp),
             "gn_mpnn_cache_bytes": ([ctypes.c_int32], ctypes.c_int64),
             "gn_mpnn_forward": ([_vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -632,6 +635,14 @@ def gn_batch_autotune(h, schedule: gn_schedule, stream=None) -> gn_tuning:
     t = gn_tuning()
     _check(lib().gn_batch_autotune(h, ctypes.byref(schedule), ctypes.byref(t), _stream(stream)), "gn_batch_autotune")
     return t
+
+
+def gn_batch_tuning_cache_size() -> int:
+    return int(lib().gn_batch_tuning_cache_size())
+
+
+def gn_batch_tuning_cache_clear():
+    lib().gn_batch_tuning_cache_clear()
 
 
 def gn_batch_graph(h):

@@ -100,15 +100,47 @@ def test_batch_results_independent_of_tuning(gpu):
     # less keep their CSR there too (the graphs up to ~1000 vertices at 5000, up to ~640
     # at 3000, only the two edgeless ones at 100), others with n <= lds_vertices keep the
     # state there, the rest run from global memory
+    assert t.light_max_deg in (8, 16) and t.mid_max_deg in (32, 64, 128)
     shapes = [t, lg.gn_tuning(128, 1, 3000, 0), lg.gn_tuning(512, 2, 3000, 0), lg.gn_tuning(1024, 1, 5000, 0),
               lg.gn_tuning(1024, 2, 100, 0),
               lg.gn_tuning(256, 4, 100, 0),   # most graphs take the global-memory state path
-              lg.gn_tuning(256, 2, 0, 0)]     # every graph on the global-memory path
-    for tu in shapes:
+              lg.gn_tuning(256, 2, 0, 0),     # every graph on the global-memory path
+              # the bin schedule: light rows up to degree 8 or 16, mid rows up to 32, 64 or 128
+              lg.gn_tuning(256, 2, 6000, 8, 32), lg.gn_tuning(512, 1, 3000, 8, 128),
+              lg.gn_tuning(1024, 1, 5000, 16, 128), lg.gn_tuning(128, 4, 100, 16, 32),
+              lg.gn_tuning(256, 2, 0, 8, 32), lg.gn_tuning(512, 2, 0, 16, 128)]
+    for tu in shapes + [None]:       # None: back to the autotuned schedule kept in the handle
         st, res, xb, sb = _run_batch(B, gs, tuning=tu)
-        assert np.array_equal(xb.view(np.uint32), base[2].view(np.uint32))
+        assert np.array_equal(xb.view(np.uint32), base[2].view(np.uint32)), tu
         assert np.array_equal(sb, base[3])
         assert [r.steps for r in res] == [r.steps for r in base[1]]
+        assert [r.set_objective for r in res] == [r.set_objective for r in base[1]]
+        assert [r.stab for r in res] == [r.stab for r in base[1]]
+    with pytest.raises(lg.GNError):
+        _run_batch(B, gs, tuning=lg.gn_tuning(256, 2, 3000, 12, 64))   # not a bound of the schedule
+
+
+def test_batch_autotune_cache(gpu):
+    """The autotuner keeps its choice by the batch's bucket: a second batch of the same
+    graphs takes it without timing and gives the same results."""
+    import time
+    lg = _lg()
+    gs, ws = _mixed_graphs()
+    lg.gn_batch_tuning_cache_clear()
+    B1 = lg.Batch.from_graphs(gs, ws)
+    t1 = B1.autotune(**SCHED)
+    assert lg.gn_batch_tuning_cache_size() == 1
+    B2 = lg.Batch.from_graphs(gs, ws)
+    c0 = time.perf_counter()
+    t2 = B2.autotune(**SCHED)
+    dt = time.perf_counter() - c0
+    assert lg.gn_batch_tuning_cache_size() == 1
+    assert [getattr(t1, f) for f, _ in t1._fields_] == [getattr(t2, f) for f, _ in t2._fields_]
+    r1, r2 = _run_batch(B1, gs), _run_batch(B2, gs)
+    assert np.array_equal(r1[2].view(np.uint32), r2[2].view(np.uint32))
+    B1.autotune(**dict(SCHED, max_steps=40))       # another step budget is another bucket
+    assert lg.gn_batch_tuning_cache_size() == 2
+    assert dt < 1.0, dt
 
 
 def test_batch_rejects_bad_x0(gpu):
