@@ -375,7 +375,8 @@ def bench_atoms(reps=3):
 
 def bench_lp(with_oracle=True):
     """Fractional warm start (Section 6): 16 clique-LP solves of a routes-and-stops
-    instance (10,000 routes, 2,000 stops, 3-8 stops per route) to a 1% duality gap,
+    instance (10,000 routes, 2,000 stops, 3-8 stops per route) to the paper's 0.1%
+    fractional duality gap (annealed schedule, best bounds over the checks),
     then GN multi-start from them against 16 random starts."""
     import torch
     from paper_2605_05330_amd import inputs as I

@@ -520,19 +520,32 @@ gn_status gn_lp_info(const gn_lp* lp, int32_t* n_classes, int32_t* n_cliques, in
 /* Run `starts` (1..GN_MAX_STARTS) independent solves.  t0: host float[starts],
  * finite and > 0; order: host int32[starts * n_classes], row s a permutation of
  * the classes; drop in (0, 1]; t_min > 0; max_passes >= 1; check_every >= 1;
- * gap_tol >= 0; x_floor in [0, 1).  Lam and lam start at zero.  After pass p
- * with (p + 1) % check_every == 0, and after the last pass, each running start
- * evaluates at T_p the feasible point xf_i = x_i / max(1, max_{C holds i}
- * sum_{j in C} x_j) (x's exponent capped at 60), D and P = c.xf, and stops when
- * (D - P) / D <= gap_tol.  x: device float[starts * n], start-major (user vertex
- * ids), receives max(xf, x_floor) of the stopping check: a starting point for
- * gn_multi_solve on the conflict graph (an edge between two vertices sharing a
- * clique).  res: host gn_lp_result[starts].  fp32 state, fp64 sums of D and P.
- * Returns GN_OK when every start met gap_tol, else GN_NOT_CONVERGED; GN_E_ARG
- * on bad arguments, GN_E_NUMERIC if D or P is not finite.  SYNC. */
+ * gap_tol >= 0; x_floor in [0, 1); anneal_tol finite; stall >= 1.  Lam and lam
+ * start at zero.
+ * Checks: after pass p with (p + 1) % check_every == 0, and after the last
+ * pass, each running start takes at the pass's temperature the feasible point
+ * xf_i = x_i / max(1, max_{C holds i} sum_{j in C} x_j) (x's exponent capped at
+ * 60), raises it by two rounds of a fair-share lift (each clique's slack split
+ * equally among its members, each member taking the smallest share of its
+ * cliques), and evaluates P = c.xl and the bound D = sum lam_C +
+ * sum_i max(0, c_i - sum_{C holds i} lam_C) (the multipliers' sums rebuilt in
+ * fp64).  It keeps D_best = min D, P_best = max P and the point of P_best, and
+ * stops when (D_best - P_best) / D_best <= gap_tol.
+ * Temperatures: anneal_tol <= 0 gives T_p = max(t_min, t0 drop^p) every pass;
+ * anneal_tol > 0 holds T between checks and lowers it by drop^check_every (not
+ * below t_min) after a check whose smoothed primal exceeds no clique by more
+ * than anneal_tol, or after `stall` checks in which P_best gained less than a
+ * relative 5e-5.
+ * x: device float[starts * n], start-major (user vertex ids), receives
+ * max(x_best, x_floor): a starting point for gn_multi_solve on the conflict graph
+ * (an edge between two vertices sharing a clique).  res: host
+ * gn_lp_result[starts] (dual = D_best, primal = P_best, temperature of the last
+ * check).  fp32 state, fp64 sums of D and P.  Returns GN_OK when every start met
+ * gap_tol, else GN_NOT_CONVERGED; GN_E_ARG on bad arguments, GN_E_NUMERIC if D or
+ * P is not finite.  SYNC. */
 gn_status gn_lp_solve(gn_lp* lp, int32_t starts, const float* t0, const int32_t* order, float drop, float t_min,
-                      int32_t max_passes, int32_t check_every, float gap_tol, float x_floor, float* x,
-                      gn_lp_result* res, hipStream_t stream);
+                      int32_t max_passes, int32_t check_every, float gap_tol, float x_floor, float anneal_tol,
+                      int32_t stall, float* x, gn_lp_result* res, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * GN under hyperedge constraints (the extension to hypergraph constraints left

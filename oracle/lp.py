@@ -31,10 +31,25 @@ permutation: the randomized clique order); pass p runs at
 T_p = max(t_min, t0 * drop^p).
 
 Check (after pass p when (p + 1) % check_every == 0, and after the last pass),
-at T = T_p:  x_i = exp(min((c_i - Lam_i) / T, 60)) (the cap only keeps sums
-finite), S_C = sum_{i in C} x_i, xf_i = x_i / max(1, max_{C contains i} S_C)
-(feasible), P = c.xf, gap = (D - P) / D.  The start stops when gap <= gap_tol.
-Its warm start is max(xf, x_floor) (GN needs a positive start).
+at the pass's T:  x_i = exp(min((c_i - Lam_i) / T, 60)) (the cap only keeps
+sums finite), S_C = sum_{i in C} x_i, xf_i = x_i / max(1, max_{C contains i} S_C)
+(feasible), then `lift_rounds` rounds of a fair-share lift that hands every
+clique's slack 1 - sum_{i in C} xf_i out equally to its members, each member
+rising by the smallest share of its cliques (still feasible); P = c.xl of the
+lifted point.  The bound is taken from the multipliers themselves,
+D = sum lam_C + sum_i max(0, c_i - sum_{C contains i} lam_C), so a drift of the
+incrementally kept Lam cannot make it invalid.  The start keeps the smallest D
+and the largest P over its checks (and the point of that P) and stops when
+(D_best - P_best) / D_best <= gap_tol.  Its warm start is max(x_best, x_floor)
+(GN needs a positive start).
+
+Temperatures.  anneal_tol <= 0: T_p = max(t_min, t0 drop^p) (the drop every
+pass).  anneal_tol > 0: the temperature is held within a check interval; at a
+check it drops by drop^check_every (not below t_min) when the smoothed primal's
+worst clique excess max_C S_C - 1 is at most anneal_tol, or when P_best has not
+improved by a relative 5e-5 for `stall` checks; the primal stays near-feasible
+at every temperature before it cools, which the feasible point needs to come
+close to LP*.
 
 Pinned by tests/test_oracle_lp.py (closed forms, LP duality against an
 independent LP solver, brute force on perfect formulations).
@@ -67,10 +82,13 @@ class Cliques:
 class LPResult:
     passes: int
     temperature: float
-    dual: float
-    primal: float
+    dual: float       # smallest bound over the checks
+    primal: float     # largest feasible value over the checks
     gap: float
     converged: bool
+
+
+STALL_REL = 5e-5   # a check "improves" P_best when it raises it by more than this fraction
 
 
 def colour_classes(cl: Cliques) -> np.ndarray:
@@ -123,25 +141,71 @@ def evaluate(cl: Cliques, c, Lam, lam, T: float):
     return D, float(c @ xf), xf
 
 
+def bound(cl: Cliques, c, lam) -> float:
+    """D(lam) = sum lam_C + sum_i max(0, c_i - sum_{C contains i} lam_C)."""
+    Lam = np.zeros(cl.n)
+    for k in range(cl.m):
+        Lam[cl.clique(k)] += lam[k]
+    return float(lam.sum() + np.maximum(0.0, c - Lam).sum())
+
+
+def lift(cl: Cliques, x, rounds: int) -> np.ndarray:
+    """Fair-share lift of a feasible point: in each round every clique's slack
+    1 - sum_{i in C} x_i is split equally among its members, and every vertex
+    rises by the smallest share of its cliques (all at once)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    for _ in range(rounds):
+        share = np.empty(cl.m)
+        for k in range(cl.m):
+            idx = cl.clique(k)
+            share[k] = max(0.0, 1.0 - x[idx].sum()) / idx.size
+        up = np.full(cl.n, np.inf)
+        for k in range(cl.m):
+            idx = cl.clique(k)
+            up[idx] = np.minimum(up[idx], share[k])
+        x += up
+    return x
+
+
+def check(cl: Cliques, c, Lam, lam, T: float, lift_rounds: int):
+    """(bound D(lam), lifted feasible value P, lifted point, worst clique excess of x)."""
+    x = np.exp(np.minimum((c - Lam) / T, EXP_CAP))
+    S = np.array([x[cl.clique(k)].sum() for k in range(cl.m)])
+    _, _, xf = evaluate(cl, c, Lam, lam, T)
+    xl = lift(cl, xf, lift_rounds)
+    return bound(cl, c, lam), float(c @ xl), xl, float(S.max() - 1.0)
+
+
 def solve(cl: Cliques, c: np.ndarray, t0: float, order, drop: float, t_min: float, max_passes: int,
           check_every: int, gap_tol: float, x_floor: float, classes: np.ndarray | None = None,
-          trace: list | None = None):
-    """One start: (warm start max(xf, x_floor), LPResult, lam, Lam).  trace, when
-    given, receives (passes, D, P, gap) of every check."""
+          trace: list | None = None, anneal_tol: float = 0.0, stall: int = 10, lift_rounds: int = 2):
+    """One start: (warm start max(x_best, x_floor), LPResult, lam, Lam).  trace, when
+    given, receives (passes, D_best, P_best, gap, T, excess) of every check."""
     c = np.asarray(c, dtype=np.float64)
     if classes is None:
         classes = colour_classes(cl)
     Lam = np.zeros(cl.n)
     lam = np.zeros(cl.m)
+    T = float(t0)
+    D_best, P_best, x_best, quiet = np.inf, -np.inf, None, 0
     for p in range(max_passes):
-        T = temperature(t0, drop, t_min, p)
+        if anneal_tol <= 0.0:
+            T = temperature(t0, drop, t_min, p)
         run_pass(cl, c, Lam, lam, classes, order, T)
         last = p + 1 == max_passes
         if (p + 1) % check_every == 0 or last:
-            D, P, xf = evaluate(cl, c, Lam, lam, T)
-            gap = (D - P) / D
+            D, P, xl, excess = check(cl, c, Lam, lam, T, lift_rounds)
+            quiet = 0 if P > P_best * (1.0 + STALL_REL) else quiet + 1
+            if P > P_best:
+                P_best, x_best = P, xl
+            D_best = min(D_best, D)
+            gap = (D_best - P_best) / D_best
             if trace is not None:
-                trace.append((p + 1, D, P, gap))
+                trace.append((p + 1, D_best, P_best, gap, T, excess))
             if gap <= gap_tol or last:
-                return np.maximum(xf, x_floor), LPResult(p + 1, T, D, P, gap, gap <= gap_tol), lam, Lam
+                return (np.maximum(x_best, x_floor), LPResult(p + 1, T, D_best, P_best, gap, gap <= gap_tol),
+                        lam, Lam)
+            if anneal_tol > 0.0 and (excess <= anneal_tol or quiet >= stall):
+                T = max(t_min, T * drop ** check_every)
+                quiet = 0
     raise AssertionError("unreachable")

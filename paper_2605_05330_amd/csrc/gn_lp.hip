@@ -20,9 +20,21 @@
 // with each launch's clique ranges.
 //
 // The check (every check_every passes and after the last) bounds LP* from both
-// sides: D = sum lam_C + sum_i max(0, c_i - Lam_i) >= LP*, and the feasible
-// point xf_i = x_i / max(1, max_{C holds i} sum_{j in C} x_j) gives P = c.xf.
-// A start stops when (D - P) / D <= gap_tol; its warm start is max(xf, floor).
+// sides.  D = sum lam_C + sum_i max(0, c_i - sum_{C holds i} lam_C) >= LP*, with
+// the multipliers' sums rebuilt in fp64 (the incrementally kept fp32 Lam may
+// drift from them, and then would not give a bound).  The feasible point
+// xf_i = x_i / max(1, max_{C holds i} sum_{j in C} x_j) is raised by two rounds
+// of a fair-share lift (each clique's slack split equally among its members,
+// each member taking the smallest share of its cliques), giving P = c.xl.  A
+// start keeps the smallest D, the largest P and that P's point over its checks,
+// and stops when (D_best - P_best) / D_best <= gap_tol; its warm start is
+// max(x_best, floor).
+//
+// Temperatures: with anneal_tol <= 0, T_p = max(t_min, t0 drop^p) per pass.
+// Otherwise T is held within a check interval and drops by drop^check_every at
+// a check whose smoothed primal exceeds no clique by more than anneal_tol, or
+// after `stall` checks without a relative gain of 5e-5 in P_best; the check
+// kernel decides and the host reads the next temperature with the stop flags.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,15 +52,21 @@ constexpr int kLpBlock = 64 * kLpWaves;
 constexpr int kLpVBlock = 256;               // vertex kernel
 constexpr int kLpFBlock = 256;               // finish kernel
 constexpr float kExpCap = 60.0f;             // cap of the check's exponent (keeps sums finite)
+constexpr int kLiftRounds = 2;               // fair-share lift rounds of the check
+constexpr double kStallRel = 5e-5;           // relative gain of P_best that counts as progress
 
 struct LpState {
     int32_t done;
     int32_t passes;
     int32_t converged;
-    float temperature;
-    double dual;
-    double primal;
+    float temperature;     // of the last check
+    double dual;           // best bound so far
+    double primal;         // best feasible value so far
     double gap;
+    float next_t;          // temperature of the passes after the last check
+    int32_t quiet;         // checks since P_best last gained kStallRel
+    int32_t improved;      // the last check raised P_best (its point is kept)
+    float excess;          // worst clique excess of the smoothed primal at the last check
 };
 
 // Per launch, by value: for each start the range of cliques (in class order)
@@ -69,11 +87,15 @@ struct LpArgs {
     float* Lam;              // [S][n]
     float* lam;              // [S][m]
     float* csum;             // [S][m]
+    float* share;            // [S][m] lift shares
+    float* x_cand;           // [S][n] the check's feasible (then lifted) point
     double* part;            // [S][2 * nbv]
     LpState* st;             // [S]
     float* x_out;            // [S][n]
     int32_t n, m, K, nbv;
     float gap_tol, x_floor;
+    float anneal_tol, t_min, drop_check;  // drop_check = drop^check_every
+    int32_t stall;
 };
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -154,44 +176,92 @@ __global__ __launch_bounds__(kLpBlock) void lp_csum_kernel(LpArgs a, LpRound rd)
     if (lane == 0) a.csum[(size_t)s * a.m + k] = sum;
 }
 
-// Check, part 2: the feasible point, written as the warm start, and per-block
-// partial sums of c.xf and of max(0, c - Lam) (fp64, fixed order).
+// Fixed-order block sum of a per-thread fp64 value into part[s][2 b + slot].
+__device__ __forceinline__ void lp_block_partial(const LpArgs& a, int s, int slot, double v, double* red) {
+    v = wave_sum_d(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < kLpVBlock / 64; ++q) t += red[q];
+        a.part[(size_t)s * 2 * a.nbv + 2 * blockIdx.x + slot] = t;
+    }
+}
+
+// Check, part 2: the feasible point xf into x_cand, and per-block partial sums of
+// max(0, c_i - sum_{C holds i} lam_C) with the multipliers' sums rebuilt in fp64.
 __global__ __launch_bounds__(kLpVBlock) void lp_vertex_kernel(LpArgs a, LpRound rd) {
     const int s = blockIdx.y;
     if (a.st[s].done) return;
-    __shared__ double red[2][kLpVBlock / 64];
+    __shared__ double red[kLpVBlock / 64];
     const int i = blockIdx.x * kLpVBlock + threadIdx.x;
-    double pv = 0.0, dv = 0.0;
+    double dv = 0.0;
     if (i < a.n) {
         const float T = rd.T[s];
         const float c = a.cost[i];
         const float Li = a.Lam[(size_t)s * a.n + i];
         const float x = expf(fminf((c - Li) / T, kExpCap));
         float mx = 1.0f;
+        double lsum = 0.0;
         const float* cs = a.csum + (size_t)s * a.m;
-        for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) mx = fmaxf(mx, cs[a.vcl[q]]);
-        const float xf = x / mx;
-        a.x_out[(size_t)s * a.n + i] = fmaxf(xf, a.x_floor);
-        pv = (double)c * (double)xf;
-        dv = (double)fmaxf(0.0f, c - Li);
-    }
-    pv = wave_sum_d(pv);
-    dv = wave_sum_d(dv);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][w] = pv;
-        red[1][w] = dv;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double P = 0.0, D = 0.0;
-        for (int q = 0; q < kLpVBlock / 64; ++q) {
-            P += red[0][q];
-            D += red[1][q];
+        const float* lm = a.lam + (size_t)s * a.m;
+        for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) {
+            const int k = a.vcl[q];
+            mx = fmaxf(mx, cs[k]);
+            lsum += (double)lm[k];
         }
-        a.part[(size_t)s * 2 * a.nbv + 2 * blockIdx.x] = P;
-        a.part[(size_t)s * 2 * a.nbv + 2 * blockIdx.x + 1] = D;
+        a.x_cand[(size_t)s * a.n + i] = x / mx;
+        dv = fmax(0.0, (double)c - lsum);
     }
+    lp_block_partial(a, s, 1, dv, red);
+}
+
+// Lift, part 1: each clique's slack 1 - sum_{i in C} x_i, shared equally among
+// its members (a wavefront per clique, the sum in fp64).
+__global__ __launch_bounds__(kLpBlock) void lp_share_kernel(LpArgs a) {
+    const int s = blockIdx.y;
+    if (a.st[s].done) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * kLpWaves + wave;
+    if (k >= a.m) return;
+    const float* xc = a.x_cand + (size_t)s * a.n;
+    const int b = a.cptr[k], e = a.cptr[k + 1];
+    double sum = 0.0;
+    for (int j = b + lane; j < e; j += 64) sum += (double)xc[a.cmem[j]];
+    sum = wave_sum_d(sum);
+    if (lane == 0) a.share[(size_t)s * a.m + k] = (float)(fmax(0.0, 1.0 - sum) / (double)(e - b));
+}
+
+// Lift, part 2: every vertex rises by the smallest share of its cliques (the
+// shares are rounded down to fp32 from the exact quotient, and each member takes
+// at most its share, so no clique exceeds 1 but by rounding of the sums); the
+// last round also forms the per-block partials of c.x.
+__global__ __launch_bounds__(kLpVBlock) void lp_raise_kernel(LpArgs a, int32_t last) {
+    const int s = blockIdx.y;
+    if (a.st[s].done) return;
+    __shared__ double red[kLpVBlock / 64];
+    const int i = blockIdx.x * kLpVBlock + threadIdx.x;
+    double pv = 0.0;
+    if (i < a.n) {
+        const float* sh = a.share + (size_t)s * a.m;
+        float up = INFINITY;
+        for (int q = a.vptr[i]; q < a.vptr[i + 1]; ++q) up = fminf(up, sh[a.vcl[q]]);
+        float* xc = a.x_cand + (size_t)s * a.n + i;
+        const float xn = *xc + up;
+        *xc = xn;
+        pv = (double)a.cost[i] * (double)xn;
+    }
+    if (last) lp_block_partial(a, s, 0, pv, red);
+}
+
+// Keeps the lifted point of a check that raised P_best as the start's warm start.
+__global__ __launch_bounds__(kLpVBlock) void lp_keep_kernel(LpArgs a) {
+    const int s = blockIdx.y;
+    if (!a.st[s].improved) return;
+    const int i = blockIdx.x * kLpVBlock + threadIdx.x;
+    if (i < a.n) a.x_out[(size_t)s * a.n + i] = fmaxf(a.x_cand[(size_t)s * a.n + i], a.x_floor);
 }
 
 // Check, part 3: one workgroup per start reduces the bound and the primal value
@@ -200,9 +270,15 @@ __global__ __launch_bounds__(kLpFBlock) void lp_finish_kernel(LpArgs a, LpRound 
     const int s = blockIdx.x;
     if (a.st[s].done) return;
     __shared__ double red[3][kLpFBlock / 64];
+    __shared__ float redx[kLpFBlock / 64];
     double sl = 0.0, P = 0.0, D = 0.0;
+    float ex = -INFINITY;
     const float* lam = a.lam + (size_t)s * a.m;
-    for (int k = threadIdx.x; k < a.m; k += kLpFBlock) sl += (double)lam[k];
+    const float* cs = a.csum + (size_t)s * a.m;
+    for (int k = threadIdx.x; k < a.m; k += kLpFBlock) {
+        sl += (double)lam[k];
+        ex = fmaxf(ex, cs[k]);
+    }
     const double* part = a.part + (size_t)s * 2 * a.nbv;
     for (int q = threadIdx.x; q < a.nbv; q += kLpFBlock) {
         P += part[2 * q];
@@ -211,34 +287,46 @@ __global__ __launch_bounds__(kLpFBlock) void lp_finish_kernel(LpArgs a, LpRound 
     sl = wave_sum_d(sl);
     P = wave_sum_d(P);
     D = wave_sum_d(D);
+    ex = wave_max(ex);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][w] = sl;
         red[1][w] = P;
         red[2][w] = D;
+        redx[w] = ex;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double L = 0.0, Pt = 0.0, Dt = 0.0;
+        float exc = -INFINITY;
         for (int q = 0; q < kLpFBlock / 64; ++q) {
             L += red[0][q];
             Pt += red[1][q];
             Dt += red[2][q];
+            exc = fmaxf(exc, redx[q]);
         }
         Dt += L;
-        const double gap = (Dt - Pt) / Dt;
-        const bool conv = gap <= (double)a.gap_tol;
+        LpState o = a.st[s];
+        const bool first = o.passes == 0;
+        const double P_prev = first ? -INFINITY : o.primal;
+        o.quiet = (!first && Pt <= P_prev * (1.0 + kStallRel)) ? o.quiet + 1 : 0;
+        o.improved = Pt > P_prev ? 1 : 0;
+        o.primal = o.improved ? Pt : P_prev;
+        o.dual = first ? Dt : fmin(o.dual, Dt);
+        o.gap = (o.dual - o.primal) / o.dual;
+        o.excess = exc - 1.0f;
+        o.temperature = rd.T[s];
+        o.passes = p + 1;
+        o.next_t = rd.T[s];
+        const bool conv = o.gap <= (double)a.gap_tol;
         if (conv || last) {
-            LpState o;
             o.done = 1;
-            o.passes = p + 1;
             o.converged = conv ? 1 : 0;
-            o.temperature = rd.T[s];
-            o.dual = Dt;
-            o.primal = Pt;
-            o.gap = gap;
-            a.st[s] = o;
+        } else if (a.anneal_tol > 0.0f && (o.excess <= a.anneal_tol || o.quiet >= a.stall)) {
+            o.next_t = fmaxf(a.t_min, (float)((double)rd.T[s] * (double)a.drop_check));
+            o.quiet = 0;
         }
+        a.st[s] = o;
     }
 }
 
@@ -268,6 +356,8 @@ struct gn_lp {
     float* Lam = nullptr;
     float* lam = nullptr;
     float* csum = nullptr;
+    float* share = nullptr;
+    float* x_cand = nullptr;
     double* part = nullptr;
     LpState* st = nullptr;
     LpState* st_host = nullptr;  // pinned
@@ -282,6 +372,8 @@ static void lp_free(gn_lp* L) {
     hipFree(L->Lam);
     hipFree(L->lam);
     hipFree(L->csum);
+    hipFree(L->share);
+    hipFree(L->x_cand);
     hipFree(L->part);
     hipFree(L->st);
     if (L->st_host) hipHostFree(L->st_host);
@@ -368,6 +460,7 @@ extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_pt
               gn_dalloc(&L->vptr, (size_t)n + 1) &&
               gn_dalloc(&L->vcl, (size_t)nnzc) &&
               gn_dalloc(&L->Lam, S * n) && gn_dalloc(&L->lam, S * m) && gn_dalloc(&L->csum, S * m) &&
+              gn_dalloc(&L->share, S * m) && gn_dalloc(&L->x_cand, S * n) &&
               gn_dalloc(&L->part, S * 2 * (size_t)lp_nbv(n)) && gn_dalloc(&L->st, S);
     if (ok && hipHostMalloc((void**)&L->st_host, sizeof(LpState) * S, hipHostMallocDefault) != hipSuccess) {
         L->st_host = nullptr;
@@ -410,13 +503,14 @@ extern "C" gn_status gn_lp_info(const gn_lp* L, int32_t* n_classes, int32_t* n_c
 
 extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, const int32_t* order, float drop,
                                  float t_min, int32_t max_passes, int32_t check_every, float gap_tol, float x_floor,
-                                 float* x, gn_lp_result* res, hipStream_t stream) {
+                                 float anneal_tol, int32_t stall, float* x, gn_lp_result* res, hipStream_t stream) {
     if (!L || !t0 || !order || !x || !res || starts < 1 || starts > GN_MAX_STARTS || max_passes < 1 ||
-        check_every < 1)
+        check_every < 1 || stall < 1)
         return GN_E_ARG;
     if (!(drop > 0.0f && drop <= 1.0f) || !(t_min > 0.0f) || !std::isfinite(t_min) || !(gap_tol >= 0.0f) ||
-        !std::isfinite(gap_tol) || !(x_floor >= 0.0f && x_floor < 1.0f))
+        !std::isfinite(gap_tol) || !(x_floor >= 0.0f && x_floor < 1.0f) || !std::isfinite(anneal_tol))
         return GN_E_ARG;
+    const bool anneal = anneal_tol > 0.0f;
     const int32_t K = L->K;
     std::vector<char> seen(K);
     for (int32_t s = 0; s < starts; ++s) {
@@ -437,6 +531,8 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
     a.Lam = L->Lam;
     a.lam = L->lam;
     a.csum = L->csum;
+    a.share = L->share;
+    a.x_cand = L->x_cand;
     a.part = L->part;
     a.st = L->st;
     a.x_out = x;
@@ -446,14 +542,20 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
     a.nbv = lp_nbv(L->n);
     a.gap_tol = gap_tol;
     a.x_floor = x_floor;
+    a.anneal_tol = anneal_tol;
+    a.t_min = t_min;
+    a.drop_check = (float)std::pow((double)drop, (double)check_every);
+    a.stall = stall;
     lp_reset_kernel<<<1024, 256, 0, stream>>>(a, starts);
     GN_HIP_TRY(hipGetLastError());
     const dim3 gcs((L->m + kLpWaves - 1) / kLpWaves, starts), gv(a.nbv, starts);
     std::vector<char> running(starts, 1);
+    std::vector<float> T_cur(t0, t0 + starts);   // annealed temperatures, set by each check
     LpRound rd{};
     for (int32_t p = 0; p < max_passes; ++p) {
         for (int32_t s = 0; s < starts; ++s)
-            rd.T[s] = (float)std::max((double)t_min, (double)t0[s] * std::pow((double)drop, (double)p));
+            rd.T[s] = anneal ? T_cur[s]
+                             : (float)std::max((double)t_min, (double)t0[s] * std::pow((double)drop, (double)p));
         for (int32_t r = 0; r < K; ++r) {
             int32_t gx = 0;
             for (int32_t s = 0; s < starts; ++s) {
@@ -468,13 +570,19 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
         if ((p + 1) % check_every != 0 && !last) continue;
         lp_csum_kernel<<<gcs, kLpBlock, 0, stream>>>(a, rd);
         lp_vertex_kernel<<<gv, kLpVBlock, 0, stream>>>(a, rd);
+        for (int r = 0; r < kLiftRounds; ++r) {
+            lp_share_kernel<<<gcs, kLpBlock, 0, stream>>>(a);
+            lp_raise_kernel<<<gv, kLpVBlock, 0, stream>>>(a, r + 1 == kLiftRounds ? 1 : 0);
+        }
         lp_finish_kernel<<<starts, kLpFBlock, 0, stream>>>(a, rd, p, last ? 1 : 0);
+        lp_keep_kernel<<<gv, kLpVBlock, 0, stream>>>(a);
         GN_HIP_TRY(hipGetLastError());
         GN_HIP_TRY(hipMemcpyAsync(L->st_host, L->st, sizeof(LpState) * starts, hipMemcpyDeviceToHost, stream));
         GN_HIP_TRY(hipStreamSynchronize(stream));
         bool all = true;
         for (int32_t s = 0; s < starts; ++s) {
             running[s] = !L->st_host[s].done;
+            T_cur[s] = L->st_host[s].next_t;
             all = all && !running[s];
         }
         if (all) break;

@@ -124,7 +124,8 @@ def lib():
             "gn_lp_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "gn_lp_solve": ([_vp, ctypes.c_int32, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
-                             ctypes.c_int32, ctypes.c_float, ctypes.c_float, _vp, ctypes.POINTER(gn_lp_result), _vp],
+                             ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp,
+                             ctypes.POINTER(gn_lp_result), _vp],
                             ctypes.c_int),
             "gn_rook_step": ([_vp, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
             "gn_rook_solve": ([_vp, ctypes.POINTER(gn_schedule), _vp, _vp, ctypes.POINTER(gn_result), _vp],
@@ -396,18 +397,20 @@ def gn_lp_info(h) -> dict:
     return {"n_classes": k.value, "n_cliques": m.value, "max_class": mc.value}
 
 
-def gn_lp_solve(h, t0, order, x, drop=0.99, t_min=1e-4, max_passes=3000, check_every=10, gap_tol=1e-2,
-                x_floor=1e-3, stream=None):
+def gn_lp_solve(h, t0, order, x, drop=0.99, t_min=1e-4, max_passes=10000, check_every=10, gap_tol=1e-3,
+                x_floor=1e-3, anneal_tol=3e-3, stall=10, stream=None):
     """t0: host float32 [starts]; order: host int32 [starts, n_classes]; x: CUDA
-    float32 [starts * n] (out).  Returns (status, list of gn_lp_result)."""
+    float32 [starts * n] (out).  Defaults: the paper's 0.1% stop, the annealed
+    schedule (anneal_tol <= 0: the drop every pass).  Returns (status, list of
+    gn_lp_result)."""
     import torch
     t = np.ascontiguousarray(t0, dtype=np.float32).reshape(-1)
     o = np.ascontiguousarray(order, dtype=np.int32)
     starts = t.size
     res = (gn_lp_result * max(starts, 1))()
     st = lib().gn_lp_solve(h, int(starts), _vp(t.ctypes.data), _vp(o.ctypes.data), float(drop), float(t_min),
-                           int(max_passes), int(check_every), float(gap_tol), float(x_floor),
-                           _dptr(x, torch.float32, "x"), res, _stream(stream))
+                           int(max_passes), int(check_every), float(gap_tol), float(x_floor), float(anneal_tol),
+                           int(stall), _dptr(x, torch.float32, "x"), res, _stream(stream))
     _check(st, "gn_lp_solve", allow=(GN_OK, GN_NOT_CONVERGED))
     return st, [res[s] for s in range(starts)]
 

@@ -53,7 +53,7 @@ def _gpu(inst, c, t0, orders, **kw):
 ])
 def test_fixed_passes_match_oracle(gpu, n, items, klo, khi, starts, seed):
     inst, c = _instance(n, items, klo, khi, seed)
-    kw = dict(drop=0.95, t_min=1e-3, max_passes=60, check_every=20, gap_tol=0.0, x_floor=1e-3)
+    kw = dict(drop=0.95, t_min=1e-3, max_passes=60, check_every=20, gap_tol=0.0, x_floor=1e-3, anneal_tol=0.0)
     libgn = _lib()
     L = libgn.LP(inst.n, inst.ptr, inst.members, c)
     K = L.info["n_classes"]
@@ -83,6 +83,7 @@ def test_single_clique_softmax_and_singletons(gpu):
     x = torch.empty(n, dtype=torch.float32, device="cuda")
     st, res = L.solve(np.array([0.3], np.float32), np.zeros((1, 1), np.int32), x, max_passes=1, check_every=1,
                       gap_tol=0.0, x_floor=0.0)
+    # the clique sums to 1: the lift has no slack to hand out
     e = np.exp((c.astype(np.float64) - c.max()) / np.float64(np.float32(0.3)))
     np.testing.assert_allclose(x.cpu().numpy(), e / e.sum(), rtol=1e-5, atol=1e-9)
     S = libgn.LP(n, np.arange(n + 1), np.arange(n), c)
@@ -95,11 +96,10 @@ def test_single_clique_softmax_and_singletons(gpu):
 
 
 def test_stopping_pass_and_duality_at_benchmark_size(gpu):
-    """10,000 routes and 2,000 stops (the benchmark's instance), 16 starts to a 1%
-    gap: D >= LP* >= P against HiGHS and the returned point is feasible
-    (x_floor = 0) for every start; for start 0, D and P at the GPU's stopping
-    pass match the oracle's at that pass, whose gap is within 5% of the
-    tolerance on the right side there and one check earlier."""
+    """10,000 routes and 2,000 stops (the benchmark's instance), 16 starts, the
+    annealed schedule to the paper's 0.1% gap: every start converges, with
+    D_best >= LP* >= P_best against HiGHS, P_best = c.x of the returned point, and
+    that point feasible (x_floor = 0)."""
     from scipy.optimize import linprog
     from scipy.sparse import csr_matrix
     inst, c = _instance(10000, 2000, 3, 8, 0)
@@ -108,8 +108,9 @@ def test_stopping_pass_and_duality_at_benchmark_size(gpu):
     K = L.info["n_classes"]
     orders = inputs.class_orders(16, K, 0)
     t0 = inputs.jittered_temperatures(16, 1.0, 1.1, 0)
-    tol = 1e-2
-    kw = dict(drop=0.99, t_min=1e-4, max_passes=3000, check_every=10, gap_tol=tol, x_floor=0.0)
+    tol = 1e-3
+    kw = dict(drop=0.99, t_min=1e-4, max_passes=10000, check_every=10, gap_tol=tol, x_floor=0.0,
+              anneal_tol=3e-3, stall=10)
     _, st, res, x = _gpu(inst, c, t0, orders, **kw)
     assert st == libgn.GN_OK
     A = csr_matrix((np.ones(inst.members.size), inst.members, inst.ptr), shape=(inst.m, inst.n))
@@ -120,15 +121,31 @@ def test_stopping_pass_and_duality_at_benchmark_size(gpu):
         assert res[s].dual >= opt * (1 - 1e-5) and res[s].primal <= opt * (1 + 1e-5)
         assert res[s].primal == pytest.approx(float(c.astype(np.float64) @ x[s]), rel=1e-5)
         assert (A @ x[s].astype(np.float64)).max() <= 1 + 1e-5
-    trace = []
-    pg = res[0].passes
-    _oracle(inst, c, t0[0], orders[0], **dict(kw, max_passes=pg, gap_tol=0.0), trace=trace)
-    passes, D, P, gap = trace[-1]
-    assert passes == pg
-    assert res[0].dual == pytest.approx(D, rel=1e-3) and res[0].primal == pytest.approx(P, rel=1e-3)
-    assert gap <= tol * 1.05
-    if len(trace) > 1:
-        assert trace[-2][3] > tol * 0.95
+    print("passes", [r_.passes for r_ in res], "LP*", opt, "best bound", min(r_.dual for r_ in res))
+
+
+def test_annealed_passes_match_oracle(gpu):
+    """The annealed schedule on a small instance, GPU against the oracle: the same
+    temperature decisions over 300 passes (the excess and stall tests are far from
+    their thresholds on this instance at every check but where both agree), the
+    best bound and value within 1e-4."""
+    inst, c = _instance(400, 90, 2, 4, 5)
+    libgn = _lib()
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    K = L.info["n_classes"]
+    orders = inputs.class_orders(2, K, 5)
+    t0 = inputs.jittered_temperatures(2, 1.0, 1.1, 5)
+    kw = dict(drop=0.99, t_min=1e-4, max_passes=300, check_every=10, gap_tol=0.0, x_floor=1e-3,
+              anneal_tol=3e-3, stall=10)
+    _, st, res, x = _gpu(inst, c, t0, orders, **kw)
+    for s in range(2):
+        trace = []
+        xo, ro, _, _ = _oracle(inst, c, t0[s], orders[s], trace=trace, **kw)
+        assert res[s].passes == ro.passes == 300
+        assert res[s].temperature == pytest.approx(ro.temperature, rel=1e-4)
+        assert res[s].dual == pytest.approx(ro.dual, rel=1e-4)
+        assert res[s].primal == pytest.approx(ro.primal, rel=1e-4)
+        np.testing.assert_allclose(x[s], xo, rtol=3e-3, atol=1e-5)
 
 
 def test_warm_start_feeds_multi_start(gpu):
@@ -142,7 +159,7 @@ def test_warm_start_feeds_multi_start(gpu):
     orders = inputs.class_orders(starts, L.info["n_classes"], 3)
     t0 = inputs.jittered_temperatures(starts, 1.0, 1.1, 3)
     x = torch.empty(starts * inst.n, dtype=torch.float32, device="cuda")
-    st, res = L.solve(t0, orders, x)
+    st, res = L.solve(t0, orders, x, gap_tol=1e-2, max_passes=4000)
     assert st == libgn.GN_OK
     G = libgn.Graph(inst.n, inst.graph.row_ptr, inst.graph.col_idx, c)
     sel = torch.zeros(starts * inst.n, dtype=torch.uint8, device="cuda")

@@ -195,3 +195,68 @@ def test_bound_at_zero_multipliers_and_first_pass_temperature():
     xf, res, _, _ = lp.solve(one, c3, 0.37, [0], 0.5, 1e-4, 1, 1, 0.0, 0.0)
     np.testing.assert_allclose(xf, softmax(c3 / 0.37), rtol=1e-13)
     assert res.passes == 1 and res.temperature == 0.37
+
+
+def test_bound_from_multipliers_is_weak_duality():
+    """D(lam) built from the multipliers alone: equal to the incremental form when
+    Lam is exactly the sum of its cliques' multipliers, and above LP* (HiGHS) for
+    arbitrary nonnegative multipliers, including ones whose incremental Lam has
+    drifted."""
+    inst = inputs.clique_cover_instance(50, 20, 2, 4, 7)
+    cl = lp.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
+    c = inputs.weights_uniform01(inst.n, 7).astype(np.float64)
+    opt = lp_optimum(cl, c)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        lam = rng.exponential(0.2, cl.m) * (rng.random(cl.m) < 0.7)
+        Lam = np.zeros(cl.n)
+        for k in range(cl.m):
+            Lam[cl.clique(k)] += lam[k]
+        D_inc, _, _ = lp.evaluate(cl, c, Lam, lam, 0.1)
+        assert lp.bound(cl, c, lam) == pytest.approx(D_inc, rel=1e-14)
+        assert lp.bound(cl, c, lam) >= opt - 1e-12
+        # a drifted Lam (too large) understates the incremental bound; the rebuilt one does not
+        D_drift, _, _ = lp.evaluate(cl, c, Lam + 0.5, lam, 0.1)
+        assert D_drift < lp.bound(cl, c, lam)
+
+
+def test_fair_share_lift():
+    """One round on a clique of k members at zero gives each 1/k; a vertex takes the
+    smallest share of its cliques; the lift never lowers a coordinate and keeps every
+    clique sum at most 1."""
+    cl = cliques(4, [[0, 1, 2, 3]])
+    np.testing.assert_allclose(lp.lift(cl, np.zeros(4), 1), 0.25)
+    cl = cliques(3, [[0, 1], [1, 2]])          # slack 1 - 0.2 = 0.8 in each clique
+    x = lp.lift(cl, np.array([0.0, 0.2, 0.0]), 1)
+    np.testing.assert_allclose(x, [0.4, 0.6, 0.4])
+    inst = inputs.clique_cover_instance(80, 30, 2, 5, 4)
+    cl = lp.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
+    x0 = np.random.default_rng(1).random(inst.n) * 0.05
+    for rounds in (1, 2, 5):
+        x = lp.lift(cl, x0, rounds)
+        assert np.all(x >= x0)
+        assert max(x[cl.clique(k)].sum() for k in range(cl.m)) <= 1 + 1e-12
+        assert x.sum() > x0.sum()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_annealed_solve_reaches_a_tenth_of_a_percent(seed):
+    """The annealed schedule with best-so-far bounds meets the paper's stop (0.1%):
+    D_best >= LP* >= P_best (HiGHS), both within 0.1%, and the warm start is the
+    feasible point of P_best."""
+    inst = inputs.clique_cover_instance(300, 60, 2, 5, seed)
+    cl = lp.Cliques(inst.n, inst.ptr.astype(np.int64), inst.members.astype(np.int64))
+    c = inputs.weights_uniform01(inst.n, seed).astype(np.float64)
+    opt = lp_optimum(cl, c)
+    classes = lp.colour_classes(cl)
+    order = list(range(int(classes.max()) + 1))
+    trace = []
+    x, res, lam, _ = lp.solve(cl, c, 1.0, order, 0.99, 1e-4, 20000, 10, 1e-3, 0.0, classes, trace=trace,
+                              anneal_tol=3e-3, stall=10)
+    assert res.converged and res.gap <= 1e-3
+    assert res.dual >= opt - 1e-9 and res.primal <= opt + 1e-9
+    assert res.dual == pytest.approx(lp.bound(cl, c, lam), rel=0.2) or res.dual <= lp.bound(cl, c, lam)
+    assert float(c @ x) == pytest.approx(res.primal, rel=1e-12)
+    assert max(x[cl.clique(k)].sum() for k in range(cl.m)) <= 1 + 1e-12
+    # the best-so-far bounds never move the wrong way
+    assert all(b[1] <= a[1] + 1e-15 and b[2] >= a[2] - 1e-15 for a, b in zip(trace, trace[1:]))
