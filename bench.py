@@ -389,6 +389,7 @@ def bench_lp(with_oracle=True):
     orders = I.class_orders(S, K, 0)
     t0 = I.jittered_temperatures(S, 1.0, 1.1, 0)
     x = torch.empty(S * inst.n, dtype=torch.float32, device="cuda")
+    fused = L.set_fused(True)
     L.solve(t0, orders, x)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -396,6 +397,16 @@ def bench_lp(with_oracle=True):
     lp_ms = (time.perf_counter() - t) * 1e3
     passes = [r.passes for r in res]
     bound = min(r.dual for r in res)
+    # the same solve with one launch per clique class (the multipliers in global memory)
+    L.set_fused(False)
+    x_pc = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, res_pc = L.solve(t0, orders, x_pc)
+    pc_ms = (time.perf_counter() - t) * 1e3
+    L.set_fused(True)
+    same = bool(torch.equal(x, x_pc)) and all(a.passes == b.passes and a.dual == b.dual and a.primal == b.primal
+                                              for a, b in zip(res, res_pc))
     G = libgn.Graph(inst.n, inst.graph.row_ptr, inst.graph.col_idx, c)
     sched = libgn.make_schedule(0.9, 1.5, 1000, 2000, 1e-4, 1)
     sel = torch.zeros(S * inst.n, dtype=torch.uint8, device="cuda")
@@ -416,9 +427,12 @@ def bench_lp(with_oracle=True):
     libgn.gn_random_starts(G.handle, S, u, xr)
     out = {"instance": {"routes": inst.n, "stops": inst.m, "memberships": int(inst.members.size),
                         "conflict_edges": inst.graph.nnz // 2, "clique_classes": K},
-           "lp": {"starts": S, "ms": lp_ms, "passes_min": min(passes), "passes_max": max(passes),
-                  "us_per_pass": lp_ms * 1e3 / max(passes), "gap_max": max(r.gap for r in res),
-                  "best_bound": bound, "converged": int(sum(r.converged for r in res))},
+           "lp": {"starts": S, "fused_passes": fused, "ms": lp_ms, "passes_min": min(passes),
+                  "passes_max": max(passes), "us_per_pass": lp_ms * 1e3 / max(passes),
+                  "gap_max": max(r.gap for r in res), "best_bound": bound,
+                  "converged": int(sum(r.converged for r in res)),
+                  "per_class_launches": {"ms": pc_ms, "us_per_pass": pc_ms * 1e3 / max(passes),
+                                         "same_bits": same}},
            "gn_from_lp": gn_from(x), "gn_from_random": gn_from(xr)}
     # the same LP points through the hyperedge form (the stops as hyperedges)
     H = libgn.Hyper(inst.n, inst.ptr, inst.members, c)

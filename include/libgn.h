@@ -517,6 +517,16 @@ void gn_lp_destroy(gn_lp* lp);
  * the size of the largest class.  Any output may be NULL. */
 gn_status gn_lp_info(const gn_lp* lp, int32_t* n_classes, int32_t* n_cliques, int32_t* max_class);
 
+/* How the passes run (testing and tuning control; results are the same bits
+ * either way).  Fused (enable = 1, the default): one workgroup per start keeps
+ * Lam and lam in LDS and runs every pass up to the next check in one launch,
+ * the classes separated by workgroup barriers; available when the instance's
+ * 4 (n + m + 2 n_classes + 1) bytes fit one CU's LDS (158 KiB).  Otherwise, or
+ * with enable = 0: one launch per class for all starts, the multipliers in
+ * global memory.  Returns 1 when solves will run fused, 0 when not, -1 for a
+ * NULL handle.  Not thread-safe against a concurrent solve on the handle. */
+int32_t gn_lp_set_fused(gn_lp* lp, int32_t enable);
+
 /* Run `starts` (1..GN_MAX_STARTS) independent solves.  t0: host float[starts],
  * finite and > 0; order: host int32[starts * n_classes], row s a permutation of
  * the classes; drop in (0, 1]; t_min > 0; max_passes >= 1; check_every >= 1;

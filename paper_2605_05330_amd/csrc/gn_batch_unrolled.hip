@@ -159,12 +159,11 @@ __device__ void unrolled_fwd_graph(const UnrolledArgs& a, const BatchDesc& d, fl
                 const float yraw = yin[i];
                 const float yi = fabsf(yraw);
                 const float s = __fmaf_rn(g, sigma, yi);
-                float xn;
-                const float yn = gnk::step_word(yraw, p.v, s, xn);
+                const float yn = gnk::step_word(yraw, p.v, s);
                 ys[i] = yraw;
                 ss[i] = s;
                 yout[i] = yn;
-                if (xT) xT[perm[i]] = xn;
+                if (xT) xT[perm[i]] = gnk::step_x(yraw, p.v, s, yn);
             });
         __syncthreads();
         float* tmp = yin;

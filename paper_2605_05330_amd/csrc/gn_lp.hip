@@ -13,11 +13,20 @@
 //
 // Cliques are coloured first-fit into classes of vertex-disjoint cliques at
 // creation; a pass visits the classes in the start's order (the caller's
-// permutation), one launch per class for all starts together, a wavefront per
-// clique.  Disjointness makes the members' Lam updates race-free and the result
-// independent of the order inside a class.  Pass p runs at
-// T_p = max(t_min, t0 drop^p), computed on the host in fp64 and passed by value
-// with each launch's clique ranges.
+// permutation).  Disjointness makes the members' Lam updates race-free and the
+// result independent of the order inside a class.  Pass p runs at
+// T_p = max(t_min, t0 drop^p), computed on the host in fp64 and passed by value.
+// Two ways to run the passes, with the same arithmetic and so the same bits:
+//   * fused: when Lam and lam of a start fit one CU's LDS, one workgroup per
+//     start runs all passes up to the next check in one launch, its multipliers
+//     in LDS and the classes separated by workgroup barriers.  The cliques of a
+//     class are dealt to the wavefronts as tasks laid out at creation (a clique
+//     of up to 64 members per wavefront, or two of up to 32, one per half; the
+//     member ids and costs in lane order), and each wavefront loads its next
+//     task while it works on the current one, so a class costs LDS and
+//     arithmetic latency only;
+//   * per class: one launch per class for all starts together, a wavefront per
+//     clique, the multipliers in global memory.
 //
 // The check (every check_every passes and after the last) bounds LP* from both
 // sides.  D = sum lam_C + sum_i max(0, c_i - sum_{C holds i} lam_C) >= LP*, with
@@ -76,6 +85,8 @@ struct LpRound {
     int32_t beg[GN_MAX_STARTS];
     int32_t end[GN_MAX_STARTS];
     float T[GN_MAX_STARTS];
+    float r2[GN_MAX_STARTS];  // log2(e) / T, rounded once from fp64
+    float tl[GN_MAX_STARTS];  // T ln 2, rounded once from fp64
 };
 
 struct LpArgs {
@@ -113,6 +124,60 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
+// Butterfly reductions of the clique updates, over a half (32 lanes) or the
+// whole wavefront, with the stages in increasing xor distance 1, 2, 4, 8, 16
+// (, 32).  After the stages below 2^k every aligned block of 2^k lanes holds
+// one value (max and fp32 addition commute), so at distance 4 and 8 any
+// permutation that swaps the two halves of each block of 8 and 16 reads the
+// same value as the xor partner: the DPP row half-mirror and row mirror do
+// it without the LDS crossbar, quad permutations do distances 1 and 2, a
+// swizzle 16 and a permute 32.  Every lane ends with the group's value.
+//
+// The clique update's log-sum-exp runs in base 2, on a_i = (c_i - Lam_i) r2
+// with r2 = log2(e) / T: lam' = max(0, lam + T ln2 (max a + log2 sum 2^(a_i -
+// max a))), the hardware exp2 and log2 on arguments where they are accurate
+// (exponents <= 0, a sum >= 1), instead of a division, expf and logf per
+// member.  r2 and T ln2 are rounded once from fp64 on the host.
+// The maximum runs on order-preserving integer keys (for non-NaN floats the
+// key k = b ^ ((b >> 31) & 0x7fffffff) of the bits b orders as the value), so
+// that every DPP stage is one integer max; the sum's DPP stages are one add
+// each.  No lane reads outside its row in these patterns, so the DPP bound
+// control changes nothing.
+__device__ __forceinline__ int lp_key(float v) {
+    const int b = __float_as_int(v);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float lp_unkey(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+
+template <bool MAX>
+__device__ __forceinline__ float lp_reduce(float v, bool full);
+
+template <>
+__device__ __forceinline__ float lp_reduce<false>(float v, bool full) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // xor 1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // xor 2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));  // 4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));  // 8
+    v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));                   // xor 16
+    const float t = __shfl_xor(v, 32, 64);
+    return full ? v + t : v;
+}
+
+template <>
+__device__ __forceinline__ float lp_reduce<true>(float v, bool full) {
+    int k = lp_key(v);
+    k = max(k, __builtin_amdgcn_update_dpp(0, k, 0xB1, 0xF, 0xF, true));
+    k = max(k, __builtin_amdgcn_update_dpp(0, k, 0x4E, 0xF, 0xF, true));
+    k = max(k, __builtin_amdgcn_update_dpp(0, k, 0x141, 0xF, 0xF, true));
+    k = max(k, __builtin_amdgcn_update_dpp(0, k, 0x140, 0xF, 0xF, true));
+    k = max(k, __builtin_amdgcn_ds_swizzle(k, 0x401F));
+    const int t = __shfl_xor(k, 32, 64);
+    return lp_unkey(full ? max(k, t) : k);
+}
+
+// maximum of two non-NaN floats (the chunked sweeps)
+__device__ __forceinline__ float lp_max2(float a, float b) { return a > b ? a : b; }
+
 // One class of every running start: a wavefront per clique.  A clique of at
 // most 64 members is held in registers (one member per lane); longer ones are
 // swept in chunks of 64.
@@ -122,7 +187,7 @@ __global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, LpRound rd
     const int lane = threadIdx.x & 63;
     const int k = rd.beg[s] + blockIdx.x * kLpWaves + wave;
     if (k >= rd.end[s]) return;
-    const float T = rd.T[s];
+    const float r2 = rd.r2[s], tl = rd.tl[s];
     const int b = a.cptr[k], e = a.cptr[k + 1];
     float* L = a.Lam + (size_t)s * a.n;
     float* lp = a.lam + (size_t)s * a.m + k;
@@ -131,10 +196,10 @@ __global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, LpRound rd
         const bool on = b + lane < e;
         const int i = on ? a.cmem[b + lane] : 0;
         const float Li = on ? L[i] : 0.0f;
-        const float ai = on ? (a.cost[i] - Li) / T : -INFINITY;
-        const float mx = wave_max(ai);
-        const float sum = wave_sum(on ? expf(ai - mx) : 0.0f);
-        const float nw = fmaxf(0.0f, old + T * (mx + logf(sum)));
+        const float ai = on ? (a.cost[i] - Li) * r2 : -INFINITY;
+        const float mx = lp_reduce<true>(ai, true);
+        const float sum = lp_reduce<false>(on ? __builtin_amdgcn_exp2f(ai - mx) : 0.0f, true);
+        const float nw = fmaxf(0.0f, old + tl * (mx + __builtin_amdgcn_logf(sum)));
         if (on) L[i] = Li + (nw - old);
         if (lane == 0) *lp = nw;
         return;
@@ -142,19 +207,203 @@ __global__ __launch_bounds__(kLpBlock) void lp_round_kernel(LpArgs a, LpRound rd
     float mx = -INFINITY;
     for (int j = b + lane; j < e; j += 64) {
         const int i = a.cmem[j];
-        mx = fmaxf(mx, (a.cost[i] - L[i]) / T);
+        mx = lp_max2(mx, (a.cost[i] - L[i]) * r2);
     }
-    mx = wave_max(mx);
+    mx = lp_reduce<true>(mx, true);
     float sum = 0.0f;
     for (int j = b + lane; j < e; j += 64) {
         const int i = a.cmem[j];
-        sum += expf((a.cost[i] - L[i]) / T - mx);
+        sum += __builtin_amdgcn_exp2f((a.cost[i] - L[i]) * r2 - mx);
     }
-    sum = wave_sum(sum);
-    const float nw = fmaxf(0.0f, old + T * (mx + logf(sum)));
+    sum = lp_reduce<false>(sum, true);
+    const float nw = fmaxf(0.0f, old + tl * (mx + __builtin_amdgcn_logf(sum)));
     const float d = nw - old;
     for (int j = b + lane; j < e; j += 64) L[a.cmem[j]] += d;
     if (lane == 0) *lp = nw;
+}
+
+// ---- fused passes --------------------------------------------------------------
+constexpr int kLpPassWaves = 16;
+constexpr int kLpPassBlock = 64 * kLpPassWaves;
+constexpr int kLpPassMax = 16;      // passes per fused launch
+constexpr int kLpTaskFull = 1;      // task flag: one clique over the whole wavefront
+constexpr int kLpTaskChunked = 2;   // task flag: one clique of more than 64 members
+constexpr int kLpTB = 4;            // tasks per batch of a wavefront
+constexpr int kLpLdsBudget = 160 * 1024 - 2048;  // dynamic LDS of the fused passes
+
+// Per fused launch, by value: the start of each workgroup and the temperature of
+// each start's passes in this launch.
+struct LpPasses {
+    int32_t start[GN_MAX_STARTS];
+    float r2[GN_MAX_STARTS * kLpPassMax];  // [s][pass of the launch]: log2(e) / T
+    float tl[GN_MAX_STARTS * kLpPassMax];  // T ln 2
+    int32_t passes;
+};
+
+struct LpTasks {
+    const int4* task;      // [slots][64]: member id, cost bits, clique (class order; -1: idle lane), flags
+    const int32_t* tbase;  // [K + 1]: first slot of each class
+    const int32_t* order;  // [S][K]: each start's class order
+};
+
+// A clique of more than 64 members (one task): the chunked update of
+// lp_round_kernel on the LDS multipliers.
+__device__ __forceinline__ void lp_task_chunked(const LpArgs& a, int k, float r2, float tl, float* sL, float* sl) {
+    const int lane = threadIdx.x & 63;
+    const int b = a.cptr[k], e = a.cptr[k + 1];
+    const float old = sl[k];
+    float mx = -INFINITY;
+    for (int j = b + lane; j < e; j += 64) {
+        const int i = a.cmem[j];
+        mx = lp_max2(mx, (a.cost[i] - sL[i]) * r2);
+    }
+    mx = lp_reduce<true>(mx, true);
+    float sum = 0.0f;
+    for (int j = b + lane; j < e; j += 64) {
+        const int i = a.cmem[j];
+        sum += __builtin_amdgcn_exp2f((a.cost[i] - sL[i]) * r2 - mx);
+    }
+    sum = lp_reduce<false>(sum, true);
+    const float nw = fmaxf(0.0f, old + tl * (mx + __builtin_amdgcn_logf(sum)));
+    const float dl = nw - old;
+    for (int j = b + lane; j < e; j += 64) sL[a.cmem[j]] += dl;
+    if (lane == 0) sl[k] = nw;
+}
+
+// A batch of NB tasks of one wavefront (idle lanes hold clique -1), their
+// dependency chains interleaved: the update of lp_round_kernel for each clique.
+// A clique of at most 32 members in one half gets the same bits as alone in a
+// wavefront: its reduction stays inside the half, and the other half's -inf
+// and 0 change neither the maximum nor the sum at distance 32.
+template <int NB>
+__device__ __forceinline__ void lp_batch(const LpArgs& a, const int4 (&d)[kLpTB], float r2, float tl, float* sL,
+                                         float* sl) {
+    const int lane = threadIdx.x & 63;
+    bool chunked = false;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) chunked |= (__builtin_amdgcn_readfirstlane(d[q].w) & kLpTaskChunked) != 0;
+    if (chunked) {
+        int ks[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            ks[q] = (__builtin_amdgcn_readfirstlane(d[q].w) & kLpTaskChunked) ? __builtin_amdgcn_readfirstlane(d[q].z)
+                                                                              : -1;
+        for (int q = 0; q < NB; ++q)  // scalar indices: no register array indexed at run time
+            if (ks[q] >= 0) lp_task_chunked(a, ks[q], r2, tl, sL, sl);
+    }
+    float Li[NB], old[NB], ai[NB], mx[NB], sm[NB];
+    bool on[NB], full[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int fl = __builtin_amdgcn_readfirstlane(d[q].w);
+        on[q] = d[q].z >= 0 && !(fl & kLpTaskChunked);
+        full[q] = (fl & kLpTaskFull) != 0;
+        Li[q] = on[q] ? sL[d[q].x] : 0.0f;
+        old[q] = on[q] ? sl[d[q].z] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ai[q] = on[q] ? (__int_as_float(d[q].y) - Li[q]) * r2 : -INFINITY;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) mx[q] = lp_reduce<true>(ai[q], full[q]);
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        sm[q] = lp_reduce<false>(on[q] ? __builtin_amdgcn_exp2f(ai[q] - mx[q]) : 0.0f, full[q]);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const float nw = fmaxf(0.0f, old[q] + tl * (mx[q] + __builtin_amdgcn_logf(sm[q])));
+        if (on[q]) sL[d[q].x] = Li[q] + (nw - old[q]);
+        if (on[q] && (lane & (full[q] ? 63 : 31)) == 0) sl[d[q].z] = nw;
+    }
+}
+
+// The passes of one launch for one start per workgroup (ps.start), Lam and lam
+// of the start in LDS, the class order and the class task offsets too.  Wave w
+// takes slots tbase[c] + w, + 16, ... of class c, kLpTB at a time, and loads
+// its next batch (of this class or the next) when it starts on one: the task
+// data are static, so the loads never wait on the multipliers.  A barrier ends
+// each class.
+__global__ __launch_bounds__(kLpPassBlock) void lp_pass_kernel(LpArgs a, LpTasks ta, LpPasses ps) {
+    extern __shared__ float sm[];
+    float* sL = sm;
+    float* sl = sm + a.n;
+    int32_t* so = reinterpret_cast<int32_t*>(sl + a.m);  // [K]
+    int32_t* sb = so + a.K;                               // [K + 1]
+    const int s = ps.start[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    float* gL = a.Lam + (size_t)s * a.n;
+    float* gl = a.lam + (size_t)s * a.m;
+    for (int q = tid; q < a.n; q += kLpPassBlock) sL[q] = gL[q];
+    for (int q = tid; q < a.m; q += kLpPassBlock) sl[q] = gl[q];
+    for (int q = tid; q < a.K; q += kLpPassBlock) so[q] = ta.order[(size_t)s * a.K + q];
+    for (int q = tid; q <= a.K; q += kLpPassBlock) sb[q] = ta.tbase[q];
+    __syncthreads();
+    const int K = a.K, P = ps.passes;
+    constexpr int kStride = kLpPassWaves * kLpTB;  // slots between a wave's batches
+    // batch at slot t (the wave's slots t, t + 16, ... below tend); returns the
+    // mask of the slots that exist (the others load slot 0 and stay unused, so
+    // no register is written while its load is in flight)
+    auto load = [&](int t, int tend, int4 (&d)[kLpTB]) -> unsigned {
+        unsigned valid = 0u;
+#pragma unroll
+        for (int q = 0; q < kLpTB; ++q) {
+            const int u = t + q * kLpPassWaves;
+            const bool ok = u < tend;
+            d[q] = ta.task[(size_t)(ok ? u : 0) * 64 + lane];
+            valid |= ok ? 1u << q : 0u;
+        }
+        return valid;
+    };
+    auto cls = [&](int r, int& tb, int& te) {
+        const int c = __builtin_amdgcn_readfirstlane(so[r]);
+        tb = __builtin_amdgcn_readfirstlane(sb[c]) + wave;
+        te = __builtin_amdgcn_readfirstlane(sb[c + 1]);
+    };
+    int tb, te;
+    cls(0, tb, te);
+    int4 cur[kLpTB];
+    unsigned cv = load(tb, te, cur);
+    for (int p = 0; p < P; ++p) {
+        const float r2 = ps.r2[s * kLpPassMax + p], tl = ps.tl[s * kLpPassMax + p];
+        for (int r = 0; r < K; ++r) {
+            // cur holds the batch at tb of class position r (idle if tb >= te)
+            const bool more = r + 1 < K || p + 1 < P;
+            int nb, ne;
+            cls(r + 1 < K ? r + 1 : 0, nb, ne);
+            if (!more) ne = nb;  // nothing after the last class
+            for (int t = tb;; t += kStride) {
+                const bool last_batch = t + kStride >= te;
+                int4 nxt[kLpTB];
+                const unsigned nv = last_batch ? load(nb, ne, nxt) : load(t + kStride, te, nxt);
+                // the valid slots are a prefix: a batch of their count
+                switch (cv) {
+                    case 0xF: lp_batch<4>(a, cur, r2, tl, sL, sl); break;
+                    case 0x7: lp_batch<3>(a, cur, r2, tl, sL, sl); break;
+                    case 0x3: lp_batch<2>(a, cur, r2, tl, sL, sl); break;
+                    case 0x1: lp_batch<1>(a, cur, r2, tl, sL, sl); break;
+                    default: break;
+                }
+#pragma unroll
+                for (int q = 0; q < kLpTB; ++q) cur[q] = nxt[q];
+                cv = nv;
+                if (last_batch) break;
+            }
+            tb = nb;
+            te = ne;
+            __syncthreads();
+        }
+    }
+    for (int q = tid; q < a.n; q += kLpPassBlock) gL[q] = sL[q];
+    for (int q = tid; q < a.m; q += kLpPassBlock) gl[q] = sl[q];
+}
+
+// log2(e) / T and T ln 2 of a pass, rounded once from fp64
+static float lp_r2(float T) { return (float)(1.4426950408889634074 / (double)T); }
+static float lp_tl(float T) { return (float)((double)T * 0.69314718055994530942); }
+
+// LDS bytes of the fused passes
+static size_t lp_pass_lds(int32_t n, int32_t m, int32_t K) {
+    return sizeof(float) * ((size_t)n + m) + sizeof(int32_t) * (2 * (size_t)K + 1);
 }
 
 // Check, part 1: the clique sums of the smoothed primal.
@@ -361,6 +610,12 @@ struct gn_lp {
     double* part = nullptr;
     LpState* st = nullptr;
     LpState* st_host = nullptr;  // pinned
+    // fused passes (null when a start's multipliers do not fit one CU's LDS)
+    int4* task = nullptr;
+    int32_t* tbase = nullptr;
+    int32_t* order_d = nullptr;
+    size_t pass_lds = 0;
+    bool fused_on = true;
 };
 
 static void lp_free(gn_lp* L) {
@@ -377,6 +632,57 @@ static void lp_free(gn_lp* L) {
     hipFree(L->part);
     hipFree(L->st);
     if (L->st_host) hipHostFree(L->st_host);
+    hipFree(L->task);
+    hipFree(L->tbase);
+    hipFree(L->order_d);
+}
+
+// The fused passes' task layout: per class, its cliques as wavefront tasks in
+// class order -- a clique of more than 64 members alone (swept in chunks), one
+// of 33..64 members alone, two of at most 32 in the two halves (consecutive
+// ones paired, the last one alone in a half if their count is odd).  Each task
+// holds per lane the member id, the member's cost bits, the clique (class-order
+// index) and the flags; idle lanes hold clique -1.
+static void lp_build_tasks(int32_t K, const std::vector<int32_t>& class_ptr, const std::vector<int32_t>& cptr,
+                           const std::vector<int32_t>& cmem, const float* cost, std::vector<int4>& task,
+                           std::vector<int32_t>& tbase) {
+    tbase.assign((size_t)K + 1, 0);
+    task.clear();
+    auto lanes = [&](int4* t, int32_t q, int flags) {  // the members of q from lane 0 of t
+        for (int32_t j = cptr[q]; j < cptr[q + 1]; ++j) {
+            const int32_t i = cmem[j];
+            int32_t cb;
+            std::memcpy(&cb, &cost[i], sizeof(cb));
+            t[j - cptr[q]] = make_int4(i, cb, q, flags);
+        }
+    };
+    auto open = [&](int flags) -> int4* {
+        const size_t at = task.size();
+        task.resize(at + 64, make_int4(0, 0, -1, flags));
+        return task.data() + at;
+    };
+    for (int32_t c = 0; c < K; ++c) {
+        tbase[c] = (int32_t)(task.size() / 64);
+        int32_t pend = -1;
+        for (int32_t q = class_ptr[c]; q < class_ptr[c + 1]; ++q) {
+            const int32_t sz = cptr[q + 1] - cptr[q];
+            if (sz > 64) {
+                int4* t = open(kLpTaskChunked);
+                for (int l = 0; l < 64; ++l) t[l].z = q;
+            } else if (sz > 32) {
+                lanes(open(kLpTaskFull), q, kLpTaskFull);
+            } else if (pend < 0) {
+                pend = q;
+            } else {
+                int4* t = open(0);
+                lanes(t, pend, 0);
+                lanes(t + 32, q, 0);
+                pend = -1;
+            }
+        }
+        if (pend >= 0) lanes(open(0), pend, 0);
+    }
+    tbase[K] = (int32_t)(task.size() / 64);
 }
 
 gn_status gn_internal_check_cliques(int32_t n, int32_t m, const int32_t* ptr, const int32_t* members,
@@ -476,6 +782,30 @@ extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_pt
     if (e == hipSuccess) e = hipMemcpyAsync(L->cmem, cmem.data(), sizeof(int32_t) * nnzc, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(L->vptr, vptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(L->vcl, vcl.data(), sizeof(int32_t) * nnzc, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && lp_pass_lds(n, m, K) <= (size_t)kLpLdsBudget) {
+        std::vector<int4> task;
+        std::vector<int32_t> tbase;
+        lp_build_tasks(K, class_ptr, cptr, cmem, cost, task, tbase);
+        if (gn_dalloc(&L->task, task.size()) && gn_dalloc(&L->tbase, tbase.size()) &&
+            gn_dalloc(&L->order_d, S * (size_t)K)) {
+            e = hipMemcpyAsync(L->task, task.data(), sizeof(int4) * task.size(), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(L->tbase, tbase.data(), sizeof(int32_t) * tbase.size(), hipMemcpyHostToDevice,
+                                   stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            L->pass_lds = lp_pass_lds(n, m, K);
+            if (e == hipSuccess && L->pass_lds > 64 * 1024)
+                e = hipFuncSetAttribute((const void*)lp_pass_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)L->pass_lds);
+        } else {
+            hipFree(L->task);
+            hipFree(L->tbase);
+            hipFree(L->order_d);
+            L->task = nullptr;
+            L->tbase = nullptr;
+            L->order_d = nullptr;
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         lp_free(L);
@@ -484,6 +814,12 @@ extern "C" gn_status gn_lp_create(int32_t n, int32_t m, const int32_t* clique_pt
     }
     *out = L;
     return GN_OK;
+}
+
+extern "C" int32_t gn_lp_set_fused(gn_lp* L, int32_t enable) {
+    if (!L) return -1;
+    L->fused_on = enable != 0;
+    return L->fused_on && L->task ? 1 : 0;
 }
 
 extern "C" void gn_lp_destroy(gn_lp* L) {
@@ -549,32 +885,63 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
     lp_reset_kernel<<<1024, 256, 0, stream>>>(a, starts);
     GN_HIP_TRY(hipGetLastError());
     const dim3 gcs((L->m + kLpWaves - 1) / kLpWaves, starts), gv(a.nbv, starts);
+    const bool fused = L->fused_on && L->task;
+    LpTasks ta{L->task, L->tbase, L->order_d};
+    if (fused)
+        GN_HIP_TRY(hipMemcpyAsync(L->order_d, order, sizeof(int32_t) * starts * K, hipMemcpyHostToDevice, stream));
     std::vector<char> running(starts, 1);
     std::vector<float> T_cur(t0, t0 + starts);   // annealed temperatures, set by each check
+    auto temp = [&](int32_t s, int32_t q) -> float {
+        return anneal ? T_cur[s] : (float)std::max((double)t_min, (double)t0[s] * std::pow((double)drop, (double)q));
+    };
     LpRound rd{};
-    for (int32_t p = 0; p < max_passes; ++p) {
-        for (int32_t s = 0; s < starts; ++s)
-            rd.T[s] = anneal ? T_cur[s]
-                             : (float)std::max((double)t_min, (double)t0[s] * std::pow((double)drop, (double)p));
-        for (int32_t r = 0; r < K; ++r) {
-            int32_t gx = 0;
-            for (int32_t s = 0; s < starts; ++s) {
-                const int32_t c = order[(size_t)s * K + r];
-                rd.beg[s] = L->class_ptr_h[c];
-                rd.end[s] = running[s] ? L->class_ptr_h[c + 1] : rd.beg[s];
-                gx = std::max(gx, (rd.end[s] - rd.beg[s] + kLpWaves - 1) / kLpWaves);
+    // passes [p, pe) up to the next check, then the check after pass pe - 1
+    for (int32_t p = 0; p < max_passes;) {
+        const int32_t pe = (int32_t)std::min<int64_t>(max_passes, ((int64_t)p / check_every + 1) * check_every);
+        if (fused) {
+            for (int32_t q0 = p; q0 < pe; q0 += kLpPassMax) {
+                LpPasses ps{};
+                ps.passes = std::min(kLpPassMax, pe - q0);
+                int32_t nb = 0;
+                for (int32_t s = 0; s < starts; ++s) {
+                    if (!running[s]) continue;
+                    ps.start[nb++] = s;
+                    for (int32_t j = 0; j < ps.passes; ++j) {
+                        const float T = temp(s, q0 + j);
+                        ps.r2[s * kLpPassMax + j] = lp_r2(T);
+                        ps.tl[s * kLpPassMax + j] = lp_tl(T);
+                    }
+                }
+                lp_pass_kernel<<<nb, kLpPassBlock, L->pass_lds, stream>>>(a, ta, ps);
             }
-            lp_round_kernel<<<dim3(gx, starts), kLpBlock, 0, stream>>>(a, rd);
+        } else {
+            for (int32_t q = p; q < pe; ++q) {
+                for (int32_t s = 0; s < starts; ++s) {
+                    rd.T[s] = temp(s, q);
+                    rd.r2[s] = lp_r2(rd.T[s]);
+                    rd.tl[s] = lp_tl(rd.T[s]);
+                }
+                for (int32_t r = 0; r < K; ++r) {
+                    int32_t gx = 0;
+                    for (int32_t s = 0; s < starts; ++s) {
+                        const int32_t c = order[(size_t)s * K + r];
+                        rd.beg[s] = L->class_ptr_h[c];
+                        rd.end[s] = running[s] ? L->class_ptr_h[c + 1] : rd.beg[s];
+                        gx = std::max(gx, (rd.end[s] - rd.beg[s] + kLpWaves - 1) / kLpWaves);
+                    }
+                    lp_round_kernel<<<dim3(gx, starts), kLpBlock, 0, stream>>>(a, rd);
+                }
+            }
         }
-        const bool last = p + 1 == max_passes;
-        if ((p + 1) % check_every != 0 && !last) continue;
+        for (int32_t s = 0; s < starts; ++s) rd.T[s] = temp(s, pe - 1);
+        const bool last = pe == max_passes;
         lp_csum_kernel<<<gcs, kLpBlock, 0, stream>>>(a, rd);
         lp_vertex_kernel<<<gv, kLpVBlock, 0, stream>>>(a, rd);
         for (int r = 0; r < kLiftRounds; ++r) {
             lp_share_kernel<<<gcs, kLpBlock, 0, stream>>>(a);
             lp_raise_kernel<<<gv, kLpVBlock, 0, stream>>>(a, r + 1 == kLiftRounds ? 1 : 0);
         }
-        lp_finish_kernel<<<starts, kLpFBlock, 0, stream>>>(a, rd, p, last ? 1 : 0);
+        lp_finish_kernel<<<starts, kLpFBlock, 0, stream>>>(a, rd, pe - 1, last ? 1 : 0);
         lp_keep_kernel<<<gv, kLpVBlock, 0, stream>>>(a);
         GN_HIP_TRY(hipGetLastError());
         GN_HIP_TRY(hipMemcpyAsync(L->st_host, L->st, sizeof(LpState) * starts, hipMemcpyDeviceToHost, stream));
@@ -585,6 +952,7 @@ extern "C" gn_status gn_lp_solve(gn_lp* L, int32_t starts, const float* t0, cons
             T_cur[s] = L->st_host[s].next_t;
             all = all && !running[s];
         }
+        p = pe;
         if (all) break;
     }
     bool conv = true;

@@ -127,8 +127,7 @@ __device__ __forceinline__ unsigned quad_update(const MultiArgs& a, const QuadCt
         const float yi = fabsf(yr);
         const float s = __fmaf_rn(c.g, comp(sigma, j), yi);
         const bool fallback = !(s > 1e-9f);
-        float xn;
-        out[j] = gnk::step_word(yr, vi, s, xn);
+        out[j] = gnk::step_word(yr, vi, s);
         const bool on = (c.act >> j) & 1u;
         if (on && c.do_write) fb[j] += fallback ? 1u : 0u;
         if (on && c.do_test) {

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     // every lane computes all 4 entries (entries outside the matrix hold y = 0,
     // v = 1 and are masked out of stores, flags and partials), so the loop has
     // no divergent branches
-    float yn[kRPW], ynew[kRPW], xo[kRPW];
+    float yn[kRPW], ynew[kRPW], sv[kRPW];
     int viol = 0, fb = 0;
     bool unnormalizable = false;
     const double C = fC[lane];
@@ -342,11 +342,10 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
         const float sigma = (float)((R - (double)yi) + (C - (double)yi));
         const float s = __fmaf_rn(c.g, sigma, yi);
         const bool fallback = !(s > 1e-9f);
-        float xn;
-        const float y_new = gnk::step_word(yraw[m], vi[m], s, xn);
+        const float y_new = gnk::step_word(yraw[m], vi[m], s);
         yn[m] = ok[m] ? y_new : 0.0f;
         ynew[m] = y_new;
-        xo[m] = xn;
+        sv[m] = s;
         fb += (c.do_write && ok[m] && fallback) ? 1 : 0;
         if (c.solve && c.k == 0 && ok[m] && yi == 0.0f && R == 0.0 && C == 0.0) unnormalizable = true;
         const bool in_s = gnk::sign_of(yraw[m]) != 0u;
@@ -359,14 +358,15 @@ __global__ __launch_bounds__(kBlock) void rook_step_kernel(RookArgs a) {
     }
     if (c.do_write) {
         // outputs: one uniform test per array, then the entries
-        for (int o = 0; o < 2; ++o) {
-            float* out = o == 0 ? a.y_out : a.x_out;
-            if (!out) continue;
+        if (a.y_out) {
 #pragma unroll
-            for (int m = 0; m < kRPW; ++m) {
-                const size_t e = (size_t)iw[m] * a.cols + j;
-                if (full || ok[m]) out[e] = o == 0 ? ynew[m] : xo[m];
-            }
+            for (int m = 0; m < kRPW; ++m)
+                if (full || ok[m]) a.y_out[(size_t)iw[m] * a.cols + j] = ynew[m];
+        }
+        if (a.x_out) {
+#pragma unroll
+            for (int m = 0; m < kRPW; ++m)
+                if (full || ok[m]) a.x_out[(size_t)iw[m] * a.cols + j] = gnk::step_x(yraw[m], vi[m], sv[m], ynew[m]);
         }
     }
     if (unnormalizable) atomicOr(&a.st->err, 2);

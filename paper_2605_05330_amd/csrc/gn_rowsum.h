@@ -62,13 +62,21 @@ __device__ __forceinline__ float log_word(int32_t q) {
 __device__ __forceinline__ float log_q_value(int32_t q) { return (float)(q - kLogFloorQ) * (1.0f / kLogScale); }
 __device__ __forceinline__ int32_t log_fixed(float l) { return __float2int_rn(l * kLogScale); }
 
+// log2 and 2^a by the hardware instructions, for arguments where they return
+// what log2f and exp2f return: lg2n for positive normal numbers (every caller
+// passes v_i = sqrt(w_i) >= 2^-75, s_i > 1e-9 or |y_i| >= 2^-100), ex2n for
+// a >= -126 (a normal result).  log2f and exp2f add a rescaling for the
+// subnormal range to every call, a dozen instructions per log-form row.
+__device__ __forceinline__ float lg2n(float a) { return __builtin_amdgcn_logf(a); }
+__device__ __forceinline__ float ex2n(float a) { return __builtin_amdgcn_exp2f(a); }
+
 // Word of a state whose log2 x is q / 2^17 - 1022, in its ordinary form when
 // v 2^(log2 x) >= 2^-100.  Only called for states far below 1/2.
 __device__ __forceinline__ float word_from_log(int32_t q, float vi) {
     q = q < 0 ? 0 : q;
-    const float ly = log_q_value(q) + log2f(vi);
+    const float ly = log_q_value(q) + lg2n(vi);
     if (ly >= -100.0f) {
-        const float yn = exp2f(ly);
+        const float yn = ex2n(ly);
         if (yn >= kYLog) return yn;
     }
     return log_word(q);
@@ -99,27 +107,29 @@ __device__ __forceinline__ float y_of_word(float w, float vi) {
 
 // One WRGN update of a row (WRGN definition with the safe division of the code
 // appendix) from its own word and s_i = |y_i| + gamma sum_j |y_j|: returns the
-// new word and sets xo = x'_i in fp32.
-__device__ __forceinline__ float step_word(float yraw, float vi, float s, float& xo) {
-    if (!(s > 1e-9f)) {  // safe-division reset: x' = 1/2
-        xo = 0.5f;
-        return vi * 0.5f;
-    }
+// new word.
+__device__ __forceinline__ float step_word(float yraw, float vi, float s) {
+    if (!(s > 1e-9f)) return vi * 0.5f;  // safe-division reset: x' = 1/2
     const uint32_t mag = mag_bits(yraw);
     if (!is_log_mag(mag)) {
         const float yi = __uint_as_float(mag);
         const float xn = yi / s;
         const float yn = vi * xn;
-        xo = xn;
         if (yn >= kYLog || mag == 0u) return xn > 0.5f ? -yn : yn;
         // below 2^-100: log2 x' = log2 y - log2 s
-        const float w = word_from_log(log_fixed(log2f(yi)) - log_fixed(log2f(s)) + kLogFloorQ, vi);
-        return w;
+        return word_from_log(log_fixed(lg2n(yi)) - log_fixed(lg2n(s)) + kLogFloorQ, vi);
     }
-    const int32_t q = (int32_t)mag - 1 + log_fixed(log2f(vi) - log2f(s));
-    const float w = word_from_log(q, vi);
-    xo = x_of_word(w, vi);
-    return w;
+    return word_from_log((int32_t)mag - 1 + log_fixed(lg2n(vi) - lg2n(s)), vi);
+}
+
+// x'_i in fp32 of that update, w its new word: the quotient y_i / s_i itself
+// for an ordinary word, 1/2 on the reset, the log word's value otherwise.
+// Called only where x' is an output, so the solves do not pay for it.
+__device__ __forceinline__ float step_x(float yraw, float vi, float s, float w) {
+    if (!(s > 1e-9f)) return 0.5f;
+    const uint32_t mag = mag_bits(yraw);
+    if (!is_log_mag(mag)) return __uint_as_float(mag) / s;
+    return x_of_word(w, vi);
 }
 
 // Group of G threads sums one row of degree d <= MAXD.  `t` is the thread's

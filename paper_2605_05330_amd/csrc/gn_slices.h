@@ -62,8 +62,7 @@ __device__ __forceinline__ bool step_row(float yraw, float vi, float sigma, bool
     const float s = __fmaf_rn(g, sigma, yi);
     const bool fallback = !(s > 1e-9f);
     if (do_write) {
-        float xn;
-        y_out[i] = gnk::step_word(yraw, vi, s, xn);
+        y_out[i] = gnk::step_word(yraw, vi, s);
         fb += fallback ? 1 : 0;
     }
     if (!do_test) return false;

@@ -28,10 +28,9 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<Step
     const bool fallback = !(s > 1e-9f);
     if (a.s_out) a.s_out[i] = s;
     if (c.do_write) {
-        float xn;
-        const float yn = gnk::step_word(yraw, vi, s, xn);
+        const float yn = gnk::step_word(yraw, vi, s);
         if (a.y_out) a.y_out[i] = yn;
-        if (a.x_out_user) a.x_out_user[a.perm[i]] = xn;
+        if (a.x_out_user) a.x_out_user[a.perm[i]] = gnk::step_x(yraw, vi, s, yn);
         fb += fallback ? 1 : 0;
     }
     if (!c.do_test) return false;

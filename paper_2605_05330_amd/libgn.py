@@ -123,6 +123,7 @@ def lib():
                                ctypes.c_int),
             "gn_lp_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "gn_lp_set_fused": ([_vp, ctypes.c_int32], ctypes.c_int32),
             "gn_lp_solve": ([_vp, ctypes.c_int32, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
                              ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp,
                              ctypes.POINTER(gn_lp_result), _vp],
@@ -397,6 +398,14 @@ def gn_lp_info(h) -> dict:
     return {"n_classes": k.value, "n_cliques": m.value, "max_class": mc.value}
 
 
+def gn_lp_set_fused(h, enable: bool) -> bool:
+    """Fused passes on or off (testing control); True when solves will run fused."""
+    r = lib().gn_lp_set_fused(h, 1 if enable else 0)
+    if r < 0:
+        raise GNError(GN_E_ARG, "gn_lp_set_fused")
+    return r == 1
+
+
 def gn_lp_solve(h, t0, order, x, drop=0.99, t_min=1e-4, max_passes=10000, check_every=10, gap_tol=1e-3,
                 x_floor=1e-3, anneal_tol=3e-3, stall=10, stream=None):
     """t0: host float32 [starts]; order: host int32 [starts, n_classes]; x: CUDA
@@ -428,6 +437,9 @@ class LP:
         if h:
             gn_lp_destroy(h)
             self.handle = None
+
+    def set_fused(self, enable: bool) -> bool:
+        return gn_lp_set_fused(self.handle, enable)
 
     def solve(self, t0, order, x, **kw):
         return gn_lp_solve(self.handle, t0, order, x, **kw)

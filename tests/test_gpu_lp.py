@@ -72,6 +72,52 @@ def test_fixed_passes_match_oracle(gpu, n, items, klo, khi, starts, seed):
         assert res[s].primal == pytest.approx(ro.primal, rel=1e-4)
 
 
+@pytest.mark.parametrize("n,items,klo,khi,starts,seed,kw", [
+    # fixed schedule, checks every 20 passes: fused launches of 16 and 4 passes
+    (300, 80, 2, 4, 4, 0, dict(drop=0.95, t_min=1e-3, max_passes=60, check_every=20, gap_tol=0.0, anneal_tol=0.0)),
+    # annealed to a 1% gap: starts stop at different checks
+    (2000, 300, 3, 8, 16, 1, dict(max_passes=3000, check_every=10, gap_tol=1e-2)),
+    # cliques of ~100-200 members: the chunked tasks
+    (400, 6, 1, 3, 3, 2, dict(drop=0.95, t_min=1e-3, max_passes=45, check_every=7, gap_tol=0.0, anneal_tol=0.0)),
+    # cliques of 13-43 members: tasks of one clique and of two (one per half)
+    (1500, 400, 1, 12, 5, 7, dict(max_passes=100, check_every=10, gap_tol=0.0)),
+])
+def test_fused_passes_same_bits_as_per_class_launches(gpu, n, items, klo, khi, starts, seed, kw):
+    """The fused passes (one workgroup per start, multipliers in LDS) and the
+    per-class launches compute the same bits: warm starts, bounds, values,
+    temperatures and pass counts."""
+    import torch
+    inst, c = _instance(n, items, klo, khi, seed)
+    libgn = _lib()
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    K = L.info["n_classes"]
+    orders = inputs.class_orders(starts, K, seed)
+    t0 = inputs.jittered_temperatures(starts, 1.0, 1.1, seed)
+    out = []
+    for fused in (True, False):
+        assert L.set_fused(fused) == fused
+        x = torch.empty(starts * inst.n, dtype=torch.float32, device="cuda")
+        st, res = L.solve(t0, orders, x, **kw)
+        out.append((st, [(r.passes, r.converged, r.temperature, r.dual, r.primal, r.gap) for r in res],
+                    x.cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == out[1][1]
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    if kw.get("gap_tol", 0.0) > 0.0:
+        assert len({r[0] for r in out[0][1]}) > 1  # starts stopped at different passes
+
+
+def test_fused_passes_need_the_multipliers_in_lds(gpu):
+    """An instance whose n + m words do not fit one CU's LDS runs the per-class
+    launches."""
+    inst, c = _instance(42000, 300, 1, 2, 11)
+    libgn = _lib()
+    L = libgn.LP(inst.n, inst.ptr, inst.members, c)
+    assert L.set_fused(True) is False
+    small, cs = _instance(300, 80, 2, 4, 0)
+    assert libgn.LP(small.n, small.ptr, small.members, cs).set_fused(True) is True
+
+
 def test_single_clique_softmax_and_singletons(gpu):
     """One clique over everything: one pass leaves softmax(c / t0).  Singleton
     cliques only: every vertex reaches x = 1 (lam_i = c_i) and the gap is 0."""
