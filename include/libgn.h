@@ -635,6 +635,24 @@ gn_status gn_set_chunk_len(int32_t len);
  * Process-wide; not thread-safe. */
 gn_status gn_set_small_graph_limit(int32_t work_max);
 
+/* Tuning: pruned neighbour lists in the chained solve of gn_solve.  A
+ * neighbour sum adds only ordinary states (y >= 2^-100; the log form and exact
+ * zeros add nothing), so the step launches may read a copy of the graph's
+ * column lists in which the entries of vertices that are not ordinary -- most
+ * of the graph once the non-selected vertices have decayed -- are marked
+ * absent and not gathered.  Vertices that stopped being ordinary are dropped
+ * before each replayed chain of step launches (gn_set_chunk_len); a vertex
+ * whose state becomes ordinary again is put back into its neighbours' lists by
+ * the step that produces that state, before any step reads it.  mode 0: never;
+ * 1 (the default): on graphs whose gathers have little cache-line locality in
+ * the internal order (most gathers touch a line of their own), where skipping
+ * them pays; 2: on every graph.  The lists are built at graph creation (the
+ * mirror position of every entry; graphs created with GN_NO_VALIDATE whose
+ * structure is not symmetric with sorted rows have none).  Results are the
+ * same bits in every mode.  GN_E_ARG for another mode.  Process-wide; not
+ * thread-safe. */
+gn_status gn_set_pruning(int32_t mode);
+
 /* Human-readable name of a status code (static string). */
 const char* gn_status_str(gn_status s);
 

@@ -145,6 +145,7 @@ static void free_graph_buffers(gn_graph* g) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(g->row_ptr); f(g->col); f(g->v); f(g->w_int); f(g->w_user); f(g->perm); f(g->iperm);
     f(g->sl_col); f(g->sl_off);
+    f(g->prune); f(g->prune_mloc); f(g->listed);
     GraphWorkspace& ws = g->ws;
     for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
     ws.chunks.clear();
@@ -238,6 +239,45 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
             iperm.swap(q2);
         }
     }
+    // Gather locality of the chosen order: distinct 128-byte lines per gathered
+    // entry.  Rows of up to 128 neighbours (a thread or a few per row) are
+    // counted over 64-row windows, one position at a time, as a wavefront
+    // gathers them; heavier rows (a wavefront or a workgroup per row, every
+    // 16th row sampled) over their own entries.  The pruned lists pay where most
+    // gathers touch a line of their own (power-law and random graphs, the
+    // column mates of assignment graphs); where neighbours share lines the
+    // skipped gathers were cache hits and the lists' upkeep costs more.
+    {
+        int64_t lines = 0, counted = 0;
+        std::vector<int32_t> buf;
+        for (int32_t w0 = 0; w0 < n; w0 += 64) {
+            const int32_t w1 = std::min(n, w0 + 64);
+            int32_t dmax = 0;
+            for (int32_t r = w0; r < w1; ++r)
+                if (deg[perm[r]] <= 128) dmax = std::max(dmax, deg[perm[r]]);
+            for (int32_t q = 0; q < dmax; ++q) {
+                buf.clear();
+                for (int32_t r = w0; r < w1; ++r) {
+                    const int32_t i = perm[r];
+                    if (deg[i] <= 128 && q < deg[i]) buf.push_back(iperm[ci[rp[i] + q]] >> 5);
+                }
+                std::sort(buf.begin(), buf.end());
+                lines += (int64_t)(std::unique(buf.begin(), buf.end()) - buf.begin());
+                counted += (int64_t)buf.size();
+            }
+        }
+        int32_t heavy = 0;
+        for (int32_t r = 0; r < n; ++r) {
+            const int32_t i = perm[r];
+            if (deg[i] <= 128 || (heavy++ & 15)) continue;
+            buf.clear();
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e) buf.push_back(iperm[ci[e]] >> 5);
+            std::sort(buf.begin(), buf.end());
+            lines += 16 * (int64_t)(std::unique(buf.begin(), buf.end()) - buf.begin());
+            counted += 16 * (int64_t)buf.size();
+        }
+        g->prune_pays = lines * 2 > counted;
+    }
 
     int32_t counts[BIN_COUNT] = {0};
     for (int32_t i = 0; i < n; ++i) counts[bin_of_degree(deg[i])]++;
@@ -304,6 +344,13 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
         sl_off[(size_t)s + 1] = (int32_t)lines;
     }
     std::vector<int32_t> sl_col((size_t)std::max<int64_t>(lines * 64, 1), -1);
+    // loc_of[e]: where internal CSR entry e is read by the step kernel, in the
+    // pruned lists' index space (sliced words, then CSR positions)
+    const int64_t sl_words = lines * 64;
+    std::vector<int32_t> loc_of((size_t)std::max<int64_t>(nnz, 1));
+    bool prunable = sl_words + nnz <= INT32_MAX;
+    for (int32_t r = 0; r < n && prunable; ++r)
+        for (int32_t e = rp_int[r]; e < rp_int[r + 1]; ++e) loc_of[(size_t)e] = (int32_t)(sl_words + e);
     for (int b = 0; b < BIN_COUNT; ++b) {
         const int G = bin_group(b);
         if (!G) continue;
@@ -317,12 +364,46 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
                 for (int32_t p = 0; p < d; ++p) {
                     const int32_t q = p / G, lane = (r - r0) * G + p % G;
                     base[(size_t)q * 64 + lane] = col_int[(size_t)rp_int[r] + p];
+                    if (prunable) loc_of[(size_t)rp_int[r] + p] = (int32_t)((int64_t)(sl_off[s] + q) * 64 + lane);
                 }
             }
         }
     }
 
+    // mirror entries: entry p of user row u points to w; u sits at position p'
+    // of user row w (rows sorted: binary search).  Internal rows keep the
+    // caller's per-row order, so mloc of internal entry (iperm[u], p) is the
+    // location of internal entry (iperm[w], p').  A missing or repeated mirror
+    // (a structure that was not validated) leaves the graph without pruned lists.
+    std::vector<int32_t> mloc;
+    if (prunable && nnz > 0) {
+        mloc.assign((size_t)nnz, -1);
+        for (int32_t u = 0; u < n && prunable; ++u) {
+            const int32_t r = iperm[u];
+            for (int32_t p = 0; p < rp[u + 1] - rp[u]; ++p) {
+                const int32_t wv = ci[(size_t)rp[u] + p];
+                const int32_t* b0 = ci.data() + rp[wv];
+                const int32_t* b1 = ci.data() + rp[wv + 1];
+                const int32_t* it = std::lower_bound(b0, b1, u);
+                if (it == b1 || *it != u || (it + 1 < b1 && it[1] == u) || wv == u) {
+                    prunable = false;
+                    break;
+                }
+                const int32_t e_mirror = rp_int[iperm[wv]] + (int32_t)(it - b0);
+                mloc[(size_t)rp_int[r] + p] = loc_of[(size_t)e_mirror];
+            }
+        }
+    }
+    prunable = prunable && nnz > 0;
+
     st = GN_OK;
+    if (prunable && ((st = dev_alloc(&g->prune, (size_t)(sl_words + nnz))) ||
+                     (st = dev_alloc(&g->prune_mloc, (size_t)nnz)) || (st = dev_alloc(&g->listed, (size_t)n)))) {
+        free_graph_buffers(g);
+        delete g;
+        return st;
+    }
+    g->prune_sl_words = prunable ? sl_words : 0;
     if ((st = dev_alloc(&g->sl_col, sl_col.size())) || (st = dev_alloc(&g->sl_off, sl_off.size())) ||
         (st = dev_alloc(&g->row_ptr, (size_t)n + 1)) || (st = dev_alloc(&g->col, (size_t)nnz)) ||
         (st = dev_alloc(&g->v, (size_t)n)) || (st = dev_alloc(&g->w_int, (size_t)n)) ||
@@ -345,6 +426,13 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
     up(g->iperm, iperm.data(), sizeof(int32_t) * (size_t)n);
     up(g->sl_col, sl_col.data(), sizeof(int32_t) * sl_col.size());
     up(g->sl_off, sl_off.data(), sizeof(int32_t) * sl_off.size());
+    if (prunable) {
+        // the pruned lists start as copies; positions past a row's end stay -1
+        up(g->prune, sl_col.data(), sizeof(int32_t) * (size_t)sl_words);
+        up(g->prune + sl_words, col_int.data(), sizeof(int32_t) * (size_t)nnz);
+        up(g->prune_mloc, mloc.data(), sizeof(int32_t) * (size_t)nnz);
+        if (e == hipSuccess) e = hipMemsetAsync(g->listed, 1, (size_t)n, stream);  // every vertex listed
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         free_graph_buffers(g);

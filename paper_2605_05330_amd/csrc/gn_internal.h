@@ -30,6 +30,7 @@ struct GraphWorkspace {
     void* host_pinned = nullptr;  // pinned staging for SolveState / statistics
     std::vector<hipGraphExec_t> chunks;  // captured step chains, chunk c covers steps [c*C, (c+1)*C)
     int32_t chunk_len = 0;
+    int32_t chunk_prune = -1;            // whether the captured chains read the pruned lists
 };
 
 struct gn_graph {
@@ -46,6 +47,15 @@ struct gn_graph {
     int32_t* iperm = nullptr;     // user -> internal
     int32_t* sl_col = nullptr;    // sliced columns of the group bins
     int32_t* sl_off = nullptr;    // [slices + 1] line offsets
+    // Pruned neighbour lists of the chained solve (gn_step.hip): the sliced
+    // lines, then the CSR columns, with the id of every vertex that is not
+    // listed replaced by -1.  Null when the graph has none (no symmetric,
+    // sorted structure to find the mirror entries, or too many entries).
+    int32_t* prune = nullptr;       // [prune_sl_words + nnz]
+    int64_t prune_sl_words = 0;     // words of the sliced part
+    int32_t* prune_mloc = nullptr;  // [nnz]: where entry (i -> j) of row i sits in row j's list, as i
+    uint8_t* listed = nullptr;      // [n]: vertex present (not -1) in its neighbours' pruned lists
+    bool prune_pays = false;        // the gathers have little locality (gn_set_pruning mode 1)
     BinLayout bins{};
     int32_t bin_count_rows[BIN_COUNT] = {0};
     mutable GraphWorkspace ws;   // work buffers; calls on one handle must not overlap
@@ -109,6 +119,7 @@ gn_status gn_internal_step_with(const gn_graph* g, float gamma, const float* x_i
 // (gn_step.hip): schedule check, gamma table and state reset, the pipelined
 // replay of captured step chains, the stopping outcome and the result record
 extern int32_t g_chunk_len;
+extern int32_t g_prune;  // pruned lists in chained solves: 0 never, 1 where they pay, 2 always (gn_set_pruning)
 float gn_internal_host_gamma(const gn_schedule* s, int32_t k);
 bool gn_internal_schedule_ok(const gn_schedule* sch);
 gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream);

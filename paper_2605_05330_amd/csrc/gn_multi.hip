@@ -101,7 +101,9 @@ __device__ __forceinline__ bool quad_ctl(const MultiArgs& a, int q, QuadCtl& c) 
 }
 
 __device__ __forceinline__ float comp(const float4& v, int j) { return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w; }
-__device__ __forceinline__ float4 abs4(const float4& v) { return make_float4(fabsf(v.x), fabsf(v.y), fabsf(v.z), fabsf(v.w)); }
+__device__ __forceinline__ float4 abs4(const float4& v) {
+    return make_float4(gnk::nbr_term(v.x), gnk::nbr_term(v.y), gnk::nbr_term(v.z), gnk::nbr_term(v.w));
+}
 __device__ __forceinline__ float4 add4(const float4& a, const float4& b) {
     return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
 }

@@ -139,8 +139,15 @@ __device__ __forceinline__ float step_x(float yraw, float vi, float s, float w) 
 // Values entering a sum: |y| for the sign-carrying state (ABS), raw values for
 // signed adjoint vectors.  Column ids are int32, or uint16 for a graph of at most
 // 65536 vertices whose columns are staged in LDS.
+// A state word enters a neighbour sum as |y| when it is ordinary (y >= 2^-100);
+// log words and zeros add nothing (their values are below 2^-100, far below
+// the last bit of any sum that takes the quotient branch).
+__device__ __forceinline__ float nbr_term(float w) {
+    const float a = fabsf(w);
+    return a >= kYLog ? a : 0.0f;
+}
 template <bool ABS>
-__device__ __forceinline__ float term(float v) { return ABS ? fabsf(v) : v; }
+__device__ __forceinline__ float term(float v) { return ABS ? nbr_term(v) : v; }
 
 template <int G, int MAXD, bool ABS = true, typename IT = int32_t>
 __device__ __forceinline__ float row_sum(const IT* __restrict__ cp, int d, const float* __restrict__ y, int t,

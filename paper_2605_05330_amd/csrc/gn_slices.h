@@ -115,8 +115,8 @@ __device__ __forceinline__ float slice_sum_k(const LT* __restrict__ ln, const fl
 #pragma unroll
     for (int q = 0; q < K; ++q) {
         const float yv = y[id[q]];
-        if (q < NQ) c[q] = ABS ? fabsf(yv) : 0.0f + yv;
-        else c[q % NQ] += ABS ? fabsf(yv) : yv;
+        if (q < NQ) c[q] = ABS ? gnk::nbr_term(yv) : 0.0f + yv;
+        else c[q % NQ] += ABS ? gnk::nbr_term(yv) : yv;
         if (ABS) bits |= __float_as_uint(yv);
     }
 #pragma unroll
@@ -163,7 +163,7 @@ __device__ __forceinline__ void heavy_lines(const LT* __restrict__ ln, const flo
     for (int q = 0; q < K; ++q) yv[q] = y[id[q]];
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        acc += ABS ? fabsf(yv[q]) : yv[q];
+        acc += ABS ? gnk::nbr_term(yv[q]) : yv[q];
         if (ABS) bits |= __float_as_uint(yv[q]);
     }
 }

@@ -12,6 +12,8 @@
 
 // defined in gn_step.hip
 __global__ void wrgn_step_kernel(StepArgs a);
+__global__ void prune_rebuild_kernel(int32_t n, const int32_t* row_ptr, const int32_t* mloc, const float* y,
+                                     uint8_t* listed, int32_t* pbuf);
 
 // x (user order) -> signed weighted state y (internal order); flags x < 0 or
 // non-finite (err bit 1).
@@ -214,13 +216,36 @@ extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, 
     return gn_internal_step_with(g, gamma, x_in, x_out, g->ws.y[0], stream);
 }
 
-// Captured chain of `len` step launches for steps [c*len, (c+1)*len).
-static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t* out) {
+// Captured chain of `len` step launches for steps [c*len, (c+1)*len), after a
+// rebuild of the pruned lists from the chain's input state when they are used
+// (the first chain's rebuild sets the lists for the solve's start).
+static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hipGraphExec_t* out) {
     GraphWorkspace& ws = g->ws;
+    if (prune && (!g->prune || !g->prune_mloc || !g->listed)) return GN_E_ARG;  // no pruned lists to read
     hipGraph_t graph;
     GN_HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
     const int nblk = gn_internal_grid_blocks(g->bins);
+    if (prune) {
+        int32_t n = g->n;
+        const int32_t* rp = g->row_ptr;
+        const int32_t* ml = g->prune_mloc;
+        const float* y = ws.y[(c * len) & 1];
+        uint8_t* lst = g->listed;
+        int32_t* pb = g->prune;
+        void* args[] = {&n, &rp, &ml, &y, &lst, &pb};
+        hipKernelNodeParams p{};
+        p.func = (void*)prune_rebuild_kernel;
+        p.gridDim = dim3((unsigned)(((int64_t)n * 8 + 255) / 256));
+        p.blockDim = dim3(256);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return GN_E_HIP;
+        }
+    }
     for (int32_t j = 0; j < len; ++j) {
         StepArgs a = base_args(g);
         a.k = c * len + j;
@@ -231,6 +256,14 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t
         a.st = ws.state;
         a.notconv = ws.notconv;
         a.x_out_user = nullptr;
+        if (prune) {
+            a.prune = 1;
+            a.pbuf = g->prune;
+            a.mloc = g->prune_mloc;
+            a.listed = g->listed;
+            a.sl_col = g->prune;
+            a.col = g->prune + g->prune_sl_words;
+        }
         void* args[] = {&a};
         hipKernelNodeParams p{};
         p.func = (void*)wrgn_step_kernel;
@@ -253,6 +286,13 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, hipGraphExec_t
 }
 
 int32_t g_chunk_len = 32;
+int32_t g_prune = 1;
+
+extern "C" gn_status gn_set_pruning(int32_t mode) {
+    if (mode < 0 || mode > 2) return GN_E_ARG;
+    g_prune = mode;
+    return GN_OK;
+}
 
 int32_t g_small_limit = kSmallWorkMax;
 
@@ -300,9 +340,15 @@ extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uin
         st = gn_internal_small_solve(g, stream);
         if (st == GN_OK && hipStreamSynchronize(stream) != hipSuccess) st = GN_E_HIP;
     } else {
-        st = gn_internal_run_chunks(ws, nchunks, C,
-                                    [g, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, out); },
-                                    stream);
+        const bool prune = g->prune && (g_prune == 2 || (g_prune == 1 && g->prune_pays));
+        if (ws.chunk_prune != (prune ? 1 : 0)) {  // chains captured for the other kind of lists
+            for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+            ws.chunks.clear();
+            ws.chunk_prune = prune ? 1 : 0;
+        }
+        st = gn_internal_run_chunks(
+            ws, nchunks, C, [g, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, prune, out); },
+            stream);
     }
     if (st != GN_OK) return st;
     int32_t steps;

@@ -20,9 +20,39 @@ using gnk::sign_of;
 
 namespace {
 
-// Row epilogue; returns true when the input state fails the stopping test at row i.
-__device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<StepArgs>& c, int i, float yraw, float vi,
-                                           float sigma, bool nbr_sel, int& fb) {
+// Pruned lists (solve mode).  A neighbour sum adds only ordinary words, so the
+// entry of a vertex that is not ordinary adds nothing whether it is read or
+// not: the lists may drop it.  Invariant: every vertex whose word is ordinary
+// in a step's input is listed (its entries hold its id) when the step reads
+// the lists.  A row whose word becomes ordinary again in this step (input not
+// ordinary, output ordinary) lists itself now if it is not listed: during
+// this step its entries add nothing either way, and the next step finds it
+// listed.  Dropping vertices that stopped being ordinary is left to
+// prune_rebuild_kernel, run before every captured chain of steps.
+__device__ __forceinline__ bool prune_revives(float yraw, float yn) {
+    return gnk::mag_bits(yraw) < gnk::kLogTop && gnk::mag_bits(yn) >= gnk::kLogTop;
+}
+
+// Writes val into row i's mirror entries, thread t of nt: 16 mirror locations
+// loaded back to back per round, so a row costs about two memory latencies
+// (row offsets, then the locations) whatever its length per thread.
+__device__ __forceinline__ void prune_write(const StepArgs& a, int i, int val, int t, int nt) {
+    constexpr int U = 16;
+    const int e1 = a.row_ptr[i + 1];
+    for (int e = a.row_ptr[i] + t; e < e1; e += nt * U) {
+        int m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = e + u * nt < e1 ? a.mloc[e + u * nt] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (m[u] >= 0) a.pbuf[m[u]] = val;
+    }
+}
+
+// Row epilogue; returns true when the input state fails the stopping test at row
+// i.  act is set when the row must list itself in the pruned lists.
+__device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<StepArgs>& c, int i, float yraw,
+                                           float vi, float sigma, bool nbr_sel, int& fb, int& act) {
     const float yi = fabsf(yraw);
     const float s = __fmaf_rn(c.g, sigma, yi);
     const bool fallback = !(s > 1e-9f);
@@ -32,6 +62,10 @@ __device__ __forceinline__ bool row_update(const StepArgs& a, const StepCtl<Step
         if (a.y_out) a.y_out[i] = yn;
         if (a.x_out_user) a.x_out_user[a.perm[i]] = gnk::step_x(yraw, vi, s, yn);
         fb += fallback ? 1 : 0;
+        if (a.prune && prune_revives(yraw, yn) && !a.listed[i]) {
+            act = 1;
+            a.listed[i] = 1;
+        }
     }
     if (!c.do_test) return false;
     const bool in_s = sign_of(yraw) != 0u;
@@ -74,8 +108,13 @@ __device__ __forceinline__ int sliced_rows(const StepArgs& a, StepCtl<StepArgs>&
     unsigned sel = 0u;
     const float sigma = idx.template sum<true>(a.y_in, sel);
     const bool any_sel = gnk::group_any<G>(sel != 0u);
-    if (valid && t == 0) return row_update(a, c, i, yraw, vi, sigma, any_sel, fb) ? 1 : 0;
-    return 0;
+    int res = 0, act = 0;
+    if (valid && t == 0) res = row_update(a, c, i, yraw, vi, sigma, any_sel, fb, act) ? 1 : 0;
+    if (a.prune) {  // the row's G threads write its mirror entries
+        if constexpr (G > 1) act = __shfl(act, lane & ~(G - 1), 64);
+        if (act) prune_write(a, i, i, t, G);
+    }
+    return res;
 }
 
 }  // namespace
@@ -84,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
     __shared__ float stage[kStage];
     __shared__ int s_viol[kWaves];
     __shared__ int s_fb[kWaves];
+    __shared__ int s_act;
 
     // the gamma and flag tables cover every step index a captured chain can reach
     StepCtl<StepArgs> c;
@@ -120,13 +160,16 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
                 cidx[u] = p < cn ? a.col[start + c0 + p] : -1;
             }
 #pragma unroll
-            for (int u = 0; u < PT; ++u)
-                if (cidx[u] >= 0) stage[threadIdx.x + kBlock * u] = a.y_in[cidx[u]];
+            for (int u = 0; u < PT; ++u) {
+                // -1 inside the row: an entry of the pruned lists, which adds nothing
+                const int p = threadIdx.x + kBlock * u;
+                if (p < cn) stage[p] = cidx[u] >= 0 ? a.y_in[cidx[u]] : 0.0f;
+            }
             __syncthreads();
             if (wave == 0) {
                 for (int q = lane; q < cn; q += 64) {
                     const float yv = stage[q];
-                    acc += fabsf(yv);
+                    acc += gnk::nbr_term(yv);
                     sel |= sign_of(yv);
                 }
             }
@@ -135,7 +178,15 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
         if (wave == 0) {
             for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
             const bool any_sel = __any(sel != 0u);
-            if (lane == 0) r = row_update(a, c, i, yraw, vi, acc, any_sel, fb) ? 1 : 0;
+            int act = 0;
+            if (lane == 0) {
+                r = row_update(a, c, i, yraw, vi, acc, any_sel, fb, act) ? 1 : 0;
+                s_act = act;
+            }
+        }
+        if (a.prune) {  // the whole workgroup writes the row's mirror entries
+            __syncthreads();
+            if (s_act) prune_write(a, i, i, threadIdx.x, kBlock);
         }
     } else if (b == BIN_WAVE) {
         // two rows per wavefront, all their loads in flight together
@@ -165,8 +216,14 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
                                                  sela, selb);
             const bool anya = __any(sela != 0u);
             const bool anyb = __any(selb != 0u);
-            if (lane == 0) r = row_update(a, c, ia, ya, va, acca, anya, fb) ? 1 : 0;
-            if (lane == 1 && hb) r = row_update(a, c, ib, yb, vb, accb, anyb, fb) ? 1 : 0;
+            int pact = 0;
+            if (lane == 0) r = row_update(a, c, ia, ya, va, acca, anya, fb, pact) ? 1 : 0;
+            if (lane == 1 && hb) r = row_update(a, c, ib, yb, vb, accb, anyb, fb, pact) ? 1 : 0;
+            if (a.prune) {  // the whole wavefront writes the rows' mirror entries
+                const int act_a = __shfl(pact, 0, 64), act_b = __shfl(pact, 1, 64);
+                if (act_a) prune_write(a, ia, ia, lane, 64);
+                if (act_b) prune_write(a, ib, ib, lane, 64);
+            }
         }
     } else {
         if (b == BIN_G8) r = sliced_rows<8, 128>(a, c, b, rb, re, lb, fb);
@@ -197,6 +254,35 @@ __global__ __launch_bounds__(kBlock) void wrgn_step_kernel(StepArgs a) {
             if (f) atomicAdd(&a.st->fallback, (unsigned long long)f);
         }
     }
+}
+
+// Drops from the pruned lists every listed vertex whose word in y (the input
+// of the next step) is not ordinary, and lists any ordinary one that is not
+// (none while the invariant holds; at a solve's start, y_0 decides).  Eight
+// lanes per row, each writing every eighth mirror entry; rows whose listing is
+// already right cost one byte and one word read.
+__global__ __launch_bounds__(256) void prune_rebuild_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
+                                                           const int32_t* __restrict__ mloc,
+                                                           const float* __restrict__ y, uint8_t* __restrict__ listed,
+                                                           int32_t* __restrict__ pbuf) {
+    constexpr int G = 8, U = 16;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int t = (int)(tid % G);
+    if (i >= n) return;
+    const bool want = gnk::mag_bits(y[i]) >= gnk::kLogTop;
+    if ((listed[i] != 0) == want) return;
+    const int32_t val = want ? i : -1;
+    const int32_t e1 = row_ptr[i + 1];
+    for (int32_t e = row_ptr[i] + t; e < e1; e += G * U) {
+        int32_t m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = e + u * G < e1 ? mloc[e + u * G] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (m[u] >= 0) pbuf[m[u]] = val;
+    }
+    if (t == 0) listed[i] = want ? 1 : 0;
 }
 
 gn_status gn_internal_launch_step(const gn_graph* g, const StepArgs& a, hipStream_t s) {

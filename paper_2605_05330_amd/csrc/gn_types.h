@@ -103,4 +103,11 @@ struct StepArgs {
     const int32_t* sl_col;   // sliced columns of the group bins (64-word lines)
     const int32_t* sl_off;   // first line of each slice; slice s spans lines [sl_off[s], sl_off[s+1])
     BinLayout bins;
+    // pruned lists (solve mode): col and sl_col then point into pbuf, whose
+    // entries of unlisted vertices are -1; the rows that change listing rewrite
+    // their mirror entries
+    int32_t prune;
+    int32_t* pbuf;
+    const int32_t* mloc;     // [nnz] location of each entry's mirror in pbuf
+    uint8_t* listed;         // [n]
 };

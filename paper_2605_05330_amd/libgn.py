@@ -90,6 +90,7 @@ def lib():
             "gn_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "gn_set_chunk_len": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_small_graph_limit": ([ctypes.c_int32], ctypes.c_int),
+            "gn_set_pruning": ([ctypes.c_int32], ctypes.c_int),
             "gn_atom_census": ([ctypes.c_int32, ctypes.POINTER(gn_atom_counts), _vp], ctypes.c_int),
             "gn_batch_create": ([ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
                                 ctypes.c_int),
@@ -309,6 +310,15 @@ SMALL_LIMIT_DEFAULT = 1 << 20
 
 def gn_set_small_graph_limit(work_max: int):
     _check(lib().gn_set_small_graph_limit(int(work_max)), "gn_set_small_graph_limit")
+
+
+PRUNE_NEVER, PRUNE_WHERE_IT_PAYS, PRUNE_ALWAYS = 0, 1, 2
+
+
+def gn_set_pruning(mode: int):
+    """Pruned neighbour lists in gn_solve's chained path: PRUNE_NEVER,
+    PRUNE_WHERE_IT_PAYS (the default) or PRUNE_ALWAYS; results do not change."""
+    _check(lib().gn_set_pruning(int(mode)), "gn_set_pruning")
 
 
 class Graph:

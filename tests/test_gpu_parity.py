@@ -492,6 +492,70 @@ def test_small_graph_path_bitexact(gpu, case):
         assert ra.steps == 40 and not ra.binarised
 
 
+@pytest.mark.parametrize("case", ["regrowth", "hubs", "rook48", "sparse_start", "check_every", "ba200k"])
+def test_pruned_lists_same_bits(gpu, case):
+    """The chained solve reads pruned neighbour lists (vertices whose state is
+    not ordinary dropped from their neighbours' lists, put back when they
+    regrow).  With and without them: the same steps, states, sets, objectives,
+    stab and fallback counts, bit for bit.  Cases: regrowth from deep decay
+    (vertices leave and re-enter the lists), rows of every bin including one
+    above 512 (its workgroup rewrites the entries), the 48x48 rook graph (rows of
+    degree 94), a start with exact zeros and log-form values (unlisted from the
+    first step), a stopping test every 5 steps, and the BA n=200,000 workload."""
+    import torch
+    libgn = _lib()
+    sch = dict(SCHED_RAMP)
+    x0 = None
+    if case == "regrowth":
+        g = I.erdos_renyi(1500, 6 / 1499, 109)
+        w = I.weights_uniform01(g.n, 109)
+    elif case == "hubs":
+        g = I.hub_graph(1200, [20, 60, 200, 700, 1100], 3.0, 5)
+        w = I.weights_uniform01(g.n, 3)
+    elif case == "rook48":
+        g = I.rook(48)
+        w, _ = I.rook_weights(48, 48)
+    elif case == "sparse_start":
+        g = I.erdos_renyi(2000, 8 / 1999, 41)
+        w = I.weights_uniform01(g.n, 41)
+        rng = np.random.default_rng(41)
+        x0 = (1.0 - rng.random(g.n)).astype(F32)
+        u = rng.random(g.n)
+        x0[u < 0.2] = 0.0
+        x0[(u >= 0.2) & (u < 0.4)] = F32(1e-35)
+    elif case == "check_every":
+        g = I.unit_disk(5000, 10, 42)
+        w = I.weights_uniform01(g.n, 42)
+        sch = dict(SCHED_CONST, check_every=5)
+    else:
+        g = I.barabasi_albert(200_000, 5, 0)
+        w = I.weights_uniform01(g.n, 0)
+    if x0 is None:
+        x0 = np.full(g.n, 0.5, F32)
+    G = _graph(g, w)
+    outs = []
+    try:
+        libgn.gn_set_small_graph_limit(0)
+        for prune in (libgn.PRUNE_ALWAYS, libgn.PRUNE_NEVER):
+            libgn.gn_set_pruning(prune)
+            x = dev(x0)
+            sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+            r = G.solve(x, sel, **sch)
+            outs.append((r, x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
+    finally:
+        libgn.gn_set_pruning(libgn.PRUNE_WHERE_IT_PAYS)
+        libgn.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT)
+    (ra, xa, sa), (rb, xb, sb) = outs
+    assert (ra.steps, ra.binarised, ra.fallback_count) == (rb.steps, rb.binarised, rb.fallback_count)
+    assert np.array_equal(xa, xb) and np.array_equal(sa, sb)
+    assert ra.set_objective == rb.set_objective and ra.relaxed_objective == rb.relaxed_objective
+    assert ra.stab == rb.stab and ra.uncovered == rb.uncovered and ra.conflicts == rb.conflicts
+    if case == "regrowth":
+        assert ra.steps == 1459
+    if case == "ba200k":
+        assert ra.steps == 881
+
+
 @pytest.mark.parametrize("gamma", [0.9, 1.5])
 def test_relaxed_objective_grows_every_step(gpu, gamma):
     """Mass growth (Theorem 3): at a fixed gamma the weighted mass sum_i w_i x_i
