@@ -145,7 +145,7 @@ static void free_graph_buffers(gn_graph* g) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(g->row_ptr); f(g->col); f(g->v); f(g->w_int); f(g->w_user); f(g->perm); f(g->iperm);
     f(g->sl_col); f(g->sl_off);
-    f(g->prune); f(g->prune_mloc); f(g->listed);
+    f(g->prune); f(g->prune_mloc); f(g->listed); f(g->prune_mirror);
     GraphWorkspace& ws = g->ws;
     for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
     ws.chunks.clear();
@@ -375,9 +375,10 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
     // caller's per-row order, so mloc of internal entry (iperm[u], p) is the
     // location of internal entry (iperm[w], p').  A missing or repeated mirror
     // (a structure that was not validated) leaves the graph without pruned lists.
-    std::vector<int32_t> mloc;
+    std::vector<int32_t> mloc, mirror;
     if (prunable && nnz > 0) {
         mloc.assign((size_t)nnz, -1);
+        mirror.assign((size_t)nnz, -1);
         for (int32_t u = 0; u < n && prunable; ++u) {
             const int32_t r = iperm[u];
             for (int32_t p = 0; p < rp[u + 1] - rp[u]; ++p) {
@@ -391,6 +392,7 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
                 }
                 const int32_t e_mirror = rp_int[iperm[wv]] + (int32_t)(it - b0);
                 mloc[(size_t)rp_int[r] + p] = loc_of[(size_t)e_mirror];
+                mirror[(size_t)rp_int[r] + p] = e_mirror;
             }
         }
     }
@@ -398,7 +400,8 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
 
     st = GN_OK;
     if (prunable && ((st = dev_alloc(&g->prune, (size_t)(sl_words + nnz))) ||
-                     (st = dev_alloc(&g->prune_mloc, (size_t)nnz)) || (st = dev_alloc(&g->listed, (size_t)n)))) {
+                     (st = dev_alloc(&g->prune_mloc, (size_t)nnz)) || (st = dev_alloc(&g->listed, (size_t)n)) ||
+                     (st = dev_alloc(&g->prune_mirror, (size_t)nnz)))) {
         free_graph_buffers(g);
         delete g;
         return st;
@@ -431,6 +434,7 @@ extern "C" gn_status gn_graph_create(int32_t n, int64_t nnz, const int32_t* row_
         up(g->prune, sl_col.data(), sizeof(int32_t) * (size_t)sl_words);
         up(g->prune + sl_words, col_int.data(), sizeof(int32_t) * (size_t)nnz);
         up(g->prune_mloc, mloc.data(), sizeof(int32_t) * (size_t)nnz);
+        up(g->prune_mirror, mirror.data(), sizeof(int32_t) * (size_t)nnz);
         if (e == hipSuccess) e = hipMemsetAsync(g->listed, 1, (size_t)n, stream);  // every vertex listed
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

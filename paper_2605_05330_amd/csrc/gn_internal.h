@@ -55,6 +55,7 @@ struct gn_graph {
     int64_t prune_sl_words = 0;     // words of the sliced part
     int32_t* prune_mloc = nullptr;  // [nnz]: where entry (i -> j) of row i sits in row j's list, as i
     uint8_t* listed = nullptr;      // [n]: vertex present (not -1) in its neighbours' pruned lists
+    int32_t* prune_mirror = nullptr;  // [nnz]: CSR index of each entry's mirror (the multi-start lists)
     bool prune_pays = false;        // the gathers have little locality (gn_set_pruning mode 1)
     BinLayout bins{};
     int32_t bin_count_rows[BIN_COUNT] = {0};

@@ -56,6 +56,12 @@ struct MultiArgs {
     int32_t l16_begin;               // light rows of degree <= 16 start here
     int32_t mid_blk, light_blk;      // first block of the mid and light parts
     int32_t l16_blk;                 // light blocks before the degree <= 16 rows
+    // pruned lists: col then points at a copy of the CSR columns in which the
+    // entries of vertices with no ordinary state in any start hold -1
+    int32_t prune;
+    int32_t* pcol;                   // the copy (written on revivals)
+    const int32_t* mirror;           // [nnz] CSR index of each entry's mirror
+    uint8_t* listed;                 // [n]
 };
 
 // Lanes work on quads of starts: lane l handles starts 4q .. 4q+3 with q = l % 4
@@ -120,7 +126,7 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int off) {
 // value already in y_out's slot (its final state may live there).
 __device__ __forceinline__ unsigned quad_update(const MultiArgs& a, const QuadCtl& c, int i, int q,
                                                 const float4& yraw, float vi, const float4& sigma, unsigned nbr_sel,
-                                                unsigned (&fb)[4]) {
+                                                unsigned (&fb)[4], bool& ord_in, bool& ord_out) {
     unsigned viol = 0u;
     float out[4];
 #pragma unroll
@@ -131,6 +137,8 @@ __device__ __forceinline__ unsigned quad_update(const MultiArgs& a, const QuadCt
         const bool fallback = !(s > 1e-9f);
         out[j] = gnk::step_word(yr, vi, s);
         const bool on = (c.act >> j) & 1u;
+        ord_in |= on && gnk::mag_bits(yr) >= gnk::kLogTop;
+        ord_out |= on && c.do_write && gnk::mag_bits(out[j]) >= gnk::kLogTop;
         if (on && c.do_write) fb[j] += fallback ? 1u : 0u;
         if (on && c.do_test) {
             const bool in_s = sign_of(yr) != 0u;
@@ -152,6 +160,41 @@ __device__ __forceinline__ unsigned quad_update(const MultiArgs& a, const QuadCt
         }
     }
     return viol;
+}
+
+// Pruned lists (as in the single-start step): a vertex is listed while some
+// start's state of it may be ordinary.  Row i lists itself again when a
+// running start's new word is ordinary while none of its running starts' input
+// words was (then, and only then, it may have been dropped); during the step
+// its entries add nothing either way.  Drops are left to multi_rebuild_kernel,
+// run before every captured chain.  `rev`: the row's flags combined over its
+// lanes; threads t of nt write the mirror entries.
+__device__ __forceinline__ void multi_relist_rows(const MultiArgs& a, int i, int t, int nt);
+__device__ __forceinline__ void multi_relist(const MultiArgs& a, int i, bool rev, int t, int nt) {
+    if (!rev || a.listed[i]) return;  // every lane of the row reads before lane t = 0 writes
+    multi_relist_rows(a, i, t, nt);
+}
+__device__ __forceinline__ void multi_relist_rows(const MultiArgs& a, int i, int t, int nt) {
+    constexpr int U = 16;
+    const int e1 = a.row_ptr[i + 1];
+    for (int e = a.row_ptr[i] + t; e < e1; e += nt * U) {
+        int m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = e + u * nt < e1 ? a.mirror[e + u * nt] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (m[u] >= 0) a.pcol[m[u]] = i;
+    }
+    if (t == 0) a.listed[i] = 1;
+}
+
+// OR of a flag over the aligned group of W lanes (all lanes take part).
+template <int W>
+__device__ __forceinline__ bool group_or(bool f) {
+    unsigned v = f ? 1u : 0u;
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) v |= (unsigned)__shfl_xor((int)v, o, 64);
+    return v != 0u;
 }
 
 // Violation bits of the 16 starts over a wavefront: bit 4q + j from lanes
@@ -205,8 +248,14 @@ __device__ __forceinline__ unsigned light_rows16(const MultiArgs& a, QuadCtl& c,
     for (int off = 8; off >= 1; off >>= 1)
 #pragma unroll
         for (int j = 0; j < off; ++j) cs[j] = add4(cs[j], cs[j + off]);
-    if (!valid) return 0u;
-    return quad_update(a, c, i, q, yraw, vi, cs[0], sel, fb);
+    unsigned viol = 0u;
+    bool oi = false, oo = false;
+    if (valid) viol = quad_update(a, c, i, q, yraw, vi, cs[0], sel, fb, oi, oo);
+    if (a.prune) {  // the row's 4 lanes
+        const bool in_any = group_or<4>(oi), out_any = group_or<4>(oo);
+        if (valid) multi_relist(a, i, out_any && !in_any, q, 4);
+    }
+    return viol;
 }
 
 // Light rows of degree 17..32: 8 rows per wavefront, lane (r, t, q) =
@@ -249,8 +298,14 @@ __device__ __forceinline__ unsigned light_rows_g2(const MultiArgs& a, QuadCtl& c
         for (int j = 0; j < off / 2; ++j) cs[j] = add4(cs[j], cs[j + off / 2]);
     const float4 s = add4(cs[0], shfl4(cs[0], 4));
     sel |= __shfl_xor(sel, 4, 64);
-    if (!valid || t != 0) return 0u;
-    return quad_update(a, c, i, q, yraw, vi, s, sel, fb);
+    unsigned viol = 0u;
+    bool oi = false, oo = false;
+    if (valid && t == 0) viol = quad_update(a, c, i, q, yraw, vi, s, sel, fb, oi, oo);
+    if (a.prune) {  // the row's 8 lanes
+        const bool in_any = group_or<8>(oi), out_any = group_or<8>(oo);
+        if (valid) multi_relist(a, i, out_any && !in_any, lane & 7, 8);
+    }
+    return viol;
 }
 
 __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
@@ -258,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
     __shared__ float4 red[kBlock];
     __shared__ unsigned s_mask[kWaves];
     __shared__ unsigned s_sel[kWaves];
+    __shared__ bool s_rev;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = tid & 3;
     const int blk = blockIdx.x;
@@ -282,10 +338,15 @@ __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
             for (int u = 0; u < kChunk / kBlock; ++u) {
                 const int e = tid + kBlock * u;
                 if (e < cn) {
-                    const float4* src =
-                        reinterpret_cast<const float4*>(a.y_in + (size_t)a.col[start + c0 + e] * kStarts);
+                    const int j = a.col[start + c0 + e];
+                    if (j >= 0) {
+                        const float4* src = reinterpret_cast<const float4*>(a.y_in + (size_t)j * kStarts);
 #pragma unroll
-                    for (int h = 0; h < kStarts / 4; ++h) stage[e][h] = src[h];
+                        for (int h = 0; h < kStarts / 4; ++h) stage[e][h] = src[h];
+                    } else {  // an entry of the pruned lists: adds nothing
+#pragma unroll
+                        for (int h = 0; h < kStarts / 4; ++h) stage[e][h] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    }
                 }
             }
             __syncthreads();
@@ -311,7 +372,14 @@ __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
         if (lane == 0) s_sel[wave] = ws;
         __syncthreads();
         const unsigned all = s_sel[0] | s_sel[1] | s_sel[2] | s_sel[3];
-        if (tid < 4) viol = quad_update(a, c, i, q, yraw, vi, acc, (all >> (4 * q)) & 0xFu, fb);
+        bool oi = false, oo = false;
+        if (tid < 4) viol = quad_update(a, c, i, q, yraw, vi, acc, (all >> (4 * q)) & 0xFu, fb, oi, oo);
+        if (a.prune) {  // the whole workgroup, after thread 0 has read the flag
+            const bool in_any = group_or<4>(oi), out_any = group_or<4>(oo);
+            if (tid == 0) s_rev = out_any && !in_any && !a.listed[i];
+            __syncthreads();
+            if (s_rev) multi_relist_rows(a, i, tid, kBlock);
+        }
     } else if (blk < a.light_blk) {
         // mid row: one wavefront, lane (t, q) = (l / 4, l % 4) runs chains t, t+16,
         // t+32, t+48 (two entries each) for 4 starts
@@ -362,7 +430,12 @@ __global__ __launch_bounds__(kBlock) void multi_step_kernel(MultiArgs a) {
             const unsigned long long m = __ballot((sel >> j) & 1u);
             any |= (m & (0x1111111111111111ull << q)) ? 1u << j : 0u;
         }
-        if (valid && t == 0) viol = quad_update(a, c, i, q, yraw, vi, s, any, fb);
+        bool oi = false, oo = false;
+        if (valid && t == 0) viol = quad_update(a, c, i, q, yraw, vi, s, any, fb, oi, oo);
+        if (a.prune) {  // the whole wavefront
+            const bool in_any = __any(oi), out_any = __any(oo);
+            if (valid) multi_relist(a, i, out_any && !in_any, lane, 64);
+        }
     } else {
         bool quit = false;
         // the block-to-rows map of the single-start step (swizzle_block): blocks
@@ -437,6 +510,39 @@ __global__ void multi_normalizable_kernel(int32_t n, int32_t count, const int32_
     atomicOr(&st->err, 2);
 }
 
+// Drops from the multi-start lists every listed vertex none of whose 16 words
+// in y (the next step's input) is ordinary, and lists any other that is not
+// (the first chain's rebuild sets the lists for the solve's start).  Eight
+// lanes per row, two words each.
+__global__ __launch_bounds__(256) void multi_rebuild_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
+                                                           const int32_t* __restrict__ mirror,
+                                                           const float* __restrict__ y, uint8_t* __restrict__ listed,
+                                                           int32_t* __restrict__ pcol) {
+    constexpr int G = 8, U = 16;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(tid / G);
+    const int t = (int)(tid % G);
+    const bool valid = i < n;
+    bool o = false;
+    if (valid) {
+        const float2 w = reinterpret_cast<const float2*>(y + (size_t)i * kStarts)[t];
+        o = gnk::mag_bits(w.x) >= gnk::kLogTop || gnk::mag_bits(w.y) >= gnk::kLogTop;
+    }
+    const bool want = group_or<G>(o);  // every lane takes part
+    if (!valid || (listed[i] != 0) == want) return;
+    const int32_t val = want ? i : -1;
+    const int32_t e1 = row_ptr[i + 1];
+    for (int32_t e = row_ptr[i] + t; e < e1; e += G * U) {
+        int32_t m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) m[u] = e + u * G < e1 ? mirror[e + u * G] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (m[u] >= 0) pcol[m[u]] = val;
+    }
+    if (t == 0) listed[i] = want ? 1 : 0;
+}
+
 // start b's state out of the interleaved buffer
 __global__ void multi_extract_kernel(int32_t n, int32_t b, const float* __restrict__ y, float* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -506,6 +612,9 @@ struct MultiWS {
     int32_t nc16_cap = 0;    // steps covered by nc16
     FinalStats* stats = nullptr;  // [16] final statistics per start
     int32_t heavy_end = 0, mid_end = 0, l16_begin = 0, mid_blk = 0, light_blk = 0, l16_blk = 0, nblk = 0;
+    int32_t* pcol = nullptr;      // pruned lists (allocated on first use): a copy of the CSR columns
+    uint8_t* listed = nullptr;    // [n]
+    int32_t chunk_prune = -1;     // whether the captured chains read the pruned lists
 };
 
 void free_ws(MultiWS* m) {
@@ -513,6 +622,7 @@ void free_ws(MultiWS* m) {
     for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
     m->ws.chunks.clear();
     f(m->Y[0]); f(m->Y[1]); f(m->yb); f(m->done); f(m->fb); f(m->nc16); f(m->maxbits); f(m->stats);
+    f(m->pcol); f(m->listed);
     f(m->ws.state); f(m->ws.notconv); f(m->ws.gamma);
     if (m->ws.host_pinned) (void)hipHostFree(m->ws.host_pinned);
     delete m;
@@ -567,10 +677,31 @@ gn_status ensure_tables(MultiWS* m, int32_t steps) {
     return GN_OK;
 }
 
-gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, hipGraphExec_t* out) {
+gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, bool prune, hipGraphExec_t* out) {
+    if (prune && (!m->pcol || !m->listed || !g->prune_mirror)) return GN_E_ARG;  // no pruned lists to read
     hipGraph_t graph;
     GN_HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
+    if (prune) {  // rebuild of the lists from the chain's input state
+        int32_t n = g->n;
+        const int32_t* rp = g->row_ptr;
+        const int32_t* mi = g->prune_mirror;
+        const float* y = m->Y[(c * len) & 1];
+        uint8_t* lst = m->listed;
+        int32_t* pc = m->pcol;
+        void* args[] = {&n, &rp, &mi, &y, &lst, &pc};
+        hipKernelNodeParams p{};
+        p.func = (void*)multi_rebuild_kernel;
+        p.gridDim = dim3((unsigned)(((int64_t)n * 8 + 255) / 256));
+        p.blockDim = dim3(256);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return GN_E_HIP;
+        }
+    }
     for (int32_t q = 0; q < len; ++q) {
         MultiArgs a{};
         a.row_ptr = g->row_ptr;
@@ -591,6 +722,13 @@ gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, hip
         a.mid_blk = m->mid_blk;
         a.light_blk = m->light_blk;
         a.l16_blk = m->l16_blk;
+        if (prune) {
+            a.prune = 1;
+            a.col = m->pcol;
+            a.pcol = m->pcol;
+            a.mirror = g->prune_mirror;
+            a.listed = m->listed;
+        }
         void* args[] = {&a};
         hipKernelNodeParams p{};
         p.func = (void*)multi_step_kernel;
@@ -657,9 +795,28 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
                        (const float*)m->Y[0], m->ws.state);
     GN_HIP_TRY(hipGetLastError());
 
+    // pruned lists (gn_set_pruning): allocated on first use as a copy of the
+    // columns with every vertex listed
+    const bool prune = g->prune_mirror && (g_prune == 2 || (g_prune == 1 && g->prune_pays));
+    if (prune && !m->pcol) {
+        if (hipMalloc(&m->pcol, sizeof(int32_t) * (size_t)std::max<int64_t>(g->nnz, 1)) != hipSuccess ||
+            hipMalloc(&m->listed, (size_t)n) != hipSuccess) {
+            (void)hipGetLastError();
+            if (m->pcol) (void)hipFree(m->pcol);
+            m->pcol = nullptr;
+            return GN_E_NOMEM;
+        }
+        GN_HIP_TRY(hipMemcpyAsync(m->pcol, g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToDevice, stream));
+        GN_HIP_TRY(hipMemsetAsync(m->listed, 1, (size_t)n, stream));
+    }
+    if (m->chunk_prune != (prune ? 1 : 0)) {  // chains captured for the other kind of lists
+        for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        m->ws.chunks.clear();
+        m->chunk_prune = prune ? 1 : 0;
+    }
     st = gn_internal_run_chunks(
-        m->ws, nchunks, C, [g, m, C](int32_t c, hipGraphExec_t* out) { return build_chunk(g, m, c, C, out); },
-        stream);
+        m->ws, nchunks, C,
+        [g, m, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, m, c, C, prune, out); }, stream);
     if (st != GN_OK) return st;
 
     // solve state, per-start outcomes and the last step's flags in one round trip

@@ -107,6 +107,51 @@ def test_multi_budget_exhausted_bitexact(gpu):
     assert all(r.steps == 60 and not r.binarised for r in res)
 
 
+@pytest.mark.parametrize("case", ["hubs", "er_5_starts", "regrowth", "budget", "ba50k"])
+def test_multi_pruned_lists_same_bits(gpu, case):
+    """The multi-start solve with its pruned lists (entries of vertices none of
+    whose states is ordinary not gathered; dropped before each chain, put back
+    by the step that revives one) and without: every start's steps, states,
+    sets and statistics bit for bit."""
+    import torch
+    libgn = _lib()
+    sched = dict(RAMP)
+    starts = 16
+    if case == "hubs":
+        g = I.hub_graph(6000, [40, 100, 200, 600, 1500], 4.0, 3)   # heavy, mid and light rows
+        sched["max_steps"] = 3000
+    elif case == "er_5_starts":
+        g = I.erdos_renyi(5000, 8 / 4999, 21)
+        starts = 5
+    elif case == "regrowth":
+        g = I.erdos_renyi(1500, 6 / 1499, 109)
+    elif case == "budget":
+        g = I.erdos_renyi(2000, 8 / 1999, 8)
+        sched["max_steps"] = 200
+    else:
+        g = I.barabasi_albert(50_000, 5, 22)
+    w = I.weights_uniform01(g.n, 3)
+    G = libgn.Graph(g.n, g.row_ptr, g.col_idx, w)
+    _, x0 = _random_x0(G, starts, g.n, 6)
+    if case == "regrowth":
+        x0[:g.n] = 0.5
+    outs = []
+    try:
+        for mode in (libgn.PRUNE_ALWAYS, libgn.PRUNE_NEVER):
+            libgn.gn_set_pruning(mode)
+            x = x0.clone()
+            sel = torch.zeros(starts * g.n, dtype=torch.uint8, device="cuda")
+            st, res, best = G.multi_solve(starts, x, sel, **sched)
+            outs.append((st, [(r.steps, r.binarised, r.fallback_count, r.set_objective, r.relaxed_objective,
+                               r.stab, r.conflicts, r.uncovered) for r in res], best,
+                         x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
+    finally:
+        libgn.gn_set_pruning(libgn.PRUNE_WHERE_IT_PAYS)
+    a, b = outs
+    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+    assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
+
+
 def test_multi_matches_oracle(gpu):
     g = I.erdos_renyi(1000, 8 / 999, 9)
     w = I.weights_uniform01(g.n, 9)
