@@ -646,7 +646,9 @@ gn_status gn_set_small_graph_limit(int32_t work_max);
  * the step that produces that state, before any step reads it.  mode 0: never;
  * 1 (the default): on graphs whose gathers have little cache-line locality in
  * the internal order (most gathers touch a line of their own), where skipping
- * them pays; 2: on every graph.  The lists are built at graph creation (the
+ * them pays, and for gn_multi_solve (whose lists drop a vertex only when none
+ * of its starts is ordinary) only when its 64 n bytes of states outgrow 4 MB;
+ * 2: on every graph.  The lists are built at graph creation (the
  * mirror position of every entry; graphs created with GN_NO_VALIDATE whose
  * structure is not symmetric with sorted rows have none).  Results are the
  * same bits in every mode.  GN_E_ARG for another mode.  Process-wide; not

@@ -796,8 +796,12 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
     GN_HIP_TRY(hipGetLastError());
 
     // pruned lists (gn_set_pruning): allocated on first use as a copy of the
-    // columns with every vertex listed
-    const bool prune = g->prune_mirror && (g_prune == 2 || (g_prune == 1 && g->prune_pays));
+    // columns with every vertex listed.  By default only where the 64-byte state
+    // rows (64 n bytes) outgrow an XCD's 4 MB L2, so that the skipped gathers
+    // would have missed it: on smaller graphs they were L2 hits and the lists'
+    // upkeep costs more (a 10,000-vertex conflict graph: +10%).
+    const bool prune = g->prune_mirror &&
+                       (g_prune == 2 || (g_prune == 1 && g->prune_pays && 64ll * g->n > (4ll << 20)));
     if (prune && !m->pcol) {
         if (hipMalloc(&m->pcol, sizeof(int32_t) * (size_t)std::max<int64_t>(g->nnz, 1)) != hipSuccess ||
             hipMalloc(&m->listed, (size_t)n) != hipSuccess) {
