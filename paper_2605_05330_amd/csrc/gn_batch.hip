@@ -204,35 +204,38 @@ __device__ void solve_graph(const BatchArgs& a, const BatchDesc& d, int gi, floa
                 const int i = 64 * s + lane;
                 const bool valid = i < d.n_light;
                 const float vi = valid ? vv[i] : 1.0f;
+                const float yr = valid ? yin[i] : 0.0f;  // issued ahead of the gathers
                 const int o = so[s];
                 const int W = __builtin_amdgcn_readfirstlane(so[s + 1] - o);
                 unsigned bits = 0u;
                 const float sigma = slice_sum<1, 16, kLightMaxDeg>(ln + o * 64 + lane, W, yin, bits);
                 if (valid)
-                    viol |= step_row(yin[i], vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, a.tau, yout, i, fb);
+                    viol |= step_row(yr, vi, sigma, (bits >> 31) != 0u, g, do_test, do_write, a.tau, yout, i, fb);
             }
 #pragma unroll 1
             for (int s = w_mid; s < nM; s += NW) {
                 const int i = d.n_light + 8 * s + (lane >> 3);
                 const bool valid = i < d.n_mid && (lane & 7) == 0;
                 const float vi = valid ? vv[i] : 1.0f;
+                const float yr = valid ? yin[i] : 0.0f;
                 const int o = so[nL + s];
                 const int W = __builtin_amdgcn_readfirstlane(so[nL + s + 1] - o);
                 unsigned bits = 0u;
                 const float sigma = slice_sum<8, 8, kMidMaxDegCap / 8>(ln + o * 64 + lane, W, yin, bits);
                 const bool any_sel = gnk::group_any<8>((bits >> 31) != 0u);
-                if (valid) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+                if (valid) viol |= step_row(yr, vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
             }
 #pragma unroll 1
             for (int s = w_heavy; s < n - d.n_mid; s += NW) {
                 const int i = d.n_mid + s;
                 const float vi = lane == 0 ? vv[i] : 1.0f;
+                const float yr = lane == 0 ? yin[i] : 0.0f;
                 const int o = so[nL + nM + s];
                 const int W = __builtin_amdgcn_readfirstlane(so[nL + nM + s + 1] - o);
                 unsigned bits = 0u;
                 const float sigma = heavy_sum(ln + o * 64 + lane, W, yin, bits);
                 const bool any_sel = __any((bits >> 31) != 0u);
-                if (lane == 0) viol |= step_row(yin[i], vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
+                if (lane == 0) viol |= step_row(yr, vi, sigma, any_sel, g, do_test, do_write, a.tau, yout, i, fb);
             }
         } else {
 #pragma unroll 1
