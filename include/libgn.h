@@ -459,12 +459,13 @@ typedef struct {
     int64_t labelled_evaluated;    /* labelled graphs the kernel classified             */
 } gn_atom_counts;
 
-/* Count the connected graphs on n vertices (1 <= n <= 8) and their atomic
+/* Count the connected graphs on n vertices (1 <= n <= 9) and their atomic
  * classes, up to isomorphism.  By Burnside's lemma over the cycle types of the
  * vertex permutations, each labelled graph fixed by a representative
  * permutation is classified on the device (one thread each: 2^28 graphs at
- * n = 8), exactly (fraction-free elimination of [B | 1], whose entries stay
- * below 2^24); the weighted sums are divided by n! on the host.  Allocates and
+ * n = 8, 2^36 at n = 9, which takes about a minute), exactly (fraction-free
+ * elimination of [B | 1], whose entries stay below 2^24); the weighted sums
+ * are divided by n! on the host.  Allocates and
  * frees its own device buffers.  Errors: GN_E_ARG (n out of range, out NULL),
  * GN_E_NOMEM, GN_E_HIP, GN_E_NUMERIC (a weighted sum not divisible by n!: an
  * internal inconsistency, never expected).  SYNC. */

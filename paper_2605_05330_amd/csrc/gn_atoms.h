@@ -9,26 +9,53 @@
 #include <cstdint>
 #include <vector>
 
-constexpr int kAtomMaxN = 8;
+constexpr int kAtomMaxN = 9;
+
+// A labelled graph as its adjacency rows packed at a fixed stride: row i (the
+// neighbours of vertex i) in bits [S i, S i + S).  Up to 8 vertices the rows
+// fit 8-bit fields of a 64-bit word; 9 vertices need 9-bit fields, 81 bits.
+template <int N>
+struct AtomRows {
+    using type = uint64_t;
+    static constexpr int S = 8;
+};
+template <>
+struct AtomRows<9> {
+    using type = unsigned __int128;
+    static constexpr int S = 9;
+};
+template <int N>
+using AtomRowsT = typename AtomRows<N>::type;
+
+// Neighbours of vertex i.
+template <int N>
+__host__ __device__ __forceinline__ unsigned atom_row(const AtomRowsT<N> rows, const int i) {
+    constexpr int S = AtomRows<N>::S;
+    return (unsigned)(rows >> (S * i)) & ((1u << S) - 1u);
+}
+
+// The packing stride for n vertices, for host code that takes n at run time.
+inline int atom_stride(int n) { return n <= 8 ? 8 : 9; }
 
 // Per-graph counters: connected graphs, then atomic irregular discrete,
 // irregular continuous, regular discrete, regular continuous.
 constexpr int kAtomCounters = 5;
 
 // Fraction-free elimination of [B_S | 1], B = A + I, S = the columns in
-// `colmask` (the others read as zero); `rows` holds the adjacency rows (byte i =
-// neighbours of vertex i).  rank: rank of B_S; consistent: 1 lies in the span of
-// B_S.  When B_S has full column rank and the system is consistent, pos / neg
-// receive the columns of S whose (unique) solution component is > 0 / < 0.
+// `colmask` (the others read as zero); `rows` holds the adjacency rows.  rank:
+// rank of B_S; consistent: 1 lies in the span of B_S.  When B_S has full column
+// rank and the system is consistent, pos / neg receive the columns of S whose
+// (unique) solution component is > 0 / < 0.
 template <int N>
-__host__ __device__ inline void atom_eliminate(const uint64_t rows, const unsigned colmask, int& rank,
+__host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const unsigned colmask, int& rank,
                                                bool& consistent, unsigned& pos, unsigned& neg) {
     float M[N][N + 1];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
+        const unsigned ri = atom_row<N>(rows, i);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const unsigned a = i == j ? 1u : (unsigned)((rows >> (8 * i + j)) & 1u);
+            const unsigned a = i == j ? 1u : (ri >> j) & 1u;
             M[i][j] = ((colmask >> j) & 1u) ? (float)a : 0.0f;
         }
         M[i][N] = 1.0f;
@@ -112,7 +139,7 @@ __host__ __device__ inline void atom_eliminate(const uint64_t rows, const unsign
 // [B | 1]: -1 not atomic, 0 atomic and discrete, or the rank of B (>= 1) when B
 // is singular and 1 lies in its span, which atom_singular_class decides.
 template <int N>
-__host__ __device__ inline int atom_class_first(const uint64_t rows) {
+__host__ __device__ inline int atom_class_first(const AtomRowsT<N> rows) {
     constexpr unsigned full = (1u << N) - 1u;
     int r;
     bool cons;
@@ -129,7 +156,7 @@ __host__ __device__ inline int atom_class_first(const uint64_t rows) {
 // step (Gosper), so lanes of a wavefront with different ranks each eliminate
 // their own subset in the same trip; a lane stops once its cover is complete.
 template <int N>
-__host__ __device__ inline int atom_singular_class(const uint64_t rows, const int r) {
+__host__ __device__ inline int atom_singular_class(const AtomRowsT<N> rows, const int r) {
     constexpr unsigned full = (1u << N) - 1u;
     unsigned cover = 0u;
     for (unsigned S = (1u << r) - 1u; S <= full;) {
@@ -148,14 +175,14 @@ __host__ __device__ inline int atom_singular_class(const uint64_t rows, const in
 
 // Class of one connected graph: -1 not atomic, else 0 discrete / 1 continuous.
 template <int N>
-__host__ __device__ inline int atom_class(const uint64_t rows) {
+__host__ __device__ inline int atom_class(const AtomRowsT<N> rows) {
     const int f = atom_class_first<N>(rows);
     return f <= 0 ? f : atom_singular_class<N>(rows, f);
 }
 
 // Whether the graph is connected, and whether it is regular.
 template <int N>
-__host__ __device__ inline bool atom_connected(const uint64_t rows) {
+__host__ __device__ inline bool atom_connected(const AtomRowsT<N> rows) {
     constexpr unsigned full = (1u << N) - 1u;
     unsigned reach = 1u;  // grow the set reachable from vertex 0
 #pragma unroll
@@ -163,18 +190,18 @@ __host__ __device__ inline bool atom_connected(const uint64_t rows) {
         unsigned nx = reach;
 #pragma unroll
         for (int i = 0; i < N; ++i)
-            if ((reach >> i) & 1u) nx |= (unsigned)((rows >> (8 * i)) & 255u);
+            if ((reach >> i) & 1u) nx |= atom_row<N>(rows, i);
         reach = nx;
     }
     return reach == full;
 }
 
 template <int N>
-__host__ __device__ inline bool atom_regular(const uint64_t rows) {
-    const int d0 = __builtin_popcount((unsigned)(rows & 255u));
+__host__ __device__ inline bool atom_regular(const AtomRowsT<N> rows) {
+    const int d0 = __builtin_popcount(atom_row<N>(rows, 0));
     bool regular = true;
 #pragma unroll
-    for (int i = 1; i < N; ++i) regular = regular && __builtin_popcount((unsigned)((rows >> (8 * i)) & 255u)) == d0;
+    for (int i = 1; i < N; ++i) regular = regular && __builtin_popcount(atom_row<N>(rows, i)) == d0;
     return regular;
 }
 
@@ -187,7 +214,7 @@ __host__ __device__ inline void atom_count(const int cls, const bool regular, un
 
 // Adds one labelled graph to the counters.
 template <int N>
-__host__ __device__ inline void atom_evaluate(const uint64_t rows, unsigned (&cnt)[kAtomCounters]) {
+__host__ __device__ inline void atom_evaluate(const AtomRowsT<N> rows, unsigned (&cnt)[kAtomCounters]) {
     if (!atom_connected<N>(rows)) return;
     cnt[0] += 1u;
     atom_count(atom_class<N>(rows), atom_regular<N>(rows), cnt);
@@ -195,10 +222,12 @@ __host__ __device__ inline void atom_evaluate(const uint64_t rows, unsigned (&cn
 
 // One cycle type of the permutations of n vertices: its weight n!/z (the
 // number of permutations of that type) and the orbits of a representative
-// permutation on vertex pairs, each as adjacency rows (byte i = neighbours of i).
+// permutation on vertex pairs, each as adjacency rows packed at the stride of n
+// (AtomRows; 128 bits hold every n up to 9, and for n <= 8 the low 64 are the
+// packed rows themselves).
 struct AtomCycleType {
     long long weight;
-    std::vector<uint64_t> orbit_rows;
+    std::vector<unsigned __int128> orbit_rows;
 };
 
 inline void atom_partitions(int n, int maxp, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
@@ -242,13 +271,14 @@ inline std::vector<AtomCycleType> atom_cycle_types(int n, long long& nfact) {
             for (int j = i + 1; j < n; ++j) {
                 if (orbit[i * n + j] >= 0) continue;
                 const int o = (int)t.orbit_rows.size();
-                uint64_t rows = 0;
+                const int S = atom_stride(n);
+                unsigned __int128 rows = 0;
                 int a = i, b = j;
                 while (orbit[(a < b ? a : b) * n + (a < b ? b : a)] < 0) {
                     const int lo = a < b ? a : b, hi = a < b ? b : a;
                     orbit[lo * n + hi] = o;
-                    rows |= 1ull << (8 * lo + hi);
-                    rows |= 1ull << (8 * hi + lo);
+                    rows |= (unsigned __int128)1 << (S * lo + hi);
+                    rows |= (unsigned __int128)1 << (S * hi + lo);
                     a = perm[a];
                     b = perm[b];
                 }

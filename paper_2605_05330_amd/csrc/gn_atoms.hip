@@ -1,4 +1,4 @@
-// Census of GN atoms on connected graphs of up to 8 vertices (Appendix A,
+// Census of GN atoms on connected graphs of up to 9 vertices (Appendix A,
 // Table atoms_10).
 //
 // A fixed point of GN with full support on a connected graph is an atom; with
@@ -15,7 +15,8 @@
 // and conjugate permutations fix isomorphic families, so the sum runs over
 // cycle types with weights n!/z (z = prod_k k^{m_k} m_k!).  The graphs fixed
 // by p are the unions of the orbits of p on vertex pairs.  One GPU thread
-// evaluates one such graph: 2^28 labelled graphs for the identity at n = 8.
+// evaluates one such graph: 2^28 labelled graphs for the identity at n = 8,
+// 2^36 at n = 9.
 //
 // Deciding atomicity exactly: fraction-free (Bareiss) elimination of [B | 1].
 // Every entry it produces is a minor of that 0/1 matrix (Sylvester's identity),
@@ -40,11 +41,24 @@ namespace {
 constexpr int kAtomBlock = 256;
 
 constexpr uint64_t kAtomChunk = 1ull << 24;  // graphs per first-pass launch (queue capacity)
+static_assert(kAtomChunk <= (1ull << 24), "queue entries hold a graph's index within its chunk in 24 bits");
 
-__device__ __forceinline__ uint64_t atom_rows(const uint64_t* s_tab, int nbytes, uint64_t g) {
-    uint64_t rows = 0;
+// Bytes of a graph index (one bit per orbit on vertex pairs): at most
+// n(n - 1)/2 orbits, 36 at n = 9.
+constexpr int kAtomTabBytes = (kAtomMaxN * (kAtomMaxN - 1) / 2 + 7) / 8;
+
+template <int N>
+__device__ __forceinline__ AtomRowsT<N> atom_rows(const AtomRowsT<N>* s_tab, int nbytes, uint64_t g) {
+    AtomRowsT<N> rows = 0;
     for (int b = 0; b < nbytes; ++b) rows |= s_tab[b * 256 + ((g >> (8 * b)) & 255u)];
     return rows;
+}
+
+template <int N>
+__device__ __forceinline__ void atom_load_tab(const unsigned __int128* __restrict__ tab, int nbytes,
+                                              AtomRowsT<N>* s_tab) {
+    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = (AtomRowsT<N>)tab[k];
+    __syncthreads();
 }
 
 template <int BT>
@@ -67,26 +81,25 @@ __device__ __forceinline__ void atom_flush(unsigned (&cnt)[kAtomCounters], unsig
 
 // First pass, one thread per labelled graph g in [base, base + count): its
 // edges are the orbits whose bits are set in g; `tab` holds, for each byte of
-// g, the adjacency rows (byte i = neighbours of vertex i) of every combination
-// of that byte's orbits.  Counts connected graphs and discrete atoms; a
-// connected graph whose B is singular with 1 in its span goes to the queue as
-// (g - base) | rank << 28 | regular << 31, appended a wavefront at a time, so
+// g, the packed adjacency rows of every combination of that byte's orbits.
+// Counts connected graphs and discrete atoms; a connected graph whose B is
+// singular with 1 in its span goes to the queue as
+// (g - base) | rank << 24 | regular << 28, appended a wavefront at a time, so
 // that the subset search of the second pass runs with every lane busy instead
 // of stalling the wavefronts of the first.
 template <int N>
-__global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t* __restrict__ tab, int nbytes,
+__global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
                                                                  uint64_t base, uint64_t count,
                                                                  unsigned long long* __restrict__ acc,
                                                                  uint32_t* __restrict__ queue,
                                                                  unsigned* __restrict__ qcount) {
-    __shared__ uint64_t s_tab[4 * 256];
-    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = tab[k];
-    __syncthreads();
+    __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
+    atom_load_tab<N>(tab, nbytes, s_tab);
     const int lane = threadIdx.x & 63;
     unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
     for (uint64_t k = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; k < count; k += stride) {
-        const uint64_t rows = atom_rows(s_tab, nbytes, base + k);
+        const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + k);
         int f = -1;
         bool regular = false;
         if (atom_connected<N>(rows)) {
@@ -104,7 +117,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t*
             at = __shfl(at, leader, 64);
             if (want)
                 queue[at + __popcll(mask & ((1ull << lane) - 1ull))] =
-                    (uint32_t)k | (uint32_t)f << 28 | (regular ? 1u << 31 : 0u);
+                    (uint32_t)k | (uint32_t)f << 24 | (regular ? 1u << 28 : 0u);
         }
     }
     atom_flush<kAtomBlock>(cnt, acc);
@@ -112,25 +125,24 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const uint64_t*
 
 // Second pass over the queue of the first: continuous atoms.
 template <int N>
-__global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const uint64_t* __restrict__ tab, int nbytes,
+__global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
                                                                    uint64_t base, const uint32_t* __restrict__ queue,
                                                                    const unsigned* __restrict__ qcount,
                                                                    unsigned long long* __restrict__ acc) {
-    __shared__ uint64_t s_tab[4 * 256];
-    for (int k = threadIdx.x; k < nbytes * 256; k += kAtomBlock) s_tab[k] = tab[k];
-    __syncthreads();
+    __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
+    atom_load_tab<N>(tab, nbytes, s_tab);
     unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const unsigned total = *qcount;
     for (unsigned i = blockIdx.x * kAtomBlock + threadIdx.x; i < total; i += gridDim.x * kAtomBlock) {
         const uint32_t e = queue[i];
-        const uint64_t rows = atom_rows(s_tab, nbytes, base + (e & 0x0fffffffu));
-        atom_count(atom_singular_class<N>(rows, (int)((e >> 28) & 7u)), (e >> 31) != 0u, cnt);
+        const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu));
+        atom_count(atom_singular_class<N>(rows, (int)((e >> 24) & 15u)), ((e >> 28) & 1u) != 0u, cnt);
     }
     atom_flush<kAtomBlock>(cnt, acc);
 }
 
 template <int N>
-gn_status launch_census(const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc, uint32_t* queue,
+gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc, uint32_t* queue,
                         unsigned* qcount, hipStream_t s) {
     for (uint64_t base = 0; base < count; base += kAtomChunk) {
         const uint64_t c = std::min(kAtomChunk, count - base);
@@ -147,7 +159,7 @@ gn_status launch_census(const uint64_t* tab, int nbytes, uint64_t count, unsigne
     return GN_OK;
 }
 
-gn_status launch_census_n(int n, const uint64_t* tab, int nbytes, uint64_t count, unsigned long long* acc,
+gn_status launch_census_n(int n, const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc,
                           uint32_t* queue, unsigned* qcount, hipStream_t s) {
     switch (n) {
         case 1: return launch_census<1>(tab, nbytes, count, acc, queue, qcount, s);
@@ -157,7 +169,8 @@ gn_status launch_census_n(int n, const uint64_t* tab, int nbytes, uint64_t count
         case 5: return launch_census<5>(tab, nbytes, count, acc, queue, qcount, s);
         case 6: return launch_census<6>(tab, nbytes, count, acc, queue, qcount, s);
         case 7: return launch_census<7>(tab, nbytes, count, acc, queue, qcount, s);
-        default: return launch_census<8>(tab, nbytes, count, acc, queue, qcount, s);
+        case 8: return launch_census<8>(tab, nbytes, count, acc, queue, qcount, s);
+        default: return launch_census<9>(tab, nbytes, count, acc, queue, qcount, s);
     }
 }
 
@@ -170,7 +183,7 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     const std::vector<AtomCycleType> types = atom_cycle_types(n, nfact);
     const size_t T = types.size();
     unsigned long long* acc = nullptr;  // per cycle type: kAtomCounters counters
-    uint64_t* tab = nullptr;            // per cycle type: 4 x 256 adjacency-row words
+    unsigned __int128* tab = nullptr;   // per cycle type: kAtomTabBytes x 256 packed adjacency rows
     uint32_t* queue = nullptr;          // singular graphs of one chunk
     unsigned* qcount = nullptr;
     auto release = [&]() {
@@ -182,7 +195,7 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     uint64_t most = 0;
     for (const AtomCycleType& t : types) most = std::max<uint64_t>(most, 1ull << t.orbit_rows.size());
     if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * T) != hipSuccess ||
-        hipMalloc((void**)&tab, sizeof(uint64_t) * 4 * 256 * T) != hipSuccess ||
+        hipMalloc((void**)&tab, sizeof(unsigned __int128) * kAtomTabBytes * 256 * T) != hipSuccess ||
         hipMalloc((void**)&queue, sizeof(uint32_t) * std::min(most, kAtomChunk)) != hipSuccess ||
         hipMalloc((void**)&qcount, sizeof(unsigned)) != hipSuccess) {
         (void)hipGetLastError();
@@ -192,7 +205,7 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     gn_status st = GN_OK;
     // per cycle type and byte b of the graph index: the adjacency rows of every
     // combination of orbits 8b .. 8b + 7
-    std::vector<uint64_t> htab(4 * 256 * T, 0);
+    std::vector<unsigned __int128> htab(kAtomTabBytes * 256 * T, 0);
     std::vector<int> nbytes(T);
     std::vector<uint64_t> counts(T);
     for (size_t t = 0; t < T; ++t) {
@@ -201,18 +214,18 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
         nbytes[t] = m > 8 ? (m + 7) / 8 : 1;
         for (int b = 0; b < nbytes[t]; ++b)
             for (int c = 0; c < 256; ++c) {
-                uint64_t rows = 0;
+                unsigned __int128 rows = 0;
                 for (int q = 0; q < 8; ++q)
                     if (((c >> q) & 1) && 8 * b + q < m) rows |= types[t].orbit_rows[8 * b + q];
-                htab[(t * 4 + b) * 256 + c] = rows;
+                htab[(t * kAtomTabBytes + b) * 256 + c] = rows;
             }
     }
-    if (hipMemcpyAsync(tab, htab.data(), sizeof(uint64_t) * htab.size(), hipMemcpyHostToDevice, stream) !=
+    if (hipMemcpyAsync(tab, htab.data(), sizeof(unsigned __int128) * htab.size(), hipMemcpyHostToDevice, stream) !=
             hipSuccess ||
         hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * T, stream) != hipSuccess)
         st = GN_E_HIP;
     for (size_t t = 0; t < T && st == GN_OK; ++t)
-        st = launch_census_n(n, tab + t * 4 * 256, nbytes[t], counts[t], acc + t * kAtomCounters, queue, qcount,
+        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], acc + t * kAtomCounters, queue, qcount,
                              stream);
     std::vector<unsigned long long> h(kAtomCounters * T, 0);
     if (st == GN_OK &&

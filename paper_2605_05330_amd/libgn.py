@@ -296,7 +296,7 @@ def gn_set_chunk_len(length: int):
 
 
 def gn_atom_census(n: int, stream=None) -> gn_atom_counts:
-    """Connected graphs on n vertices (1..8) up to isomorphism and their GN-atomic
+    """Connected graphs on n vertices (1..9) up to isomorphism and their GN-atomic
     classes (Appendix A, Table atoms_10), counted on the device."""
     out = gn_atom_counts()
     _check(lib().gn_atom_census(int(n), ctypes.byref(out), _stream(stream)), "gn_atom_census")

@@ -1,12 +1,36 @@
 // Host run of the atom census's shared code (gn_atoms.h): the per-graph
 // classification and the cycle-type enumeration, summed by Burnside's lemma on
 // the CPU.  Prints "n connected irregular_discrete irregular_continuous
-// regular_discrete regular_continuous" for n = 1 .. argv[1].  Built and run by
+// regular_discrete regular_continuous" for n = 1 .. argv[1].
+// "classify N" instead reads edge masks of N-vertex graphs from stdin (bit k =
+// the k-th vertex pair i < j in lexicographic order) and prints, per graph,
+// "connected regular class" with class -1 (not atomic), 0 (discrete) or 1
+// (continuous), or -2 for a graph that is not connected.  Built and run by
 // test_atoms_cpu.py; no GPU involved.
 #include "gn_atoms.h"
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+
+template <int N>
+static int classify() {
+    constexpr int S = AtomRows<N>::S;
+    unsigned long long mask;
+    while (std::scanf("%llu", &mask) == 1) {
+        AtomRowsT<N> rows = 0;
+        int k = 0;
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 1; j < N; ++j, ++k)
+                if ((mask >> k) & 1ull) {
+                    rows |= (AtomRowsT<N>)1 << (S * i + j);
+                    rows |= (AtomRowsT<N>)1 << (S * j + i);
+                }
+        const bool conn = atom_connected<N>(rows);
+        std::printf("%d %d %d\n", conn ? 1 : 0, atom_regular<N>(rows) ? 1 : 0, conn ? atom_class<N>(rows) : -2);
+    }
+    return 0;
+}
 
 template <int N>
 static int run() {
@@ -17,9 +41,9 @@ static int run() {
         const int m = (int)t.orbit_rows.size();
         unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
         for (uint64_t g = 0; g < (1ull << m); ++g) {
-            uint64_t rows = 0;
+            AtomRowsT<N> rows = 0;
             for (int o = 0; o < m; ++o)
-                if ((g >> o) & 1u) rows |= t.orbit_rows[o];
+                if ((g >> o) & 1u) rows |= (AtomRowsT<N>)t.orbit_rows[o];
             atom_evaluate<N>(rows, cnt);
         }
         for (int k = 0; k < kAtomCounters; ++k) sum[k] += (long long)cnt[k] * t.weight;
@@ -35,6 +59,12 @@ static int run() {
 }
 
 int main(int argc, char** argv) {
+    if (argc > 2 && std::strcmp(argv[1], "classify") == 0) {
+        const int n = std::atoi(argv[2]);
+        if (n == 8) return classify<8>();
+        if (n == 9) return classify<9>();
+        return 2;
+    }
     const int nmax = argc > 1 ? std::atoi(argv[1]) : 6;
     int rc = 0;
     if (nmax >= 1) rc |= run<1>();

@@ -52,8 +52,20 @@ def test_census_n8(gpu):
     assert c.labelled_evaluated >= 1 << 28
 
 
+def test_census_n9(gpu):
+    """n = 9: 2^36 labelled graphs for the identity alone (68.7e9 of 9!'s
+    Burnside terms), rows packed at a 9-bit stride.  The printed row adds up
+    (1,202 + 1,091 + 12 + 10 = 2,315) and is reproduced in full."""
+    from paper_2605_05330_amd import libgn
+    c = libgn.gn_atom_census(9)
+    conn, idisc, icont, rdisc, rcont, total = _table()[9]
+    assert _counts(c) == [conn, idisc, icont, rdisc, rcont]
+    assert c.atomic == total == 2315
+    assert c.labelled_evaluated >= 1 << 36
+
+
 def test_census_rejects_bad_n(gpu):
     from paper_2605_05330_amd import libgn
-    for n in (0, 9, -1):
+    for n in (0, 10, -1):
         with pytest.raises(libgn.GNError):
             libgn.gn_atom_census(n)
