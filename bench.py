@@ -346,8 +346,8 @@ def bench_er1000(reps, with_oracle=True):
 
 
 def bench_atoms(reps=3):
-    """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..8 on the
-    device; n = 8 timed.  Compared with the table's rows (tests/golden)."""
+    """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..9 on the
+    device; n = 8 and n = 9 timed.  Compared with the table's rows (tests/golden)."""
     from paper_2605_05330_amd import libgn
     rows = {}
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "atoms_table.txt")) as f:
@@ -364,13 +364,23 @@ def bench_atoms(reps=3):
     for _ in range(reps):
         c = libgn.gn_atom_census(8)
     dt = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    c9 = libgn.gn_atom_census(9)
+    dt9 = time.perf_counter() - t0
+    got9 = [c9.connected, c9.irregular_discrete, c9.irregular_continuous, c9.regular_discrete, c9.regular_continuous]
     return {"n": 8, "connected": c.connected, "irregular_discrete": c.irregular_discrete,
             "irregular_continuous": c.irregular_continuous, "regular_discrete": c.regular_discrete,
             "regular_continuous": c.regular_continuous, "atomic": c.atomic,
             "labelled_graphs": c.labelled_evaluated, "ms": dt * 1e3,
             "labelled_graphs_per_s": c.labelled_evaluated / dt,
             "classes_match_table_n1_to_8": all(match),
-            "note": "Burnside sum over cycle types; the table's n = 8 classes add up to 247, its printed total is 230"}
+            "note": "Burnside sum over cycle types; the table's n = 8 classes add up to 247, its printed total is 230",
+            "n9": {"connected": c9.connected, "irregular_discrete": c9.irregular_discrete,
+                   "irregular_continuous": c9.irregular_continuous, "regular_discrete": c9.regular_discrete,
+                   "regular_continuous": c9.regular_continuous, "atomic": c9.atomic,
+                   "labelled_graphs": c9.labelled_evaluated, "s": dt9,
+                   "labelled_graphs_per_s": c9.labelled_evaluated / dt9,
+                   "row_matches_table": got9 == rows[9][:5] and c9.atomic == rows[9][5]}}
 
 
 def bench_lp(with_oracle=True):

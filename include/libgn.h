@@ -463,9 +463,10 @@ typedef struct {
  * classes, up to isomorphism.  By Burnside's lemma over the cycle types of the
  * vertex permutations, each labelled graph fixed by a representative
  * permutation is classified on the device (one thread each: 2^28 graphs at
- * n = 8, 2^36 at n = 9, which takes about a minute), exactly (fraction-free
- * elimination of [B | 1], whose entries stay below 2^24); the weighted sums
- * are divided by n! on the host.  Allocates and
+ * n = 8, 2^36 at n = 9, which takes about 11 s), exactly (fraction-free
+ * elimination of [B | 1], whose entries stay below 2^24, after an exact filter:
+ * a graph in which one closed neighbourhood strictly contains another has no
+ * atom); the weighted sums are divided by n! on the host.  Allocates and
  * frees its own device buffers.  Errors: GN_E_ARG (n out of range, out NULL),
  * GN_E_NOMEM, GN_E_HIP, GN_E_NUMERIC (a weighted sum not divisible by n!: an
  * internal inconsistency, never expected).  SYNC. */

@@ -135,12 +135,31 @@ __host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const un
     neg = ng;
 }
 
+// Whether some closed neighbourhood strictly contains another.  Such a graph
+// has no atom: with N[i] a proper subset of N[j] and x > 0, (B x)_j exceeds
+// (B x)_i by the mass of N[j] \ N[i], so the two cannot both equal 1.  (Equal
+// closed neighbourhoods, twins, are allowed.)
+template <int N>
+__host__ __device__ inline bool atom_nested(const AtomRowsT<N> rows) {
+    unsigned c[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) c[i] = atom_row<N>(rows, i) | 1u << i;
+    bool nested = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (j != i) nested = nested || ((c[i] & ~c[j]) == 0u && c[i] != c[j]);
+    return nested;
+}
+
 // First part of the class of a connected graph, from the elimination of
 // [B | 1]: -1 not atomic, 0 atomic and discrete, or the rank of B (>= 1) when B
 // is singular and 1 lies in its span, which atom_singular_class decides.
 template <int N>
 __host__ __device__ inline int atom_class_first(const AtomRowsT<N> rows) {
     constexpr unsigned full = (1u << N) - 1u;
+    if (atom_nested<N>(rows)) return -1;
     int r;
     bool cons;
     unsigned pos, neg;

@@ -79,14 +79,27 @@ __device__ __forceinline__ void atom_flush(unsigned (&cnt)[kAtomCounters], unsig
     }
 }
 
+// Appends the lanes of a wavefront that `want` to a queue: one atomic per
+// wavefront, entries in lane order.
+__device__ __forceinline__ void atom_push(bool want, uint32_t entry, uint32_t* __restrict__ queue,
+                                          unsigned* __restrict__ qcount) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t mask = __ballot(want);
+    if (!mask) return;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned at = 0u;
+    if (lane == leader) at = atomicAdd(qcount, (unsigned)__popcll(mask));
+    at = __shfl(at, leader, 64);
+    if (want) queue[at + __popcll(mask & ((1ull << lane) - 1ull))] = entry;
+}
+
 // First pass, one thread per labelled graph g in [base, base + count): its
 // edges are the orbits whose bits are set in g; `tab` holds, for each byte of
 // g, the packed adjacency rows of every combination of that byte's orbits.
-// Counts connected graphs and discrete atoms; a connected graph whose B is
-// singular with 1 in its span goes to the queue as
-// (g - base) | rank << 24 | regular << 28, appended a wavefront at a time, so
-// that the subset search of the second pass runs with every lane busy instead
-// of stalling the wavefronts of the first.
+// Counts the connected graphs and queues those whose closed neighbourhoods
+// are not nested (the others have no atom, atom_nested), as
+// (g - base) | regular << 28: most graphs stop here, and the eliminations of
+// the next pass run with every lane busy.
 template <int N>
 __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
                                                                  uint64_t base, uint64_t count,
@@ -95,35 +108,54 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned 
                                                                  unsigned* __restrict__ qcount) {
     __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
     atom_load_tab<N>(tab, nbytes, s_tab);
-    const int lane = threadIdx.x & 63;
     unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
     for (uint64_t k = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; k < count; k += stride) {
         const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + k);
-        int f = -1;
-        bool regular = false;
+        bool want = false;
         if (atom_connected<N>(rows)) {
             cnt[0] += 1u;
-            regular = atom_regular<N>(rows);
-            f = atom_class_first<N>(rows);
-            if (f == 0) atom_count(0, regular, cnt);
+            want = !atom_nested<N>(rows);
         }
-        const bool want = f > 0;
-        const uint64_t mask = __ballot(want);
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            unsigned at = 0u;
-            if (lane == leader) at = atomicAdd(qcount, (unsigned)__popcll(mask));
-            at = __shfl(at, leader, 64);
-            if (want)
-                queue[at + __popcll(mask & ((1ull << lane) - 1ull))] =
-                    (uint32_t)k | (uint32_t)f << 24 | (regular ? 1u << 28 : 0u);
-        }
+        atom_push(want, (uint32_t)k | (atom_regular<N>(rows) ? 1u << 28 : 0u), queue, qcount);
     }
     atom_flush<kAtomBlock>(cnt, acc);
 }
 
-// Second pass over the queue of the first: continuous atoms.
+// Second pass over the first's queue: one elimination of [B | 1] per graph.
+// Counts the discrete atoms; a graph whose B is singular with 1 in its span
+// goes to the next queue as (g - base) | rank << 24 | regular << 28.
+template <int N>
+__global__ __launch_bounds__(kAtomBlock) void atom_first_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
+                                                                uint64_t base, const uint32_t* __restrict__ qin,
+                                                                const unsigned* __restrict__ qin_count,
+                                                                unsigned long long* __restrict__ acc,
+                                                                uint32_t* __restrict__ queue,
+                                                                unsigned* __restrict__ qcount) {
+    __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
+    atom_load_tab<N>(tab, nbytes, s_tab);
+    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    const unsigned total = *qin_count;
+    const unsigned stride = gridDim.x * kAtomBlock;
+    // the bound rounded up to whole wavefronts: every lane reaches the ballot of atom_push
+    const unsigned bound = (total + 63u) & ~63u;
+    for (unsigned i = blockIdx.x * kAtomBlock + threadIdx.x; i < bound; i += stride) {
+        bool want = false;
+        uint32_t entry = 0u;
+        if (i < total) {
+            const uint32_t e = qin[i];
+            const bool regular = ((e >> 28) & 1u) != 0u;
+            const int f = atom_class_first<N>(atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu)));
+            if (f == 0) atom_count(0, regular, cnt);
+            want = f > 0;
+            entry = (e & 0x00ffffffu) | (uint32_t)f << 24 | (regular ? 1u << 28 : 0u);
+        }
+        atom_push(want, entry, queue, qcount);
+    }
+    atom_flush<kAtomBlock>(cnt, acc);
+}
+
+// Third pass over the second's queue: continuous atoms.
 template <int N>
 __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
                                                                    uint64_t base, const uint32_t* __restrict__ queue,
@@ -141,36 +173,44 @@ __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigne
     atom_flush<kAtomBlock>(cnt, acc);
 }
 
+// The three passes over the graphs of one cycle type, a chunk of 2^24 at a
+// time.  queue: two arrays of qcap >= min(count, kAtomChunk) entries; qcount:
+// their two counters.
 template <int N>
-gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc, uint32_t* queue,
-                        unsigned* qcount, hipStream_t s) {
+gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc,
+                        uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
+    uint32_t* q1 = queue;
+    uint32_t* q2 = queue + qcap;
     for (uint64_t base = 0; base < count; base += kAtomChunk) {
         const uint64_t c = std::min(kAtomChunk, count - base);
-        GN_HIP_TRY(hipMemsetAsync(qcount, 0, sizeof(unsigned), s));
+        GN_HIP_TRY(hipMemsetAsync(qcount, 0, 2 * sizeof(unsigned), s));
         const uint64_t blocks = std::min<uint64_t>((c + kAtomBlock - 1) / kAtomBlock, 256 * 64);
+        const unsigned later = (unsigned)std::min<uint64_t>(blocks, 256 * 16);
         hipLaunchKernelGGL(atom_census_kernel<N>, dim3((unsigned)blocks), dim3(kAtomBlock), 0, s, tab, nbytes, base,
-                           c, acc, queue, qcount);
+                           c, acc, q1, qcount);
         GN_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(atom_singular_kernel<N>, dim3((unsigned)std::min<uint64_t>(blocks, 256 * 16)),
-                           dim3(kAtomBlock), 0, s, tab, nbytes, base, (const uint32_t*)queue,
-                           (const unsigned*)qcount, acc);
+        hipLaunchKernelGGL(atom_first_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base,
+                           (const uint32_t*)q1, (const unsigned*)qcount, acc, q2, qcount + 1);
+        GN_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(atom_singular_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base,
+                           (const uint32_t*)q2, (const unsigned*)(qcount + 1), acc);
         GN_HIP_TRY(hipGetLastError());
     }
     return GN_OK;
 }
 
 gn_status launch_census_n(int n, const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc,
-                          uint32_t* queue, unsigned* qcount, hipStream_t s) {
+                          uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
     switch (n) {
-        case 1: return launch_census<1>(tab, nbytes, count, acc, queue, qcount, s);
-        case 2: return launch_census<2>(tab, nbytes, count, acc, queue, qcount, s);
-        case 3: return launch_census<3>(tab, nbytes, count, acc, queue, qcount, s);
-        case 4: return launch_census<4>(tab, nbytes, count, acc, queue, qcount, s);
-        case 5: return launch_census<5>(tab, nbytes, count, acc, queue, qcount, s);
-        case 6: return launch_census<6>(tab, nbytes, count, acc, queue, qcount, s);
-        case 7: return launch_census<7>(tab, nbytes, count, acc, queue, qcount, s);
-        case 8: return launch_census<8>(tab, nbytes, count, acc, queue, qcount, s);
-        default: return launch_census<9>(tab, nbytes, count, acc, queue, qcount, s);
+        case 1: return launch_census<1>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 2: return launch_census<2>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 3: return launch_census<3>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 4: return launch_census<4>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 5: return launch_census<5>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 6: return launch_census<6>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 7: return launch_census<7>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 8: return launch_census<8>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        default: return launch_census<9>(tab, nbytes, count, acc, queue, qcap, qcount, s);
     }
 }
 
@@ -184,8 +224,8 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     const size_t T = types.size();
     unsigned long long* acc = nullptr;  // per cycle type: kAtomCounters counters
     unsigned __int128* tab = nullptr;   // per cycle type: kAtomTabBytes x 256 packed adjacency rows
-    uint32_t* queue = nullptr;          // singular graphs of one chunk
-    unsigned* qcount = nullptr;
+    uint32_t* queue = nullptr;          // two queues of one chunk: graphs to eliminate, singular graphs
+    unsigned* qcount = nullptr;         // their counters
     auto release = [&]() {
         if (acc) (void)hipFree(acc);
         if (tab) (void)hipFree(tab);
@@ -194,10 +234,11 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     };
     uint64_t most = 0;
     for (const AtomCycleType& t : types) most = std::max<uint64_t>(most, 1ull << t.orbit_rows.size());
+    const uint64_t qcap = std::min(most, kAtomChunk);
     if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * T) != hipSuccess ||
         hipMalloc((void**)&tab, sizeof(unsigned __int128) * kAtomTabBytes * 256 * T) != hipSuccess ||
-        hipMalloc((void**)&queue, sizeof(uint32_t) * std::min(most, kAtomChunk)) != hipSuccess ||
-        hipMalloc((void**)&qcount, sizeof(unsigned)) != hipSuccess) {
+        hipMalloc((void**)&queue, sizeof(uint32_t) * 2 * qcap) != hipSuccess ||
+        hipMalloc((void**)&qcount, 2 * sizeof(unsigned)) != hipSuccess) {
         (void)hipGetLastError();
         release();
         return GN_E_NOMEM;
@@ -225,7 +266,7 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
         hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * T, stream) != hipSuccess)
         st = GN_E_HIP;
     for (size_t t = 0; t < T && st == GN_OK; ++t)
-        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], acc + t * kAtomCounters, queue, qcount,
+        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], acc + t * kAtomCounters, queue, qcap, qcount,
                              stream);
     std::vector<unsigned long long> h(kAtomCounters * T, 0);
     if (st == GN_OK &&
