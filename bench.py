@@ -39,6 +39,7 @@ def _args():
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-multi", action="store_true")
     p.add_argument("--no-atoms", action="store_true")
+    p.add_argument("--atoms10", action="store_true", help="also the n = 10 atom census (about two minutes)")
     p.add_argument("--no-lp", action="store_true")
     p.add_argument("--no-hyper", action="store_true")
     return p.parse_args()
@@ -345,9 +346,10 @@ def bench_er1000(reps, with_oracle=True):
     return out
 
 
-def bench_atoms(reps=3):
+def bench_atoms(reps=3, with_n10=False):
     """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..9 on the
-    device; n = 8 and n = 9 timed.  Compared with the table's rows (tests/golden)."""
+    device (and n = 10 on request); n = 8 and up timed.  Compared with the
+    table's rows (tests/golden)."""
     from paper_2605_05330_amd import libgn
     rows = {}
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "atoms_table.txt")) as f:
@@ -364,10 +366,19 @@ def bench_atoms(reps=3):
     for _ in range(reps):
         c = libgn.gn_atom_census(8)
     dt = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    c9 = libgn.gn_atom_census(9)
-    dt9 = time.perf_counter() - t0
-    got9 = [c9.connected, c9.irregular_discrete, c9.irregular_continuous, c9.regular_discrete, c9.regular_continuous]
+    def big(n):
+        t0 = time.perf_counter()
+        c = libgn.gn_atom_census(n)
+        dt = time.perf_counter() - t0
+        got = [c.connected, c.irregular_discrete, c.irregular_continuous, c.regular_discrete, c.regular_continuous]
+        return {"connected": c.connected, "irregular_discrete": c.irregular_discrete,
+                "irregular_continuous": c.irregular_continuous, "regular_discrete": c.regular_discrete,
+                "regular_continuous": c.regular_continuous, "atomic": c.atomic,
+                "labelled_graphs": c.labelled_evaluated, "s": dt, "labelled_graphs_per_s": c.labelled_evaluated / dt,
+                "row_matches_table": got == rows[n][:5] and c.atomic == rows[n][5]}
+    extra = {"n9": big(9)}
+    if with_n10:
+        extra["n10"] = big(10)
     return {"n": 8, "connected": c.connected, "irregular_discrete": c.irregular_discrete,
             "irregular_continuous": c.irregular_continuous, "regular_discrete": c.regular_discrete,
             "regular_continuous": c.regular_continuous, "atomic": c.atomic,
@@ -375,12 +386,7 @@ def bench_atoms(reps=3):
             "labelled_graphs_per_s": c.labelled_evaluated / dt,
             "classes_match_table_n1_to_8": all(match),
             "note": "Burnside sum over cycle types; the table's n = 8 classes add up to 247, its printed total is 230",
-            "n9": {"connected": c9.connected, "irregular_discrete": c9.irregular_discrete,
-                   "irregular_continuous": c9.irregular_continuous, "regular_discrete": c9.regular_discrete,
-                   "regular_continuous": c9.regular_continuous, "atomic": c9.atomic,
-                   "labelled_graphs": c9.labelled_evaluated, "s": dt9,
-                   "labelled_graphs_per_s": c9.labelled_evaluated / dt9,
-                   "row_matches_table": got9 == rows[9][:5] and c9.atomic == rows[9][5]}}
+            **extra}
 
 
 def bench_lp(with_oracle=True):
@@ -807,7 +813,7 @@ def main():
     if not a.no_warm:
         out["learned_warm_start"] = bench_warm(not a.no_cpu_baseline)
     if not a.no_atoms:
-        out["atom_census8"] = bench_atoms()
+        out["atom_census8"] = bench_atoms(with_n10=args.atoms10)
     if not a.no_lp:
         out["lp_warm_start"] = bench_lp(not a.no_cpu_baseline)
     if not a.no_hyper:

@@ -459,14 +459,17 @@ typedef struct {
     int64_t labelled_evaluated;    /* labelled graphs the kernel classified             */
 } gn_atom_counts;
 
-/* Count the connected graphs on n vertices (1 <= n <= 9) and their atomic
+/* Count the connected graphs on n vertices (1 <= n <= 10) and their atomic
  * classes, up to isomorphism.  By Burnside's lemma over the cycle types of the
  * vertex permutations, each labelled graph fixed by a representative
- * permutation is classified on the device (one thread each: 2^28 graphs at
- * n = 8, 2^36 at n = 9, which takes about 11 s), exactly (fraction-free
- * elimination of [B | 1], whose entries stay below 2^24, after an exact filter:
- * a graph in which one closed neighbourhood strictly contains another has no
- * atom); the weighted sums are divided by n! on the host.  Allocates and
+ * permutation is classified on the device, one thread each, exactly
+ * (fraction-free elimination of [B | 1], whose entries stay below 2^24, after
+ * an exact filter: a graph in which one closed neighbourhood strictly contains
+ * another has no atom).  The identity's term is summed in a marked-vertex form
+ * (a vertex of maximum degree d relabelled 0 with neighbours 1..d, each graph
+ * weighted by n C(n-1, d) / (number of degree-d vertices)): 2^39 graphs at
+ * n = 10 instead of 2^45.  n = 9 takes under a second, n = 10 about two
+ * minutes.  The sums are divided by n! on the host.  Allocates and
  * frees its own device buffers.  Errors: GN_E_ARG (n out of range, out NULL),
  * GN_E_NOMEM, GN_E_HIP, GN_E_NUMERIC (a weighted sum not divisible by n!: an
  * internal inconsistency, never expected).  SYNC. */

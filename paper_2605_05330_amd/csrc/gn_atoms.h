@@ -7,22 +7,19 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
-constexpr int kAtomMaxN = 9;
+constexpr int kAtomMaxN = 10;
 
 // A labelled graph as its adjacency rows packed at a fixed stride: row i (the
 // neighbours of vertex i) in bits [S i, S i + S).  Up to 8 vertices the rows
-// fit 8-bit fields of a 64-bit word; 9 vertices need 9-bit fields, 81 bits.
+// fit 8-bit fields of a 64-bit word; 9 and 10 vertices take N-bit fields of a
+// 128-bit word (81 and 100 bits).
 template <int N>
 struct AtomRows {
-    using type = uint64_t;
-    static constexpr int S = 8;
-};
-template <>
-struct AtomRows<9> {
-    using type = unsigned __int128;
-    static constexpr int S = 9;
+    using type = std::conditional_t<(N <= 8), uint64_t, unsigned __int128>;
+    static constexpr int S = N <= 8 ? 8 : N;
 };
 template <int N>
 using AtomRowsT = typename AtomRows<N>::type;
@@ -35,7 +32,7 @@ __host__ __device__ __forceinline__ unsigned atom_row(const AtomRowsT<N> rows, c
 }
 
 // The packing stride for n vertices, for host code that takes n at run time.
-inline int atom_stride(int n) { return n <= 8 ? 8 : 9; }
+inline int atom_stride(int n) { return n <= 8 ? 8 : n; }
 
 // Per-graph counters: connected graphs, then atomic irregular discrete,
 // irregular continuous, regular discrete, regular continuous.
@@ -157,7 +154,7 @@ __host__ __device__ inline bool atom_nested(const AtomRowsT<N> rows) {
 // [B | 1]: -1 not atomic, 0 atomic and discrete, or the rank of B (>= 1) when B
 // is singular and 1 lies in its span, which atom_singular_class decides.
 template <int N>
-__host__ __device__ inline int atom_class_first(const AtomRowsT<N> rows) {
+__host__ __device__ __forceinline__ int atom_class_first(const AtomRowsT<N> rows) {
     constexpr unsigned full = (1u << N) - 1u;
     if (atom_nested<N>(rows)) return -1;
     int r;
@@ -169,13 +166,13 @@ __host__ __device__ inline int atom_class_first(const AtomRowsT<N> rows) {
     return r;
 }
 
-// Singular B of rank r with 1 in its span: atomic (continuous, returns 1) iff
-// the non-negative basic solutions of B x = 1 cover every vertex, else -1.
-// The subsets of size r are walked in increasing order by the next-combination
-// step (Gosper), so lanes of a wavefront with different ranks each eliminate
-// their own subset in the same trip; a lane stops once its cover is complete.
+// Singular B of rank r with 1 in its span: whether the non-negative basic
+// solutions of B x = 1 cover every vertex (returns 1), else -1.  The subsets of
+// size r are walked in increasing order by the next-combination step (Gosper),
+// so lanes of a wavefront with different ranks each eliminate their own subset
+// in the same trip; a lane stops once its cover is complete.
 template <int N>
-__host__ __device__ inline int atom_singular_class(const AtomRowsT<N> rows, const int r) {
+__host__ __device__ __forceinline__ int atom_subset_search(const AtomRowsT<N> rows, const int r) {
     constexpr unsigned full = (1u << N) - 1u;
     unsigned cover = 0u;
     for (unsigned S = (1u << r) - 1u; S <= full;) {
@@ -190,6 +187,63 @@ __host__ __device__ inline int atom_singular_class(const AtomRowsT<N> rows, cons
         S = up | (((up ^ S) >> 2) >> __builtin_ctz(low));
     }
     return cover == full ? 1 : -1;
+}
+
+// Twins (vertices with equal closed neighbourhoods) give B equal rows and
+// equal columns, so B x = 1 depends on x only through the sums over twin
+// classes, and it has a positive solution iff the system of the quotient graph
+// does (one vertex per class, two classes adjacent when their vertices are;
+// split each class's positive sum among its members).
+// Returns the quotient's rows, its vertices numbered in the order of their
+// smallest members and padded with isolated vertices up to N (an isolated
+// vertex reads x = 1 and changes neither the existence of a positive solution
+// nor the search over the rest); a graph without twins is its own quotient.
+template <int N>
+__host__ __device__ __forceinline__ AtomRowsT<N> atom_twin_quotient(const AtomRowsT<N> rows) {
+    constexpr unsigned full = (1u << N) - 1u;
+    constexpr int S = AtomRows<N>::S;
+    unsigned c[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) c[i] = atom_row<N>(rows, i) | 1u << i;
+    unsigned reps = 0u;  // the smallest vertex of each class
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        bool first = true;
+#pragma unroll
+        for (int j = 0; j < i; ++j) first = first && c[j] != c[i];
+        reps |= first ? 1u << i : 0u;
+    }
+    if (reps == full) return rows;
+    AtomRowsT<N> out = 0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (!((reps >> a) & 1u)) continue;
+        const unsigned nb = c[a] & reps & ~(1u << a);  // representatives of the neighbouring classes
+        unsigned row = 0u;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+            row |= ((nb >> b) & 1u) << __builtin_popcount(reps & ((1u << b) - 1u));
+        out |= (AtomRowsT<N>)row << (S * __builtin_popcount(reps & ((1u << a) - 1u)));
+    }
+    return out;
+}
+
+// Singular B of rank r with 1 in its span: atomic (continuous, returns 1) iff
+// B x = 1 has a positive solution, else -1.  A graph with twins is decided on
+// its twin quotient (smaller nullity, so a shorter subset search, often none:
+// a quotient with an invertible B answers at once).
+template <int N>
+__host__ __device__ inline int atom_singular_class(const AtomRowsT<N> rows, const int r) {
+    const AtomRowsT<N> q = atom_twin_quotient<N>(rows);
+    AtomRowsT<N> sys = rows;
+    int rank = r;
+    if (q != rows) {
+        const int f = atom_class_first<N>(q);
+        if (f <= 0) return f < 0 ? -1 : 1;
+        sys = q;
+        rank = f;
+    }
+    return atom_subset_search<N>(sys, rank);
 }
 
 // Class of one connected graph: -1 not atomic, else 0 discrete / 1 continuous.
@@ -224,11 +278,40 @@ __host__ __device__ inline bool atom_regular(const AtomRowsT<N> rows) {
     return regular;
 }
 
-// Adds an atomic class (0 discrete / 1 continuous) to the counters.
-__host__ __device__ inline void atom_count(const int cls, const bool regular, unsigned (&cnt)[kAtomCounters]) {
+// Adds an atomic class (0 discrete / 1 continuous) to the counters, with
+// weight w.
+__host__ __device__ inline void atom_count(const int cls, const bool regular, unsigned (&cnt)[kAtomCounters],
+                                           const unsigned w = 1u) {
     const int idx = cls < 0 ? -1 : 1 + (regular ? 2 : 0) + cls;
 #pragma unroll
-    for (int k = 1; k < kAtomCounters; ++k) cnt[k] += idx == k ? 1u : 0u;  // fixed indices: no scratch array
+    for (int k = 1; k < kAtomCounters; ++k) cnt[k] += idx == k ? w : 0u;  // fixed indices: no scratch array
+}
+
+// Weights of the marked-vertex sum: lcm(1, ..., 10), so that L / k is an
+// integer for every count k of maximum-degree vertices.
+constexpr unsigned kAtomLcm = 2520;
+
+// Marked-vertex form of the identity's term of Burnside's sum (the number of
+// labelled graphs with an invariant property P).  Marking one vertex of
+// maximum degree and relabelling it to 0 with neighbours 1..d,
+//     #{labelled G with P} = n sum_d C(n-1, d) sum_G' P(G') / k(G'),
+// G' over the graphs with N(0) = {1, .., d} in which no vertex has degree
+// above d, k(G') the number of vertices of degree d.  For such a G' this
+// returns true and w = L / k; false when some vertex has a larger degree than
+// vertex 0 (the graph is not in the sum).
+template <int N>
+__host__ __device__ inline bool atom_marked_weight(const AtomRowsT<N> rows, unsigned& w) {
+    const int d0 = __builtin_popcount(atom_row<N>(rows, 0));
+    int k = 1;
+    bool in = true;
+#pragma unroll
+    for (int v = 1; v < N; ++v) {
+        const int dv = __builtin_popcount(atom_row<N>(rows, v));
+        in = in && dv <= d0;
+        k += dv == d0 ? 1 : 0;
+    }
+    w = kAtomLcm / (unsigned)k;
+    return in;
 }
 
 // Adds one labelled graph to the counters.

@@ -102,7 +102,7 @@ __device__ __forceinline__ void atom_push(bool want, uint32_t entry, uint32_t* _
 // the next pass run with every lane busy.
 template <int N>
 __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
-                                                                 uint64_t base, uint64_t count,
+                                                                 uint64_t base, uint64_t count, int marked,
                                                                  unsigned long long* __restrict__ acc,
                                                                  uint32_t* __restrict__ queue,
                                                                  unsigned* __restrict__ qcount) {
@@ -112,9 +112,11 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned 
     const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
     for (uint64_t k = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; k < count; k += stride) {
         const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + k);
+        unsigned w = 1u;
+        const bool in = !marked || atom_marked_weight<N>(rows, w);
         bool want = false;
-        if (atom_connected<N>(rows)) {
-            cnt[0] += 1u;
+        if (in && atom_connected<N>(rows)) {
+            cnt[0] += w;
             want = !atom_nested<N>(rows);
         }
         atom_push(want, (uint32_t)k | (atom_regular<N>(rows) ? 1u << 28 : 0u), queue, qcount);
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned 
 // goes to the next queue as (g - base) | rank << 24 | regular << 28.
 template <int N>
 __global__ __launch_bounds__(kAtomBlock) void atom_first_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
-                                                                uint64_t base, const uint32_t* __restrict__ qin,
+                                                                uint64_t base, int marked, const uint32_t* __restrict__ qin,
                                                                 const unsigned* __restrict__ qin_count,
                                                                 unsigned long long* __restrict__ acc,
                                                                 uint32_t* __restrict__ queue,
@@ -145,8 +147,11 @@ __global__ __launch_bounds__(kAtomBlock) void atom_first_kernel(const unsigned _
         if (i < total) {
             const uint32_t e = qin[i];
             const bool regular = ((e >> 28) & 1u) != 0u;
-            const int f = atom_class_first<N>(atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu)));
-            if (f == 0) atom_count(0, regular, cnt);
+            const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu));
+            unsigned w = 1u;
+            if (marked) (void)atom_marked_weight<N>(rows, w);
+            const int f = atom_class_first<N>(rows);
+            if (f == 0) atom_count(0, regular, cnt, w);
             want = f > 0;
             entry = (e & 0x00ffffffu) | (uint32_t)f << 24 | (regular ? 1u << 28 : 0u);
         }
@@ -158,7 +163,8 @@ __global__ __launch_bounds__(kAtomBlock) void atom_first_kernel(const unsigned _
 // Third pass over the second's queue: continuous atoms.
 template <int N>
 __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
-                                                                   uint64_t base, const uint32_t* __restrict__ queue,
+                                                                   uint64_t base, int marked,
+                                                                   const uint32_t* __restrict__ queue,
                                                                    const unsigned* __restrict__ qcount,
                                                                    unsigned long long* __restrict__ acc) {
     __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
@@ -168,7 +174,9 @@ __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigne
     for (unsigned i = blockIdx.x * kAtomBlock + threadIdx.x; i < total; i += gridDim.x * kAtomBlock) {
         const uint32_t e = queue[i];
         const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu));
-        atom_count(atom_singular_class<N>(rows, (int)((e >> 24) & 15u)), ((e >> 28) & 1u) != 0u, cnt);
+        unsigned w = 1u;
+        if (marked) (void)atom_marked_weight<N>(rows, w);
+        atom_count(atom_singular_class<N>(rows, (int)((e >> 24) & 15u)), ((e >> 28) & 1u) != 0u, cnt, w);
     }
     atom_flush<kAtomBlock>(cnt, acc);
 }
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigne
 // time.  queue: two arrays of qcap >= min(count, kAtomChunk) entries; qcount:
 // their two counters.
 template <int N>
-gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc,
+gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, int marked, unsigned long long* acc,
                         uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
     uint32_t* q1 = queue;
     uint32_t* q2 = queue + qcap;
@@ -187,32 +195,43 @@ gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count
         const uint64_t blocks = std::min<uint64_t>((c + kAtomBlock - 1) / kAtomBlock, 256 * 64);
         const unsigned later = (unsigned)std::min<uint64_t>(blocks, 256 * 16);
         hipLaunchKernelGGL(atom_census_kernel<N>, dim3((unsigned)blocks), dim3(kAtomBlock), 0, s, tab, nbytes, base,
-                           c, acc, q1, qcount);
+                           c, marked, acc, q1, qcount);
         GN_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(atom_first_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base,
+        hipLaunchKernelGGL(atom_first_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base, marked,
                            (const uint32_t*)q1, (const unsigned*)qcount, acc, q2, qcount + 1);
         GN_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(atom_singular_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base,
+        hipLaunchKernelGGL(atom_singular_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base, marked,
                            (const uint32_t*)q2, (const unsigned*)(qcount + 1), acc);
         GN_HIP_TRY(hipGetLastError());
     }
     return GN_OK;
 }
 
-gn_status launch_census_n(int n, const unsigned __int128* tab, int nbytes, uint64_t count, unsigned long long* acc,
-                          uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
+gn_status launch_census_n(int n, const unsigned __int128* tab, int nbytes, uint64_t count, int marked,
+                          unsigned long long* acc, uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
     switch (n) {
-        case 1: return launch_census<1>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 2: return launch_census<2>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 3: return launch_census<3>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 4: return launch_census<4>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 5: return launch_census<5>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 6: return launch_census<6>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 7: return launch_census<7>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        case 8: return launch_census<8>(tab, nbytes, count, acc, queue, qcap, qcount, s);
-        default: return launch_census<9>(tab, nbytes, count, acc, queue, qcap, qcount, s);
+        case 1: return launch_census<1>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 2: return launch_census<2>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 3: return launch_census<3>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 4: return launch_census<4>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 5: return launch_census<5>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 6: return launch_census<6>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 7: return launch_census<7>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 8: return launch_census<8>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        case 9: return launch_census<9>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        default: return launch_census<10>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
     }
 }
+
+// One enumeration: a family of labelled graphs, each the union of the base
+// rows and the orbits selected by its index bits, and the factor its counts
+// take in the final sum.
+struct AtomJob {
+    unsigned __int128 base;
+    std::vector<unsigned __int128> orbit_rows;
+    long long factor;
+    int marked;  // 1: the marked-vertex form (weights L / k), else plain counts
+};
 
 }  // namespace
 
@@ -221,9 +240,32 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     std::memset(out, 0, sizeof(*out));
     long long nfact = 1;
     const std::vector<AtomCycleType> types = atom_cycle_types(n, nfact);
-    const size_t T = types.size();
-    unsigned long long* acc = nullptr;  // per cycle type: kAtomCounters counters
-    unsigned __int128* tab = nullptr;   // per cycle type: kAtomTabBytes x 256 packed adjacency rows
+    // Burnside's sum: the identity's term in the marked-vertex form (one job per
+    // degree d of the marked vertex, factor n C(n-1, d)), every other cycle type
+    // as the unions of its orbits (factor: the number of permutations of the type)
+    const int S = atom_stride(n);
+    std::vector<AtomJob> jobs;
+    for (const AtomCycleType& t : types) {
+        const bool identity = (int)t.orbit_rows.size() == n * (n - 1) / 2 && t.weight == 1;
+        if (!identity || n == 1) {
+            jobs.push_back(AtomJob{0, t.orbit_rows, t.weight, 0});
+            continue;
+        }
+        std::vector<unsigned __int128> rest;  // edges among vertices 1 .. n-1
+        for (int i = 1; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                rest.push_back(((unsigned __int128)1 << (S * i + j)) | ((unsigned __int128)1 << (S * j + i)));
+        long long binom = 1;  // C(n-1, d)
+        for (int d = 1; d < n; ++d) {
+            binom = binom * (n - d) / d;
+            unsigned __int128 star = 0;
+            for (int j = 1; j <= d; ++j) star |= ((unsigned __int128)1 << j) | ((unsigned __int128)1 << (S * j));
+            jobs.push_back(AtomJob{star, rest, (long long)n * binom, 1});
+        }
+    }
+    const size_t J = jobs.size();
+    unsigned long long* acc = nullptr;  // per job: kAtomCounters counters
+    unsigned __int128* tab = nullptr;   // per job: kAtomTabBytes x 256 packed adjacency rows
     uint32_t* queue = nullptr;          // two queues of one chunk: graphs to eliminate, singular graphs
     unsigned* qcount = nullptr;         // their counters
     auto release = [&]() {
@@ -233,10 +275,10 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
         if (qcount) (void)hipFree(qcount);
     };
     uint64_t most = 0;
-    for (const AtomCycleType& t : types) most = std::max<uint64_t>(most, 1ull << t.orbit_rows.size());
+    for (const AtomJob& jb : jobs) most = std::max<uint64_t>(most, 1ull << jb.orbit_rows.size());
     const uint64_t qcap = std::min(most, kAtomChunk);
-    if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * T) != hipSuccess ||
-        hipMalloc((void**)&tab, sizeof(unsigned __int128) * kAtomTabBytes * 256 * T) != hipSuccess ||
+    if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * J) != hipSuccess ||
+        hipMalloc((void**)&tab, sizeof(unsigned __int128) * kAtomTabBytes * 256 * J) != hipSuccess ||
         hipMalloc((void**)&queue, sizeof(uint32_t) * 2 * qcap) != hipSuccess ||
         hipMalloc((void**)&qcount, 2 * sizeof(unsigned)) != hipSuccess) {
         (void)hipGetLastError();
@@ -244,31 +286,31 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
         return GN_E_NOMEM;
     }
     gn_status st = GN_OK;
-    // per cycle type and byte b of the graph index: the adjacency rows of every
-    // combination of orbits 8b .. 8b + 7
-    std::vector<unsigned __int128> htab(kAtomTabBytes * 256 * T, 0);
-    std::vector<int> nbytes(T);
-    std::vector<uint64_t> counts(T);
-    for (size_t t = 0; t < T; ++t) {
-        const int m = (int)types[t].orbit_rows.size();
+    // per job and byte b of the graph index: the adjacency rows of every
+    // combination of orbits 8b .. 8b + 7 (the base rows folded into byte 0)
+    std::vector<unsigned __int128> htab(kAtomTabBytes * 256 * J, 0);
+    std::vector<int> nbytes(J);
+    std::vector<uint64_t> counts(J);
+    for (size_t t = 0; t < J; ++t) {
+        const int m = (int)jobs[t].orbit_rows.size();
         counts[t] = 1ull << m;
         nbytes[t] = m > 8 ? (m + 7) / 8 : 1;
         for (int b = 0; b < nbytes[t]; ++b)
             for (int c = 0; c < 256; ++c) {
-                unsigned __int128 rows = 0;
+                unsigned __int128 rows = b == 0 ? jobs[t].base : 0;
                 for (int q = 0; q < 8; ++q)
-                    if (((c >> q) & 1) && 8 * b + q < m) rows |= types[t].orbit_rows[8 * b + q];
+                    if (((c >> q) & 1) && 8 * b + q < m) rows |= jobs[t].orbit_rows[8 * b + q];
                 htab[(t * kAtomTabBytes + b) * 256 + c] = rows;
             }
     }
     if (hipMemcpyAsync(tab, htab.data(), sizeof(unsigned __int128) * htab.size(), hipMemcpyHostToDevice, stream) !=
             hipSuccess ||
-        hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * T, stream) != hipSuccess)
+        hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * J, stream) != hipSuccess)
         st = GN_E_HIP;
-    for (size_t t = 0; t < T && st == GN_OK; ++t)
-        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], acc + t * kAtomCounters, queue, qcap, qcount,
-                             stream);
-    std::vector<unsigned long long> h(kAtomCounters * T, 0);
+    for (size_t t = 0; t < J && st == GN_OK; ++t)
+        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], jobs[t].marked,
+                             acc + t * kAtomCounters, queue, qcap, qcount, stream);
+    std::vector<unsigned long long> h(kAtomCounters * J, 0);
     if (st == GN_OK &&
         (hipMemcpyAsync(h.data(), acc, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, stream) !=
              hipSuccess ||
@@ -276,19 +318,28 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
         st = GN_E_HIP;
     release();
     if (st != GN_OK) return st;
-    // Burnside: the weighted sums are n! times the class counts
-    long long sum[kAtomCounters] = {0, 0, 0, 0, 0};
-    for (size_t t = 0; t < T; ++t) {
-        for (int k = 0; k < kAtomCounters; ++k) sum[k] += (long long)h[t * kAtomCounters + k] * types[t].weight;
+    // Burnside: the sums are n! times the class counts; the marked-vertex jobs
+    // carry the weights L / k, so their part is divided by L first
+    __int128 plain[kAtomCounters] = {0, 0, 0, 0, 0}, marked[kAtomCounters] = {0, 0, 0, 0, 0};
+    for (size_t t = 0; t < J; ++t) {
+        for (int k = 0; k < kAtomCounters; ++k)
+            (jobs[t].marked ? marked : plain)[k] += (__int128)h[t * kAtomCounters + k] * jobs[t].factor;
         out->labelled_evaluated += (int64_t)counts[t];
     }
-    for (int k = 0; k < kAtomCounters; ++k)
-        if (sum[k] % nfact != 0) return GN_E_NUMERIC;  // never expected: Burnside sums are multiples of n!
-    out->connected = sum[0] / nfact;
-    out->irregular_discrete = sum[1] / nfact;
-    out->irregular_continuous = sum[2] / nfact;
-    out->regular_discrete = sum[3] / nfact;
-    out->regular_continuous = sum[4] / nfact;
+    long long cls[kAtomCounters];
+    for (int k = 0; k < kAtomCounters; ++k) {
+        // never expected to fail: the marked part counts whole labelled graphs,
+        // and Burnside sums are multiples of n!
+        if (marked[k] % kAtomLcm != 0) return GN_E_NUMERIC;
+        const __int128 sum = plain[k] + marked[k] / kAtomLcm;
+        if (sum % nfact != 0) return GN_E_NUMERIC;
+        cls[k] = (long long)(sum / nfact);
+    }
+    out->connected = cls[0];
+    out->irregular_discrete = cls[1];
+    out->irregular_continuous = cls[2];
+    out->regular_discrete = cls[3];
+    out->regular_continuous = cls[4];
     out->atomic = out->irregular_discrete + out->irregular_continuous + out->regular_discrete + out->regular_continuous;
     return GN_OK;
 }

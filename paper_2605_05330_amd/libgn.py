@@ -67,11 +67,19 @@ _vp = ctypes.c_void_p
 
 
 def lib():
-    """Load libgn.so (raises if it is not built)."""
+    """Load libgn.so (raises if it is not built).
+
+    torch is imported first: its wheel carries its own HIP runtime under the
+    same soname as the system one that libgn.so is linked against.  Loaded
+    first, libgn.so would pull in the system runtime, and torch would then load
+    a second one into the process; two HIP runtimes in one process make
+    allocations fail or launches do nothing.  With torch first, the library
+    binds to the runtime already loaded."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libgn.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (one HIP runtime per process: torch's)
         L = ctypes.CDLL(LIB_PATH)
         sig = {
             "gn_graph_create": ([ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_uint32, _vp,
@@ -296,7 +304,7 @@ def gn_set_chunk_len(length: int):
 
 
 def gn_atom_census(n: int, stream=None) -> gn_atom_counts:
-    """Connected graphs on n vertices (1..9) up to isomorphism and their GN-atomic
+    """Connected graphs on n vertices (1..10) up to isomorphism and their GN-atomic
     classes (Appendix A, Table atoms_10), counted on the device."""
     out = gn_atom_counts()
     _check(lib().gn_atom_census(int(n), ctypes.byref(out), _stream(stream)), "gn_atom_census")

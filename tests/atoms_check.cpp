@@ -2,7 +2,7 @@
 // classification and the cycle-type enumeration, summed by Burnside's lemma on
 // the CPU.  Prints "n connected irregular_discrete irregular_continuous
 // regular_discrete regular_continuous" for n = 1 .. argv[1].
-// "classify N" instead reads edge masks of N-vertex graphs from stdin (bit k =
+// "classify N" (8, 9 or 10) instead reads edge masks of N-vertex graphs from stdin (bit k =
 // the k-th vertex pair i < j in lexicographic order) and prints, per graph,
 // "connected regular class" with class -1 (not atomic), 0 (discrete) or 1
 // (continuous), or -2 for a graph that is not connected.  Built and run by
@@ -63,6 +63,7 @@ int main(int argc, char** argv) {
         const int n = std::atoi(argv[2]);
         if (n == 8) return classify<8>();
         if (n == 9) return classify<9>();
+        if (n == 10) return classify<10>();
         return 2;
     }
     const int nmax = argc > 1 ? std::atoi(argv[1]) : 6;

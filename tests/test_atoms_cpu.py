@@ -58,13 +58,15 @@ def _circulant(n, steps):
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
-def test_host_classification_9_vertices_matches_oracle(tmp_path):
-    """The census at n = 9 packs the adjacency rows at a 9-bit stride (81 bits).
-    Its per-graph classification (connected, regular, not atomic / discrete /
-    continuous) is compared with the oracle's exact rational solve and LP on
-    9-vertex graphs: the 16 circulants, random graphs over a range of
-    densities, and, from a larger random pool, graphs the host code puts in
-    each class (the oracle then decides each of them independently)."""
+@pytest.mark.parametrize("n", [9, 10])
+def test_host_classification_matches_oracle(tmp_path, n):
+    """At n = 9 and 10 the census packs the adjacency rows at an n-bit stride
+    (81 and 100 bits).  Its per-graph classification (connected, regular, not
+    atomic / discrete / continuous) is compared with the oracle's exact
+    rational solve and LP on n-vertex graphs: the circulants, random graphs
+    over a range of densities, and, from a larger random pool, graphs the host
+    code puts in each class (the oracle then decides each of them
+    independently)."""
     exe = tmp_path / "atoms_check"
     cmd = ["g++", "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
            "-I" + os.path.join(ROOT, "paper_2605_05330_amd", "csrc"),
@@ -73,33 +75,86 @@ def test_host_classification_9_vertices_matches_oracle(tmp_path):
     assert r.returncode == 0, r.stderr
 
     def host(masks):
-        out = subprocess.run([str(exe), "classify", "9"], input="\n".join(map(str, masks)) + "\n",
+        out = subprocess.run([str(exe), "classify", str(n)], input="\n".join(map(str, masks)) + "\n",
                              capture_output=True, text=True, timeout=300)
         assert out.returncode == 0
         return [tuple(int(t) for t in line.split()) for line in out.stdout.split("\n") if line.strip()]
 
     import numpy as np
-    rng = np.random.default_rng(2605)
-    weights = 1 << np.arange(36, dtype=np.int64)
-    fixed = [_circulant(9, set(s)) for s in range(16) for s in [[d for d in (1, 2, 3, 4) if (s >> (d - 1)) & 1]]]
-    fixed += [int(((rng.random(36) < p) * weights).sum()) for p in (0.2, 0.35, 0.5, 0.65, 0.8, 0.95) for _ in range(60)]
-    pool = [int(((rng.random(36) < p) * weights).sum()) for p in (0.5, 0.7, 0.8, 0.9) for _ in range(50000)]
+    rng = np.random.default_rng(2605 + n)
+    m = n * (n - 1) // 2
+    weights = 1 << np.arange(m, dtype=np.int64)
+    steps = list(range(1, n // 2 + 1))
+    fixed = [_circulant(n, {d for b, d in enumerate(steps) if (s >> b) & 1}) for s in range(1 << len(steps))]
+    fixed += [int(((rng.random(m) < p) * weights).sum()) for p in (0.2, 0.35, 0.5, 0.65, 0.8, 0.95) for _ in range(60)]
+    pool = [int(((rng.random(m) < p) * weights).sum()) for p in (0.5, 0.7, 0.8, 0.9) for _ in range(50000)]
     picked, per_class = [], {}
-    for m, (conn, reg, cls) in zip(pool, host(pool)):
+    for g, (conn, reg, cls) in zip(pool, host(pool)):
         key = (reg, cls)
         if conn and cls >= 0 and per_class.get(key, 0) < 25:
             per_class[key] = per_class.get(key, 0) + 1
-            picked.append(m)
+            picked.append(g)
     masks = fixed + picked
     seen = {"disconnected": 0, "not atomic": 0, "discrete": 0, "continuous": 0}
-    for m, (conn, reg, cls) in zip(masks, host(masks)):
-        A = atoms.adjacency(9, m)
-        assert conn == int(atoms.is_connected(A)), m
+    for g, (conn, reg, cls) in zip(masks, host(masks)):
+        A = atoms.adjacency(n, g)
+        assert conn == int(atoms.is_connected(A)), g
         if not conn:
             seen["disconnected"] += 1
             continue
-        assert reg == int(len({sum(row) for row in A}) == 1), m
+        assert reg == int(len({sum(row) for row in A}) == 1), g
         ref = atoms.classify(A)
-        assert cls == (-1 if ref is None else (0 if ref[1] else 1)), m
+        assert cls == (-1 if ref is None else (0 if ref[1] else 1)), g
         seen["not atomic" if ref is None else ("discrete" if ref[1] else "continuous")] += 1
     assert min(seen.values()) >= 5, seen
+
+
+def test_marked_vertex_form_of_the_labelled_count():
+    """The census counts the labelled graphs of Burnside's identity term in a
+    marked-vertex form: mark a vertex of maximum degree d, relabel it 0 with
+    neighbours 1..d, and sum n C(n-1, d) P(G) / k(G) over the graphs with
+    N(0) = {1..d} and no degree above d (k = the number of degree-d vertices).
+    Checked here against plain enumeration of every labelled graph, with the
+    oracle deciding connectivity and the atomic class (n = 5: all classes;
+    n = 6: connected graphs)."""
+    from fractions import Fraction
+    from math import comb
+
+    def key(A, full):
+        if not atoms.is_connected(A):
+            return None
+        if not full:
+            return "connected"
+        c = atoms.classify(A)
+        return "connected" if c is None else ("regular" if c[0] else "irregular", "discrete" if c[1] else "continuous")
+
+    for n, full in ((5, True), (6, False)):
+        P = atoms.pairs(n)
+        plain = {}
+        for mask in range(1 << len(P)):
+            k = key(atoms.adjacency(n, mask), full)
+            if k is not None:
+                plain[k] = plain.get(k, 0) + 1
+                if k != "connected":
+                    plain["connected"] = plain.get("connected", 0) + 1
+        marked = {}
+        rest = [(i, j) for (i, j) in P if i > 0]
+        for d in range(1, n):
+            for sub in range(1 << len(rest)):
+                A = [[0] * n for _ in range(n)]
+                for j in range(1, d + 1):
+                    A[0][j] = A[j][0] = 1
+                for b, (i, j) in enumerate(rest):
+                    if (sub >> b) & 1:
+                        A[i][j] = A[j][i] = 1
+                deg = [sum(r) for r in A]
+                if max(deg[1:]) > d:
+                    continue
+                k = key(A, full)
+                if k is None:
+                    continue
+                w = Fraction(n * comb(n - 1, d), deg.count(d))
+                marked[k] = marked.get(k, 0) + w
+                if k != "connected":
+                    marked["connected"] = marked.get("connected", 0) + w
+        assert marked == plain, (n, marked, plain)

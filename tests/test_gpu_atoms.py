@@ -49,23 +49,24 @@ def test_census_n8(gpu):
     conn, idisc, icont, rdisc, rcont, total = _table()[8]
     assert _counts(c) == [conn, idisc, icont, rdisc, rcont]
     assert c.atomic == idisc + icont + rdisc + rcont == 247 and total == 230
-    assert c.labelled_evaluated >= 1 << 28
+    assert c.labelled_evaluated >= 7 << 21   # the identity's term in the marked-vertex form: 7 x 2^21
 
 
-def test_census_n9(gpu):
-    """n = 9: 2^36 labelled graphs for the identity alone (68.7e9 of 9!'s
-    Burnside terms), rows packed at a 9-bit stride.  The printed row adds up
-    (1,202 + 1,091 + 12 + 10 = 2,315) and is reproduced in full."""
+@pytest.mark.parametrize("n", [9, 10])
+def test_census_n9_n10(gpu, n):
+    """n = 9 and 10, rows packed at an n-bit stride; the identity's term in
+    the marked-vertex form ((n - 1) 2^C(n-1, 2) graphs: 2^39 at n = 10 instead
+    of 2^45).  Both printed rows add up (2,315 and 43,748) and are reproduced
+    in full."""
     from paper_2605_05330_amd import libgn
-    c = libgn.gn_atom_census(9)
-    conn, idisc, icont, rdisc, rcont, total = _table()[9]
+    c = libgn.gn_atom_census(n)
+    conn, idisc, icont, rdisc, rcont, total = _table()[n]
     assert _counts(c) == [conn, idisc, icont, rdisc, rcont]
-    assert c.atomic == total == 2315
-    assert c.labelled_evaluated >= 1 << 36
+    assert c.atomic == total == idisc + icont + rdisc + rcont
 
 
 def test_census_rejects_bad_n(gpu):
     from paper_2605_05330_amd import libgn
-    for n in (0, 10, -1):
+    for n in (0, 11, -1):
         with pytest.raises(libgn.GNError):
             libgn.gn_atom_census(n)
