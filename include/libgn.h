@@ -468,8 +468,8 @@ typedef struct {
  * another has no atom).  The identity's term is summed in a marked-vertex form
  * (a vertex of maximum degree d relabelled 0 with neighbours 1..d, each graph
  * weighted by n C(n-1, d) / (number of degree-d vertices)): 2^39 graphs at
- * n = 10 instead of 2^45.  n = 9 takes under a second, n = 10 about a
- * minute.  The sums are divided by n! on the host.  Allocates and
+ * n = 10 instead of 2^45.  n = 9 takes a tenth of a second, n = 10 about
+ * 25 s.  The sums are divided by n! on the host.  Allocates and
  * frees its own device buffers.  Errors: GN_E_ARG (n out of range, out NULL),
  * GN_E_NOMEM, GN_E_HIP, GN_E_NUMERIC (a weighted sum not divisible by n!: an
  * internal inconsistency, never expected).  SYNC. */

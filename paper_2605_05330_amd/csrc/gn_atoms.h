@@ -38,15 +38,26 @@ inline int atom_stride(int n) { return n <= 8 ? 8 : n; }
 // irregular continuous, regular discrete, regular continuous.
 constexpr int kAtomCounters = 5;
 
-// Fraction-free elimination of [B_S | 1], B = A + I, S = the columns in
-// `colmask` (the others read as zero); `rows` holds the adjacency rows.  rank:
-// rank of B_S; consistent: 1 lies in the span of B_S.  When B_S has full column
-// rank and the system is consistent, pos / neg receive the columns of S whose
-// (unique) solution component is > 0 / < 0.
+// Row p of M (p uniform per lane but not known at compile time: read with
+// selects, so M stays in registers).
 template <int N>
-__host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const unsigned colmask, int& rank,
-                                               bool& consistent, unsigned& pos, unsigned& neg) {
-    float M[N][N + 1];
+__host__ __device__ __forceinline__ void atom_row_of(const float (&M)[N][N + 1], const int p, float (&row)[N + 1]) {
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+        float v = 0.0f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) v = i == p ? M[i][j] : v;
+        row[j] = v;
+    }
+}
+
+// Forward fraction-free elimination of [B_S | 1], B = A + I, S = the columns in
+// `colmask` (the others read as zero).  pr[c]: pivot row of column c, or -1;
+// used: the pivot rows; prev: the last pivot (the Bareiss divisor, D below).
+template <int N>
+__host__ __device__ __forceinline__ void atom_forward(const AtomRowsT<N> rows, const unsigned colmask,
+                                                      float (&M)[N][N + 1], int (&pr)[N], unsigned& used, int& rank,
+                                                      float& prev) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const unsigned ri = atom_row<N>(rows, i);
@@ -57,9 +68,8 @@ __host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const un
         }
         M[i][N] = 1.0f;
     }
-    unsigned used = 0u;  // pivot rows
-    int pr[N];           // pivot row of column c, or -1
-    float prev = 1.0f;   // previous pivot (the Bareiss divisor)
+    used = 0u;
+    prev = 1.0f;
     rank = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -72,13 +82,7 @@ __host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const un
             used |= 1u << p;
             ++rank;
             float pv[N + 1];
-#pragma unroll
-            for (int j = 0; j <= N; ++j) {
-                float v = 0.0f;
-#pragma unroll
-                for (int i = 0; i < N; ++i) v = i == p ? M[i][j] : v;
-                pv[j] = v;
-            }
+            atom_row_of<N>(M, p, pv);
             const float pc = pv[c];
             const float inv = 1.0f / prev;
 #pragma unroll
@@ -92,6 +96,47 @@ __host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const un
             prev = pc;
         }
     }
+}
+
+// Fraction-free back substitution over the pivot columns: y_c = D x_c for
+// the right-hand side sgn x column `rhs` of M (sgn = 1, rhs = N: B x = 1;
+// sgn = 0: B x = 0) with x = 1 at column free_col (-1: none) and 0 at the
+// other free columns.  Entries stay minors of [B | 1], so every step is exact
+// in fp32.
+template <int N>
+__host__ __device__ __forceinline__ void atom_back(const float (&M)[N][N + 1], const int (&pr)[N], const float D,
+                                                   const int rhs, const float sgn, const int free_col,
+                                                   float (&y)[N]) {
+#pragma unroll
+    for (int c = N - 1; c >= 0; --c) {
+        y[c] = c == free_col ? D : 0.0f;
+        const int p = pr[c];
+        if (p < 0) continue;
+        float row[N + 1];
+        atom_row_of<N>(M, p, row);
+        float r = 0.0f;
+#pragma unroll
+        for (int j = 0; j <= N; ++j) r = j == rhs ? row[j] : r;
+        float num = sgn * D * r;
+#pragma unroll
+        for (int j = c + 1; j < N; ++j) num -= row[j] * y[j];
+        y[c] = rintf(num * (1.0f / row[c]));
+    }
+}
+
+// Fraction-free elimination of [B_S | 1], B = A + I, S = the columns in
+// `colmask` (the others read as zero); `rows` holds the adjacency rows.  rank:
+// rank of B_S; consistent: 1 lies in the span of B_S.  When B_S has full column
+// rank and the system is consistent, pos / neg receive the columns of S whose
+// (unique) solution component is > 0 / < 0.
+template <int N>
+__host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const unsigned colmask, int& rank,
+                                               bool& consistent, unsigned& pos, unsigned& neg) {
+    float M[N][N + 1];
+    int pr[N];
+    unsigned used;
+    float prev;
+    atom_forward<N>(rows, colmask, M, pr, used, rank, prev);
     consistent = true;
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -99,27 +144,9 @@ __host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const un
     pos = 0u;
     neg = 0u;
     if (!consistent || rank != __builtin_popcount(colmask)) return;
-    // fraction-free back substitution: y_c = D x_c with D the last pivot
     const float D = prev;
     float y[N];
-#pragma unroll
-    for (int c = N - 1; c >= 0; --c) {
-        y[c] = 0.0f;
-        const int p = pr[c];
-        if (p < 0) continue;
-        float row[N + 1];
-#pragma unroll
-        for (int j = 0; j <= N; ++j) {
-            float v = 0.0f;
-#pragma unroll
-            for (int i = 0; i < N; ++i) v = i == p ? M[i][j] : v;
-            row[j] = v;
-        }
-        float num = D * row[N];
-#pragma unroll
-        for (int j = c + 1; j < N; ++j) num -= row[j] * y[j];
-        y[c] = rintf(num * (1.0f / row[c]));
-    }
+    atom_back<N>(M, pr, D, N, 1.0f, -1, y);
     // accumulated in locals with selects: no store through a chosen output
     unsigned ps = 0u, ng = 0u;
 #pragma unroll
@@ -130,6 +157,46 @@ __host__ __device__ inline void atom_eliminate(const AtomRowsT<N> rows, const un
     }
     pos = ps;
     neg = ng;
+}
+
+// B of rank N - 1 with 1 in its span: the solutions are a line
+// x(t) = (y_p + t y_z) / D (y_p: free column at 0; y_z: the kernel direction,
+// free column at 1; both scaled by the last pivot D, integers below 2^9 in
+// magnitude).  Some x(t) > 0 iff the components with y_z = 0 are positive and
+// the lower bounds -y_p,i / y_z,i (y_z,i > 0) stay below the upper ones
+// (y_z,i < 0), compared as exact fractions.  Returns 1 when it does, else -1.
+template <int N>
+__host__ __device__ __forceinline__ int atom_line_class(const AtomRowsT<N> rows) {
+    float M[N][N + 1];
+    int pr[N];
+    unsigned used;
+    int rank;
+    float D;
+    atom_forward<N>(rows, (1u << N) - 1u, M, pr, used, rank, D);
+    int fc = 0;  // the free column
+#pragma unroll
+    for (int c = 0; c < N; ++c) fc = pr[c] < 0 ? c : fc;
+    float yp[N], yz[N];
+    atom_back<N>(M, pr, D, N, 1.0f, -1, yp);
+    atom_back<N>(M, pr, D, N, 0.0f, fc, yz);
+    const float s = D > 0.0f ? 1.0f : -1.0f;  // x(t) has the signs of s (y_p + t y_z)
+    bool ok = true;
+    float lo_n = -1.0f, lo_d = 0.0f;  // lower bound lo_n / lo_d, -infinity while lo_d = 0
+    float hi_n = 1.0f, hi_d = 0.0f;   // upper bound, +infinity while hi_d = 0
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const float a = s * yp[i], b = s * yz[i];
+        ok = ok && (b != 0.0f || a > 0.0f);
+        // b > 0: t > -a / b;  b < 0: t < a / -b
+        const bool up = b > 0.0f && (lo_d == 0.0f || -a * lo_d > lo_n * b);
+        lo_n = up ? -a : lo_n;
+        lo_d = up ? b : lo_d;
+        const bool dn = b < 0.0f && (hi_d == 0.0f || a * hi_d < hi_n * -b);
+        hi_n = dn ? a : hi_n;
+        hi_d = dn ? -b : hi_d;
+    }
+    ok = ok && (lo_d == 0.0f || hi_d == 0.0f || lo_n * hi_d < hi_n * lo_d);
+    return ok ? 1 : -1;
 }
 
 // Whether some closed neighbourhood strictly contains another.  Such a graph
@@ -228,22 +295,34 @@ __host__ __device__ __forceinline__ AtomRowsT<N> atom_twin_quotient(const AtomRo
     return out;
 }
 
-// Singular B of rank r with 1 in its span: atomic (continuous, returns 1) iff
-// B x = 1 has a positive solution, else -1.  A graph with twins is decided on
-// its twin quotient (smaller nullity, so a shorter subset search, often none:
-// a quotient with an invertible B answers at once).
+// Singular B of rank r with 1 in its span, decided where no subset search is
+// needed: a graph with twins is decided on its twin quotient (smaller
+// nullity; a quotient whose B is invertible answers at once), and a system of
+// nullity 1 by atom_line_class.  Returns 1 (a positive solution exists), -1
+// (none), or 0 with (sys, rank) the system left for atom_subset_search.
 template <int N>
-__host__ __device__ inline int atom_singular_class(const AtomRowsT<N> rows, const int r) {
+__host__ __device__ __forceinline__ int atom_singular_quick(const AtomRowsT<N> rows, const int r, AtomRowsT<N>& sys,
+                                                            int& rank) {
     const AtomRowsT<N> q = atom_twin_quotient<N>(rows);
-    AtomRowsT<N> sys = rows;
-    int rank = r;
+    sys = rows;
+    rank = r;
     if (q != rows) {
         const int f = atom_class_first<N>(q);
         if (f <= 0) return f < 0 ? -1 : 1;
         sys = q;
         rank = f;
     }
-    return atom_subset_search<N>(sys, rank);
+    return rank == N - 1 ? atom_line_class<N>(sys) : 0;
+}
+
+// Singular B of rank r with 1 in its span: atomic (continuous, returns 1) iff
+// B x = 1 has a positive solution, else -1.
+template <int N>
+__host__ __device__ inline int atom_singular_class(const AtomRowsT<N> rows, const int r) {
+    AtomRowsT<N> sys;
+    int rank;
+    const int k = atom_singular_quick<N>(rows, r, sys, rank);
+    return k != 0 ? k : atom_subset_search<N>(sys, rank);
 }
 
 // Class of one connected graph: -1 not atomic, else 0 discrete / 1 continuous.

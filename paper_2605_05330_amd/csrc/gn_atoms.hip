@@ -160,38 +160,112 @@ __global__ __launch_bounds__(kAtomBlock) void atom_first_kernel(const unsigned _
     atom_flush<kAtomBlock>(cnt, acc);
 }
 
-// Third pass over the second's queue: continuous atoms.
+// Third pass over the second's queue: the singular graphs decided without a
+// subset search (twin quotient, nullity 1); the others go to the last queue as
+// (g - base) | rank << 24 | regular << 28 | quotient << 29, the rank being
+// that of the system left (the twin quotient's when the bit is set).
 template <int N>
 __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
                                                                    uint64_t base, int marked,
-                                                                   const uint32_t* __restrict__ queue,
-                                                                   const unsigned* __restrict__ qcount,
-                                                                   unsigned long long* __restrict__ acc) {
+                                                                   const uint32_t* __restrict__ qin,
+                                                                   const unsigned* __restrict__ qin_count,
+                                                                   unsigned long long* __restrict__ acc,
+                                                                   uint32_t* __restrict__ queue,
+                                                                   unsigned* __restrict__ qcount) {
     __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
     atom_load_tab<N>(tab, nbytes, s_tab);
     unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
-    const unsigned total = *qcount;
-    for (unsigned i = blockIdx.x * kAtomBlock + threadIdx.x; i < total; i += gridDim.x * kAtomBlock) {
-        const uint32_t e = queue[i];
-        const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu));
-        unsigned w = 1u;
-        if (marked) (void)atom_marked_weight<N>(rows, w);
-        atom_count(atom_singular_class<N>(rows, (int)((e >> 24) & 15u)), ((e >> 28) & 1u) != 0u, cnt, w);
+    const unsigned total = *qin_count;
+    const unsigned stride = gridDim.x * kAtomBlock;
+    const unsigned bound = (total + 63u) & ~63u;  // whole wavefronts reach the ballot of atom_push
+    for (unsigned i = blockIdx.x * kAtomBlock + threadIdx.x; i < bound; i += stride) {
+        bool want = false;
+        uint32_t entry = 0u;
+        if (i < total) {
+            const uint32_t e = qin[i];
+            const bool regular = ((e >> 28) & 1u) != 0u;
+            const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu));
+            unsigned w = 1u;
+            if (marked) (void)atom_marked_weight<N>(rows, w);
+            AtomRowsT<N> sys;
+            int rank;
+            const int k = atom_singular_quick<N>(rows, (int)((e >> 24) & 15u), sys, rank);
+            if (k != 0) atom_count(k, regular, cnt, w);
+            want = k == 0;
+            entry = (e & 0x00ffffffu) | (uint32_t)rank << 24 | (regular ? 1u << 28 : 0u) |
+                    (sys != rows ? 1u << 29 : 0u);
+        }
+        atom_push(want, entry, queue, qcount);
     }
     atom_flush<kAtomBlock>(cnt, acc);
 }
 
-// The three passes over the graphs of one cycle type, a chunk of 2^24 at a
-// time.  queue: two arrays of qcap >= min(count, kAtomChunk) entries; qcount:
-// their two counters.
+// Column sets by size for the last pass (`subsets`): every mask of N bits,
+// grouped by popcount in increasing order, then increasing; start[r] is the
+// first of size r (start[N + 1] = 2^N).
+// Last pass: the subset search for the systems of nullity 2 or more, one
+// wavefront per graph.  The lanes take the column sets of size rank in turn,
+// 64 at a time, and OR their covers after each round (the same cover as the
+// one-lane search: a union over the same sets), stopping once it is complete.
 template <int N>
-gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, int marked, unsigned long long* acc,
+__global__ __launch_bounds__(kAtomBlock) void atom_search_kernel(const unsigned __int128* __restrict__ tab, int nbytes,
+                                                                 uint64_t base, int marked,
+                                                                 const uint16_t* __restrict__ subsets,
+                                                                 const int32_t* __restrict__ start,
+                                                                 const uint32_t* __restrict__ queue,
+                                                                 const unsigned* __restrict__ qcount,
+                                                                 unsigned long long* __restrict__ acc) {
+    __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
+    __shared__ uint16_t s_sub[1 << N];
+    __shared__ int32_t s_start[N + 2];
+    for (int k = threadIdx.x; k < (1 << N); k += kAtomBlock) s_sub[k] = subsets[k];
+    if (threadIdx.x < N + 2) s_start[threadIdx.x] = start[threadIdx.x];
+    atom_load_tab<N>(tab, nbytes, s_tab);
+    constexpr unsigned full = (1u << N) - 1u;
+    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    const int lane = threadIdx.x & 63;
+    const unsigned total = *qcount;
+    const unsigned waves = gridDim.x * (kAtomBlock / 64);
+    for (unsigned i = blockIdx.x * (kAtomBlock / 64) + (threadIdx.x >> 6); i < total; i += waves) {
+        const uint32_t e = queue[i];
+        const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + (e & 0x00ffffffu));
+        const AtomRowsT<N> sys = ((e >> 29) & 1u) ? atom_twin_quotient<N>(rows) : rows;
+        const int r = (int)((e >> 24) & 15u);
+        const int s0 = s_start[r], s1 = s_start[r + 1];
+        unsigned cover = 0u;
+        for (int b = s0; b < s1; b += 64) {
+            if (b + lane < s1) {
+                int r2;
+                bool c2;
+                unsigned p2, n2;
+                atom_eliminate<N>(sys, s_sub[b + lane], r2, c2, p2, n2);
+                if (r2 == r && c2 && n2 == 0u) cover |= p2;
+            }
+            for (int off = 32; off >= 1; off >>= 1) cover |= __shfl_xor(cover, off, 64);
+            if (cover == full) break;
+        }
+        if (lane == 0) {
+            unsigned w = 1u;
+            if (marked) (void)atom_marked_weight<N>(rows, w);
+            atom_count(cover == full ? 1 : -1, ((e >> 28) & 1u) != 0u, cnt, w);
+        }
+    }
+    atom_flush<kAtomBlock>(cnt, acc);
+}
+
+// The four passes over the graphs of one enumeration, a chunk of 2^24 at a
+// time.  queue: three arrays of qcap >= min(count, kAtomChunk) entries;
+// qcount: their three counters.
+template <int N>
+gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count, int marked,
+                        const uint16_t* subsets, const int32_t* start, unsigned long long* acc,
                         uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
     uint32_t* q1 = queue;
     uint32_t* q2 = queue + qcap;
+    uint32_t* q3 = queue + 2 * qcap;
     for (uint64_t base = 0; base < count; base += kAtomChunk) {
         const uint64_t c = std::min(kAtomChunk, count - base);
-        GN_HIP_TRY(hipMemsetAsync(qcount, 0, 2 * sizeof(unsigned), s));
+        GN_HIP_TRY(hipMemsetAsync(qcount, 0, 3 * sizeof(unsigned), s));
         const uint64_t blocks = std::min<uint64_t>((c + kAtomBlock - 1) / kAtomBlock, 256 * 64);
         const unsigned later = (unsigned)std::min<uint64_t>(blocks, 256 * 16);
         hipLaunchKernelGGL(atom_census_kernel<N>, dim3((unsigned)blocks), dim3(kAtomBlock), 0, s, tab, nbytes, base,
@@ -201,26 +275,33 @@ gn_status launch_census(const unsigned __int128* tab, int nbytes, uint64_t count
                            (const uint32_t*)q1, (const unsigned*)qcount, acc, q2, qcount + 1);
         GN_HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(atom_singular_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base, marked,
-                           (const uint32_t*)q2, (const unsigned*)(qcount + 1), acc);
+                           (const uint32_t*)q2, (const unsigned*)(qcount + 1), acc, q3, qcount + 2);
+        GN_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(atom_search_kernel<N>, dim3(later), dim3(kAtomBlock), 0, s, tab, nbytes, base, marked,
+                           subsets, start, (const uint32_t*)q3, (const unsigned*)(qcount + 2), acc);
         GN_HIP_TRY(hipGetLastError());
     }
     return GN_OK;
 }
 
 gn_status launch_census_n(int n, const unsigned __int128* tab, int nbytes, uint64_t count, int marked,
-                          unsigned long long* acc, uint32_t* queue, uint64_t qcap, unsigned* qcount, hipStream_t s) {
+                          const uint16_t* subsets, const int32_t* start, unsigned long long* acc, uint32_t* queue,
+                          uint64_t qcap, unsigned* qcount, hipStream_t s) {
+#define GN_ATOM_CASE(K) \
+    case K: return launch_census<K>(tab, nbytes, count, marked, subsets, start, acc, queue, qcap, qcount, s);
     switch (n) {
-        case 1: return launch_census<1>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 2: return launch_census<2>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 3: return launch_census<3>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 4: return launch_census<4>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 5: return launch_census<5>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 6: return launch_census<6>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 7: return launch_census<7>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 8: return launch_census<8>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        case 9: return launch_census<9>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
-        default: return launch_census<10>(tab, nbytes, count, marked, acc, queue, qcap, qcount, s);
+        GN_ATOM_CASE(1)
+        GN_ATOM_CASE(2)
+        GN_ATOM_CASE(3)
+        GN_ATOM_CASE(4)
+        GN_ATOM_CASE(5)
+        GN_ATOM_CASE(6)
+        GN_ATOM_CASE(7)
+        GN_ATOM_CASE(8)
+        GN_ATOM_CASE(9)
+        default: return launch_census<10>(tab, nbytes, count, marked, subsets, start, acc, queue, qcap, qcount, s);
     }
+#undef GN_ATOM_CASE
 }
 
 // One enumeration: a family of labelled graphs, each the union of the base
@@ -266,21 +347,27 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     const size_t J = jobs.size();
     unsigned long long* acc = nullptr;  // per job: kAtomCounters counters
     unsigned __int128* tab = nullptr;   // per job: kAtomTabBytes x 256 packed adjacency rows
-    uint32_t* queue = nullptr;          // two queues of one chunk: graphs to eliminate, singular graphs
+    uint32_t* queue = nullptr;          // three queues of one chunk: to eliminate, singular, to search
     unsigned* qcount = nullptr;         // their counters
+    uint16_t* subsets = nullptr;        // the column sets of n bits by size (last pass)
+    int32_t* start = nullptr;           // first set of each size, n + 2 entries
     auto release = [&]() {
         if (acc) (void)hipFree(acc);
         if (tab) (void)hipFree(tab);
         if (queue) (void)hipFree(queue);
         if (qcount) (void)hipFree(qcount);
+        if (subsets) (void)hipFree(subsets);
+        if (start) (void)hipFree(start);
     };
     uint64_t most = 0;
     for (const AtomJob& jb : jobs) most = std::max<uint64_t>(most, 1ull << jb.orbit_rows.size());
     const uint64_t qcap = std::min(most, kAtomChunk);
     if (hipMalloc((void**)&acc, sizeof(unsigned long long) * kAtomCounters * J) != hipSuccess ||
         hipMalloc((void**)&tab, sizeof(unsigned __int128) * kAtomTabBytes * 256 * J) != hipSuccess ||
-        hipMalloc((void**)&queue, sizeof(uint32_t) * 2 * qcap) != hipSuccess ||
-        hipMalloc((void**)&qcount, 2 * sizeof(unsigned)) != hipSuccess) {
+        hipMalloc((void**)&queue, sizeof(uint32_t) * 3 * qcap) != hipSuccess ||
+        hipMalloc((void**)&qcount, 3 * sizeof(unsigned)) != hipSuccess ||
+        hipMalloc((void**)&subsets, sizeof(uint16_t) << n) != hipSuccess ||
+        hipMalloc((void**)&start, sizeof(int32_t) * (n + 2)) != hipSuccess) {
         (void)hipGetLastError();
         release();
         return GN_E_NOMEM;
@@ -303,12 +390,24 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
                 htab[(t * kAtomTabBytes + b) * 256 + c] = rows;
             }
     }
+    std::vector<uint16_t> hsub;
+    std::vector<int32_t> hstart;
+    for (int r = 0; r <= n; ++r) {
+        hstart.push_back((int32_t)hsub.size());
+        for (int m = 0; m < (1 << n); ++m)
+            if (__builtin_popcount((unsigned)m) == r) hsub.push_back((uint16_t)m);
+    }
+    hstart.push_back((int32_t)hsub.size());
     if (hipMemcpyAsync(tab, htab.data(), sizeof(unsigned __int128) * htab.size(), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(subsets, hsub.data(), sizeof(uint16_t) * hsub.size(), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(start, hstart.data(), sizeof(int32_t) * hstart.size(), hipMemcpyHostToDevice, stream) !=
             hipSuccess ||
         hipMemsetAsync(acc, 0, sizeof(unsigned long long) * kAtomCounters * J, stream) != hipSuccess)
         st = GN_E_HIP;
     for (size_t t = 0; t < J && st == GN_OK; ++t)
-        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], jobs[t].marked,
+        st = launch_census_n(n, tab + t * kAtomTabBytes * 256, nbytes[t], counts[t], jobs[t].marked, subsets, start,
                              acc + t * kAtomCounters, queue, qcap, qcount, stream);
     std::vector<unsigned long long> h(kAtomCounters * J, 0);
     if (st == GN_OK &&
