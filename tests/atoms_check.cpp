@@ -5,8 +5,9 @@
 // "classify N" (8, 9 or 10) instead reads edge masks of N-vertex graphs from stdin (bit k =
 // the k-th vertex pair i < j in lexicographic order) and prints, per graph,
 // "connected regular class" with class -1 (not atomic), 0 (discrete) or 1
-// (continuous), or -2 for a graph that is not connected.  Built and run by
-// test_atoms_cpu.py; no GPU involved.
+// (continuous), or -2 for a graph that is not connected.  "linecheck" (below)
+// compares the nullity-one line test with the subset search.  Built and run
+// by test_atoms_cpu.py; no GPU involved.
 #include "gn_atoms.h"
 
 #include <cstdio>
@@ -58,7 +59,61 @@ static int run() {
     return 0;
 }
 
+// "linecheck N count seed": random graphs on N vertices whose B, or twin
+// quotient's B, has nullity one; prints "tested agreeing positive" for the
+// closed-form line test against the subset search.
+template <int N>
+static int linecheck(long long iters, unsigned long long seed) {
+    unsigned long long x = seed * 0x9E3779B97F4A7C15ull + 1ull;
+    auto next = [&x]() {  // xorshift64*
+        x ^= x >> 12;
+        x ^= x << 25;
+        x ^= x >> 27;
+        return x * 0x2545F4914F6CDD1Dull;
+    };
+    constexpr int S = AtomRows<N>::S;
+    static_assert(N * (N - 1) / 2 <= 64, "one random word per graph");
+    long long tested = 0, agree = 0, positive = 0;
+    for (long long it = 0; it < iters; ++it) {
+        const unsigned long long m = next();
+        AtomRowsT<N> rows = 0;
+        int k = 0;
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 1; j < N; ++j, ++k)
+                if ((m >> k) & 1ull)
+                    rows |= ((AtomRowsT<N>)1 << (S * i + j)) | ((AtomRowsT<N>)1 << (S * j + i));
+        if (!atom_connected<N>(rows) || atom_nested<N>(rows)) continue;
+        const int f = atom_class_first<N>(rows);
+        if (f <= 0) continue;
+        const AtomRowsT<N> q = atom_twin_quotient<N>(rows);
+        AtomRowsT<N> sys = rows;
+        int r = f;
+        if (q != rows) {
+            const int g = atom_class_first<N>(q);
+            if (g <= 0) continue;
+            sys = q;
+            r = g;
+        }
+        if (r != N - 1) continue;
+        ++tested;
+        const int b = atom_subset_search<N>(sys, r);
+        agree += atom_line_class<N>(sys) == b ? 1 : 0;
+        positive += b > 0 ? 1 : 0;
+    }
+    std::printf("%lld %lld %lld\n", tested, agree, positive);
+    return 0;
+}
+
 int main(int argc, char** argv) {
+    if (argc > 4 && std::strcmp(argv[1], "linecheck") == 0) {
+        const int n = std::atoi(argv[2]);
+        const long long iters = std::atoll(argv[3]);
+        const unsigned long long seed = std::strtoull(argv[4], nullptr, 10);
+        if (n == 8) return linecheck<8>(iters, seed);
+        if (n == 9) return linecheck<9>(iters, seed);
+        if (n == 10) return linecheck<10>(iters, seed);
+        return 2;
+    }
     if (argc > 2 && std::strcmp(argv[1], "classify") == 0) {
         const int n = std::atoi(argv[2]);
         if (n == 8) return classify<8>();

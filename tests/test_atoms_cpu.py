@@ -158,3 +158,24 @@ def test_marked_vertex_form_of_the_labelled_count():
                 if k != "connected":
                     marked["connected"] = marked.get("connected", 0) + w
         assert marked == plain, (n, marked, plain)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_nullity_one_line_test_matches_subset_search(tmp_path):
+    """Singular systems of nullity one are decided in closed form (the
+    solutions of B x = 1 are a line; a positive point exists iff an interval
+    of the line parameter is non-empty).  On random graphs of 8, 9 and 10
+    vertices whose B, or twin quotient's B, has nullity one, the test agrees
+    with the subset search over bases, and both outcomes occur."""
+    exe = tmp_path / "atoms_check"
+    cmd = ["g++", "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I" + os.path.join(ROOT, "paper_2605_05330_amd", "csrc"),
+           os.path.join(ROOT, "tests", "atoms_check.cpp"), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    for n in (8, 9, 10):
+        out = subprocess.run([str(exe), "linecheck", str(n), "1500000", str(n)], capture_output=True, text=True,
+                             timeout=300)
+        assert out.returncode == 0
+        tested, agree, positive = (int(t) for t in out.stdout.split())
+        assert tested >= 1000 and agree == tested and 0 < positive < tested, (n, tested, agree, positive)
