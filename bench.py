@@ -813,7 +813,7 @@ def main():
     if not a.no_warm:
         out["learned_warm_start"] = bench_warm(not a.no_cpu_baseline)
     if not a.no_atoms:
-        out["atom_census8"] = bench_atoms(with_n10=args.atoms10)
+        out["atom_census8"] = bench_atoms(with_n10=a.atoms10)
     if not a.no_lp:
         out["lp_warm_start"] = bench_lp(not a.no_cpu_baseline)
     if not a.no_hyper:
