@@ -409,6 +409,7 @@ __host__ __device__ inline void atom_evaluate(const AtomRowsT<N> rows, unsigned 
 struct AtomCycleType {
     long long weight;
     std::vector<unsigned __int128> orbit_rows;
+    bool identity;  // every cycle of length 1
 };
 
 inline void atom_partitions(int n, int maxp, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
@@ -447,6 +448,7 @@ inline std::vector<AtomCycleType> atom_cycle_types(int n, long long& nfact) {
             for (int k = 2; k <= mult[len]; ++k) z *= k;
         AtomCycleType t;
         t.weight = nfact / z;
+        t.identity = (int)parts.size() == n;
         std::vector<int> orbit(n * n, -1);
         for (int i = 0; i < n; ++i)
             for (int j = i + 1; j < n; ++j) {

@@ -327,8 +327,7 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     const int S = atom_stride(n);
     std::vector<AtomJob> jobs;
     for (const AtomCycleType& t : types) {
-        const bool identity = (int)t.orbit_rows.size() == n * (n - 1) / 2 && t.weight == 1;
-        if (!identity || n == 1) {
+        if (!t.identity || n == 1) {
             jobs.push_back(AtomJob{0, t.orbit_rows, t.weight, 0});
             continue;
         }
