@@ -660,6 +660,16 @@ gn_status gn_set_small_graph_limit(int32_t work_max);
  * thread-safe. */
 gn_status gn_set_pruning(int32_t mode);
 
+/* Tuning knob of gn_multi_solve (GN multi-start above).  A 16-start step costs
+ * about as much with one start still running as with sixteen.  With the
+ * hand-off enabled (1, the default), once a single start of a call with two or
+ * more is left running and at least two chains of step launches remain, its
+ * state moves at the next chain boundary to the chained single-start solve of
+ * gn_solve (same arithmetic in the same order: the same words, tests, steps,
+ * fallback count and results as without it).  0 keeps every start in the
+ * 16-start steps.  GN_E_ARG for another value.  Process-wide; not thread-safe. */
+gn_status gn_set_multi_handoff(int32_t enable);
+
 /* Human-readable name of a status code (static string). */
 const char* gn_status_str(gn_status s);
 

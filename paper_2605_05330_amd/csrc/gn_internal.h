@@ -124,9 +124,24 @@ extern int32_t g_prune;  // pruned lists in chained solves: 0 never, 1 where the
 float gn_internal_host_gamma(const gn_schedule* s, int32_t k);
 bool gn_internal_schedule_ok(const gn_schedule* sch);
 gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream);
+// Optional hooks of gn_internal_run_chunks: after_launch(c) enqueues more work
+// after chain c, ahead of its completion event; stop_after(c) is asked once
+// chain c has completed (chain c + 1 is then in flight) and returns true to
+// launch no further chain.  *last receives the last chain launched.
+struct ChunkHooks {
+    std::function<gn_status(int32_t)> after_launch;
+    std::function<bool(int32_t)> stop_after;
+};
 gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
                                  const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
-                                 hipStream_t stream);
+                                 hipStream_t stream, int32_t c_begin = 0, const ChunkHooks* hooks = nullptr,
+                                 int32_t* last = nullptr);
+// The chained single-start solve of g from chain c_begin on: ws.y[(c_begin C) & 1]
+// holds the state at step c_begin C (C = g_chunk_len), and the solve state and
+// flags are set up (gn_solve.hip).
+gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream);
+// multi-start solves hand their last running start to the single-start chains (gn_set_multi_handoff)
+extern int32_t g_multi_handoff;
 gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_t* steps, bool* binarised);
 gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
                                   gn_result* res);

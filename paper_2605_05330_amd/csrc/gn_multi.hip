@@ -36,7 +36,9 @@ constexpr int kStarts = 16;
 constexpr int kChunk = 256;  // heavy rows: entries staged per round
 
 // Offsets in the 4 KiB pinned staging block of a multi-start solve.
-constexpr size_t kPinDone = 64, kPinFb = 128, kPinNc = 256, kPinStats = 512;
+constexpr size_t kPinDone = 64, kPinFb = 128, kPinNc = 256, kPinStats = 512, kPinRun = 3072;
+static_assert(kPinStats + kStarts * sizeof(FinalStats) <= kPinRun && kPinRun + 2 * kStarts * 4 <= 4096,
+              "pinned staging layout");
 static_assert(sizeof(SolveState) <= kPinDone && kPinStats + kStarts * sizeof(FinalStats) <= 4096,
               "pinned staging layout");
 
@@ -771,13 +773,15 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
         return GN_OK;
     }
     if (!x || !sel) return GN_E_ARG;
-    gn_status st = gn_internal_ensure_ws(g, 1);  // the single-start buffers serve the final statistics
-    if (st != GN_OK) return st;
-    MultiWS* m = get_ws(g);
-    if (!m) return GN_E_NOMEM;
     const int32_t ms = sch->max_steps;
     const int32_t C = g_chunk_len;
     const int32_t nchunks = (ms + 1 + C - 1) / C;
+    // the single-start buffers serve the final statistics, and the chained
+    // single-start solve of a start handed over (below)
+    gn_status st = gn_internal_ensure_ws(g, g_multi_handoff ? nchunks * C : 1);
+    if (st != GN_OK) return st;
+    MultiWS* m = get_ws(g);
+    if (!m) return GN_E_NOMEM;
     if ((st = ensure_tables(m, nchunks * C)) != GN_OK) return st;
     const int n = g->n;
 
@@ -818,14 +822,41 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
         m->ws.chunks.clear();
         m->chunk_prune = prune ? 1 : 0;
     }
+    // Hand-off: once a single start is left running, the 16-start step costs as
+    // much as ever for it alone.  Its state moves at a chain boundary to the
+    // single-start chained solve, which computes the same words, tests and
+    // steps (the per-start arithmetic of the two step kernels is the same).
+    char* hp = (char*)m->ws.host_pinned;
+    volatile int32_t* run = (volatile int32_t*)(hp + kPinRun);  // per chain slot: done step of each start
+    int32_t handoff = -1;  // the start handed over
+    ChunkHooks hooks;
+    if (g_multi_handoff && starts > 1) {
+        hooks.after_launch = [m, run, stream](int32_t c) {
+            return hipMemcpyAsync((void*)(run + kStarts * (c & 1)), m->done, kStarts * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, stream) == hipSuccess ? GN_OK : GN_E_HIP;
+        };
+        hooks.stop_after = [run, starts, nchunks, &handoff](int32_t c) {
+            if (c + 2 >= nchunks) return false;  // chain c + 1 (in flight) is the last or next to last
+            int left = 0, who = -1;
+            for (int b = 0; b < starts; ++b)
+                if (run[kStarts * (c & 1) + b] < 0) {
+                    ++left;
+                    who = b;
+                }
+            if (left != 1) return false;
+            handoff = who;
+            return true;
+        };
+    }
+    int32_t last = -1;
     st = gn_internal_run_chunks(
         m->ws, nchunks, C,
-        [g, m, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, m, c, C, prune, out); }, stream);
+        [g, m, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, m, c, C, prune, out); }, stream, 0,
+        &hooks, &last);
     if (st != GN_OK) return st;
 
     // solve state, per-start outcomes and the last step's flags in one round trip
     // through the pinned staging block; the per-start statistics in a second one
-    char* hp = (char*)m->ws.host_pinned;
     SolveState* hs = (SolveState*)hp;
     int32_t* done = (int32_t*)(hp + kPinDone);
     unsigned long long* fbh = (unsigned long long*)(hp + kPinFb);
@@ -844,11 +875,41 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
     for (int b = 0; b < starts; ++b) {
         bin_of[b] = done[b] >= 0 || (ms >= 1 && nc_last[b] == 0);
         steps_of[b] = done[b] >= 0 ? done[b] : ms;
-        // stream order lets consecutive starts share the extraction and statistics buffers
-        hipLaunchKernelGGL(multi_extract_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, b,
-                           (const float*)m->Y[steps_of[b] & 1], m->yb);
+    }
+    // the start handed over, if it was still running after the last multi-start chain
+    const float* y_handed = nullptr;
+    if (handoff >= 0 && last >= 0 && last + 1 < nchunks && done[handoff] < 0) {
+        const int32_t k0 = (last + 1) * C;  // its state y_k0 is in Y[k0 & 1]
+        GraphWorkspace& ws = g->ws;
+        if ((st = gn_internal_init_solve(ws, sch, stream)) != GN_OK) return st;
+        hipLaunchKernelGGL(multi_extract_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, handoff,
+                           (const float*)m->Y[k0 & 1], ws.y[k0 & 1]);
         GN_HIP_TRY(hipGetLastError());
-        st = gn_internal_final_stats_launch(g, m->yb, gn_internal_host_gamma(sch, steps_of[b]), x + (size_t)b * n,
+        // the test of step k0 - 1, which the first single-start step reads
+        GN_HIP_TRY(hipMemcpyAsync(ws.notconv + (k0 - 1), m->nc16 + (size_t)(k0 - 1) * kStarts + handoff,
+                                  sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+        if ((st = gn_internal_chain_solve(g, nchunks, last + 1, stream)) != GN_OK) return st;
+        int32_t steps;
+        bool binarised;
+        if ((st = gn_internal_solve_outcome(ws, ms, &steps, &binarised)) != GN_OK) return st;
+        SolveState tail;
+        GN_HIP_TRY(hipMemcpy(&tail, ws.state, sizeof(tail), hipMemcpyDeviceToHost));
+        steps_of[handoff] = steps;
+        bin_of[handoff] = binarised;
+        fbh[handoff] += tail.fallback;
+        y_handed = ws.y[steps & 1];
+    }
+    for (int b = 0; b < starts; ++b) {
+        const float* yb = m->yb;
+        if (b == handoff && y_handed) {
+            yb = y_handed;
+        } else {
+            // stream order lets consecutive starts share the extraction and statistics buffers
+            hipLaunchKernelGGL(multi_extract_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, b,
+                               (const float*)m->Y[steps_of[b] & 1], m->yb);
+            GN_HIP_TRY(hipGetLastError());
+        }
+        st = gn_internal_final_stats_launch(g, yb, gn_internal_host_gamma(sch, steps_of[b]), x + (size_t)b * n,
                                             sel + (size_t)b * n, m->stats + b, stream);
         if (st != GN_OK) return st;
     }
@@ -885,6 +946,14 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
     }
     if (*best < 0) *best = best_any;
     return all_bin ? GN_OK : GN_NOT_CONVERGED;
+}
+
+int32_t g_multi_handoff = 1;
+
+extern "C" gn_status gn_set_multi_handoff(int32_t enable) {
+    if (enable != 0 && enable != 1) return GN_E_ARG;
+    g_multi_handoff = enable;
+    return GN_OK;
 }
 
 extern "C" gn_status gn_random_starts(gn_graph* g, int32_t starts, const float* u, float* x, hipStream_t stream) {

@@ -94,7 +94,7 @@ gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hip
 
 gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
                                  const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
-                                 hipStream_t stream) {
+                                 hipStream_t stream, int32_t c_begin, const ChunkHooks* hooks, int32_t* last) {
     if (ws.chunk_len != C) {
         for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
         ws.chunks.clear();
@@ -109,27 +109,35 @@ gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
         return GN_E_HIP;
     }
     gn_status rs = GN_OK;
-    for (int32_t c = 0; c < nchunks && rs == GN_OK; ++c) {
+    int32_t launched = c_begin - 1;
+    for (int32_t c = c_begin; c < nchunks && rs == GN_OK; ++c) {
         if (!ws.chunks[c]) {
             rs = build(c, &ws.chunks[c]);
             if (rs != GN_OK) break;
         }
         if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess ||
             hipMemcpyAsync((void*)(pin + 2 * (c & 1)), ws.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           stream) != hipSuccess ||
-            hipEventRecord(ev[c & 1], stream) != hipSuccess) {
+                           stream) != hipSuccess) {
             rs = GN_E_HIP;
             break;
         }
-        if (c >= 1) {
+        launched = c;
+        if (hooks && hooks->after_launch && (rs = hooks->after_launch(c)) != GN_OK) break;
+        if (hipEventRecord(ev[c & 1], stream) != hipSuccess) {
+            rs = GN_E_HIP;
+            break;
+        }
+        if (c > c_begin) {
             const int p = (c - 1) & 1;
             if (hipEventSynchronize(ev[p]) != hipSuccess) {
                 rs = GN_E_HIP;
                 break;
             }
             if (pin[2 * p] >= 0 || pin[2 * p + 1] != 0) break;
+            if (hooks && hooks->stop_after && hooks->stop_after(c - 1)) break;
         }
     }
+    if (last) *last = launched;
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (rs != GN_OK) return rs;
@@ -288,6 +296,20 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hi
 int32_t g_chunk_len = 32;
 int32_t g_prune = 1;
 
+gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream) {
+    GraphWorkspace& ws = g->ws;
+    const int32_t C = g_chunk_len;
+    const bool prune = g->prune && (g_prune == 2 || (g_prune == 1 && g->prune_pays));
+    if (ws.chunk_prune != (prune ? 1 : 0)) {  // chains captured for the other kind of lists
+        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        ws.chunks.clear();
+        ws.chunk_prune = prune ? 1 : 0;
+    }
+    return gn_internal_run_chunks(
+        ws, nchunks, C, [g, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, prune, out); },
+        stream, c_begin);
+}
+
 extern "C" gn_status gn_set_pruning(int32_t mode) {
     if (mode < 0 || mode > 2) return GN_E_ARG;
     g_prune = mode;
@@ -340,15 +362,7 @@ extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uin
         st = gn_internal_small_solve(g, stream);
         if (st == GN_OK && hipStreamSynchronize(stream) != hipSuccess) st = GN_E_HIP;
     } else {
-        const bool prune = g->prune && (g_prune == 2 || (g_prune == 1 && g->prune_pays));
-        if (ws.chunk_prune != (prune ? 1 : 0)) {  // chains captured for the other kind of lists
-            for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
-            ws.chunks.clear();
-            ws.chunk_prune = prune ? 1 : 0;
-        }
-        st = gn_internal_run_chunks(
-            ws, nchunks, C, [g, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, prune, out); },
-            stream);
+        st = gn_internal_chain_solve(g, nchunks, 0, stream);
     }
     if (st != GN_OK) return st;
     int32_t steps;

@@ -99,6 +99,7 @@ def lib():
             "gn_set_chunk_len": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_small_graph_limit": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_pruning": ([ctypes.c_int32], ctypes.c_int),
+            "gn_set_multi_handoff": ([ctypes.c_int32], ctypes.c_int),
             "gn_atom_census": ([ctypes.c_int32, ctypes.POINTER(gn_atom_counts), _vp], ctypes.c_int),
             "gn_batch_create": ([ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
                                 ctypes.c_int),
@@ -321,6 +322,13 @@ def gn_set_small_graph_limit(work_max: int):
 
 
 PRUNE_NEVER, PRUNE_WHERE_IT_PAYS, PRUNE_ALWAYS = 0, 1, 2
+
+
+def gn_set_multi_handoff(enable: bool):
+    """gn_multi_solve: hand the last running start to the single-start chained
+    solve (True, the default) or keep it in the 16-start steps; results do not
+    change."""
+    _check(lib().gn_set_multi_handoff(1 if enable else 0), "gn_set_multi_handoff")
 
 
 def gn_set_pruning(mode: int):
