@@ -235,7 +235,7 @@ def test_multi_zero_steps(gpu):
     assert np.array_equal(sel.cpu().numpy().astype(bool), xn > 0.5)
 
 
-@pytest.mark.parametrize("case", ["late", "budget", "n2900"])
+@pytest.mark.parametrize("case", ["late", "budget", "n2900", "check_every_5", "chain_33"])
 def test_multi_handoff_same_bits(gpu, case):
     """Once a single start is left running, gn_multi_solve hands it to the
     single-start chained solve at a chain boundary.  With and without the
@@ -244,19 +244,23 @@ def test_multi_handoff_same_bits(gpu, case):
     each case one start outlasts the others by many chains, so the hand-off
     happens: the uniform start ½ binarises thousands of steps after the others
     (late) or reaches the step budget (budget), or a random start binarises
-    ~700 steps after the others on a larger graph (n2900)."""
+    ~700 steps after the others on a larger graph (n2900); the first again
+    with the test every 5 steps, and with chains of 33 steps (the hand-off at
+    an odd step)."""
     import torch
     libgn = _lib()
     sched = dict(RAMP, max_steps=4000)
     starts = 6
-    if case in ("late", "budget"):
+    if case == "n2900":
+        g = I.erdos_renyi(2900, 6 / 2899, 319)
+        w = I.weights_uniform01(2900, 319)
+    else:
         g = I.erdos_renyi(233, 6 / 232, 109)
         w = I.weights_uniform01(233, 109)
         if case == "budget":
             sched["max_steps"] = 2000
-    else:
-        g = I.erdos_renyi(2900, 6 / 2899, 319)
-        w = I.weights_uniform01(2900, 319)
+        if case == "check_every_5":
+            sched["check_every"] = 5
     G = libgn.Graph(g.n, g.row_ptr, g.col_idx, w)
     u = torch.from_numpy((1.0 - I.rng_for(1, 41).random(starts * g.n)).astype(np.float32)).cuda()
     x0 = torch.empty(starts * g.n, device="cuda")
@@ -264,6 +268,8 @@ def test_multi_handoff_same_bits(gpu, case):
     x0[:g.n] = 0.5
     outs = []
     try:
+        if case == "chain_33":
+            libgn.gn_set_chunk_len(33)
         for on in (True, False):
             libgn.gn_set_multi_handoff(on)
             x = x0.clone()
@@ -272,18 +278,20 @@ def test_multi_handoff_same_bits(gpu, case):
             outs.append((st, [(r.steps, r.binarised, r.fallback_count, r.set_objective, r.relaxed_objective,
                                r.stab, r.conflicts, r.uncovered, r.set_size) for r in res], best,
                          x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
+        a, b = outs
+        steps = sorted(r[0] for r in a[1])
+        assert steps[-1] > steps[-2] + 3 * 33, steps   # one start ran alone for more than two chains
+        late = int(np.argmax([r[0] for r in a[1]]))
+        assert a[1][late][1] == (case != "budget")
+        assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+        assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
+        # the handed-over start as gn_solve from the same point
+        x = x0[late * g.n:(late + 1) * g.n].clone()
+        sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        r = G.solve(x, sel, **sched)
+        assert (r.steps, r.binarised, r.fallback_count, r.set_objective, r.relaxed_objective,
+                r.stab) == a[1][late][:6]
+        assert np.array_equal(x.cpu().numpy().view(np.uint32), a[3][late * g.n:(late + 1) * g.n])
     finally:
         libgn.gn_set_multi_handoff(True)
-    a, b = outs
-    steps = sorted(r[0] for r in a[1])
-    assert steps[-1] > steps[-2] + 3 * 32, steps   # one start ran alone for more than two chains
-    late = int(np.argmax([r[0] for r in a[1]]))
-    assert a[1][late][1] == (case != "budget")
-    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
-    assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
-    # the handed-over start as gn_solve from the same point
-    x = x0[late * g.n:(late + 1) * g.n].clone()
-    sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
-    r = G.solve(x, sel, **sched)
-    assert (r.steps, r.binarised, r.fallback_count, r.set_objective, r.relaxed_objective, r.stab) == a[1][late][:6]
-    assert np.array_equal(x.cpu().numpy().view(np.uint32), a[3][late * g.n:(late + 1) * g.n])
+        libgn.gn_set_chunk_len(32)
