@@ -39,7 +39,7 @@ def _args():
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-multi", action="store_true")
     p.add_argument("--no-atoms", action="store_true")
-    p.add_argument("--atoms10", action="store_true", help="also the n = 10 atom census (about 25 s)")
+    p.add_argument("--atoms10", action="store_true", help="also the n = 10 atom census (about 11 s)")
     p.add_argument("--no-lp", action="store_true")
     p.add_argument("--no-hyper", action="store_true")
     return p.parse_args()

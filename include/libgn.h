@@ -465,11 +465,12 @@ typedef struct {
  * permutation is classified on the device, one thread each, exactly
  * (fraction-free elimination of [B | 1], whose entries stay below 2^24, after
  * an exact filter: a graph in which one closed neighbourhood strictly contains
- * another has no atom).  The identity's term is summed in a marked-vertex form
- * (a vertex of maximum degree d relabelled 0 with neighbours 1..d, each graph
- * weighted by n C(n-1, d) / (number of degree-d vertices)): 2^39 graphs at
- * n = 10 instead of 2^45.  n = 9 takes a tenth of a second, n = 10 about
- * 25 s.  The sums are divided by n! on the host.  Allocates and
+ * another has no atom).  The identity's term is summed in a two-level
+ * marked-vertex form (a vertex of maximum degree relabelled 0, then one of
+ * largest degree among its neighbours relabelled 1, each with its
+ * neighbourhood fixed and the graph weighted by the number of such choices):
+ * about 2.5e10 graphs at n = 10 instead of 2^45.  n = 9 takes under a tenth of
+ * a second, n = 10 about 11 s.  The sums are divided by n! on the host.  Allocates and
  * frees its own device buffers.  Errors: GN_E_ARG (n out of range, out NULL),
  * GN_E_NOMEM, GN_E_HIP, GN_E_NUMERIC (a weighted sum not divisible by n!: an
  * internal inconsistency, never expected).  SYNC. */

@@ -359,43 +359,53 @@ __host__ __device__ inline bool atom_regular(const AtomRowsT<N> rows) {
 
 // Adds an atomic class (0 discrete / 1 continuous) to the counters, with
 // weight w.
-__host__ __device__ inline void atom_count(const int cls, const bool regular, unsigned (&cnt)[kAtomCounters],
+__host__ __device__ inline void atom_count(const int cls, const bool regular, unsigned long long (&cnt)[kAtomCounters],
                                            const unsigned w = 1u) {
     const int idx = cls < 0 ? -1 : 1 + (regular ? 2 : 0) + cls;
 #pragma unroll
     for (int k = 1; k < kAtomCounters; ++k) cnt[k] += idx == k ? w : 0u;  // fixed indices: no scratch array
 }
 
-// Weights of the marked-vertex sum: lcm(1, ..., 10), so that L / k is an
-// integer for every count k of maximum-degree vertices.
+// Weights of the marked-vertex sum: L^2 with L = lcm(1, ..., 10), so that
+// L^2 / (k k') is an integer for any two counts k, k' <= 10.
 constexpr unsigned kAtomLcm = 2520;
+constexpr unsigned kAtomMarkW = kAtomLcm * kAtomLcm;
 
 // Marked-vertex form of the identity's term of Burnside's sum (the number of
-// labelled graphs with an invariant property P).  Marking one vertex of
-// maximum degree and relabelling it to 0 with neighbours 1..d,
-//     #{labelled G with P} = n sum_d C(n-1, d) sum_G' P(G') / k(G'),
-// G' over the graphs with N(0) = {1, .., d} in which no vertex has degree
-// above d, k(G') the number of vertices of degree d.  For such a G' this
-// returns true and w = L / k; false when some vertex has a larger degree than
-// vertex 0 (the graph is not in the sum).
+// labelled graphs with an invariant property P), two levels deep.  Mark a
+// vertex of maximum degree d and relabel it 0 with neighbours A = {1..d};
+// then mark a vertex of largest degree within A and relabel it 1 with
+// neighbours {0} u {2..a+1} u {d+1..d+b}.  Counting each graph once per
+// choice of marks (weight 1 / (k k')),
+//     #{labelled G with P} = sum_{d,a,b} n C(n-1,d) d C(d-1,a) C(n-1-d,b)
+//                            sum_G' P(G') / (k(G') k'(G')),
+// G' over the graphs with those two neighbourhoods in which no vertex has
+// degree above d and no vertex of A a degree above vertex 1's; k = the number
+// of vertices of degree d, k' = those of A with vertex 1's degree.  For such a
+// G' this returns true and w = L^2 / (k k'); false when G' is outside the sum.
 template <int N>
 __host__ __device__ inline bool atom_marked_weight(const AtomRowsT<N> rows, unsigned& w) {
-    const int d0 = __builtin_popcount(atom_row<N>(rows, 0));
-    int k = 1;
+    const unsigned A = atom_row<N>(rows, 0);  // {1..d}
+    const int d0 = __builtin_popcount(A);
+    const int d1 = __builtin_popcount(atom_row<N>(rows, 1));
+    int k = 1, ka = 0;
     bool in = true;
 #pragma unroll
     for (int v = 1; v < N; ++v) {
         const int dv = __builtin_popcount(atom_row<N>(rows, v));
         in = in && dv <= d0;
         k += dv == d0 ? 1 : 0;
+        const bool ina = ((A >> v) & 1u) != 0u;
+        in = in && (!ina || dv <= d1);
+        ka += ina && dv == d1 ? 1 : 0;
     }
-    w = kAtomLcm / (unsigned)k;
+    w = kAtomMarkW / (unsigned)(k * (ka > 0 ? ka : 1));
     return in;
 }
 
 // Adds one labelled graph to the counters.
 template <int N>
-__host__ __device__ inline void atom_evaluate(const AtomRowsT<N> rows, unsigned (&cnt)[kAtomCounters]) {
+__host__ __device__ inline void atom_evaluate(const AtomRowsT<N> rows, unsigned long long (&cnt)[kAtomCounters]) {
     if (!atom_connected<N>(rows)) return;
     cnt[0] += 1u;
     atom_count(atom_class<N>(rows), atom_regular<N>(rows), cnt);

@@ -62,12 +62,12 @@ __device__ __forceinline__ void atom_load_tab(const unsigned __int128* __restric
 }
 
 template <int BT>
-__device__ __forceinline__ void atom_flush(unsigned (&cnt)[kAtomCounters], unsigned long long* acc) {
-    __shared__ unsigned s_red[BT / 64][kAtomCounters];
+__device__ __forceinline__ void atom_flush(unsigned long long (&cnt)[kAtomCounters], unsigned long long* acc) {
+    __shared__ unsigned long long s_red[BT / 64][kAtomCounters];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kAtomCounters; ++k) {
-        unsigned v = cnt[k];
+        unsigned long long v = cnt[k];
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) s_red[wave][k] = v;
     }
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_census_kernel(const unsigned 
                                                                  unsigned* __restrict__ qcount) {
     __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
     atom_load_tab<N>(tab, nbytes, s_tab);
-    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    unsigned long long cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const uint64_t stride = (uint64_t)gridDim.x * kAtomBlock;
     for (uint64_t k = (uint64_t)blockIdx.x * kAtomBlock + threadIdx.x; k < count; k += stride) {
         const AtomRowsT<N> rows = atom_rows<N>(s_tab, nbytes, base + k);
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_first_kernel(const unsigned _
                                                                 unsigned* __restrict__ qcount) {
     __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
     atom_load_tab<N>(tab, nbytes, s_tab);
-    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    unsigned long long cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const unsigned total = *qin_count;
     const unsigned stride = gridDim.x * kAtomBlock;
     // the bound rounded up to whole wavefronts: every lane reaches the ballot of atom_push
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_singular_kernel(const unsigne
                                                                    unsigned* __restrict__ qcount) {
     __shared__ AtomRowsT<N> s_tab[kAtomTabBytes * 256];
     atom_load_tab<N>(tab, nbytes, s_tab);
-    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    unsigned long long cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const unsigned total = *qin_count;
     const unsigned stride = gridDim.x * kAtomBlock;
     const unsigned bound = (total + 63u) & ~63u;  // whole wavefronts reach the ballot of atom_push
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kAtomBlock) void atom_search_kernel(const unsigned 
     if (threadIdx.x < N + 2) s_start[threadIdx.x] = start[threadIdx.x];
     atom_load_tab<N>(tab, nbytes, s_tab);
     constexpr unsigned full = (1u << N) - 1u;
-    unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+    unsigned long long cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
     const int lane = threadIdx.x & 63;
     const unsigned total = *qcount;
     const unsigned waves = gridDim.x * (kAtomBlock / 64);
@@ -311,7 +311,7 @@ struct AtomJob {
     unsigned __int128 base;
     std::vector<unsigned __int128> orbit_rows;
     long long factor;
-    int marked;  // 1: the marked-vertex form (weights L / k), else plain counts
+    int marked;  // 1: the marked-vertex form (weights L^2 / (k k')), else plain counts
 };
 
 }  // namespace
@@ -321,9 +321,10 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     std::memset(out, 0, sizeof(*out));
     long long nfact = 1;
     const std::vector<AtomCycleType> types = atom_cycle_types(n, nfact);
-    // Burnside's sum: the identity's term in the marked-vertex form (one job per
-    // degree d of the marked vertex, factor n C(n-1, d)), every other cycle type
-    // as the unions of its orbits (factor: the number of permutations of the type)
+    // Burnside's sum: the identity's term in the two-level marked-vertex form
+    // (atom_marked_weight: one job per degree d of the first marked vertex and
+    // per neighbourhood sizes a, b of the second), every other cycle type as the
+    // unions of its orbits (factor: the number of permutations of the type)
     const int S = atom_stride(n);
     std::vector<AtomJob> jobs;
     for (const AtomCycleType& t : types) {
@@ -331,17 +332,29 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
             jobs.push_back(AtomJob{0, t.orbit_rows, t.weight, 0});
             continue;
         }
-        std::vector<unsigned __int128> rest;  // edges among vertices 1 .. n-1
-        for (int i = 1; i < n; ++i)
+        std::vector<unsigned __int128> rest;  // edges among vertices 2 .. n-1
+        for (int i = 2; i < n; ++i)
             for (int j = i + 1; j < n; ++j)
                 rest.push_back(((unsigned __int128)1 << (S * i + j)) | ((unsigned __int128)1 << (S * j + i)));
-        long long binom = 1;  // C(n-1, d)
-        for (int d = 1; d < n; ++d) {
-            binom = binom * (n - d) / d;
-            unsigned __int128 star = 0;
-            for (int j = 1; j <= d; ++j) star |= ((unsigned __int128)1 << j) | ((unsigned __int128)1 << (S * j));
-            jobs.push_back(AtomJob{star, rest, (long long)n * binom, 1});
-        }
+        auto edge = [S](int i, int j) {
+            return ((unsigned __int128)1 << (S * i + j)) | ((unsigned __int128)1 << (S * j + i));
+        };
+        auto binom = [](int p, int q) {
+            long long r = 1;
+            for (int t = 1; t <= q; ++t) r = r * (p - q + t) / t;
+            return r;
+        };
+        for (int d = 1; d < n; ++d)
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b <= n - 1 - d && 1 + a + b <= d; ++b) {
+                    unsigned __int128 base = 0;  // N(0) = {1..d}, N(1) = {0} u {2..a+1} u {d+1..d+b}
+                    for (int j = 1; j <= d; ++j) base |= edge(0, j);
+                    for (int j = 2; j <= a + 1; ++j) base |= edge(1, j);
+                    for (int j = d + 1; j <= d + b; ++j) base |= edge(1, j);
+                    const long long factor =
+                        (long long)n * binom(n - 1, d) * d * binom(d - 1, a) * binom(n - 1 - d, b);
+                    jobs.push_back(AtomJob{base, rest, factor, 1});
+                }
     }
     const size_t J = jobs.size();
     unsigned long long* acc = nullptr;  // per job: kAtomCounters counters
@@ -417,7 +430,7 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     release();
     if (st != GN_OK) return st;
     // Burnside: the sums are n! times the class counts; the marked-vertex jobs
-    // carry the weights L / k, so their part is divided by L first
+    // carry the weights L^2 / (k k'), so their part is divided by L^2 first
     __int128 plain[kAtomCounters] = {0, 0, 0, 0, 0}, marked[kAtomCounters] = {0, 0, 0, 0, 0};
     for (size_t t = 0; t < J; ++t) {
         for (int k = 0; k < kAtomCounters; ++k)
@@ -428,8 +441,8 @@ extern "C" gn_status gn_atom_census(int32_t n, gn_atom_counts* out, hipStream_t 
     for (int k = 0; k < kAtomCounters; ++k) {
         // never expected to fail: the marked part counts whole labelled graphs,
         // and Burnside sums are multiples of n!
-        if (marked[k] % kAtomLcm != 0) return GN_E_NUMERIC;
-        const __int128 sum = plain[k] + marked[k] / kAtomLcm;
+        if (marked[k] % kAtomMarkW != 0) return GN_E_NUMERIC;
+        const __int128 sum = plain[k] + marked[k] / kAtomMarkW;
         if (sum % nfact != 0) return GN_E_NUMERIC;
         cls[k] = (long long)(sum / nfact);
     }

@@ -40,7 +40,7 @@ static int run() {
     long long sum[kAtomCounters] = {0, 0, 0, 0, 0};
     for (const AtomCycleType& t : types) {
         const int m = (int)t.orbit_rows.size();
-        unsigned cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
+        unsigned long long cnt[kAtomCounters] = {0u, 0u, 0u, 0u, 0u};
         for (uint64_t g = 0; g < (1ull << m); ++g) {
             AtomRowsT<N> rows = 0;
             for (int o = 0; o < m; ++o)

@@ -111,12 +111,15 @@ def test_host_classification_matches_oracle(tmp_path, n):
 
 def test_marked_vertex_form_of_the_labelled_count():
     """The census counts the labelled graphs of Burnside's identity term in a
-    marked-vertex form: mark a vertex of maximum degree d, relabel it 0 with
-    neighbours 1..d, and sum n C(n-1, d) P(G) / k(G) over the graphs with
-    N(0) = {1..d} and no degree above d (k = the number of degree-d vertices).
-    Checked here against plain enumeration of every labelled graph, with the
-    oracle deciding connectivity and the atomic class (n = 5: all classes;
-    n = 6: connected graphs)."""
+    two-level marked-vertex form: mark a vertex of maximum degree d, relabel it
+    0 with neighbours A = {1..d}; mark a vertex of largest degree within A,
+    relabel it 1 with neighbours {0} u {2..a+1} u {d+1..d+b}; then sum
+    n C(n-1, d) d C(d-1, a) C(n-1-d, b) P(G) / (k(G) k'(G)) over the graphs
+    with those neighbourhoods, no degree above d and no vertex of A above
+    vertex 1's degree (k: the vertices of degree d; k': those of A with
+    vertex 1's degree).  Checked here against plain enumeration of every
+    labelled graph, with the oracle deciding connectivity and the atomic class
+    (n = 4, 5: all classes; n = 6: connected graphs)."""
     from fractions import Fraction
     from math import comb
 
@@ -128,35 +131,43 @@ def test_marked_vertex_form_of_the_labelled_count():
         c = atoms.classify(A)
         return "connected" if c is None else ("regular" if c[0] else "irregular", "discrete" if c[1] else "continuous")
 
-    for n, full in ((5, True), (6, False)):
+    def add(acc, k, w):
+        acc[k] = acc.get(k, 0) + w
+        if k != "connected":
+            acc["connected"] = acc.get("connected", 0) + w
+
+    for n, full in ((4, True), (5, True), (6, False)):
         P = atoms.pairs(n)
         plain = {}
         for mask in range(1 << len(P)):
             k = key(atoms.adjacency(n, mask), full)
             if k is not None:
-                plain[k] = plain.get(k, 0) + 1
-                if k != "connected":
-                    plain["connected"] = plain.get("connected", 0) + 1
+                add(plain, k, 1)
         marked = {}
-        rest = [(i, j) for (i, j) in P if i > 0]
+        rest = [(i, j) for (i, j) in P if i >= 2]
         for d in range(1, n):
-            for sub in range(1 << len(rest)):
-                A = [[0] * n for _ in range(n)]
-                for j in range(1, d + 1):
-                    A[0][j] = A[j][0] = 1
-                for b, (i, j) in enumerate(rest):
-                    if (sub >> b) & 1:
-                        A[i][j] = A[j][i] = 1
-                deg = [sum(r) for r in A]
-                if max(deg[1:]) > d:
-                    continue
-                k = key(A, full)
-                if k is None:
-                    continue
-                w = Fraction(n * comb(n - 1, d), deg.count(d))
-                marked[k] = marked.get(k, 0) + w
-                if k != "connected":
-                    marked["connected"] = marked.get("connected", 0) + w
+            for a in range(d):
+                for b in range(n - d):
+                    if 1 + a + b > d:
+                        continue
+                    fac = n * comb(n - 1, d) * d * comb(d - 1, a) * comb(n - 1 - d, b)
+                    for sub in range(1 << len(rest)):
+                        A = [[0] * n for _ in range(n)]
+                        for j in range(1, d + 1):
+                            A[0][j] = A[j][0] = 1
+                        for j in list(range(2, a + 2)) + list(range(d + 1, d + 1 + b)):
+                            A[1][j] = A[j][1] = 1
+                        for bit, (i, j) in enumerate(rest):
+                            if (sub >> bit) & 1:
+                                A[i][j] = A[j][i] = 1
+                        deg = [sum(r) for r in A]
+                        if max(deg[1:]) > d or max(deg[1:d + 1]) > deg[1]:
+                            continue
+                        k = key(A, full)
+                        if k is None:
+                            continue
+                        kk = sum(1 for v in range(1, d + 1) if deg[v] == deg[1])
+                        add(marked, k, Fraction(fac, deg.count(d) * kk))
         assert marked == plain, (n, marked, plain)
 
 
