@@ -39,7 +39,7 @@ def _args():
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-multi", action="store_true")
     p.add_argument("--no-atoms", action="store_true")
-    p.add_argument("--atoms10", action="store_true", help="also the n = 10 atom census (about 11 s)")
+    p.add_argument("--no-atoms10", action="store_true", help="skip the n = 10 atom census (about 11 s)")
     p.add_argument("--no-lp", action="store_true")
     p.add_argument("--no-hyper", action="store_true")
     return p.parse_args()
@@ -346,10 +346,10 @@ def bench_er1000(reps, with_oracle=True):
     return out
 
 
-def bench_atoms(reps=3, with_n10=False):
-    """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..9 on the
-    device (and n = 10 on request); n = 8 and up timed.  Compared with the
-    table's rows (tests/golden)."""
+def bench_atoms(reps=3, with_n10=True):
+    """Census of GN atoms (Appendix A, Table atoms_10) for n = 1..10 on the
+    device; n = 8 and up timed.  Compared with the table's rows
+    (tests/golden)."""
     from paper_2605_05330_amd import libgn
     rows = {}
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "atoms_table.txt")) as f:
@@ -813,7 +813,7 @@ def main():
     if not a.no_warm:
         out["learned_warm_start"] = bench_warm(not a.no_cpu_baseline)
     if not a.no_atoms:
-        out["atom_census8"] = bench_atoms(with_n10=a.atoms10)
+        out["atom_census8"] = bench_atoms(with_n10=not a.no_atoms10)
     if not a.no_lp:
         out["lp_warm_start"] = bench_lp(not a.no_cpu_baseline)
     if not a.no_hyper:
