@@ -1,4 +1,4 @@
-// Census of GN atoms on connected graphs of up to 9 vertices (Appendix A,
+// Census of GN atoms on connected graphs of up to 10 vertices (Appendix A,
 // Table atoms_10).
 //
 // A fixed point of GN with full support on a connected graph is an atom; with
@@ -14,13 +14,15 @@
 //     (1/n!) sum over permutations p of #{labelled graphs fixed by p with it},
 // and conjugate permutations fix isomorphic families, so the sum runs over
 // cycle types with weights n!/z (z = prod_k k^{m_k} m_k!).  The graphs fixed
-// by p are the unions of the orbits of p on vertex pairs.  One GPU thread
-// evaluates one such graph: 2^28 labelled graphs for the identity at n = 8,
-// 2^36 at n = 9.
+// by p are the unions of the orbits of p on vertex pairs; one GPU thread
+// evaluates one such graph.  The identity fixes every labelled graph (2^45 at
+// n = 10); its term is taken in a marked-vertex form instead, which fixes the
+// neighbourhoods of two marked vertices and weights each graph by the number
+// of ways to mark it (atom_marked_weight): about 2.5e10 graphs at n = 10.
 //
 // Deciding atomicity exactly: fraction-free (Bareiss) elimination of [B | 1].
 // Every entry it produces is a minor of that 0/1 matrix (Sylvester's identity),
-// at most 144 in magnitude for size <= 9, so products stay below 2^24 and fp32
+// at most 320 in magnitude for size <= 10, so products stay below 2^24 and fp32
 // arithmetic is exact; each exact division is a multiply by the reciprocal and
 // a round to the nearest integer.  When B is invertible the graph is atomic iff
 // every component of B^-1 1 is positive.  When B is singular, the set
@@ -28,7 +30,10 @@
 // point of P is positive iff the supports of P's vertices cover every vertex of
 // the graph (the mean of one positive-in-i vertex per i is in P and positive).
 // The vertices are the non-negative basic solutions: for every set S of
-// rank(B) independent columns with B_S x_S = 1 solvable, x_S >= 0.
+// rank(B) independent columns with B_S x_S = 1 solvable, x_S >= 0.  Exact
+// shortcuts before that search: nested closed neighbourhoods rule an atom out,
+// twins reduce the system to the twin quotient's, and a system of nullity one
+// is decided on its line of solutions (gn_atoms.h).
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -44,7 +49,7 @@ constexpr uint64_t kAtomChunk = 1ull << 24;  // graphs per first-pass launch (qu
 static_assert(kAtomChunk <= (1ull << 24), "queue entries hold a graph's index within its chunk in 24 bits");
 
 // Bytes of a graph index (one bit per orbit on vertex pairs): at most
-// n(n - 1)/2 orbits, 36 at n = 9.
+// n(n - 1)/2 orbits, 45 at n = 10.
 constexpr int kAtomTabBytes = (kAtomMaxN * (kAtomMaxN - 1) / 2 + 7) / 8;
 
 template <int N>
