@@ -414,7 +414,7 @@ __host__ __device__ inline void atom_evaluate(const AtomRowsT<N> rows, unsigned 
 // One cycle type of the permutations of n vertices: its weight n!/z (the
 // number of permutations of that type) and the orbits of a representative
 // permutation on vertex pairs, each as adjacency rows packed at the stride of n
-// (AtomRows; 128 bits hold every n up to 9, and for n <= 8 the low 64 are the
+// (AtomRows; 128 bits hold every n up to 10, and for n <= 8 the low 64 are the
 // packed rows themselves).
 struct AtomCycleType {
     long long weight;
