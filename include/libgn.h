@@ -625,9 +625,11 @@ gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t*
 gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t starts, float* x, uint8_t* sel,
                                gn_result* res, int32_t* best, hipStream_t stream);
 
-/* Tuning: number of step launches captured in one replayed chain by gn_solve and
- * gn_rook_solve (default 32, 1..4096).  A longer chain checks the stop flag less
- * often from the host; results do not change.  Process-wide; not thread-safe. */
+/* Tuning: number of step launches captured in one replayed chain by gn_solve,
+ * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  A longer chain checks
+ * the stop flag less often from the host and rebuilds the pruned lists less
+ * often; once the solve has stopped, the launches left in the chains in flight
+ * return at once.  Results do not change.  Process-wide; not thread-safe. */
 gn_status gn_set_chunk_len(int32_t len);
 
 /* Tuning: gn_solve runs a graph with nnz + 2 n <= work_max (0 .. 1048576, the

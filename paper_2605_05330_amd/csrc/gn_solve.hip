@@ -293,7 +293,7 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hi
     return e == hipSuccess ? GN_OK : GN_E_HIP;
 }
 
-int32_t g_chunk_len = 32;
+int32_t g_chunk_len = 64;
 int32_t g_prune = 1;
 
 gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream) {

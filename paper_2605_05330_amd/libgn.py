@@ -300,6 +300,9 @@ def gn_check_independent(h, sel, stream=None) -> tuple[int, int]:
     return c.value, u.value
 
 
+CHUNK_LEN_DEFAULT = 64   # the library's default chain length (gn_set_chunk_len)
+
+
 def gn_set_chunk_len(length: int):
     _check(lib().gn_set_chunk_len(int(length)), "gn_set_chunk_len")
 

@@ -125,7 +125,7 @@ def test_chunk_length_bounds():
     L = libgn.lib()
     assert L.gn_set_chunk_len(0) == libgn.GN_E_ARG
     assert L.gn_set_chunk_len(4097) == libgn.GN_E_ARG
-    assert L.gn_set_chunk_len(32) == libgn.GN_OK
+    assert L.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT) == libgn.GN_OK
     assert L.gn_set_small_graph_limit(-1) == libgn.GN_E_ARG
     assert L.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT + 1) == libgn.GN_E_ARG
     assert L.gn_set_small_graph_limit(20000) == libgn.GN_OK

@@ -280,7 +280,7 @@ def test_multi_handoff_same_bits(gpu, case):
                          x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
         a, b = outs
         steps = sorted(r[0] for r in a[1])
-        assert steps[-1] > steps[-2] + 3 * 33, steps   # one start ran alone for more than two chains
+        assert steps[-1] > steps[-2] + 3 * libgn.CHUNK_LEN_DEFAULT, steps   # one start ran alone for over two chains
         late = int(np.argmax([r[0] for r in a[1]]))
         assert a[1][late][1] == (case != "budget")
         assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
@@ -294,4 +294,4 @@ def test_multi_handoff_same_bits(gpu, case):
         assert np.array_equal(x.cpu().numpy().view(np.uint32), a[3][late * g.n:(late + 1) * g.n])
     finally:
         libgn.gn_set_multi_handoff(True)
-        libgn.gn_set_chunk_len(32)
+        libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)

@@ -437,7 +437,7 @@ def test_solve_independent_of_chain_length(gpu):
             r = G.solve(x, sel, **SCHED_RAMP)
             outs.append((r.steps, r.fallback_count, x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
     finally:
-        libgn.gn_set_chunk_len(32)
+        libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)
         libgn.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT)
     for o in outs[1:]:
         assert o[0] == outs[0][0] and o[1] == outs[0][1]
