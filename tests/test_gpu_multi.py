@@ -235,7 +235,7 @@ def test_multi_zero_steps(gpu):
     assert np.array_equal(sel.cpu().numpy().astype(bool), xn > 0.5)
 
 
-@pytest.mark.parametrize("case", ["late", "budget", "n2900", "check_every_5", "chain_33"])
+@pytest.mark.parametrize("case", ["late", "budget", "n2900", "check_every_5", "chain_33", "pruned"])
 def test_multi_handoff_same_bits(gpu, case):
     """Once a single start is left running, gn_multi_solve hands it to the
     single-start chained solve at a chain boundary.  With and without the
@@ -245,8 +245,9 @@ def test_multi_handoff_same_bits(gpu, case):
     happens: the uniform start ½ binarises thousands of steps after the others
     (late) or reaches the step budget (budget), or a random start binarises
     ~700 steps after the others on a larger graph (n2900); the first again
-    with the test every 5 steps, and with chains of 33 steps (the hand-off at
-    an odd step)."""
+    with the test every 5 steps, with chains of 33 steps (the hand-off at an
+    odd step), and with the pruned lists of both solves forced on (the
+    single-start chains rebuild theirs from the state handed over)."""
     import torch
     libgn = _lib()
     sched = dict(RAMP, max_steps=4000)
@@ -270,6 +271,8 @@ def test_multi_handoff_same_bits(gpu, case):
     try:
         if case == "chain_33":
             libgn.gn_set_chunk_len(33)
+        if case == "pruned":
+            libgn.gn_set_pruning(libgn.PRUNE_ALWAYS)
         for on in (True, False):
             libgn.gn_set_multi_handoff(on)
             x = x0.clone()
@@ -295,3 +298,4 @@ def test_multi_handoff_same_bits(gpu, case):
     finally:
         libgn.gn_set_multi_handoff(True)
         libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)
+        libgn.gn_set_pruning(libgn.PRUNE_WHERE_IT_PAYS)
