@@ -627,10 +627,20 @@ gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t star
 
 /* Tuning: number of step launches captured in one replayed chain by gn_solve,
  * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  A longer chain checks
- * the stop flag less often from the host and rebuilds the pruned lists less
- * often; once the solve has stopped, the launches left in the chains in flight
- * return at once.  Results do not change.  Process-wide; not thread-safe. */
+ * the stop flag less often from the host; once the solve has stopped, the
+ * launches left in the chains in flight return at once, so a shorter chain
+ * wastes fewer of them.  Results do not change.  Process-wide; not
+ * thread-safe. */
 gn_status gn_set_chunk_len(int32_t len);
+
+/* Tuning: steps between rebuilds of the pruned neighbour lists
+ * (gn_set_pruning) in gn_solve and gn_multi_solve (default 64, 1..4096).  The
+ * first chain of step launches rebuilds them, and so does each chain that
+ * starts at or first after a multiple of this interval; a chain longer than
+ * the interval rebuilds once.  Fewer rebuilds cost less upkeep and leave more
+ * decayed vertices listed (gathered, adding nothing).  Results do not change.
+ * GN_E_ARG outside 1..4096.  Process-wide; not thread-safe. */
+gn_status gn_set_prune_interval(int32_t steps);
 
 /* Tuning: gn_solve runs a graph with nnz + 2 n <= work_max (0 .. 1048576, the
  * default) in one workgroup and one launch when the graph has an LDS image that
@@ -649,7 +659,8 @@ gn_status gn_set_small_graph_limit(int32_t work_max);
  * column lists in which the entries of vertices that are not ordinary -- most
  * of the graph once the non-selected vertices have decayed -- are marked
  * absent and not gathered.  Vertices that stopped being ordinary are dropped
- * before each replayed chain of step launches (gn_set_chunk_len); a vertex
+ * at rebuilds between replayed chains of step launches
+ * (gn_set_prune_interval); a vertex
  * whose state becomes ordinary again is put back into its neighbours' lists by
  * the step that produces that state, before any step reads it.  mode 0: never;
  * 1 (the default): on graphs whose gathers have little cache-line locality in

@@ -12,11 +12,17 @@
 namespace {
 
 // Final state: x = clamp(|y| / v, 0, 1), S = {x > 1/2}; outputs in user order.
+// `pick` (may be null) supplies y, or says that nothing is to be written.
 __global__ void finalize_kernel(int32_t n, const float* __restrict__ y, const float* __restrict__ v,
                                 const int32_t* __restrict__ perm, float* __restrict__ x_user,
-                                uint8_t* __restrict__ sel_user, uint8_t* __restrict__ sel_int) {
+                                uint8_t* __restrict__ sel_user, uint8_t* __restrict__ sel_int,
+                                const FinalPick* __restrict__ pick) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (pick) {
+        if (pick->skip) return;
+        y = pick->y;
+    }
     float x = gnk::x_of_word(y[i], v[i]);
     x = fminf(fmaxf(x, 0.0f), 1.0f);
     const uint8_t s = x > 0.5f ? 1 : 0;
@@ -40,8 +46,13 @@ __global__ __launch_bounds__(kBlock) void set_stats_kernel(int32_t n, int32_t li
                                                           const float* __restrict__ v,
                                                           const float* __restrict__ w_int,
                                                           const float* __restrict__ y,  // may be null
-                                                          const uint8_t* __restrict__ sel, Partial* out) {
+                                                          const uint8_t* __restrict__ sel, Partial* out,
+                                                          const FinalPick* __restrict__ pick) {  // may be null
     Partial p{0.0, 0.0, 0, 0, 0, INFINITY, 0};
+    if (pick) {
+        if (pick->skip) return;  // the reduction then reads stale partials, unused
+        y = pick->y;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     auto row_tail = [&](int i, long long conf, bool any_sel, float vsum) {
         const bool in_s = sel[i] != 0;
@@ -127,7 +138,7 @@ gn_status ensure_partials(const gn_graph* g, int64_t count) {
 // Set statistics of sel_int (and the relaxed objective of y when given), reduced
 // into dev_out on the device; no host synchronisation.
 gn_status launch_set_stats(const gn_graph* g, const float* y, const uint8_t* sel_int, float gamma,
-                           FinalStats* dev_out, hipStream_t s) {
+                           FinalStats* dev_out, hipStream_t s, const FinalPick* pick = nullptr) {
     const int n = g->n;
     const int light_begin = g->bins.row_begin[BIN_LANE32];
     const int heavy_blocks = (light_begin + kWaves - 1) / kWaves;
@@ -138,10 +149,11 @@ gn_status launch_set_stats(const gn_graph* g, const float* y, const uint8_t* sel
     Partial* part = (Partial*)g->ws.partials;
     if (nb > 0) {
         hipLaunchKernelGGL(set_stats_kernel, dim3(nb), dim3(kBlock), 0, s, n, light_begin, heavy_blocks, g->row_ptr,
-                           g->col, g->v, g->w_int, y, sel_int, part);
+                           g->col, g->v, g->w_int, y, sel_int, part, pick);
         GN_HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, nb, (const Partial*)part, gamma, dev_out);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, nb, (const Partial*)part, gamma, dev_out,
+                       pick);
     GN_HIP_TRY(hipGetLastError());
     return GN_OK;
 }
@@ -159,9 +171,18 @@ gn_status gn_internal_final_stats_launch(gn_graph* g, const float* y_fin, float 
                                          uint8_t* sel_user, FinalStats* dev_out, hipStream_t s) {
     const int n = g->n;
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, y_fin, g->v, g->perm, x_user,
-                       sel_user, g->ws.sel_int);
+                       sel_user, g->ws.sel_int, (const FinalPick*)nullptr);
     GN_HIP_TRY(hipGetLastError());
     return launch_set_stats(g, y_fin, g->ws.sel_int, gamma_fin, dev_out, s);
+}
+
+gn_status gn_internal_final_stats_picked(gn_graph* g, const FinalPick* pick, float* x_user, uint8_t* sel_user,
+                                         FinalStats* dev_out, hipStream_t s) {
+    const int n = g->n;
+    hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, (const float*)nullptr, g->v,
+                       g->perm, x_user, sel_user, g->ws.sel_int, pick);
+    GN_HIP_TRY(hipGetLastError());
+    return launch_set_stats(g, nullptr, g->ws.sel_int, 0.0f, dev_out, s, pick);
 }
 
 gn_status gn_internal_final_stats(gn_graph* g, const float* y_fin, float gamma_fin, float* x_user, uint8_t* sel_user,
@@ -196,7 +217,7 @@ extern "C" gn_status gn_objective(const gn_graph* g, const float* x, double* out
     hipLaunchKernelGGL(objective_kernel, dim3(nb), dim3(kBlock), 0, stream, g->n, (const float*)g->w_user, x, part);
     GN_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, stream, nb, (const Partial*)part, 1.0f,
-                       (FinalStats*)g->ws.final_out);
+                       (FinalStats*)g->ws.final_out, (const FinalPick*)nullptr);
     GN_HIP_TRY(hipGetLastError());
     GN_HIP_TRY(hipMemcpyAsync(g->ws.host_pinned, g->ws.final_out, sizeof(FinalStats), hipMemcpyDeviceToHost, stream));
     GN_HIP_TRY(hipStreamSynchronize(stream));

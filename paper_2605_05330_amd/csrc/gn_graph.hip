@@ -147,8 +147,7 @@ static void free_graph_buffers(gn_graph* g) {
     f(g->sl_col); f(g->sl_off);
     f(g->prune); f(g->prune_mloc); f(g->listed); f(g->prune_mirror);
     GraphWorkspace& ws = g->ws;
-    for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
-    ws.chunks.clear();
+    ws.destroy_chains();
     f(ws.y[0]); f(ws.y[1]); f(ws.state); f(ws.notconv); f(ws.gamma); f(ws.sel_int);
     f(ws.partials); f(ws.final_out);
     if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
@@ -471,7 +470,7 @@ gn_status gn_internal_ensure_ws(gn_graph* g, int32_t steps_needed) {
         gn_status st;
         if ((st = dev_alloc(&ws.y[0], (size_t)n)) || (st = dev_alloc(&ws.y[1], (size_t)n)) ||
             (st = dev_alloc(&ws.state, 1)) || (st = dev_alloc(&ws.sel_int, (size_t)n)) ||
-            (st = dev_alloc((FinalStats**)&ws.final_out, 1)))
+            (st = dev_alloc((SolveTail**)&ws.final_out, 1)))
             return st;
         if (hipHostMalloc(&ws.host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
             ws.host_pinned = nullptr;

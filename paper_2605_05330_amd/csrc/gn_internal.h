@@ -30,7 +30,16 @@ struct GraphWorkspace {
     void* host_pinned = nullptr;  // pinned staging for SolveState / statistics
     std::vector<hipGraphExec_t> chunks;  // captured step chains, chunk c covers steps [c*C, (c+1)*C)
     int32_t chunk_len = 0;
-    int32_t chunk_prune = -1;            // whether the captured chains read the pruned lists
+    int32_t chunk_prune = -1;            // captured chains' lists: 0 full, else the pruned lists' rebuild interval
+    hipEvent_t chain_ev[2] = {nullptr, nullptr};  // completion events of the chains in flight (created on first use)
+    void destroy_chains() {
+        for (auto ex : chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        chunks.clear();
+        for (auto& e : chain_ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    }
 };
 
 struct gn_graph {
@@ -76,6 +85,27 @@ struct FinalStats {
     int32_t pad;
 };
 
+// A solve's outcome, decided on the device after its last step (gn_solve): the
+// step count, whether the state binarised, the final state words and the gamma
+// of the final step; `skip` is set when the solve failed its input checks, and
+// then the final-state kernels write nothing.
+struct FinalPick {
+    const float* y;
+    float gamma;
+    int32_t steps;
+    int32_t binarised;
+    int32_t skip;
+};
+
+// The block gn_solve's epilogue fills on the device and the host reads back in
+// one copy (the workspace's final_out; the statistics come first, where the
+// other callers of final_out read them).
+struct SolveTail {
+    FinalStats stats;
+    FinalPick pick;
+    SolveState state;
+};
+
 // Validation of clique (hyperedge) constraints given on the host: clique k is
 // members[ptr[k] .. ptr[k+1]-1], non-empty, ids strictly increasing in [0, n);
 // every vertex in some clique; w finite and > 0.  cover receives each vertex's
@@ -108,6 +138,10 @@ gn_status gn_internal_final_stats_launch(gn_graph* g, const float* y_fin, float 
                                          uint8_t* sel_user, FinalStats* dev_out, hipStream_t s);
 gn_status gn_internal_sel_stats(const gn_graph* g, const uint8_t* sel_user, FinalStats* host_out,
                                 hipStream_t s);
+// same, for the final state and gamma that `pick` (device memory) names; writes
+// nothing when pick->skip is set
+gn_status gn_internal_final_stats_picked(gn_graph* g, const FinalPick* pick, float* x_user, uint8_t* sel_user,
+                                         FinalStats* dev_out, hipStream_t s);
 int32_t gn_internal_grid_blocks(const BinLayout& b);
 // gn_step's argument checks, and its work (x_in -> state words in y_words, n
 // floats; one step launch writing x_out) on a caller-chosen word buffer
@@ -121,25 +155,42 @@ gn_status gn_internal_step_with(const gn_graph* g, float gamma, const float* x_i
 // replay of captured step chains, the stopping outcome and the result record
 extern int32_t g_chunk_len;
 extern int32_t g_prune;  // pruned lists in chained solves: 0 never, 1 where they pay, 2 always (gn_set_pruning)
+extern int32_t g_prune_every;  // steps between rebuilds of the pruned lists (gn_set_prune_interval)
+// Whether chain c of length C rebuilds the pruned lists before its first step:
+// the first chain does, and so does each chain whose first step s is the
+// first chain start at or after a multiple of the rebuild interval (one lies
+// in (s - C, s]).
+inline bool gn_internal_chain_rebuilds(int32_t c, int32_t C) {
+    const int64_t s = (int64_t)c * C;
+    return c == 0 || s / g_prune_every != (s - C) / g_prune_every;
+}
 float gn_internal_host_gamma(const gn_schedule* s, int32_t k);
 bool gn_internal_schedule_ok(const gn_schedule* sch);
 gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream);
-// Optional hooks of gn_internal_run_chunks: after_launch(c) enqueues more work
-// after chain c, ahead of its completion event; stop_after(c) is asked once
-// chain c has completed (chain c + 1 is then in flight) and returns true to
-// launch no further chain.  *last receives the last chain launched.
+// Optional hooks of gn_internal_run_chunks: when pin_src is set, each chain's
+// last node also copies pin_words words from pin_src to the pinned block at
+// byte offset pin_offset + 4 pin_words (c & 1) for chain c; stop_after(c) is
+// asked once chain c has completed (chain c + 1 is then in flight) and returns
+// true to launch no further chain.  *last receives the last chain launched.
 struct ChunkHooks {
-    std::function<gn_status(int32_t)> after_launch;
+    const void* pin_src = nullptr;
+    int32_t pin_words = 0;
+    size_t pin_offset = 0;
     std::function<bool(int32_t)> stop_after;
 };
-gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
-                                 const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
+// The chains' builder adds chain c's nodes to `graph`, each after the one
+// before, and returns the last one in *tail (nullptr for an empty chain).
+using ChainBuilder = std::function<gn_status(int32_t c, hipGraph_t graph, hipGraphNode_t* tail)>;
+// With sync_end the call returns once every launched chain has completed;
+// without it the stream is left running (the caller enqueues more work).
+gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C, const ChainBuilder& build,
                                  hipStream_t stream, int32_t c_begin = 0, const ChunkHooks* hooks = nullptr,
-                                 int32_t* last = nullptr);
+                                 int32_t* last = nullptr, bool sync_end = true);
 // The chained single-start solve of g from chain c_begin on: ws.y[(c_begin C) & 1]
 // holds the state at step c_begin C (C = g_chunk_len), and the solve state and
 // flags are set up (gn_solve.hip).
-gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream);
+gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream,
+                                  bool sync_end = true);
 // multi-start solves hand their last running start to the single-start chains (gn_set_multi_handoff)
 extern int32_t g_multi_handoff;
 gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_t* steps, bool* binarised);

@@ -616,13 +616,12 @@ struct MultiWS {
     int32_t heavy_end = 0, mid_end = 0, l16_begin = 0, mid_blk = 0, light_blk = 0, l16_blk = 0, nblk = 0;
     int32_t* pcol = nullptr;      // pruned lists (allocated on first use): a copy of the CSR columns
     uint8_t* listed = nullptr;    // [n]
-    int32_t chunk_prune = -1;     // whether the captured chains read the pruned lists
+    int32_t chunk_prune = -1;     // captured chains' lists: 0 full, else the pruned lists' rebuild interval
 };
 
 void free_ws(MultiWS* m) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
-    for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
-    m->ws.chunks.clear();
+    m->ws.destroy_chains();
     f(m->Y[0]); f(m->Y[1]); f(m->yb); f(m->done); f(m->fb); f(m->nc16); f(m->maxbits); f(m->stats);
     f(m->pcol); f(m->listed);
     f(m->ws.state); f(m->ws.notconv); f(m->ws.gamma);
@@ -679,12 +678,11 @@ gn_status ensure_tables(MultiWS* m, int32_t steps) {
     return GN_OK;
 }
 
-gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, bool prune, hipGraphExec_t* out) {
+gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, bool prune, hipGraph_t graph,
+                      hipGraphNode_t* tail) {
     if (prune && (!m->pcol || !m->listed || !g->prune_mirror)) return GN_E_ARG;  // no pruned lists to read
-    hipGraph_t graph;
-    GN_HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
-    if (prune) {  // rebuild of the lists from the chain's input state
+    if (prune && gn_internal_chain_rebuilds(c, len)) {  // rebuild of the lists from the chain's input state
         int32_t n = g->n;
         const int32_t* rp = g->row_ptr;
         const int32_t* mi = g->prune_mirror;
@@ -699,10 +697,7 @@ gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, boo
         p.sharedMemBytes = 0;
         p.kernelParams = args;
         p.extra = nullptr;
-        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return GN_E_HIP;
-        }
+        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) return GN_E_HIP;
     }
     for (int32_t q = 0; q < len; ++q) {
         MultiArgs a{};
@@ -740,15 +735,12 @@ gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, boo
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node;
-        if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) {
-            (void)hipGraphDestroy(graph);
+        if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
             return GN_E_HIP;
-        }
         prev = node;
     }
-    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    return e == hipSuccess ? GN_OK : GN_E_HIP;
+    *tail = prev;
+    return GN_OK;
 }
 
 }  // namespace
@@ -817,10 +809,10 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
         GN_HIP_TRY(hipMemcpyAsync(m->pcol, g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToDevice, stream));
         GN_HIP_TRY(hipMemsetAsync(m->listed, 1, (size_t)n, stream));
     }
-    if (m->chunk_prune != (prune ? 1 : 0)) {  // chains captured for the other kind of lists
+    if (m->chunk_prune != (prune ? g_prune_every : 0)) {  // chains captured for other lists or rebuild interval
         for (auto ex : m->ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
         m->ws.chunks.clear();
-        m->chunk_prune = prune ? 1 : 0;
+        m->chunk_prune = prune ? g_prune_every : 0;
     }
     // Hand-off: once a single start is left running, the 16-start step costs as
     // much as ever for it alone.  Its state moves at a chain boundary to the
@@ -829,12 +821,13 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
     char* hp = (char*)m->ws.host_pinned;
     volatile int32_t* run = (volatile int32_t*)(hp + kPinRun);  // per chain slot: done step of each start
     int32_t handoff = -1;  // the start handed over
+    // Each chain's last node copies the starts' done steps to `run`, in every
+    // call, since later calls replay the same captured chains.
     ChunkHooks hooks;
+    hooks.pin_src = m->done;
+    hooks.pin_words = kStarts;
+    hooks.pin_offset = kPinRun;
     if (g_multi_handoff && starts > 1) {
-        hooks.after_launch = [m, run, stream](int32_t c) {
-            return hipMemcpyAsync((void*)(run + kStarts * (c & 1)), m->done, kStarts * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, stream) == hipSuccess ? GN_OK : GN_E_HIP;
-        };
         hooks.stop_after = [run, starts, nchunks, &handoff](int32_t c) {
             if (c + 2 >= nchunks) return false;  // chain c + 1 (in flight) is the last or next to last
             int left = 0, who = -1;
@@ -851,8 +844,10 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
     int32_t last = -1;
     st = gn_internal_run_chunks(
         m->ws, nchunks, C,
-        [g, m, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, m, c, C, prune, out); }, stream, 0,
-        &hooks, &last);
+        [g, m, C, prune](int32_t c, hipGraph_t graph, hipGraphNode_t* tail) {
+            return build_chunk(g, m, c, C, prune, graph, tail);
+        },
+        stream, 0, &hooks, &last);
     if (st != GN_OK) return st;
 
     // solve state, per-start outcomes and the last step's flags in one round trip

@@ -552,8 +552,7 @@ static void rook_free(gn_rook* r) {
     f(r->w); f(r->v); f(r->rpart[0]); f(r->rpart[1]); f(r->cpart[0]); f(r->cpart[1]); f(r->rsum); f(r->csum);
     f(r->rcnt); f(r->ccnt); f(r->rvs); f(r->cvs); f(r->colpart_cnt); f(r->colpart_vs); f(r->partials);
     GraphWorkspace& ws = r->ws;
-    for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
-    ws.chunks.clear();
+    ws.destroy_chains();
     f(ws.y[0]); f(ws.y[1]); f(ws.state); f(ws.notconv); f(ws.gamma); f(ws.final_out);
     if (ws.host_pinned) (void)hipHostFree(ws.host_pinned);
 }
@@ -697,10 +696,8 @@ extern "C" gn_status gn_rook_step(gn_rook* r, float gamma, const float* x_in, fl
     return GN_OK;
 }
 
-static gn_status rook_build_chunk(gn_rook* r, int32_t c, int32_t len, hipGraphExec_t* out) {
+static gn_status rook_build_chunk(gn_rook* r, int32_t c, int32_t len, hipGraph_t graph, hipGraphNode_t* tail) {
     GraphWorkspace& ws = r->ws;
-    hipGraph_t graph;
-    GN_HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
     for (int32_t q = 0; q < len; ++q) {
         RookArgs a = rook_args(r);
@@ -725,16 +722,12 @@ static gn_status rook_build_chunk(gn_rook* r, int32_t c, int32_t len, hipGraphEx
             p.kernelParams = args;
             p.extra = nullptr;
             hipGraphNode_t node;
-            if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return GN_E_HIP;
-            }
+            if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) return GN_E_HIP;
             prev = node;
         }
     }
-    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    return e == hipSuccess ? GN_OK : GN_E_HIP;
+    *tail = prev;
+    return GN_OK;
 }
 
 static gn_status rook_final_stats(gn_rook* r, const float* y, float gamma_fin, float* x, uint8_t* sel,
@@ -758,7 +751,8 @@ static gn_status rook_final_stats(gn_rook* r, const float* y, float gamma_fin, f
                        r->partials + nbr + nbc);
     GN_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, r->npartials,
-                       (const Partial*)r->partials, gamma_fin, (FinalStats*)r->ws.final_out);
+                       (const Partial*)r->partials, gamma_fin, (FinalStats*)r->ws.final_out,
+                       (const FinalPick*)nullptr);
     GN_HIP_TRY(hipGetLastError());
     GN_HIP_TRY(hipMemcpyAsync(r->ws.host_pinned, r->ws.final_out, sizeof(FinalStats), hipMemcpyDeviceToHost, s));
     GN_HIP_TRY(hipStreamSynchronize(s));
@@ -780,7 +774,9 @@ extern "C" gn_status gn_rook_solve(gn_rook* r, const gn_schedule* sch, float* x,
     if ((st = gn_internal_init_solve(ws, sch, stream)) != GN_OK) return st;
     if ((st = rook_prep(r, x, ws.state, stream)) != GN_OK) return st;
     st = gn_internal_run_chunks(ws, nchunks, C,
-                                [r, C](int32_t c, hipGraphExec_t* out) { return rook_build_chunk(r, c, C, out); },
+                                [r, C](int32_t c, hipGraph_t graph, hipGraphNode_t* tail) {
+                                    return rook_build_chunk(r, c, C, graph, tail);
+                                },
                                 stream);
     if (st != GN_OK) return st;
     int32_t steps;

@@ -42,6 +42,43 @@ __global__ void normalizable_kernel(int32_t n, const int32_t* __restrict__ row_p
     atomicOr(&st->err, 2);
 }
 
+// Copies the solve state's done step and error word, and optionally a second
+// run of words, to pinned host memory with system-scope stores.  It is the last
+// node of every captured chain, so the flags travel inside the chain: a copy
+// enqueued between two chains costs the stream a gap of several microseconds.
+__global__ void pin_copy_kernel(const int32_t* __restrict__ st, int32_t* dst, const int32_t* __restrict__ src2,
+                                int32_t words2, int32_t* dst2) {
+    const int t = threadIdx.x;
+    if (t < 2) __hip_atomic_store(dst + t, st[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (int i = t; i < words2; i += blockDim.x)
+        __hip_atomic_store(dst2 + i, src2[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
+// A solve's outcome after its last step, as gn_internal_solve_outcome decides
+// it on the host: the stop's step when the stopping test passed, else max_steps,
+// binarised when that last state passed the test; the final state words are
+// y[steps & 1] and its gamma the table's entry for that step.
+__global__ void pick_final_kernel(const SolveState* __restrict__ st, const int32_t* __restrict__ notconv,
+                                  int32_t ms, const float* __restrict__ gamma, const float* y0, const float* y1,
+                                  SolveTail* tail) {
+    if (threadIdx.x != 0) return;
+    const SolveState s = *st;
+    FinalPick p;
+    if (s.done_step >= 0) {
+        p.steps = s.done_step;
+        p.binarised = 1;
+    } else {
+        p.steps = ms;
+        p.binarised = ms >= 1 && notconv[ms] == 0;
+    }
+    p.y = (p.steps & 1) ? y1 : y0;
+    p.gamma = gamma[p.steps];
+    p.skip = s.err != 0;
+    tail->pick = p;
+    tail->state = s;
+}
+
 // Reset the solve state and fill the gamma table (Section 6 gamma-pursuit,
 // evaluated in double and rounded once to fp32).
 __global__ void init_solve_kernel(SolveState* st, int32_t* notconv, float* gamma, int32_t max_steps,
@@ -92,9 +129,9 @@ gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hip
     return GN_OK;
 }
 
-gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
-                                 const std::function<gn_status(int32_t, hipGraphExec_t*)>& build,
-                                 hipStream_t stream, int32_t c_begin, const ChunkHooks* hooks, int32_t* last) {
+gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C, const ChainBuilder& build,
+                                 hipStream_t stream, int32_t c_begin, const ChunkHooks* hooks, int32_t* last,
+                                 bool sync_end) {
     if (ws.chunk_len != C) {
         for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
         ws.chunks.clear();
@@ -102,27 +139,54 @@ gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
     }
     if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
     volatile int32_t* pin = (volatile int32_t*)ws.host_pinned;  // [slot][done_step, err]
-    hipEvent_t ev[2];
-    GN_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
-        (void)hipEventDestroy(ev[0]);
-        return GN_E_HIP;
-    }
+    char* pin_dev = nullptr;  // the same block as the device addresses it
+    GN_HIP_TRY(hipHostGetDevicePointer((void**)&pin_dev, ws.host_pinned, 0));
+    // chain c with its flag copy as the last node
+    auto instantiate = [&](int32_t c, hipGraphExec_t* out) -> gn_status {
+        hipGraph_t graph;
+        GN_HIP_TRY(hipGraphCreate(&graph, 0));
+        hipGraphNode_t tail = nullptr;
+        gn_status st = build(c, graph, &tail);
+        if (st == GN_OK) {
+            const int32_t* s0 = (const int32_t*)ws.state;
+            int32_t* d0 = (int32_t*)pin_dev + 2 * (c & 1);
+            const bool extra = hooks && hooks->pin_src;
+            const int32_t* s2 = extra ? (const int32_t*)hooks->pin_src : nullptr;
+            int32_t w2 = extra ? hooks->pin_words : 0;
+            int32_t* d2 = extra ? (int32_t*)(pin_dev + hooks->pin_offset) + (size_t)w2 * (c & 1) : nullptr;
+            void* args[] = {&s0, &d0, &s2, &w2, &d2};
+            hipKernelNodeParams p{};
+            p.func = (void*)pin_copy_kernel;
+            p.gridDim = dim3(1);
+            p.blockDim = dim3(64);
+            p.sharedMemBytes = 0;
+            p.kernelParams = args;
+            p.extra = nullptr;
+            hipGraphNode_t node;
+            if (hipGraphAddKernelNode(&node, graph, tail ? &tail : nullptr, tail ? 1 : 0, &p) != hipSuccess ||
+                hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess)
+                st = GN_E_HIP;
+        }
+        (void)hipGraphDestroy(graph);
+        return st;
+    };
+    // per-workspace events: a call that returns with chains still in flight
+    // leaves them recorded
+    for (auto& e : ws.chain_ev)
+        if (!e) GN_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipEvent_t* ev = ws.chain_ev;
     gn_status rs = GN_OK;
     int32_t launched = c_begin - 1;
     for (int32_t c = c_begin; c < nchunks && rs == GN_OK; ++c) {
         if (!ws.chunks[c]) {
-            rs = build(c, &ws.chunks[c]);
+            rs = instantiate(c, &ws.chunks[c]);
             if (rs != GN_OK) break;
         }
-        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess ||
-            hipMemcpyAsync((void*)(pin + 2 * (c & 1)), ws.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           stream) != hipSuccess) {
+        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess) {
             rs = GN_E_HIP;
             break;
         }
         launched = c;
-        if (hooks && hooks->after_launch && (rs = hooks->after_launch(c)) != GN_OK) break;
         if (hipEventRecord(ev[c & 1], stream) != hipSuccess) {
             rs = GN_E_HIP;
             break;
@@ -138,10 +202,8 @@ gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C,
         }
     }
     if (last) *last = launched;
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     if (rs != GN_OK) return rs;
-    GN_HIP_TRY(hipStreamSynchronize(stream));
+    if (sync_end) GN_HIP_TRY(hipStreamSynchronize(stream));
     return GN_OK;
 }
 
@@ -162,10 +224,8 @@ gn_status gn_internal_solve_outcome(const GraphWorkspace& ws, int32_t ms, int32_
     return GN_OK;
 }
 
-gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
-                                  gn_result* res) {
-    SolveState hs;
-    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+static gn_status fill_result(const SolveState& hs, int32_t steps, bool binarised, const FinalStats& fs,
+                             gn_result* res) {
     res->steps = steps;
     res->binarised = binarised ? 1 : 0;
     res->fallback_count = (int64_t)hs.fallback;
@@ -176,6 +236,13 @@ gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool 
     res->uncovered = fs.uncovered;
     res->stab = fs.stab;
     return binarised ? GN_OK : GN_NOT_CONVERGED;
+}
+
+gn_status gn_internal_fill_result(const GraphWorkspace& ws, int32_t steps, bool binarised, const FinalStats& fs,
+                                  gn_result* res) {
+    SolveState hs;
+    GN_HIP_TRY(hipMemcpy(&hs, ws.state, sizeof(hs), hipMemcpyDeviceToHost));
+    return fill_result(hs, steps, binarised, fs, res);
 }
 
 static StepArgs base_args(const gn_graph* g) {
@@ -224,17 +291,17 @@ extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, 
     return gn_internal_step_with(g, gamma, x_in, x_out, g->ws.y[0], stream);
 }
 
-// Captured chain of `len` step launches for steps [c*len, (c+1)*len), after a
-// rebuild of the pruned lists from the chain's input state when they are used
-// (the first chain's rebuild sets the lists for the solve's start).
-static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hipGraphExec_t* out) {
+// Captured chain of `len` step launches for steps [c*len, (c+1)*len).  When the
+// pruned lists are used, chains that begin the solve or cross a multiple of the
+// rebuild interval first rebuild them from the chain's input state (the first
+// chain's rebuild sets the lists for the solve's start).
+static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hipGraph_t graph,
+                             hipGraphNode_t* tail) {
     GraphWorkspace& ws = g->ws;
     if (prune && (!g->prune || !g->prune_mloc || !g->listed)) return GN_E_ARG;  // no pruned lists to read
-    hipGraph_t graph;
-    GN_HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
     const int nblk = gn_internal_grid_blocks(g->bins);
-    if (prune) {
+    if (prune && gn_internal_chain_rebuilds(c, len)) {
         int32_t n = g->n;
         const int32_t* rp = g->row_ptr;
         const int32_t* ml = g->prune_mloc;
@@ -249,10 +316,7 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hi
         p.sharedMemBytes = 0;
         p.kernelParams = args;
         p.extra = nullptr;
-        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return GN_E_HIP;
-        }
+        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) return GN_E_HIP;
     }
     for (int32_t j = 0; j < len; ++j) {
         StepArgs a = base_args(g);
@@ -281,33 +345,43 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hi
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node;
-        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
+        if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
             return GN_E_HIP;
-        }
         prev = node;
     }
-    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    return e == hipSuccess ? GN_OK : GN_E_HIP;
+    *tail = prev;
+    return GN_OK;
 }
 
 int32_t g_chunk_len = 64;
 int32_t g_prune = 1;
+int32_t g_prune_every = 64;
 
-gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream) {
+gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream,
+                                  bool sync_end) {
     GraphWorkspace& ws = g->ws;
     const int32_t C = g_chunk_len;
     const bool prune = g->prune && (g_prune == 2 || (g_prune == 1 && g->prune_pays));
-    if (ws.chunk_prune != (prune ? 1 : 0)) {  // chains captured for the other kind of lists
+    const int32_t key = prune ? g_prune_every : 0;
+    if (ws.chunk_prune != key) {  // chains captured for other lists or another rebuild interval
         for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
         ws.chunks.clear();
-        ws.chunk_prune = prune ? 1 : 0;
+        ws.chunk_prune = key;
+    }
+    if (prune && !gn_internal_chain_rebuilds(c_begin, C)) {
+        // the lists may be stale (another solve's, or none yet): rebuild them
+        // from this chain's input state before its first step reads them
+        hipLaunchKernelGGL(prune_rebuild_kernel, dim3((unsigned)(((int64_t)g->n * 8 + 255) / 256)), dim3(256), 0,
+                           stream, g->n, (const int32_t*)g->row_ptr, (const int32_t*)g->prune_mloc,
+                           (const float*)ws.y[((int64_t)c_begin * C) & 1], g->listed, g->prune);
+        GN_HIP_TRY(hipGetLastError());
     }
     return gn_internal_run_chunks(
-        ws, nchunks, C, [g, C, prune](int32_t c, hipGraphExec_t* out) { return build_chunk(g, c, C, prune, out); },
-        stream, c_begin);
+        ws, nchunks, C,
+        [g, C, prune](int32_t c, hipGraph_t graph, hipGraphNode_t* tail) {
+            return build_chunk(g, c, C, prune, graph, tail);
+        },
+        stream, c_begin, nullptr, nullptr, sync_end);
 }
 
 extern "C" gn_status gn_set_pruning(int32_t mode) {
@@ -321,6 +395,12 @@ int32_t g_small_limit = kSmallWorkMax;
 extern "C" gn_status gn_set_small_graph_limit(int32_t work_max) {
     if (work_max < 0 || work_max > kSmallWorkMax) return GN_E_ARG;
     g_small_limit = work_max;
+    return GN_OK;
+}
+
+extern "C" gn_status gn_set_prune_interval(int32_t steps) {
+    if (steps < 1 || steps > 4096) return GN_E_ARG;
+    g_prune_every = steps;
     return GN_OK;
 }
 
@@ -358,18 +438,25 @@ extern "C" gn_status gn_solve(gn_graph* g, const gn_schedule* sch, float* x, uin
     GN_HIP_TRY(hipGetLastError());
 
     // one workgroup (one launch for the whole solve) while a step is small
-    if (g->nnz + 2 * (int64_t)n <= g_small_limit && gn_internal_small_fits(g)) {
+    if (g->nnz + 2 * (int64_t)n <= g_small_limit && gn_internal_small_fits(g))
         st = gn_internal_small_solve(g, stream);
-        if (st == GN_OK && hipStreamSynchronize(stream) != hipSuccess) st = GN_E_HIP;
-    } else {
-        st = gn_internal_chain_solve(g, nchunks, 0, stream);
-    }
+    else
+        st = gn_internal_chain_solve(g, nchunks, 0, stream, false);
     if (st != GN_OK) return st;
-    int32_t steps;
-    bool binarised;
-    if ((st = gn_internal_solve_outcome(ws, ms, &steps, &binarised)) != GN_OK) return st;
-    FinalStats fs{};
-    st = gn_internal_final_stats(g, ws.y[steps & 1], gn_internal_host_gamma(sch, steps), x, sel, &fs, stream);
-    if (st != GN_OK) return st;
-    return gn_internal_fill_result(ws, steps, binarised, fs, res);
+
+    // Epilogue, stream-ordered after the last step: the outcome, the final state
+    // and its statistics are decided on the device and come back in one copy.
+    SolveTail* tail = (SolveTail*)ws.final_out;
+    hipLaunchKernelGGL(pick_final_kernel, dim3(1), dim3(64), 0, stream, (const SolveState*)ws.state,
+                       (const int32_t*)ws.notconv, ms, (const float*)ws.gamma, (const float*)ws.y[0],
+                       (const float*)ws.y[1], tail);
+    GN_HIP_TRY(hipGetLastError());
+    if ((st = gn_internal_final_stats_picked(g, &tail->pick, x, sel, &tail->stats, stream)) != GN_OK) return st;
+    GN_HIP_TRY(hipMemcpyAsync(ws.host_pinned, tail, sizeof(SolveTail), hipMemcpyDeviceToHost, stream));
+    GN_HIP_TRY(hipStreamSynchronize(stream));
+    SolveTail h;
+    std::memcpy(&h, ws.host_pinned, sizeof(h));
+    if (h.state.err & 1) return GN_E_ARG;
+    if (h.state.err & 2) return GN_E_NOT_NORMALIZABLE;
+    return fill_result(h.state, h.pick.steps, h.pick.binarised != 0, h.stats, res);
 }

@@ -60,8 +60,11 @@ __device__ void block_reduce_store(Partial p, Partial* out) {
 }
 
 // Single-block fixed-order reduction of the per-block partials.
+// gamma scales the stability; `pick` (may be null) supplies it instead.
 __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(int32_t count, const Partial* __restrict__ in,
-                                                                 float gamma, FinalStats* out) {
+                                                                 float gamma, FinalStats* out,
+                                                                 const FinalPick* pick) {
+    if (pick) gamma = pick->gamma;
     Partial p{0.0, 0.0, 0, 0, 0, INFINITY, 0};
     for (int b = threadIdx.x; b < count; b += kBlock) {
         const Partial q = in[b];

@@ -99,6 +99,7 @@ def lib():
             "gn_set_chunk_len": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_small_graph_limit": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_pruning": ([ctypes.c_int32], ctypes.c_int),
+            "gn_set_prune_interval": ([ctypes.c_int32], ctypes.c_int),
             "gn_set_multi_handoff": ([ctypes.c_int32], ctypes.c_int),
             "gn_atom_census": ([ctypes.c_int32, ctypes.POINTER(gn_atom_counts), _vp], ctypes.c_int),
             "gn_batch_create": ([ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
@@ -301,6 +302,7 @@ def gn_check_independent(h, sel, stream=None) -> tuple[int, int]:
 
 
 CHUNK_LEN_DEFAULT = 64   # the library's default chain length (gn_set_chunk_len)
+PRUNE_INTERVAL_DEFAULT = 64   # steps between rebuilds of the pruned lists (gn_set_prune_interval)
 
 
 def gn_set_chunk_len(length: int):
@@ -338,6 +340,11 @@ def gn_set_pruning(mode: int):
     """Pruned neighbour lists in gn_solve's chained path: PRUNE_NEVER,
     PRUNE_WHERE_IT_PAYS (the default) or PRUNE_ALWAYS; results do not change."""
     _check(lib().gn_set_pruning(int(mode)), "gn_set_pruning")
+
+
+def gn_set_prune_interval(steps: int):
+    """Steps between rebuilds of the pruned neighbour lists; results do not change."""
+    _check(lib().gn_set_prune_interval(int(steps)), "gn_set_prune_interval")
 
 
 class Graph:

@@ -126,6 +126,9 @@ def test_chunk_length_bounds():
     assert L.gn_set_chunk_len(0) == libgn.GN_E_ARG
     assert L.gn_set_chunk_len(4097) == libgn.GN_E_ARG
     assert L.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT) == libgn.GN_OK
+    assert L.gn_set_prune_interval(0) == libgn.GN_E_ARG
+    assert L.gn_set_prune_interval(4097) == libgn.GN_E_ARG
+    assert L.gn_set_prune_interval(libgn.PRUNE_INTERVAL_DEFAULT) == libgn.GN_OK
     assert L.gn_set_small_graph_limit(-1) == libgn.GN_E_ARG
     assert L.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT + 1) == libgn.GN_E_ARG
     assert L.gn_set_small_graph_limit(20000) == libgn.GN_OK

@@ -235,7 +235,8 @@ def test_multi_zero_steps(gpu):
     assert np.array_equal(sel.cpu().numpy().astype(bool), xn > 0.5)
 
 
-@pytest.mark.parametrize("case", ["late", "budget", "n2900", "check_every_5", "chain_33", "pruned"])
+@pytest.mark.parametrize("case", ["late", "budget", "n2900", "check_every_5", "chain_33", "pruned",
+                                  "pruned_stale"])
 def test_multi_handoff_same_bits(gpu, case):
     """Once a single start is left running, gn_multi_solve hands it to the
     single-start chained solve at a chain boundary.  With and without the
@@ -247,7 +248,10 @@ def test_multi_handoff_same_bits(gpu, case):
     ~700 steps after the others on a larger graph (n2900); the first again
     with the test every 5 steps, with chains of 33 steps (the hand-off at an
     odd step), and with the pruned lists of both solves forced on (the
-    single-start chains rebuild theirs from the state handed over)."""
+    single-start chains rebuild theirs from the state handed over); last with
+    the single-start lists left pruned by an earlier solve and rebuilt only by
+    the first chain (interval 4096), so that the hand-off, which starts
+    between rebuilds, must rebuild them itself."""
     import torch
     libgn = _lib()
     sched = dict(RAMP, max_steps=4000)
@@ -271,8 +275,13 @@ def test_multi_handoff_same_bits(gpu, case):
     try:
         if case == "chain_33":
             libgn.gn_set_chunk_len(33)
-        if case == "pruned":
+        if case in ("pruned", "pruned_stale"):
             libgn.gn_set_pruning(libgn.PRUNE_ALWAYS)
+        if case == "pruned_stale":
+            libgn.gn_set_chunk_len(33)
+            libgn.gn_set_prune_interval(4096)
+            xs = x0[g.n:2 * g.n].clone()
+            G.solve(xs, torch.zeros(g.n, dtype=torch.uint8, device="cuda"), **sched)
         for on in (True, False):
             libgn.gn_set_multi_handoff(on)
             x = x0.clone()
@@ -298,4 +307,5 @@ def test_multi_handoff_same_bits(gpu, case):
     finally:
         libgn.gn_set_multi_handoff(True)
         libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)
+        libgn.gn_set_prune_interval(libgn.PRUNE_INTERVAL_DEFAULT)
         libgn.gn_set_pruning(libgn.PRUNE_WHERE_IT_PAYS)

@@ -444,6 +444,39 @@ def test_solve_independent_of_chain_length(gpu):
         assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
 
 
+def test_solve_independent_of_prune_interval(gpu):
+    """How often the pruned lists are rebuilt, and where the chains start
+    against those rebuilds, changes only which decayed vertices are still
+    gathered: steps, states and sets are the bits of the full lists."""
+    import torch
+    libgn = _lib()
+    g = I.barabasi_albert(20_000, 4, 23)
+    w = I.weights_uniform01(g.n, 23)
+    G = _graph(g, w)
+    outs = []
+    libgn.gn_set_small_graph_limit(0)
+    try:
+        for prune, C, P in ((libgn.PRUNE_NEVER, 32, 64), (libgn.PRUNE_ALWAYS, 7, 64), (libgn.PRUNE_ALWAYS, 32, 1),
+                            (libgn.PRUNE_ALWAYS, 24, 64), (libgn.PRUNE_ALWAYS, 64, 16),
+                            (libgn.PRUNE_ALWAYS, 9, 4096)):
+            libgn.gn_set_pruning(prune)
+            libgn.gn_set_chunk_len(C)
+            libgn.gn_set_prune_interval(P)
+            x = dev(np.full(g.n, 0.5, F32))
+            sel = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+            r = G.solve(x, sel, **SCHED_RAMP)
+            outs.append((r.steps, r.fallback_count, x.cpu().numpy().view(np.uint32), sel.cpu().numpy()))
+    finally:
+        libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)
+        libgn.gn_set_prune_interval(libgn.PRUNE_INTERVAL_DEFAULT)
+        libgn.gn_set_pruning(libgn.PRUNE_WHERE_IT_PAYS)
+        libgn.gn_set_small_graph_limit(libgn.SMALL_LIMIT_DEFAULT)
+    assert outs[0][0] > 64
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1]
+        assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
+
+
 @pytest.mark.parametrize("case", ["er1000", "hubs", "fits3000", "ud2500", "ud3000", "ba3000", "budget",
                                   "check_every"])
 def test_small_graph_path_bitexact(gpu, case):
