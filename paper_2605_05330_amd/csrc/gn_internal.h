@@ -156,14 +156,9 @@ gn_status gn_internal_step_with(const gn_graph* g, float gamma, const float* x_i
 extern int32_t g_chunk_len;
 extern int32_t g_prune;  // pruned lists in chained solves: 0 never, 1 where they pay, 2 always (gn_set_pruning)
 extern int32_t g_prune_every;  // steps between rebuilds of the pruned lists (gn_set_prune_interval)
-// Whether chain c of length C rebuilds the pruned lists before its first step:
-// the first chain does, and so does each chain whose first step s is the
-// first chain start at or after a multiple of the rebuild interval (one lies
-// in (s - C, s]).
-inline bool gn_internal_chain_rebuilds(int32_t c, int32_t C) {
-    const int64_t s = (int64_t)c * C;
-    return c == 0 || s / g_prune_every != (s - C) / g_prune_every;
-}
+// Whether the captured chains rebuild the pruned lists before step k: at every
+// multiple of the rebuild interval, step 0 included, wherever it falls in a chain.
+inline bool gn_internal_rebuilds_at(int64_t k) { return k % g_prune_every == 0; }
 float gn_internal_host_gamma(const gn_schedule* s, int32_t k);
 bool gn_internal_schedule_ok(const gn_schedule* sch);
 gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream);

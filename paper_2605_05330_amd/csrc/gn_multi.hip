@@ -682,24 +682,27 @@ gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, boo
                       hipGraphNode_t* tail) {
     if (prune && (!m->pcol || !m->listed || !g->prune_mirror)) return GN_E_ARG;  // no pruned lists to read
     hipGraphNode_t prev = nullptr;
-    if (prune && gn_internal_chain_rebuilds(c, len)) {  // rebuild of the lists from the chain's input state
-        int32_t n = g->n;
-        const int32_t* rp = g->row_ptr;
-        const int32_t* mi = g->prune_mirror;
-        const float* y = m->Y[(c * len) & 1];
-        uint8_t* lst = m->listed;
-        int32_t* pc = m->pcol;
-        void* args[] = {&n, &rp, &mi, &y, &lst, &pc};
-        hipKernelNodeParams p{};
-        p.func = (void*)multi_rebuild_kernel;
-        p.gridDim = dim3((unsigned)(((int64_t)n * 8 + 255) / 256));
-        p.blockDim = dim3(256);
-        p.sharedMemBytes = 0;
-        p.kernelParams = args;
-        p.extra = nullptr;
-        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) return GN_E_HIP;
-    }
     for (int32_t q = 0; q < len; ++q) {
+        if (prune && gn_internal_rebuilds_at((int64_t)c * len + q)) {  // rebuild of the lists from step k's input
+            int32_t n = g->n;
+            const int32_t* rp = g->row_ptr;
+            const int32_t* mi = g->prune_mirror;
+            const float* y = m->Y[(c * len + q) & 1];
+            uint8_t* lst = m->listed;
+            int32_t* pc = m->pcol;
+            void* args[] = {&n, &rp, &mi, &y, &lst, &pc};
+            hipKernelNodeParams p{};
+            p.func = (void*)multi_rebuild_kernel;
+            p.gridDim = dim3((unsigned)(((int64_t)n * 8 + 255) / 256));
+            p.blockDim = dim3(256);
+            p.sharedMemBytes = 0;
+            p.kernelParams = args;
+            p.extra = nullptr;
+            hipGraphNode_t node;
+            if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                return GN_E_HIP;
+            prev = node;
+        }
         MultiArgs a{};
         a.row_ptr = g->row_ptr;
         a.col = g->col;

@@ -291,34 +291,64 @@ extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, 
     return gn_internal_step_with(g, gamma, x_in, x_out, g->ws.y[0], stream);
 }
 
-// Captured chain of `len` step launches for steps [c*len, (c+1)*len).  When the
-// pruned lists are used, chains that begin the solve or cross a multiple of the
-// rebuild interval first rebuild them from the chain's input state (the first
-// chain's rebuild sets the lists for the solve's start).
-static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, hipGraph_t graph,
-                             hipGraphNode_t* tail) {
+// Progress mark of chain c for the host, a node inside the chain: the solve
+// state's done step and error word, then the marker c + 1 (release), stored to
+// pinned memory with system scope.
+__global__ void chain_mark_kernel(const SolveState* __restrict__ st, int32_t* slot, int32_t marker) {
+    if (threadIdx.x != 0) return;
+    __hip_atomic_store(slot + 1, st->done_step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(slot + 2, st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(slot, marker, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Captured chain of `len` step launches for steps [c*len, (c+1)*len), with the
+// chain's progress mark before step mark_at.  When the pruned lists are used,
+// they are rebuilt before every step k that is a multiple of the rebuild
+// interval, from k's input state (step 0's rebuild sets the lists for the
+// solve's start).
+static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, int32_t mark_at, int32_t* mark_slot,
+                             hipGraph_t graph, hipGraphNode_t* tail) {
     GraphWorkspace& ws = g->ws;
     if (prune && (!g->prune || !g->prune_mloc || !g->listed)) return GN_E_ARG;  // no pruned lists to read
     hipGraphNode_t prev = nullptr;
     const int nblk = gn_internal_grid_blocks(g->bins);
-    if (prune && gn_internal_chain_rebuilds(c, len)) {
-        int32_t n = g->n;
-        const int32_t* rp = g->row_ptr;
-        const int32_t* ml = g->prune_mloc;
-        const float* y = ws.y[(c * len) & 1];
-        uint8_t* lst = g->listed;
-        int32_t* pb = g->prune;
-        void* args[] = {&n, &rp, &ml, &y, &lst, &pb};
-        hipKernelNodeParams p{};
-        p.func = (void*)prune_rebuild_kernel;
-        p.gridDim = dim3((unsigned)(((int64_t)n * 8 + 255) / 256));
-        p.blockDim = dim3(256);
-        p.sharedMemBytes = 0;
-        p.kernelParams = args;
-        p.extra = nullptr;
-        if (hipGraphAddKernelNode(&prev, graph, nullptr, 0, &p) != hipSuccess) return GN_E_HIP;
-    }
     for (int32_t j = 0; j < len; ++j) {
+        if (prune && gn_internal_rebuilds_at((int64_t)c * len + j)) {  // rebuild of the lists from step k's input
+            int32_t n = g->n;
+            const int32_t* rp = g->row_ptr;
+            const int32_t* ml = g->prune_mloc;
+            const float* y = ws.y[(c * len + j) & 1];
+            uint8_t* lst = g->listed;
+            int32_t* pb = g->prune;
+            void* args[] = {&n, &rp, &ml, &y, &lst, &pb};
+            hipKernelNodeParams p{};
+            p.func = (void*)prune_rebuild_kernel;
+            p.gridDim = dim3((unsigned)(((int64_t)n * 8 + 255) / 256));
+            p.blockDim = dim3(256);
+            p.sharedMemBytes = 0;
+            p.kernelParams = args;
+            p.extra = nullptr;
+            hipGraphNode_t node;
+            if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                return GN_E_HIP;
+            prev = node;
+        }
+        if (j == mark_at) {  // the host launches the next chain once this mark is written
+            const SolveState* st = ws.state;
+            int32_t marker = c + 1;
+            void* margs[] = {&st, &mark_slot, &marker};
+            hipKernelNodeParams p{};
+            p.func = (void*)chain_mark_kernel;
+            p.gridDim = dim3(1);
+            p.blockDim = dim3(64);
+            p.sharedMemBytes = 0;
+            p.kernelParams = margs;
+            p.extra = nullptr;
+            hipGraphNode_t node;
+            if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                return GN_E_HIP;
+            prev = node;
+        }
         StepArgs a = base_args(g);
         a.k = c * len + j;
         a.y_in = ws.y[a.k & 1];
@@ -357,6 +387,77 @@ int32_t g_chunk_len = 64;
 int32_t g_prune = 1;
 int32_t g_prune_every = 64;
 
+namespace {
+
+// The single-start chains carry their progress mark this many steps before
+// their end: the host launches chain c + 1 once chain c's mark is written, so
+// the next chain is queued while these steps run, and a solve that has stopped
+// by the mark launches no further chain.
+constexpr int32_t kMarkLead = 8;
+constexpr size_t kMarkPin = 256;  // byte offset of the two mark slots [4 words each] in the pinned block
+static_assert(sizeof(SolveTail) <= kMarkPin, "the epilogue's copy shares the pinned block");
+
+// Waits for chain c's mark (spinning on pinned memory; the stream is polled now
+// and then so that a failed stream ends the wait).
+gn_status wait_mark(volatile int32_t* slot, int32_t marker, hipStream_t stream) {
+    for (uint32_t spin = 1;; ++spin) {
+        if (__atomic_load_n(slot, __ATOMIC_ACQUIRE) == marker) return GN_OK;
+        if ((spin & 1023u) == 0) {
+            const hipError_t e = hipStreamQuery(stream);
+            if (e == hipSuccess) return __atomic_load_n(slot, __ATOMIC_ACQUIRE) == marker ? GN_OK : GN_E_HIP;
+            if (e != hipErrorNotReady) return GN_E_HIP;
+        }
+    }
+}
+
+// Replays the single-start chains from c_begin: chain c + 1 is launched when
+// chain c's mark shows the solve still running, none once it shows a stop or
+// an error.  The chains after the last launched one are never run.
+gn_status run_marked_chains(gn_graph* g, int32_t nchunks, int32_t C, bool prune, int32_t c_begin,
+                            hipStream_t stream, bool sync_end) {
+    GraphWorkspace& ws = g->ws;
+    if (ws.chunk_len != C) {
+        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
+        ws.chunks.clear();
+        ws.chunk_len = C;
+    }
+    if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
+    volatile int32_t* slots = (volatile int32_t*)((char*)ws.host_pinned + kMarkPin);
+    char* pin_dev = nullptr;  // the same block as the device addresses it
+    GN_HIP_TRY(hipHostGetDevicePointer((void**)&pin_dev, ws.host_pinned, 0));
+    const int32_t mark_at = std::max<int32_t>(0, C - kMarkLead);
+    auto launch = [&](int32_t c) -> gn_status {
+        if (!ws.chunks[c]) {
+            hipGraph_t graph;
+            GN_HIP_TRY(hipGraphCreate(&graph, 0));
+            hipGraphNode_t tail = nullptr;
+            gn_status st = build_chunk(g, c, C, prune, mark_at, (int32_t*)(pin_dev + kMarkPin) + 4 * (c & 1),
+                                       graph, &tail);
+            if (st == GN_OK && hipGraphInstantiate(&ws.chunks[c], graph, nullptr, nullptr, 0) != hipSuccess) {
+                ws.chunks[c] = nullptr;
+                st = GN_E_HIP;
+            }
+            (void)hipGraphDestroy(graph);
+            if (st != GN_OK) return st;
+        }
+        // slot c & 1 last held chain c - 2's mark, whose chain has ended
+        __atomic_store_n(slots + 4 * (c & 1), 0, __ATOMIC_RELEASE);
+        return hipGraphLaunch(ws.chunks[c], stream) == hipSuccess ? GN_OK : GN_E_HIP;
+    };
+    gn_status rs = launch(c_begin);
+    for (int32_t c = c_begin; rs == GN_OK; ++c) {
+        volatile int32_t* s = slots + 4 * (c & 1);
+        if ((rs = wait_mark(s, c + 1, stream)) != GN_OK) break;
+        if (s[1] >= 0 || s[2] != 0 || c + 1 >= nchunks) break;
+        rs = launch(c + 1);
+    }
+    if (rs != GN_OK) return rs;
+    if (sync_end) GN_HIP_TRY(hipStreamSynchronize(stream));
+    return GN_OK;
+}
+
+}  // namespace
+
 gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream,
                                   bool sync_end) {
     GraphWorkspace& ws = g->ws;
@@ -368,7 +469,7 @@ gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin,
         ws.chunks.clear();
         ws.chunk_prune = key;
     }
-    if (prune && !gn_internal_chain_rebuilds(c_begin, C)) {
+    if (prune && !gn_internal_rebuilds_at((int64_t)c_begin * C)) {
         // the lists may be stale (another solve's, or none yet): rebuild them
         // from this chain's input state before its first step reads them
         hipLaunchKernelGGL(prune_rebuild_kernel, dim3((unsigned)(((int64_t)g->n * 8 + 255) / 256)), dim3(256), 0,
@@ -376,12 +477,7 @@ gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin,
                            (const float*)ws.y[((int64_t)c_begin * C) & 1], g->listed, g->prune);
         GN_HIP_TRY(hipGetLastError());
     }
-    return gn_internal_run_chunks(
-        ws, nchunks, C,
-        [g, C, prune](int32_t c, hipGraph_t graph, hipGraphNode_t* tail) {
-            return build_chunk(g, c, C, prune, graph, tail);
-        },
-        stream, c_begin, nullptr, nullptr, sync_end);
+    return run_marked_chains(g, nchunks, C, prune, c_begin, stream, sync_end);
 }
 
 extern "C" gn_status gn_set_pruning(int32_t mode) {

@@ -358,21 +358,29 @@ def test_solve_edge_cases(gpu, path):
     assert res.steps == 0 and not res.binarised and np.all(x == 0.5)
 
 
-def test_solve_rejects_bad_x0(gpu):
+@pytest.mark.parametrize("path", PATHS)
+def test_solve_rejects_bad_x0(gpu, path):
+    """A start that is not normalizable, or has a negative entry, fails the
+    solve with its status, and neither x nor sel is written (the outcome is
+    decided on the device before the final rounding)."""
     import torch
     lg = _lib()
     g = I.csr_from_edges(4, np.array([0, 2]), np.array([1, 3]))
     G = _graph(g, np.ones(4, F32))
+    for x0, status in (([0.5, 0.5, 0.0, 0.0], lg.GN_E_NOT_NORMALIZABLE), ([0.5, -0.1, 0.3, 0.3], lg.GN_E_ARG)):
+        sel = torch.full((4,), 7, dtype=torch.uint8, device="cuda")
+        x = dev(np.array(x0, F32))
+        with _path(path), pytest.raises(lg.GNError) as e:
+            G.solve(x, sel)
+        assert e.value.status == status
+        assert torch.equal(x.cpu(), torch.tensor(x0, dtype=torch.float32))  # untouched
+        assert torch.equal(sel.cpu(), torch.full((4,), 7, dtype=torch.uint8))
+    # the handle still solves afterwards
+    x = dev(np.array([0.6, 0.4, 0.4, 0.6], F32))
     sel = torch.zeros(4, dtype=torch.uint8, device="cuda")
-    x = dev(np.array([0.5, 0.5, 0.0, 0.0], F32))
-    with pytest.raises(lg.GNError) as e:
-        G.solve(x, sel)
-    assert e.value.status == lg.GN_E_NOT_NORMALIZABLE
-    assert torch.equal(x.cpu(), torch.tensor([0.5, 0.5, 0.0, 0.0]))  # untouched
-    x = dev(np.array([0.5, -0.1, 0.3, 0.3], F32))
-    with pytest.raises(lg.GNError) as e:
-        G.solve(x, sel)
-    assert e.value.status == lg.GN_E_ARG
+    with _path(path):
+        r = G.solve(x, sel, **SCHED_RAMP)
+    assert r.binarised and sel.cpu().tolist() == [1, 0, 0, 1]
 
 
 def test_step_rejects_aliasing(gpu):
