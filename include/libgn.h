@@ -626,20 +626,22 @@ gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t star
                                gn_result* res, int32_t* best, hipStream_t stream);
 
 /* Tuning: number of step launches captured in one replayed chain by gn_solve,
- * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  A longer chain checks
- * the stop flag less often from the host; once the solve has stopped, the
- * launches left in the chains in flight return at once, so a shorter chain
- * wastes fewer of them.  Results do not change.  Process-wide; not
- * thread-safe. */
+ * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  gn_solve launches
+ * the next chain when a progress mark 8 steps before a chain's end shows the
+ * solve still running; the other two keep two chains in flight and check the
+ * stop flag after each.  A longer chain costs fewer transitions between
+ * chains; once the solve has stopped, the launches left in the chains in
+ * flight return at once, so a shorter chain wastes fewer of them.  Results do
+ * not change.  Process-wide; not thread-safe. */
 gn_status gn_set_chunk_len(int32_t len);
 
 /* Tuning: steps between rebuilds of the pruned neighbour lists
  * (gn_set_pruning) in gn_solve and gn_multi_solve (default 64, 1..4096).  The
- * first chain of step launches rebuilds them, and so does each chain that
- * starts at or first after a multiple of this interval; a chain longer than
- * the interval rebuilds once.  Fewer rebuilds cost less upkeep and leave more
- * decayed vertices listed (gathered, adding nothing).  Results do not change.
- * GN_E_ARG outside 1..4096.  Process-wide; not thread-safe. */
+ * lists are rebuilt before every step whose index is a multiple of this
+ * interval (step 0 included), wherever it falls in a chain of step launches.
+ * Fewer rebuilds cost less upkeep and leave more decayed vertices listed
+ * (gathered, adding nothing).  Results do not change.  GN_E_ARG outside
+ * 1..4096.  Process-wide; not thread-safe. */
 gn_status gn_set_prune_interval(int32_t steps);
 
 /* Tuning: gn_solve runs a graph with nnz + 2 n <= work_max (0 .. 1048576, the
