@@ -181,6 +181,18 @@ using ChainBuilder = std::function<gn_status(int32_t c, hipGraph_t graph, hipGra
 gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C, const ChainBuilder& build,
                                  hipStream_t stream, int32_t c_begin = 0, const ChunkHooks* hooks = nullptr,
                                  int32_t* last = nullptr, bool sync_end = true);
+// Steps [c C + j0, c C + j1) of chain c, added to `graph` after *last (null for
+// none), which is updated to the last node added.
+using StepRangeBuilder =
+    std::function<gn_status(int32_t c, int32_t j0, int32_t j1, hipGraph_t graph, hipGraphNode_t* last)>;
+// Replays chains of C steps from c_begin with a progress mark 8 steps before
+// each chain's end (the solve state's done step and error word, stored to
+// pinned memory): chain c + 1 is launched when chain c's mark shows the solve
+// still running, none once it shows a stop or an error, so a solve that stops
+// before a mark launches no further chain.  With sync_end the call returns once
+// the chains have completed.
+gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C, const StepRangeBuilder& build,
+                                 int32_t c_begin, hipStream_t stream, bool sync_end = true);
 // The chained single-start solve of g from chain c_begin on: ws.y[(c_begin C) & 1]
 // holds the state at step c_begin C (C = g_chunk_len), and the solve state and
 // flags are set up (gn_solve.hip).

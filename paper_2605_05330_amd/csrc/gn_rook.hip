@@ -696,10 +696,13 @@ extern "C" gn_status gn_rook_step(gn_rook* r, float gamma, const float* x_in, fl
     return GN_OK;
 }
 
-static gn_status rook_build_chunk(gn_rook* r, int32_t c, int32_t len, hipGraph_t graph, hipGraphNode_t* tail) {
+// Steps [c len + q0, c len + q1) of a captured chain (one or two launches per
+// step), added to `graph` after *last, which is updated to the last node.
+static gn_status rook_build_steps(gn_rook* r, int32_t c, int32_t len, int32_t q0, int32_t q1, hipGraph_t graph,
+                                 hipGraphNode_t* last) {
     GraphWorkspace& ws = r->ws;
-    hipGraphNode_t prev = nullptr;
-    for (int32_t q = 0; q < len; ++q) {
+    hipGraphNode_t prev = *last;
+    for (int32_t q = q0; q < q1; ++q) {
         RookArgs a = rook_args(r);
         a.k = c * len + q;
         a.y_in = ws.y[a.k & 1];
@@ -726,7 +729,7 @@ static gn_status rook_build_chunk(gn_rook* r, int32_t c, int32_t len, hipGraph_t
             prev = node;
         }
     }
-    *tail = prev;
+    *last = prev;
     return GN_OK;
 }
 
@@ -773,11 +776,12 @@ extern "C" gn_status gn_rook_solve(gn_rook* r, const gn_schedule* sch, float* x,
     if (st != GN_OK) return st;
     if ((st = gn_internal_init_solve(ws, sch, stream)) != GN_OK) return st;
     if ((st = rook_prep(r, x, ws.state, stream)) != GN_OK) return st;
-    st = gn_internal_run_chunks(ws, nchunks, C,
-                                [r, C](int32_t c, hipGraph_t graph, hipGraphNode_t* tail) {
-                                    return rook_build_chunk(r, c, C, graph, tail);
-                                },
-                                stream);
+    st = gn_internal_run_marked(
+        ws, nchunks, C,
+        [r, C](int32_t c, int32_t q0, int32_t q1, hipGraph_t graph, hipGraphNode_t* last) {
+            return rook_build_steps(r, c, C, q0, q1, graph, last);
+        },
+        0, stream);
     if (st != GN_OK) return st;
     int32_t steps;
     bool binarised;

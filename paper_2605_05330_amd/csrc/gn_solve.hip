@@ -301,18 +301,18 @@ __global__ void chain_mark_kernel(const SolveState* __restrict__ st, int32_t* sl
     __hip_atomic_store(slot, marker, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Captured chain of `len` step launches for steps [c*len, (c+1)*len), with the
-// chain's progress mark before step mark_at.  When the pruned lists are used,
-// they are rebuilt before every step k that is a multiple of the rebuild
+// Steps [c*len + j0, c*len + j1) of chain c of `len` step launches, added to
+// `graph` after *prev (updated to the last node).  When the pruned lists are
+// used, they are rebuilt before every step k that is a multiple of the rebuild
 // interval, from k's input state (step 0's rebuild sets the lists for the
 // solve's start).
-static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, int32_t mark_at, int32_t* mark_slot,
-                             hipGraph_t graph, hipGraphNode_t* tail) {
+static gn_status build_steps(gn_graph* g, int32_t c, int32_t len, bool prune, int32_t j0, int32_t j1,
+                             hipGraph_t graph, hipGraphNode_t* last) {
     GraphWorkspace& ws = g->ws;
     if (prune && (!g->prune || !g->prune_mloc || !g->listed)) return GN_E_ARG;  // no pruned lists to read
-    hipGraphNode_t prev = nullptr;
+    hipGraphNode_t prev = *last;
     const int nblk = gn_internal_grid_blocks(g->bins);
-    for (int32_t j = 0; j < len; ++j) {
+    for (int32_t j = j0; j < j1; ++j) {
         if (prune && gn_internal_rebuilds_at((int64_t)c * len + j)) {  // rebuild of the lists from step k's input
             int32_t n = g->n;
             const int32_t* rp = g->row_ptr;
@@ -327,22 +327,6 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, in
             p.blockDim = dim3(256);
             p.sharedMemBytes = 0;
             p.kernelParams = args;
-            p.extra = nullptr;
-            hipGraphNode_t node;
-            if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
-                return GN_E_HIP;
-            prev = node;
-        }
-        if (j == mark_at) {  // the host launches the next chain once this mark is written
-            const SolveState* st = ws.state;
-            int32_t marker = c + 1;
-            void* margs[] = {&st, &mark_slot, &marker};
-            hipKernelNodeParams p{};
-            p.func = (void*)chain_mark_kernel;
-            p.gridDim = dim3(1);
-            p.blockDim = dim3(64);
-            p.sharedMemBytes = 0;
-            p.kernelParams = margs;
             p.extra = nullptr;
             hipGraphNode_t node;
             if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
@@ -379,7 +363,7 @@ static gn_status build_chunk(gn_graph* g, int32_t c, int32_t len, bool prune, in
             return GN_E_HIP;
         prev = node;
     }
-    *tail = prev;
+    *last = prev;
     return GN_OK;
 }
 
@@ -389,10 +373,10 @@ int32_t g_prune_every = 64;
 
 namespace {
 
-// The single-start chains carry their progress mark this many steps before
-// their end: the host launches chain c + 1 once chain c's mark is written, so
-// the next chain is queued while these steps run, and a solve that has stopped
-// by the mark launches no further chain.
+// Marked chains carry their progress mark this many steps before their end:
+// the host launches chain c + 1 once chain c's mark is written, so the next
+// chain is queued while these steps run, and a solve that has stopped by the
+// mark launches no further chain.
 constexpr int32_t kMarkLead = 8;
 constexpr size_t kMarkPin = 256;  // byte offset of the two mark slots [4 words each] in the pinned block
 static_assert(sizeof(SolveTail) <= kMarkPin, "the epilogue's copy shares the pinned block");
@@ -410,12 +394,10 @@ gn_status wait_mark(volatile int32_t* slot, int32_t marker, hipStream_t stream) 
     }
 }
 
-// Replays the single-start chains from c_begin: chain c + 1 is launched when
-// chain c's mark shows the solve still running, none once it shows a stop or
-// an error.  The chains after the last launched one are never run.
-gn_status run_marked_chains(gn_graph* g, int32_t nchunks, int32_t C, bool prune, int32_t c_begin,
-                            hipStream_t stream, bool sync_end) {
-    GraphWorkspace& ws = g->ws;
+}  // namespace
+
+gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C, const StepRangeBuilder& build,
+                                 int32_t c_begin, hipStream_t stream, bool sync_end) {
     if (ws.chunk_len != C) {
         for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
         ws.chunks.clear();
@@ -426,13 +408,33 @@ gn_status run_marked_chains(gn_graph* g, int32_t nchunks, int32_t C, bool prune,
     char* pin_dev = nullptr;  // the same block as the device addresses it
     GN_HIP_TRY(hipHostGetDevicePointer((void**)&pin_dev, ws.host_pinned, 0));
     const int32_t mark_at = std::max<int32_t>(0, C - kMarkLead);
+    // chain c: steps before the mark, the mark, the remaining steps
+    auto capture = [&](int32_t c, hipGraph_t graph) -> gn_status {
+        hipGraphNode_t prev = nullptr;
+        gn_status st = build(c, 0, mark_at, graph, &prev);
+        if (st != GN_OK) return st;
+        const SolveState* sp = ws.state;
+        int32_t* slot = (int32_t*)(pin_dev + kMarkPin) + 4 * (c & 1);
+        int32_t marker = c + 1;
+        void* args[] = {&sp, &slot, &marker};
+        hipKernelNodeParams p{};
+        p.func = (void*)chain_mark_kernel;
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(64);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+            return GN_E_HIP;
+        prev = node;
+        return build(c, mark_at, C, graph, &prev);
+    };
     auto launch = [&](int32_t c) -> gn_status {
         if (!ws.chunks[c]) {
             hipGraph_t graph;
             GN_HIP_TRY(hipGraphCreate(&graph, 0));
-            hipGraphNode_t tail = nullptr;
-            gn_status st = build_chunk(g, c, C, prune, mark_at, (int32_t*)(pin_dev + kMarkPin) + 4 * (c & 1),
-                                       graph, &tail);
+            gn_status st = capture(c, graph);
             if (st == GN_OK && hipGraphInstantiate(&ws.chunks[c], graph, nullptr, nullptr, 0) != hipSuccess) {
                 ws.chunks[c] = nullptr;
                 st = GN_E_HIP;
@@ -456,8 +458,6 @@ gn_status run_marked_chains(gn_graph* g, int32_t nchunks, int32_t C, bool prune,
     return GN_OK;
 }
 
-}  // namespace
-
 gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin, hipStream_t stream,
                                   bool sync_end) {
     GraphWorkspace& ws = g->ws;
@@ -477,7 +477,12 @@ gn_status gn_internal_chain_solve(gn_graph* g, int32_t nchunks, int32_t c_begin,
                            (const float*)ws.y[((int64_t)c_begin * C) & 1], g->listed, g->prune);
         GN_HIP_TRY(hipGetLastError());
     }
-    return run_marked_chains(g, nchunks, C, prune, c_begin, stream, sync_end);
+    return gn_internal_run_marked(
+        ws, nchunks, C,
+        [g, C, prune](int32_t c, int32_t j0, int32_t j1, hipGraph_t graph, hipGraphNode_t* last) {
+            return build_steps(g, c, C, prune, j0, j1, graph, last);
+        },
+        c_begin, stream, sync_end);
 }
 
 extern "C" gn_status gn_set_pruning(int32_t mode) {
