@@ -162,25 +162,17 @@ inline bool gn_internal_rebuilds_at(int64_t k) { return k % g_prune_every == 0; 
 float gn_internal_host_gamma(const gn_schedule* s, int32_t k);
 bool gn_internal_schedule_ok(const gn_schedule* sch);
 gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hipStream_t stream);
-// Optional hooks of gn_internal_run_chunks: when pin_src is set, each chain's
-// last node also copies pin_words words from pin_src to the pinned block at
+// Optional hooks of gn_internal_run_marked: when pin_src is set, each chain's
+// progress mark also copies pin_words words from pin_src to the pinned block at
 // byte offset pin_offset + 4 pin_words (c & 1) for chain c; stop_after(c) is
-// asked once chain c has completed (chain c + 1 is then in flight) and returns
-// true to launch no further chain.  *last receives the last chain launched.
+// asked once chain c's mark shows the solve still running, and returns true to
+// launch no further chain.
 struct ChunkHooks {
     const void* pin_src = nullptr;
     int32_t pin_words = 0;
     size_t pin_offset = 0;
     std::function<bool(int32_t)> stop_after;
 };
-// The chains' builder adds chain c's nodes to `graph`, each after the one
-// before, and returns the last one in *tail (nullptr for an empty chain).
-using ChainBuilder = std::function<gn_status(int32_t c, hipGraph_t graph, hipGraphNode_t* tail)>;
-// With sync_end the call returns once every launched chain has completed;
-// without it the stream is left running (the caller enqueues more work).
-gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C, const ChainBuilder& build,
-                                 hipStream_t stream, int32_t c_begin = 0, const ChunkHooks* hooks = nullptr,
-                                 int32_t* last = nullptr, bool sync_end = true);
 // Steps [c C + j0, c C + j1) of chain c, added to `graph` after *last (null for
 // none), which is updated to the last node added.
 using StepRangeBuilder =
@@ -190,9 +182,10 @@ using StepRangeBuilder =
 // pinned memory): chain c + 1 is launched when chain c's mark shows the solve
 // still running, none once it shows a stop or an error, so a solve that stops
 // before a mark launches no further chain.  With sync_end the call returns once
-// the chains have completed.
+// the chains have completed; *last receives the last chain launched.
 gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C, const StepRangeBuilder& build,
-                                 int32_t c_begin, hipStream_t stream, bool sync_end = true);
+                                 int32_t c_begin, hipStream_t stream, bool sync_end = true,
+                                 const ChunkHooks* hooks = nullptr, int32_t* last = nullptr);
 // The chained single-start solve of g from chain c_begin on: ws.y[(c_begin C) & 1]
 // holds the state at step c_begin C (C = g_chunk_len), and the solve state and
 // flags are set up (gn_solve.hip).

@@ -678,11 +678,11 @@ gn_status ensure_tables(MultiWS* m, int32_t steps) {
     return GN_OK;
 }
 
-gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, bool prune, hipGraph_t graph,
-                      hipGraphNode_t* tail) {
+gn_status build_steps(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, bool prune, int32_t q0, int32_t q1,
+                      hipGraph_t graph, hipGraphNode_t* last) {
     if (prune && (!m->pcol || !m->listed || !g->prune_mirror)) return GN_E_ARG;  // no pruned lists to read
-    hipGraphNode_t prev = nullptr;
-    for (int32_t q = 0; q < len; ++q) {
+    hipGraphNode_t prev = *last;
+    for (int32_t q = q0; q < q1; ++q) {
         if (prune && gn_internal_rebuilds_at((int64_t)c * len + q)) {  // rebuild of the lists from step k's input
             int32_t n = g->n;
             const int32_t* rp = g->row_ptr;
@@ -742,7 +742,7 @@ gn_status build_chunk(const gn_graph* g, MultiWS* m, int32_t c, int32_t len, boo
             return GN_E_HIP;
         prev = node;
     }
-    *tail = prev;
+    *last = prev;
     return GN_OK;
 }
 
@@ -824,15 +824,17 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
     char* hp = (char*)m->ws.host_pinned;
     volatile int32_t* run = (volatile int32_t*)(hp + kPinRun);  // per chain slot: done step of each start
     int32_t handoff = -1;  // the start handed over
-    // Each chain's last node copies the starts' done steps to `run`, in every
-    // call, since later calls replay the same captured chains.
+    // Each chain's progress mark copies the starts' done steps to `run`, in
+    // every call, since later calls replay the same captured chains.
     ChunkHooks hooks;
     hooks.pin_src = m->done;
     hooks.pin_words = kStarts;
     hooks.pin_offset = kPinRun;
     if (g_multi_handoff && starts > 1) {
-        hooks.stop_after = [run, starts, nchunks, &handoff](int32_t c) {
-            if (c + 2 >= nchunks) return false;  // chain c + 1 (in flight) is the last or next to last
+        // asked at chain c's mark while chain c + 1 is still to come: with a
+        // single start left running, no further chain is launched and that
+        // start moves on at step (c + 1) C
+        hooks.stop_after = [run, starts, &handoff](int32_t c) {
             int left = 0, who = -1;
             for (int b = 0; b < starts; ++b)
                 if (run[kStarts * (c & 1) + b] < 0) {
@@ -845,12 +847,12 @@ extern "C" gn_status gn_multi_solve(gn_graph* g, const gn_schedule* sch, int32_t
         };
     }
     int32_t last = -1;
-    st = gn_internal_run_chunks(
+    st = gn_internal_run_marked(
         m->ws, nchunks, C,
-        [g, m, C, prune](int32_t c, hipGraph_t graph, hipGraphNode_t* tail) {
-            return build_chunk(g, m, c, C, prune, graph, tail);
+        [g, m, C, prune](int32_t c, int32_t q0, int32_t q1, hipGraph_t graph, hipGraphNode_t* tl) {
+            return build_steps(g, m, c, C, prune, q0, q1, graph, tl);
         },
-        stream, 0, &hooks, &last);
+        0, stream, true, &hooks, &last);
     if (st != GN_OK) return st;
 
     // solve state, per-start outcomes and the last step's flags in one round trip

@@ -42,19 +42,6 @@ __global__ void normalizable_kernel(int32_t n, const int32_t* __restrict__ row_p
     atomicOr(&st->err, 2);
 }
 
-// Copies the solve state's done step and error word, and optionally a second
-// run of words, to pinned host memory with system-scope stores.  It is the last
-// node of every captured chain, so the flags travel inside the chain: a copy
-// enqueued between two chains costs the stream a gap of several microseconds.
-__global__ void pin_copy_kernel(const int32_t* __restrict__ st, int32_t* dst, const int32_t* __restrict__ src2,
-                                int32_t words2, int32_t* dst2) {
-    const int t = threadIdx.x;
-    if (t < 2) __hip_atomic_store(dst + t, st[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    for (int i = t; i < words2; i += blockDim.x)
-        __hip_atomic_store(dst2 + i, src2[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __threadfence_system();
-}
-
 // A solve's outcome after its last step, as gn_internal_solve_outcome decides
 // it on the host: the stop's step when the stopping test passed, else max_steps,
 // binarised when that last state passed the test; the final state words are
@@ -126,84 +113,6 @@ gn_status gn_internal_init_solve(GraphWorkspace& ws, const gn_schedule* sch, hip
                        ws.notconv, ws.gamma, ms, sch->check_every, sch->tau, sch->gamma0, sch->gamma1,
                        sch->ramp_steps);
     GN_HIP_TRY(hipGetLastError());
-    return GN_OK;
-}
-
-gn_status gn_internal_run_chunks(GraphWorkspace& ws, int32_t nchunks, int32_t C, const ChainBuilder& build,
-                                 hipStream_t stream, int32_t c_begin, const ChunkHooks* hooks, int32_t* last,
-                                 bool sync_end) {
-    if (ws.chunk_len != C) {
-        for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
-        ws.chunks.clear();
-        ws.chunk_len = C;
-    }
-    if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
-    volatile int32_t* pin = (volatile int32_t*)ws.host_pinned;  // [slot][done_step, err]
-    char* pin_dev = nullptr;  // the same block as the device addresses it
-    GN_HIP_TRY(hipHostGetDevicePointer((void**)&pin_dev, ws.host_pinned, 0));
-    // chain c with its flag copy as the last node
-    auto instantiate = [&](int32_t c, hipGraphExec_t* out) -> gn_status {
-        hipGraph_t graph;
-        GN_HIP_TRY(hipGraphCreate(&graph, 0));
-        hipGraphNode_t tail = nullptr;
-        gn_status st = build(c, graph, &tail);
-        if (st == GN_OK) {
-            const int32_t* s0 = (const int32_t*)ws.state;
-            int32_t* d0 = (int32_t*)pin_dev + 2 * (c & 1);
-            const bool extra = hooks && hooks->pin_src;
-            const int32_t* s2 = extra ? (const int32_t*)hooks->pin_src : nullptr;
-            int32_t w2 = extra ? hooks->pin_words : 0;
-            int32_t* d2 = extra ? (int32_t*)(pin_dev + hooks->pin_offset) + (size_t)w2 * (c & 1) : nullptr;
-            void* args[] = {&s0, &d0, &s2, &w2, &d2};
-            hipKernelNodeParams p{};
-            p.func = (void*)pin_copy_kernel;
-            p.gridDim = dim3(1);
-            p.blockDim = dim3(64);
-            p.sharedMemBytes = 0;
-            p.kernelParams = args;
-            p.extra = nullptr;
-            hipGraphNode_t node;
-            if (hipGraphAddKernelNode(&node, graph, tail ? &tail : nullptr, tail ? 1 : 0, &p) != hipSuccess ||
-                hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess)
-                st = GN_E_HIP;
-        }
-        (void)hipGraphDestroy(graph);
-        return st;
-    };
-    // per-workspace events: a call that returns with chains still in flight
-    // leaves them recorded
-    for (auto& e : ws.chain_ev)
-        if (!e) GN_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    hipEvent_t* ev = ws.chain_ev;
-    gn_status rs = GN_OK;
-    int32_t launched = c_begin - 1;
-    for (int32_t c = c_begin; c < nchunks && rs == GN_OK; ++c) {
-        if (!ws.chunks[c]) {
-            rs = instantiate(c, &ws.chunks[c]);
-            if (rs != GN_OK) break;
-        }
-        if (hipGraphLaunch(ws.chunks[c], stream) != hipSuccess) {
-            rs = GN_E_HIP;
-            break;
-        }
-        launched = c;
-        if (hipEventRecord(ev[c & 1], stream) != hipSuccess) {
-            rs = GN_E_HIP;
-            break;
-        }
-        if (c > c_begin) {
-            const int p = (c - 1) & 1;
-            if (hipEventSynchronize(ev[p]) != hipSuccess) {
-                rs = GN_E_HIP;
-                break;
-            }
-            if (pin[2 * p] >= 0 || pin[2 * p + 1] != 0) break;
-            if (hooks && hooks->stop_after && hooks->stop_after(c - 1)) break;
-        }
-    }
-    if (last) *last = launched;
-    if (rs != GN_OK) return rs;
-    if (sync_end) GN_HIP_TRY(hipStreamSynchronize(stream));
     return GN_OK;
 }
 
@@ -291,10 +200,16 @@ extern "C" gn_status gn_step(const gn_graph* g, float gamma, const float* x_in, 
     return gn_internal_step_with(g, gamma, x_in, x_out, g->ws.y[0], stream);
 }
 
-// Progress mark of chain c for the host, a node inside the chain: the solve
-// state's done step and error word, then the marker c + 1 (release), stored to
-// pinned memory with system scope.
-__global__ void chain_mark_kernel(const SolveState* __restrict__ st, int32_t* slot, int32_t marker) {
+// Progress mark of chain c for the host, a node inside the chain (one
+// wavefront): words2 words from src2 to dst2 when given, the solve state's done
+// step and error word, then the marker c + 1 (release), all stored to pinned
+// memory with system scope.
+__global__ void chain_mark_kernel(const SolveState* __restrict__ st, int32_t* slot, int32_t marker,
+                                  const int32_t* __restrict__ src2, int32_t words2, int32_t* dst2) {
+    for (int i = threadIdx.x; i < words2; i += blockDim.x)
+        __hip_atomic_store(dst2 + i, src2[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+    __syncthreads();
     if (threadIdx.x != 0) return;
     __hip_atomic_store(slot + 1, st->done_step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(slot + 2, st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -378,8 +293,11 @@ namespace {
 // chain is queued while these steps run, and a solve that has stopped by the
 // mark launches no further chain.
 constexpr int32_t kMarkLead = 8;
-constexpr size_t kMarkPin = 256;  // byte offset of the two mark slots [4 words each] in the pinned block
-static_assert(sizeof(SolveTail) <= kMarkPin, "the epilogue's copy shares the pinned block");
+// byte offset of the two mark slots [4 words each] in a workspace's 4 KiB
+// pinned block, past what the solvers stage there (gn_solve's epilogue from 0,
+// the multi-start solve's staging below 3200 bytes)
+constexpr size_t kMarkPin = 3584;
+static_assert(sizeof(SolveTail) <= kMarkPin && kMarkPin + 32 <= 4096, "pinned block layout");
 
 // Waits for chain c's mark (spinning on pinned memory; the stream is polled now
 // and then so that a failed stream ends the wait).
@@ -397,7 +315,8 @@ gn_status wait_mark(volatile int32_t* slot, int32_t marker, hipStream_t stream) 
 }  // namespace
 
 gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C, const StepRangeBuilder& build,
-                                 int32_t c_begin, hipStream_t stream, bool sync_end) {
+                                 int32_t c_begin, hipStream_t stream, bool sync_end, const ChunkHooks* hooks,
+                                 int32_t* last) {
     if (ws.chunk_len != C) {
         for (auto ex : ws.chunks) if (ex) (void)hipGraphExecDestroy(ex);
         ws.chunks.clear();
@@ -416,7 +335,11 @@ gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C,
         const SolveState* sp = ws.state;
         int32_t* slot = (int32_t*)(pin_dev + kMarkPin) + 4 * (c & 1);
         int32_t marker = c + 1;
-        void* args[] = {&sp, &slot, &marker};
+        const bool extra = hooks && hooks->pin_src;
+        const int32_t* s2 = extra ? (const int32_t*)hooks->pin_src : nullptr;
+        int32_t w2 = extra ? hooks->pin_words : 0;
+        int32_t* d2 = extra ? (int32_t*)(pin_dev + hooks->pin_offset) + (size_t)w2 * (c & 1) : nullptr;
+        void* args[] = {&sp, &slot, &marker, &s2, &w2, &d2};
         hipKernelNodeParams p{};
         p.func = (void*)chain_mark_kernel;
         p.gridDim = dim3(1);
@@ -447,12 +370,15 @@ gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C,
         return hipGraphLaunch(ws.chunks[c], stream) == hipSuccess ? GN_OK : GN_E_HIP;
     };
     gn_status rs = launch(c_begin);
+    int32_t launched = c_begin;
     for (int32_t c = c_begin; rs == GN_OK; ++c) {
         volatile int32_t* s = slots + 4 * (c & 1);
         if ((rs = wait_mark(s, c + 1, stream)) != GN_OK) break;
         if (s[1] >= 0 || s[2] != 0 || c + 1 >= nchunks) break;
-        rs = launch(c + 1);
+        if (hooks && hooks->stop_after && hooks->stop_after(c)) break;
+        if ((rs = launch(c + 1)) == GN_OK) launched = c + 1;
     }
+    if (last) *last = launched;
     if (rs != GN_OK) return rs;
     if (sync_end) GN_HIP_TRY(hipStreamSynchronize(stream));
     return GN_OK;
