@@ -626,10 +626,9 @@ gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t star
                                gn_result* res, int32_t* best, hipStream_t stream);
 
 /* Tuning: number of step launches captured in one replayed chain by gn_solve,
- * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  gn_solve launches
- * the next chain when a progress mark 8 steps before a chain's end shows the
- * solve still running; the other two keep two chains in flight and check the
- * stop flag after each.  A longer chain costs fewer transitions between
+ * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  The next chain is
+ * launched when a progress mark 8 steps before a chain's end shows the solve
+ * still running.  A longer chain costs fewer transitions between
  * chains; once the solve has stopped, the launches left in the chains in
  * flight return at once, so a shorter chain wastes fewer of them.  Results do
  * not change.  Process-wide; not thread-safe. */
@@ -678,9 +677,10 @@ gn_status gn_set_pruning(int32_t mode);
 
 /* Tuning knob of gn_multi_solve (GN multi-start above).  A 16-start step costs
  * about as much with one start still running as with sixteen.  With the
- * hand-off enabled (1, the default), once a single start of a call with two or
- * more is left running and at least two chains of step launches remain, its
- * state moves at the next chain boundary to the chained single-start solve of
+ * hand-off enabled (1, the default), once a chain's progress mark shows a
+ * single start of a call with two or more still running and another chain of
+ * step launches to come, its state moves at the end of that chain to the
+ * chained single-start solve of
  * gn_solve (same arithmetic in the same order: the same words, tests, steps,
  * fallback count and results as without it).  0 keeps every start in the
  * 16-start steps.  GN_E_ARG for another value.  Process-wide; not thread-safe. */
