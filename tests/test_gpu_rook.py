@@ -205,6 +205,30 @@ def test_solve_is_deterministic(gpu):
     assert a[0].steps == b[0].steps and np.array_equal(a[1], b[1])
 
 
+def test_solve_independent_of_chain_length(gpu):
+    """The chain length moves only the progress marks the host waits on (at
+    step 0 of every chain when it is 8 or less): steps, states and sets are
+    identical, also when the budget ends the solve."""
+    libgn = _lib()
+    rows, cols = 40, 56
+    w = I.rook_weights_rect(rows, cols, 17)
+    outs = []
+    try:
+        for C in (64, 1, 8, 9, 33, 500):
+            libgn.gn_set_chunk_len(C)
+            for ms in (2000, 37):
+                r, x, sel = _solve(rows, cols, w, np.full(rows * cols, 0.5), **dict(RAMP, max_steps=ms))
+                outs.append((C, ms, r.steps, r.binarised, r.fallback_count, r.set_objective, x.view(np.uint32), sel))
+    finally:
+        libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)
+    ref = {o[1]: o for o in outs[:2]}
+    assert ref[2000][3] and ref[2000][2] > 64 and not ref[37][3] and ref[37][2] == 37
+    for o in outs[2:]:
+        b = ref[o[1]]
+        assert o[2:6] == b[2:6], (o[0], o[1])
+        assert np.array_equal(o[6], b[6]) and np.array_equal(o[7], b[7])
+
+
 def test_errors(gpu):
     libgn = _lib()
     with pytest.raises(libgn.GNError) as e:
