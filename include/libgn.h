@@ -628,7 +628,8 @@ gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t star
 /* Tuning: number of step launches captured in one replayed chain by gn_solve,
  * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  The next chain is
  * launched when a progress mark 8 steps before a chain's end shows the solve
- * still running.  A longer chain costs fewer transitions between
+ * still running; the calling thread waits for each mark by spinning on pinned
+ * host memory.  A longer chain costs fewer transitions between
  * chains; once the solve has stopped, the launches left in the chains in
  * flight return at once, so a shorter chain wastes fewer of them.  Results do
  * not change.  Process-wide; not thread-safe. */
