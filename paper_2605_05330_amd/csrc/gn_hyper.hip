@@ -37,7 +37,7 @@ namespace {
 constexpr int kHWaves = 4;           // hyperedges per workgroup
 constexpr int kHBlock = 64 * kHWaves;
 constexpr int kHVBlock = 256;        // vertex kernels
-constexpr int kHChain = 64;          // steps enqueued between looks at the stop flag
+constexpr size_t kHPinState = 1024;  // byte offset of the marks' copies of the starts' HState in the pinned block
 constexpr float kSafeDiv = 1e-9f;    // safe division threshold of the WRGN step
 
 // x-space state words: an ordinary fp32 x >= 2^-100 (or 0), never signed, else
@@ -398,6 +398,20 @@ struct gn_hyper {
     HPart* part = nullptr;               // [GN_MAX_STARTS][nparts]
     HPart* out = nullptr;                // [GN_MAX_STARTS]
     void* host = nullptr;                // pinned: HState[GN_MAX_STARTS] + HPart[GN_MAX_STARTS]
+    // Captured chains of steps (the steps' gamma, test steps and the start
+    // count are baked in, so the chains are kept for one schedule), their
+    // pinned block, and a solve state that never stops them by itself: the
+    // starts' own flags do, through the marks' copies.
+    GraphWorkspace ws;
+    struct ChainKey {
+        int32_t starts, ms, ramp, check_every, vstride;
+        float g0, g1, tau;
+        const int32_t* viol;
+        bool operator==(const ChainKey& o) const {
+            return starts == o.starts && ms == o.ms && ramp == o.ramp && check_every == o.check_every &&
+                   vstride == o.vstride && g0 == o.g0 && g1 == o.g1 && tau == o.tau && viol == o.viol;
+        }
+    } key{};
 };
 
 static void hyper_free(gn_hyper* h) {
@@ -417,6 +431,9 @@ static void hyper_free(gn_hyper* h) {
     hipFree(h->part);
     hipFree(h->out);
     if (h->host) hipHostFree(h->host);
+    h->ws.destroy_chains();
+    hipFree(h->ws.state);
+    if (h->ws.host_pinned) hipHostFree(h->ws.host_pinned);
 }
 
 static int32_t hyper_nbv(int32_t n) { return (n + kHVBlock - 1) / kHVBlock; }
@@ -570,20 +587,71 @@ extern "C" gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, i
     HState* hs = (HState*)h->host;
     HPart* hp = (HPart*)((char*)h->host + GN_MAX_STARTS * sizeof(HState));
     const dim3 ge(a.nbe, starts), gv(a.nbv, starts);
-    bool done = false;
-    for (int32_t k0 = 0; k0 < ms && !done; k0 += kHChain) {
-        const int32_t k1 = std::min(ms, k0 + kHChain);
-        for (int32_t k = k0; k < k1; ++k) {
-            const float g = gn_internal_host_gamma(sch, k);
-            const int32_t chk = k >= 1 && k % sch->check_every == 0;
-            hyper_edge_kernel<<<ge, kHBlock, 0, stream>>>(a, h->buf[k & 1], k, 1);
-            hyper_vertex_kernel<<<gv, kHVBlock, 0, stream>>>(a, h->buf[k & 1], h->buf[(k + 1) & 1], g, k, 1, chk, 1);
+    if (ms > 0) {
+        // steps 0 .. ms - 1 in captured chains; no further chain once every start has stopped
+        if (!h->ws.state) {
+            const SolveState never{-1, 0, 0, 0, 0.0f, 0, 0ull};
+            if (!gn_dalloc(&h->ws.state, 1)) return GN_E_NOMEM;
+            GN_HIP_TRY(hipMemcpy(h->ws.state, &never, sizeof(never), hipMemcpyHostToDevice));
         }
-        GN_HIP_TRY(hipGetLastError());
-        GN_HIP_TRY(hipMemcpyAsync(hs, h->st, sizeof(HState) * starts, hipMemcpyDeviceToHost, stream));
-        GN_HIP_TRY(hipStreamSynchronize(stream));
-        done = true;
-        for (int32_t s = 0; s < starts; ++s) done = done && hs[s].done != 0;
+        if (!h->ws.host_pinned && hipHostMalloc(&h->ws.host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+            h->ws.host_pinned = nullptr;
+            return GN_E_NOMEM;
+        }
+        const gn_hyper::ChainKey key{starts, ms, sch->ramp_steps, sch->check_every, a.vstride,
+                                     sch->gamma0, sch->gamma1, sch->tau, h->viol};
+        if (!(h->key == key)) {
+            h->ws.destroy_chains();
+            h->key = key;
+        }
+        const int32_t C = g_chunk_len;
+        const int32_t words = starts * (int32_t)(sizeof(HState) / sizeof(int32_t));
+        const char* run = (const char*)h->ws.host_pinned + kHPinState;
+        ChunkHooks hooks;
+        hooks.pin_src = h->st;
+        hooks.pin_words = words;
+        hooks.pin_offset = kHPinState;
+        hooks.stop_after = [run, words, starts](int32_t c) {
+            const volatile HState* p = (const volatile HState*)(run + sizeof(int32_t) * (size_t)words * (c & 1));
+            for (int32_t s = 0; s < starts; ++s)
+                if (!p[s].done) return false;
+            return true;
+        };
+        auto build = [h, a, sch, starts, ms, C](int32_t c, int32_t j0, int32_t j1, hipGraph_t graph,
+                                                hipGraphNode_t* last) -> gn_status {
+            hipGraphNode_t prev = *last;
+            for (int32_t j = j0; j < j1 && c * C + j < ms; ++j) {
+                HArgs aa = a;
+                int32_t k = c * C + j, solve = 1, write = 1;
+                int32_t chk = k >= 1 && k % sch->check_every == 0;
+                float g = gn_internal_host_gamma(sch, k);
+                const float* xin = h->buf[k & 1];
+                float* xout = h->buf[(k + 1) & 1];
+                void* ea[] = {&aa, &xin, &k, &solve};
+                void* va[] = {&aa, &xin, &xout, &g, &k, &solve, &chk, &write};
+                hipKernelNodeParams p{};
+                p.func = (void*)hyper_edge_kernel;
+                p.gridDim = dim3(aa.nbe, starts);
+                p.blockDim = dim3(kHBlock);
+                p.sharedMemBytes = 0;
+                p.kernelParams = ea;
+                p.extra = nullptr;
+                hipGraphNode_t node;
+                if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                    return GN_E_HIP;
+                prev = node;
+                p.func = (void*)hyper_vertex_kernel;
+                p.gridDim = dim3(aa.nbv, starts);
+                p.blockDim = dim3(kHVBlock);
+                p.kernelParams = va;
+                if (hipGraphAddKernelNode(&node, graph, &prev, 1, &p) != hipSuccess) return GN_E_HIP;
+                prev = node;
+            }
+            *last = prev;
+            return GN_OK;
+        };
+        gn_status rs = gn_internal_run_marked(h->ws, (ms + C - 1) / C, C, build, 0, stream, false, &hooks);
+        if (rs != GN_OK) return rs;
     }
     // the last check: a pending check of step ms - 1, then x^ms itself
     hyper_edge_kernel<<<ge, kHBlock, 0, stream>>>(a, h->buf[ms & 1], ms, 1);

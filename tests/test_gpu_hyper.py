@@ -99,6 +99,42 @@ def test_solve_matches_oracle(gpu, case, check_every):
     assert res.stab == pytest.approx(ref.stab, rel=1e-5)
 
 
+def test_solve_independent_of_chain_length(gpu):
+    """The steps run in captured chains with a progress mark before each
+    chain's end; the chain length moves only where the host looks: every
+    start's steps, states, sets and statistics are the same bits, for one
+    start and for five, also when the budget ends the solve and when one
+    handle's chains are rebuilt for another schedule."""
+    import torch
+    libgn = _lib()
+    n, ptr, mem = _cases()[list(_cases())[0]]
+    w = inputs.weights_uniform01(n, 8)
+    H = libgn.Hyper(n, ptr, mem, w)
+    u = 1.0 - inputs.rng_for(8, 29).random((5, n))
+    x0 = np.clip(u, 1e-3, 1.0).astype(np.float32).reshape(-1)
+    outs = {}
+    try:
+        for C in (64, 1, 8, 9, 100):
+            libgn.gn_set_chunk_len(C)
+            for ms in (3000, 23):
+                for starts in (1, 5):
+                    x = torch.from_numpy(x0[:starts * n].copy()).cuda()
+                    sel = torch.zeros(starts * n, dtype=torch.uint8, device="cuda")
+                    st, res, best = H.multi_solve(starts, x, sel, max_steps=ms)
+                    key = (ms, starts)
+                    o = ([(r.steps, r.binarised, r.fallback_count, r.set_objective, r.relaxed_objective, r.stab)
+                          for r in res], x.cpu().numpy().view(np.uint32), sel.cpu().numpy())
+                    if key not in outs:
+                        outs[key] = o
+                        continue
+                    assert o[0] == outs[key][0], (C, key)
+                    assert np.array_equal(o[1], outs[key][1]) and np.array_equal(o[2], outs[key][2])
+    finally:
+        libgn.gn_set_chunk_len(libgn.CHUNK_LEN_DEFAULT)
+    assert max(r[0] for r in outs[(3000, 5)][0]) > 64
+    assert all(r[0] == 23 and not r[1] for r in outs[(23, 1)][0])
+
+
 def test_solve_cut_by_max_steps(gpu):
     import torch
     libgn = _lib()
