@@ -607,7 +607,9 @@ gn_status gn_hyper_step(gn_hyper* h, float gamma, const float* x_in, float* x_ou
  * hyperedges hold no selected vertex, and stab is gamma_k * min over unselected
  * i of sum_{e holds i} sum_{j in e, selected} v_j / v_i (+inf when every
  * vertex is selected).  Returns GN_OK when binarised, GN_NOT_CONVERGED when
- * max_steps ran out.  SYNC. */
+ * max_steps ran out.  The steps replay as captured chains of launches
+ * (gn_set_chunk_len), which the handle keeps for the last schedule and start
+ * count it ran; calls on one handle must not overlap.  SYNC. */
 gn_status gn_hyper_solve(gn_hyper* h, const gn_schedule* sch, float* x, uint8_t* sel, gn_result* res,
                          hipStream_t stream);
 
@@ -626,7 +628,8 @@ gn_status gn_hyper_multi_solve(gn_hyper* h, const gn_schedule* sch, int32_t star
                                gn_result* res, int32_t* best, hipStream_t stream);
 
 /* Tuning: number of step launches captured in one replayed chain by gn_solve,
- * gn_multi_solve and gn_rook_solve (default 64, 1..4096).  The next chain is
+ * gn_multi_solve, gn_rook_solve and the hyperedge solves (default 64,
+ * 1..4096).  The next chain is
  * launched when a progress mark 8 steps before a chain's end shows the solve
  * still running; the calling thread waits for each mark by spinning on pinned
  * host memory.  A longer chain costs fewer transitions between
@@ -661,8 +664,7 @@ gn_status gn_set_small_graph_limit(int32_t work_max);
  * column lists in which the entries of vertices that are not ordinary -- most
  * of the graph once the non-selected vertices have decayed -- are marked
  * absent and not gathered.  Vertices that stopped being ordinary are dropped
- * at rebuilds between replayed chains of step launches
- * (gn_set_prune_interval); a vertex
+ * at rebuilds every few steps (gn_set_prune_interval); a vertex
  * whose state becomes ordinary again is put back into its neighbours' lists by
  * the step that produces that state, before any step reads it.  mode 0: never;
  * 1 (the default): on graphs whose gathers have little cache-line locality in
