@@ -428,6 +428,8 @@ def bench_lp(with_oracle=True):
     sel = torch.zeros(S * inst.n, dtype=torch.uint8, device="cuda")
 
     def gn_from(x0):
+        # one untimed call first: the handle captures its chains of step launches once
+        libgn.gn_multi_solve(G.handle, sched, S, x0.clone(), sel)
         xs = x0.clone()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -452,6 +454,7 @@ def bench_lp(with_oracle=True):
            "gn_from_lp": gn_from(x), "gn_from_random": gn_from(xr)}
     # the same LP points through the hyperedge form (the stops as hyperedges)
     H = libgn.Hyper(inst.n, inst.ptr, inst.members, c)
+    libgn.gn_hyper_multi_solve(H.handle, sched, S, x.clone(), sel)  # untimed: captures the chains
     xs = x.clone()
     torch.cuda.synchronize()
     t = time.perf_counter()
