@@ -322,6 +322,9 @@ gn_status gn_internal_run_marked(GraphWorkspace& ws, int32_t nchunks, int32_t C,
         ws.chunks.clear();
         ws.chunk_len = C;
     }
+    if (hooks && hooks->pin_src &&
+        (hooks->pin_words < 0 || hooks->pin_offset + 8 * (size_t)hooks->pin_words > kMarkPin))
+        return GN_E_ARG;  // the two copies must fit below the mark slots
     if ((int32_t)ws.chunks.size() < nchunks) ws.chunks.resize(nchunks, nullptr);
     volatile int32_t* slots = (volatile int32_t*)((char*)ws.host_pinned + kMarkPin);
     char* pin_dev = nullptr;  // the same block as the device addresses it
